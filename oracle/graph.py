@@ -1,0 +1,65 @@
+"""Bilateral-filter graph (paper Section 2).
+
+Readings (the paper leaves these open):
+  * Window: a square (Chebyshev) window |o|_inf <= r around each pixel, so a
+    K = (2r+1)^d point neighbourhood; the spatial term of eq. (2) uses the
+    Euclidean distance ||o||^2 in pixel units.
+  * Self-loop: eq. (1) sums over all j including j = i, and eq. (3) must
+    reproduce that average, so w_ii = exp(0) * exp(0) = 1 belongs to W and D.
+  * Boundary: windows are truncated at the border (no padding), which keeps
+    W exactly symmetric; d_i sums only in-grid neighbours.
+  * Guidance: the weights use a guidance signal g (the noisy input itself in
+    the self-guided case), computed once (the linear filter of Section 2).
+"""
+from __future__ import annotations
+
+import itertools
+
+import numpy as np
+import scipy.sparse as sp
+
+
+def window_offsets(ndim: int, radius: int):
+    """All offsets o of the square window |o|_inf <= radius, including o = 0."""
+    rng = range(-radius, radius + 1)
+    return [np.array(o, dtype=np.int64) for o in itertools.product(rng, repeat=ndim)]
+
+
+def bf_weight_matrix(g: np.ndarray, radius: int, sigma_s: float, sigma_r: float) -> sp.csr_matrix:
+    """Adjacency W of the BF graph, eq. (2):
+
+        w_ij = exp(-||p_i - p_j||^2 / (2 sigma_s^2)) * exp(-|g_i - g_j|^2 / (2 sigma_r^2))
+
+    for every j in the (border-truncated) window of i, w_ii = 1 included.
+    Pixels are numbered row-major; p_i are integer grid coordinates.
+    sigma_s = inf or sigma_r = inf switch the corresponding factor to 1.
+    """
+    g = np.asarray(g, dtype=np.float64)
+    shape = g.shape
+    n = g.size
+    gf = g.ravel()
+    coords = np.indices(shape).reshape(len(shape), -1).T  # (n, ndim) grid positions p_i
+    rows, cols, vals = [], [], []
+    for o in window_offsets(len(shape), radius):
+        nb = coords + o
+        inside = np.all((nb >= 0) & (nb < np.array(shape)), axis=1)
+        i = np.flatnonzero(inside)
+        j = np.ravel_multi_index(tuple(nb[inside].T), shape)
+        dist2 = float(np.dot(o, o))
+        spatial = np.exp(-dist2 / (2.0 * sigma_s ** 2)) if np.isfinite(sigma_s) else 1.0
+        if np.isfinite(sigma_r):
+            photometric = np.exp(-((gf[i] - gf[j]) ** 2) / (2.0 * sigma_r ** 2))
+        else:
+            photometric = np.ones(i.size)
+        rows.append(i)
+        cols.append(j)
+        vals.append(spatial * photometric)
+    rows = np.concatenate(rows)
+    cols = np.concatenate(cols)
+    vals = np.concatenate(vals)
+    return sp.csr_matrix((vals, (rows, cols)), shape=(n, n))
+
+
+def degrees(W) -> np.ndarray:
+    """d_i = sum_j w_ij (Section 2, the diagonal of D)."""
+    return np.asarray(W.sum(axis=1)).ravel()

@@ -1,0 +1,99 @@
+"""Graph operators in the three forms the filters use.
+
+For adjacency W and degrees D (Section 2, eq. (4): L = D - W):
+  random-walk form   D^-1 W x = x - D^-1 L x      (eq. (3): one BF / GF pass)
+  normalized form    N z = D^-1/2 W D^-1/2 z
+  normalized Laplacian  L_sym z = z - N z = D^-1/2 L D^-1/2 z
+
+Reading of the normalization (Section 4 writes (diag L)^-1/2 L (diag L)^-1/2):
+we normalize by D, the degree matrix that includes the self-loop.  Then
+D^-1 W = D^-1/2 N D^1/2 is exactly the BF of eq. (3), and D is exactly the
+preconditioner of Algorithm 2; z = D^1/2 x maps between the two.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+from .graph import bf_weight_matrix, degrees
+from .guided import guided_filter, gf_degrees, gf_stats
+
+FORM_N, FORM_LSYM, FORM_RW = 0, 1, 2
+
+
+@dataclass
+class GraphOperator:
+    kind: str                 # "bf" or "gf"
+    shape: tuple
+    guidance: np.ndarray      # float64, grid shape
+    radius: int
+    sigma_s: float = 0.0
+    sigma_r: float = 0.0
+    eps: float = 0.0
+    W: object = None          # scipy.sparse (BF) or None (GF: implicit)
+    d: np.ndarray = None      # flat degrees
+    sqrt_d: np.ndarray = None
+
+    @property
+    def n(self) -> int:
+        return int(np.prod(self.shape))
+
+    # -- adjacency ------------------------------------------------------
+    def apply_w(self, x):
+        """W x for a flat vector (or n x m block)."""
+        x = np.asarray(x, dtype=np.float64)
+        if self.kind == "bf":
+            return self.W @ x
+        # GF: W = D (D^-1 W) and D^-1 W x is Algorithm 1 with fixed guidance.
+        if x.ndim == 2:
+            return np.stack([self.apply_w(x[:, j]) for j in range(x.shape[1])], axis=1)
+        gx = guided_filter(x.reshape(self.shape), self.guidance, self.radius, self.eps).ravel()
+        return self.d * gx
+
+    def _scale(self, v, s):
+        return v * (s[:, None] if np.ndim(v) == 2 else s)
+
+    # -- the three forms --------------------------------------------------
+    def apply_rw(self, x):
+        """D^-1 W x (eq. (3))."""
+        return self._scale(self.apply_w(x), 1.0 / self.d)
+
+    def apply_n(self, z):
+        """N z = D^-1/2 W D^-1/2 z."""
+        inv = 1.0 / self.sqrt_d
+        return self._scale(self.apply_w(self._scale(z, inv)), inv)
+
+    def apply_lsym(self, z):
+        """L_sym z = z - N z."""
+        return np.asarray(z, dtype=np.float64) - self.apply_n(z)
+
+    def apply_l(self, x):
+        """L x = D x - W x (eq. (4))."""
+        return self._scale(np.asarray(x, dtype=np.float64), self.d) - self.apply_w(x)
+
+    def apply(self, form: int, v):
+        return {FORM_N: self.apply_n, FORM_LSYM: self.apply_lsym, FORM_RW: self.apply_rw}[form](v)
+
+    # -- normalized planes (for parity with a stored-operator build) --------
+    def gf_window_stats(self):
+        """(mu_k, 1/(sigma_k^2 + eps)) of the fixed guidance (GF only)."""
+        return gf_stats(self.guidance, self.radius, self.eps)
+
+
+def build_operator(kind: str, guidance, radius: int, sigma_s: float = 0.0,
+                   sigma_r: float = 0.0, eps: float = 0.0) -> GraphOperator:
+    """Build the graph operator of the BF (eq. (2)) or the GF (eqs. (5)-(6))
+    from a fixed guidance signal (the linear filters of Sections 2-3)."""
+    g = np.asarray(guidance, dtype=np.float64)
+    if kind == "bf":
+        W = bf_weight_matrix(g, radius, sigma_s, sigma_r)
+        d = degrees(W)
+    elif kind == "gf":
+        W = None
+        d = gf_degrees(g.shape, radius).ravel()
+    else:
+        raise ValueError(kind)
+    return GraphOperator(kind=kind, shape=g.shape, guidance=g, radius=radius,
+                         sigma_s=sigma_s, sigma_r=sigma_r, eps=eps, W=W, d=d,
+                         sqrt_d=np.sqrt(d))

@@ -1,0 +1,131 @@
+"""Seeded synthetic inputs: noisy piecewise-constant 1D signals and noisy
+piecewise-smooth 2D scenes.
+
+These generators stand in for the paper's test data (Section 7 uses a
+piecewise-linear 1D signal with additive Gaussian noise and an unnamed test
+image with Gaussian noise of variance 0.01; neither is available).  They hold
+none of the filtering method's arithmetic: they only draw random numbers and
+paint shapes.  Both the CPU oracle and the GPU library consume their output.
+
+G1  1D: 8 distinct breakpoints drawn from {1, ..., n-1} without replacement,
+    9 constant pieces with levels U[0,1], plus sigma * N(0,1) noise (no clip).
+G2  2D: linear-gradient background g0 + (g1-g0) * t(p) along a random
+    direction, then 40 random rectangles / disks (probability 1/2 each) in
+    painter's order with intensities U[0,1], centres uniform over the image,
+    half-sides / radius U[0.02, 0.15] * side, pixel-centre inclusion; plus
+    sigma * N(0,1) noise (no clip).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+__all__ = ["piecewise_constant_1d", "scene_2d", "batch_items", "lobpcg_gaussian_block"]
+
+
+def piecewise_constant_1d(n: int, sigma: float, seed, n_breaks: int = 8):
+    """Return (clean, noisy) float64 arrays of length n (G1)."""
+    rng = np.random.default_rng(seed)
+    n_breaks = min(n_breaks, max(n - 1, 0))
+    clean = np.empty(n, dtype=np.float64)
+    if n_breaks > 0:
+        cuts = np.sort(rng.choice(np.arange(1, n), size=n_breaks, replace=False))
+    else:
+        cuts = np.zeros(0, dtype=np.int64)
+    levels = rng.uniform(0.0, 1.0, size=n_breaks + 1)
+    edges = np.concatenate(([0], cuts, [n]))
+    for k in range(n_breaks + 1):
+        clean[edges[k]:edges[k + 1]] = levels[k]
+    noisy = clean + sigma * rng.standard_normal(n)
+    return clean, noisy
+
+
+def scene_2d(height: int, width: int, sigma: float, seed, n_shapes: int = 40):
+    """Return (clean, noisy) float64 arrays of shape (height, width) (G2)."""
+    rng = np.random.default_rng(seed)
+    side = float(max(height, width))
+    yy, xx = np.meshgrid(np.arange(height) + 0.5, np.arange(width) + 0.5, indexing="ij")
+    g0, g1 = rng.uniform(0.0, 1.0, size=2)
+    phi = rng.uniform(0.0, 2.0 * np.pi)
+    t = np.cos(phi) * xx + np.sin(phi) * yy
+    tmin, tmax = t.min(), t.max()
+    t = (t - tmin) / (tmax - tmin) if tmax > tmin else np.zeros_like(t)
+    img = g0 + (g1 - g0) * t
+    for _ in range(n_shapes):
+        is_rect = rng.uniform() < 0.5
+        cy = rng.uniform(0.0, height)
+        cx = rng.uniform(0.0, width)
+        level = rng.uniform(0.0, 1.0)
+        if is_rect:
+            hy = rng.uniform(0.02, 0.15) * side
+            hx = rng.uniform(0.02, 0.15) * side
+            y0, y1 = int(max(0, np.floor(cy - hy))), int(min(height, np.ceil(cy + hy) + 1))
+            x0, x1 = int(max(0, np.floor(cx - hx))), int(min(width, np.ceil(cx + hx) + 1))
+            sub_y, sub_x = yy[y0:y1, x0:x1], xx[y0:y1, x0:x1]
+            mask = (np.abs(sub_y - cy) <= hy) & (np.abs(sub_x - cx) <= hx)
+        else:
+            rad = rng.uniform(0.02, 0.15) * side
+            y0, y1 = int(max(0, np.floor(cy - rad))), int(min(height, np.ceil(cy + rad) + 1))
+            x0, x1 = int(max(0, np.floor(cx - rad))), int(min(width, np.ceil(cx + rad) + 1))
+            sub_y, sub_x = yy[y0:y1, x0:x1], xx[y0:y1, x0:x1]
+            mask = (sub_y - cy) ** 2 + (sub_x - cx) ** 2 <= rad * rad
+        img[y0:y1, x0:x1][mask] = level
+    noisy = img + sigma * rng.standard_normal((height, width))
+    return img, noisy
+
+
+def lobpcg_gaussian_block(n: int, m: int, seed):
+    """Seeded standard-normal n x m block (used only where a caller wants an
+    explicit LOBPCG start block instead of the Krylov start)."""
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((n, m))
+
+
+def batch_items(seed: int = 4, n_images: int = 256, n_signals: int = 64,
+                side_range=(64, 1024), len_range=(2 ** 10, 2 ** 20), max_pixels=None):
+    """Per-item recipe of the uneven batch workload.
+
+    Image sides are log-uniform in side_range (square images), signal lengths
+    log-uniform in len_range, noise sigma ~ U[0.03, 0.1].  Each item carries
+    its own operator parameters: kind BF or GF with probability 1/2; BF radius
+    in {1..5}, sigma_d ~ U[1,3], sigma_r ~ U[0.05,0.3]; GF radius in {1..8},
+    eps log-uniform in [1e-3, 1e-1]; solver CG or LOBPCG (m=4) with
+    probability 1/2; kmax = 50, tol = 1e-6.  Item i uses sub-seed (seed, i).
+    Returns a list of dicts (signals are produced lazily by `item_signal`).
+    """
+    rng = np.random.default_rng(seed)
+    items = []
+    total = n_images + n_signals
+    for i in range(total):
+        is_img = i < n_images
+        if is_img:
+            s = int(round(np.exp(rng.uniform(np.log(side_range[0]), np.log(side_range[1])))))
+            shape = (s, s)
+        else:
+            n = int(round(np.exp(rng.uniform(np.log(len_range[0]), np.log(len_range[1])))))
+            shape = (n,)
+        sigma = float(rng.uniform(0.03, 0.1))
+        kind = "bf" if rng.uniform() < 0.5 else "gf"
+        if kind == "bf":
+            radius = int(rng.integers(1, 6))
+            sigma_d = float(rng.uniform(1.0, 3.0))
+            sigma_r = float(rng.uniform(0.05, 0.3))
+            eps = 0.0
+        else:
+            radius = int(rng.integers(1, 9))
+            sigma_d = sigma_r = 0.0
+            eps = float(np.exp(rng.uniform(np.log(1e-3), np.log(1e-1))))
+        method = "cg" if rng.uniform() < 0.5 else "lobpcg"
+        items.append(dict(index=i, shape=shape, sigma=sigma, kind=kind, radius=radius,
+                          sigma_d=sigma_d, sigma_r=sigma_r, eps=eps, method=method,
+                          m=4 if method == "lobpcg" else 1, kmax=50, tol=1e-6,
+                          seed=(seed, i)))
+    if max_pixels is not None:
+        items = [it for it in items if int(np.prod(it["shape"])) <= max_pixels]
+    return items
+
+
+def item_signal(item):
+    """(clean, noisy) for one batch item."""
+    if len(item["shape"]) == 1:
+        return piecewise_constant_1d(item["shape"][0], item["sigma"], item["seed"])
+    return scene_2d(item["shape"][0], item["shape"][1], item["sigma"], item["seed"])

@@ -1,0 +1,45 @@
+"""Named workloads: input recipes plus the operator and solver parameters the
+experiments use.  Sizes and parameters only; no filter arithmetic.
+
+signal_1d_4096   1D, n=4096, G1, sigma=0.1, seed 1; BF radius 5, sigma_d=3,
+                 sigma_r=0.2, FP64; 30 iterations of power / CG / LOBPCG(m=3).
+image_1024_bf11  2D 1024x1024, G2, sigma=0.05, seed 2; BF 11x11, sigma_d=2,
+                 sigma_r=0.1, FP32 (FP64 Rayleigh-Ritz); CG 50, LOBPCG(m=4) 50.
+image_4096_bf7   2D 4096x4096, G2, sigma=0.08, seed 3; BF 7x7, sigma_d=2,
+                 sigma_r=0.15; LOBPCG(m=8) 100.
+image_4096_gf8   same image; GF radius 8, eps=1e-2; LOBPCG(m=8) 100.
+image_2048_bf11  2D 2048x2048 evaluation images (seeds 5900..5903); BF 11x11,
+                 sigma_d=2, sigma_r=0.1; LOBPCG(m=4) with the constraint, tol 1e-6.
+"""
+from __future__ import annotations
+
+from .generators import piecewise_constant_1d, scene_2d
+
+WORKLOADS = {
+    "signal_1d_4096": dict(shape=(4096,), sigma=0.1, seed=1, kind="bf", radius=5,
+                           sigma_d=3.0, sigma_r=0.2, eps=0.0, prec="f64",
+                           power_iters=30, cg_iters=30, lobpcg_iters=30, lobpcg_m=3),
+    "image_1024_bf11": dict(shape=(1024, 1024), sigma=0.05, seed=2, kind="bf", radius=5,
+                            sigma_d=2.0, sigma_r=0.1, eps=0.0, prec="f32",
+                            cg_iters=50, lobpcg_iters=50, lobpcg_m=4),
+    "image_4096_bf7": dict(shape=(4096, 4096), sigma=0.08, seed=3, kind="bf", radius=3,
+                           sigma_d=2.0, sigma_r=0.15, eps=0.0, prec="f32",
+                           lobpcg_iters=100, lobpcg_m=8),
+    "image_4096_gf8": dict(shape=(4096, 4096), sigma=0.08, seed=3, kind="gf", radius=8,
+                           sigma_d=0.0, sigma_r=0.0, eps=1e-2, prec="f32",
+                           lobpcg_iters=100, lobpcg_m=8),
+    "image_2048_bf11": dict(shape=(2048, 2048), sigma=0.05, seed=5900, kind="bf", radius=5,
+                            sigma_d=2.0, sigma_r=0.1, eps=0.0, prec="f32",
+                            lobpcg_m=4, tol=1e-6, max_iters=20000, constraint=True),
+}
+
+
+def make_signal(name: str, shape=None, seed=None):
+    """(clean, noisy) float64 input of a named workload; `shape`/`seed`
+    override the defaults (used for crops at test sizes)."""
+    w = WORKLOADS[name]
+    shape = tuple(shape) if shape is not None else w["shape"]
+    seed = w["seed"] if seed is None else seed
+    if len(shape) == 1:
+        return piecewise_constant_1d(shape[0], w["sigma"], seed)
+    return scene_2d(shape[0], shape[1], w["sigma"], seed)
