@@ -1,0 +1,174 @@
+"""Benchmark of the graph spectral filter hot path on one MI355X.
+
+One step = one pass of the whole path over one noisy image of the workload:
+build the BF operator (eq. (2), weights computed once), run CG for kmax_cg
+steps (Algorithm 2) and block LOBPCG (m vectors, kmax_lob steps,
+Algorithm 3).  Inputs are resident in HBM before timing starts.
+
+value = pixel-vector-applies of the Laplacian per second over the whole step
+(Mpixel-iters/s): per step, CG applies L_sym to 1 vector kmax_cg + 1 times and
+LOBPCG applies it to m vectors kmax_lob + 1 times.
+
+roofline: the dominant kernel (the stencil apply) timed with HIP events on its
+own stream over `--roofline-reps` launches; achieved = algorithmic bytes per
+launch / average duration, with algorithmic bytes per pixel
+4 * ((K+1)/2 + 2m) for FP32 (each undirected edge once, the diagonal, x in, y
+out; halo re-reads are not algorithmic).
+cpu_baseline: the FP64 oracle (numpy/scipy, single thread) on a bounded crop
+of the same image, in the same unit.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def _args():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="image_1024_bf11")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--roofline-reps", type=int, default=50)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    return ap.parse_args()
+
+
+def cpu_baseline(w, noisy, budget_s):
+    """Time the oracle on a crop of the workload image: CG and LOBPCG steps,
+    counted in the same unit (pixel-vector-applies per second)."""
+    import oracle
+    rows = max(32, min(noisy.shape[0], 128))
+    crop = noisy[:rows, :]
+    t0 = time.perf_counter()
+    op = oracle.build_operator("bf", crop, w["radius"], w["sigma_d"], w["sigma_r"])
+    t_build = time.perf_counter() - t0
+    n = crop.size
+    work = 0
+    t0 = time.perf_counter()
+    k_cg, k_lob, m = 10, 5, w["lobpcg_m"]
+    while True:
+        oracle.cg_filter(op, crop.ravel(), k_cg, data_prec="f32")
+        oracle.lobpcg_filter(op, crop.ravel(), m, k_lob, data_prec="f32")
+        work += n * ((k_cg + 1) + m * (k_lob + 1))
+        if time.perf_counter() - t0 > budget_s:
+            break
+    el = time.perf_counter() - t0
+    return {"value": work / el / 1e6, "unit": "Mpixel-iters/s", "cores": 1, "kind": "oracle",
+            "sample": f"{crop.shape[0]}x{crop.shape[1]} crop of the workload image, BF {2*w['radius']+1}x"
+                      f"{2*w['radius']+1} operator (build {t_build:.1f} s excluded), repeated CG({k_cg}) + "
+                      f"LOBPCG(m={m}, {k_lob}) for {el:.1f} s, FP64, single thread"}
+
+
+def main():
+    a = _args()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is described in DESIGN.md"}))
+        sys.exit(2)
+    import torch
+    import paper_1509_02468_amd as gsf
+    from synth import WORKLOADS, make_signal
+
+    gsf.load_library()
+    torch.cuda.set_device(0)
+    w = WORKLOADS[a.workload]
+    shape = w["shape"]
+    n = int(np.prod(shape))
+    prec = gsf.F32 if w["prec"] == "f32" else gsf.F64
+    dt = torch.float32 if prec == gsf.F32 else torch.float64
+    _, noisy = make_signal(a.workload)
+    x0 = torch.tensor(noisy.ravel(), dtype=dt, device="cuda")
+    kcg, klob, m = w["cg_iters"], w["lobpcg_iters"], w["lobpcg_m"]
+    stream = torch.cuda.current_stream()
+
+    # allocate everything once; steps reuse the buffers
+    op = gsf.Operator(w["kind"], shape, x0, w["radius"], w["sigma_d"], w["sigma_r"], w["eps"], prec)
+    ws_cg = op.workspace(gsf.METHOD_CG)
+    ws_lob = op.workspace(gsf.METHOD_LOBPCG, m)
+    y_cg = torch.empty_like(x0)
+    y_lob = torch.empty_like(x0)
+
+    def step():
+        op_s = gsf.Operator(w["kind"], shape, x0, w["radius"], w["sigma_d"], w["sigma_r"], w["eps"], prec)
+        op_s.cg_filter(x0, kcg, out=y_cg, ws=ws_cg, info=False)
+        op_s.lobpcg_filter(x0, m, klob, out=y_lob, ws=ws_lob, info=False)
+        return op_s
+
+    keep = []
+    for _ in range(a.warmup):
+        keep.append(step())
+    torch.cuda.synchronize()
+    keep.clear()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        keep.append(step())
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ms = el / a.steps * 1e3
+    applies = n * ((kcg + 1) + m * (klob + 1))
+    value = applies / (el / a.steps) / 1e6
+
+    # dominant kernel: stencil apply (m = 1 and m = block size), events on one stream
+    K = (2 * w["radius"] + 1) ** len(shape)
+    esz = 4 if prec == gsf.F32 else 8
+    rl = {}
+    s2 = torch.cuda.Stream()
+    for mm in (1, m):
+        xb = torch.randn((n, mm) if mm > 1 else (n,), dtype=dt, device="cuda")
+        yb = torch.empty_like(xb)
+        with torch.cuda.stream(s2):
+            for _ in range(5):
+                op.apply(xb, gsf.FORM_LSYM, out=yb, stream=s2)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(s2)
+            for _ in range(a.roofline_reps):
+                op.apply(xb, gsf.FORM_LSYM, out=yb, stream=s2)
+            e1.record(s2)
+        e1.synchronize()
+        t_ms = e0.elapsed_time(e1) / a.roofline_reps
+        algo = esz * ((K + 1) // 2 + 2 * mm) * n
+        rl[mm] = (algo, t_ms)
+    # the block apply moves more bytes per launch and runs as often as the m = 1 apply
+    dom = m if rl[m][1] * (klob + 1) >= rl[1][1] * (kcg + 1) else 1
+    algo, t_ms = rl[dom]
+    achieved = algo / (t_ms * 1e-3) / 1e9
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        try:
+            tr = json.load(open(TRAFFIC_FILE)).get(f"{a.workload}:m{dom}")
+            traffic = tr.get("bytes_per_launch") if tr else None
+        except Exception:
+            traffic = None
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": f"bf_apply2d m={dom}", "us_per_launch": round(t_ms * 1e3, 2),
+                "algorithmic_bytes_per_launch": algo,
+                "m1_us": round(rl[1][1] * 1e3, 2), f"m{m}_us": round(rl[m][1] * 1e3, 2)}
+
+    cpu = None if a.no_cpu else cpu_baseline(w, noisy, a.cpu_seconds)
+    out = {"metric": "Mpixel-iters/s of Laplacian apply", "value": round(value, 1), "unit": "Mpixel-iters/s",
+           "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(ms, 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32" if prec == gsf.F32 else "f64", "data": "synthetic",
+           "config": {"workload": a.workload, "shape": list(shape), "operator": f"{w['kind']} r={w['radius']}",
+                      "cg_iters": kcg, "lobpcg_iters": klob, "lobpcg_m": m, "parallelism": "single-gpu"},
+           "roofline": roofline, "cpu_baseline": cpu}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,233 @@
+/*
+ * gsf.h -- C ABI of libgsf: graph spectral polynomial filters on MI355X (gfx950).
+ *
+ * Method: Knyazev & Malyshev, "Accelerated graph-based spectral polynomial
+ * filters" (IEEE MLSP 2015).  A noisy signal x (1D samples or a 2D image,
+ * row-major) defines, through a fixed guidance signal g, a weighted graph:
+ * bilateral-filter weights (Section 2, eq. (2)) or the guided filter's
+ * implicit matrix (Section 3, Algorithm 1, eqs. (5)-(6)).  With adjacency W,
+ * degrees D and Laplacian L = D - W (eq. (4)) the library applies
+ *     N      = D^-1/2 W D^-1/2          (normalized operator, Section 4)
+ *     L_sym  = I - N = D^-1/2 L D^-1/2  (normalized Laplacian)
+ *     RW     = D^-1 W                   (one BF / GF pass, eq. (3))
+ * and runs the paper's polynomial filters on it: power iteration (Section 4),
+ * preconditioned CG for L x = 0 with preconditioner D (Algorithm 2) and block
+ * LOBPCG used as a low-pass filter (Algorithm 3, Section 6).
+ *
+ * Conventions shared by every entry point
+ *  - Device memory: every data pointer (guidance, x, y, workspaces) is a
+ *    device pointer on the current HIP device.  The caller owns all of it;
+ *    the library never allocates device memory.  Workspace sizes come from
+ *    the *_workspace_bytes queries; a workspace must stay alive and untouched
+ *    while a handle or call uses it.
+ *  - Element type: FP32 (`float`) or FP64 (`double`) as selected by
+ *    gsf_operator_desc.prec; every vector argument of a call on an operator
+ *    has that type.  Small reductions, scalars and the Rayleigh-Ritz step are
+ *    always computed in FP64.
+ *  - Vector layout: a block of m vectors over n grid points is stored
+ *    point-major: element (i, j) at index i*m + j (m contiguous values per
+ *    grid point).  m = 1 is a plain vector.
+ *  - Streams: `stream` is a hipStream_t (NULL = the default stream).  All work
+ *    is enqueued asynchronously on it; a call only synchronizes the stream
+ *    when it is given a non-NULL host `info` pointer to fill.
+ *  - Errors: status codes only.  Arguments are validated on the host before
+ *    anything is launched; on GSF_EINVAL / GSF_ENOMEM nothing has been
+ *    enqueued and no output was touched.  Input vectors are never modified.
+ *  - Threading: a handle may be used by one stream at a time.
+ */
+#ifndef GSF_H
+#define GSF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GSF_OK = 0,
+  GSF_EINVAL = 1,      /* invalid argument (shape, parameter, NULL pointer, non-finite parameter) */
+  GSF_ENOMEM = 2,      /* workspace smaller than the size query returned */
+  GSF_EDEVICE = 3,     /* a HIP runtime call failed */
+  GSF_ENOTCONV = 4,    /* tol > 0 was not reached within kmax steps; the result is still valid */
+  GSF_EBREAKDOWN = 5   /* the iteration stopped early (see each solver); the result is still valid */
+} gsf_status;
+
+typedef enum { GSF_BF = 0, GSF_GF = 1 } gsf_kind;
+typedef enum { GSF_F32 = 0, GSF_F64 = 1 } gsf_prec;
+typedef enum { GSF_FORM_N = 0, GSF_FORM_LSYM = 1, GSF_FORM_RW = 2 } gsf_form;
+typedef enum { GSF_METHOD_POWER = 0, GSF_METHOD_CG = 1, GSF_METHOD_LOBPCG = 2 } gsf_method;
+
+/* Operator description.
+ *  kind    GSF_BF: weights of eq. (2) over the square window |o|_inf <= radius,
+ *            w_ij = exp(-||p_i - p_j||^2 / (2 sigma_d^2) - (g_i - g_j)^2 / (2 sigma_r^2)),
+ *            self-loop w_ii = 1 included, windows truncated at the border.
+ *          GSF_GF: Algorithm 1 with mean filters of width 2*radius+1 over
+ *            border-truncated windows and regularisation gf_eps; its matrix
+ *            W_ij = (1/|w|) sum_{k: i,j in w_k} (1/N_k)(1 + (g_i-mu_k)(g_j-mu_k)/(s_k^2+eps))
+ *            (eq. (6) in the interior) has row sums d_i = N_i/|w|.
+ *  ndim    1 (dims[0] = n) or 2 (dims[0] = rows H, dims[1] = columns W).
+ *  prec    element type of the guidance, of all vectors and of the stored
+ *          operator.  Weights and window statistics are always computed in
+ *          FP64 and rounded once to this type.
+ *  radius  1..8.
+ *  sigma_d, sigma_r > 0 (BF; +inf allowed, removing that factor).
+ *  gf_eps  >= 0 (GF). */
+typedef struct {
+  int32_t kind;
+  int32_t ndim;
+  int64_t dims[2];
+  int32_t prec;
+  int32_t radius;
+  double sigma_d;
+  double sigma_r;
+  double gf_eps;
+} gsf_operator_desc;
+
+typedef struct gsf_operator gsf_operator;   /* opaque host handle */
+
+/* Device layout of a built operator, for inspection (all pointers point into
+ * the caller's operator workspace; element type = prec).
+ *  BF: `planes` holds nplanes = ((2r+1)^ndim - 1)/2 planes of n values; plane
+ *      o (half-window offsets in the order: 1D o = 1..r; 2D (dy, dx) with
+ *      dy = 0, dx = 1..r, then dy = 1..r, dx = -r..r) stores the weight
+ *      w_{i,i+o} of eq. (2) at index i (0 where i+o is outside the grid);
+ *      each undirected edge is stored once.  `inv_sqrt_d` holds 1/sqrt(d_i).
+ *      The apply evaluates L_sym z = D^-1/2 L D^-1/2 z as
+ *      (1/sqrt(d_i)) sum_j w_ij (u_i - u_j) with u = D^-1/2 z, and
+ *      N z = z - L_sym z.
+ *  GF: `mu` and `inv` hold the window statistics mu_k and 1/(sigma_k^2 + eps)
+ *      of the guidance (Algorithm 1), `guidance` a copy of g.
+ *  Both: `sqrt_d` holds sqrt(d_i); `degree` holds d_i in FP64. */
+typedef struct {
+  int32_t kind, ndim, prec, radius;
+  int64_t n;
+  int32_t nplanes;
+  const void* planes;
+  const void* inv_sqrt_d;
+  const void* sqrt_d;
+  const double* degree;
+  const void* guidance;
+  const void* mu;
+  const void* inv;
+} gsf_operator_layout;
+
+/* CG result summary (z-space 2-norms, FP64). */
+typedef struct {
+  int32_t iters;      /* completed updates */
+  int32_t status;     /* gsf_status of the run */
+  double res0;        /* ||r_0|| = sqrt(s_0^T r_0) */
+  double res;         /* ||r|| at exit */
+} gsf_cg_info;
+
+/* LOBPCG result summary. */
+typedef struct {
+  int32_t iters;      /* completed Rayleigh-Ritz steps */
+  int32_t status;     /* gsf_status of the run */
+  int32_t dropped;    /* trial columns dropped by the Rayleigh-Ritz Cholesky, summed over steps */
+  int32_t m;
+  double res[8];      /* ||L_sym x_j - theta_j x_j||, unit x_j (z-space), per column */
+  double theta[8];    /* Ritz values, ascending */
+} gsf_lobpcg_info;
+
+/* ---- version / errors ------------------------------------------------- */
+int gsf_version(void);
+const char* gsf_status_string(int status);
+
+/* ---- operator (Sections 2-3) ----------------------------------------------
+ * gsf_operator_workspace_bytes: bytes of device workspace the operator needs.
+ * gsf_build_operator: computes the weights (BF, eq. (2)) and degrees, or the
+ *   guided-filter window statistics (Algorithm 1, the g-only lines), from the
+ *   guidance `guidance` (n values of type prec) into `ws`, and returns a host
+ *   handle in *out.  The build is asynchronous: the guidance must stay valid
+ *   until the stream has executed it (it is not read afterwards).
+ *   GSF_EINVAL for bad shapes or parameters; a non-finite guidance value is
+ *   not checked on the host (it yields non-finite weights).
+ * gsf_destroy_operator: frees the host handle only (NULL is allowed). */
+gsf_status gsf_operator_workspace_bytes(const gsf_operator_desc* desc, size_t* bytes);
+gsf_status gsf_build_operator(const gsf_operator_desc* desc, const void* guidance,
+                              void* ws, size_t ws_bytes, void* stream, gsf_operator** out);
+gsf_status gsf_operator_get_layout(const gsf_operator* op, gsf_operator_layout* out);
+void gsf_destroy_operator(gsf_operator* op);
+
+/* ---- apply (eqs. (1), (3); Section 4) -------------------------------------
+ * y = F x for a block of m (1..8) vectors, F = N, L_sym or D^-1 W (`form`).
+ * N and L_sym act on z-space vectors (z = D^1/2 x); RW acts on x directly.
+ * x and y: n*m elements, point-major; y must not overlap x. */
+gsf_status gsf_apply(const gsf_operator* op, int form, int m, const void* x, void* y,
+                     void* stream);
+
+/* ---- solvers ---------------------------------------------------------------
+ * gsf_solver_workspace_bytes: workspace for `method` with block size m
+ *   (m is ignored for power and CG). */
+gsf_status gsf_solver_workspace_bytes(const gsf_operator* op, int method, int m, size_t* bytes);
+
+/* Power iteration (Section 4): x_out = (D^-1 W)^kmax x0, kmax >= 0.
+ * x0 and x_out: n elements; they may be the same buffer. */
+gsf_status gsf_power_filter(const gsf_operator* op, const void* x0, void* x_out, int kmax,
+                            void* ws, size_t ws_bytes, void* stream);
+
+/* Preconditioned CG for L x = 0 with preconditioner D, started at x0
+ * (Algorithm 2), run in z = D^1/2 x as CG on L_sym with identity
+ * preconditioner.  beta = s^T (r - r_old) / (s_old^T r_old) (the printed
+ * s_old^T s_old denominator read as s_old^T r_old).  Runs kmax updates unless
+ *   - tol > 0 and ||r_k|| <= tol ||r_0||: stop, GSF_OK;
+ *   - s^T r <= (tau ||z_0||)^2 (tau = 1e-13 FP64, 1e-6 FP32) or non-finite,
+ *     or p^T q <= 0 or non-finite: stop, GSF_EBREAKDOWN (x so far is returned;
+ *     a constant x0 returns x0);
+ * and returns GSF_ENOTCONV when tol > 0 was not met after kmax updates.
+ * The returned status is only known after the stream has reached the end of
+ * the call: with info == NULL the call returns GSF_OK after enqueueing. */
+gsf_status gsf_cg_filter(const gsf_operator* op, const void* x0, void* x_out, int kmax,
+                         double tol, void* ws, size_t ws_bytes, gsf_cg_info* info, void* stream);
+
+/* Block LOBPCG low-pass filter (Algorithm 3 generalised to m = 1..8 vectors):
+ * operator L_sym, preconditioner T = I (T = D^-1 in x-space).  Start block
+ * X0[:, j] = z0 * phi_j with phi_0 = 1 and phi_j products of Legendre
+ * polynomials of the normalised coordinates t = 2(i + 1/2)/n - 1 (degrees by
+ * total degree, then row degree).  With constraint != 0 every block is kept
+ * orthogonal to Y = D^1/2 e / ||D^1/2 e|| (x orthogonal to e in the D inner
+ * product).  Each step: R = AX - X Theta, W = R (projected), Rayleigh-Ritz on
+ * [X, W, P] in FP64 with a column-dropping Cholesky (drop when the pivot of the
+ * unit-diagonal Gram is <= 1e-10 (FP64) / 1e-6 (FP32), or the column norm^2 is
+ * <= tau^2 max norm^2), keep the m smallest Ritz pairs, P = [W, P] C.
+ * Output x_out = D^-1/2 (X X^T z0 (+ Y Y^T z0)), n elements.
+ * ritz_vecs (NULL or n*m, z-space, column signs with x_j^T z0 >= 0).
+ * tol > 0 stops when every column residual <= tol (GSF_ENOTCONV if not met).
+ * A start block of rank < m returns x0 with GSF_EBREAKDOWN.
+ * T must be NULL (plain method) or a learned preconditioner handle. */
+typedef struct gsf_precond gsf_precond;
+gsf_status gsf_lobpcg_filter(const gsf_operator* op, const void* x0, void* x_out, int m,
+                             int kmax, double tol, int constraint, const gsf_precond* T,
+                             void* ritz_vecs, void* ws, size_t ws_bytes, gsf_lobpcg_info* info,
+                             void* stream);
+
+/* ---- diagnostic entry points (the solver's inner kernels on caller data) ----
+ * gsf_block_gram: the Gram pair of the LOBPCG Rayleigh-Ritz step (Algorithm 3,
+ *   the Rayleigh-Ritz line): GA = S^T (A S), GB = S^T S for S = [S0 .. S_{nb-1}]
+ *   (nb = 1..3 point-major blocks of n x m, m = 1..8, element type prec) and
+ *   AS = [A0 ..]; S and AS are arrays of nb device pointers.  Results are
+ *   written to host arrays GA, GB (ns x ns, ns = nb*m, row-major).  The
+ *   device workspace size comes from gsf_block_gram_workspace_bytes(n).
+ *   Synchronizes the stream.
+ * gsf_rayleigh_ritz: the FP64 Rayleigh-Ritz step on a host Gram pair
+ *   (ns = 1..24, m <= min(8, ns)): the m smallest Ritz values theta (host, m)
+ *   and coefficients C (host, ns x m row-major, zero rows at dropped columns),
+ *   kept flags (host int, ns) and the number kept (*nkept).  A column is
+ *   dropped when GB_jj <= zero_tol^2 max GB_jj or when the pivot of the
+ *   unit-diagonal Cholesky is <= drop_tol.  Device workspace of
+ *   gsf_rr_workspace_bytes() bytes; synchronizes the stream. */
+gsf_status gsf_block_gram_workspace_bytes(int64_t n, size_t* bytes);
+gsf_status gsf_block_gram(int prec, int64_t n, int m, int nb, const void* const* S,
+                          const void* const* AS, double* GA, double* GB, void* ws,
+                          size_t ws_bytes, void* stream);
+size_t gsf_rr_workspace_bytes(void);
+gsf_status gsf_rayleigh_ritz(int ns, int m, const double* GA, const double* GB, double drop_tol,
+                             double zero_tol, double* theta, double* C, int* kept, int* nkept,
+                             void* ws, size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GSF_H */

@@ -1,0 +1,16 @@
+"""MI355X-native graph spectral polynomial filters (Knyazev & Malyshev,
+"Accelerated graph-based spectral polynomial filters").
+
+The compute path is the HIP library libgsf.so (C ABI in include/gsf.h); this
+package is its thin ctypes binding.  There is no CPU fallback: calls fail if
+the library has not been built.
+"""
+from .gsf import (OK, EINVAL, ENOMEM, EDEVICE, ENOTCONV, EBREAKDOWN, BF, GF, F32, F64,
+                  FORM_N, FORM_LSYM, FORM_RW, METHOD_POWER, METHOD_CG, METHOD_LOBPCG,
+                  LIB_PATH, GsfError, Operator, build_operator, block_gram, rayleigh_ritz,
+                  load_library)
+
+__all__ = ["OK", "EINVAL", "ENOMEM", "EDEVICE", "ENOTCONV", "EBREAKDOWN", "BF", "GF", "F32", "F64",
+           "FORM_N", "FORM_LSYM", "FORM_RW", "METHOD_POWER", "METHOD_CG", "METHOD_LOBPCG",
+           "LIB_PATH", "GsfError", "Operator", "build_operator", "block_gram", "rayleigh_ritz",
+           "load_library"]

@@ -1,0 +1,599 @@
+// C ABI of libgsf: validation, workspace layout and the solver drivers.
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "gsf_internal.h"
+#include "lobpcg_launch.h"
+#include "solver_state.h"
+
+namespace gsf {
+
+gsf_status launch_bf_apply(const Operator& op, int form, int m, const void* x, int64_t ldx, void* y,
+                           int64_t ldy, double* dot, int* nparts, hipStream_t s);
+int bf_apply_blocks(const Operator& op, int m);
+gsf_status launch_gf_apply(const Operator& op, void* scratch, int form, int m, const void* x, int64_t ldx,
+                           void* y, int64_t ldy, hipStream_t s);
+int vec_blocks(int64_t n);
+gsf_status launch_scale(const Operator& op, const void* in, void* out, int divide, hipStream_t s);
+gsf_status launch_cg_init(const Operator& op, const void* z, void* r, double* partials, CgState* st,
+                          hipStream_t s);
+gsf_status launch_cg_pupdate(const Operator& op, const void* r, void* p, const CgState* st, hipStream_t s);
+gsf_status launch_dot(const Operator& op, const void* a, const void* b, double* partials, int* nparts,
+                      const CgState* st, hipStream_t s);
+gsf_status launch_cg_alpha(const double* partials, int nparts, CgState* st, hipStream_t s);
+gsf_status launch_cg_update(const Operator& op, void* z, void* r, const void* p, const void* q, double* partials,
+                            CgState* st, hipStream_t s);
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+__global__ void lob_state_init_kernel(LobpcgState* dst, LobpcgState v) { *dst = v; }
+__global__ void cg_state_init_kernel(CgState* dst, CgState v) { *dst = v; }
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+gsf_status validate_desc(const gsf_operator_desc* d) {
+  if (d == nullptr) return GSF_EINVAL;
+  if (d->kind != GSF_BF && d->kind != GSF_GF) return GSF_EINVAL;
+  if (d->ndim != 1 && d->ndim != 2) return GSF_EINVAL;
+  if (d->prec != GSF_F32 && d->prec != GSF_F64) return GSF_EINVAL;
+  if (d->radius < 1 || d->radius > kMaxRadius) return GSF_EINVAL;
+  if (d->dims[0] < 1) return GSF_EINVAL;
+  if (d->ndim == 2 && d->dims[1] < 1) return GSF_EINVAL;
+  const int64_t n = d->ndim == 1 ? d->dims[0] : d->dims[0] * d->dims[1];
+  if (d->ndim == 2 && (d->dims[0] > (int64_t)1 << 30 || d->dims[1] > (int64_t)1 << 30)) return GSF_EINVAL;
+  if (n > ((int64_t)1 << 34)) return GSF_EINVAL;
+  if (d->kind == GSF_BF) {
+    if (!(d->sigma_d > 0.0) || std::isnan(d->sigma_d)) return GSF_EINVAL;
+    if (!(d->sigma_r > 0.0) || std::isnan(d->sigma_r)) return GSF_EINVAL;
+  } else {
+    if (!(d->gf_eps >= 0.0) || !std::isfinite(d->gf_eps)) return GSF_EINVAL;
+  }
+  return GSF_OK;
+}
+
+// Operator workspace layout, in order, each region 256-byte aligned:
+//   BF: planes (nplanes*n), diag (n), sqd (n), deg (n doubles)
+//   GF: g (n), mu (n), inv (n), sqd (n), deg (n doubles), 4 scratch planes (n)
+size_t layout_operator(const gsf_operator_desc* d, Operator* op, char* base) {
+  const int64_t n = d->ndim == 1 ? d->dims[0] : d->dims[0] * d->dims[1];
+  const size_t elem = d->prec == GSF_F32 ? 4 : 8;
+  const size_t plane = align_up((size_t)n * elem, kAlign);
+  const size_t dplane = align_up((size_t)n * 8, kAlign);
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> void* {
+    void* p = base ? base + off : nullptr;
+    off += bytes;
+    return p;
+  };
+  if (op) {
+    std::memset(op, 0, sizeof(*op));
+    op->desc = *d;
+    op->n = n;
+    op->rows = d->ndim == 1 ? 1 : d->dims[0];
+    op->cols = d->ndim == 1 ? d->dims[0] : d->dims[1];
+    op->elem = elem;
+  }
+  if (d->kind == GSF_BF) {
+    const int k = d->ndim == 1 ? 2 * d->radius + 1 : (2 * d->radius + 1) * (2 * d->radius + 1);
+    const int np = (k - 1) / 2;
+    void* planes = take(align_up((size_t)np * n * elem, kAlign));
+    void* diag = take(plane);
+    void* sqd = take(plane);
+    void* deg = take(dplane);
+    if (op) {
+      op->nplanes = np;
+      op->planes = planes;
+      op->diag = diag;
+      op->sqd = sqd;
+      op->deg = (double*)deg;
+    }
+  } else {
+    void* g = take(plane);
+    void* mu = take(plane);
+    void* inv = take(plane);
+    void* sqd = take(plane);
+    void* deg = take(dplane);
+    take(4 * plane);  // apply scratch
+    if (op) {
+      op->g = g;
+      op->mu = mu;
+      op->inv = inv;
+      op->sqd = sqd;
+      op->deg = (double*)deg;
+    }
+  }
+  return off;
+}
+
+void* gf_scratch(const Operator& op) {
+  const size_t plane = align_up((size_t)op.n * op.elem, kAlign);
+  const size_t dplane = align_up((size_t)op.n * 8, kAlign);
+  return (char*)op.g + 4 * plane + dplane;
+}
+
+gsf_status apply_any(const Operator& op, int form, int m, const void* x, int64_t ldx, void* y, int64_t ldy,
+                     double* dot, int* nparts, hipStream_t s) {
+  if (op.desc.kind == GSF_BF) return launch_bf_apply(op, form, m, x, ldx, y, ldy, dot, nparts, s);
+  return launch_gf_apply(op, gf_scratch(op), form, m, x, ldx, y, ldy, s);
+}
+
+// Bump allocator over a caller workspace (nullptr base: size query).
+struct Carve {
+  char* base;
+  size_t off = 0;
+  void* take(size_t bytes) {
+    void* p = base ? base + off : nullptr;
+    off += align_up(bytes, kAlign);
+    return p;
+  }
+};
+
+double breakdown_tau(int prec) { return prec == GSF_F32 ? 1e-6 : 1e-13; }
+double drop_tol_of(int prec) { return prec == GSF_F32 ? 1e-6 : 1e-10; }
+
+struct CgWs {
+  void *z, *r, *p, *q;
+  double* partials;
+  CgState* st;
+};
+
+size_t carve_cg(const Operator& op, char* base, CgWs* w) {
+  Carve c{base};
+  const size_t v = (size_t)op.n * op.elem;
+  w->z = c.take(v);
+  w->r = c.take(v);
+  w->p = c.take(v);
+  w->q = c.take(v);
+  int nb = vec_blocks(op.n);
+  if (op.desc.kind == GSF_BF) {
+    const int ab = bf_apply_blocks(op, 1);
+    nb = ab > nb ? ab : nb;
+  }
+  w->partials = (double*)c.take((size_t)nb * 2 * sizeof(double));
+  w->st = (CgState*)c.take(sizeof(CgState));
+  return c.off;
+}
+
+struct LobWs {
+  void *X, *W, *P, *AX, *AW, *AP;
+  double* gram_partials;
+  double* gram_level2;
+  double* C;
+  double* theta;
+  double* vpart;
+  unsigned int* gram_counter;
+  LobpcgState* st;
+};
+
+int gram_blocks(int64_t n) {
+  int64_t b = (n + 1023) / 1024;
+  if (b < 1) b = 1;
+  if (b > kGramBlocks) b = kGramBlocks;
+  return (int)b;
+}
+
+size_t carve_lob(const Operator& op, int m, char* base, LobWs* w) {
+  Carve c{base};
+  const size_t blk = (size_t)op.n * m * op.elem;
+  w->X = c.take(blk);
+  w->W = c.take(blk);
+  w->P = c.take(blk);
+  w->AX = c.take(blk);
+  w->AW = c.take(blk);
+  w->AP = c.take(blk);
+  w->gram_partials = (double*)c.take((size_t)gram_blocks(op.n) * 7 * 256 * sizeof(double));
+  w->gram_level2 = (double*)c.take((size_t)kGramChunks * 7 * 256 * sizeof(double));
+  w->C = (double*)c.take(24 * 8 * sizeof(double));
+  w->theta = (double*)c.take(8 * sizeof(double));
+  w->vpart = (double*)c.take((size_t)vec_blocks(op.n) * 17 * sizeof(double));
+  w->gram_counter = (unsigned int*)c.take(64);
+  w->st = (LobpcgState*)c.take(sizeof(LobpcgState));
+  return c.off;
+}
+
+StartDegrees start_degrees(int ndim, int m) {
+  StartDegrees d{};
+  if (ndim == 1) {
+    for (int j = 0; j < m; ++j) {
+      d.a[j] = 0;
+      d.b[j] = j;
+    }
+    return d;
+  }
+  int j = 0;
+  for (int s = 0; j < m; ++s)
+    for (int a = 0; a <= s && j < m; ++a, ++j) {
+      d.a[j] = a;
+      d.b[j] = s - a;
+    }
+  return d;
+}
+
+gsf_status hip_ok(hipError_t e) { return e == hipSuccess ? GSF_OK : GSF_EDEVICE; }
+
+#define GSF_TRY(expr)                 \
+  do {                                \
+    gsf_status _st = (expr);          \
+    if (_st != GSF_OK) return _st;    \
+  } while (0)
+
+}  // namespace
+
+gsf_status launch_lob_state_init(LobpcgState* dst, const LobpcgState& v, hipStream_t s) {
+  lob_state_init_kernel<<<1, 1, 0, s>>>(dst, v);
+  return hip_ok(hipGetLastError());
+}
+gsf_status launch_cg_state_init(CgState* dst, const CgState& v, hipStream_t s) {
+  cg_state_init_kernel<<<1, 1, 0, s>>>(dst, v);
+  return hip_ok(hipGetLastError());
+}
+
+}  // namespace gsf
+
+using namespace gsf;
+
+extern "C" {
+
+gsf_status gsf_block_gram_workspace_bytes(int64_t n, size_t* bytes);
+
+int gsf_version(void) { return 1; }
+
+const char* gsf_status_string(int status) {
+  switch (status) {
+    case GSF_OK: return "ok";
+    case GSF_EINVAL: return "invalid argument";
+    case GSF_ENOMEM: return "workspace too small";
+    case GSF_EDEVICE: return "HIP runtime error";
+    case GSF_ENOTCONV: return "tolerance not reached";
+    case GSF_EBREAKDOWN: return "iteration broke down";
+    default: return "unknown status";
+  }
+}
+
+gsf_status gsf_operator_workspace_bytes(const gsf_operator_desc* desc, size_t* bytes) {
+  if (bytes == nullptr) return GSF_EINVAL;
+  GSF_TRY(validate_desc(desc));
+  *bytes = layout_operator(desc, nullptr, nullptr);
+  return GSF_OK;
+}
+
+gsf_status gsf_build_operator(const gsf_operator_desc* desc, const void* guidance, void* ws, size_t ws_bytes,
+                              void* stream, gsf_operator** out) {
+  if (out == nullptr || guidance == nullptr || ws == nullptr) return GSF_EINVAL;
+  GSF_TRY(validate_desc(desc));
+  if (ws_bytes < layout_operator(desc, nullptr, nullptr)) return GSF_ENOMEM;
+  gsf_operator* h = new (std::nothrow) gsf_operator;
+  if (h == nullptr) return GSF_EDEVICE;
+  layout_operator(desc, &h->op, (char*)ws);
+  hipStream_t s = (hipStream_t)stream;
+  gsf_status st = desc->kind == GSF_BF ? launch_bf_build(h->op, guidance, s) : launch_gf_build(h->op, guidance, s);
+  if (st != GSF_OK) {
+    delete h;
+    return st;
+  }
+  *out = h;
+  return GSF_OK;
+}
+
+gsf_status gsf_operator_get_layout(const gsf_operator* h, gsf_operator_layout* out) {
+  if (h == nullptr || out == nullptr) return GSF_EINVAL;
+  const Operator& op = h->op;
+  std::memset(out, 0, sizeof(*out));
+  out->kind = op.desc.kind;
+  out->ndim = op.desc.ndim;
+  out->prec = op.desc.prec;
+  out->radius = op.desc.radius;
+  out->n = op.n;
+  out->nplanes = op.nplanes;
+  out->planes = op.planes;
+  out->inv_sqrt_d = op.diag;
+  out->sqrt_d = op.sqd;
+  out->degree = op.deg;
+  out->guidance = op.g;
+  out->mu = op.mu;
+  out->inv = op.inv;
+  return GSF_OK;
+}
+
+void gsf_destroy_operator(gsf_operator* h) { delete h; }
+
+gsf_status gsf_apply(const gsf_operator* h, int form, int m, const void* x, void* y, void* stream) {
+  if (h == nullptr || x == nullptr || y == nullptr) return GSF_EINVAL;
+  if (form != GSF_FORM_N && form != GSF_FORM_LSYM && form != GSF_FORM_RW) return GSF_EINVAL;
+  if (m < 1 || m > kMaxBlock) return GSF_EINVAL;
+  const Operator& op = h->op;
+  const size_t bytes = (size_t)op.n * m * op.elem;
+  const char *xa = (const char*)x, *ya = (const char*)y;
+  if (xa < ya + bytes && ya < xa + bytes) return GSF_EINVAL;  // overlap
+  return apply_any(op, form, m, x, m, y, m, nullptr, nullptr, (hipStream_t)stream);
+}
+
+gsf_status gsf_solver_workspace_bytes(const gsf_operator* h, int method, int m, size_t* bytes) {
+  if (h == nullptr || bytes == nullptr) return GSF_EINVAL;
+  const Operator& op = h->op;
+  if (method == GSF_METHOD_POWER) {
+    *bytes = 2 * align_up((size_t)op.n * op.elem, 256);
+  } else if (method == GSF_METHOD_CG) {
+    CgWs w;
+    *bytes = carve_cg(op, nullptr, &w);
+  } else if (method == GSF_METHOD_LOBPCG) {
+    if (m < 1 || m > kMaxBlock) return GSF_EINVAL;
+    LobWs w;
+    *bytes = carve_lob(op, m, nullptr, &w);
+  } else {
+    return GSF_EINVAL;
+  }
+  return GSF_OK;
+}
+
+gsf_status gsf_power_filter(const gsf_operator* h, const void* x0, void* x_out, int kmax, void* ws,
+                            size_t ws_bytes, void* stream) {
+  if (h == nullptr || x0 == nullptr || x_out == nullptr || kmax < 0) return GSF_EINVAL;
+  const Operator& op = h->op;
+  const size_t v = align_up((size_t)op.n * op.elem, 256);
+  if (kmax > 0 && (ws == nullptr || ws_bytes < 2 * v)) return GSF_ENOMEM;
+  hipStream_t s = (hipStream_t)stream;
+  if (kmax == 0) return hip_ok(hipMemcpyAsync(x_out, x0, (size_t)op.n * op.elem, hipMemcpyDeviceToDevice, s));
+  char* a = (char*)ws;
+  char* b = a + v;
+  GSF_TRY(launch_scale(op, x0, a, 0, s));  // z = D^1/2 x
+  for (int k = 0; k < kmax; ++k) {
+    GSF_TRY(apply_any(op, GSF_FORM_N, 1, a, 1, b, 1, nullptr, nullptr, s));
+    char* t = a;
+    a = b;
+    b = t;
+  }
+  return launch_scale(op, a, x_out, 1, s);  // x = D^-1/2 z
+}
+
+gsf_status gsf_cg_filter(const gsf_operator* h, const void* x0, void* x_out, int kmax, double tol, void* ws,
+                         size_t ws_bytes, gsf_cg_info* info, void* stream) {
+  if (h == nullptr || x0 == nullptr || x_out == nullptr || kmax < 0 || !(tol >= 0.0) || !std::isfinite(tol))
+    return GSF_EINVAL;
+  const Operator& op = h->op;
+  CgWs w;
+  if (ws == nullptr || ws_bytes < carve_cg(op, nullptr, &w)) return GSF_ENOMEM;
+  carve_cg(op, (char*)ws, &w);
+  hipStream_t s = (hipStream_t)stream;
+  CgState init{};
+  init.tol = tol;
+  init.tau = breakdown_tau(op.desc.prec);
+  GSF_TRY(launch_cg_state_init(w.st, init, s));
+  GSF_TRY(launch_scale(op, x0, w.z, 0, s));
+  GSF_TRY(apply_any(op, GSF_FORM_LSYM, 1, w.z, 1, w.r, 1, nullptr, nullptr, s));
+  GSF_TRY(launch_cg_init(op, w.z, w.r, w.partials, w.st, s));
+  for (int k = 1; k <= kmax; ++k) {
+    GSF_TRY(launch_cg_pupdate(op, w.r, w.p, w.st, s));
+    int nparts = 0;
+    if (op.desc.kind == GSF_BF) {
+      GSF_TRY(apply_any(op, GSF_FORM_LSYM, 1, w.p, 1, w.q, 1, w.partials, &nparts, s));
+    } else {
+      GSF_TRY(apply_any(op, GSF_FORM_LSYM, 1, w.p, 1, w.q, 1, nullptr, nullptr, s));
+      GSF_TRY(launch_dot(op, w.p, w.q, w.partials, &nparts, w.st, s));
+    }
+    GSF_TRY(launch_cg_alpha(w.partials, nparts, w.st, s));
+    GSF_TRY(launch_cg_update(op, w.z, w.r, w.p, w.q, w.partials, w.st, s));
+  }
+  GSF_TRY(launch_scale(op, w.z, x_out, 1, s));
+  if (info == nullptr) return GSF_OK;
+  CgState host{};
+  GSF_TRY(hip_ok(hipMemcpyAsync(&host, w.st, sizeof(host), hipMemcpyDeviceToHost, s)));
+  GSF_TRY(hip_ok(hipStreamSynchronize(s)));
+  gsf_status status = (gsf_status)host.status;
+  if (status == GSF_OK && tol > 0.0 && host.active && !(host.rho <= host.tol2)) status = GSF_ENOTCONV;
+  info->iters = host.iters;
+  info->status = status;
+  info->res0 = host.res0;
+  info->res = std::sqrt(host.rho > 0.0 ? host.rho : 0.0);
+  return status;
+}
+
+gsf_status gsf_lobpcg_filter(const gsf_operator* h, const void* x0, void* x_out, int m, int kmax, double tol,
+                             int constraint, const gsf_precond* T, void* ritz_vecs, void* ws, size_t ws_bytes,
+                             gsf_lobpcg_info* info, void* stream) {
+  if (h == nullptr || x0 == nullptr || x_out == nullptr || kmax < 0 || !(tol >= 0.0) || !std::isfinite(tol))
+    return GSF_EINVAL;
+  if (m < 1 || m > kMaxBlock) return GSF_EINVAL;
+  if (T != nullptr) return GSF_EINVAL;  // learned preconditioner: not in this entry point yet
+  const Operator& op = h->op;
+  LobWs w;
+  if (ws == nullptr || ws_bytes < carve_lob(op, m, nullptr, &w)) return GSF_ENOMEM;
+  carve_lob(op, m, (char*)ws, &w);
+  hipStream_t s = (hipStream_t)stream;
+
+  LobpcgState init{};
+  init.tol = tol;
+  init.drop_tol = drop_tol_of(op.desc.prec);
+  init.zero_tol = breakdown_tau(op.desc.prec);
+  init.m = m;
+  init.active = 1;
+  init.status = GSF_OK;
+  GSF_TRY(launch_lob_state_init(w.st, init, s));
+
+  LobArgs a{};
+  a.prec = op.desc.prec;
+  a.n = op.n;
+  a.rows = op.rows;
+  a.cols = op.cols;
+  a.ndim = op.desc.ndim;
+  a.m = m;
+  a.constraint = constraint ? 1 : 0;
+  a.x0 = x0;
+  a.sqd = op.sqd;
+  a.X = w.X;
+  a.W = w.W;
+  a.P = w.P;
+  a.AX = w.AX;
+  a.AW = w.AW;
+  a.AP = w.AP;
+  a.C = w.C;
+  a.vpart = w.vpart;
+  a.st = w.st;
+  a.xout = x_out;
+  a.ritz = ritz_vecs;
+  const int nb = vec_blocks(op.n);
+  const StartDegrees deg = start_degrees(op.desc.ndim, m);
+
+  GramArgs g{};
+  g.m = m;
+  g.n = op.n;
+  g.nparts = gram_blocks(op.n);
+  g.partials = w.gram_partials;
+  g.level2 = w.gram_level2;
+  g.counter = w.gram_counter;
+  g.active = &w.st->active;
+  RRArgs rr{};
+  rr.C = w.C;
+  rr.theta = w.theta;
+  rr.st = w.st;
+  rr.drop_tol = init.drop_tol;
+  rr.zero_tol = init.zero_tol;
+
+  GSF_TRY(hip_ok(hipMemsetAsync(w.gram_counter, 0, 64, s)));
+  if (constraint) GSF_TRY(lob_launch_ynorm(a, nb, s));
+  GSF_TRY(lob_launch_mkernel(0, a, nb, m, 1, deg, s));  // X0
+  if (constraint) GSF_TRY(lob_launch_project(a, w.X, nb, s));
+  GSF_TRY(apply_any(op, GSF_FORM_LSYM, m, w.X, m, w.AX, m, nullptr, nullptr, s));
+  // start-block Rayleigh-Ritz
+  g.ns = m;
+  g.S[0] = w.X;
+  g.AS[0] = w.AX;
+  rr.init = 1;
+  GSF_TRY(lob_launch_gram(g, rr, op.desc.prec, s));
+  rr.init = 0;
+  GSF_TRY(lob_launch_mkernel(1, a, nb, m, 1, deg, s));  // X = X0 C, AX, W = R
+  for (int k = 0; k < kmax; ++k) {
+    if (constraint) GSF_TRY(lob_launch_project(a, w.W, nb, s));
+    GSF_TRY(apply_any(op, GSF_FORM_LSYM, m, w.W, m, w.AW, m, nullptr, nullptr, s));
+    const int ns = (k == 0) ? 2 * m : 3 * m;
+    g.ns = ns;
+    g.S[0] = w.X;
+    g.S[1] = w.W;
+    g.S[2] = w.P;
+    g.AS[0] = w.AX;
+    g.AS[1] = w.AW;
+    g.AS[2] = w.AP;
+    GSF_TRY(lob_launch_gram(g, rr, op.desc.prec, s));
+    GSF_TRY(lob_launch_mkernel(1, a, nb, ns, 0, deg, s));
+  }
+  GSF_TRY(lob_launch_mkernel(2, a, nb, m, 0, deg, s));  // X^T z0, Y^T z0
+  GSF_TRY(lob_launch_mkernel(3, a, nb, m, 0, deg, s));  // x_out
+  if (info == nullptr) return GSF_OK;
+  LobpcgState host{};
+  GSF_TRY(hip_ok(hipMemcpyAsync(&host, w.st, sizeof(host), hipMemcpyDeviceToHost, s)));
+  GSF_TRY(hip_ok(hipStreamSynchronize(s)));
+  gsf_status status = (gsf_status)host.status;
+  double mx = 0.0;
+  for (int j = 0; j < m; ++j) mx = host.res[j] > mx ? host.res[j] : mx;
+  if (status == GSF_OK && tol > 0.0 && mx > tol) status = GSF_ENOTCONV;
+  info->iters = host.iters;
+  info->status = status;
+  info->dropped = host.dropped;
+  info->m = m;
+  for (int j = 0; j < 8; ++j) {
+    info->res[j] = j < m ? host.res[j] : 0.0;
+    info->theta[j] = j < m ? host.theta[j] : 0.0;
+  }
+  return status;
+}
+
+// ---- diagnostics: the Gram and Rayleigh-Ritz kernels on caller data ----------
+// Gram pair (S^T A S, S^T S) of S = [S0, S1, S2] (nb blocks of m columns,
+// point-major, element type prec) with AS = [A0, A1, A2]; results copied to
+// host arrays GA, GB (ns x ns, ns = nb*m).  Synchronizes the stream.
+gsf_status gsf_block_gram(int prec, int64_t n, int m, int nb, const void* const* S, const void* const* AS,
+                          double* GA, double* GB, void* ws, size_t ws_bytes, void* stream) {
+  if (n < 1 || m < 1 || m > 8 || nb < 1 || nb > 3 || S == nullptr || AS == nullptr || GA == nullptr ||
+      GB == nullptr)
+    return GSF_EINVAL;
+  if (prec != GSF_F32 && prec != GSF_F64) return GSF_EINVAL;
+  size_t need = 0;
+  gsf_block_gram_workspace_bytes(n, &need);
+  if (ws == nullptr || ws_bytes < need) return GSF_ENOMEM;
+  const int gb = gram_blocks(n);
+  Carve w{(char*)ws};
+  GramArgs g{};
+  g.ns = nb * m;
+  g.m = m;
+  g.n = n;
+  g.nparts = gb;
+  g.partials = (double*)w.take((size_t)gb * 7 * 256 * 8);
+  g.level2 = (double*)w.take((size_t)kGramChunks * 7 * 256 * 8);
+  double* gout = (double*)w.take(2 * 24 * 24 * 8);
+  double* C = (double*)w.take(24 * 8 * 8);
+  double* th = (double*)w.take(64);
+  int* kept = (int*)w.take(256);
+  g.counter = (unsigned int*)w.take(64);
+  for (int b = 0; b < nb; ++b) {
+    g.S[b] = S[b];
+    g.AS[b] = AS[b];
+  }
+  RRArgs r{};
+  r.C = C;
+  r.theta = th;
+  r.drop_tol = 1e-10;
+  r.zero_tol = 0.0;
+  r.gram_out = gout;
+  r.kept_out = kept;
+  r.nkept_out = kept + 32;
+  hipStream_t s = (hipStream_t)stream;
+  GSF_TRY(hip_ok(hipMemsetAsync(g.counter, 0, 64, s)));
+  GSF_TRY(lob_launch_gram(g, r, prec, s));
+  const int ns = nb * m;
+  GSF_TRY(hip_ok(hipMemcpyAsync(GA, gout, (size_t)ns * ns * 8, hipMemcpyDeviceToHost, s)));
+  GSF_TRY(hip_ok(hipMemcpyAsync(GB, gout + ns * ns, (size_t)ns * ns * 8, hipMemcpyDeviceToHost, s)));
+  return hip_ok(hipStreamSynchronize(s));
+}
+
+gsf_status gsf_block_gram_workspace_bytes(int64_t n, size_t* bytes) {
+  if (n < 1 || bytes == nullptr) return GSF_EINVAL;
+  Carve c{nullptr};
+  const int gb = gram_blocks(n);
+  c.take((size_t)gb * 7 * 256 * 8);
+  c.take((size_t)kGramChunks * 7 * 256 * 8);
+  c.take(2 * 24 * 24 * 8);
+  c.take(24 * 8 * 8);
+  c.take(64);
+  c.take(256);
+  c.take(64);
+  *bytes = c.off;
+  return GSF_OK;
+}
+
+// Rayleigh-Ritz step alone: GA, GB (ns x ns, host, row-major) -> theta (m),
+// C (ns x m, row-major), kept (ns), *nkept.  Uses a device workspace of
+// gsf_rr_workspace_bytes() bytes; synchronizes the stream.
+gsf_status gsf_rayleigh_ritz(int ns, int m, const double* GA, const double* GB, double drop_tol, double zero_tol,
+                             double* theta, double* C, int* kept, int* nkept, void* ws, size_t ws_bytes,
+                             void* stream) {
+  if (ns < 1 || ns > 24 || m < 1 || m > 8 || m > ns || !GA || !GB || !theta || !C || !kept || !nkept)
+    return GSF_EINVAL;
+  if (ws == nullptr || ws_bytes < 8192 + 4096) return GSF_ENOMEM;
+  hipStream_t s = (hipStream_t)stream;
+  double* G = (double*)ws;
+  double* Cd = G + 2 * 24 * 24;
+  double* thd = Cd + 24 * 8;
+  int* kd = (int*)(thd + 8);
+  GSF_TRY(hip_ok(hipMemcpyAsync(G, GA, (size_t)ns * ns * 8, hipMemcpyHostToDevice, s)));
+  GSF_TRY(hip_ok(hipMemcpyAsync(G + ns * ns, GB, (size_t)ns * ns * 8, hipMemcpyHostToDevice, s)));
+  RRArgs r{};
+  r.C = Cd;
+  r.theta = thd;
+  r.drop_tol = drop_tol;
+  r.zero_tol = zero_tol;
+  r.kept_out = kd;
+  r.nkept_out = kd + 32;
+  GSF_TRY(lob_launch_rr_only(G, ns, m, r, s));
+  GSF_TRY(hip_ok(hipMemcpyAsync(theta, thd, (size_t)m * 8, hipMemcpyDeviceToHost, s)));
+  GSF_TRY(hip_ok(hipMemcpyAsync(C, Cd, (size_t)ns * m * 8, hipMemcpyDeviceToHost, s)));
+  GSF_TRY(hip_ok(hipMemcpyAsync(kept, kd, (size_t)ns * 4, hipMemcpyDeviceToHost, s)));
+  GSF_TRY(hip_ok(hipMemcpyAsync(nkept, kd + 32, 4, hipMemcpyDeviceToHost, s)));
+  return hip_ok(hipStreamSynchronize(s));
+}
+
+size_t gsf_rr_workspace_bytes(void) { return 8192 + 4096; }
+
+}  // extern "C"

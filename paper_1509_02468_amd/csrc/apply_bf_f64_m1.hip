@@ -1,0 +1,10 @@
+// BF apply instantiations for double, block width 1.
+#include "apply_bf_impl.h"
+
+namespace gsf {
+template <typename T, int M>
+void bf_apply_tm(const bfk::ApplyArgs& a, int ndim, int r, hipStream_t s, int* nb) {
+  bfk::launch_bf_r<T, M>(a, ndim, r, s, nb);
+}
+template void bf_apply_tm<double, 1>(const bfk::ApplyArgs&, int, int, hipStream_t, int*);
+}  // namespace gsf

@@ -1,0 +1,178 @@
+// Operator construction: BF weights and normalisation (Section 2, eq. (2),
+// eq. (4); Section 4 normalisation) and GF window statistics (Section 3,
+// Algorithm 1).  Everything is computed in FP64 and rounded once to the
+// storage type.
+#include <cmath>
+
+#include "gsf_internal.h"
+
+namespace gsf {
+namespace {
+
+struct BfParams {
+  int64_t n, rows, cols;
+  int radius, ndim;
+  double cs;  // 1 / (2 sigma_d^2), 0 for sigma_d = inf
+  double cr;  // 1 / (2 sigma_r^2), 0 for sigma_r = inf
+};
+
+// eq. (2) in one exponential: exp(-(|o|^2 cs + (g_i - g_j)^2 cr)).  The
+// argument is bitwise the same for (i, j) and (j, i), so W is exactly
+// symmetric wherever it is evaluated.
+__device__ __forceinline__ double bf_weight(double gi, double gj, int o2, const BfParams& p) {
+  const double dg = gi - gj;
+  return exp(-((double)o2 * p.cs + dg * dg * p.cr));
+}
+
+// K1: d_i = sum over the truncated window of w_ij (self-loop w_ii = 1 included).
+template <typename T>
+__global__ void __launch_bounds__(kThreads) bf_degree_kernel(const T* __restrict__ g, double* __restrict__ deg,
+                                                             BfParams p) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= p.n) return;
+  const int r = p.radius;
+  const double gi = (double)g[i];
+  double d = 0.0;
+  if (p.ndim == 1) {
+    for (int o = -r; o <= r; ++o) {
+      const int64_t j = i + o;
+      if (j < 0 || j >= p.n) continue;
+      d += bf_weight(gi, (double)g[j], o * o, p);
+    }
+  } else {
+    const int64_t y = i / p.cols, x = i - y * p.cols;
+    for (int dy = -r; dy <= r; ++dy) {
+      const int64_t yy = y + dy;
+      if (yy < 0 || yy >= p.rows) continue;
+      for (int dx = -r; dx <= r; ++dx) {
+        const int64_t xx = x + dx;
+        if (xx < 0 || xx >= p.cols) continue;
+        d += bf_weight(gi, (double)g[yy * p.cols + xx], dy * dy + dx * dx, p);
+      }
+    }
+  }
+  deg[i] = d;
+}
+
+// K2: half-window planes of the symmetric weights w_{i,i+o} (0 off the grid),
+// 1/sqrt(d_i) and sqrt(d_i).  Plane order: 1D o = 1..r; 2D (0, 1..r) then
+// dy = 1..r with dx = -r..r.
+template <typename T>
+__global__ void __launch_bounds__(kThreads) bf_fold_kernel(const T* __restrict__ g, const double* __restrict__ deg,
+                                                           T* __restrict__ planes, T* __restrict__ diag,
+                                                           T* __restrict__ sqd, BfParams p) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= p.n) return;
+  const int r = p.radius;
+  const double gi = (double)g[i];
+  const double di = deg[i];
+  diag[i] = (T)(1.0 / sqrt(di));
+  sqd[i] = (T)sqrt(di);
+  int q = 0;
+  if (p.ndim == 1) {
+    for (int o = 1; o <= r; ++o, ++q) {
+      const int64_t j = i + o;
+      double v = 0.0;
+      if (j < p.n) v = bf_weight(gi, (double)g[j], o * o, p);
+      planes[(int64_t)q * p.n + i] = (T)v;
+    }
+  } else {
+    const int64_t y = i / p.cols, x = i - y * p.cols;
+    for (int dy = 0; dy <= r; ++dy) {
+      const int dx0 = (dy == 0) ? 1 : -r;
+      for (int dx = dx0; dx <= r; ++dx, ++q) {
+        const int64_t yy = y + dy, xx = x + dx;
+        double v = 0.0;
+        if (yy < p.rows && xx >= 0 && xx < p.cols) {
+          const int64_t j = yy * p.cols + xx;
+          v = bf_weight(gi, (double)g[j], dy * dy + dx * dx, p);
+        }
+        planes[(int64_t)q * p.n + i] = (T)v;
+      }
+    }
+  }
+}
+
+struct GfParams {
+  int64_t n, rows, cols;
+  int radius, ndim;
+  double eps, omega;
+};
+
+// K3: mu_k = mean of g over the truncated window, inv_k = 1/(corr_g - mu^2 + eps)
+// (Algorithm 1, mean_g, corr_g, var_g), d_k = N_k/|w|, sqrt(d_k); copy of g.
+template <typename T>
+__global__ void __launch_bounds__(kThreads) gf_stats_kernel(const T* __restrict__ g, T* __restrict__ gcopy,
+                                                            T* __restrict__ mu, T* __restrict__ inv,
+                                                            T* __restrict__ sqd, double* __restrict__ deg,
+                                                            GfParams p) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= p.n) return;
+  const int r = p.radius;
+  double s1 = 0.0, s2 = 0.0, cnt = 0.0;
+  if (p.ndim == 1) {
+    const int64_t lo = k - r < 0 ? 0 : k - r, hi = k + r >= p.n ? p.n - 1 : k + r;
+    for (int64_t j = lo; j <= hi; ++j) {
+      const double v = (double)g[j];
+      s1 += v;
+      s2 += v * v;
+    }
+    cnt = (double)(hi - lo + 1);
+  } else {
+    const int64_t y = k / p.cols, x = k - y * p.cols;
+    const int64_t y0 = y - r < 0 ? 0 : y - r, y1 = y + r >= p.rows ? p.rows - 1 : y + r;
+    const int64_t x0 = x - r < 0 ? 0 : x - r, x1 = x + r >= p.cols ? p.cols - 1 : x + r;
+    for (int64_t yy = y0; yy <= y1; ++yy)
+      for (int64_t xx = x0; xx <= x1; ++xx) {
+        const double v = (double)g[yy * p.cols + xx];
+        s1 += v;
+        s2 += v * v;
+      }
+    cnt = (double)((y1 - y0 + 1) * (x1 - x0 + 1));
+  }
+  const double m = s1 / cnt;
+  const double var = s2 / cnt - m * m;
+  mu[k] = (T)m;
+  inv[k] = (T)(1.0 / (var + p.eps));
+  const double d = cnt / p.omega;
+  deg[k] = d;
+  sqd[k] = (T)sqrt(d);
+  gcopy[k] = g[k];
+}
+
+inline double inv_two_sigma2(double s) { return std::isinf(s) ? 0.0 : 1.0 / (2.0 * s * s); }
+
+}  // namespace
+
+gsf_status launch_bf_build(const Operator& op, const void* guidance, hipStream_t s) {
+  BfParams p{op.n, op.rows, op.cols, op.desc.radius, op.desc.ndim, inv_two_sigma2(op.desc.sigma_d),
+             inv_two_sigma2(op.desc.sigma_r)};
+  const unsigned grid = (unsigned)((op.n + kThreads - 1) / kThreads);
+  if (op.desc.prec == GSF_F32) {
+    bf_degree_kernel<float><<<grid, kThreads, 0, s>>>((const float*)guidance, op.deg, p);
+    bf_fold_kernel<float><<<grid, kThreads, 0, s>>>((const float*)guidance, op.deg, (float*)op.planes,
+                                                    (float*)op.diag, (float*)op.sqd, p);
+  } else {
+    bf_degree_kernel<double><<<grid, kThreads, 0, s>>>((const double*)guidance, op.deg, p);
+    bf_fold_kernel<double><<<grid, kThreads, 0, s>>>((const double*)guidance, op.deg, (double*)op.planes,
+                                                     (double*)op.diag, (double*)op.sqd, p);
+  }
+  return hipGetLastError() == hipSuccess ? GSF_OK : GSF_EDEVICE;
+}
+
+gsf_status launch_gf_build(const Operator& op, const void* guidance, hipStream_t s) {
+  const double omega = op.desc.ndim == 1 ? (double)(2 * op.desc.radius + 1)
+                                         : (double)((2 * op.desc.radius + 1) * (2 * op.desc.radius + 1));
+  GfParams p{op.n, op.rows, op.cols, op.desc.radius, op.desc.ndim, op.desc.gf_eps, omega};
+  const unsigned grid = (unsigned)((op.n + kThreads - 1) / kThreads);
+  if (op.desc.prec == GSF_F32) {
+    gf_stats_kernel<float><<<grid, kThreads, 0, s>>>((const float*)guidance, (float*)op.g, (float*)op.mu,
+                                                     (float*)op.inv, (float*)op.sqd, op.deg, p);
+  } else {
+    gf_stats_kernel<double><<<grid, kThreads, 0, s>>>((const double*)guidance, (double*)op.g, (double*)op.mu,
+                                                      (double*)op.inv, (double*)op.sqd, op.deg, p);
+  }
+  return hipGetLastError() == hipSuccess ? GSF_OK : GSF_EDEVICE;
+}
+
+}  // namespace gsf

@@ -1,0 +1,135 @@
+// Internal declarations of libgsf (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "gsf.h"
+
+namespace gsf {
+
+constexpr int kMaxRadius = 8;
+constexpr int kMaxBlock = 8;   // largest LOBPCG block size m
+constexpr int kThreads = 256;  // threads per workgroup of the streaming kernels
+
+// Host-side description of a built operator.  All device pointers point into
+// the caller's operator workspace.
+struct Operator {
+  gsf_operator_desc desc;
+  int64_t n;        // grid points
+  int64_t rows;     // 2D: H, 1D: 1
+  int64_t cols;     // 2D: W, 1D: n
+  int nplanes;      // BF half-window planes
+  size_t elem;      // sizeof element type
+  void* planes;     // BF: nplanes * n symmetric weights w_{i,i+o}
+  void* diag;       // BF: 1/sqrt(d)
+  void* sqd;        // sqrt(d)
+  double* deg;      // d (FP64)
+  void* g;          // GF: guidance copy
+  void* mu;         // GF: window means
+  void* inv;        // GF: 1/(var + eps)
+};
+
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// ---------------------------------------------------------------------------
+// device helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Sum NV values over the whole workgroup (blockDim.x a multiple of 64,
+// at most 1024 threads) in a fixed order; the result is valid in thread 0.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double* lds /* NV * 16 */) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nwaves = blockDim.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double s = wave_sum(v[k]);
+    if (lane == 0) lds[k * 16 + wave] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      double s = 0.0;
+      for (int w = 0; w < nwaves; ++w) s += lds[k * 16 + w];
+      v[k] = s;
+    }
+  }
+  __syncthreads();
+}
+
+// Device-coherent load (bypasses the non-coherent per-CU cache).
+template <typename T>
+__device__ __forceinline__ T load_coherent(const T* p) {
+  return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// "Last workgroup" detection for one-pass reductions: every workgroup has
+// written its partials before calling this; the workgroup that arrives last
+// returns true (uniformly over its threads) and may then read all partials.
+// The counter is left at zero for the next launch.
+__device__ __forceinline__ bool arrive_last(unsigned int* counter, unsigned int nblocks) {
+  __shared__ int s_last;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned int prev = atomicAdd(counter, 1u);
+    s_last = (prev == nblocks - 1) ? 1 : 0;
+    if (s_last) atomicExch(counter, 0u);
+  }
+  __syncthreads();
+  if (s_last) __threadfence();
+  return s_last != 0;
+}
+
+// Sum partials[b * stride + k] over b = 0..nparts-1 for k < NV in a fixed
+// order (independent of which workgroup runs it).  Result valid in thread 0.
+template <int NV>
+__device__ __forceinline__ void reduce_partials(const double* partials, int nparts, int stride,
+                                                double (&out)[NV], double* lds) {
+#pragma unroll
+  for (int k = 0; k < NV; ++k) out[k] = 0.0;
+  for (int b = threadIdx.x; b < nparts; b += blockDim.x) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) out[k] += load_coherent(partials + (size_t)b * stride + k);
+  }
+  block_sum<NV>(out, lds);
+}
+
+// Map a workgroup index to a tile so that each of the 8 XCDs (workgroups are
+// dispatched round-robin over them) walks a contiguous band of tiles: tiles
+// sharing halos then share that XCD's L2.
+__device__ __forceinline__ int xcd_tile(int b, int ntiles) {
+  const int q = ntiles >> 3, rem = ntiles & 7;
+  const int k = b & 7, l = b >> 3;
+  return k * q + (k < rem ? k : rem) + l;
+}
+
+// ---------------------------------------------------------------------------
+// launchers (implemented in the .hip files)
+// ---------------------------------------------------------------------------
+gsf_status launch_bf_build(const Operator& op, const void* guidance, hipStream_t s);
+gsf_status launch_gf_build(const Operator& op, const void* guidance, hipStream_t s);
+
+// y = F x (F: form) for an m-column block; x and y have leading dimensions
+// ldx / ldy (elements between consecutive grid points) and start at column
+// offsets already applied by the caller.  If dot_partials != nullptr (m = 1
+// only) every workgroup b writes sum_i x_i y_i of its points to
+// dot_partials[b]; *nparts receives the number of workgroups.
+gsf_status launch_apply(const Operator& op, int form, int m, const void* x, int64_t ldx, void* y,
+                        int64_t ldy, double* dot_partials, int* nparts, hipStream_t s);
+int apply_num_blocks(const Operator& op, int m);
+
+}  // namespace gsf
+
+struct gsf_operator {
+  gsf::Operator op;
+};

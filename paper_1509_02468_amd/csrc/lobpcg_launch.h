@@ -1,0 +1,65 @@
+// Argument blocks and launchers of the LOBPCG kernels.
+#pragma once
+
+#include "gsf_internal.h"
+#include "solver_state.h"
+
+namespace gsf {
+
+constexpr int kGramChunks = 8;   // second-level split of the Gram partial reduction
+constexpr int kGramBlocks = 256; // workgroups of the Gram kernel (at most)
+
+struct LobArgs {
+  int prec;
+  int64_t n, rows, cols;
+  int ndim, m, constraint;
+  const void* x0;
+  const void* sqd;
+  void *X, *W, *P, *AX, *AW, *AP;
+  const double* C;     // ns x m coefficients of the last Rayleigh-Ritz step
+  double* vpart;       // per-workgroup partial sums
+  LobpcgState* st;
+  void* xout;
+  void* ritz;          // nullable
+};
+
+struct StartDegrees {
+  int a[8];  // row (2D) degree of phi_j
+  int b[8];  // column / sample degree of phi_j
+};
+
+struct GramArgs {
+  const void* S[3];
+  const void* AS[3];
+  int ns, m;
+  int64_t n;
+  int nparts;          // workgroups of the Gram kernel
+  double* partials;    // nparts x tiles x 256
+  double* level2;      // kGramChunks x tiles x 256
+  unsigned int* counter;
+  const int* active;   // nullable
+};
+
+struct RRArgs {
+  double* C;
+  double* theta;
+  LobpcgState* st;     // nullable
+  double drop_tol, zero_tol;
+  double* gram_out;    // nullable: GA then GB (ns x ns)
+  int* kept_out;       // nullable
+  int* nkept_out;      // nullable
+  int init;            // 1 for the start-block Rayleigh-Ritz
+};
+
+int gram_tiles_total(int ns);
+gsf_status lob_launch_ynorm(const LobArgs& a, int nb, hipStream_t s);
+// which: 0 start, 1 update (ns, first), 2 output dots, 3 output
+gsf_status lob_launch_mkernel(int which, const LobArgs& a, int nb, int ns, int first, StartDegrees deg,
+                              hipStream_t s);
+gsf_status lob_launch_project(const LobArgs& a, void* B, int nb, hipStream_t s);
+gsf_status lob_launch_gram(const GramArgs& g, const RRArgs& r, int prec, hipStream_t s);
+gsf_status lob_launch_rr_only(const double* G, int ns, int m, const RRArgs& r, hipStream_t s);
+gsf_status launch_lob_state_init(LobpcgState* dst, const LobpcgState& v, hipStream_t s);
+gsf_status launch_cg_state_init(CgState* dst, const CgState& v, hipStream_t s);
+
+}  // namespace gsf

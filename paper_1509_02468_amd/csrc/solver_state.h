@@ -1,0 +1,47 @@
+// Device-resident solver state (one small struct per solver call).
+#pragma once
+
+#include <cstdint>
+
+namespace gsf {
+
+struct CgState {
+  double rho;    // r^T r of the current residual (z-space)
+  double rho0;
+  double res0;
+  double floor;  // breakdown floor (tau ||z0||)^2
+  double tol;    // requested tolerance (<= 0: run kmax steps)
+  double tol2;   // tol^2 rho0, or -1
+  double tau;    // breakdown tau of the data precision
+  double alpha, beta, pq;
+  int32_t active;
+  int32_t status;
+  int32_t iters;
+  int32_t k;     // 1-based index of the next step
+  unsigned int counter;
+  int32_t pad;
+};
+
+struct LobpcgState {
+  double theta[8];
+  double res[8];       // residual norms of the current X
+  double yx[8];        // Y^T W (constraint projection coefficients)
+  double ynorm_inv;    // 1 / ||sqrt(d)||
+  double tol;
+  double drop_tol;
+  double zero_tol;
+  int32_t m;
+  int32_t ns;          // columns in the current trial basis (m, 2m or 3m)
+  int32_t active;
+  int32_t status;
+  int32_t iters;
+  int32_t dropped;
+  int32_t have_p;      // P block valid
+  int32_t nkept;       // kept columns of the last Rayleigh-Ritz
+  int32_t start_failed;  // the start block had rank < m
+  int32_t kept[24];
+  unsigned int counter;
+  unsigned int counter2;
+};
+
+}  // namespace gsf

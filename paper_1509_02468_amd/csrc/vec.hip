@@ -1,0 +1,219 @@
+// Vector kernels of the power iteration and of CG (Algorithm 2 in z-space),
+// with deterministic FP64 reductions: each workgroup writes one partial per
+// quantity, and the last workgroup to finish sums them in workgroup order and
+// updates the solver state.
+#include <cmath>
+
+#include "gsf_internal.h"
+#include "solver_state.h"
+
+namespace gsf {
+namespace {
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) scale_kernel(const T* __restrict__ in, const T* __restrict__ s,
+                                                         T* __restrict__ out, int64_t n, int divide) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    out[i] = divide ? in[i] / s[i] : in[i] * s[i];
+}
+
+// r holds L_sym z on entry; r <- -L_sym z; state <- rho0, breakdown floor.
+template <typename T>
+__global__ void __launch_bounds__(kThreads) cg_init_kernel(const T* __restrict__ z, T* __restrict__ r, int64_t n,
+                                                           double* __restrict__ partials, CgState* st) {
+  __shared__ double red[32];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  double v[2] = {0.0, 0.0};
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const T ri = -r[i];
+    r[i] = ri;
+    v[0] += (double)ri * (double)ri;
+    v[1] += (double)z[i] * (double)z[i];
+  }
+  block_sum<2>(v, red);
+  if (threadIdx.x == 0) {
+    partials[2 * blockIdx.x] = v[0];
+    partials[2 * blockIdx.x + 1] = v[1];
+  }
+  if (!arrive_last(&st->counter, gridDim.x)) return;
+  double t[2];
+  reduce_partials<2>(partials, gridDim.x, 2, t, red);
+  if (threadIdx.x == 0) {
+    const double rho = t[0];
+    st->rho = rho;
+    st->rho0 = rho;
+    st->res0 = sqrt(rho > 0.0 ? rho : 0.0);
+    st->floor = st->tau * st->tau * t[1];
+    st->tol2 = st->tol > 0.0 ? st->tol * st->tol * rho : -1.0;
+    st->iters = 0;
+    st->k = 1;
+    st->beta = 0.0;
+    st->status = GSF_OK;
+    st->active = 1;
+    if (!(__builtin_isfinite(rho) && rho > st->floor)) {
+      st->status = GSF_EBREAKDOWN;
+      st->active = 0;
+    } else if (st->tol2 > 0.0 && rho <= st->tol2) {
+      st->active = 0;
+    }
+  }
+}
+
+// p = r (k = 1) or p = r + beta p
+template <typename T>
+__global__ void __launch_bounds__(kThreads) cg_pupdate_kernel(const T* __restrict__ r, T* __restrict__ p, int64_t n,
+                                                              const CgState* st) {
+  if (!st->active) return;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  if (st->k == 1) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = r[i];
+  } else {
+    const T beta = (T)st->beta;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = r[i] + beta * p[i];
+  }
+}
+
+// partials[b] = sum over workgroup b of a_i b_i
+template <typename T>
+__global__ void __launch_bounds__(kThreads) dot_kernel(const T* __restrict__ a, const T* __restrict__ b, int64_t n,
+                                                       double* __restrict__ partials, const CgState* st) {
+  __shared__ double red[16];
+  if (st != nullptr && !st->active) return;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  double v[1] = {0.0};
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    v[0] += (double)a[i] * (double)b[i];
+  block_sum<1>(v, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = v[0];
+}
+
+// one workgroup: p^T q from the partials, alpha, breakdown test
+__global__ void __launch_bounds__(kThreads) cg_alpha_kernel(const double* __restrict__ partials, int nparts,
+                                                            CgState* st) {
+  __shared__ double red[16];
+  if (!st->active) return;
+  double t[1];
+  reduce_partials<1>(partials, nparts, 1, t, red);
+  if (threadIdx.x == 0) {
+    const double pq = t[0];
+    st->pq = pq;
+    if (!(__builtin_isfinite(pq) && pq > 0.0)) {
+      st->status = GSF_EBREAKDOWN;
+      st->active = 0;
+    } else {
+      st->alpha = st->rho / pq;
+    }
+  }
+}
+
+// z += alpha p; r -= alpha q; rho_new, beta = (rho_new - r_new.r_old) / rho_old;
+// then the tests that precede the next step.
+template <typename T>
+__global__ void __launch_bounds__(kThreads) cg_update_kernel(T* __restrict__ z, T* __restrict__ r,
+                                                             const T* __restrict__ p, const T* __restrict__ q,
+                                                             int64_t n, double* __restrict__ partials, CgState* st) {
+  __shared__ double red[32];
+  if (!st->active) return;
+  const T alpha = (T)st->alpha;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  double v[2] = {0.0, 0.0};
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    z[i] += alpha * p[i];
+    const T ro = r[i];
+    const T rn = ro - alpha * q[i];
+    r[i] = rn;
+    v[0] += (double)rn * (double)rn;
+    v[1] += (double)rn * (double)ro;
+  }
+  block_sum<2>(v, red);
+  if (threadIdx.x == 0) {
+    partials[2 * blockIdx.x] = v[0];
+    partials[2 * blockIdx.x + 1] = v[1];
+  }
+  if (!arrive_last(&st->counter, gridDim.x)) return;
+  double t[2];
+  reduce_partials<2>(partials, gridDim.x, 2, t, red);
+  if (threadIdx.x == 0) {
+    const double rho_old = st->rho;
+    const double rho = t[0];
+    st->beta = (rho - t[1]) / rho_old;
+    st->rho = rho;
+    st->iters = st->k;
+    st->k = st->k + 1;
+    if (!(__builtin_isfinite(rho) && rho > st->floor)) {
+      st->status = GSF_EBREAKDOWN;
+      st->active = 0;
+    } else if (st->tol2 > 0.0 && rho <= st->tol2) {
+      st->active = 0;
+    }
+  }
+}
+
+}  // namespace
+
+int vec_blocks(int64_t n) {
+  int64_t b = (n + kThreads * 4 - 1) / (kThreads * 4);
+  if (b < 1) b = 1;
+  if (b > 1024) b = 1024;
+  return (int)b;
+}
+
+gsf_status launch_scale(const Operator& op, const void* in, void* out, int divide, hipStream_t s) {
+  const int nb = vec_blocks(op.n);
+  if (op.desc.prec == GSF_F32)
+    scale_kernel<float><<<nb, kThreads, 0, s>>>((const float*)in, (const float*)op.sqd, (float*)out, op.n, divide);
+  else
+    scale_kernel<double><<<nb, kThreads, 0, s>>>((const double*)in, (const double*)op.sqd, (double*)out, op.n,
+                                                 divide);
+  return hipGetLastError() == hipSuccess ? GSF_OK : GSF_EDEVICE;
+}
+
+gsf_status launch_cg_init(const Operator& op, const void* z, void* r, double* partials, CgState* st,
+                          hipStream_t s) {
+  const int nb = vec_blocks(op.n);
+  if (op.desc.prec == GSF_F32)
+    cg_init_kernel<float><<<nb, kThreads, 0, s>>>((const float*)z, (float*)r, op.n, partials, st);
+  else
+    cg_init_kernel<double><<<nb, kThreads, 0, s>>>((const double*)z, (double*)r, op.n, partials, st);
+  return hipGetLastError() == hipSuccess ? GSF_OK : GSF_EDEVICE;
+}
+
+gsf_status launch_cg_pupdate(const Operator& op, const void* r, void* p, const CgState* st, hipStream_t s) {
+  const int nb = vec_blocks(op.n);
+  if (op.desc.prec == GSF_F32)
+    cg_pupdate_kernel<float><<<nb, kThreads, 0, s>>>((const float*)r, (float*)p, op.n, st);
+  else
+    cg_pupdate_kernel<double><<<nb, kThreads, 0, s>>>((const double*)r, (double*)p, op.n, st);
+  return hipGetLastError() == hipSuccess ? GSF_OK : GSF_EDEVICE;
+}
+
+gsf_status launch_dot(const Operator& op, const void* a, const void* b, double* partials, int* nparts,
+                      const CgState* st, hipStream_t s) {
+  const int nb = vec_blocks(op.n);
+  *nparts = nb;
+  if (op.desc.prec == GSF_F32)
+    dot_kernel<float><<<nb, kThreads, 0, s>>>((const float*)a, (const float*)b, op.n, partials, st);
+  else
+    dot_kernel<double><<<nb, kThreads, 0, s>>>((const double*)a, (const double*)b, op.n, partials, st);
+  return hipGetLastError() == hipSuccess ? GSF_OK : GSF_EDEVICE;
+}
+
+gsf_status launch_cg_alpha(const double* partials, int nparts, CgState* st, hipStream_t s) {
+  cg_alpha_kernel<<<1, kThreads, 0, s>>>(partials, nparts, st);
+  return hipGetLastError() == hipSuccess ? GSF_OK : GSF_EDEVICE;
+}
+
+gsf_status launch_cg_update(const Operator& op, void* z, void* r, const void* p, const void* q, double* partials,
+                            CgState* st, hipStream_t s) {
+  const int nb = vec_blocks(op.n);
+  if (op.desc.prec == GSF_F32)
+    cg_update_kernel<float><<<nb, kThreads, 0, s>>>((float*)z, (float*)r, (const float*)p, (const float*)q, op.n,
+                                                    partials, st);
+  else
+    cg_update_kernel<double><<<nb, kThreads, 0, s>>>((double*)z, (double*)r, (const double*)p, (const double*)q,
+                                                     op.n, partials, st);
+  return hipGetLastError() == hipSuccess ? GSF_OK : GSF_EDEVICE;
+}
+
+}  // namespace gsf

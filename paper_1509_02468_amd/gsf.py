@@ -1,0 +1,284 @@
+"""ctypes binding of libgsf (argument marshalling only; every step runs in the
+HIP library).  Device buffers are torch CUDA tensors (ROCm); torch is used for
+device memory and streams only.
+
+Names mirror the C ABI in include/gsf.h: build_operator, apply, power_filter,
+cg_filter, lobpcg_filter, plus the diagnostic block_gram / rayleigh_ritz.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgsf.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, ENOTCONV, EBREAKDOWN = range(6)
+BF, GF = 0, 1
+F32, F64 = 0, 1
+FORM_N, FORM_LSYM, FORM_RW = 0, 1, 2
+METHOD_POWER, METHOD_CG, METHOD_LOBPCG = 0, 1, 2
+STATUS_NAMES = {OK: "ok", EINVAL: "einval", ENOMEM: "enomem", EDEVICE: "edevice",
+                ENOTCONV: "notconv", EBREAKDOWN: "breakdown"}
+
+
+class OperatorDesc(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("ndim", ctypes.c_int32), ("dims", ctypes.c_int64 * 2),
+                ("prec", ctypes.c_int32), ("radius", ctypes.c_int32), ("sigma_d", ctypes.c_double),
+                ("sigma_r", ctypes.c_double), ("gf_eps", ctypes.c_double)]
+
+
+class OperatorLayout(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("ndim", ctypes.c_int32), ("prec", ctypes.c_int32),
+                ("radius", ctypes.c_int32), ("n", ctypes.c_int64), ("nplanes", ctypes.c_int32),
+                ("planes", ctypes.c_void_p), ("inv_sqrt_d", ctypes.c_void_p), ("sqrt_d", ctypes.c_void_p),
+                ("degree", ctypes.c_void_p), ("guidance", ctypes.c_void_p), ("mu", ctypes.c_void_p),
+                ("inv", ctypes.c_void_p)]
+
+
+class CgInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("status", ctypes.c_int32), ("res0", ctypes.c_double),
+                ("res", ctypes.c_double)]
+
+
+class LobpcgInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("status", ctypes.c_int32), ("dropped", ctypes.c_int32),
+                ("m", ctypes.c_int32), ("res", ctypes.c_double * 8), ("theta", ctypes.c_double * 8)]
+
+
+_lib = None
+
+
+class GsfError(RuntimeError):
+    def __init__(self, status, where):
+        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)}")
+        self.status = status
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libgsf.so (raises if it has not been built; there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_1509_02468_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, sz, i32, i64, dbl = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_int64, ctypes.c_double
+    P = ctypes.POINTER
+    sig = {
+        "gsf_version": ([], i32),
+        "gsf_status_string": ([i32], ctypes.c_char_p),
+        "gsf_operator_workspace_bytes": ([P(OperatorDesc), P(sz)], i32),
+        "gsf_build_operator": ([P(OperatorDesc), vp, vp, sz, vp, P(vp)], i32),
+        "gsf_operator_get_layout": ([vp, P(OperatorLayout)], i32),
+        "gsf_destroy_operator": ([vp], None),
+        "gsf_apply": ([vp, i32, i32, vp, vp, vp], i32),
+        "gsf_solver_workspace_bytes": ([vp, i32, i32, P(sz)], i32),
+        "gsf_power_filter": ([vp, vp, vp, i32, vp, sz, vp], i32),
+        "gsf_cg_filter": ([vp, vp, vp, i32, dbl, vp, sz, P(CgInfo), vp], i32),
+        "gsf_lobpcg_filter": ([vp, vp, vp, i32, i32, dbl, i32, vp, vp, vp, sz, P(LobpcgInfo), vp], i32),
+        "gsf_block_gram": ([i32, i64, i32, i32, P(vp), P(vp), vp, vp, vp, sz, vp], i32),
+        "gsf_block_gram_workspace_bytes": ([i64, P(sz)], i32),
+        "gsf_rayleigh_ritz": ([i32, i32, vp, vp, dbl, dbl, vp, vp, vp, vp, vp, sz, vp], i32),
+        "gsf_rr_workspace_bytes": ([], sz),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def _check(status, where):
+    if status not in (OK, ENOTCONV, EBREAKDOWN):
+        raise GsfError(status, where)
+    return status
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dtype(prec):
+    torch = _torch()
+    return torch.float32 if prec == F32 else torch.float64
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Operator:
+    """A built graph operator (BF eq. (2) or GF Algorithm 1) on the GPU.
+    Owns its device workspace (a torch uint8 tensor)."""
+
+    def __init__(self, kind, shape, guidance, radius, sigma_d=0.0, sigma_r=0.0, eps=0.0, prec=F32,
+                 stream=None):
+        torch = _torch()
+        lib = load_library()
+        shape = tuple(int(s) for s in shape)
+        self.shape, self.prec, self.kind, self.radius = shape, prec, kind, radius
+        self.n = int(np.prod(shape))
+        d = OperatorDesc()
+        d.kind = BF if kind in ("bf", BF) else GF
+        d.ndim = len(shape)
+        d.dims[0] = shape[0]
+        d.dims[1] = shape[1] if len(shape) == 2 else 1
+        d.prec = prec
+        d.radius = radius
+        d.sigma_d = sigma_d
+        d.sigma_r = sigma_r
+        d.gf_eps = eps
+        self.desc = d
+        nbytes = ctypes.c_size_t()
+        _check(lib.gsf_operator_workspace_bytes(ctypes.byref(d), ctypes.byref(nbytes)), "operator_workspace_bytes")
+        self.ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device="cuda")
+        g = guidance
+        if not isinstance(g, torch.Tensor):
+            g = torch.as_tensor(np.ascontiguousarray(g))
+        g = g.to(device="cuda", dtype=_dtype(prec)).contiguous().reshape(-1)
+        if g.numel() != self.n:
+            raise ValueError("guidance size does not match shape")
+        h = ctypes.c_void_p()
+        _check(lib.gsf_build_operator(ctypes.byref(d), _ptr(g), _ptr(self.ws), nbytes.value, _stream(stream),
+                                      ctypes.byref(h)), "build_operator")
+        self.handle = h
+        self._guidance = g  # keep alive until the build has run
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.gsf_destroy_operator(self.handle)
+            self.handle = None
+
+    @property
+    def dtype(self):
+        return _dtype(self.prec)
+
+    def layout(self):
+        lay = OperatorLayout()
+        _check(_lib.gsf_operator_get_layout(self.handle, ctypes.byref(lay)), "operator_get_layout")
+        return lay
+
+    def _view(self, ptr, count, dtype):
+        """Copy `count` elements at device address ptr (inside the workspace)."""
+        torch = _torch()
+        base = self.ws.data_ptr()
+        off = int(ptr) - base
+        esz = torch.tensor([], dtype=dtype).element_size()
+        return self.ws[off:off + count * esz].view(dtype).clone()
+
+    def planes(self):
+        lay = self.layout()
+        return self._view(lay.planes, lay.nplanes * self.n, self.dtype).reshape(lay.nplanes, self.n)
+
+    def inv_sqrt_d(self):
+        return self._view(self.layout().inv_sqrt_d, self.n, self.dtype)
+
+    def sqrt_d(self):
+        return self._view(self.layout().sqrt_d, self.n, self.dtype)
+
+    def degree(self):
+        return self._view(self.layout().degree, self.n, _torch().float64)
+
+    def gf_stats(self):
+        lay = self.layout()
+        return self._view(lay.mu, self.n, self.dtype), self._view(lay.inv, self.n, self.dtype)
+
+    # -- entry points --------------------------------------------------------
+    def apply(self, x, form=FORM_N, out=None, stream=None):
+        torch = _torch()
+        m = 1 if x.dim() == 1 else x.shape[1]
+        if x.dtype != self.dtype or not x.is_cuda or not x.is_contiguous():
+            raise ValueError("x must be a contiguous device tensor of the operator dtype")
+        y = out if out is not None else torch.empty_like(x)
+        _check(_lib.gsf_apply(self.handle, form, m, _ptr(x), _ptr(y), _stream(stream)), "apply")
+        return y
+
+    def workspace(self, method, m=1):
+        torch = _torch()
+        nbytes = ctypes.c_size_t()
+        _check(_lib.gsf_solver_workspace_bytes(self.handle, method, m, ctypes.byref(nbytes)), "solver_workspace_bytes")
+        return torch.empty(max(int(nbytes.value), 1), dtype=torch.uint8, device="cuda")
+
+    def power_filter(self, x0, kmax, out=None, ws=None, stream=None):
+        torch = _torch()
+        y = out if out is not None else torch.empty_like(x0)
+        ws = ws if ws is not None else self.workspace(METHOD_POWER)
+        _check(_lib.gsf_power_filter(self.handle, _ptr(x0), _ptr(y), kmax, _ptr(ws), ws.numel(), _stream(stream)),
+               "power_filter")
+        return y
+
+    def cg_filter(self, x0, kmax, tol=0.0, out=None, ws=None, info=True, stream=None):
+        torch = _torch()
+        y = out if out is not None else torch.empty_like(x0)
+        ws = ws if ws is not None else self.workspace(METHOD_CG)
+        inf = CgInfo()
+        st = _lib.gsf_cg_filter(self.handle, _ptr(x0), _ptr(y), kmax, tol, _ptr(ws), ws.numel(),
+                                ctypes.byref(inf) if info else None, _stream(stream))
+        _check(st, "cg_filter")
+        return y, (inf if info else None)
+
+    def lobpcg_filter(self, x0, m, kmax, tol=0.0, constraint=False, out=None, ritz=None, ws=None, info=True,
+                      stream=None):
+        torch = _torch()
+        y = out if out is not None else torch.empty_like(x0)
+        ws = ws if ws is not None else self.workspace(METHOD_LOBPCG, m)
+        inf = LobpcgInfo()
+        st = _lib.gsf_lobpcg_filter(self.handle, _ptr(x0), _ptr(y), m, kmax, tol, int(bool(constraint)), None,
+                                    _ptr(ritz) if ritz is not None else None, _ptr(ws), ws.numel(),
+                                    ctypes.byref(inf) if info else None, _stream(stream))
+        _check(st, "lobpcg_filter")
+        return y, (inf if info else None)
+
+
+def build_operator(kind, shape, guidance, radius, sigma_d=0.0, sigma_r=0.0, eps=0.0, prec=F32, stream=None):
+    return Operator(kind, shape, guidance, radius, sigma_d, sigma_r, eps, prec, stream)
+
+
+def block_gram(S_blocks, AS_blocks, prec=F32, stream=None):
+    """(S^T A S, S^T S) through the MFMA Gram kernel; S_blocks/AS_blocks are
+    lists of n x m device tensors."""
+    torch = _torch()
+    lib = load_library()
+    n, m = S_blocks[0].shape
+    nb = len(S_blocks)
+    need = ctypes.c_size_t()
+    _check(lib.gsf_block_gram_workspace_bytes(n, ctypes.byref(need)), "block_gram_workspace_bytes")
+    ws = torch.empty(int(need.value), dtype=torch.uint8, device="cuda")
+    sp = (ctypes.c_void_p * 3)(*[b.data_ptr() for b in S_blocks] + [0] * (3 - nb))
+    ap = (ctypes.c_void_p * 3)(*[b.data_ptr() for b in AS_blocks] + [0] * (3 - nb))
+    ns = nb * m
+    GA = np.zeros((ns, ns))
+    GB = np.zeros((ns, ns))
+    _check(lib.gsf_block_gram(prec, n, m, nb, sp, ap, GA.ctypes.data_as(ctypes.c_void_p),
+                              GB.ctypes.data_as(ctypes.c_void_p), _ptr(ws), ws.numel(), _stream(stream)),
+           "block_gram")
+    return GA, GB
+
+
+def rayleigh_ritz(GA, GB, m, drop_tol, zero_tol=0.0, stream=None):
+    """Device FP64 Rayleigh-Ritz step on a host Gram pair."""
+    torch = _torch()
+    lib = load_library()
+    ns = GA.shape[0]
+    GA = np.ascontiguousarray(GA, dtype=np.float64)
+    GB = np.ascontiguousarray(GB, dtype=np.float64)
+    theta = np.zeros(m)
+    C = np.zeros((ns, m))
+    kept = np.zeros(ns, dtype=np.int32)
+    nkept = np.zeros(1, dtype=np.int32)
+    ws = torch.empty(int(lib.gsf_rr_workspace_bytes()), dtype=torch.uint8, device="cuda")
+    vp = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    _check(lib.gsf_rayleigh_ritz(ns, m, vp(GA), vp(GB), drop_tol, zero_tol, vp(theta), vp(C), vp(kept), vp(nkept),
+                                 _ptr(ws), ws.numel(), _stream(stream)), "rayleigh_ritz")
+    return theta, C, kept.astype(bool), int(nkept[0])

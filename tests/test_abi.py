@@ -1,0 +1,92 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every entry point declared in include/gsf.h, and validates arguments before
+touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gsf.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(gsf_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_1509_02468_amd as pkg
+    if not os.path.exists(pkg.LIB_PATH):
+        pytest.skip("libgsf.so not built")
+    return pkg.load_library()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared()
+    assert len(names) >= 15
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_version_and_status_strings(lib):
+    assert lib.gsf_version() >= 1
+    assert lib.gsf_status_string(0) == b"ok"
+    assert lib.gsf_status_string(99) == b"unknown status"
+
+
+def _desc(**kw):
+    from paper_1509_02468_amd.gsf import OperatorDesc
+    d = OperatorDesc()
+    d.kind, d.ndim, d.prec, d.radius = kw.get("kind", 0), kw.get("ndim", 2), kw.get("prec", 0), kw.get("radius", 5)
+    d.dims[0], d.dims[1] = kw.get("dims", (64, 80))
+    d.sigma_d, d.sigma_r, d.gf_eps = kw.get("sigma_d", 2.0), kw.get("sigma_r", 0.1), kw.get("eps", 0.01)
+    return d
+
+
+def test_operator_workspace_sizes(lib):
+    n = 64 * 80
+    sz = ctypes.c_size_t()
+    assert lib.gsf_operator_workspace_bytes(ctypes.byref(_desc()), ctypes.byref(sz)) == 0
+    # 60 half-window planes + diag + sqrt(d) in FP32, + FP64 degrees
+    assert sz.value >= (60 + 2) * n * 4 + n * 8
+    assert lib.gsf_operator_workspace_bytes(ctypes.byref(_desc(prec=1)), ctypes.byref(sz)) == 0
+    assert sz.value >= (60 + 2) * n * 8 + n * 8
+    assert lib.gsf_operator_workspace_bytes(ctypes.byref(_desc(kind=1, radius=8)), ctypes.byref(sz)) == 0
+    assert sz.value >= 8 * n * 4 + n * 8
+
+
+@pytest.mark.parametrize("bad", [dict(radius=0), dict(radius=9), dict(ndim=3), dict(kind=2), dict(prec=5),
+                                 dict(dims=(0, 5)), dict(sigma_r=0.0), dict(sigma_d=-1.0),
+                                 dict(sigma_r=float("nan")), dict(kind=1, eps=-1.0),
+                                 dict(kind=1, eps=float("inf"))])
+def test_invalid_descriptors_rejected(lib, bad):
+    sz = ctypes.c_size_t()
+    assert lib.gsf_operator_workspace_bytes(ctypes.byref(_desc(**bad)), ctypes.byref(sz)) == 1
+
+
+def test_build_rejects_small_workspace_and_nulls(lib):
+    d = _desc()
+    out = ctypes.c_void_p()
+    # NULL guidance / workspace: EINVAL before any device call
+    assert lib.gsf_build_operator(ctypes.byref(d), None, None, 0, None, ctypes.byref(out)) == 1
+    # non-null fake pointers with a too small size: ENOMEM (nothing is launched)
+    fake = ctypes.c_void_p(0x1000)
+    assert lib.gsf_build_operator(ctypes.byref(d), fake, fake, 16, None, ctypes.byref(out)) == 2
+
+
+def test_solver_calls_reject_null_operator(lib):
+    sz = ctypes.c_size_t()
+    assert lib.gsf_solver_workspace_bytes(None, 1, 1, ctypes.byref(sz)) == 1
+    assert lib.gsf_apply(None, 0, 1, None, None, None) == 1
+    assert lib.gsf_rr_workspace_bytes() > 0
+
+
+def test_gram_workspace_query(lib):
+    sz = ctypes.c_size_t()
+    assert lib.gsf_block_gram_workspace_bytes(ctypes.c_int64(1 << 20), ctypes.byref(sz)) == 0
+    assert sz.value > 0
+    assert lib.gsf_block_gram_workspace_bytes(ctypes.c_int64(0), ctypes.byref(sz)) == 1

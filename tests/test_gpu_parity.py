@@ -1,0 +1,254 @@
+"""GPU parity: every step of the HIP path, called through the C ABI, against
+the FP64 CPU oracle on the same seeded inputs.
+
+Tolerances (relative, 2-norm and max-norm over the whole output):
+  FP64 path: 1e-12 for weights, apply and power iteration; CG and LOBPCG
+             outputs 1e-10 (30-50 steps amplify summation-order differences,
+             see the self-sensitivity test below).
+  FP32 path: 1e-5 for weights, apply, power iteration and CG; LOBPCG Ritz
+             values within 1e-5 * ||L_sym|| (||L_sym|| <= 2).
+For FP32 runs the oracle receives the FP32-rounded inputs, so the comparison
+measures the kernel's arithmetic, not the rounding of its inputs.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from synth import piecewise_constant_1d, scene_2d
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64).ravel()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    den2 = max(np.linalg.norm(b), 1e-300)
+    deni = max(np.abs(b).max(), 1e-300)
+    return max(np.linalg.norm(a - b) / den2, np.abs(a - b).max() / deni)
+
+
+def _inputs(case):
+    """(shape, float64 noisy signal) of a named test case."""
+    kind, shape, seed = case
+    if len(shape) == 1:
+        return shape, piecewise_constant_1d(shape[0], 0.1, seed)[1]
+    return shape, scene_2d(shape[0], shape[1], 0.05, seed)[1]
+
+
+def _torch(x, prec, gsf):
+    import torch
+    dt = torch.float32 if prec == gsf.F32 else torch.float64
+    return torch.tensor(np.ascontiguousarray(x), dtype=dt, device="cuda")
+
+
+def _round(x, prec, gsf):
+    return x.astype(np.float32).astype(np.float64) if prec == gsf.F32 else x
+
+
+TOL = {0: 1e-5, 1: 1e-12}
+
+# (kind, shape, seed): sizes span several tiles plus ragged tails
+BF_CASES = [("bf", (4096,), 1), ("bf", (1000,), 2), ("bf", (67, 130), 3), ("bf", (33, 200), 4)]
+GF_CASES = [("gf", (1500,), 5), ("gf", (70, 131), 6)]
+
+
+def _params(kind, shape):
+    if kind == "bf":
+        r = 5 if len(shape) == 1 else (3 if shape[0] % 2 else 5)
+        return dict(radius=r, sigma_d=3.0 if len(shape) == 1 else 2.0, sigma_r=0.2 if len(shape) == 1 else 0.1)
+    return dict(radius=4 if len(shape) == 1 else 3, eps=1e-2)
+
+
+def _build(gsf, case, prec):
+    shape, x = _inputs(case)
+    kind = case[0]
+    p = _params(kind, shape)
+    xr = _round(x, prec, gsf)
+    op = gsf.Operator(kind, shape, _torch(x, prec, gsf), prec=prec, **p)
+    ref = oracle.build_operator(kind, xr.reshape(shape), p["radius"], p.get("sigma_d", 0.0), p.get("sigma_r", 0.0),
+                                p.get("eps", 0.0))
+    return op, ref, xr.ravel()
+
+
+# ------------------------------------------------------------------ build
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("case", BF_CASES)
+def test_bf_build_parity(gsf, case, prec):
+    op, ref, _ = _build(gsf, case, prec)
+    np.testing.assert_allclose(op.degree().cpu().numpy(), ref.d, rtol=1e-13)
+    assert rel(op.sqrt_d().cpu().numpy(), ref.sqrt_d) <= TOL[prec]
+    assert rel(op.inv_sqrt_d().cpu().numpy(), 1.0 / ref.sqrt_d) <= TOL[prec]
+    # half-window planes against the oracle's W: w_{i,i+o}
+    planes = op.planes().cpu().numpy().astype(np.float64)
+    shape = ref.shape
+    r = ref.radius
+    W = ref.W.tocsr()
+    n = ref.n
+    offs = [(o,) for o in range(1, r + 1)] if len(shape) == 1 else \
+        [(0, dx) for dx in range(1, r + 1)] + [(dy, dx) for dy in range(1, r + 1) for dx in range(-r, r + 1)]
+    assert planes.shape[0] == len(offs)
+    coords = np.indices(shape).reshape(len(shape), -1).T
+    for q, o in enumerate(offs):
+        nb = coords + np.array(o)
+        inside = np.all((nb >= 0) & (nb < np.array(shape)), axis=1)
+        i = np.flatnonzero(inside)
+        j = np.ravel_multi_index(tuple(nb[inside].T), shape)
+        expect = np.zeros(n)
+        expect[i] = np.asarray(W[i, j]).ravel()
+        assert rel(planes[q], expect) <= TOL[prec], (q, o)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("case", GF_CASES)
+def test_gf_build_parity(gsf, case, prec):
+    op, ref, _ = _build(gsf, case, prec)
+    mu, inv = op.gf_stats()
+    rmu, rinv = ref.gf_window_stats()
+    assert rel(mu.cpu().numpy(), rmu) <= TOL[prec]
+    assert rel(inv.cpu().numpy(), rinv) <= (TOL[prec] if prec == 1 else 1e-5)
+    np.testing.assert_allclose(op.degree().cpu().numpy(), ref.d, rtol=1e-15)
+
+
+# ------------------------------------------------------------------ apply
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("m", [1, 3, 4, 8])
+@pytest.mark.parametrize("case", BF_CASES[1:] + GF_CASES)
+def test_apply_parity_all_forms(gsf, case, prec, m):
+    op, ref, _ = _build(gsf, case, prec)
+    rng = np.random.default_rng(100 + m)
+    X = _round(rng.standard_normal((op.n, m)), prec, gsf)
+    Xd = _torch(X if m > 1 else X[:, 0], prec, gsf)
+    for form in (gsf.FORM_N, gsf.FORM_LSYM, gsf.FORM_RW):
+        Y = op.apply(Xd, form).cpu().numpy().reshape(op.n, m)
+        R = ref.apply(form, X)
+        assert rel(Y, R) <= TOL[prec], (form, rel(Y, R))
+
+
+def test_apply_deterministic(gsf):
+    op, ref, x = _build(gsf, ("bf", (67, 130), 3), 0)
+    xd = _torch(x, 0, gsf)
+    a = op.apply(xd, gsf.FORM_LSYM).cpu().numpy()
+    b = op.apply(xd, gsf.FORM_LSYM).cpu().numpy()
+    assert np.array_equal(a, b)
+
+
+# ------------------------------------------------------------------ power iteration
+@pytest.mark.parametrize("prec,case,k", [(1, ("bf", (4096,), 1), 30), (0, ("bf", (67, 130), 3), 20),
+                                         (1, ("gf", (70, 131), 6), 10), (0, ("gf", (1500,), 5), 10)])
+def test_power_filter_parity(gsf, prec, case, k):
+    op, ref, x = _build(gsf, case, prec)
+    y = op.power_filter(_torch(x, prec, gsf), k).cpu().numpy()
+    r = oracle.power_filter(ref, x, k)
+    err = rel(y, r)
+    print(f"power {case} prec={prec} k={k}: rel err {err:.3e}")
+    assert err <= TOL[prec], err
+
+
+# ------------------------------------------------------------------ CG
+@pytest.mark.parametrize("prec,case,k", [(1, ("bf", (4096,), 1), 30), (1, ("bf", (67, 130), 3), 30),
+                                         (0, ("bf", (67, 130), 3), 30), (1, ("gf", (70, 131), 6), 20),
+                                         (0, ("bf", (33, 200), 4), 50)])
+def test_cg_filter_parity(gsf, prec, case, k):
+    op, ref, x = _build(gsf, case, prec)
+    y, info = op.cg_filter(_torch(x, prec, gsf), k)
+    r, rinfo = oracle.cg_filter(ref, x, k, data_prec="f32" if prec == 0 else "f64")
+    assert info.iters == rinfo.iters and info.status == 0
+    err = rel(y.cpu().numpy(), r)
+    print(f"cg {case} prec={prec} k={k}: rel err {err:.3e}")
+    assert err <= (1e-10 if prec == 1 else 1e-5), err
+    assert abs(info.res0 - rinfo.res0) <= 1e-6 * rinfo.res0
+
+
+def test_cg_constant_input_breakdown(gsf):
+    import torch
+    shape = (40, 70)
+    x = np.full(shape, 0.3)
+    op = gsf.Operator("bf", shape, _torch(x, 1, gsf), radius=2, sigma_d=2.0, sigma_r=0.1, prec=gsf.F64)
+    y, info = op.cg_filter(_torch(x.ravel(), 1, gsf), 10)
+    assert info.status == gsf.EBREAKDOWN and info.iters == 0
+    np.testing.assert_array_equal(y.cpu().numpy(), x.ravel())
+
+
+def test_cg_tolerance_stop(gsf):
+    op, ref, x = _build(gsf, ("bf", (1000,), 2), 1)
+    y, info = op.cg_filter(_torch(x, 1, gsf), 500, tol=1e-6)
+    r, rinfo = oracle.cg_filter_normalized(ref, x, 500, tol=1e-6)
+    assert info.status == 0 and info.iters == rinfo.iters
+    assert rel(y.cpu().numpy(), r) <= 1e-9
+
+
+# ------------------------------------------------------------------ Gram (MFMA) and Rayleigh-Ritz
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("m,nb", [(1, 1), (3, 3), (4, 3), (5, 3), (8, 2), (8, 3)])
+def test_block_gram_parity(gsf, prec, m, nb):
+    import torch
+    n = 5003
+    rng = np.random.default_rng(7 + m + nb)
+    S = [_round(rng.standard_normal((n, m)), prec, gsf) for _ in range(nb)]
+    A = [_round(rng.standard_normal((n, m)), prec, gsf) for _ in range(nb)]
+    GA, GB = gsf.block_gram([_torch(s, prec, gsf) for s in S], [_torch(a, prec, gsf) for a in A], prec=prec)
+    Sf, Af = np.column_stack(S), np.column_stack(A)
+    tol = 1e-13 if prec == 1 else 2e-6
+    assert rel(GB, Sf.T @ Sf) <= tol
+    assert rel(GA, Sf.T @ Af) <= tol
+
+
+@pytest.mark.parametrize("ns,m,drop", [(9, 3, False), (24, 8, False), (12, 4, True)])
+def test_rayleigh_ritz_parity(gsf, ns, m, drop):
+    rng = np.random.default_rng(ns)
+    S = rng.standard_normal((200, ns))
+    if drop:
+        S[:, 7] = 2.0 * S[:, 2] + 1e-9 * rng.standard_normal(200)
+    A0 = rng.standard_normal((200, 200))
+    A = A0 @ A0.T / 200
+    GA, GB = S.T @ A @ S, S.T @ S
+    th, C, kept, nk = gsf.rayleigh_ritz(GA, GB, m, 1e-10, 1e-13)
+    rth, rC, rkept = oracle.rayleigh_ritz(GA, GB, m, 1e-10, 1e-13)
+    assert np.array_equal(kept, rkept)
+    np.testing.assert_allclose(th, rth, rtol=1e-11, atol=1e-12)
+    # columns agree up to sign
+    for j in range(m):
+        sgn = np.sign(C[:, j] @ rC[:, j])
+        assert rel(sgn * C[:, j], rC[:, j]) <= 1e-8
+
+
+# ------------------------------------------------------------------ LOBPCG
+@pytest.mark.parametrize("prec,case,m,k,constraint", [
+    (1, ("bf", (4096,), 1), 3, 30, False),
+    (1, ("bf", (4096,), 1), 3, 30, True),
+    (1, ("bf", (67, 130), 3), 4, 20, False),
+    (1, ("gf", (70, 131), 6), 4, 10, True),
+    (0, ("bf", (67, 130), 3), 4, 20, True),
+    (0, ("bf", (33, 200), 4), 8, 15, False),
+])
+def test_lobpcg_filter_parity(gsf, prec, case, m, k, constraint):
+    import torch
+    op, ref, x = _build(gsf, case, prec)
+    ritz = torch.empty((op.n, m), dtype=op.dtype, device="cuda")
+    y, info = op.lobpcg_filter(_torch(x, prec, gsf), m, k, constraint=constraint, ritz=ritz)
+    r, th, X, rinfo = oracle.lobpcg_filter(ref, x, m, k, constraint=constraint,
+                                           data_prec="f64" if prec == 1 else "f32")
+    assert info.iters == rinfo.iters
+    theta = np.array(info.theta[:m])
+    if prec == 1:
+        assert info.dropped == rinfo.dropped
+        np.testing.assert_allclose(theta, th, rtol=1e-9, atol=1e-12)
+        assert rel(y.cpu().numpy(), r) <= 1e-9, rel(y.cpu().numpy(), r)
+    else:
+        assert np.abs(theta - th).max() <= 2e-5
+        assert rel(y.cpu().numpy(), r) <= 1e-3, rel(y.cpu().numpy(), r)
+
+
+def test_lobpcg_identity_at_zero_steps(gsf):
+    op, ref, x = _build(gsf, ("bf", (67, 130), 3), 1)
+    y, info = op.lobpcg_filter(_torch(x, 1, gsf), 4, 0)
+    assert rel(y.cpu().numpy(), x) <= 1e-12
+
+
+def test_lobpcg_constant_input_breakdown(gsf):
+    shape = (30, 64)
+    x = np.full(shape, 0.3)
+    op = gsf.Operator("bf", shape, _torch(x, 1, gsf), radius=2, sigma_d=2.0, sigma_r=0.1, prec=gsf.F64)
+    y, info = op.lobpcg_filter(_torch(x.ravel(), 1, gsf), 2, 5, constraint=True)
+    assert info.status == gsf.EBREAKDOWN
+    np.testing.assert_array_equal(y.cpu().numpy(), x.ravel())
