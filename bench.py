@@ -44,7 +44,38 @@ def _args():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--roofline-reps", type=int, default=50)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--kernels-only", action="store_true",
+                    help="only the stencil applies (m = 1 and m) and a 1 GiB copy, for hardware counters")
     return ap.parse_args()
+
+
+def kernels_only(a):
+    """Launch the dominant kernels alone (tuned tile choice), then a plain
+    device copy of 1 GiB whose counter readings calibrate the byte counters."""
+    import torch
+    import paper_1509_02468_amd as gsf
+    from synth import WORKLOADS, make_signal
+    gsf.load_library()
+    w = WORKLOADS[a.workload]
+    shape, m = w["shape"], w["lobpcg_m"]
+    n = int(np.prod(shape))
+    prec = gsf.F32 if w["prec"] == "f32" else gsf.F64
+    dt = torch.float32 if prec == gsf.F32 else torch.float64
+    _, noisy = make_signal(a.workload)
+    x0 = torch.tensor(noisy.ravel(), dtype=dt, device="cuda")
+    op = gsf.Operator(w["kind"], shape, x0, w["radius"], w["sigma_d"], w["sigma_r"], w["eps"], prec)
+    for mm in sorted({1, m}):
+        op.tune_apply(mm, reps=5)
+        xb = torch.randn((n, mm) if mm > 1 else (n,), dtype=dt, device="cuda")
+        yb = torch.empty_like(xb)
+        for _ in range(10):
+            op.apply(xb, gsf.FORM_LSYM, out=yb)
+    src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"kernels_only": a.workload, "n": n, "copy_bytes": src.numel() * 4}), flush=True)
 
 
 def cpu_baseline(w, noisy, budget_s):
@@ -75,6 +106,9 @@ def cpu_baseline(w, noisy, budget_s):
 
 def main():
     a = _args()
+    if a.kernels_only:
+        kernels_only(a)
+        return
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is described in DESIGN.md"}))
         sys.exit(2)
@@ -96,6 +130,11 @@ def main():
 
     # allocate everything once; steps reuse the buffers
     op = gsf.Operator(w["kind"], shape, x0, w["radius"], w["sigma_d"], w["sigma_r"], w["eps"], prec)
+    # pick the apply tile height once (process-wide, reused by every step's operator)
+    tuned = {}
+    for mm in sorted({1, m}):
+        best, times = op.tune_apply(mm, reps=20)
+        tuned[f"m{mm}"] = {"rows_per_thread": best, "us_by_rows_1_2_4": [round(t, 1) for t in times]}
     ws_cg = op.workspace(gsf.METHOD_CG)
     ws_lob = op.workspace(gsf.METHOD_LOBPCG, m)
     y_cg = torch.empty_like(x0)
@@ -165,7 +204,8 @@ def main():
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "f32" if prec == gsf.F32 else "f64", "data": "synthetic",
            "config": {"workload": a.workload, "shape": list(shape), "operator": f"{w['kind']} r={w['radius']}",
-                      "cg_iters": kcg, "lobpcg_iters": klob, "lobpcg_m": m, "parallelism": "single-gpu"},
+                      "cg_iters": kcg, "lobpcg_iters": klob, "lobpcg_m": m, "parallelism": "single-gpu",
+                      "apply_tuning": tuned},
            "roofline": roofline, "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
 

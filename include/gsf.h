@@ -203,6 +203,18 @@ gsf_status gsf_lobpcg_filter(const gsf_operator* op, const void* x0, void* x_out
                              void* ritz_vecs, void* ws, size_t ws_bytes, gsf_lobpcg_info* info,
                              void* stream);
 
+/* ---- tuning ---------------------------------------------------------------
+ * gsf_tune_apply: times the BF apply (form L_sym, block width m in
+ *   {1, 2, 3, 4, 8}) with 1, 2 and 4 grid rows per thread (tile heights 4, 8
+ *   and 16 rows), `reps` launches each, on caller buffers x, y (n*m
+ *   elements); records the fastest choice for every later apply with the same
+ *   precision, dimension, radius, width and size class (process-wide), and
+ *   returns it in *best_rpt and the three timings (microseconds per launch)
+ *   in times_us (NULL allowed).  GF operators: no-op, *best_rpt = 0.
+ *   Synchronizes the stream. */
+gsf_status gsf_tune_apply(const gsf_operator* op, int m, const void* x, void* y, int reps,
+                          int* best_rpt, float* times_us, void* stream);
+
 /* ---- diagnostic entry points (the solver's inner kernels on caller data) ----
  * gsf_block_gram: the Gram pair of the LOBPCG Rayleigh-Ritz step (Algorithm 3,
  *   the Rayleigh-Ritz line): GA = S^T (A S), GB = S^T S for S = [S0 .. S_{nb-1}]

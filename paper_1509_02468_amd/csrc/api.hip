@@ -12,6 +12,10 @@ namespace gsf {
 gsf_status launch_bf_apply(const Operator& op, int form, int m, const void* x, int64_t ldx, void* y,
                            int64_t ldy, double* dot, int* nparts, hipStream_t s);
 int bf_apply_blocks(const Operator& op, int m);
+int bf_rpt(const Operator& op, int w);
+void bf_set_rpt(const Operator& op, int w, int rpt);
+gsf_status launch_bf_apply_rpt(const Operator& op, int form, int m, const void* x, int64_t ldx, void* y,
+                               int64_t ldy, double* dot, int* nparts, int rpt_override, hipStream_t s);
 gsf_status launch_gf_apply(const Operator& op, void* scratch, int form, int m, const void* x, int64_t ldx,
                            void* y, int64_t ldy, hipStream_t s);
 int vec_blocks(int64_t n);
@@ -452,7 +456,6 @@ gsf_status gsf_lobpcg_filter(const gsf_operator* h, const void* x0, void* x_out,
   rr.drop_tol = init.drop_tol;
   rr.zero_tol = init.zero_tol;
 
-  GSF_TRY(hip_ok(hipMemsetAsync(w.gram_counter, 0, 64, s)));
   if (constraint) GSF_TRY(lob_launch_ynorm(a, nb, s));
   GSF_TRY(lob_launch_mkernel(0, a, nb, m, 1, deg, s));  // X0
   if (constraint) GSF_TRY(lob_launch_project(a, w.X, nb, s));
@@ -540,7 +543,6 @@ gsf_status gsf_block_gram(int prec, int64_t n, int m, int nb, const void* const*
   r.kept_out = kept;
   r.nkept_out = kept + 32;
   hipStream_t s = (hipStream_t)stream;
-  GSF_TRY(hip_ok(hipMemsetAsync(g.counter, 0, 64, s)));
   GSF_TRY(lob_launch_gram(g, r, prec, s));
   const int ns = nb * m;
   GSF_TRY(hip_ok(hipMemcpyAsync(GA, gout, (size_t)ns * ns * 8, hipMemcpyDeviceToHost, s)));
@@ -595,5 +597,50 @@ gsf_status gsf_rayleigh_ritz(int ns, int m, const double* GA, const double* GB, 
 }
 
 size_t gsf_rr_workspace_bytes(void) { return 8192 + 4096; }
+
+gsf_status gsf_tune_apply(const gsf_operator* h, int m, const void* x, void* y, int reps, int* best_rpt,
+                          float* times_us, void* stream) {
+  if (h == nullptr || x == nullptr || y == nullptr || m < 1 || m > kMaxBlock || reps < 1) return GSF_EINVAL;
+  const Operator& op = h->op;
+  const int w = m >= 8 ? 8 : (m >= 4 ? 4 : m);
+  if (w != m) return GSF_EINVAL;  // tune the supported widths 1, 2, 3, 4, 8
+  if (op.desc.kind != GSF_BF) {
+    if (best_rpt) *best_rpt = 0;
+    return GSF_OK;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return GSF_EDEVICE;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    hipEventDestroy(e0);
+    return GSF_EDEVICE;
+  }
+  const int cand[3] = {1, 2, 4};
+  float best_t = 1e30f;
+  int best = bf_rpt(op, w);
+  gsf_status st = GSF_OK;
+  for (int c = 0; c < 3 && st == GSF_OK; ++c) {
+    st = launch_bf_apply_rpt(op, GSF_FORM_LSYM, m, x, m, y, m, nullptr, nullptr, cand[c], s);  // warm-up
+    if (st != GSF_OK) break;
+    if (hipEventRecord(e0, s) != hipSuccess) { st = GSF_EDEVICE; break; }
+    for (int k = 0; k < reps && st == GSF_OK; ++k)
+      st = launch_bf_apply_rpt(op, GSF_FORM_LSYM, m, x, m, y, m, nullptr, nullptr, cand[c], s);
+    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) { st = GSF_EDEVICE; break; }
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, e0, e1);
+    const float us = ms * 1000.f / (float)reps;
+    if (times_us) times_us[c] = us;
+    if (us < best_t) {
+      best_t = us;
+      best = cand[c];
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (st != GSF_OK) return st;
+  bf_set_rpt(op, w, best);
+  if (best_rpt) *best_rpt = best;
+  return GSF_OK;
+}
 
 }  // extern "C"

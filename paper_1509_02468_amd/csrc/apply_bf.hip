@@ -4,19 +4,40 @@
 namespace gsf {
 namespace {
 template <typename T>
-void launch_bf_m(const bfk::ApplyArgs& a, int ndim, int r, int m, hipStream_t s, int* nb) {
+void launch_bf_m(const bfk::ApplyArgs& a, int ndim, int r, int m, int rpt, hipStream_t s, int* nb) {
   switch (m) {
-    case 1: bf_apply_tm<T, 1>(a, ndim, r, s, nb); break;
-    case 2: bf_apply_tm<T, 2>(a, ndim, r, s, nb); break;
-    case 3: bf_apply_tm<T, 3>(a, ndim, r, s, nb); break;
-    case 4: bf_apply_tm<T, 4>(a, ndim, r, s, nb); break;
-    default: bf_apply_tm<T, 8>(a, ndim, r, s, nb); break;
+    case 1: bf_apply_tm<T, 1>(a, ndim, r, rpt, s, nb); break;
+    case 2: bf_apply_tm<T, 2>(a, ndim, r, rpt, s, nb); break;
+    case 3: bf_apply_tm<T, 3>(a, ndim, r, rpt, s, nb); break;
+    case 4: bf_apply_tm<T, 4>(a, ndim, r, rpt, s, nb); break;
+    default: bf_apply_tm<T, 8>(a, ndim, r, rpt, s, nb); break;
   }
 }
+
+// Tuned rows-per-thread choices, per (precision, ndim, radius, block width,
+// size class); 0 = not tuned (use the default).  Written by the apply tuner.
+int g_rpt[2][2][kMaxRadius + 1][kMaxBlock + 1][4];
+
+int size_class(int64_t n) { return n < (1 << 16) ? 0 : (n < (1 << 20) ? 1 : (n < (1 << 23) ? 2 : 3)); }
+
+int width_of(int left) { return left >= 8 ? 8 : (left >= 4 ? 4 : left); }
+
 }  // namespace
 
-gsf_status launch_bf_apply(const Operator& op, int form, int m, const void* x, int64_t ldx, void* y,
-                           int64_t ldy, double* dot, int* nparts, hipStream_t s) {
+int bf_rpt(const Operator& op, int w) {
+  const int t = g_rpt[op.desc.prec][op.desc.ndim - 1][op.desc.radius][w][size_class(op.n)];
+  return t > 0 ? t : bfk::default_rpt((int)op.elem, w);
+}
+
+void bf_set_rpt(const Operator& op, int w, int rpt) {
+  g_rpt[op.desc.prec][op.desc.ndim - 1][op.desc.radius][w][size_class(op.n)] = rpt;
+}
+
+gsf_status launch_bf_apply_rpt(const Operator& op, int form, int m, const void* x, int64_t ldx, void* y,
+                               int64_t ldy, double* dot, int* nparts, int rpt_override, hipStream_t s);
+
+gsf_status launch_bf_apply_rpt(const Operator& op, int form, int m, const void* x, int64_t ldx, void* y,
+                               int64_t ldy, double* dot, int* nparts, int rpt_override, hipStream_t s) {
   bfk::ApplyArgs a{};
   a.planes = op.planes;
   a.isqd = op.diag;
@@ -31,24 +52,29 @@ gsf_status launch_bf_apply(const Operator& op, int form, int m, const void* x, i
   int c0 = 0;
   int nb = 0;
   while (c0 < m) {
-    const int left = m - c0;
-    const int w = left >= 8 ? 8 : (left >= 4 ? 4 : left);
+    const int w = width_of(m - c0);
+    const int rpt = rpt_override > 0 ? rpt_override : bf_rpt(op, w);
     a.x = (const char*)x + (size_t)c0 * op.elem;
     a.y = (char*)y + (size_t)c0 * op.elem;
     if (op.desc.prec == GSF_F32)
-      launch_bf_m<float>(a, op.desc.ndim, op.desc.radius, w, s, &nb);
+      launch_bf_m<float>(a, op.desc.ndim, op.desc.radius, w, rpt, s, &nb);
     else
-      launch_bf_m<double>(a, op.desc.ndim, op.desc.radius, w, s, &nb);
+      launch_bf_m<double>(a, op.desc.ndim, op.desc.radius, w, rpt, s, &nb);
     c0 += w;
   }
   if (nparts) *nparts = nb;
   return hipGetLastError() == hipSuccess ? GSF_OK : GSF_EDEVICE;
 }
 
+gsf_status launch_bf_apply(const Operator& op, int form, int m, const void* x, int64_t ldx, void* y,
+                           int64_t ldy, double* dot, int* nparts, hipStream_t s) {
+  return launch_bf_apply_rpt(op, form, m, x, ldx, y, ldy, dot, nparts, 0, s);
+}
+
+// Upper bound of the workgroups (and so of the dot partials) of an apply.
 int bf_apply_blocks(const Operator& op, int m) {
-  const int w = m >= 8 ? 8 : (m >= 4 ? 4 : m);
-  const int mb = w * (int)op.elem;
-  const int rpt = mb <= 16 ? 4 : (mb <= 32 ? 2 : 1);
+  const int rpt = 1;  // fewest rows per thread = most workgroups
+  (void)m;
   if (op.desc.ndim == 2) {
     const int64_t tiles_x = (op.cols + 63) / 64, tiles_y = (op.rows + 4 * rpt - 1) / (4 * rpt);
     return (int)(tiles_x * tiles_y);

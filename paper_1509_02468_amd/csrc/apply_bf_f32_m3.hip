@@ -3,8 +3,8 @@
 
 namespace gsf {
 template <typename T, int M>
-void bf_apply_tm(const bfk::ApplyArgs& a, int ndim, int r, hipStream_t s, int* nb) {
-  bfk::launch_bf_r<T, M>(a, ndim, r, s, nb);
+void bf_apply_tm(const bfk::ApplyArgs& a, int ndim, int r, int rpt, hipStream_t s, int* nb) {
+  bfk::launch_bf_r<T, M>(a, ndim, r, rpt, s, nb);
 }
-template void bf_apply_tm<float, 3>(const bfk::ApplyArgs&, int, int, hipStream_t, int*);
+template void bf_apply_tm<float, 3>(const bfk::ApplyArgs&, int, int, int, hipStream_t, int*);
 }  // namespace gsf

@@ -33,12 +33,20 @@ struct ApplyArgs {
   double* dot;  // nullable, per-workgroup partial sum x.y (m = 1)
 };
 
+// Rows of points per thread (RPT) is a template choice in {1, 2, 4}: more rows
+// amortise the LDS halo, fewer rows give more workgroups (and so more loads in
+// flight per CU).  The default below keeps the LDS tile under ~64 KB; the
+// apply tuner may pick another one per (type, m, r).
 template <typename T, int M>
 struct Rows {
-  // rows of points per thread: keep the LDS tile under ~64 KB
   static constexpr int MB = M * (int)sizeof(T);
   static constexpr int RPT = MB <= 16 ? 4 : (MB <= 32 ? 2 : 1);
 };
+
+inline int default_rpt(int elem, int m) {
+  const int mb = elem * m;
+  return mb <= 16 ? 4 : (mb <= 32 ? 2 : 1);
+}
 
 // y from the Laplacian sum acc = sum_j w_ij (u_i - u_j) for one point.
 template <typename T, int M>
@@ -57,10 +65,17 @@ __device__ __forceinline__ void finish_point(int form, T is, const T* __restrict
   }
 }
 
-template <typename T, int M, int R>
+// How many offsets of one row of the window are scheduled together: all of
+// them for narrow blocks; for wide blocks fewer, so that the loaded weights
+// and neighbour values fit in registers at a useful occupancy.
+template <typename T, int M>
+struct DxUnroll {
+  static constexpr int value = (M * (int)sizeof(T) >= 16) ? 4 : 17;
+};
+
+template <typename T, int M, int R, int RPT>
 __global__ void __launch_bounds__(kThreads) bf_apply2d_kernel(ApplyArgs a) {
   constexpr int TX = 64;
-  constexpr int RPT = Rows<T, M>::RPT;
   constexpr int TY = 4 * RPT;
   constexpr int LW = TX + 2 * R;
   constexpr int LH = TY + 2 * R;
@@ -126,7 +141,7 @@ __global__ void __launch_bounds__(kThreads) bf_apply2d_kernel(ApplyArgs a) {
       const int64_t mshift = (int64_t)dy * W;
       const T* urow = uc + dy * LW * M;
       const T* umrow = uc - dy * LW * M;
-#pragma unroll
+#pragma unroll(DxUnroll<T, M>::value)
       for (int dx = -R; dx <= R; ++dx) {
         const T wo = valid ? pp[0] : T(0);
         const bool mok = up && gx - dx >= 0 && gx - dx < W;
@@ -155,9 +170,8 @@ __global__ void __launch_bounds__(kThreads) bf_apply2d_kernel(ApplyArgs a) {
   }
 }
 
-template <typename T, int M, int R>
+template <typename T, int M, int R, int RPT>
 __global__ void __launch_bounds__(kThreads) bf_apply1d_kernel(ApplyArgs a) {
-  constexpr int RPT = Rows<T, M>::RPT;
   constexpr int TN = kThreads * RPT;
   constexpr int LN = TN + 2 * R;
   __shared__ T us[LN * M];
@@ -221,35 +235,52 @@ __global__ void __launch_bounds__(kThreads) bf_apply1d_kernel(ApplyArgs a) {
   }
 }
 
-template <typename T, int M, int R>
+template <typename T, int M, int R, int RPT>
 void launch_bf_tile(const ApplyArgs& a, int ndim, hipStream_t s, int* nblocks) {
   if (ndim == 2) {
-    constexpr int TY = 4 * Rows<T, M>::RPT;
+    constexpr int TY = 4 * RPT;
     ApplyArgs b = a;
     b.tiles_x = (int)((a.cols + 63) / 64);
     const int tiles_y = (int)((a.rows + TY - 1) / TY);
     b.ntiles = b.tiles_x * tiles_y;
     *nblocks = b.ntiles;
-    bf_apply2d_kernel<T, M, R><<<b.ntiles, kThreads, 0, s>>>(b);
+    bf_apply2d_kernel<T, M, R, RPT><<<b.ntiles, kThreads, 0, s>>>(b);
   } else {
-    constexpr int TN = kThreads * Rows<T, M>::RPT;
+    constexpr int TN = kThreads * RPT;
     const int nb = (int)((a.n + TN - 1) / TN);
     *nblocks = nb;
-    bf_apply1d_kernel<T, M, R><<<nb, kThreads, 0, s>>>(a);
+    bf_apply1d_kernel<T, M, R, RPT><<<nb, kThreads, 0, s>>>(a);
   }
 }
 
+template <typename T, int M, int R>
+void launch_bf_rpt(const ApplyArgs& a, int ndim, int rpt, hipStream_t s, int* nb) {
+  constexpr int MB = M * (int)sizeof(T);
+  // taller tiles do not fit in LDS for wide FP64 blocks
+  if constexpr (MB <= 32) {
+    if (rpt >= 4) {
+      launch_bf_tile<T, M, R, 4>(a, ndim, s, nb);
+      return;
+    }
+    if (rpt >= 2) {
+      launch_bf_tile<T, M, R, 2>(a, ndim, s, nb);
+      return;
+    }
+  }
+  launch_bf_tile<T, M, R, 1>(a, ndim, s, nb);
+}
+
 template <typename T, int M>
-void launch_bf_r(const ApplyArgs& a, int ndim, int r, hipStream_t s, int* nb) {
+void launch_bf_r(const ApplyArgs& a, int ndim, int r, int rpt, hipStream_t s, int* nb) {
   switch (r) {
-    case 1: launch_bf_tile<T, M, 1>(a, ndim, s, nb); break;
-    case 2: launch_bf_tile<T, M, 2>(a, ndim, s, nb); break;
-    case 3: launch_bf_tile<T, M, 3>(a, ndim, s, nb); break;
-    case 4: launch_bf_tile<T, M, 4>(a, ndim, s, nb); break;
-    case 5: launch_bf_tile<T, M, 5>(a, ndim, s, nb); break;
-    case 6: launch_bf_tile<T, M, 6>(a, ndim, s, nb); break;
-    case 7: launch_bf_tile<T, M, 7>(a, ndim, s, nb); break;
-    default: launch_bf_tile<T, M, 8>(a, ndim, s, nb); break;
+    case 1: launch_bf_rpt<T, M, 1>(a, ndim, rpt, s, nb); break;
+    case 2: launch_bf_rpt<T, M, 2>(a, ndim, rpt, s, nb); break;
+    case 3: launch_bf_rpt<T, M, 3>(a, ndim, rpt, s, nb); break;
+    case 4: launch_bf_rpt<T, M, 4>(a, ndim, rpt, s, nb); break;
+    case 5: launch_bf_rpt<T, M, 5>(a, ndim, rpt, s, nb); break;
+    case 6: launch_bf_rpt<T, M, 6>(a, ndim, rpt, s, nb); break;
+    case 7: launch_bf_rpt<T, M, 7>(a, ndim, rpt, s, nb); break;
+    default: launch_bf_rpt<T, M, 8>(a, ndim, rpt, s, nb); break;
   }
 }
 
@@ -257,6 +288,6 @@ void launch_bf_r(const ApplyArgs& a, int ndim, int r, hipStream_t s, int* nb) {
 
 // one translation unit per (T, M) instantiates this
 template <typename T, int M>
-void bf_apply_tm(const bfk::ApplyArgs& a, int ndim, int r, hipStream_t s, int* nb);
+void bf_apply_tm(const bfk::ApplyArgs& a, int ndim, int r, int rpt, hipStream_t s, int* nb);
 
 }  // namespace gsf

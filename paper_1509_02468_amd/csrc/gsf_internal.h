@@ -66,32 +66,9 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* lds /* NV * 1
   __syncthreads();
 }
 
-// Device-coherent load (bypasses the non-coherent per-CU cache).
-template <typename T>
-__device__ __forceinline__ T load_coherent(const T* p) {
-  return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// "Last workgroup" detection for one-pass reductions: every workgroup has
-// written its partials before calling this; the workgroup that arrives last
-// returns true (uniformly over its threads) and may then read all partials.
-// The counter is left at zero for the next launch.
-__device__ __forceinline__ bool arrive_last(unsigned int* counter, unsigned int nblocks) {
-  __shared__ int s_last;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned int prev = atomicAdd(counter, 1u);
-    s_last = (prev == nblocks - 1) ? 1 : 0;
-    if (s_last) atomicExch(counter, 0u);
-  }
-  __syncthreads();
-  if (s_last) __threadfence();
-  return s_last != 0;
-}
-
 // Sum partials[b * stride + k] over b = 0..nparts-1 for k < NV in a fixed
-// order (independent of which workgroup runs it).  Result valid in thread 0.
+// order (the partials were written by an earlier kernel on the stream).
+// Result valid in thread 0.
 template <int NV>
 __device__ __forceinline__ void reduce_partials(const double* partials, int nparts, int stride,
                                                 double (&out)[NV], double* lds) {
@@ -99,7 +76,7 @@ __device__ __forceinline__ void reduce_partials(const double* partials, int npar
   for (int k = 0; k < NV; ++k) out[k] = 0.0;
   for (int b = threadIdx.x; b < nparts; b += blockDim.x) {
 #pragma unroll
-    for (int k = 0; k < NV; ++k) out[k] += load_coherent(partials + (size_t)b * stride + k);
+    for (int k = 0; k < NV; ++k) out[k] += partials[(size_t)b * stride + k];
   }
   block_sum<NV>(out, lds);
 }

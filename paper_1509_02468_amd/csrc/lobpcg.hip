@@ -8,8 +8,8 @@
 //   gram           partial Gram tiles S^T S, S^T (A S) of S = [X, W, P] with
 //                  MFMA (FP32: v_mfma_f32_16x16x4f32 accumulated in FP32 over
 //                  256 points then in FP64; FP64: v_mfma_f64_16x16x4f64)
-//   gram_rr        fixed-order reduction of the tiles, then the Rayleigh-Ritz
-//                  step on one workgroup in FP64: unit-diagonal scaling,
+//   gram_reduce /  fixed-order two-level reduction of the tiles, then the
+//   gram_rr        Rayleigh-Ritz step on one workgroup in FP64: unit-diagonal scaling,
 //                  column-dropping Cholesky, reduction to L^-1 A L^-T, cyclic
 //                  parallel Jacobi eigensolver, m smallest Ritz pairs
 //   lob_update     X = S C, AX = (AS) C, P = [W,P] C, AP likewise, the next
@@ -52,10 +52,34 @@ __global__ void __launch_bounds__(kThreads) lob_ynorm_kernel(const T* __restrict
     v[0] += (double)sqd[i] * (double)sqd[i];
   block_sum<1>(v, red);
   if (threadIdx.x == 0) partials[blockIdx.x] = v[0];
-  if (!arrive_last(&st->counter, gridDim.x)) return;
-  double t[1];
-  reduce_partials<1>(partials, gridDim.x, 1, t, red);
-  if (threadIdx.x == 0) st->ynorm_inv = 1.0 / sqrt(t[0]);
+}
+
+// one workgroup: sum the partials of a previous kernel in workgroup order;
+// mode 0: ynorm_inv, 1: yx (M values), 2: update residuals (2M values),
+// 3: output coefficients (M+1 values)
+template <int NV>
+__global__ void __launch_bounds__(kThreads) lob_final_kernel(const double* __restrict__ partials, int nparts,
+                                                             LobpcgState* st, int mode, int m, int first,
+                                                             int constraint) {
+  __shared__ double red[16 * NV];
+  if (mode == 2 && !st->active) return;
+  double t[NV];
+  reduce_partials<NV>(partials, nparts, NV, t, red);
+  if (threadIdx.x != 0) return;
+  if (mode == 0) {
+    st->ynorm_inv = 1.0 / sqrt(t[0]);
+  } else if (mode == 1 || mode == 3) {
+    for (int j = 0; j < NV; ++j) st->yx[j] = t[j];
+  } else {
+    double mx = 0.0;
+    for (int j = 0; j < m; ++j) {
+      st->res[j] = sqrt(t[j]);
+      st->yx[j] = constraint ? t[m + j] : 0.0;
+      mx = st->res[j] > mx ? st->res[j] : mx;
+    }
+    if (!first) st->iters += 1;
+    if (st->tol > 0.0 && mx <= st->tol) st->active = 0;
+  }
 }
 
 // X0[i, j] = sqrt(d_i) x0_i phi_j(i); with the constraint also Y^T X0.
@@ -89,11 +113,6 @@ __global__ void __launch_bounds__(kThreads) lob_start_kernel(LobArgs a, StartDeg
   block_sum<M>(v, red);
   if (threadIdx.x == 0)
     for (int j = 0; j < M; ++j) a.vpart[(size_t)blockIdx.x * M + j] = v[j];
-  if (!arrive_last(&a.st->counter, gridDim.x)) return;
-  double t[M];
-  reduce_partials<M>(a.vpart, gridDim.x, M, t, red);
-  if (threadIdx.x == 0)
-    for (int j = 0; j < M; ++j) a.st->yx[j] = t[j];
 }
 
 // B[i, j] -= Y_i c_j with c = st->yx
@@ -134,18 +153,19 @@ struct MfmaAcc<double> {
   }
 };
 
-template <typename T>
+template <typename T, int NT>
 __global__ void __launch_bounds__(kThreads) gram_kernel(GramArgs g) {
   typedef typename MfmaAcc<T>::type acc_t;
-  __shared__ double wsum[4][7][4][64];  // per wave, tile, register, lane
+  constexpr int U = 8;  // point groups of 4 loaded ahead of their MFMAs
+  constexpr int ntb = NT == 1 ? 1 : 3, nta = NT == 1 ? 1 : 4;
+  constexpr int nt = NT;
+  __shared__ double wsum[4][4][64];  // one tile at a time: wave, register, lane
   if (g.active != nullptr && *g.active == 0) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int ns = g.ns, m = g.m;
-  const int nt = (ns + 15) >> 4;
-  const int ntb = n_tiles_b(nt), nta = n_tiles_a(nt);
   const int col = lane & 15, krow = lane >> 4;
 
-  // the S / AS column each lane feeds for tile row I
+  // the S / AS column each lane feeds for tile row I (0 past the last column)
   const T* sp[2] = {nullptr, nullptr};
   const T* ap[2] = {nullptr, nullptr};
   for (int I = 0; I < nt; ++I) {
@@ -160,57 +180,60 @@ __global__ void __launch_bounds__(kThreads) gram_kernel(GramArgs g) {
   const int64_t nw = (int64_t)gridDim.x * 4;
   const int64_t wid = (int64_t)blockIdx.x * 4 + wave;
   int64_t chunk = (g.n + nw - 1) / nw;
-  chunk = (chunk + 3) & ~(int64_t)3;
+  chunk = (chunk + 4 * U - 1) / (4 * U) * (4 * U);
   const int64_t p_begin = wid * chunk;
   const int64_t p_end = (p_begin + chunk < g.n) ? p_begin + chunk : g.n;
 
-  double totb[3][4], tota[4][4];
+  double totb[ntb][4], tota[nta][4];
 #pragma unroll
-  for (int t = 0; t < 3; ++t)
+  for (int t = 0; t < ntb; ++t)
 #pragma unroll
     for (int v = 0; v < 4; ++v) totb[t][v] = 0.0;
 #pragma unroll
-  for (int t = 0; t < 4; ++t)
+  for (int t = 0; t < nta; ++t)
 #pragma unroll
     for (int v = 0; v < 4; ++v) tota[t][v] = 0.0;
-  acc_t accb[3], acca[4];
+  acc_t accb[ntb], acca[nta];
 #pragma unroll
-  for (int t = 0; t < 3; ++t) accb[t] = acc_t{0, 0, 0, 0};
+  for (int t = 0; t < ntb; ++t) accb[t] = acc_t{0, 0, 0, 0};
 #pragma unroll
-  for (int t = 0; t < 4; ++t) acca[t] = acc_t{0, 0, 0, 0};
+  for (int t = 0; t < nta; ++t) acca[t] = acc_t{0, 0, 0, 0};
 
   int steps = 0;
-  for (int64_t p0 = p_begin; p0 < p_end; p0 += 4) {
-    const int64_t p = p0 + krow;
-    const bool ok = p < p_end;
-    T s0 = T(0), s1 = T(0), a0 = T(0), a1 = T(0);
-    if (ok && sp[0]) {
-      s0 = sp[0][p * m];
-      a0 = ap[0][p * m];
+  for (int64_t p0 = p_begin; p0 < p_end; p0 += 4 * U) {
+    T s0[U], s1[U], a0[U], a1[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t p = p0 + 4 * u + krow;
+      const bool ok = p < p_end;
+      s0[u] = (ok && sp[0]) ? sp[0][p * m] : T(0);
+      a0[u] = (ok && sp[0]) ? ap[0][p * m] : T(0);
+      s1[u] = (NT > 1 && ok && sp[1]) ? sp[1][p * m] : T(0);
+      a1[u] = (NT > 1 && ok && sp[1]) ? ap[1][p * m] : T(0);
     }
-    if (nt > 1 && ok && sp[1]) {
-      s1 = sp[1][p * m];
-      a1 = ap[1][p * m];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      accb[0] = MfmaAcc<T>::mfma(s0[u], s0[u], accb[0]);
+      acca[0] = MfmaAcc<T>::mfma(s0[u], a0[u], acca[0]);
+      if constexpr (NT > 1) {
+        accb[1] = MfmaAcc<T>::mfma(s0[u], s1[u], accb[1]);
+        accb[2] = MfmaAcc<T>::mfma(s1[u], s1[u], accb[2]);
+        acca[1] = MfmaAcc<T>::mfma(s0[u], a1[u], acca[1]);
+        acca[2] = MfmaAcc<T>::mfma(s1[u], a0[u], acca[2]);
+        acca[3] = MfmaAcc<T>::mfma(s1[u], a1[u], acca[3]);
+      }
     }
-    accb[0] = MfmaAcc<T>::mfma(s0, s0, accb[0]);
-    acca[0] = MfmaAcc<T>::mfma(s0, a0, acca[0]);
-    if (nt > 1) {
-      accb[1] = MfmaAcc<T>::mfma(s0, s1, accb[1]);
-      accb[2] = MfmaAcc<T>::mfma(s1, s1, accb[2]);
-      acca[1] = MfmaAcc<T>::mfma(s0, a1, acca[1]);
-      acca[2] = MfmaAcc<T>::mfma(s1, a0, acca[2]);
-      acca[3] = MfmaAcc<T>::mfma(s1, a1, acca[3]);
-    }
-    if (sizeof(T) == 4 && ++steps == 64) {  // FP32: move the 256-point partial into FP64
+    steps += U;
+    if (sizeof(T) == 4 && steps >= 64) {  // FP32: move each 256-point partial into FP64
       steps = 0;
 #pragma unroll
-      for (int t = 0; t < 3; ++t) {
+      for (int t = 0; t < ntb; ++t) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) totb[t][v] += (double)accb[t][v];
         accb[t] = acc_t{0, 0, 0, 0};
       }
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
+      for (int t = 0; t < nta; ++t) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) tota[t][v] += (double)acca[t][v];
         acca[t] = acc_t{0, 0, 0, 0};
@@ -218,31 +241,41 @@ __global__ void __launch_bounds__(kThreads) gram_kernel(GramArgs g) {
     }
   }
 #pragma unroll
-  for (int t = 0; t < 3; ++t)
+  for (int t = 0; t < ntb; ++t)
 #pragma unroll
     for (int v = 0; v < 4; ++v) totb[t][v] += (double)accb[t][v];
 #pragma unroll
-  for (int t = 0; t < 4; ++t)
+  for (int t = 0; t < nta; ++t)
 #pragma unroll
     for (int v = 0; v < 4; ++v) tota[t][v] += (double)acca[t][v];
 
-  // fixed-order sum over the 4 waves of the workgroup
-  for (int t = 0; t < ntb; ++t)
-    for (int v = 0; v < 4; ++v) wsum[wave][t][v][lane] = totb[t][v];
-  for (int t = 0; t < nta; ++t)
-    for (int v = 0; v < 4; ++v) wsum[wave][ntb + t][v][lane] = tota[t][v];
-  __syncthreads();
-  const int ntot = ntb + nta;
-  // entry e = tile*256 + i*16 + j.  Output layouts of the two MFMA variants:
+  // fixed-order sum over the 4 waves, one tile at a time.  Output layouts of
+  // the two MFMA variants (entry e = i*16 + j of a tile):
   //   16x16x4 f32: D[i][j] in lane j + 16*(i/4), register i%4
   //   16x16x4 f64: D[i][j] in lane j + 16*(i%4), register i/4
-  for (int e = threadIdx.x; e < ntot * 256; e += blockDim.x) {
-    const int t = e >> 8, ij = e & 255;
-    const int i = ij >> 4, j = ij & 15;
-    const int ln = sizeof(T) == 4 ? j + 16 * (i >> 2) : j + 16 * (i & 3);
-    const int v = sizeof(T) == 4 ? (i & 3) : (i >> 2);
-    const double s = wsum[0][t][v][ln] + wsum[1][t][v][ln] + wsum[2][t][v][ln] + wsum[3][t][v][ln];
-    g.partials[(size_t)blockIdx.x * (ntot * 256) + e] = s;
+  const int ntot = ntb + nta;
+  for (int t = 0; t < ntot; ++t) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      double val = 0.0;
+#pragma unroll
+      for (int tt = 0; tt < ntb; ++tt)
+        if (t == tt) val = totb[tt][v];
+#pragma unroll
+      for (int tt = 0; tt < nta; ++tt)
+        if (t == ntb + tt) val = tota[tt][v];
+      wsum[wave][v][lane] = val;
+    }
+    __syncthreads();
+    {
+      const int ij = threadIdx.x;  // 256 threads = 256 entries
+      const int i = ij >> 4, j = ij & 15;
+      const int ln = sizeof(T) == 4 ? j + 16 * (i >> 2) : j + 16 * (i & 3);
+      const int v = sizeof(T) == 4 ? (i & 3) : (i >> 2);
+      const double sm = wsum[0][v][ln] + wsum[1][v][ln] + wsum[2][v][ln] + wsum[3][v][ln];
+      g.partials[((size_t)blockIdx.x * ntot + t) * 256 + ij] = sm;
+    }
+    __syncthreads();
   }
 }
 
@@ -256,7 +289,7 @@ struct RRShared {
   double A[KMAX * LD];
   double B[KMAX * LD];
   double L[KMAX * LD];
-  double Li[KMAX * LD];
+  double LK[KMAX * LD];  // compressed Cholesky factor of the kept columns
   double M[KMAX * LD];
   double M2[KMAX * LD];
   double V[KMAX * LD];
@@ -264,6 +297,7 @@ struct RRShared {
   double delta[KMAX];
   double jself[KMAX + 1];
   double joff[KMAX + 1];
+  double dnew[KMAX + 1];
   int partner[KMAX + 1];
   int good[KMAX];
   int kept[KMAX];
@@ -358,50 +392,55 @@ __device__ void rayleigh_ritz(RRShared& sh, int ns, int m, double drop_tol, doub
     __syncthreads();
     return;
   }
-  // compressed factor LK -> M, reduced A -> M2
+  // compressed factor LK (in L) and reduced A (in M2)
   for (int e = tid; e < K * K; e += nth) {
     const int a = e / K, b = e - (e / K) * K;
-    sh.M[a * LD + b] = (b <= a) ? sh.L[sh.idx[a] * LD + sh.idx[b]] : 0.0;
+    sh.LK[a * LD + b] = (b <= a) ? sh.L[sh.idx[a] * LD + sh.idx[b]] : 0.0;
     sh.M2[a * LD + b] = sh.A[sh.idx[a] * LD + sh.idx[b]];
   }
   __syncthreads();
-  // Li = LK^-1 by forward substitution, one column per thread
+  // T = LK^-1 A_K: thread c solves LK t = A_K[:, c] by forward substitution
+  // with its column in registers (LK read as LDS broadcasts), then writes row
+  // c of T^T.  A_K is symmetric, so M = T LK^-T = (LK^-1 T^T)^T.
   if (tid < K) {
     const int c = tid;
-    for (int i = 0; i < K; ++i) {
-      double v = (i == c) ? 1.0 : 0.0;
-      if (i > c)
-        for (int t = c; t < i; ++t) v -= sh.M[i * LD + t] * sh.Li[t * LD + c];
-      sh.Li[i * LD + c] = (i < c) ? 0.0 : v / sh.M[i * LD + i];
+    double col[KMAX];
+#pragma unroll
+    for (int i = 0; i < KMAX; ++i) {
+      if (i < K) {
+        double v = sh.M2[i * LD + c];
+#pragma unroll
+        for (int t = 0; t < KMAX; ++t)
+          if (t < i) v -= sh.LK[i * LD + t] * col[t];
+        col[i] = v / sh.LK[i * LD + i];
+      }
     }
+#pragma unroll
+    for (int i = 0; i < KMAX; ++i)
+      if (i < K) sh.V[c * LD + i] = col[i];  // V = T^T
   }
   __syncthreads();
-  // V = Li * A_K (temporary), then M = V * Li^T
-  for (int e = tid; e < K * K; e += nth) {
-    const int a = e / K, b = e - (e / K) * K;
-    double s = 0.0;
-    for (int t = 0; t <= a; ++t) s += sh.Li[a * LD + t] * sh.M2[t * LD + b];
-    sh.V[a * LD + b] = s;
-  }
-  __syncthreads();
-  for (int e = tid; e < K * K; e += nth) {
-    const int a = e / K, b = e - (e / K) * K;
-    double s = 0.0;
-    for (int t = 0; t <= b; ++t) s += sh.V[a * LD + t] * sh.Li[b * LD + t];
-    sh.M[a * LD + b] = s;
-  }
-  __syncthreads();
-  for (int e = tid; e < K * K; e += nth) {
-    const int a = e / K, b = e - (e / K) * K;
-    if (a < b) {
-      const double s = 0.5 * (sh.M[a * LD + b] + sh.M[b * LD + a]);
-      sh.M2[a * LD + b] = s;
+  if (tid < K) {
+    const int c = tid;
+    double col[KMAX];
+#pragma unroll
+    for (int i = 0; i < KMAX; ++i) {
+      if (i < K) {
+        double v = sh.V[i * LD + c];
+#pragma unroll
+        for (int t = 0; t < KMAX; ++t)
+          if (t < i) v -= sh.LK[i * LD + t] * col[t];
+        col[i] = v / sh.LK[i * LD + i];
+      }
     }
+#pragma unroll
+    for (int i = 0; i < KMAX; ++i)
+      if (i < K) sh.M2[c * LD + i] = col[i];  // M2 = (LK^-1 T^T)^T = M
   }
   __syncthreads();
   for (int e = tid; e < K * K; e += nth) {
     const int a = e / K, b = e - (e / K) * K;
-    if (a < b) sh.M[a * LD + b] = sh.M[b * LD + a] = sh.M2[a * LD + b];
+    sh.M[a * LD + b] = 0.5 * (sh.M2[a * LD + b] + sh.M2[b * LD + a]);
     sh.V[a * LD + b] = (a == b) ? 1.0 : 0.0;
   }
   __syncthreads();
@@ -412,20 +451,23 @@ __device__ void rayleigh_ritz(RRShared& sh, int ns, int m, double drop_tol, doub
   double* Mn = sh.M2;
   double* Vc = sh.V;
   double* Vn = sh.V2;
-  for (int sweep = 0; sweep < 40; ++sweep) {
+  for (int sweep = 0; sweep < 30; ++sweep) {
     for (int rnd = 0; rnd < np - 1; ++rnd) {
       if (tid < np / 2) {
         const int s0 = tid, s1 = np - 1 - tid;
         const int pa = (s0 == 0) ? 0 : 1 + ((s0 - 1 + rnd) % (np - 1));
         const int pb = 1 + ((s1 - 1 + rnd) % (np - 1));
         const int p = pa < pb ? pa : pb, q = pa < pb ? pb : pa;
-        double c = 1.0, s = 0.0;
+        double c = 1.0, s = 0.0, t = 0.0, apq = 0.0;
         if (q < K) {
-          const double apq = Mc[p * LD + q];
+          apq = Mc[p * LD + q];
           if (apq != 0.0) {
-            const double th = (Mc[q * LD + q] - Mc[p * LD + p]) / (2.0 * apq);
-            const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(1.0 + th * th));
-            c = 1.0 / sqrt(1.0 + t * t);
+            // t = tan of the rotation angle, the root of t^2 + 2 theta t - 1 = 0
+            // of smaller magnitude, theta = (a_qq - a_pp) / (2 a_pq)
+            const double d = Mc[q * LD + q] - Mc[p * LD + p];
+            const double h = sqrt(d * d + 4.0 * apq * apq);
+            t = 2.0 * apq / (d >= 0.0 ? d + h : d - h);
+            c = rsqrt(1.0 + t * t);
             s = t * c;
           }
         }
@@ -435,17 +477,27 @@ __device__ void rayleigh_ritz(RRShared& sh, int ns, int m, double drop_tol, doub
         sh.jself[q] = c;
         sh.joff[p] = -s;  // J[q][p]
         sh.joff[q] = s;   // J[p][q]
+        // the rotated pair: a_pq becomes exactly 0, the diagonal moves by t a_pq
+        sh.dnew[p] = (q < K) ? Mc[p * LD + p] - t * apq : Mc[p * LD + p];
+        if (q < K) sh.dnew[q] = Mc[q * LD + q] + t * apq;
       }
       __syncthreads();
       for (int e = tid; e < K * K; e += nth) {
         const int i = e / K, j = e - (e / K) * K;
         const int pi = sh.partner[i], pj = sh.partner[j];
         const double ci = sh.jself[i], oi = sh.joff[i], cj = sh.jself[j], oj = sh.joff[j];
-        double v = ci * cj * Mc[i * LD + j];
-        if (pj < K) v += ci * oj * Mc[i * LD + pj];
-        if (pi < K) {
-          v += oi * cj * Mc[pi * LD + j];
-          if (pj < K) v += oi * oj * Mc[pi * LD + pj];
+        double v;
+        if (i == j) {
+          v = sh.dnew[i];
+        } else if (pi == j) {
+          v = 0.0;
+        } else {
+          v = ci * cj * Mc[i * LD + j];
+          if (pj < K) v += ci * oj * Mc[i * LD + pj];
+          if (pi < K) {
+            v += oi * cj * Mc[pi * LD + j];
+            if (pj < K) v += oi * oj * Mc[pi * LD + pj];
+          }
         }
         Mn[i * LD + j] = v;
         double w = Vc[i * LD + j] * cj;
@@ -471,7 +523,8 @@ __device__ void rayleigh_ritz(RRShared& sh, int ns, int m, double drop_tol, doub
         acc[0] += v;
     }
     block_sum<2>(acc, sh.red);
-    if (tid == 0) sh.stop = (acc[0] <= 1e-30 * acc[1]) ? 1 : 0;
+    // off-diagonal Frobenius mass below 1e-14 of the whole (relative)
+    if (tid == 0) sh.stop = (acc[0] <= 1e-28 * (acc[0] + acc[1])) ? 1 : 0;
     __syncthreads();
     if (sh.stop) break;
   }
@@ -486,42 +539,67 @@ __device__ void rayleigh_ritz(RRShared& sh, int ns, int m, double drop_tol, doub
   }
   __syncthreads();
   if (tid < m) theta[tid] = sh.ev[sh.order[tid]];
-  // C rows: C[idx[a]][t] = delta * sum_b Li[b][a] Z[b][t]
+  // C_K = LK^-T Z_m: thread t solves LK^T c = Z[:, order[t]] by back substitution
   for (int e = tid; e < ns * m; e += nth) Cout[e] = 0.0;
   __syncthreads();
-  for (int e = tid; e < K * m; e += nth) {
-    const int a = e / m, t = e - (e / m) * m;
-    const int col = sh.order[t];
-    double s = 0.0;
-    for (int b = a; b < K; ++b) s += sh.Li[b * LD + a] * Vc[b * LD + col];
-    const int row = sh.idx[a];
-    Cout[row * m + t] = sh.delta[row] * s;
+  if (tid < m) {
+    const int t = tid, col = sh.order[t];
+    double c[KMAX];
+#pragma unroll
+    for (int ii = KMAX - 1; ii >= 0; --ii) {
+      if (ii < K) {
+        double v = Vc[ii * LD + col];
+#pragma unroll
+        for (int b = 0; b < KMAX; ++b)
+          if (b > ii && b < K) v -= sh.LK[b * LD + ii] * c[b];
+        c[ii] = v / sh.LK[ii * LD + ii];
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < KMAX; ++a)
+      if (a < K) {
+        const int row = sh.idx[a];
+        Cout[row * m + t] = sh.delta[row] * c[a];
+      }
   }
   __syncthreads();
 }
 
-// Reduces the Gram partials (tiles x 256 entries) and runs Rayleigh-Ritz in
-// the last workgroup.  grid = (ntiles, 8 partial chunks).
+// First stage of the Gram reduction: workgroup (tile, chunk) sums the partials
+// of its chunk of Gram workgroups for the 256 entries of one tile.
+__global__ void __launch_bounds__(kThreads) gram_reduce_kernel(GramArgs g) {
+  if (g.active != nullptr && *g.active == 0) return;
+  const int nt = (g.ns + 15) >> 4;
+  const int ntot = n_tiles_b(nt) + n_tiles_a(nt);
+  const int tile = blockIdx.x, chunk = blockIdx.y, nchunks = gridDim.y;
+  const int per = (g.nparts + nchunks - 1) / nchunks;
+  const int b0 = chunk * per, b1 = (b0 + per < g.nparts) ? b0 + per : g.nparts;
+  const int e = tile * 256 + threadIdx.x;
+  const size_t st = (size_t)ntot * 256;
+  // up to kGramPerChunk partials, loaded together, summed in order
+  double v[kGramPerChunk];
+#pragma unroll
+  for (int k = 0; k < kGramPerChunk; ++k) v[k] = (b0 + k < b1) ? g.partials[(size_t)(b0 + k) * st + e] : 0.0;
+  double s = 0.0;
+#pragma unroll
+  for (int k = 0; k < kGramPerChunk; ++k) s += v[k];
+  g.level2[(size_t)chunk * st + e] = s;
+}
+
+// One workgroup: sums the chunks, assembles GA and GB (ns x ns) and runs the
+// Rayleigh-Ritz step.
 __global__ void __launch_bounds__(kThreads) gram_rr_kernel(GramArgs g, RRArgs r) {
   __shared__ RRShared sh;
   if (r.st != nullptr && !r.st->active) return;
   const int nt = (g.ns + 15) >> 4;
-  const int ntb = n_tiles_b(nt), nta = n_tiles_a(nt), ntot = ntb + nta;
-  const int tile = blockIdx.x, chunk = blockIdx.y, nchunks = gridDim.y;
-  const int nparts = g.nparts;
-  const int per = (nparts + nchunks - 1) / nchunks;
-  const int b0 = chunk * per, b1 = (b0 + per < nparts) ? b0 + per : nparts;
-  {
-    const int e = tile * 256 + threadIdx.x;
-    double s = 0.0;
-    for (int b = b0; b < b1; ++b) s += g.partials[(size_t)b * (ntot * 256) + e];
-    g.level2[(size_t)chunk * (ntot * 256) + e] = s;
-  }
-  if (!arrive_last(g.counter, gridDim.x * gridDim.y)) return;
-  // assemble GA and GB (ns x ns) from the tiles
+  const int ntb = n_tiles_b(nt), ntot = ntb + n_tiles_a(nt);
   for (int e = threadIdx.x; e < ntot * 256; e += blockDim.x) {
+    double v[kGramChunks];
+#pragma unroll
+    for (int c = 0; c < kGramChunks; ++c) v[c] = g.level2[(size_t)c * (ntot * 256) + e];
     double s = 0.0;
-    for (int c = 0; c < nchunks; ++c) s += load_coherent(g.level2 + (size_t)c * (ntot * 256) + e);
+#pragma unroll
+    for (int c = 0; c < kGramChunks; ++c) s += v[c];
     const int t = e >> 8, i = (e & 255) >> 4, j = e & 15;
     int I, J;
     bool isb;
@@ -579,14 +657,45 @@ __global__ void __launch_bounds__(kThreads) gram_rr_kernel(GramArgs g, RRArgs r)
 // ---------------------------------------------------------------------------
 // update + next residual
 // ---------------------------------------------------------------------------
+// Row helpers: the M values of one point, as vector memory operations when
+// the row is a whole number of 16-byte words.
 template <typename T, int M>
-__global__ void __launch_bounds__(kThreads) lob_update_kernel(LobArgs a, int ns, int first) {
+__device__ __forceinline__ void load_row(const T* __restrict__ src, T (&v)[M]) {
+  if constexpr (sizeof(T) * M % 16 == 0) {
+    constexpr int W = (int)(sizeof(T) * M / 16);
+    const float4* s4 = reinterpret_cast<const float4*>(src);
+#pragma unroll
+    for (int w = 0; w < W; ++w) reinterpret_cast<float4*>(v)[w] = s4[w];
+  } else {
+#pragma unroll
+    for (int j = 0; j < M; ++j) v[j] = src[j];
+  }
+}
+
+template <typename T, int M>
+__device__ __forceinline__ void store_row(T* __restrict__ dst, const T (&v)[M]) {
+  if constexpr (sizeof(T) * M % 16 == 0) {
+    constexpr int W = (int)(sizeof(T) * M / 16);
+    float4* d4 = reinterpret_cast<float4*>(dst);
+#pragma unroll
+    for (int w = 0; w < W; ++w) d4[w] = reinterpret_cast<const float4*>(v)[w];
+  } else {
+#pragma unroll
+    for (int j = 0; j < M; ++j) dst[j] = v[j];
+  }
+}
+
+// NB = number of blocks in the trial basis: 1 (start block), 2 ([X, W]),
+// 3 ([X, W, P]).  Coefficients C (NB*M x M, FP64) are read from LDS; every
+// output column is accumulated in FP64 and rounded once.
+template <typename T, int M, int NB>
+__global__ void __launch_bounds__(kThreads) lob_update_kernel(LobArgs a, int first) {
   __shared__ double Cs[3 * M * M];
   __shared__ double th[M];
   __shared__ double red[16 * 2 * M];
   LobpcgState* st = a.st;
   if (!st->active) return;
-  for (int e = threadIdx.x; e < ns * M; e += blockDim.x) Cs[e] = a.C[e];
+  for (int e = threadIdx.x; e < NB * M * M; e += blockDim.x) Cs[e] = a.C[e];
   if (threadIdx.x < M) th[threadIdx.x] = st->theta[threadIdx.x];
   __syncthreads();
   T* __restrict__ X = (T*)a.X;
@@ -597,81 +706,66 @@ __global__ void __launch_bounds__(kThreads) lob_update_kernel(LobArgs a, int ns,
   T* __restrict__ AP = (T*)a.AP;
   const T* __restrict__ sqd = (const T*)a.sqd;
   const double yinv = st->ynorm_inv;
-  const int nb = ns / M;  // 1, 2 or 3 blocks in the trial basis
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   double v[2 * M];
 #pragma unroll
   for (int j = 0; j < 2 * M; ++j) v[j] = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += stride) {
-    double s[3][M], as[3][M];
-#pragma unroll
-    for (int j = 0; j < M; ++j) {
-      s[0][j] = (double)X[i * M + j];
-      as[0][j] = (double)AX[i * M + j];
-      s[1][j] = nb > 1 ? (double)W[i * M + j] : 0.0;
-      as[1][j] = nb > 1 ? (double)AW[i * M + j] : 0.0;
-      s[2][j] = nb > 2 ? (double)P[i * M + j] : 0.0;
-      as[2][j] = nb > 2 ? (double)AP[i * M + j] : 0.0;
+    // keep the coefficients in LDS: without this the loop-invariant reads are
+    // hoisted into (NB*M*M doubles of) registers and occupancy collapses
+    __asm__ volatile("" ::: "memory");
+    T s[NB][M], as[NB][M];
+    load_row<T, M>(X + i * M, s[0]);
+    load_row<T, M>(AX + i * M, as[0]);
+    if constexpr (NB > 1) {
+      load_row<T, M>(W + i * M, s[1]);
+      load_row<T, M>(AW + i * M, as[1]);
     }
-    double xn[M], axn[M], pn[M], apn[M];
+    if constexpr (NB > 2) {
+      load_row<T, M>(P + i * M, s[2]);
+      load_row<T, M>(AP + i * M, as[2]);
+    }
+    const double yi = (double)sqd[i] * yinv;
+    T xo[M], axo[M], po[M], apo[M], ro[M];
 #pragma unroll
     for (int t = 0; t < M; ++t) {
       double px = 0.0, pax = 0.0, pp = 0.0, pap = 0.0;
 #pragma unroll
       for (int j = 0; j < M; ++j) {
-        px += s[0][j] * Cs[j * M + t];
-        pax += as[0][j] * Cs[j * M + t];
+        const double c = Cs[j * M + t];
+        px += (double)s[0][j] * c;
+        pax += (double)as[0][j] * c;
       }
-      if (nb > 1) {
+#pragma unroll
+      for (int b = 1; b < NB; ++b) {
 #pragma unroll
         for (int j = 0; j < M; ++j) {
-          pp += s[1][j] * Cs[(M + j) * M + t];
-          pap += as[1][j] * Cs[(M + j) * M + t];
+          const double c = Cs[(b * M + j) * M + t];
+          pp += (double)s[b][j] * c;
+          pap += (double)as[b][j] * c;
         }
       }
-      if (nb > 2) {
-#pragma unroll
-        for (int j = 0; j < M; ++j) {
-          pp += s[2][j] * Cs[(2 * M + j) * M + t];
-          pap += as[2][j] * Cs[(2 * M + j) * M + t];
-        }
-      }
-      xn[t] = px + pp;
-      axn[t] = pax + pap;
-      pn[t] = pp;
-      apn[t] = pap;
-    }
-    const double yi = (double)sqd[i] * yinv;
-#pragma unroll
-    for (int t = 0; t < M; ++t) {
-      const double rt = axn[t] - xn[t] * th[t];
-      X[i * M + t] = (T)xn[t];
-      AX[i * M + t] = (T)axn[t];
-      if (!first) {
-        P[i * M + t] = (T)pn[t];
-        AP[i * M + t] = (T)apn[t];
-      }
-      W[i * M + t] = (T)rt;
+      const double xn = px + pp, axn = pax + pap;
+      const double rt = axn - xn * th[t];
+      xo[t] = (T)xn;
+      axo[t] = (T)axn;
+      po[t] = (T)pp;
+      apo[t] = (T)pap;
+      ro[t] = (T)rt;
       v[t] += rt * rt;
       v[M + t] += yi * rt;
     }
+    store_row<T, M>(X + i * M, xo);
+    store_row<T, M>(AX + i * M, axo);
+    if (!first) {
+      store_row<T, M>(P + i * M, po);
+      store_row<T, M>(AP + i * M, apo);
+    }
+    store_row<T, M>(W + i * M, ro);
   }
   block_sum<2 * M>(v, red);
   if (threadIdx.x == 0)
     for (int j = 0; j < 2 * M; ++j) a.vpart[(size_t)blockIdx.x * (2 * M) + j] = v[j];
-  if (!arrive_last(&st->counter, gridDim.x)) return;
-  double t[2 * M];
-  reduce_partials<2 * M>(a.vpart, gridDim.x, 2 * M, t, red);
-  if (threadIdx.x == 0) {
-    double mx = 0.0;
-    for (int j = 0; j < M; ++j) {
-      st->res[j] = sqrt(t[j]);
-      st->yx[j] = a.constraint ? t[M + j] : 0.0;
-      mx = st->res[j] > mx ? st->res[j] : mx;
-    }
-    if (!first) st->iters += 1;
-    if (st->tol > 0.0 && mx <= st->tol) st->active = 0;
-  }
 }
 
 // ---------------------------------------------------------------------------
@@ -699,11 +793,6 @@ __global__ void __launch_bounds__(kThreads) lob_out_dots_kernel(LobArgs a) {
   block_sum<M + 1>(v, red);
   if (threadIdx.x == 0)
     for (int j = 0; j <= M; ++j) a.vpart[(size_t)blockIdx.x * (M + 1) + j] = v[j];
-  if (!arrive_last(&st->counter, gridDim.x)) return;
-  double t[M + 1];
-  reduce_partials<M + 1>(a.vpart, gridDim.x, M + 1, t, red);
-  if (threadIdx.x == 0)
-    for (int j = 0; j <= M; ++j) st->yx[j] = t[j];  // reused: X^T z0 and Y^T z0
 }
 
 template <typename T, int M>
@@ -744,9 +833,23 @@ __global__ void __launch_bounds__(kThreads) lob_output_kernel(LobArgs a) {
 template <typename T, int M>
 void launch_m_kernels(int which, const LobArgs& a, int nb, int ns, int first, StartDegrees deg, hipStream_t s) {
   switch (which) {
-    case 0: lob_start_kernel<T, M><<<nb, kThreads, 0, s>>>(a, deg); break;
-    case 1: lob_update_kernel<T, M><<<nb, kThreads, 0, s>>>(a, ns, first); break;
-    case 2: lob_out_dots_kernel<T, M><<<nb, kThreads, 0, s>>>(a); break;
+    case 0:
+      lob_start_kernel<T, M><<<nb, kThreads, 0, s>>>(a, deg);
+      if (a.constraint) lob_final_kernel<M><<<1, kThreads, 0, s>>>(a.vpart, nb, a.st, 1, M, 0, 1);
+      break;
+    case 1:
+      if (ns == M)
+        lob_update_kernel<T, M, 1><<<nb, kThreads, 0, s>>>(a, first);
+      else if (ns == 2 * M)
+        lob_update_kernel<T, M, 2><<<nb, kThreads, 0, s>>>(a, first);
+      else
+        lob_update_kernel<T, M, 3><<<nb, kThreads, 0, s>>>(a, first);
+      lob_final_kernel<2 * M><<<1, kThreads, 0, s>>>(a.vpart, nb, a.st, 2, M, first, a.constraint);
+      break;
+    case 2:
+      lob_out_dots_kernel<T, M><<<nb, kThreads, 0, s>>>(a);
+      lob_final_kernel<M + 1><<<1, kThreads, 0, s>>>(a.vpart, nb, a.st, 3, M, 0, a.constraint);
+      break;
     default: lob_output_kernel<T, M><<<nb, kThreads, 0, s>>>(a); break;
   }
 }
@@ -772,6 +875,7 @@ gsf_status lob_launch_ynorm(const LobArgs& a, int nb, hipStream_t s) {
     lob_ynorm_kernel<float><<<nb, kThreads, 0, s>>>((const float*)a.sqd, a.n, a.vpart, a.st);
   else
     lob_ynorm_kernel<double><<<nb, kThreads, 0, s>>>((const double*)a.sqd, a.n, a.vpart, a.st);
+  lob_final_kernel<1><<<1, kThreads, 0, s>>>(a.vpart, nb, a.st, 0, a.m, 0, 0);
   return hipGetLastError() == hipSuccess ? GSF_OK : GSF_EDEVICE;
 }
 
@@ -792,18 +896,30 @@ gsf_status lob_launch_project(const LobArgs& a, void* B, int nb, hipStream_t s) 
   return hipGetLastError() == hipSuccess ? GSF_OK : GSF_EDEVICE;
 }
 
+// The Rayleigh-Ritz step runs on one workgroup of four waves.
+int rr_threads(int ns) { return kThreads; }
+
 int gram_tiles_total(int ns) {
   const int nt = (ns + 15) >> 4;
   return nt == 1 ? 2 : 7;
 }
 
 gsf_status lob_launch_gram(const GramArgs& g, const RRArgs& r, int prec, hipStream_t s) {
-  if (prec == GSF_F32)
-    gram_kernel<float><<<g.nparts, kThreads, 0, s>>>(g);
-  else
-    gram_kernel<double><<<g.nparts, kThreads, 0, s>>>(g);
+  const bool two = g.ns > 16;
+  if (prec == GSF_F32) {
+    if (two)
+      gram_kernel<float, 2><<<g.nparts, kThreads, 0, s>>>(g);
+    else
+      gram_kernel<float, 1><<<g.nparts, kThreads, 0, s>>>(g);
+  } else {
+    if (two)
+      gram_kernel<double, 2><<<g.nparts, kThreads, 0, s>>>(g);
+    else
+      gram_kernel<double, 1><<<g.nparts, kThreads, 0, s>>>(g);
+  }
   dim3 grid(gram_tiles_total(g.ns), kGramChunks);
-  gram_rr_kernel<<<grid, kThreads, 0, s>>>(g, r);
+  gram_reduce_kernel<<<grid, kThreads, 0, s>>>(g);
+  gram_rr_kernel<<<1, rr_threads(g.ns), 0, s>>>(g, r);
   return hipGetLastError() == hipSuccess ? GSF_OK : GSF_EDEVICE;
 }
 
@@ -825,7 +941,7 @@ __global__ void __launch_bounds__(kThreads) rr_only_kernel(const double* __restr
 }
 
 gsf_status lob_launch_rr_only(const double* G, int ns, int m, const RRArgs& r, hipStream_t s) {
-  rr_only_kernel<<<1, kThreads, 0, s>>>(G, ns, m, r);
+  rr_only_kernel<<<1, rr_threads(ns), 0, s>>>(G, ns, m, r);
   return hipGetLastError() == hipSuccess ? GSF_OK : GSF_EDEVICE;
 }
 

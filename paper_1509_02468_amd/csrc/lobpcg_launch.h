@@ -6,8 +6,9 @@
 
 namespace gsf {
 
-constexpr int kGramChunks = 8;   // second-level split of the Gram partial reduction
-constexpr int kGramBlocks = 256; // workgroups of the Gram kernel (at most)
+constexpr int kGramChunks = 16;     // first-stage split of the Gram partial reduction
+constexpr int kGramPerChunk = 64;   // partials per chunk (kGramBlocks / kGramChunks)
+constexpr int kGramBlocks = 1024; // workgroups of the Gram kernel (at most)
 
 struct LobArgs {
   int prec;

@@ -1,7 +1,9 @@
 // Vector kernels of the power iteration and of CG (Algorithm 2 in z-space),
 // with deterministic FP64 reductions: each workgroup writes one partial per
-// quantity, and the last workgroup to finish sums them in workgroup order and
-// updates the solver state.
+// quantity, and a one-workgroup kernel that follows on the stream sums them in
+// workgroup order and updates the solver state.  (Handing the partials over
+// inside one launch would need an agent-scope release fence per workgroup,
+// which writes back the whole L2 of its XCD.)
 #include <cmath>
 
 #include "gsf_internal.h"
@@ -36,9 +38,14 @@ __global__ void __launch_bounds__(kThreads) cg_init_kernel(const T* __restrict__
     partials[2 * blockIdx.x] = v[0];
     partials[2 * blockIdx.x + 1] = v[1];
   }
-  if (!arrive_last(&st->counter, gridDim.x)) return;
+}
+
+// one workgroup: rho0, breakdown floor and the tests before the first step
+__global__ void __launch_bounds__(kThreads) cg_init_final_kernel(const double* __restrict__ partials, int nparts,
+                                                                 CgState* st) {
+  __shared__ double red[32];
   double t[2];
-  reduce_partials<2>(partials, gridDim.x, 2, t, red);
+  reduce_partials<2>(partials, nparts, 2, t, red);
   if (threadIdx.x == 0) {
     const double rho = t[0];
     st->rho = rho;
@@ -131,9 +138,16 @@ __global__ void __launch_bounds__(kThreads) cg_update_kernel(T* __restrict__ z, 
     partials[2 * blockIdx.x] = v[0];
     partials[2 * blockIdx.x + 1] = v[1];
   }
-  if (!arrive_last(&st->counter, gridDim.x)) return;
+}
+
+// one workgroup: rho_new, beta = (rho_new - r_new.r_old) / rho_old, and the
+// tests that precede the next step
+__global__ void __launch_bounds__(kThreads) cg_beta_kernel(const double* __restrict__ partials, int nparts,
+                                                           CgState* st) {
+  __shared__ double red[32];
+  if (!st->active) return;
   double t[2];
-  reduce_partials<2>(partials, gridDim.x, 2, t, red);
+  reduce_partials<2>(partials, nparts, 2, t, red);
   if (threadIdx.x == 0) {
     const double rho_old = st->rho;
     const double rho = t[0];
@@ -176,6 +190,7 @@ gsf_status launch_cg_init(const Operator& op, const void* z, void* r, double* pa
     cg_init_kernel<float><<<nb, kThreads, 0, s>>>((const float*)z, (float*)r, op.n, partials, st);
   else
     cg_init_kernel<double><<<nb, kThreads, 0, s>>>((const double*)z, (double*)r, op.n, partials, st);
+  cg_init_final_kernel<<<1, kThreads, 0, s>>>(partials, nb, st);
   return hipGetLastError() == hipSuccess ? GSF_OK : GSF_EDEVICE;
 }
 
@@ -213,6 +228,7 @@ gsf_status launch_cg_update(const Operator& op, void* z, void* r, const void* p,
   else
     cg_update_kernel<double><<<nb, kThreads, 0, s>>>((double*)z, (double*)r, (const double*)p, (const double*)q,
                                                      op.n, partials, st);
+  cg_beta_kernel<<<1, kThreads, 0, s>>>(partials, nb, st);
   return hipGetLastError() == hipSuccess ? GSF_OK : GSF_EDEVICE;
 }
 

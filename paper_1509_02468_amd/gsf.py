@@ -83,6 +83,7 @@ def load_library(path: str = LIB_PATH):
         "gsf_block_gram_workspace_bytes": ([i64, P(sz)], i32),
         "gsf_rayleigh_ritz": ([i32, i32, vp, vp, dbl, dbl, vp, vp, vp, vp, vp, sz, vp], i32),
         "gsf_rr_workspace_bytes": ([], sz),
+        "gsf_tune_apply": ([vp, i32, vp, vp, i32, P(ctypes.c_int), P(ctypes.c_float), vp], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -203,6 +204,18 @@ class Operator:
         y = out if out is not None else torch.empty_like(x)
         _check(_lib.gsf_apply(self.handle, form, m, _ptr(x), _ptr(y), _stream(stream)), "apply")
         return y
+
+    def tune_apply(self, m=1, reps=20, stream=None):
+        """Pick the apply tile height for block width m (see gsf_tune_apply);
+        returns (rows per thread, [us per launch for 1, 2, 4])."""
+        torch = _torch()
+        x = torch.randn((self.n, m) if m > 1 else (self.n,), dtype=self.dtype, device="cuda")
+        y = torch.empty_like(x)
+        best = ctypes.c_int()
+        times = (ctypes.c_float * 3)()
+        _check(_lib.gsf_tune_apply(self.handle, m, _ptr(x), _ptr(y), reps, ctypes.byref(best), times,
+                                   _stream(stream)), "tune_apply")
+        return best.value, list(times)
 
     def workspace(self, method, m=1):
         torch = _torch()
