@@ -282,6 +282,19 @@ __global__ void __launch_bounds__(kThreads) gram_kernel(GramArgs g) {
 // ---------------------------------------------------------------------------
 // Rayleigh-Ritz on one workgroup (FP64)
 // ---------------------------------------------------------------------------
+// Reciprocal and reciprocal square root: the hardware approximations refined
+// by one Newton step (a few ulp), short dependency chains for the Jacobi
+// rotations.  The rotation stays orthogonal to rounding because c and s are
+// both derived from the same t: c = (1 + t^2)^-1/2, s = t c.
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+__device__ __forceinline__ double rsq_nr(double x) {
+  double r = __builtin_amdgcn_rsq(x);
+  const double e = fma(-x * r, r, 1.0);
+  return fma(0.5 * r, e, r);
+}
 constexpr int KMAX = 24;
 constexpr int LD = KMAX + 1;
 
@@ -314,7 +327,7 @@ struct RRShared {
 // Solves the Rayleigh-Ritz problem for GA, GB (ns x ns, already loaded into
 // sh.A and sh.B) and writes C (ns x m, row-major with leading dimension m),
 // theta and the kept flags.  All threads of the workgroup take part.
-__device__ void rayleigh_ritz(RRShared& sh, int ns, int m, double drop_tol, double zero_tol, double* Cout,
+__device__ __forceinline__ void rayleigh_ritz(RRShared& sh, int ns, int m, double drop_tol, double zero_tol, double* Cout,
                               double* theta, int* kept_out, int* nkept_out) {
   const int tid = threadIdx.x, nth = blockDim.x;
   // symmetrise
@@ -447,6 +460,15 @@ __device__ void rayleigh_ritz(RRShared& sh, int ns, int m, double drop_tol, doub
 
   // cyclic Jacobi with round-robin parallel ordering
   const int np = (K + 1) & ~1;  // players (a dummy when K is odd)
+  // this thread's matrix elements, fixed for the whole eigensolve
+  constexpr int EPT = (KMAX * KMAX + 63) / 64;  // enough for any launch of >= 64 threads
+  int ei[EPT], ej[EPT];
+#pragma unroll
+  for (int k = 0; k < EPT; ++k) {
+    const int e = tid + k * nth;
+    ei[k] = e < K * K ? e / K : -1;
+    ej[k] = e < K * K ? e - (e / K) * K : 0;
+  }
   double* Mc = sh.M;
   double* Mn = sh.M2;
   double* Vc = sh.V;
@@ -465,9 +487,10 @@ __device__ void rayleigh_ritz(RRShared& sh, int ns, int m, double drop_tol, doub
             // t = tan of the rotation angle, the root of t^2 + 2 theta t - 1 = 0
             // of smaller magnitude, theta = (a_qq - a_pp) / (2 a_pq)
             const double d = Mc[q * LD + q] - Mc[p * LD + p];
-            const double h = sqrt(d * d + 4.0 * apq * apq);
-            t = 2.0 * apq / (d >= 0.0 ? d + h : d - h);
-            c = rsqrt(1.0 + t * t);
+            const double y = fma(d, d, 4.0 * apq * apq);
+            const double h = y * rsq_nr(y);
+            t = 2.0 * apq * rcp_nr(d >= 0.0 ? d + h : d - h);
+            c = rsq_nr(fma(t, t, 1.0));
             s = t * c;
           }
         }
@@ -482,8 +505,10 @@ __device__ void rayleigh_ritz(RRShared& sh, int ns, int m, double drop_tol, doub
         if (q < K) sh.dnew[q] = Mc[q * LD + q] + t * apq;
       }
       __syncthreads();
-      for (int e = tid; e < K * K; e += nth) {
-        const int i = e / K, j = e - (e / K) * K;
+#pragma unroll
+      for (int k = 0; k < EPT; ++k) {
+        if (ei[k] < 0) continue;
+        const int i = ei[k], j = ej[k];
         const int pi = sh.partner[i], pj = sh.partner[j];
         const double ci = sh.jself[i], oi = sh.joff[i], cj = sh.jself[j], oj = sh.joff[j];
         double v;
