@@ -45,6 +45,7 @@ def _args():
     ap.add_argument("--roofline-reps", type=int, default=50)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--serial", action="store_true", help="run CG and LOBPCG one after the other")
+    ap.add_argument("--no-batch", action="store_true", help="skip the uneven-batch measurement")
     ap.add_argument("--kernels-only", action="store_true",
                     help="only the stencil applies (m = 1 and m) and a 1 GiB copy, for hardware counters")
     return ap.parse_args()
@@ -103,6 +104,76 @@ def cpu_baseline(w, noisy, budget_s):
             "sample": f"{crop.shape[0]}x{crop.shape[1]} crop of the workload image, BF {2*w['radius']+1}x"
                       f"{2*w['radius']+1} operator (build {t_build:.1f} s excluded), repeated CG({k_cg}) + "
                       f"LOBPCG(m={m}, {k_lob}) for {el:.1f} s, FP64, single thread"}
+
+
+def batch_bench(seed=4):
+    """Uneven batch (256 images with sides log-uniform in [64, 1024] and 64
+    signals with lengths log-uniform in [2^10, 2^20], per-item BF/GF
+    parameters, CG or LOBPCG(m=4), kmax 50, tol 1e-6): one graph launch of
+    the batch against a sequential loop of single-item calls (operator build +
+    solve per item, workspaces allocated beforehand, one stream)."""
+    import torch
+    import paper_1509_02468_amd as gsf
+    from synth import batch_items, item_signal
+    recipe = batch_items(seed=seed)
+    items = []
+    for it in recipe:
+        _, noisy = item_signal(it)
+        g = torch.tensor(noisy.ravel(), dtype=torch.float32, device="cuda")
+        items.append(dict(kind=it["kind"], shape=it["shape"], radius=it["radius"], sigma_d=it["sigma_d"],
+                          sigma_r=it["sigma_r"], eps=it["eps"], guidance=g, x0=g, method=it["method"], m=it["m"],
+                          kmax=it["kmax"], tol=it["tol"]))
+    npix = sum(int(np.prod(it["shape"])) for it in items)
+    batch = gsf.Batch(items, prec=gsf.F32, autotune=True)
+    batch_g = gsf.Batch(items, prec=gsf.F32, autotune=False, graphs=True)
+    # sequential baseline: preallocated workspaces, one stream, no host syncs
+    ops_ws, solver_ws, outs = [], [], []
+    for it in items:
+        op = gsf.Operator(it["kind"], it["shape"], it["guidance"], it["radius"], it["sigma_d"], it["sigma_r"],
+                          it["eps"], gsf.F32)
+        ops_ws.append(op.ws)
+        solver_ws.append(op.workspace(gsf.METHOD_CG if it["method"] == "cg" else gsf.METHOD_LOBPCG, it["m"]))
+        outs.append(torch.empty_like(it["x0"]))
+
+    def sequential():
+        keep = []
+        for k, it in enumerate(items):
+            op = gsf.Operator(it["kind"], it["shape"], it["guidance"], it["radius"], it["sigma_d"], it["sigma_r"],
+                              it["eps"], gsf.F32, ws=ops_ws[k])
+            if it["method"] == "cg":
+                op.cg_filter(it["x0"], it["kmax"], tol=it["tol"], out=outs[k], ws=solver_ws[k], info=False)
+            else:
+                op.lobpcg_filter(it["x0"], it["m"], it["kmax"], tol=it["tol"], out=outs[k], ws=solver_ws[k],
+                                 info=False)
+            keep.append(op)
+        return keep
+
+    def timed(fn, reps):
+        ts = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+            del r
+        return float(np.median(ts))
+
+    sequential()
+    t_seq = timed(sequential, 3)
+    batch.run()
+    t_graph = timed(batch.run, 5)
+    batch_g.run()
+    t_graphs = timed(batch_g.run, 3)
+    info = batch.info()
+    same = all(torch.equal(outs[k], it["out"]) for k, it in enumerate(items))
+    applies = sum(int(np.prod(it["shape"])) * (it["m"] if it["method"] == "lobpcg" else 1) * (info[k][0] + 1)
+                  for k, it in enumerate(items))
+    return {"workload": "batch_256img_64sig", "items": len(items), "points": npix,
+            "sequential_ms": round(t_seq * 1e3, 2), "batched_ms": round(t_graph * 1e3, 2),
+            "branch_graphs_ms": round(t_graphs * 1e3, 2),
+            "speedup": round(t_seq / t_graph, 3), "Mpixel_iters_per_s": round(applies / t_graph / 1e6, 1),
+            "items_converged": int(sum(1 for i in info if i[1] == 0)), "outputs_equal_sequential": bool(same)}
 
 
 def main():
@@ -216,6 +287,7 @@ def main():
                 "algorithmic_bytes_per_launch": algo,
                 "m1_us": round(rl[1][1] * 1e3, 2), f"m{m}_us": round(rl[m][1] * 1e3, 2)}
 
+    batch = None if a.no_batch else batch_bench()
     cpu = None if a.no_cpu else cpu_baseline(w, noisy, a.cpu_seconds)
     out = {"metric": "Mpixel-iters/s of Laplacian apply", "value": round(value, 1), "unit": "Mpixel-iters/s",
            "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(ms, 3),
@@ -224,7 +296,7 @@ def main():
            "config": {"workload": a.workload, "shape": list(shape), "operator": f"{w['kind']} r={w['radius']}",
                       "cg_iters": kcg, "lobpcg_iters": klob, "lobpcg_m": m, "parallelism": "single-gpu",
                       "apply_tuning": tuned, "cg_lobpcg_streams": 2 if concurrent else 1},
-           "roofline": roofline, "cpu_baseline": cpu}
+           "roofline": roofline, "cpu_baseline": cpu, "batch": batch}
     print(json.dumps(out), flush=True)
 
 

@@ -215,6 +215,62 @@ gsf_status gsf_lobpcg_filter(const gsf_operator* op, const void* x0, void* x_out
 gsf_status gsf_tune_apply(const gsf_operator* op, int m, const void* x, void* y, int reps,
                           int* best_rpt, float* times_us, void* stream);
 
+/* ---- batching ----------------------------------------------------------------
+ * Many independent items (each its own operator, signal and solver) filtered
+ * by one call: the items are spread over 8 branches (longest first), each
+ * branch is a HIP graph of its items' operator builds and solves, and a run
+ * launches the branch graphs on private streams forked from and joined back
+ * to the caller's stream, so branches run side by side.  Every item computes exactly what the
+ * single-item calls above compute (same kernels, same order within the
+ * item); converged items (tol > 0) turn their remaining kernels into no-ops
+ * through their own device-side solver state.
+ *  gsf_batch_item: op (all items of a batch share op.prec), device pointers
+ *    guidance, x0 (n values) and x_out (n values), method (GSF_METHOD_*), m
+ *    (LOBPCG block size 1..8), kmax, constraint (LOBPCG), tol (CG, LOBPCG).
+ *  gsf_batch_workspace_bytes: device workspace for the whole batch.
+ *  gsf_batch_create: carves the workspace and assigns items to branches;
+ *    flags: GSF_BATCH_AUTOTUNE times the BF apply tile per item class (see
+ *    gsf_tune_apply; scratch is the item's solver workspace);
+ *    GSF_BATCH_GRAPHS records each branch once as a HIP graph (the item
+ *    pointers are then baked in: buffers must stay at the same addresses
+ *    while the batch exists; their contents may change between runs).
+ *    Without GSF_BATCH_GRAPHS each run issues the items' kernels from the
+ *    library onto the branch streams (measured faster on ROCm 7.2, whose
+ *    graph launch costs more host time per kernel node than a launch).
+ *  gsf_batch_run: runs the batch ordered after prior work on `stream`;
+ *    later work on `stream` waits for every branch (asynchronous).
+ *  gsf_batch_get_info: per item (host array of count), after synchronizing
+ *    the stream: completed steps, status (as the single-item calls report it),
+ *    initial and final residual (CG: ||r||; LOBPCG: largest column residual).
+ *  gsf_batch_destroy: frees the host plan and the graph. */
+typedef struct {
+  gsf_operator_desc op;
+  const void* guidance;
+  const void* x0;
+  void* x_out;
+  int32_t method;
+  int32_t m;
+  int32_t kmax;
+  int32_t constraint;
+  double tol;
+} gsf_batch_item;
+
+typedef struct {
+  int32_t iters;
+  int32_t status;
+  double res0;
+  double res;
+} gsf_batch_info;
+
+typedef struct gsf_batch gsf_batch;
+enum { GSF_BATCH_AUTOTUNE = 1, GSF_BATCH_GRAPHS = 2 };
+gsf_status gsf_batch_workspace_bytes(const gsf_batch_item* items, int count, size_t* bytes);
+gsf_status gsf_batch_create(const gsf_batch_item* items, int count, void* ws, size_t ws_bytes, int flags,
+                            gsf_batch** out);
+gsf_status gsf_batch_run(gsf_batch* batch, void* stream);
+gsf_status gsf_batch_get_info(const gsf_batch* batch, gsf_batch_info* info, void* stream);
+void gsf_batch_destroy(gsf_batch* batch);
+
 /* ---- diagnostic entry points (the solver's inner kernels on caller data) ----
  * gsf_block_gram: the Gram pair of the LOBPCG Rayleigh-Ritz step (Algorithm 3,
  *   the Rayleigh-Ritz line): GA = S^T (A S), GB = S^T S for S = [S0 .. S_{nb-1}]

@@ -226,6 +226,36 @@ gsf_status hip_ok(hipError_t e) { return e == hipSuccess ? GSF_OK : GSF_EDEVICE;
 
 }  // namespace
 
+// Host description of an operator without device memory (pointers null):
+// used to size workspaces before anything is built.
+gsf_status describe_operator(const gsf_operator_desc* d, Operator* out) {
+  GSF_TRY(validate_desc(d));
+  layout_operator(d, out, nullptr);
+  return GSF_OK;
+}
+
+size_t solver_bytes(const Operator& op, int method, int m) {
+  if (method == GSF_METHOD_POWER) return 2 * align_up((size_t)op.n * op.elem, 256);
+  if (method == GSF_METHOD_CG) {
+    CgWs w;
+    return carve_cg(op, nullptr, &w);
+  }
+  LobWs w;
+  return carve_lob(op, m, nullptr, &w);
+}
+
+CgState* cg_state_ptr(const Operator& op, void* ws) {
+  CgWs w;
+  carve_cg(op, (char*)ws, &w);
+  return w.st;
+}
+
+LobpcgState* lob_state_ptr(const Operator& op, int m, void* ws) {
+  LobWs w;
+  carve_lob(op, m, (char*)ws, &w);
+  return w.st;
+}
+
 gsf_status launch_lob_state_init(LobpcgState* dst, const LobpcgState& v, hipStream_t s) {
   lob_state_init_kernel<<<1, 1, 0, s>>>(dst, v);
   return hip_ok(hipGetLastError());

@@ -48,6 +48,17 @@ class LobpcgInfo(ctypes.Structure):
                 ("m", ctypes.c_int32), ("res", ctypes.c_double * 8), ("theta", ctypes.c_double * 8)]
 
 
+class BatchItem(ctypes.Structure):
+    _fields_ = [("op", OperatorDesc), ("guidance", ctypes.c_void_p), ("x0", ctypes.c_void_p),
+                ("x_out", ctypes.c_void_p), ("method", ctypes.c_int32), ("m", ctypes.c_int32),
+                ("kmax", ctypes.c_int32), ("constraint", ctypes.c_int32), ("tol", ctypes.c_double)]
+
+
+class BatchInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("status", ctypes.c_int32), ("res0", ctypes.c_double),
+                ("res", ctypes.c_double)]
+
+
 _lib = None
 
 
@@ -84,6 +95,11 @@ def load_library(path: str = LIB_PATH):
         "gsf_rayleigh_ritz": ([i32, i32, vp, vp, dbl, dbl, vp, vp, vp, vp, vp, sz, vp], i32),
         "gsf_rr_workspace_bytes": ([], sz),
         "gsf_tune_apply": ([vp, i32, vp, vp, i32, P(ctypes.c_int), P(ctypes.c_float), vp], i32),
+        "gsf_batch_workspace_bytes": ([P(BatchItem), i32, P(sz)], i32),
+        "gsf_batch_create": ([P(BatchItem), i32, vp, sz, i32, P(vp)], i32),
+        "gsf_batch_run": ([vp, vp], i32),
+        "gsf_batch_get_info": ([vp, P(BatchInfo), vp], i32),
+        "gsf_batch_destroy": ([vp], None),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -119,12 +135,76 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def make_desc(kind, shape, radius, sigma_d=0.0, sigma_r=0.0, eps=0.0, prec=F32):
+    d = OperatorDesc()
+    d.kind = BF if kind in ("bf", BF) else GF
+    d.ndim = len(shape)
+    d.dims[0] = shape[0]
+    d.dims[1] = shape[1] if len(shape) == 2 else 1
+    d.prec = prec
+    d.radius = radius
+    d.sigma_d = sigma_d
+    d.sigma_r = sigma_r
+    d.gf_eps = eps
+    return d
+
+
+class Batch:
+    """Many items filtered by one graph launch (gsf_batch_*).  Each item is a
+    dict with kind, shape, radius, sigma_d, sigma_r, eps, guidance, x0 (device
+    tensors of the batch dtype), method ("power", "cg", "lobpcg"), m, kmax,
+    tol, constraint; outputs are allocated here (item["out"])."""
+
+    METHODS = {"power": METHOD_POWER, "cg": METHOD_CG, "lobpcg": METHOD_LOBPCG}
+
+    def __init__(self, items, prec=F32, autotune=True, graphs=False):
+        torch = _torch()
+        lib = load_library()
+        self.items = items
+        self.arr = (BatchItem * len(items))()
+        for k, it in enumerate(items):
+            it.setdefault("out", torch.empty_like(it["x0"]))
+            b = self.arr[k]
+            b.op = make_desc(it["kind"], it["shape"], it["radius"], it.get("sigma_d", 0.0), it.get("sigma_r", 0.0),
+                             it.get("eps", 0.0), prec)
+            b.guidance = it["guidance"].data_ptr()
+            b.x0 = it["x0"].data_ptr()
+            b.x_out = it["out"].data_ptr()
+            b.method = self.METHODS[it["method"]]
+            b.m = it.get("m", 1)
+            b.kmax = it["kmax"]
+            b.constraint = int(bool(it.get("constraint", False)))
+            b.tol = it.get("tol", 0.0)
+        nbytes = ctypes.c_size_t()
+        _check(lib.gsf_batch_workspace_bytes(self.arr, len(items), ctypes.byref(nbytes)), "batch_workspace_bytes")
+        self.ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device="cuda")
+        torch.cuda.synchronize()
+        h = ctypes.c_void_p()
+        flags = (1 if autotune else 0) | (2 if graphs else 0)
+        _check(lib.gsf_batch_create(self.arr, len(items), _ptr(self.ws), nbytes.value, flags, ctypes.byref(h)),
+               "batch_create")
+        self.handle = h
+
+    def run(self, stream=None):
+        _check(_lib.gsf_batch_run(self.handle, _stream(stream)), "batch_run")
+
+    def info(self, stream=None):
+        out = (BatchInfo * len(self.items))()
+        _check(_lib.gsf_batch_get_info(self.handle, out, _stream(stream)), "batch_get_info")
+        return [(o.iters, o.status, o.res0, o.res) for o in out]
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.gsf_batch_destroy(self.handle)
+            self.handle = None
+
+
 class Operator:
     """A built graph operator (BF eq. (2) or GF Algorithm 1) on the GPU.
     Owns its device workspace (a torch uint8 tensor)."""
 
     def __init__(self, kind, shape, guidance, radius, sigma_d=0.0, sigma_r=0.0, eps=0.0, prec=F32,
-                 stream=None):
+                 stream=None, ws=None):
         torch = _torch()
         lib = load_library()
         shape = tuple(int(s) for s in shape)
@@ -143,7 +223,10 @@ class Operator:
         self.desc = d
         nbytes = ctypes.c_size_t()
         _check(lib.gsf_operator_workspace_bytes(ctypes.byref(d), ctypes.byref(nbytes)), "operator_workspace_bytes")
-        self.ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device="cuda")
+        if ws is not None and ws.numel() >= nbytes.value:
+            self.ws = ws
+        else:
+            self.ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device="cuda")
         g = guidance
         if not isinstance(g, torch.Tensor):
             g = torch.as_tensor(np.ascontiguousarray(g))
