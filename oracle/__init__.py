@@ -18,8 +18,8 @@ Contents (each function cites the passage it follows):
              Section 6).
   spectral   dense spectral factorization eq. (8) and GFT low-pass filters.
   quality    PSNR.
-  convnet    FP64 reference of the small convolutional preconditioner with
-             optional BF16 rounding emulation.
+  convnet    FP64 reference of the learned convolutional preconditioner
+             (forward, backward, Adam) with BF16 rounding emulation.
 
 Readings where the paper is silent or ambiguous are stated at each function.
 """
@@ -27,7 +27,9 @@ from .graph import window_offsets, bf_weight_matrix, degrees
 from .guided import box_sum, box_count, f_mean, guided_filter, gf_stats, gf_weight_matrix_dense, gf_degrees
 from .operator import GraphOperator, build_operator
 from .solvers import (power_filter, cg_filter, cg_filter_normalized, modulated_start, modulation_degrees,
-                      rayleigh_ritz, lobpcg_filter, CgInfo, LobpcgInfo)
+                      rayleigh_ritz, lobpcg_filter, CgInfo, LobpcgInfo, precondition, lobpcg_residual,
+                      shifted_cg, ShiftedCgInfo)
+from . import convnet
 from .quality import psnr
 
 __all__ = [
@@ -35,5 +37,6 @@ __all__ = [
     "box_sum", "box_count", "f_mean", "guided_filter", "gf_stats", "gf_weight_matrix_dense", "gf_degrees",
     "GraphOperator", "build_operator",
     "power_filter", "cg_filter", "cg_filter_normalized", "modulated_start", "modulation_degrees", "rayleigh_ritz",
-    "lobpcg_filter", "CgInfo", "LobpcgInfo", "psnr",
+    "lobpcg_filter", "CgInfo", "LobpcgInfo", "psnr", "precondition", "lobpcg_residual", "shifted_cg",
+    "ShiftedCgInfo", "convnet",
 ]

@@ -281,9 +281,26 @@ def rayleigh_ritz(GA, GB, m: int, drop_tol: float, zero_tol: float = 0.0):
     return theta[:m], C, kept
 
 
+def precondition(T, R):
+    """W = T(R) column by column with the fallback rule of the learned
+    preconditioner (our reading): a column whose output has a non-finite
+    entry or for which r^T T(r) <= 0 (T(r) not a descent direction of the
+    Rayleigh quotient) uses T = I instead."""
+    W = np.asarray(T(R), dtype=np.float64)
+    out = R.copy()
+    for j in range(R.shape[1]):
+        w = W[:, j]
+        if np.all(np.isfinite(w)) and float(R[:, j] @ w) > 0.0:
+            out[:, j] = w
+    return out
+
+
 def lobpcg_filter(op, x0, m: int, kmax: int, tol: float = 0.0, constraint: bool = False,
-                  data_prec: str = "f64", X0=None):
+                  data_prec: str = "f64", X0=None, precond=None):
     """Block LOBPCG low-pass filter (see module docstring).
+    precond: None (T = I) or a callable R (n, m) -> T(R) used with the
+    fallback rule of `precondition` (flexible LOBPCG: T may change or be
+    non-linear; the Rayleigh-Ritz step over [X, W, P] needs no other change).
     Returns (x_out, theta, X, info); X columns have sign x_j^T z0 >= 0."""
     drop_tol = DROP_TOL[data_prec]
     x0 = np.asarray(x0, dtype=np.float64).ravel()
@@ -313,7 +330,7 @@ def lobpcg_filter(op, x0, m: int, kmax: int, tol: float = 0.0, constraint: bool 
         res = np.linalg.norm(R, axis=0)
         if tol > 0.0 and np.max(res) <= tol:
             break
-        W = R
+        W = R if precond is None else precondition(precond, R)
         if constraint:
             W = W - np.outer(Y, Y @ W)
         AW = A(W)
@@ -339,3 +356,51 @@ def lobpcg_filter(op, x0, m: int, kmax: int, tol: float = 0.0, constraint: bool 
         y = y + Y * (Y @ z0)
     signs = np.where(X.T @ z0 >= 0.0, 1.0, -1.0)
     return y / op.sqrt_d, theta, X * signs[None, :], info
+
+
+def lobpcg_residual(op, X, theta):
+    """Residual block R = L_sym X - X diag(theta) of given Ritz pairs
+    (Algorithm 3, residual line, in z-space)."""
+    X = np.asarray(X, dtype=np.float64)
+    return op.apply_lsym(X) - X * np.asarray(theta, dtype=np.float64)[None, :]
+
+
+@dataclass
+class ShiftedCgInfo:
+    iters: int = 0
+    status: str = "ok"
+    res: float = 0.0
+
+
+def shifted_cg(op, alpha: float, b, kmax: int, tol: float):
+    """Plain CG for (L_sym + alpha I) y = b from y = 0 (the training targets
+    of the learned preconditioner; the same recurrences as Algorithm 2 with
+    T = I on an SPD matrix).  Stops when ||b - (L_sym + alpha I) y|| <=
+    tol ||b|| (recursive residual) or after kmax steps; p^T q <= 0 is a
+    breakdown.  Returns (y, info)."""
+    b = np.asarray(b, dtype=np.float64).ravel()
+    y = np.zeros_like(b)
+    r = b.copy()
+    p = r.copy()
+    rho = float(r @ r)
+    bn = np.sqrt(rho)
+    info = ShiftedCgInfo()
+    for k in range(kmax):
+        if np.sqrt(rho) <= tol * bn:
+            break
+        q = op.apply_lsym(p) + alpha * p
+        pq = float(p @ q)
+        if not (pq > 0.0):
+            info.status = "breakdown"
+            break
+        a = rho / pq
+        y = y + a * p
+        r = r - a * q
+        rho_new = float(r @ r)
+        p = r + (rho_new / rho) * p
+        rho = rho_new
+        info.iters = k + 1
+    info.res = float(np.sqrt(rho))
+    if info.status == "ok" and np.sqrt(rho) > tol * bn:
+        info.status = "notconv"
+    return y, info

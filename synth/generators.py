@@ -19,7 +19,7 @@ from __future__ import annotations
 
 import numpy as np
 
-__all__ = ["piecewise_constant_1d", "scene_2d", "batch_items", "lobpcg_gaussian_block"]
+__all__ = ["piecewise_constant_1d", "scene_2d", "batch_items", "lobpcg_gaussian_block", "convnet_init"]
 
 
 def piecewise_constant_1d(n: int, sigma: float, seed, n_breaks: int = 8):
@@ -129,3 +129,16 @@ def item_signal(item):
     if len(item["shape"]) == 1:
         return piecewise_constant_1d(item["shape"][0], item["sigma"], item["seed"])
     return scene_2d(item["shape"][0], item["shape"][1], item["sigma"], item["seed"])
+
+
+def convnet_init(seed, hidden: int = 16, inputs: int = 2):
+    """Seeded initial weights of the 3-layer 3x3 convolutional network, flat
+    in layer order (layer1 hidden x inputs x 3 x 3, layer2 hidden x hidden x
+    3 x 3, layer3 hidden x 3 x 3).  He-normal scale sqrt(2 / fan_in) for the
+    two ReLU layers, sqrt(1 / fan_in) for the linear output layer; float32."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for shape, gain in (((hidden, inputs, 3, 3), 2.0), ((hidden, hidden, 3, 3), 2.0), ((1, hidden, 3, 3), 1.0)):
+        fan_in = shape[1] * 9
+        parts.append(rng.standard_normal(shape).ravel() * np.sqrt(gain / fan_in))
+    return np.concatenate(parts).astype(np.float32)
