@@ -129,6 +129,8 @@ typedef struct {
   int32_t m;
   double res[8];      /* ||L_sym x_j - theta_j x_j||, unit x_j (z-space), per column */
   double theta[8];    /* Ritz values, ascending */
+  int32_t fallbacks;  /* learned T: column-steps that fell back to T = I */
+  int32_t pad;
 } gsf_lobpcg_info;
 
 /* ---- version / errors ------------------------------------------------- */
@@ -196,12 +198,93 @@ gsf_status gsf_cg_filter(const gsf_operator* op, const void* x0, void* x_out, in
  * ritz_vecs (NULL or n*m, z-space, column signs with x_j^T z0 >= 0).
  * tol > 0 stops when every column residual <= tol (GSF_ENOTCONV if not met).
  * A start block of rank < m returns x0 with GSF_EBREAKDOWN.
- * T must be NULL (plain method) or a learned preconditioner handle. */
+ * T: NULL (plain method) or a learned preconditioner (gsf_precond_create)
+ *   built for this operator's grid and precision; then W = T(R) column by
+ *   column (flexible LOBPCG: the Rayleigh-Ritz step on [X, W, P] is
+ *   unchanged), with T = I for a column whose T(r) has a non-finite entry or
+ *   r^T T(r) <= 0 (counted in info->fallbacks). */
 typedef struct gsf_precond gsf_precond;
 gsf_status gsf_lobpcg_filter(const gsf_operator* op, const void* x0, void* x_out, int m,
                              int kmax, double tol, int constraint, const gsf_precond* T,
                              void* ritz_vecs, void* ws, size_t ws_bytes, gsf_lobpcg_info* info,
                              void* stream);
+
+/* ---- learned preconditioner (the preconditioner T of Algorithm 3) ----------
+ * Network: conv3x3 (2 -> 16 channels) + ReLU, conv3x3 (16 -> 16) + ReLU,
+ * conv3x3 (16 -> 1); cross-correlation with zero padding, no biases.  Input
+ * channels (r / s, g): the residual column scaled by s = RMS(r) = ||r|| /
+ * sqrt(n) and the guidance image; T(r) = s * net.  Weights, input and the two
+ * hidden activations are BF16 (round to nearest even), accumulation FP32.
+ * Weight vector (GSF_NET_WEIGHTS values): W1[o][c][ky][kx] (16x2x3x3), then
+ * W2[o][c][ky][kx] (16x16x3x3), then W3[c][ky][kx] (16x3x3).  BF16 weights are
+ * passed as uint16 bit patterns.  All arrays are device memory owned by the
+ * caller; every call is asynchronous on `stream`.
+ *
+ * Training set: sample s occupies inputs[(s*rows*cols + p)*2 + {0, 1}] =
+ * (r/s, g) and targets[s*rows*cols + p] = t / s (FP32, row-major pixels p),
+ * with t = (L_sym + alpha I)^-1 r (gsf_shifted_cg) and s = RMS(r)
+ * (gsf_net_make_pair writes both).
+ *  gsf_net_workspace_bytes: scratch of gsf_net_forward / gsf_net_loss_grad
+ *    for a batch of `batch` samples.
+ *  gsf_net_forward: y[b*rows*cols + p] = net(inputs of sample idx[b]).
+ *  gsf_net_loss_grad: loss = mean over the batch's pixels of
+ *    (net - target)^2 (one double in device memory) and its gradient with
+ *    respect to the weights (GSF_NET_WEIGHTS floats, the BF16 weights taken
+ *    as the variables); deterministic (fixed-order FP64 reductions).
+ *  gsf_net_adam: one Adam step t >= 1 (bias-corrected, Kingma and Ba) on the
+ *    FP32 master weights w with moments mom, vel; writes the BF16 copy w_bf16.
+ *  gsf_net_to_bf16: w_bf16 = round(w).
+ *  gsf_net_pair_workspace_bytes / gsf_net_make_pair: one training pair from a
+ *    residual r (stride ldr), its target y (stride ldy) and the guidance g
+ *    (op's element type, n values each) into inputs (2n floats) and targets
+ *    (n floats).
+ * Errors: GSF_EINVAL for null pointers, batch < 1, non-positive sizes,
+ * t < 1; GSF_ENOMEM for a short workspace. */
+#define GSF_NET_WEIGHTS 2736
+gsf_status gsf_net_workspace_bytes(int batch, int64_t rows, int64_t cols, size_t* bytes);
+gsf_status gsf_net_forward(const uint16_t* w_bf16, int batch, const int32_t* idx, int64_t rows,
+                           int64_t cols, const float* inputs, float* y, void* ws, size_t ws_bytes,
+                           void* stream);
+gsf_status gsf_net_loss_grad(const uint16_t* w_bf16, int batch, const int32_t* idx, int64_t rows,
+                             int64_t cols, const float* inputs, const float* targets, float* grad,
+                             double* loss, void* ws, size_t ws_bytes, void* stream);
+gsf_status gsf_net_adam(int64_t count, int t, double lr, double beta1, double beta2, double eps,
+                        float* w, float* mom, float* vel, const float* grad, uint16_t* w_bf16,
+                        void* stream);
+gsf_status gsf_net_to_bf16(int64_t count, const float* w, uint16_t* w_bf16, void* stream);
+gsf_status gsf_net_pair_workspace_bytes(const gsf_operator* op, size_t* bytes);
+gsf_status gsf_net_make_pair(const gsf_operator* op, const void* r, int64_t ldr, const void* y,
+                             int64_t ldy, const void* g, float* inputs, float* targets, void* ws,
+                             size_t ws_bytes, void* stream);
+
+/* Preconditioner handle for gsf_lobpcg_filter: the operator's grid
+ * (rows x cols; a 1D operator is one row), guidance g (n values of the
+ * operator's element type) and BF16 weights, all borrowed (they must outlive
+ * the handle; their contents are read at each use).
+ *  gsf_precond_apply: W = T(R) column by column for an n x m point-major
+ *    block (no fallback), scratch from gsf_precond_workspace_bytes.
+ * Errors: GSF_EINVAL for null pointers or m outside 1..8. */
+gsf_status gsf_precond_create(const gsf_operator* op, const void* g, const uint16_t* w_bf16,
+                              gsf_precond** out);
+void gsf_precond_destroy(gsf_precond* T);
+gsf_status gsf_precond_workspace_bytes(const gsf_precond* T, int m, size_t* bytes);
+gsf_status gsf_precond_apply(const gsf_precond* T, int m, const void* R, void* W, void* ws,
+                             size_t ws_bytes, void* stream);
+
+/* Training targets and residuals.
+ *  gsf_shifted_cg: CG for (L_sym + alpha I) y = b from y = 0 (alpha >= 0;
+ *    b with stride ldb, y contiguous, n values of the operator's element
+ *    type), the recurrences of Algorithm 2 with T = I; stops when
+ *    ||r|| <= tol ||b|| or after kmax steps (GSF_ENOTCONV if tol > 0 is not
+ *    met); p^T q <= 0 is GSF_EBREAKDOWN.  Workspace: gsf_solver_workspace_bytes
+ *    (op, GSF_METHOD_CG, 1, ...).  info may be NULL (then no host sync).
+ *  gsf_lobpcg_residual: R = L_sym X - X diag(theta) for an n x m point-major
+ *    block (theta: m host doubles). */
+gsf_status gsf_shifted_cg(const gsf_operator* op, double alpha, const void* b, int64_t ldb, void* y,
+                          int kmax, double tol, void* ws, size_t ws_bytes, gsf_cg_info* info,
+                          void* stream);
+gsf_status gsf_lobpcg_residual(const gsf_operator* op, int m, const void* X, const double* theta,
+                               void* R, void* stream);
 
 /* ---- tuning ---------------------------------------------------------------
  * gsf_tune_apply: times the BF apply (form L_sym, block width m in

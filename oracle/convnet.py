@@ -27,7 +27,8 @@ Training target: y* = (L_sym + alpha I)^-1 r with alpha = 1e-2 (the shifted
 solve `shifted_cg`), loss = mean over samples and pixels of (y - y*/s)^2.
 Gradients flow through the rounded weights unchanged (the master copy is the
 FP32 weight vector that Adam updates).  ReLU derivative: 1 where the stored
-activation is > 0.
+activation is > 0.  relu(NaN) = NaN, so a NaN inside the network reaches the
+output (and triggers the T = I fallback of the solver).
 
 Adam (Kingma and Ba 2015): m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
 w -= lr * (m / (1-b1^t)) / (sqrt(v / (1-b2^t)) + eps).

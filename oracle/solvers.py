@@ -374,10 +374,10 @@ class ShiftedCgInfo:
 
 def shifted_cg(op, alpha: float, b, kmax: int, tol: float):
     """Plain CG for (L_sym + alpha I) y = b from y = 0 (the training targets
-    of the learned preconditioner; the same recurrences as Algorithm 2 with
-    T = I on an SPD matrix).  Stops when ||b - (L_sym + alpha I) y|| <=
-    tol ||b|| (recursive residual) or after kmax steps; p^T q <= 0 is a
-    breakdown.  Returns (y, info)."""
+    of the learned preconditioner; the recurrences of Algorithm 2 with T = I
+    on an SPD matrix, including its beta numerator r^T (r - r_old)).  Stops
+    when ||b - (L_sym + alpha I) y|| <= tol ||b|| (recursive residual) or
+    after kmax steps; p^T q <= 0 is a breakdown.  Returns (y, info)."""
     b = np.asarray(b, dtype=np.float64).ravel()
     y = np.zeros_like(b)
     r = b.copy()
@@ -395,9 +395,10 @@ def shifted_cg(op, alpha: float, b, kmax: int, tol: float):
             break
         a = rho / pq
         y = y + a * p
+        r_old = r
         r = r - a * q
         rho_new = float(r @ r)
-        p = r + (rho_new / rho) * p
+        p = r + (float(r @ (r - r_old)) / rho) * p
         rho = rho_new
         info.iters = k + 1
     info.res = float(np.sqrt(rho))

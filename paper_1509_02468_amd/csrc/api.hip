@@ -29,6 +29,30 @@ gsf_status launch_cg_alpha(const double* partials, int nparts, CgState* st, hipS
 gsf_status launch_cg_update(const Operator& op, void* z, void* r, const void* p, const void* q, double* partials,
                             CgState* st, hipStream_t s);
 
+// learned preconditioner (net.hip)
+size_t net_train_bytes(int batch, int64_t hw);
+gsf_status net_forward_train(const uint16_t* w, int batch, const int32_t* idx, int64_t rows, int64_t cols,
+                             const float* inputs, const float* targets, float* y_out, float* grad, double* loss,
+                             void* ws, hipStream_t s);
+gsf_status net_adam(int64_t count, int t, double lr, double b1, double b2, double eps, float* w, float* mom,
+                    float* vel, const float* grad, uint16_t* wb, hipStream_t s);
+gsf_status net_to_bf16(int64_t count, const float* w, uint16_t* wb, hipStream_t s);
+int net_tiles(int64_t rows, int64_t cols);
+gsf_status net_infer(int prec, const uint16_t* w, int64_t rows, int64_t cols, int m, const void* R, void* Z,
+                     const void* g, const void* sqd, const double* colnorm, const LobpcgState* st, double* partials,
+                     hipStream_t s);
+gsf_status net_lob_select(int prec, int64_t rows, int64_t cols, int m, int constraint, void* W, const void* Z,
+                          const void* sqd, const double* partials, LobpcgState* st, hipStream_t s);
+gsf_status launch_colnorm(int prec, const void* R, int64_t n, int m, int64_t ld, double* partials, double* out,
+                          hipStream_t s);
+gsf_status launch_net_pair(int prec, const void* r, int64_t ldr, const void* y, int64_t ldy, const void* g,
+                           int64_t n, const double* norm, float* in, float* tg, hipStream_t s);
+gsf_status launch_residual(int prec, const void* X, void* R, int64_t n, int m, const double* theta, hipStream_t s);
+gsf_status launch_scg_init(int prec, const void* b, int64_t ldb, void* y, void* r, int64_t n, double* partials,
+                           CgState* st, hipStream_t s);
+gsf_status launch_scg_shift(int prec, const void* p, void* q, int64_t n, double shift, double* partials, int* nparts,
+                            const CgState* st, hipStream_t s);
+
 namespace {
 
 constexpr size_t kAlign = 256;
@@ -163,6 +187,8 @@ size_t carve_cg(const Operator& op, char* base, CgWs* w) {
 
 struct LobWs {
   void *X, *W, *P, *AX, *AW, *AP;
+  void* Z;               // learned preconditioner output T(R)
+  double* net_partials;  // per-tile partials of the preconditioner
   double* gram_partials;
   double* gram_level2;
   double* C;
@@ -195,6 +221,8 @@ size_t carve_lob(const Operator& op, int m, char* base, LobWs* w) {
   w->vpart = (double*)c.take((size_t)vec_blocks(op.n) * 17 * sizeof(double));
   w->gram_counter = (unsigned int*)c.take(64);
   w->st = (LobpcgState*)c.take(sizeof(LobpcgState));
+  w->Z = c.take(blk);
+  w->net_partials = (double*)c.take((size_t)net_tiles(op.rows, op.cols) * 3 * m * sizeof(double));
   return c.off;
 }
 
@@ -431,8 +459,9 @@ gsf_status gsf_lobpcg_filter(const gsf_operator* h, const void* x0, void* x_out,
   if (h == nullptr || x0 == nullptr || x_out == nullptr || kmax < 0 || !(tol >= 0.0) || !std::isfinite(tol))
     return GSF_EINVAL;
   if (m < 1 || m > kMaxBlock) return GSF_EINVAL;
-  if (T != nullptr) return GSF_EINVAL;  // learned preconditioner: not in this entry point yet
   const Operator& op = h->op;
+  if (T != nullptr && (T->n != op.n || T->rows != op.rows || T->cols != op.cols || T->prec != op.desc.prec))
+    return GSF_EINVAL;
   LobWs w;
   if (ws == nullptr || ws_bytes < carve_lob(op, m, nullptr, &w)) return GSF_ENOMEM;
   carve_lob(op, m, (char*)ws, &w);
@@ -499,7 +528,14 @@ gsf_status gsf_lobpcg_filter(const gsf_operator* h, const void* x0, void* x_out,
   rr.init = 0;
   GSF_TRY(lob_launch_mkernel(1, a, nb, m, 1, deg, s));  // X = X0 C, AX, W = R
   for (int k = 0; k < kmax; ++k) {
-    if (constraint) GSF_TRY(lob_launch_project(a, w.W, nb, s));
+    if (T != nullptr) {
+      GSF_TRY(net_infer(op.desc.prec, T->w, op.rows, op.cols, m, w.W, w.Z, T->g, constraint ? op.sqd : nullptr,
+                        w.st->res, w.st, w.net_partials, s));
+      GSF_TRY(net_lob_select(op.desc.prec, op.rows, op.cols, m, constraint ? 1 : 0, w.W, w.Z, op.sqd,
+                             w.net_partials, w.st, s));
+    } else if (constraint) {
+      GSF_TRY(lob_launch_project(a, w.W, nb, s));
+    }
     GSF_TRY(apply_any(op, GSF_FORM_LSYM, m, w.W, m, w.AW, m, nullptr, nullptr, s));
     const int ns = (k == 0) ? 2 * m : 3 * m;
     g.ns = ns;
@@ -526,6 +562,8 @@ gsf_status gsf_lobpcg_filter(const gsf_operator* h, const void* x0, void* x_out,
   info->status = status;
   info->dropped = host.dropped;
   info->m = m;
+  info->fallbacks = host.fallbacks;
+  info->pad = 0;
   for (int j = 0; j < 8; ++j) {
     info->res[j] = j < m ? host.res[j] : 0.0;
     info->theta[j] = j < m ? host.theta[j] : 0.0;
@@ -671,6 +709,50 @@ gsf_status gsf_tune_apply(const gsf_operator* h, int m, const void* x, void* y, 
   bf_set_rpt(op, w, best);
   if (best_rpt) *best_rpt = best;
   return GSF_OK;
+}
+
+gsf_status gsf_shifted_cg(const gsf_operator* h, double alpha, const void* b, int64_t ldb, void* y, int kmax,
+                          double tol, void* ws, size_t ws_bytes, gsf_cg_info* info, void* stream) {
+  if (h == nullptr || b == nullptr || y == nullptr || ldb < 1 || kmax < 0 || !(alpha >= 0.0) ||
+      !std::isfinite(alpha) || !(tol >= 0.0) || !std::isfinite(tol))
+    return GSF_EINVAL;
+  const Operator& op = h->op;
+  CgWs w;
+  if (ws == nullptr || ws_bytes < carve_cg(op, nullptr, &w)) return GSF_ENOMEM;
+  carve_cg(op, (char*)ws, &w);
+  hipStream_t s = (hipStream_t)stream;
+  CgState init{};
+  init.tol = tol;
+  GSF_TRY(launch_cg_state_init(w.st, init, s));
+  GSF_TRY(launch_scg_init(op.desc.prec, b, ldb, y, w.r, op.n, w.partials, w.st, s));
+  for (int k = 1; k <= kmax; ++k) {
+    GSF_TRY(launch_cg_pupdate(op, w.r, w.p, w.st, s));
+    GSF_TRY(apply_any(op, GSF_FORM_LSYM, 1, w.p, 1, w.q, 1, nullptr, nullptr, s));
+    int nparts = 0;
+    GSF_TRY(launch_scg_shift(op.desc.prec, w.p, w.q, op.n, alpha, w.partials, &nparts, w.st, s));
+    GSF_TRY(launch_cg_alpha(w.partials, nparts, w.st, s));
+    GSF_TRY(launch_cg_update(op, y, w.r, w.p, w.q, w.partials, w.st, s));
+  }
+  if (info == nullptr) return GSF_OK;
+  CgState host{};
+  GSF_TRY(hip_ok(hipMemcpyAsync(&host, w.st, sizeof(host), hipMemcpyDeviceToHost, s)));
+  GSF_TRY(hip_ok(hipStreamSynchronize(s)));
+  gsf_status status = (gsf_status)host.status;
+  if (status == GSF_OK && tol > 0.0 && !(host.rho <= host.tol2)) status = GSF_ENOTCONV;
+  info->iters = host.iters;
+  info->status = status;
+  info->res0 = host.res0;
+  info->res = std::sqrt(host.rho > 0.0 ? host.rho : 0.0);
+  return status;
+}
+
+gsf_status gsf_lobpcg_residual(const gsf_operator* h, int m, const void* X, const double* theta, void* R,
+                               void* stream) {
+  if (h == nullptr || X == nullptr || theta == nullptr || R == nullptr || m < 1 || m > kMaxBlock) return GSF_EINVAL;
+  const Operator& op = h->op;
+  hipStream_t s = (hipStream_t)stream;
+  GSF_TRY(apply_any(op, GSF_FORM_LSYM, m, X, m, R, m, nullptr, nullptr, s));
+  return launch_residual(op.desc.prec, X, R, op.n, m, theta, s);
 }
 
 }  // extern "C"

@@ -110,3 +110,11 @@ int apply_num_blocks(const Operator& op, int m);
 struct gsf_operator {
   gsf::Operator op;
 };
+
+// Learned preconditioner: grid, precision and borrowed device pointers.
+struct gsf_precond {
+  int64_t n, rows, cols;
+  int prec;
+  const void* g;       // guidance, n elements of the operator's type
+  const uint16_t* w;   // BF16 weights
+};

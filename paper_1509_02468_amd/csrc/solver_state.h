@@ -26,6 +26,7 @@ struct LobpcgState {
   double theta[8];
   double res[8];       // residual norms of the current X
   double yx[8];        // Y^T W (constraint projection coefficients)
+  double yz[8];        // Y^T T(R) (learned preconditioner)
   double ynorm_inv;    // 1 / ||sqrt(d)||
   double tol;
   double drop_tol;
@@ -40,6 +41,9 @@ struct LobpcgState {
   int32_t nkept;       // kept columns of the last Rayleigh-Ritz
   int32_t start_failed;  // the start block had rank < m
   int32_t kept[24];
+  int32_t tuse[8];     // column j uses T(r_j) this step (else T = I)
+  int32_t fallbacks;   // column-steps that fell back to T = I
+  int32_t pad2;
   unsigned int counter;
   unsigned int counter2;
 };

@@ -3,7 +3,9 @@ HIP library).  Device buffers are torch CUDA tensors (ROCm); torch is used for
 device memory and streams only.
 
 Names mirror the C ABI in include/gsf.h: build_operator, apply, power_filter,
-cg_filter, lobpcg_filter, plus the diagnostic block_gram / rayleigh_ritz.
+cg_filter, lobpcg_filter, the learned preconditioner (net_* training entry
+points, Precond, shifted_cg, lobpcg_residual, make_pair), batching (Batch),
+plus the diagnostic block_gram / rayleigh_ritz.
 """
 from __future__ import annotations
 
@@ -45,7 +47,8 @@ class CgInfo(ctypes.Structure):
 
 class LobpcgInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("status", ctypes.c_int32), ("dropped", ctypes.c_int32),
-                ("m", ctypes.c_int32), ("res", ctypes.c_double * 8), ("theta", ctypes.c_double * 8)]
+                ("m", ctypes.c_int32), ("res", ctypes.c_double * 8), ("theta", ctypes.c_double * 8),
+                ("fallbacks", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 class BatchItem(ctypes.Structure):
@@ -100,6 +103,19 @@ def load_library(path: str = LIB_PATH):
         "gsf_batch_run": ([vp, vp], i32),
         "gsf_batch_get_info": ([vp, P(BatchInfo), vp], i32),
         "gsf_batch_destroy": ([vp], None),
+        "gsf_net_workspace_bytes": ([i32, i64, i64, P(sz)], i32),
+        "gsf_net_forward": ([vp, i32, vp, i64, i64, vp, vp, vp, sz, vp], i32),
+        "gsf_net_loss_grad": ([vp, i32, vp, i64, i64, vp, vp, vp, vp, vp, sz, vp], i32),
+        "gsf_net_adam": ([i64, i32, dbl, dbl, dbl, dbl, vp, vp, vp, vp, vp, vp], i32),
+        "gsf_net_to_bf16": ([i64, vp, vp, vp], i32),
+        "gsf_net_pair_workspace_bytes": ([vp, P(sz)], i32),
+        "gsf_net_make_pair": ([vp, vp, i64, vp, i64, vp, vp, vp, vp, sz, vp], i32),
+        "gsf_precond_create": ([vp, vp, vp, P(vp)], i32),
+        "gsf_precond_destroy": ([vp], None),
+        "gsf_precond_workspace_bytes": ([vp, i32, P(sz)], i32),
+        "gsf_precond_apply": ([vp, i32, vp, vp, vp, sz, vp], i32),
+        "gsf_shifted_cg": ([vp, dbl, vp, i64, vp, i32, dbl, vp, sz, P(CgInfo), vp], i32),
+        "gsf_lobpcg_residual": ([vp, i32, vp, vp, vp, vp], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -325,16 +341,133 @@ class Operator:
         return y, (inf if info else None)
 
     def lobpcg_filter(self, x0, m, kmax, tol=0.0, constraint=False, out=None, ritz=None, ws=None, info=True,
-                      stream=None):
+                      stream=None, precond=None):
         torch = _torch()
         y = out if out is not None else torch.empty_like(x0)
         ws = ws if ws is not None else self.workspace(METHOD_LOBPCG, m)
         inf = LobpcgInfo()
-        st = _lib.gsf_lobpcg_filter(self.handle, _ptr(x0), _ptr(y), m, kmax, tol, int(bool(constraint)), None,
+        st = _lib.gsf_lobpcg_filter(self.handle, _ptr(x0), _ptr(y), m, kmax, tol, int(bool(constraint)),
+                                    precond.handle if precond is not None else None,
                                     _ptr(ritz) if ritz is not None else None, _ptr(ws), ws.numel(),
                                     ctypes.byref(inf) if info else None, _stream(stream))
         _check(st, "lobpcg_filter")
         return y, (inf if info else None)
+
+    def shifted_cg(self, alpha, b, kmax, tol, ldb=1, out=None, ws=None, info=True, stream=None):
+        """y = (L_sym + alpha I)^-1 b by CG (b: n values at stride ldb)."""
+        torch = _torch()
+        y = out if out is not None else torch.empty(self.n, dtype=self.dtype, device="cuda")
+        ws = ws if ws is not None else self.workspace(METHOD_CG)
+        inf = CgInfo()
+        st = _lib.gsf_shifted_cg(self.handle, alpha, _ptr(b), ldb, _ptr(y), kmax, tol, _ptr(ws), ws.numel(),
+                                 ctypes.byref(inf) if info else None, _stream(stream))
+        _check(st, "shifted_cg")
+        return y, (inf if info else None)
+
+    def lobpcg_residual(self, X, theta, out=None, stream=None):
+        """R = L_sym X - X diag(theta) for an n x m block."""
+        torch = _torch()
+        m = X.shape[1]
+        R = out if out is not None else torch.empty_like(X)
+        th = np.ascontiguousarray(np.asarray(theta, dtype=np.float64)[:m])
+        _check(_lib.gsf_lobpcg_residual(self.handle, m, _ptr(X), th.ctypes.data_as(ctypes.c_void_p), _ptr(R),
+                                        _stream(stream)), "lobpcg_residual")
+        return R
+
+    def make_pair(self, r, y, g, inputs, targets, ldr=1, ldy=1, stream=None):
+        """Training pair (r/s, g), y/s into FP32 views inputs (2n), targets (n)."""
+        torch = _torch()
+        nbytes = ctypes.c_size_t()
+        _check(_lib.gsf_net_pair_workspace_bytes(self.handle, ctypes.byref(nbytes)), "net_pair_workspace_bytes")
+        ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device="cuda")
+        _check(_lib.gsf_net_make_pair(self.handle, _ptr(r), ldr, _ptr(y), ldy, _ptr(g), _ptr(inputs),
+                                      _ptr(targets), _ptr(ws), ws.numel(), _stream(stream)), "net_make_pair")
+        return ws  # caller keeps it alive until the stream has run
+
+
+NET_WEIGHTS = 2736
+
+
+class Precond:
+    """Learned preconditioner handle (gsf_precond_create): borrows the
+    operator grid, the guidance tensor and the BF16 weight tensor (uint16 or
+    bfloat16 storage), which must stay alive."""
+
+    def __init__(self, op, guidance, w_bf16):
+        lib = load_library()
+        torch = _torch()
+        g = guidance.to(device="cuda", dtype=op.dtype).contiguous().reshape(-1)
+        if g.numel() != op.n or w_bf16.numel() != NET_WEIGHTS or not w_bf16.is_cuda:
+            raise ValueError("guidance / weights do not match")
+        self.op, self.g, self.w = op, g, w_bf16
+        h = ctypes.c_void_p()
+        _check(lib.gsf_precond_create(op.handle, _ptr(g), _ptr(w_bf16), ctypes.byref(h)), "precond_create")
+        self.handle = h
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.gsf_precond_destroy(self.handle)
+            self.handle = None
+
+    def apply(self, R, out=None, stream=None):
+        torch = _torch()
+        m = 1 if R.dim() == 1 else R.shape[1]
+        W = out if out is not None else torch.empty_like(R)
+        nbytes = ctypes.c_size_t()
+        _check(_lib.gsf_precond_workspace_bytes(self.handle, m, ctypes.byref(nbytes)), "precond_workspace_bytes")
+        ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device="cuda")
+        _check(_lib.gsf_precond_apply(self.handle, m, _ptr(R), _ptr(W), _ptr(ws), ws.numel(), _stream(stream)),
+               "precond_apply")
+        self._ws = ws
+        return W
+
+
+class NetTrainer:
+    """Device state of the network's training: FP32 master weights, Adam
+    moments, the BF16 copy and the scratch of the loss / gradient kernels."""
+
+    def __init__(self, w_init, batch, rows, cols):
+        torch = _torch()
+        lib = load_library()
+        w = torch.as_tensor(np.asarray(w_init, dtype=np.float32)).to("cuda")
+        if w.numel() != NET_WEIGHTS:
+            raise ValueError("weight vector has the wrong length")
+        self.w = w.contiguous()
+        self.mom = torch.zeros_like(self.w)
+        self.vel = torch.zeros_like(self.w)
+        self.grad = torch.zeros_like(self.w)
+        self.wb = torch.empty(NET_WEIGHTS, dtype=torch.int16, device="cuda")
+        self.loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+        self.batch, self.rows, self.cols = batch, rows, cols
+        nbytes = ctypes.c_size_t()
+        _check(lib.gsf_net_workspace_bytes(batch, rows, cols, ctypes.byref(nbytes)), "net_workspace_bytes")
+        self.ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device="cuda")
+        self.t = 0
+        _check(lib.gsf_net_to_bf16(NET_WEIGHTS, _ptr(self.w), _ptr(self.wb), _stream()), "net_to_bf16")
+
+    def loss_grad(self, idx, inputs, targets, stream=None):
+        """loss (device double) and grad for the samples idx (int32 device)."""
+        _check(_lib.gsf_net_loss_grad(_ptr(self.wb), idx.numel(), _ptr(idx), self.rows, self.cols, _ptr(inputs),
+                                      _ptr(targets), _ptr(self.grad), _ptr(self.loss), _ptr(self.ws),
+                                      self.ws.numel(), _stream(stream)), "net_loss_grad")
+        return self.loss, self.grad
+
+    def adam(self, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8, stream=None):
+        self.t += 1
+        _check(_lib.gsf_net_adam(NET_WEIGHTS, self.t, lr, b1, b2, eps, _ptr(self.w), _ptr(self.mom), _ptr(self.vel),
+                                 _ptr(self.grad), _ptr(self.wb), _stream(stream)), "net_adam")
+
+    def forward(self, idx, inputs, stream=None):
+        torch = _torch()
+        y = torch.empty(idx.numel() * self.rows * self.cols, dtype=torch.float32, device="cuda")
+        nbytes = ctypes.c_size_t()
+        _check(_lib.gsf_net_workspace_bytes(idx.numel(), self.rows, self.cols, ctypes.byref(nbytes)),
+               "net_workspace_bytes")
+        ws = self.ws if nbytes.value <= self.ws.numel() else torch.empty(int(nbytes.value), dtype=torch.uint8,
+                                                                         device="cuda")
+        _check(_lib.gsf_net_forward(_ptr(self.wb), idx.numel(), _ptr(idx), self.rows, self.cols, _ptr(inputs),
+                                    _ptr(y), _ptr(ws), ws.numel(), _stream(stream)), "net_forward")
+        return y
 
 
 def build_operator(kind, shape, guidance, radius, sigma_d=0.0, sigma_r=0.0, eps=0.0, prec=F32, stream=None):

@@ -90,3 +90,30 @@ def test_gram_workspace_query(lib):
     assert lib.gsf_block_gram_workspace_bytes(ctypes.c_int64(1 << 20), ctypes.byref(sz)) == 0
     assert sz.value > 0
     assert lib.gsf_block_gram_workspace_bytes(ctypes.c_int64(0), ctypes.byref(sz)) == 1
+
+
+def test_learned_preconditioner_argument_checks(lib):
+    """The network and training entry points validate before touching the
+    device (EINVAL = 1, ENOMEM = 2)."""
+    sz = ctypes.c_size_t()
+    assert lib.gsf_net_workspace_bytes(0, 64, 64, ctypes.byref(sz)) == 1
+    assert lib.gsf_net_workspace_bytes(16, 0, 64, ctypes.byref(sz)) == 1
+    assert lib.gsf_net_workspace_bytes(16, 512, 512, ctypes.byref(sz)) == 0
+    # a1, a2 (BF16 x 16) + dz1, dz2 (FP32 x 16) + y, dy per pixel
+    assert sz.value >= 16 * 512 * 512 * (2 * 32 + 2 * 64 + 2 * 4)
+    v = ctypes.c_void_p(16)
+    assert lib.gsf_net_forward(None, 1, v, 8, 8, v, v, v, 1 << 30, None) == 1
+    assert lib.gsf_net_forward(v, 1, v, 8, 8, v, v, v, 16, None) == 2
+    assert lib.gsf_net_loss_grad(v, 0, v, 8, 8, v, v, v, v, v, 1 << 30, None) == 1
+    assert lib.gsf_net_adam(0, 1, 1e-3, 0.9, 0.999, 1e-8, v, v, v, v, v, None) == 1
+    assert lib.gsf_net_adam(10, 0, 1e-3, 0.9, 0.999, 1e-8, v, v, v, v, v, None) == 1
+    assert lib.gsf_net_adam(10, 1, 1e-3, 1.0, 0.999, 1e-8, v, v, v, v, v, None) == 1
+    assert lib.gsf_net_to_bf16(0, v, v, None) == 1
+    h = ctypes.c_void_p()
+    assert lib.gsf_precond_create(None, v, v, ctypes.byref(h)) == 1
+    assert lib.gsf_precond_workspace_bytes(None, 4, ctypes.byref(sz)) == 1
+    assert lib.gsf_precond_apply(None, 4, v, v, v, 1 << 30, None) == 1
+    assert lib.gsf_shifted_cg(None, 1e-2, v, 1, v, 10, 1e-10, v, 1 << 30, None, None) == 1
+    assert lib.gsf_lobpcg_residual(None, 4, v, v, v, None) == 1
+    assert lib.gsf_net_make_pair(None, v, 1, v, 1, v, v, v, v, 1 << 30, None) == 1
+    assert lib.gsf_net_pair_workspace_bytes(None, ctypes.byref(sz)) == 1
