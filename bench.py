@@ -46,6 +46,9 @@ def _args():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--serial", action="store_true", help="run CG and LOBPCG one after the other")
     ap.add_argument("--no-batch", action="store_true", help="skip the uneven-batch measurement")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner measurement")
+    ap.add_argument("--learned-images", type=int, default=200, help="training images (10 pairs each)")
+    ap.add_argument("--learned-eval", type=int, default=2048, help="side of the evaluation image")
     ap.add_argument("--kernels-only", action="store_true",
                     help="only the stencil applies (m = 1 and m) and a 1 GiB copy, for hardware counters")
     return ap.parse_args()
@@ -176,6 +179,55 @@ def batch_bench(seed=4):
             "items_converged": int(sum(1 for i in info if i[1] == 0)), "outputs_equal_sequential": bool(same)}
 
 
+def learned_bench(n_images=200, side=512, eval_side=2048, tol=1e-6, kmax=20000, m=4):
+    """Learned preconditioner: training pairs from the method itself on
+    n_images noisy scenes of side^2 (BF 11x11, sigma_d = 2, sigma_r = 0.1,
+    noise 0.05), 20 Adam epochs (batch 16, lr 1e-3), then block LOBPCG
+    (m = 4, constraint, FP32 data, FP64 Rayleigh-Ritz) to a residual of tol on
+    an unseen eval_side^2 scene, plain T = I against the learned T."""
+    import torch
+    import paper_1509_02468_amd as gsf
+    from paper_1509_02468_amd import learned
+    from synth import scene_2d, convnet_init
+
+    imgs = [scene_2d(side, side, 0.05, 5000 + i)[1] for i in range(n_images)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    inputs, targets, cgi = learned.generate_pairs(imgs, 5, 2.0, 0.1, m=m)
+    torch.cuda.synchronize()
+    t_pairs = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    trainer, losses = learned.train(inputs, targets, side, side, convnet_init(5), epochs=20, batch=16, lr=1e-3)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    del inputs, targets
+    g = scene_2d(eval_side, eval_side, 0.05, 5900)[1]
+    gd = torch.tensor(g.ravel(), dtype=torch.float32, device="cuda")
+    op = gsf.Operator("bf", (eval_side, eval_side), gd, 5, 2.0, 0.1, prec=gsf.F32)
+    op.tune_apply(m)
+    T = gsf.Precond(op, gd, trainer.wb)
+    ws = op.workspace(gsf.METHOD_LOBPCG, m)
+    res = {}
+    for name, P in (("plain", None), ("learned", T)):
+        op.lobpcg_filter(gd, m, 3, constraint=True, ws=ws, precond=P)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, info = op.lobpcg_filter(gd, m, kmax, tol=tol, constraint=True, ws=ws, precond=P)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        res[name] = {"iters": info.iters, "ms": round(dt * 1e3, 1), "ms_per_iter": round(dt * 1e3 / max(info.iters, 1), 3),
+                     "status": gsf.gsf.STATUS_NAMES.get(info.status, info.status),
+                     "max_res": float(max(list(info.res)[:m])), "theta": [float(t) for t in list(info.theta)[:m]],
+                     "fallbacks": info.fallbacks}
+    return {"workload": f"learned_bf11_train{n_images}x{side}_eval{eval_side}",
+            "train": {"pairs": n_images * 10, "pair_gen_s": round(t_pairs, 1), "train_s": round(t_train, 1),
+                      "cg_iters_mean": round(float(np.mean(cgi)), 1), "loss_first_epoch": round(float(losses[0]), 3),
+                      "loss_last_epoch": round(float(losses[-1]), 3)},
+            "tol": tol, "plain": res["plain"], "learned": res["learned"],
+            "iters_ratio_learned_over_plain": round(res["learned"]["iters"] / max(res["plain"]["iters"], 1), 3),
+            "time_ratio_learned_over_plain": round(res["learned"]["ms"] / max(res["plain"]["ms"], 1e-9), 3)}
+
+
 def main():
     a = _args()
     if a.kernels_only:
@@ -288,6 +340,7 @@ def main():
                 "m1_us": round(rl[1][1] * 1e3, 2), f"m{m}_us": round(rl[m][1] * 1e3, 2)}
 
     batch = None if a.no_batch else batch_bench()
+    learned_res = None if a.no_learned else learned_bench(a.learned_images, eval_side=a.learned_eval)
     cpu = None if a.no_cpu else cpu_baseline(w, noisy, a.cpu_seconds)
     out = {"metric": "Mpixel-iters/s of Laplacian apply", "value": round(value, 1), "unit": "Mpixel-iters/s",
            "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(ms, 3),
@@ -296,7 +349,7 @@ def main():
            "config": {"workload": a.workload, "shape": list(shape), "operator": f"{w['kind']} r={w['radius']}",
                       "cg_iters": kcg, "lobpcg_iters": klob, "lobpcg_m": m, "parallelism": "single-gpu",
                       "apply_tuning": tuned, "cg_lobpcg_streams": 2 if concurrent else 1},
-           "roofline": roofline, "cpu_baseline": cpu, "batch": batch}
+           "roofline": roofline, "cpu_baseline": cpu, "batch": batch, "learned": learned_res}
     print(json.dumps(out), flush=True)
 
 

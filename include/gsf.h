@@ -179,6 +179,8 @@ gsf_status gsf_power_filter(const gsf_operator* op, const void* x0, void* x_out,
  *     or p^T q <= 0 or non-finite: stop, GSF_EBREAKDOWN (x so far is returned;
  *     a constant x0 returns x0);
  * and returns GSF_ENOTCONV when tol > 0 was not met after kmax updates.
+ * With tol > 0 and info != NULL the host stops issuing steps once the device
+ * state reports the stop (read every 16 steps, 16 steps behind the queue).
  * The returned status is only known after the stream has reached the end of
  * the call: with info == NULL the call returns GSF_OK after enqueueing. */
 gsf_status gsf_cg_filter(const gsf_operator* op, const void* x0, void* x_out, int kmax,
@@ -196,7 +198,9 @@ gsf_status gsf_cg_filter(const gsf_operator* op, const void* x0, void* x_out, in
  * <= tau^2 max norm^2), keep the m smallest Ritz pairs, P = [W, P] C.
  * Output x_out = D^-1/2 (X X^T z0 (+ Y Y^T z0)), n elements.
  * ritz_vecs (NULL or n*m, z-space, column signs with x_j^T z0 >= 0).
- * tol > 0 stops when every column residual <= tol (GSF_ENOTCONV if not met).
+ * tol > 0 stops when every column residual <= tol (GSF_ENOTCONV if not met);
+ * with info != NULL the host then also stops issuing steps (it reads the
+ * device convergence flag every 16 steps, 16 steps behind the queue).
  * A start block of rank < m returns x0 with GSF_EBREAKDOWN.
  * T: NULL (plain method) or a learned preconditioner (gsf_precond_create)
  *   built for this operator's grid and precision; then W = T(R) column by
@@ -276,7 +280,8 @@ gsf_status gsf_precond_apply(const gsf_precond* T, int m, const void* R, void* W
  *    b with stride ldb, y contiguous, n values of the operator's element
  *    type), the recurrences of Algorithm 2 with T = I; stops when
  *    ||r|| <= tol ||b|| or after kmax steps (GSF_ENOTCONV if tol > 0 is not
- *    met); p^T q <= 0 is GSF_EBREAKDOWN.  Workspace: gsf_solver_workspace_bytes
+ *    met; with info != NULL the host stops issuing steps after convergence,
+ *    as for gsf_cg_filter); p^T q <= 0 is GSF_EBREAKDOWN.  Workspace: gsf_solver_workspace_bytes
  *    (op, GSF_METHOD_CG, 1, ...).  info may be NULL (then no host sync).
  *  gsf_lobpcg_residual: R = L_sym X - X diag(theta) for an n x m point-major
  *    block (theta: m host doubles). */

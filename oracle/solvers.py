@@ -238,7 +238,10 @@ def rayleigh_ritz(GA, GB, m: int, drop_tol: float, zero_tol: float = 0.0):
     (delta = diag(GB)^-1/2); Cholesky factor the scaled GB column by column,
     dropping a column whose pivot (squared distance from the span of the kept
     columns) is <= drop_tol; reduce A to L^-1 A_K L^-T; dense symmetric
-    eigensolve; back-transform.
+    eigensolve; back-transform; fix the sign of each column of C so that its
+    largest-magnitude entry (the first one on ties) is positive (the Ritz
+    vectors, and so the residuals a non-linear preconditioner sees, then have
+    a sign that does not depend on the eigensolver).
     Returns (theta[m] ascending, C[k x m] with zero rows at dropped columns,
     kept[k] bool)."""
     GA = 0.5 * (np.asarray(GA) + np.asarray(GA).T)
@@ -278,6 +281,10 @@ def rayleigh_ritz(GA, GB, m: int, drop_tol: float, zero_tol: float = 0.0):
     CK = Linv.T @ Z[:, :m]
     C = np.zeros((k, m))
     C[idx, :] = delta[idx, None] * CK
+    for j in range(C.shape[1]):
+        i = int(np.argmax(np.abs(C[:, j])))
+        if C[i, j] < 0.0:
+            C[:, j] = -C[:, j]
     return theta[:m], C, kept
 
 

@@ -252,6 +252,58 @@ gsf_status hip_ok(hipError_t e) { return e == hipSuccess ? GSF_OK : GSF_EDEVICE;
     if (_st != GSF_OK) return _st;    \
   } while (0)
 
+// Stops a solver's host loop once its device state reports convergence or
+// breakdown: every kPoll steps the state's `active` flag is copied to pinned
+// host memory behind the queued work, and the copy from the previous poll is
+// read (so kPoll steps stay queued on the GPU while the host waits).  Off
+// under stream capture and when the caller asked for no info (no host sync).
+class Poller {
+ public:
+  static constexpr int kPoll = 16;
+  Poller(hipStream_t s, const int32_t* flag, bool enabled) : s_(s), flag_(flag) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (!enabled || hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
+    static thread_local int32_t* pinned = nullptr;
+    if (pinned == nullptr && hipHostMalloc((void**)&pinned, 64, hipHostMallocDefault) != hipSuccess) {
+      pinned = nullptr;
+      return;
+    }
+    host_ = pinned;
+    for (int i = 0; i < 2; ++i)
+      if (hipEventCreateWithFlags(&ev_[i], hipEventDisableTiming) != hipSuccess) return;
+    on_ = true;
+  }
+  ~Poller() {
+    if (pending_ >= 0) hipEventSynchronize(ev_[pending_]);
+    for (int i = 0; i < 2; ++i)
+      if (ev_[i]) hipEventDestroy(ev_[i]);
+  }
+  // false once the solver is known to have stopped (call before step k)
+  bool keep_going(int k) {
+    if (!on_ || k == 0 || k % kPoll != 0) return true;
+    if (pending_ >= 0) {
+      if (hipEventSynchronize(ev_[pending_]) != hipSuccess) return true;
+      if (host_[pending_] == 0) return false;
+    }
+    const int slot = (k / kPoll) & 1;
+    if (hipMemcpyAsync(&host_[slot], flag_, sizeof(int32_t), hipMemcpyDeviceToHost, s_) != hipSuccess ||
+        hipEventRecord(ev_[slot], s_) != hipSuccess) {
+      on_ = false;
+      return true;
+    }
+    pending_ = slot;
+    return true;
+  }
+
+ private:
+  hipStream_t s_;
+  const int32_t* flag_;
+  int32_t* host_ = nullptr;
+  hipEvent_t ev_[2] = {nullptr, nullptr};
+  int pending_ = -1;
+  bool on_ = false;
+};
+
 }  // namespace
 
 // Host description of an operator without device memory (pointers null):
@@ -427,7 +479,9 @@ gsf_status gsf_cg_filter(const gsf_operator* h, const void* x0, void* x_out, int
   GSF_TRY(launch_scale(op, x0, w.z, 0, s));
   GSF_TRY(apply_any(op, GSF_FORM_LSYM, 1, w.z, 1, w.r, 1, nullptr, nullptr, s));
   GSF_TRY(launch_cg_init(op, w.z, w.r, w.partials, w.st, s));
+  Poller poll(s, &w.st->active, info != nullptr && tol > 0.0);
   for (int k = 1; k <= kmax; ++k) {
+    if (!poll.keep_going(k - 1)) break;
     GSF_TRY(launch_cg_pupdate(op, w.r, w.p, w.st, s));
     int nparts = 0;
     if (op.desc.kind == GSF_BF) {
@@ -527,7 +581,9 @@ gsf_status gsf_lobpcg_filter(const gsf_operator* h, const void* x0, void* x_out,
   GSF_TRY(lob_launch_gram(g, rr, op.desc.prec, s));
   rr.init = 0;
   GSF_TRY(lob_launch_mkernel(1, a, nb, m, 1, deg, s));  // X = X0 C, AX, W = R
+  Poller poll(s, &w.st->active, info != nullptr && tol > 0.0);
   for (int k = 0; k < kmax; ++k) {
+    if (!poll.keep_going(k)) break;
     if (T != nullptr) {
       GSF_TRY(net_infer(op.desc.prec, T->w, op.rows, op.cols, m, w.W, w.Z, T->g, constraint ? op.sqd : nullptr,
                         w.st->res, w.st, w.net_partials, s));
@@ -725,7 +781,9 @@ gsf_status gsf_shifted_cg(const gsf_operator* h, double alpha, const void* b, in
   init.tol = tol;
   GSF_TRY(launch_cg_state_init(w.st, init, s));
   GSF_TRY(launch_scg_init(op.desc.prec, b, ldb, y, w.r, op.n, w.partials, w.st, s));
+  Poller poll(s, &w.st->active, info != nullptr && tol > 0.0);
   for (int k = 1; k <= kmax; ++k) {
+    if (!poll.keep_going(k - 1)) break;
     GSF_TRY(launch_cg_pupdate(op, w.r, w.p, w.st, s));
     GSF_TRY(apply_any(op, GSF_FORM_LSYM, 1, w.p, 1, w.q, 1, nullptr, nullptr, s));
     int nparts = 0;

@@ -580,11 +580,23 @@ __device__ __forceinline__ void rayleigh_ritz(RRShared& sh, int ns, int m, doubl
         c[ii] = v / sh.LK[ii * LD + ii];
       }
     }
+    // sign: the largest-magnitude coefficient (first on ties) is positive, so
+    // Ritz vectors (and residuals) have a fixed sign for a non-odd T
+    double big = 0.0, sgn = 1.0;
+#pragma unroll
+    for (int a = 0; a < KMAX; ++a)
+      if (a < K) {
+        const double v = sh.delta[sh.idx[a]] * c[a];
+        if (fabs(v) > big) {
+          big = fabs(v);
+          sgn = v < 0.0 ? -1.0 : 1.0;
+        }
+      }
 #pragma unroll
     for (int a = 0; a < KMAX; ++a)
       if (a < K) {
         const int row = sh.idx[a];
-        Cout[row * m + t] = sh.delta[row] * c[a];
+        Cout[row * m + t] = sgn * (sh.delta[row] * c[a]);
       }
   }
   __syncthreads();

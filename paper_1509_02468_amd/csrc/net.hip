@@ -11,7 +11,7 @@
 // fused kernel per 28x28 output tile that keeps the whole receptive field in
 // LDS and does the three convolutions as implicit GEMMs on bf16 MFMA
 // (v_mfma_f32_16x16x16bf16_1k: 16 output channels x 16 pixels per
-// instruction).
+// instruction; layer 3 as 9 per-tap 1x1 products summed over the taps).
 #include <cmath>
 
 #include "gsf_internal.h"
@@ -388,7 +388,7 @@ constexpr int kA2N = kA2 * kA2;     // 900
 constexpr int kA1N = kA1 * kA1;     // 1024
 constexpr int kXN = kXS * kXS;      // 1156
 constexpr int kA2Chunks = (kA2N + 15) / 16;  // 57
-static_assert(9 * kA2N * 4 <= kA1N * 16 * 2, "layer-3 taps must fit in the layer-1 buffer");
+static_assert(kA1N / 16 % 16 == 0, "layer-1 chunks must split into pairs over 8 waves");
 
 struct NetInferArgs {
   const uint16_t* w;       // BF16 weights (flat layout)
@@ -417,11 +417,18 @@ __device__ __forceinline__ short4_t as_short4(uint32_t lo, uint32_t hi) {
   return r;
 }
 
+constexpr int kNetThreads = 512;    // 8 waves per tile
+constexpr int kNetWaves = kNetThreads / 64;
+constexpr int kA2PerWave = (kA2Chunks + kNetWaves - 1) / kNetWaves;  // 8
+
+// Two independent 16-pixel chunks per step keep two MFMA chains in flight.
+// Layer 1 writes a1 to LDS; layer 2 feeds its BF16 output (already in the
+// layer-3 operand layout) straight into the layer-3 per-tap products.
 template <typename T>
-__global__ void __launch_bounds__(kThreads, 2) net_infer_kernel(NetInferArgs a) {
+__global__ void __launch_bounds__(kNetThreads) net_infer_kernel(NetInferArgs a) {
   __shared__ uint32_t xs[kXN];                         // (r/s, g) as a BF16 pair per pixel
-  __shared__ __align__(16) uint16_t a1s[kA1N * 16];    // layer-1 output; layer-3 taps afterwards
-  __shared__ __align__(16) uint16_t a2s[kA2N * 16];    // layer-2 output
+  __shared__ __align__(16) uint16_t a1s[kA1N * 16];    // layer-1 output
+  __shared__ float c3[9 * kA2N];                       // layer-3 per-tap products
   __shared__ double red[16 * 3];
   if (a.st != nullptr && !a.st->active) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -460,7 +467,7 @@ __global__ void __launch_bounds__(kThreads, 2) net_infer_kernel(NetInferArgs a) 
   for (int j = 0; j < a.m; ++j) {
     const double s = a.colnorm[j] / rn;
     // stage the input region
-    for (int e = threadIdx.x; e < kXN; e += kThreads) {
+    for (int e = threadIdx.x; e < kXN; e += kNetThreads) {
       const int64_t gy = y0 - 3 + e / kXS, gx = x0 - 3 + e % kXS;
       uint32_t v = 0;
       if (inside(gy, gx, a.rows, a.cols)) {
@@ -472,64 +479,81 @@ __global__ void __launch_bounds__(kThreads, 2) net_infer_kernel(NetInferArgs a) 
     }
     __syncthreads();
     // layer 1: 2 -> 16 channels on the 32 x 32 region, K = 9 taps x 2 (padded to 32)
-    for (int ch = wave; ch < kA1N / 16; ch += 4) {
-      const int p = ch * 16 + l16, py = p >> 5, px = p & 31;
-      const int base = py * kXS + px;
-      const short4_t b0 = as_short4(xs[base + xo0], xs[base + xo1]);
-      const short4_t b1 = as_short4(q == 0 ? xs[base + xo8] : 0u, 0u);
-      floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-      acc = mfma_bf16(w1a[0], b0, acc);
-      acc = mfma_bf16(w1a[1], b1, acc);
-      const bool in = inside(y0 - 2 + py, x0 - 2 + px, a.rows, a.cols);
-      uint32_t u0 = 0, u1 = 0;
-      if (in) {
-        u0 = f2bf(relu(acc[0])) | (f2bf(relu(acc[1])) << 16);
-        u1 = f2bf(relu(acc[2])) | (f2bf(relu(acc[3])) << 16);
+#pragma unroll
+    for (int k = 0; k < kA1N / 16 / kNetWaves; k += 2) {
+      floatx4 acc[2];
+      int pp[2];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int p = (wave + kNetWaves * (k + u)) * 16 + l16, py = p >> 5, px = p & 31;
+        const int base = py * kXS + px;
+        const short4_t b0 = as_short4(xs[base + xo0], xs[base + xo1]);
+        const short4_t b1 = as_short4(q == 0 ? xs[base + xo8] : 0u, 0u);
+        floatx4 c = {0.0f, 0.0f, 0.0f, 0.0f};
+        c = mfma_bf16(w1a[0], b0, c);
+        acc[u] = mfma_bf16(w1a[1], b1, c);
+        pp[u] = p;
       }
-      *(uint2*)&a1s[p * 16 + 4 * q] = make_uint2(u0, u1);
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int p = pp[u], py = p >> 5, px = p & 31;
+        uint32_t u0 = 0, u1 = 0;
+        if (inside(y0 - 2 + py, x0 - 2 + px, a.rows, a.cols)) {
+          u0 = f2bf(relu(acc[u][0])) | (f2bf(relu(acc[u][1])) << 16);
+          u1 = f2bf(relu(acc[u][2])) | (f2bf(relu(acc[u][3])) << 16);
+        }
+        *(uint2*)&a1s[p * 16 + 4 * q] = make_uint2(u0, u1);
+      }
     }
     __syncthreads();
-    // layer 2: 16 -> 16 channels on the 30 x 30 region, K = 9 taps x 16
-    for (int ch = wave; ch < kA2Chunks; ch += 4) {
-      const int pv = ch * 16 + l16;
-      const int p = pv < kA2N ? pv : kA2N - 1;
-      const int py = p / kA2, px = p - (p / kA2) * kA2;
-      const int base = (py * kA1 + px) * 16 + 4 * q;
-      floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    // layer 2 (16 -> 16 channels on the 30 x 30 region, K = 9 taps x 16) and
+    // layer 3 as 9 per-tap 1x1 products c3[tap][p] = sum_c W3[c][tap] a2[p][c]
+#pragma unroll
+    for (int k = 0; k < kA2PerWave; k += 2) {
+      int base[2];
+      bool in[2];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        int ch = wave + kNetWaves * (k + u);
+        ch = ch < kA2Chunks ? ch : kA2Chunks - 1;
+        const int pv = ch * 16 + l16;
+        const int p = pv < kA2N ? pv : kA2N - 1;
+        const int py = p / kA2, px = p - (p / kA2) * kA2;
+        base[u] = (py * kA1 + px) * 16 + 4 * q;
+        in[u] = inside(y0 - 1 + py, x0 - 1 + px, a.rows, a.cols);
+      }
+      floatx4 acc0 = {0.0f, 0.0f, 0.0f, 0.0f}, acc1 = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
       for (int tap = 0; tap < 9; ++tap) {
-        const uint2 bv = *(const uint2*)&a1s[base + ((tap / 3) * kA1 + tap % 3) * 16];
-        acc = mfma_bf16(w2a[tap], as_short4(bv.x, bv.y), acc);
+        const int off = ((tap / 3) * kA1 + tap % 3) * 16;
+        const uint2 bv0 = *(const uint2*)&a1s[base[0] + off];
+        const uint2 bv1 = *(const uint2*)&a1s[base[1] + off];
+        acc0 = mfma_bf16(w2a[tap], as_short4(bv0.x, bv0.y), acc0);
+        acc1 = mfma_bf16(w2a[tap], as_short4(bv1.x, bv1.y), acc1);
       }
-      if (pv < kA2N) {
-        const bool in = inside(y0 - 1 + py, x0 - 1 + px, a.rows, a.cols);
+      const floatx4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const floatx4 acc = u == 0 ? acc0 : acc1;
         uint32_t u0 = 0, u1 = 0;
-        if (in) {
+        if (in[u]) {
           u0 = f2bf(relu(acc[0])) | (f2bf(relu(acc[1])) << 16);
           u1 = f2bf(relu(acc[2])) | (f2bf(relu(acc[3])) << 16);
         }
-        *(uint2*)&a2s[p * 16 + 4 * q] = make_uint2(u0, u1);
-      }
-    }
-    __syncthreads();
-    // layer 3 as 9 per-tap 1x1 products: c3[tap][p] = sum_c W3[c][tap] a2[p][c]
-    float* c3 = (float*)a1s;
-    for (int ch = wave; ch < kA2Chunks; ch += 4) {
-      const int pv = ch * 16 + l16;
-      const int p = pv < kA2N ? pv : kA2N - 1;
-      const uint2 bv = *(const uint2*)&a2s[p * 16 + 4 * q];
-      floatx4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
-      const floatx4 acc = mfma_bf16(w3a, as_short4(bv.x, bv.y), zero);
-      if (pv < kA2N) {
+        const floatx4 t = mfma_bf16(w3a, as_short4(u0, u1), zero);
+        const int ch = wave + kNetWaves * (k + u);
+        const int pv = ch * 16 + l16;
+        if (ch < kA2Chunks && pv < kA2N) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-          if (4 * q + i < 9) c3[(4 * q + i) * kA2N + p] = acc[i];
+          for (int i = 0; i < 4; ++i)
+            if (4 * q + i < 9) c3[(4 * q + i) * kA2N + pv] = t[i];
+        }
       }
     }
     __syncthreads();
     // output: y[o] = sum_tap c3[tap][o + off(tap)], w = s y
     double v[3] = {0.0, 0.0, 0.0};
-    for (int e = threadIdx.x; e < kOT * kOT; e += kThreads) {
+    for (int e = threadIdx.x; e < kOT * kOT; e += kNetThreads) {
       const int oy = e / kOT, ox = e - (e / kOT) * kOT;
       const int64_t gy = y0 + oy, gx = x0 + ox;
       if (gy >= a.rows || gx >= a.cols) continue;
@@ -845,9 +869,9 @@ gsf_status net_infer(int prec, const uint16_t* w, int64_t rows, int64_t cols, in
   a.ntiles = net_tiles(rows, cols);
   a.partials = partials;
   if (prec == GSF_F32)
-    net_infer_kernel<float><<<a.ntiles, kThreads, 0, s>>>(a);
+    net_infer_kernel<float><<<a.ntiles, kNetThreads, 0, s>>>(a);
   else
-    net_infer_kernel<double><<<a.ntiles, kThreads, 0, s>>>(a);
+    net_infer_kernel<double><<<a.ntiles, kNetThreads, 0, s>>>(a);
   return hipGetLastError() == hipSuccess ? GSF_OK : GSF_EDEVICE;
 }
 

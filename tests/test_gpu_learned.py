@@ -264,21 +264,35 @@ def test_lobpcg_identity_network_matches_oracle(gsf, constraint):
 
 def test_lobpcg_random_network_matches_oracle(gsf):
     """A non-linear network (the identity plus a random perturbation, so that
-    r^T T(r) > 0 and T is used in every column): the GPU and oracle runs
-    agree; a rare BF16 flip inside the network perturbs W by one BF16 unit at
-    a few pixels, which the Rayleigh-Ritz step absorbs."""
-    op, oop, g, gd = _lob_case(gsf, gsf.F64, seed=18)
+    r^T T(r) > 0 and T is used in every column), GPU against oracle.  T is
+    computed with FP32 accumulation on the GPU, so a rare BF16 flip inside
+    the network moves a column of W by ~5e-5 (see the precond parity test);
+    early LOBPCG steps with nearly equal Ritz values amplify that, so the
+    comparison is after one preconditioned step (y within 1e-3) and at
+    convergence, where the result is unique (Ritz values within 1e-9, y
+    within tol / gap)."""
+    op, oop, g, gd = _lob_case(gsf, gsf.F64, H=24, W=28, seed=18)
     w = (cn.identity_weights() + 0.1 * convnet_init(18)).astype(np.float32)
     T = gsf.Precond(op, gd, _bf16_bits(w))
-    m, k = 3, 5
-    out, info = op.lobpcg_filter(gd, m, k, constraint=True, precond=T)
-    ref = oracle.lobpcg_filter(oop, g.ravel(), m, k, constraint=True, precond=cn.make_precond(w, g, g.shape))
+    Tref = cn.make_precond(w, g, g.shape)
+    m = 3
+    out, info = op.lobpcg_filter(gd, m, 1, constraint=True, precond=T)
+    ref = oracle.lobpcg_filter(oop, g.ravel(), m, 1, constraint=True, precond=Tref)
+    e1 = nrel(out.cpu().numpy(), ref[0])
+    assert info.fallbacks == 0
+    assert e1 <= 1e-3
+    tol = 1e-9
+    out, info = op.lobpcg_filter(gd, m, 3000, tol=tol, constraint=True, precond=T)
+    ref = oracle.lobpcg_filter(oop, g.ravel(), m, 3000, tol=tol, constraint=True, precond=Tref)
+    lam = np.linalg.eigvalsh(oracle.spectral.dense_normalized(oop)[1])
     e = nrel(out.cpu().numpy(), ref[0])
     et = np.abs(np.array(list(info.theta)[:m]) - ref[1]).max()
-    print(f"random net LOBPCG: y rel {e:.2e}, theta abs {et:.2e}, fallbacks {info.fallbacks} "
-          f"vs oracle iters {ref[3].iters}")
-    assert info.fallbacks == 0
-    assert e <= 1e-3 and et <= 1e-5
+    print(f"random net LOBPCG: one step y rel {e1:.2e}; converged in {info.iters} vs {ref[3].iters} steps: "
+          f"y rel {e:.2e}, theta abs {et:.2e}, fallbacks {info.fallbacks}")
+    assert info.status == gsf.OK and ref[3].status == "ok"
+    gap = lam[m + 1] - lam[m]
+    assert et <= 1e-9 and np.abs(ref[1] - lam[1:m + 1]).max() <= 1e-9
+    assert e <= max(1e-6, 100 * tol / gap)
 
 
 def test_training_reduces_loss(gsf):

@@ -288,3 +288,20 @@ def test_lobpcg_constant_input_breakdown():
     y, _, _, info = oracle.lobpcg_filter(op, x0, 2, 5, constraint=True)
     assert info.status == "breakdown"
     np.testing.assert_array_equal(y, x0)
+
+
+def test_rayleigh_ritz_sign_convention():
+    """Each coefficient column has its largest-magnitude entry positive, and
+    the rest of the result is the plain eigen-decomposition's (up to sign)."""
+    rng = np.random.default_rng(21)
+    S = rng.standard_normal((40, 6))
+    A = rng.standard_normal((40, 40))
+    A = A @ A.T
+    GA, GB = S.T @ A @ S, S.T @ S
+    theta, C, kept = oracle.rayleigh_ritz(GA, GB, 3, 1e-12)
+    for j in range(3):
+        i = int(np.argmax(np.abs(C[:, j])))
+        assert C[i, j] > 0
+    w, V = sla.eigh(GA, GB)
+    np.testing.assert_allclose(theta, w[:3], rtol=1e-10)
+    np.testing.assert_allclose(np.abs(C), np.abs(V[:, :3]), rtol=1e-8, atol=1e-10)
