@@ -49,6 +49,9 @@ def _args():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner measurement")
     ap.add_argument("--learned-images", type=int, default=200, help="training images (10 pairs each)")
     ap.add_argument("--learned-eval", type=int, default=2048, help="side of the evaluation image")
+    ap.add_argument("--precision-study", action="store_true",
+                    help="FP32 against all-FP64 LOBPCG (m = 8, 100 steps) on the 4096^2 BF 7x7 and GF r = 8 "
+                         "workloads, and both against the FP64 oracle on a 384^2 image of the same class")
     ap.add_argument("--kernels-only", action="store_true",
                     help="only the stencil applies (m = 1 and m) and a 1 GiB copy, for hardware counters")
     return ap.parse_args()
@@ -228,10 +231,70 @@ def learned_bench(n_images=200, side=512, eval_side=2048, tol=1e-6, kmax=20000, 
             "time_ratio_learned_over_plain": round(res["learned"]["ms"] / max(res["plain"]["ms"], 1e-9), 3)}
 
 
+def precision_study(oracle_side=384):
+    """Per-result errors of the precision modes: FP32 data with MFMA Gram and
+    FP64 Rayleigh-Ritz against the all-FP64 GPU run at 4096^2, and both
+    against the FP64 oracle at oracle_side^2 (same generator class and
+    operators; the oracle cannot run at 4096^2 in bounded time)."""
+    import torch
+    import paper_1509_02468_amd as gsf
+    import oracle
+    from synth import WORKLOADS, make_signal, scene_2d
+
+    def run(kind, shape, x, prec, w, m, k):
+        dt = torch.float32 if prec == gsf.F32 else torch.float64
+        xd = torch.tensor(x.ravel(), dtype=dt, device="cuda")
+        op = gsf.Operator(kind, shape, xd, w["radius"], w["sigma_d"], w["sigma_r"], w["eps"], prec)
+        ws = op.workspace(gsf.METHOD_LOBPCG, m)
+        op.lobpcg_filter(xd, m, 2, ws=ws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        y, info = op.lobpcg_filter(xd, m, k, ws=ws)
+        torch.cuda.synchronize()
+        return y.double().cpu().numpy(), np.array(list(info.theta)[:m]), np.array(list(info.res)[:m]), \
+            time.perf_counter() - t0
+
+    def rel(a, b):
+        return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+    out = {}
+    for name in ("image_4096_bf7", "image_4096_gf8"):
+        w = WORKLOADS[name]
+        m, k = w["lobpcg_m"], w["lobpcg_iters"]
+        _, x = make_signal(name)
+        x32 = x.astype(np.float32).astype(np.float64)
+        y32, t32, r32, s32 = run(w["kind"], w["shape"], x32, gsf.F32, w, m, k)
+        y64, t64, r64, s64 = run(w["kind"], w["shape"], x32, gsf.F64, w, m, k)
+        res = {"full": {"shape": list(w["shape"]), "m": m, "steps": k,
+                        "fp32_vs_fp64_theta_abs": float(np.abs(t32 - t64).max()),
+                        "fp32_vs_fp64_theta_rel": float(np.abs(t32 / t64 - 1).max()),
+                        "fp32_vs_fp64_y_rel": rel(y32, y64),
+                        "fp32_res_max": float(r32.max()), "fp64_res_max": float(r64.max()),
+                        "fp32_s": round(s32, 3), "fp64_s": round(s64, 3)}}
+        xs = scene_2d(oracle_side, oracle_side, w["sigma"], w["seed"])[1].astype(np.float32).astype(np.float64)
+        shp = (oracle_side, oracle_side)
+        ys32, ts32, _, _ = run(w["kind"], shp, xs, gsf.F32, w, m, k)
+        ys64, ts64, _, _ = run(w["kind"], shp, xs, gsf.F64, w, m, k)
+        ref = oracle.build_operator(w["kind"], xs, w["radius"], w["sigma_d"], w["sigma_r"], w["eps"])
+        t0 = time.perf_counter()
+        yo, to, _, _ = oracle.lobpcg_filter(ref, xs.ravel(), m, k)
+        res["oracle"] = {"shape": list(shp), "oracle_s": round(time.perf_counter() - t0, 1),
+                         "fp64_theta_abs": float(np.abs(ts64 - to).max()), "fp64_y_rel": rel(ys64, yo),
+                         "fp32_theta_abs": float(np.abs(ts32 - to).max()), "fp32_y_rel": rel(ys32, yo)}
+        out[name] = res
+    return out
+
+
 def main():
     a = _args()
     if a.kernels_only:
         kernels_only(a)
+        return
+    if a.precision_study:
+        import torch
+        import paper_1509_02468_amd as gsf
+        gsf.load_library()
+        print(json.dumps({"precision_study": precision_study()}))
         return
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is described in DESIGN.md"}))

@@ -252,3 +252,39 @@ def test_lobpcg_constant_input_breakdown(gsf):
     y, info = op.lobpcg_filter(_torch(x.ravel(), 1, gsf), 2, 5, constraint=True)
     assert info.status == gsf.EBREAKDOWN
     np.testing.assert_array_equal(y.cpu().numpy(), x.ravel())
+
+
+# ------------------------------------------------------------------ precision study
+@pytest.mark.parametrize("kind", ["bf7", "gf8"])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_precision_study_lobpcg_m8_100_steps(gsf, kind, prec):
+    """The precision-study configuration (noise 0.08; BF 7x7 with sigma_d = 2,
+    sigma_r = 0.15, or GF radius 8 with eps = 1e-2; LOBPCG m = 8, 100 steps)
+    at a size the oracle finishes in seconds.  FP64: Ritz values within 1e-9
+    relative, output within 1e-8 (100 steps of an m = 8 block amplify
+    summation-order differences more than the 30-step cases above).  FP32
+    (FP32 data and MFMA Gram, FP64 Rayleigh-Ritz): Ritz values within
+    1e-5 * ||L_sym|| (||L_sym|| <= 2); the output error is reported."""
+    import torch
+    H, W = 96, 112
+    x = scene_2d(H, W, 0.08, 3)[1]
+    xr = _round(x, prec, gsf)
+    if kind == "bf7":
+        op = gsf.Operator("bf", (H, W), _torch(xr, prec, gsf), 3, 2.0, 0.15, prec=prec)
+        ref = oracle.build_operator("bf", xr, 3, 2.0, 0.15)
+    else:
+        op = gsf.Operator("gf", (H, W), _torch(xr, prec, gsf), 8, eps=1e-2, prec=prec)
+        ref = oracle.build_operator("gf", xr, 8, eps=1e-2)
+    m, k = 8, 100
+    y, info = op.lobpcg_filter(_torch(xr, prec, gsf), m, k)
+    r, th, X, rinfo = oracle.lobpcg_filter(ref, xr.ravel(), m, k, data_prec="f64" if prec == 1 else "f32")
+    theta = np.array(info.theta[:m])
+    ey = rel(y.cpu().numpy(), r)
+    et = np.abs(theta - th).max()
+    print(f"precision study {kind} prec {prec}: theta abs {et:.2e} (rel {np.abs(theta / th - 1).max():.2e}), "
+          f"y rel {ey:.2e}, dropped {info.dropped} vs {rinfo.dropped}")
+    if prec == 1:
+        np.testing.assert_allclose(theta, th, rtol=1e-9, atol=1e-12)
+        assert ey <= 1e-8
+    else:
+        assert et <= 2e-5
