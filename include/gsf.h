@@ -67,7 +67,8 @@ typedef enum { GSF_METHOD_POWER = 0, GSF_METHOD_CG = 1, GSF_METHOD_LOBPCG = 2 } 
  *            border-truncated windows and regularisation gf_eps; its matrix
  *            W_ij = (1/|w|) sum_{k: i,j in w_k} (1/N_k)(1 + (g_i-mu_k)(g_j-mu_k)/(s_k^2+eps))
  *            (eq. (6) in the interior) has row sums d_i = N_i/|w|.
- *  ndim    1 (dims[0] = n) or 2 (dims[0] = rows H, dims[1] = columns W).
+ *  ndim    1 (dims[0] = n) or 2 (dims[0] = rows H, dims[1] = columns W);
+ *          a GF operator has fewer than 2^27 points.
  *  prec    element type of the guidance, of all vectors and of the stored
  *          operator.  Weights and window statistics are always computed in
  *          FP64 and rounded once to this type.
@@ -98,8 +99,11 @@ typedef struct gsf_operator gsf_operator;   /* opaque host handle */
  *      (1/sqrt(d_i)) sum_j w_ij (u_i - u_j) with u = D^-1/2 z, and
  *      N z = z - L_sym z.
  *  GF: `mu` and `inv` hold the window statistics mu_k and 1/(sigma_k^2 + eps)
- *      of the guidance (Algorithm 1), `guidance` a copy of g.
- *  Both: `sqrt_d` holds sqrt(d_i); `degree` holds d_i in FP64. */
+ *      of the guidance (Algorithm 1), `guidance` a copy of g; `planes` is
+ *      NULL (the workspace also holds 16 scratch planes of the apply, which
+ *      is why two GF applies on one operator must not run concurrently).
+ *  Both: `inv_sqrt_d` holds 1/sqrt(d_i), `sqrt_d` sqrt(d_i); `degree` holds
+ *  d_i in FP64. */
 typedef struct {
   int32_t kind, ndim, prec, radius;
   int64_t n;

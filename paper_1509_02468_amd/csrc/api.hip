@@ -78,13 +78,15 @@ gsf_status validate_desc(const gsf_operator_desc* d) {
     if (!(d->sigma_r > 0.0) || std::isnan(d->sigma_r)) return GSF_EINVAL;
   } else {
     if (!(d->gf_eps >= 0.0) || !std::isfinite(d->gf_eps)) return GSF_EINVAL;
+    if (n >= ((int64_t)1 << 27)) return GSF_EINVAL;  // the GF kernels index with 32 bits
   }
   return GSF_OK;
 }
 
 // Operator workspace layout, in order, each region 256-byte aligned:
 //   BF: planes (nplanes*n), diag (n), sqd (n), deg (n doubles)
-//   GF: g (n), mu (n), inv (n), sqd (n), deg (n doubles), 4 scratch planes (n)
+//   GF: g (n), mu (n), inv (n), sqd (n), diag (n), deg (n doubles), 16 scratch
+//       planes (n): (a, b) of up to 8 columns for the apply
 size_t layout_operator(const gsf_operator_desc* d, Operator* op, char* base) {
   const int64_t n = d->ndim == 1 ? d->dims[0] : d->dims[0] * d->dims[1];
   const size_t elem = d->prec == GSF_F32 ? 4 : 8;
@@ -123,24 +125,23 @@ size_t layout_operator(const gsf_operator_desc* d, Operator* op, char* base) {
     void* mu = take(plane);
     void* inv = take(plane);
     void* sqd = take(plane);
+    void* diag = take(plane);
     void* deg = take(dplane);
-    take(4 * plane);  // apply scratch
+    void* scratch = take(align_up((size_t)2 * kMaxBlock * n * elem, kAlign));  // apply: (a, b) of 8 columns
     if (op) {
       op->g = g;
       op->mu = mu;
       op->inv = inv;
       op->sqd = sqd;
+      op->diag = diag;
       op->deg = (double*)deg;
+      op->planes = scratch;
     }
   }
   return off;
 }
 
-void* gf_scratch(const Operator& op) {
-  const size_t plane = align_up((size_t)op.n * op.elem, kAlign);
-  const size_t dplane = align_up((size_t)op.n * 8, kAlign);
-  return (char*)op.g + 4 * plane + dplane;
-}
+void* gf_scratch(const Operator& op) { return op.planes; }
 
 gsf_status apply_any(const Operator& op, int form, int m, const void* x, int64_t ldx, void* y, int64_t ldy,
                      double* dot, int* nparts, hipStream_t s) {
@@ -402,7 +403,7 @@ gsf_status gsf_operator_get_layout(const gsf_operator* h, gsf_operator_layout* o
   out->radius = op.desc.radius;
   out->n = op.n;
   out->nplanes = op.nplanes;
-  out->planes = op.planes;
+  out->planes = op.desc.kind == GSF_BF ? op.planes : nullptr;
   out->inv_sqrt_d = op.diag;
   out->sqrt_d = op.sqd;
   out->degree = op.deg;

@@ -1,171 +1,366 @@
-// Normalized guided-filter operator apply (Section 3, Algorithm 1, eqs. (5)-(6)):
+// Guided-filter operator (Section 3, Algorithm 1, eqs. (5)-(6)): the operator
+// build (window statistics of the guidance) and the normalized apply
 //   N x = D^1/2 GF(D^-1/2 x),  D = diag(N_i / |w|),
-// where GF is Algorithm 1 with the fixed guidance g (linear filter), mean
-// filters over border-truncated windows (N_k points) and the precomputed window
+// where GF is Algorithm 1 with the fixed guidance g (a linear filter), mean
+// filters over border-truncated windows (N_k points) and the window
 // statistics mu_k, inv_k = 1/(sigma_k^2 + eps):
 //   u      = D^-1/2 x            (RW form: u = x)
 //   a_k    = (box(g u)_k / N_k - mu_k box(u)_k / N_k) inv_k
 //   b_k    = box(u)_k / N_k - a_k mu_k
 //   GF(u)_i = (g_i box(a)_i + box(b)_i) / N_i
-// The separable window sums run as four passes (rows, columns, rows, columns)
-// through two scratch planes of the operator; a 1D signal is a single row, so
-// its column passes are the identity.
+//
+// Every window sum runs in one streaming kernel of one wave per workgroup (see
+// gf_box_kernel): running FP64 vertical sums in registers, sliding horizontal
+// sums over the wave's own LDS row, no barriers.  Cost per point is O(1) in
+// the radius.  The apply is two such kernels (u, g u) -> (a, b) and
+// (a, b) -> output for up to 8 columns at once; the build is one kernel on
+// (g, g^2).  A 1D signal is one row.
+#include <cmath>
+
 #include "gsf_internal.h"
 
 namespace gsf {
 namespace {
 
-struct GfArgs {
-  const void* g;
-  const void* mu;
-  const void* inv;
-  const void* x;
-  void* y;
-  void* s0;
-  void* s1;
-  int64_t ldx, ldy;
-  int64_t n, rows, cols;
+constexpr int kGfLanes = 64;   // one wave per workgroup; lane = halo column
+constexpr int kGfRows = 64;    // output rows per workgroup
+
+// 32-bit indices: the operator build rejects GF grids of 2^27 points or more,
+// so point * 16 fits.
+struct GfGeom {
+  int rows, cols;
   int r;
-  int form;
-  double omega;  // |w| = (2r+1)^ndim
 };
 
-__device__ __forceinline__ int64_t win_count(int64_t v, int64_t len, int r) {
-  const int64_t lo = v - r < 0 ? 0 : v - r;
-  const int64_t hi = v + r >= len ? len - 1 : v + r;
+__device__ __forceinline__ int win_count(int v, int len, int r) {
+  const int lo = v - r < 0 ? 0 : v - r;
+  const int hi = v + r >= len ? len - 1 : v + r;
   return hi - lo + 1;
 }
 
-// pass 1: s0 = rowbox(u), s1 = rowbox(g u)
-template <typename T>
-__global__ void __launch_bounds__(kThreads) gf_pass1(GfArgs a) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= a.n) return;
-  const T* __restrict__ x = (const T*)a.x;
-  const T* __restrict__ g = (const T*)a.g;
-  const int64_t yy = i / a.cols, xx = i - yy * a.cols;
-  const int64_t lo = xx - a.r < 0 ? 0 : xx - a.r;
-  const int64_t hi = xx + a.r >= a.cols ? a.cols - 1 : xx + a.r;
-  T su = T(0), sgu = T(0);
-  for (int64_t c = lo; c <= hi; ++c) {
-    const int64_t j = yy * a.cols + c;
-    T u = x[j * a.ldx];
-    if (a.form != GSF_FORM_RW) {
-      const int64_t nj = win_count(yy, a.rows, a.r) * win_count(c, a.cols, a.r);
-      u *= (T)sqrt(a.omega / (double)nj);
+// Keeps the compiler from moving LDS accesses across this point; a wave's
+// own LDS operations complete in order, so no hardware barrier is needed.
+__device__ __forceinline__ void wave_lds_fence() { __asm__ volatile("" ::: "memory"); }
+
+// One wave owns a strip of 64 - 2r output columns (64 halo columns, one per
+// lane) and kGfRows rows.  Lane l keeps the FP64 running vertical window sums
+// of column c0 - r + l for the 2M channels (P::M groups of two); per row it
+// adds the entering row, writes its sums to the wave's LDS row, and then
+// takes the horizontal window sums as lane (group, run of consecutive output
+// columns) with a sliding sum over that LDS row, before subtracting the
+// leaving row.  Loads are unconditional (clamped addresses, results selected)
+// and issued D rows ahead (a register ring, the row loop unrolled by D), so
+// a memory latency is spread over D rows.
+//   P::Row       raw loads of one point (all groups)
+//   P::fetch(i)  -> Row;    P::value(row, j) -> double2 (group j)
+//   P::Epi / P::pre(k, j) / P::store(k, j, s0, s1, rc, src, e): epilogue at
+//   point k with rc = 1 / (points in the window), src = sqrt(rc).
+template <class P>
+__global__ void __launch_bounds__(kGfLanes) gf_box_kernel(P p, GfGeom g) {
+  constexpr int M = P::M;
+  constexpr int R = kGfLanes / M;  // runs per group
+  typedef typename P::Row Row;
+  typedef typename P::Epi Epi;
+  __shared__ double vs[2 * M][kGfLanes + 1];
+  const int r = g.r, ow = kGfLanes - 2 * r;
+  const int lane = threadIdx.x;
+  const int c0 = (int)blockIdx.x * ow;
+  const int y0 = (int)blockIdx.y * kGfRows;
+  const int y1 = y0 + kGfRows < g.rows ? y0 + kGfRows : g.rows;
+  // column role
+  const int gc = c0 - r + lane;
+  const bool cok = gc >= 0 && gc < g.cols;
+  const int gcs = cok ? gc : 0;
+  // run role: group j, output columns [run * L, run * L + L) of the strip
+  const int L = (ow + R - 1) / R;
+  const int j = lane / R, run = lane - (lane / R) * R;
+  const int cb = run * L;
+  int nout = ow - cb < L ? ow - cb : L;
+  if (c0 + cb + nout > g.cols) nout = (int)(g.cols - c0 - cb);
+  if (nout < 0) nout = 0;
+  double rh[M], srh[M];  // L <= ceil(62 M / 64) = M outputs per lane
+#pragma unroll
+  for (int t = 0; t < M; ++t) {
+    rh[t] = 1.0 / (double)win_count(c0 + cb + t, g.cols, r);
+    srh[t] = sqrt(rh[t]);
+  }
+
+  double s[2 * M];
+#pragma unroll
+  for (int c = 0; c < 2 * M; ++c) s[c] = 0.0;
+  auto clamp_row = [&](int y) { return y < 0 ? 0 : (y >= g.rows ? g.rows - 1 : y); };
+  const int w0 = y0 - r < 0 ? 0 : y0 - r;
+  const int w1 = y0 + r - 1 < g.rows - 1 ? y0 + r - 1 : g.rows - 1;
+  {
+    Row cur = p.fetch(clamp_row(w0) * g.cols + gcs);
+    for (int yy = w0; yy <= w1; ++yy) {
+      const Row nxt = p.fetch(clamp_row(yy + 1) * g.cols + gcs);
+      if (cok) {
+#pragma unroll
+        for (int q = 0; q < M; ++q) {
+          const double2 v = p.value(cur, q);
+          s[2 * q] += v.x;
+          s[2 * q + 1] += v.y;
+        }
+      }
+      cur = nxt;
     }
-    su += u;
-    sgu += g[j] * u;
   }
-  ((T*)a.s0)[i] = su;
-  ((T*)a.s1)[i] = sgu;
+  // ring of the entering / leaving points of the next D output rows
+  constexpr int D = M <= 2 ? 4 : (M == 4 ? 2 : 1);
+  Row fa[D], fd[D];
+#pragma unroll
+  for (int u = 0; u < D; ++u) {
+    fa[u] = p.fetch(clamp_row(y0 + u + r) * g.cols + gcs);
+    fd[u] = p.fetch(clamp_row(y0 + u - r) * g.cols + gcs);
+  }
+  for (int yb = y0; yb < y1; yb += D) {
+#pragma unroll
+    for (int u = 0; u < D; ++u) {
+      const int yo = yb + u;
+      if (yo < y1) {
+        const int ya = yo + r, yd = yo - r;
+        Epi e[M];
+#pragma unroll
+        for (int t = 0; t < M; ++t) e[t] = p.pre(yo * g.cols + (t < nout ? c0 + cb + t : c0), j);
+        const bool add = cok && ya < g.rows;
+#pragma unroll
+        for (int q = 0; q < M; ++q) {
+          const double2 v = p.value(fa[u], q);
+          s[2 * q] += add ? v.x : 0.0;
+          s[2 * q + 1] += add ? v.y : 0.0;
+        }
+        wave_lds_fence();
+#pragma unroll
+        for (int c = 0; c < 2 * M; ++c) vs[c][lane] = cok ? s[c] : 0.0;
+        wave_lds_fence();
+        const int vc = (ya < g.rows ? ya : g.rows - 1) - (yd < 0 ? 0 : yd) + 1;
+        const double rv = 1.0 / (double)vc, srv = sqrt(rv);
+        if (nout > 0) {
+          const double* v0 = &vs[2 * j][cb];
+          const double* v1 = &vs[2 * j + 1][cb];
+          double a0 = 0.0, a1 = 0.0;
+          for (int h = 0; h < 2 * r; ++h) {
+            a0 += v0[h];
+            a1 += v1[h];
+          }
+#pragma unroll
+          for (int t = 0; t < M; ++t) {
+            if (t < nout) {
+              a0 += v0[t + 2 * r];
+              a1 += v1[t + 2 * r];
+              p.store(yo * g.cols + c0 + cb + t, j, a0, a1, rv * rh[t], srv * srh[t], e[t]);
+              a0 -= v0[t];
+              a1 -= v1[t];
+            }
+          }
+        }
+        wave_lds_fence();
+        const bool sub = cok && yd >= 0;
+#pragma unroll
+        for (int q = 0; q < M; ++q) {
+          const double2 v = p.value(fd[u], q);
+          s[2 * q] -= sub ? v.x : 0.0;
+          s[2 * q + 1] -= sub ? v.y : 0.0;
+        }
+        fa[u] = p.fetch(clamp_row(ya + D) * g.cols + gcs);
+        fd[u] = p.fetch(clamp_row(yd + D) * g.cols + gcs);
+      }
+    }
+  }
 }
 
-// pass 2: column sums -> a_k, b_k (in place in s0, s1)
-template <typename T>
-__global__ void __launch_bounds__(kThreads) gf_pass2(GfArgs a, T* __restrict__ outa, T* __restrict__ outb) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= a.n) return;
-  const T* __restrict__ s0 = (const T*)a.s0;
-  const T* __restrict__ s1 = (const T*)a.s1;
-  const int64_t yy = k / a.cols, xx = k - yy * a.cols;
-  const int64_t lo = yy - a.r < 0 ? 0 : yy - a.r;
-  const int64_t hi = yy + a.r >= a.rows ? a.rows - 1 : yy + a.r;
-  T su = T(0), sgu = T(0);
-  for (int64_t rr = lo; rr <= hi; ++rr) {
-    su += s0[rr * a.cols + xx];
-    sgu += s1[rr * a.cols + xx];
+// (u, g u) -> (a, b) at every window centre; AB point-major, pairs per group
+template <typename T, int MM, bool SCALE>
+struct GfStage1 {
+  static constexpr int M = MM;
+  const T* x;
+  int ldx;
+  const T* g;
+  const T* dinv;  // 1/sqrt(d) (SCALE), else u = x (RW form)
+  const T* mu;
+  const T* inv;
+  T* ab;
+  struct Row {
+    T x[M];
+    T g, d;
+  };
+  __device__ __forceinline__ Row fetch(int i) const {
+    Row w;
+#pragma unroll
+    for (int q = 0; q < M; ++q) w.x[q] = x[i * ldx + q];
+    w.g = g[i];
+    w.d = SCALE ? dinv[i] : T(1);
+    return w;
   }
-  const T nk = (T)((hi - lo + 1) * win_count(xx, a.cols, a.r));
-  const T mean_u = su / nk, mean_gu = sgu / nk;
-  const T m = ((const T*)a.mu)[k];
-  const T av = (mean_gu - m * mean_u) * ((const T*)a.inv)[k];
-  outa[k] = av;
-  outb[k] = mean_u - av * m;
+  __device__ __forceinline__ double2 value(const Row& w, int q) const {
+    const double u = (double)w.x[q] * (double)w.d;
+    return make_double2(u, (double)w.g * u);
+  }
+  struct Epi {
+    T mu, inv;
+  };
+  __device__ __forceinline__ Epi pre(int k, int) const { return Epi{mu[k], inv[k]}; }
+  __device__ __forceinline__ void store(int k, int j, double su, double sgu, double rc, double, const Epi& e) const {
+    const double mk = (double)e.mu;
+    const double mean_u = su * rc, mean_gu = sgu * rc;
+    const double av = (mean_gu - mk * mean_u) * (double)e.inv;
+    ab[(k * M + j) * 2] = (T)av;
+    ab[(k * M + j) * 2 + 1] = (T)(mean_u - av * mk);
+  }
+};
+
+// (a, b) -> y = D^1/2 GF(u) (N), x - D^1/2 GF(u) (L_sym) or GF(x) (RW)
+template <typename T, int MM>
+struct GfStage2 {
+  static constexpr int M = MM;
+  const T* ab;
+  const T* g;
+  const T* x;
+  int ldx;
+  T* y;
+  int ldy;
+  int form;
+  double sromega;  // 1 / sqrt(|w|)
+  struct Row {
+    T v[2 * M];
+  };
+  __device__ __forceinline__ Row fetch(int i) const {
+    Row w;
+#pragma unroll
+    for (int q = 0; q < 2 * M; ++q) w.v[q] = ab[i * 2 * M + q];
+    return w;
+  }
+  __device__ __forceinline__ double2 value(const Row& w, int q) const {
+    return make_double2((double)w.v[2 * q], (double)w.v[2 * q + 1]);
+  }
+  struct Epi {
+    T g, x;
+  };
+  __device__ __forceinline__ Epi pre(int i, int j) const {
+    return Epi{g[i], form == GSF_FORM_LSYM ? x[i * ldx + j] : T(0)};
+  }
+  __device__ __forceinline__ void store(int i, int j, double sa, double sb, double rc, double src,
+                                        const Epi& e) const {
+    const double gfu = (double)e.g * sa + sb;
+    double out;
+    if (form == GSF_FORM_RW) {
+      out = gfu * rc;
+    } else {
+      const double nx = gfu * (src * sromega);  // (g sum a + sum b) / sqrt(N_i |w|)
+      out = form == GSF_FORM_LSYM ? (double)e.x - nx : nx;
+    }
+    y[i * ldy + j] = (T)out;
+  }
+};
+
+// build: (g, g^2) -> mu, 1/(var + eps), d = N/|w|, sqrt(d), 1/sqrt(d), copy of g
+template <typename T>
+struct GfStats {
+  static constexpr int M = 1;
+  const T* gin;
+  T* gcopy;
+  T* mu;
+  T* inv;
+  T* sqd;
+  T* dinv;
+  double* deg;
+  double eps, omega;
+  struct Row {
+    T v;
+  };
+  __device__ __forceinline__ Row fetch(int i) const { return Row{gin[i]}; }
+  __device__ __forceinline__ double2 value(const Row& w, int) const {
+    const double v = (double)w.v;
+    return make_double2(v, v * v);
+  }
+  struct Epi {
+    T gk;
+  };
+  __device__ __forceinline__ Epi pre(int k, int) const { return Epi{gin[k]}; }
+  __device__ __forceinline__ void store(int k, int, double s1, double s2, double rc, double, const Epi& e) const {
+    const double m = s1 * rc;
+    const double var = s2 * rc - m * m;
+    mu[k] = (T)m;
+    inv[k] = (T)(1.0 / (var + eps));
+    const double d = 1.0 / (rc * omega);
+    deg[k] = d;
+    sqd[k] = (T)sqrt(d);
+    dinv[k] = (T)(1.0 / sqrt(d));
+    gcopy[k] = e.gk;
+  }
+};
+
+dim3 gf_grid(const Operator& op) {
+  const int ow = kGfLanes - 2 * op.desc.radius;
+  return dim3((unsigned)((op.cols + ow - 1) / ow), (unsigned)((op.rows + kGfRows - 1) / kGfRows));
 }
 
-// pass 3: row sums of a and b
-template <typename T>
-__global__ void __launch_bounds__(kThreads) gf_pass3(GfArgs a, const T* __restrict__ ina, const T* __restrict__ inb) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= a.n) return;
-  const int64_t yy = i / a.cols, xx = i - yy * a.cols;
-  const int64_t lo = xx - a.r < 0 ? 0 : xx - a.r;
-  const int64_t hi = xx + a.r >= a.cols ? a.cols - 1 : xx + a.r;
-  T sa = T(0), sb = T(0);
-  for (int64_t c = lo; c <= hi; ++c) {
-    sa += ina[yy * a.cols + c];
-    sb += inb[yy * a.cols + c];
-  }
-  ((T*)a.s0)[i] = sa;
-  ((T*)a.s1)[i] = sb;
+double gf_omega(const Operator& op) {
+  const double w = 2.0 * op.desc.radius + 1.0;
+  return op.desc.ndim == 1 ? w : w * w;
 }
 
-// pass 4: column sums -> output
-template <typename T>
-__global__ void __launch_bounds__(kThreads) gf_pass4(GfArgs a) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= a.n) return;
-  const T* __restrict__ s0 = (const T*)a.s0;
-  const T* __restrict__ s1 = (const T*)a.s1;
-  const int64_t yy = i / a.cols, xx = i - yy * a.cols;
-  const int64_t lo = yy - a.r < 0 ? 0 : yy - a.r;
-  const int64_t hi = yy + a.r >= a.rows ? a.rows - 1 : yy + a.r;
-  T sa = T(0), sb = T(0);
-  for (int64_t rr = lo; rr <= hi; ++rr) {
-    sa += s0[rr * a.cols + xx];
-    sb += s1[rr * a.cols + xx];
-  }
-  const double ni = (double)((hi - lo + 1) * win_count(xx, a.cols, a.r));
-  const T gfu = (((const T*)a.g)[i] * sa + sb);
-  T out;
-  if (a.form == GSF_FORM_RW) {
-    out = gfu / (T)ni;
+template <typename T, int M>
+void gf_apply_group(const Operator& op, T* ab, int form, const T* x, int64_t ldx, T* y, int64_t ldy,
+                    hipStream_t s) {
+  const GfGeom geo{(int)op.rows, (int)op.cols, op.desc.radius};
+  if (form == GSF_FORM_RW) {
+    GfStage1<T, M, false> p1{x, (int)ldx, (const T*)op.g, nullptr, (const T*)op.mu, (const T*)op.inv, ab};
+    gf_box_kernel<GfStage1<T, M, false>><<<gf_grid(op), kGfLanes, 0, s>>>(p1, geo);
   } else {
-    const T nx = gfu / (T)sqrt(ni * a.omega);  // D^1/2 GF(u) = (g sum a + sum b) / sqrt(N_i |w|)
-    out = (a.form == GSF_FORM_LSYM) ? ((const T*)a.x)[i * a.ldx] - nx : nx;
+    GfStage1<T, M, true> p1{x, (int)ldx, (const T*)op.g, (const T*)op.diag, (const T*)op.mu, (const T*)op.inv, ab};
+    gf_box_kernel<GfStage1<T, M, true>><<<gf_grid(op), kGfLanes, 0, s>>>(p1, geo);
   }
-  ((T*)a.y)[i * a.ldy] = out;
+  GfStage2<T, M> p2{ab, (const T*)op.g, x, (int)ldx, y, (int)ldy, form, 1.0 / sqrt(gf_omega(op))};
+  gf_box_kernel<GfStage2<T, M>><<<gf_grid(op), kGfLanes, 0, s>>>(p2, geo);
+}
+
+template <typename T>
+void gf_apply_typed(const Operator& op, void* scratch, int form, int m, const T* x, int64_t ldx, T* y, int64_t ldy,
+                    hipStream_t s) {
+  T* ab = (T*)scratch;
+  int c = 0;
+  while (c < m) {
+    const int left = m - c;
+    if (left >= 8 && sizeof(T) == 4) {
+      gf_apply_group<T, 8>(op, ab, form, x + c, ldx, y + c, ldy, s);
+      c += 8;
+    } else if (left >= 4) {
+      gf_apply_group<T, 4>(op, ab, form, x + c, ldx, y + c, ldy, s);
+      c += 4;
+    } else if (left >= 2) {
+      gf_apply_group<T, 2>(op, ab, form, x + c, ldx, y + c, ldy, s);
+      c += 2;
+    } else {
+      gf_apply_group<T, 1>(op, ab, form, x + c, ldx, y + c, ldy, s);
+      c += 1;
+    }
+  }
 }
 
 }  // namespace
 
-// Scratch: 4 planes of n elements (two for the window sums, two for a and b).
+// Scratch: 2 * kMaxBlock planes of n elements (a, b of up to 8 columns).
 gsf_status launch_gf_apply(const Operator& op, void* scratch, int form, int m, const void* x, int64_t ldx,
                            void* y, int64_t ldy, hipStream_t s) {
-  GfArgs a{};
-  a.g = op.g;
-  a.mu = op.mu;
-  a.inv = op.inv;
-  a.ldx = ldx;
-  a.ldy = ldy;
-  a.n = op.n;
-  a.rows = op.rows;
-  a.cols = op.cols;
-  a.r = op.desc.radius;
-  a.form = form;
-  a.omega = op.desc.ndim == 1 ? (double)(2 * a.r + 1) : (double)((2 * a.r + 1) * (2 * a.r + 1));
-  const unsigned grid = (unsigned)((op.n + kThreads - 1) / kThreads);
-  char* base = (char*)scratch;
-  const size_t plane = align_up((size_t)op.n * op.elem, 256);
-  a.s0 = base;
-  a.s1 = base + plane;
-  void* pa = base + 2 * plane;
-  void* pb = base + 3 * plane;
-  for (int c = 0; c < m; ++c) {
-    a.x = (const char*)x + (size_t)c * op.elem;
-    a.y = (char*)y + (size_t)c * op.elem;
-    if (op.desc.prec == GSF_F32) {
-      gf_pass1<float><<<grid, kThreads, 0, s>>>(a);
-      gf_pass2<float><<<grid, kThreads, 0, s>>>(a, (float*)pa, (float*)pb);
-      gf_pass3<float><<<grid, kThreads, 0, s>>>(a, (const float*)pa, (const float*)pb);
-      gf_pass4<float><<<grid, kThreads, 0, s>>>(a);
-    } else {
-      gf_pass1<double><<<grid, kThreads, 0, s>>>(a);
-      gf_pass2<double><<<grid, kThreads, 0, s>>>(a, (double*)pa, (double*)pb);
-      gf_pass3<double><<<grid, kThreads, 0, s>>>(a, (const double*)pa, (const double*)pb);
-      gf_pass4<double><<<grid, kThreads, 0, s>>>(a);
-    }
+  if (op.desc.prec == GSF_F32)
+    gf_apply_typed<float>(op, scratch, form, m, (const float*)x, ldx, (float*)y, ldy, s);
+  else
+    gf_apply_typed<double>(op, scratch, form, m, (const double*)x, ldx, (double*)y, ldy, s);
+  return hipGetLastError() == hipSuccess ? GSF_OK : GSF_EDEVICE;
+}
+
+gsf_status launch_gf_build(const Operator& op, const void* guidance, hipStream_t s) {
+  const GfGeom geo{(int)op.rows, (int)op.cols, op.desc.radius};
+  if (op.desc.prec == GSF_F32) {
+    GfStats<float> p{(const float*)guidance, (float*)op.g, (float*)op.mu, (float*)op.inv,
+                     (float*)op.sqd, (float*)op.diag, op.deg, op.desc.gf_eps, gf_omega(op)};
+    gf_box_kernel<GfStats<float>><<<gf_grid(op), kGfLanes, 0, s>>>(p, geo);
+  } else {
+    GfStats<double> p{(const double*)guidance, (double*)op.g, (double*)op.mu, (double*)op.inv,
+                      (double*)op.sqd, (double*)op.diag, op.deg, op.desc.gf_eps, gf_omega(op)};
+    gf_box_kernel<GfStats<double>><<<gf_grid(op), kGfLanes, 0, s>>>(p, geo);
   }
   return hipGetLastError() == hipSuccess ? GSF_OK : GSF_EDEVICE;
 }

@@ -93,53 +93,9 @@ __global__ void __launch_bounds__(kThreads) bf_fold_kernel(const T* __restrict__
   }
 }
 
-struct GfParams {
-  int64_t n, rows, cols;
-  int radius, ndim;
-  double eps, omega;
-};
 
 // K3: mu_k = mean of g over the truncated window, inv_k = 1/(corr_g - mu^2 + eps)
 // (Algorithm 1, mean_g, corr_g, var_g), d_k = N_k/|w|, sqrt(d_k); copy of g.
-template <typename T>
-__global__ void __launch_bounds__(kThreads) gf_stats_kernel(const T* __restrict__ g, T* __restrict__ gcopy,
-                                                            T* __restrict__ mu, T* __restrict__ inv,
-                                                            T* __restrict__ sqd, double* __restrict__ deg,
-                                                            GfParams p) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= p.n) return;
-  const int r = p.radius;
-  double s1 = 0.0, s2 = 0.0, cnt = 0.0;
-  if (p.ndim == 1) {
-    const int64_t lo = k - r < 0 ? 0 : k - r, hi = k + r >= p.n ? p.n - 1 : k + r;
-    for (int64_t j = lo; j <= hi; ++j) {
-      const double v = (double)g[j];
-      s1 += v;
-      s2 += v * v;
-    }
-    cnt = (double)(hi - lo + 1);
-  } else {
-    const int64_t y = k / p.cols, x = k - y * p.cols;
-    const int64_t y0 = y - r < 0 ? 0 : y - r, y1 = y + r >= p.rows ? p.rows - 1 : y + r;
-    const int64_t x0 = x - r < 0 ? 0 : x - r, x1 = x + r >= p.cols ? p.cols - 1 : x + r;
-    for (int64_t yy = y0; yy <= y1; ++yy)
-      for (int64_t xx = x0; xx <= x1; ++xx) {
-        const double v = (double)g[yy * p.cols + xx];
-        s1 += v;
-        s2 += v * v;
-      }
-    cnt = (double)((y1 - y0 + 1) * (x1 - x0 + 1));
-  }
-  const double m = s1 / cnt;
-  const double var = s2 / cnt - m * m;
-  mu[k] = (T)m;
-  inv[k] = (T)(1.0 / (var + p.eps));
-  const double d = cnt / p.omega;
-  deg[k] = d;
-  sqd[k] = (T)sqrt(d);
-  gcopy[k] = g[k];
-}
-
 inline double inv_two_sigma2(double s) { return std::isinf(s) ? 0.0 : 1.0 / (2.0 * s * s); }
 
 }  // namespace
@@ -156,21 +112,6 @@ gsf_status launch_bf_build(const Operator& op, const void* guidance, hipStream_t
     bf_degree_kernel<double><<<grid, kThreads, 0, s>>>((const double*)guidance, op.deg, p);
     bf_fold_kernel<double><<<grid, kThreads, 0, s>>>((const double*)guidance, op.deg, (double*)op.planes,
                                                      (double*)op.diag, (double*)op.sqd, p);
-  }
-  return hipGetLastError() == hipSuccess ? GSF_OK : GSF_EDEVICE;
-}
-
-gsf_status launch_gf_build(const Operator& op, const void* guidance, hipStream_t s) {
-  const double omega = op.desc.ndim == 1 ? (double)(2 * op.desc.radius + 1)
-                                         : (double)((2 * op.desc.radius + 1) * (2 * op.desc.radius + 1));
-  GfParams p{op.n, op.rows, op.cols, op.desc.radius, op.desc.ndim, op.desc.gf_eps, omega};
-  const unsigned grid = (unsigned)((op.n + kThreads - 1) / kThreads);
-  if (op.desc.prec == GSF_F32) {
-    gf_stats_kernel<float><<<grid, kThreads, 0, s>>>((const float*)guidance, (float*)op.g, (float*)op.mu,
-                                                     (float*)op.inv, (float*)op.sqd, op.deg, p);
-  } else {
-    gf_stats_kernel<double><<<grid, kThreads, 0, s>>>((const double*)guidance, (double*)op.g, (double*)op.mu,
-                                                      (double*)op.inv, (double*)op.sqd, op.deg, p);
   }
   return hipGetLastError() == hipSuccess ? GSF_OK : GSF_EDEVICE;
 }
