@@ -23,13 +23,14 @@ namespace gsf {
 namespace {
 
 constexpr int kGfLanes = 64;   // one wave per workgroup; lane = halo column
-constexpr int kGfRows = 64;    // output rows per workgroup
+constexpr int kGfRowsMax = 64;  // output rows per workgroup (fewer on small grids)
 
 // 32-bit indices: the operator build rejects GF grids of 2^27 points or more,
 // so point * 16 fits.
 struct GfGeom {
   int rows, cols;
   int r;
+  int rb;  // output rows per workgroup
 };
 
 __device__ __forceinline__ int win_count(int v, int len, int r) {
@@ -43,7 +44,7 @@ __device__ __forceinline__ int win_count(int v, int len, int r) {
 __device__ __forceinline__ void wave_lds_fence() { __asm__ volatile("" ::: "memory"); }
 
 // One wave owns a strip of 64 - 2r output columns (64 halo columns, one per
-// lane) and kGfRows rows.  Lane l keeps the FP64 running vertical window sums
+// lane) and g.rb rows (8..64).  Lane l keeps the FP64 running vertical window sums
 // of column c0 - r + l for the 2M channels (P::M groups of two); per row it
 // adds the entering row, writes its sums to the wave's LDS row, and then
 // takes the horizontal window sums as lane (group, run of consecutive output
@@ -65,8 +66,8 @@ __global__ void __launch_bounds__(kGfLanes) gf_box_kernel(P p, GfGeom g) {
   const int r = g.r, ow = kGfLanes - 2 * r;
   const int lane = threadIdx.x;
   const int c0 = (int)blockIdx.x * ow;
-  const int y0 = (int)blockIdx.y * kGfRows;
-  const int y1 = y0 + kGfRows < g.rows ? y0 + kGfRows : g.rows;
+  const int y0 = (int)blockIdx.y * g.rb;
+  const int y1 = y0 + g.rb < g.rows ? y0 + g.rb : g.rows;
   // column role
   const int gc = c0 - r + lane;
   const bool cok = gc >= 0 && gc < g.cols;
@@ -291,9 +292,19 @@ struct GfStats {
   }
 };
 
-dim3 gf_grid(const Operator& op) {
+// Rows per workgroup: as many as possible (the 2r warm-up rows are amortised)
+// while the grid still has about 2048 waves to hide memory latency.
+GfGeom gf_geom(const Operator& op) {
   const int ow = kGfLanes - 2 * op.desc.radius;
-  return dim3((unsigned)((op.cols + ow - 1) / ow), (unsigned)((op.rows + kGfRows - 1) / kGfRows));
+  const int64_t strips = (op.cols + ow - 1) / ow;
+  int64_t rb = (op.rows * strips + 2047) / 2048;
+  rb = rb < 8 ? 8 : (rb > kGfRowsMax ? kGfRowsMax : rb);
+  return GfGeom{(int)op.rows, (int)op.cols, op.desc.radius, (int)rb};
+}
+
+dim3 gf_grid(const Operator& op, const GfGeom& g) {
+  const int ow = kGfLanes - 2 * op.desc.radius;
+  return dim3((unsigned)((op.cols + ow - 1) / ow), (unsigned)((op.rows + g.rb - 1) / g.rb));
 }
 
 double gf_omega(const Operator& op) {
@@ -304,16 +315,16 @@ double gf_omega(const Operator& op) {
 template <typename T, int M>
 void gf_apply_group(const Operator& op, T* ab, int form, const T* x, int64_t ldx, T* y, int64_t ldy,
                     hipStream_t s) {
-  const GfGeom geo{(int)op.rows, (int)op.cols, op.desc.radius};
+  const GfGeom geo = gf_geom(op);
   if (form == GSF_FORM_RW) {
     GfStage1<T, M, false> p1{x, (int)ldx, (const T*)op.g, nullptr, (const T*)op.mu, (const T*)op.inv, ab};
-    gf_box_kernel<GfStage1<T, M, false>><<<gf_grid(op), kGfLanes, 0, s>>>(p1, geo);
+    gf_box_kernel<GfStage1<T, M, false>><<<gf_grid(op, geo), kGfLanes, 0, s>>>(p1, geo);
   } else {
     GfStage1<T, M, true> p1{x, (int)ldx, (const T*)op.g, (const T*)op.diag, (const T*)op.mu, (const T*)op.inv, ab};
-    gf_box_kernel<GfStage1<T, M, true>><<<gf_grid(op), kGfLanes, 0, s>>>(p1, geo);
+    gf_box_kernel<GfStage1<T, M, true>><<<gf_grid(op, geo), kGfLanes, 0, s>>>(p1, geo);
   }
   GfStage2<T, M> p2{ab, (const T*)op.g, x, (int)ldx, y, (int)ldy, form, 1.0 / sqrt(gf_omega(op))};
-  gf_box_kernel<GfStage2<T, M>><<<gf_grid(op), kGfLanes, 0, s>>>(p2, geo);
+  gf_box_kernel<GfStage2<T, M>><<<gf_grid(op, geo), kGfLanes, 0, s>>>(p2, geo);
 }
 
 template <typename T>
@@ -352,15 +363,15 @@ gsf_status launch_gf_apply(const Operator& op, void* scratch, int form, int m, c
 }
 
 gsf_status launch_gf_build(const Operator& op, const void* guidance, hipStream_t s) {
-  const GfGeom geo{(int)op.rows, (int)op.cols, op.desc.radius};
+  const GfGeom geo = gf_geom(op);
   if (op.desc.prec == GSF_F32) {
     GfStats<float> p{(const float*)guidance, (float*)op.g, (float*)op.mu, (float*)op.inv,
                      (float*)op.sqd, (float*)op.diag, op.deg, op.desc.gf_eps, gf_omega(op)};
-    gf_box_kernel<GfStats<float>><<<gf_grid(op), kGfLanes, 0, s>>>(p, geo);
+    gf_box_kernel<GfStats<float>><<<gf_grid(op, geo), kGfLanes, 0, s>>>(p, geo);
   } else {
     GfStats<double> p{(const double*)guidance, (double*)op.g, (double*)op.mu, (double*)op.inv,
                       (double*)op.sqd, (double*)op.diag, op.deg, op.desc.gf_eps, gf_omega(op)};
-    gf_box_kernel<GfStats<double>><<<gf_grid(op), kGfLanes, 0, s>>>(p, geo);
+    gf_box_kernel<GfStats<double>><<<gf_grid(op, geo), kGfLanes, 0, s>>>(p, geo);
   }
   return hipGetLastError() == hipSuccess ? GSF_OK : GSF_EDEVICE;
 }
