@@ -68,7 +68,8 @@ typedef enum { GSF_METHOD_POWER = 0, GSF_METHOD_CG = 1, GSF_METHOD_LOBPCG = 2 } 
  *            W_ij = (1/|w|) sum_{k: i,j in w_k} (1/N_k)(1 + (g_i-mu_k)(g_j-mu_k)/(s_k^2+eps))
  *            (eq. (6) in the interior) has row sums d_i = N_i/|w|.
  *  ndim    1 (dims[0] = n) or 2 (dims[0] = rows H, dims[1] = columns W);
- *          a GF operator has fewer than 2^27 points.
+ *          a BF operator has fewer than 2^30 points, a GF operator fewer
+ *          than 2^27.
  *  prec    element type of the guidance, of all vectors and of the stored
  *          operator.  Weights and window statistics are always computed in
  *          FP64 and rounded once to this type.
@@ -94,7 +95,9 @@ typedef struct gsf_operator gsf_operator;   /* opaque host handle */
  *      o (half-window offsets in the order: 1D o = 1..r; 2D (dy, dx) with
  *      dy = 0, dx = 1..r, then dy = 1..r, dx = -r..r) stores the weight
  *      w_{i,i+o} of eq. (2) at index i (0 where i+o is outside the grid);
- *      each undirected edge is stored once.  `inv_sqrt_d` holds 1/sqrt(d_i).
+ *      each undirected edge is stored once.  Plane q starts at
+ *      planes + q * plane_stride and is preceded by r*W + r (2D) or r (1D)
+ *      zeros.  `inv_sqrt_d` holds 1/sqrt(d_i).
  *      The apply evaluates L_sym z = D^-1/2 L D^-1/2 z as
  *      (1/sqrt(d_i)) sum_j w_ij (u_i - u_j) with u = D^-1/2 z, and
  *      N z = z - L_sym z.
@@ -115,6 +118,7 @@ typedef struct {
   const void* guidance;
   const void* mu;
   const void* inv;
+  int64_t plane_stride;  /* BF: elements between the starts of consecutive planes */
 } gsf_operator_layout;
 
 /* CG result summary (z-space 2-norms, FP64). */

@@ -74,6 +74,7 @@ gsf_status validate_desc(const gsf_operator_desc* d) {
   if (d->ndim == 2 && (d->dims[0] > (int64_t)1 << 30 || d->dims[1] > (int64_t)1 << 30)) return GSF_EINVAL;
   if (n > ((int64_t)1 << 34)) return GSF_EINVAL;
   if (d->kind == GSF_BF) {
+    if (n >= ((int64_t)1 << 30)) return GSF_EINVAL;  // the BF apply indexes planes with 32 bits
     if (!(d->sigma_d > 0.0) || std::isnan(d->sigma_d)) return GSF_EINVAL;
     if (!(d->sigma_r > 0.0) || std::isnan(d->sigma_r)) return GSF_EINVAL;
   } else {
@@ -84,7 +85,8 @@ gsf_status validate_desc(const gsf_operator_desc* d) {
 }
 
 // Operator workspace layout, in order, each region 256-byte aligned:
-//   BF: planes (nplanes*n), diag (n), sqd (n), deg (n doubles)
+//   BF: planes (nplanes padded planes, see layout_operator), diag (n), sqd (n),
+//       deg (n doubles)
 //   GF: g (n), mu (n), inv (n), sqd (n), diag (n), deg (n doubles), 16 scratch
 //       planes (n): (a, b) of up to 8 columns for the apply
 size_t layout_operator(const gsf_operator_desc* d, Operator* op, char* base) {
@@ -109,13 +111,21 @@ size_t layout_operator(const gsf_operator_desc* d, Operator* op, char* base) {
   if (d->kind == GSF_BF) {
     const int k = d->ndim == 1 ? 2 * d->radius + 1 : (2 * d->radius + 1) * (2 * d->radius + 1);
     const int np = (k - 1) / 2;
-    void* planes = take(align_up((size_t)np * n * elem, kAlign));
+    // every plane is preceded by ppad zeros, so that the apply's mirrored
+    // reads w_{i-o,i} above the first row (or before the first sample) read
+    // zeros instead of branching
+    const int64_t cols = d->ndim == 1 ? d->dims[0] : d->dims[1];
+    const int64_t ppad = d->ndim == 1 ? d->radius : (int64_t)d->radius * cols + d->radius;
+    const int64_t pstride = (int64_t)align_up((size_t)(n + ppad), 64);
+    void* planes = take(align_up((size_t)(np * pstride + ppad) * elem, kAlign));
     void* diag = take(plane);
     void* sqd = take(plane);
     void* deg = take(dplane);
     if (op) {
       op->nplanes = np;
       op->planes = planes;
+      op->pstride = pstride;
+      op->ppad = ppad;
       op->diag = diag;
       op->sqd = sqd;
       op->deg = (double*)deg;
@@ -403,7 +413,8 @@ gsf_status gsf_operator_get_layout(const gsf_operator* h, gsf_operator_layout* o
   out->radius = op.desc.radius;
   out->n = op.n;
   out->nplanes = op.nplanes;
-  out->planes = op.desc.kind == GSF_BF ? op.planes : nullptr;
+  out->planes = op.desc.kind == GSF_BF ? (const char*)op.planes + op.ppad * op.elem : nullptr;
+  out->plane_stride = op.desc.kind == GSF_BF ? op.pstride : 0;
   out->inv_sqrt_d = op.diag;
   out->sqrt_d = op.sqd;
   out->degree = op.deg;

@@ -40,6 +40,8 @@ gsf_status launch_bf_apply_rpt(const Operator& op, int form, int m, const void* 
                                int64_t ldy, double* dot, int* nparts, int rpt_override, hipStream_t s) {
   bfk::ApplyArgs a{};
   a.planes = op.planes;
+  a.pstride = op.pstride;
+  a.ppad = op.ppad;
   a.isqd = op.diag;
   a.ldx = ldx;
   a.ldy = ldy;

@@ -8,7 +8,11 @@
 //
 // Each undirected edge is stored once, at its lower endpoint, in half-window
 // planes w[o][i] = w_{i,i+o}; a point reads its own plane entry and, mirrored,
-// the entry of the point i-o for the edge (i-o, i).
+// the entry of the point i-o for the edge (i-o, i).  Every weight read is
+// unconditional: a mirrored read above the first row (before the first
+// sample) lands in the zeros that precede each plane, and one that wraps
+// around a row end lands on an entry whose partner is off the grid, which is
+// zero too.  Plane offsets are 32-bit per lane from a uniform plane base.
 //
 // Tiling: a workgroup of 256 threads owns a 64-wide tile of TY rows (2D) or
 // 256*RPT consecutive samples (1D).  u for the tile plus an r-wide halo is
@@ -22,7 +26,9 @@ namespace gsf {
 namespace bfk {
 
 struct ApplyArgs {
-  const void* planes;
+  const void* planes;  // padded start of plane 0
+  int64_t pstride;     // elements between consecutive planes' padded starts
+  int64_t ppad;        // zeros before each plane's data
   const void* isqd;  // 1/sqrt(d)
   const void* x;
   void* y;
@@ -122,35 +128,43 @@ __global__ void __launch_bounds__(kThreads) bf_apply2d_kernel(ApplyArgs a) {
       ui[c] = uc[c];
       acc[c] = T(0);
     }
+    // byte offsets of this point in a padded plane (unsigned 32-bit, from a
+    // uniform plane base)
+    const uint32_t pv = ((uint32_t)p + (uint32_t)a.ppad) * (uint32_t)sizeof(T);
+    const char* __restrict__ qb = (const char*)planes;  // padded start of the current plane
+    const size_t qstep = (size_t)a.pstride * sizeof(T);
     // dy = 0: planes 0..R-1, offsets (0, dx)
-    const T* __restrict__ pp = planes + p;
 #pragma unroll
     for (int dx = 1; dx <= R; ++dx) {
-      const T wo = valid ? pp[0] : T(0);
-      const T wm = (valid && gx - dx >= 0) ? pp[-dx] : T(0);
-      pp += n;
+      const T wo = *(const T*)(qb + pv);
+      const T wm = *(const T*)(qb + (pv - (uint32_t)(dx * (int)sizeof(T))));
+      qb += qstep;
       const T* uo = uc + dx * M;
       const T* um = uc - dx * M;
 #pragma unroll
-      for (int c = 0; c < M; ++c) acc[c] += wo * (ui[c] - uo[c]) + wm * (ui[c] - um[c]);
+      for (int c = 0; c < M; ++c) {
+        acc[c] = fma(wo, ui[c] - uo[c], acc[c]);
+        acc[c] = fma(wm, ui[c] - um[c], acc[c]);
+      }
     }
     // dy = 1..R, dx = -R..R: one row of 2R+1 planes per dy
 #pragma unroll 1
     for (int dy = 1; dy <= R; ++dy) {
-      const bool up = valid && gy - dy >= 0;
-      const int64_t mshift = (int64_t)dy * W;
+      const uint32_t mrow = pv - (uint32_t)(dy * (int)W) * (uint32_t)sizeof(T);
       const T* urow = uc + dy * LW * M;
       const T* umrow = uc - dy * LW * M;
 #pragma unroll(DxUnroll<T, M>::value)
       for (int dx = -R; dx <= R; ++dx) {
-        const T wo = valid ? pp[0] : T(0);
-        const bool mok = up && gx - dx >= 0 && gx - dx < W;
-        const T wm = mok ? pp[-mshift - dx] : T(0);
-        pp += n;
+        const T wo = *(const T*)(qb + pv);
+        const T wm = *(const T*)(qb + (mrow - (uint32_t)(dx * (int)sizeof(T))));
+        qb += qstep;
         const T* uo = urow + dx * M;
         const T* um = umrow - dx * M;
 #pragma unroll
-        for (int c = 0; c < M; ++c) acc[c] += wo * (ui[c] - uo[c]) + wm * (ui[c] - um[c]);
+        for (int c = 0; c < M; ++c) {
+          acc[c] = fma(wo, ui[c] - uo[c], acc[c]);
+          acc[c] = fma(wm, ui[c] - um[c], acc[c]);
+        }
       }
     }
     if (valid) {
@@ -209,14 +223,19 @@ __global__ void __launch_bounds__(kThreads) bf_apply1d_kernel(ApplyArgs a) {
       ui[c] = uc[c];
       acc[c] = T(0);
     }
-    const T* __restrict__ pp = planes + p;
+    const uint32_t pv = ((uint32_t)p + (uint32_t)a.ppad) * (uint32_t)sizeof(T);
+    const char* __restrict__ qb = (const char*)planes;
+    const size_t qstep = (size_t)a.pstride * sizeof(T);
 #pragma unroll
     for (int o = 1; o <= R; ++o) {
-      const T wo = valid ? pp[0] : T(0);
-      const T wm = (valid && p - o >= 0) ? pp[-o] : T(0);
-      pp += n;
+      const T wo = *(const T*)(qb + pv);
+      const T wm = *(const T*)(qb + (pv - (uint32_t)(o * (int)sizeof(T))));
+      qb += qstep;
 #pragma unroll
-      for (int c = 0; c < M; ++c) acc[c] += wo * (ui[c] - uc[o * M + c]) + wm * (ui[c] - uc[-o * M + c]);
+      for (int c = 0; c < M; ++c) {
+        acc[c] = fma(wo, ui[c] - uc[o * M + c], acc[c]);
+        acc[c] = fma(wm, ui[c] - uc[-o * M + c], acc[c]);
+      }
     }
     if (valid) {
       T xg[M], out[M];

@@ -57,12 +57,26 @@ __global__ void __launch_bounds__(kThreads) bf_degree_kernel(const T* __restrict
 // K2: half-window planes of the symmetric weights w_{i,i+o} (0 off the grid),
 // 1/sqrt(d_i) and sqrt(d_i).  Plane order: 1D o = 1..r; 2D (0, 1..r) then
 // dy = 1..r with dx = -r..r.
+// Plane q's data starts at planes + ppad + q * pstride; every element of the
+// plane region that is not a weight (the ppad zeros before each plane and the
+// tail up to the next one) is written as zero: thread i covers index i of
+// every plane's stride window, threads i < ppad also the region's tail.
 template <typename T>
 __global__ void __launch_bounds__(kThreads) bf_fold_kernel(const T* __restrict__ g, const double* __restrict__ deg,
                                                            T* __restrict__ planes, T* __restrict__ diag,
-                                                           T* __restrict__ sqd, BfParams p) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= p.n) return;
+                                                           T* __restrict__ sqd, BfParams p, int64_t pstride,
+                                                           int64_t ppad, int nplanes) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= pstride) return;
+  if (t < ppad)
+    planes[(int64_t)nplanes * pstride + t] = T(0);
+  // region index t of every plane window: data point t - ppad, or a pad
+  const int64_t i = t - ppad;
+  if (i < 0 || i >= p.n) {
+    for (int q = 0; q < nplanes; ++q) planes[(int64_t)q * pstride + t] = T(0);
+    return;
+  }
+  planes += ppad;
   const int r = p.radius;
   const double gi = (double)g[i];
   const double di = deg[i];
@@ -74,7 +88,7 @@ __global__ void __launch_bounds__(kThreads) bf_fold_kernel(const T* __restrict__
       const int64_t j = i + o;
       double v = 0.0;
       if (j < p.n) v = bf_weight(gi, (double)g[j], o * o, p);
-      planes[(int64_t)q * p.n + i] = (T)v;
+      planes[(int64_t)q * pstride + i] = (T)v;
     }
   } else {
     const int64_t y = i / p.cols, x = i - y * p.cols;
@@ -87,7 +101,7 @@ __global__ void __launch_bounds__(kThreads) bf_fold_kernel(const T* __restrict__
           const int64_t j = yy * p.cols + xx;
           v = bf_weight(gi, (double)g[j], dy * dy + dx * dx, p);
         }
-        planes[(int64_t)q * p.n + i] = (T)v;
+        planes[(int64_t)q * pstride + i] = (T)v;
       }
     }
   }
@@ -104,14 +118,17 @@ gsf_status launch_bf_build(const Operator& op, const void* guidance, hipStream_t
   BfParams p{op.n, op.rows, op.cols, op.desc.radius, op.desc.ndim, inv_two_sigma2(op.desc.sigma_d),
              inv_two_sigma2(op.desc.sigma_r)};
   const unsigned grid = (unsigned)((op.n + kThreads - 1) / kThreads);
+  const unsigned fgrid = (unsigned)((op.pstride + kThreads - 1) / kThreads);
   if (op.desc.prec == GSF_F32) {
     bf_degree_kernel<float><<<grid, kThreads, 0, s>>>((const float*)guidance, op.deg, p);
-    bf_fold_kernel<float><<<grid, kThreads, 0, s>>>((const float*)guidance, op.deg, (float*)op.planes,
-                                                    (float*)op.diag, (float*)op.sqd, p);
+    bf_fold_kernel<float><<<fgrid, kThreads, 0, s>>>((const float*)guidance, op.deg, (float*)op.planes,
+                                                     (float*)op.diag, (float*)op.sqd, p, op.pstride, op.ppad,
+                                                     op.nplanes);
   } else {
     bf_degree_kernel<double><<<grid, kThreads, 0, s>>>((const double*)guidance, op.deg, p);
-    bf_fold_kernel<double><<<grid, kThreads, 0, s>>>((const double*)guidance, op.deg, (double*)op.planes,
-                                                     (double*)op.diag, (double*)op.sqd, p);
+    bf_fold_kernel<double><<<fgrid, kThreads, 0, s>>>((const double*)guidance, op.deg, (double*)op.planes,
+                                                      (double*)op.diag, (double*)op.sqd, p, op.pstride, op.ppad,
+                                                      op.nplanes);
   }
   return hipGetLastError() == hipSuccess ? GSF_OK : GSF_EDEVICE;
 }

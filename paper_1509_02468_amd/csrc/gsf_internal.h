@@ -23,7 +23,9 @@ struct Operator {
   int64_t cols;     // 2D: W, 1D: n
   int nplanes;      // BF half-window planes
   size_t elem;      // sizeof element type
-  void* planes;     // BF: nplanes * n symmetric weights w_{i,i+o}
+  void* planes;     // BF: padded start of plane 0 (see pstride, ppad); GF: apply scratch
+  int64_t pstride;  // BF: elements from one plane's padded start to the next
+  int64_t ppad;     // BF: zeros before each plane's data (r W + r in 2D, r in 1D)
   void* diag;       // BF: 1/sqrt(d)
   void* sqd;        // sqrt(d)
   double* deg;      // d (FP64)

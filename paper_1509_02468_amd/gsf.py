@@ -37,7 +37,7 @@ class OperatorLayout(ctypes.Structure):
                 ("radius", ctypes.c_int32), ("n", ctypes.c_int64), ("nplanes", ctypes.c_int32),
                 ("planes", ctypes.c_void_p), ("inv_sqrt_d", ctypes.c_void_p), ("sqrt_d", ctypes.c_void_p),
                 ("degree", ctypes.c_void_p), ("guidance", ctypes.c_void_p), ("mu", ctypes.c_void_p),
-                ("inv", ctypes.c_void_p)]
+                ("inv", ctypes.c_void_p), ("plane_stride", ctypes.c_int64)]
 
 
 class CgInfo(ctypes.Structure):
@@ -278,8 +278,11 @@ class Operator:
         return self.ws[off:off + count * esz].view(dtype).clone()
 
     def planes(self):
+        torch = _torch()
         lay = self.layout()
-        return self._view(lay.planes, lay.nplanes * self.n, self.dtype).reshape(lay.nplanes, self.n)
+        esz = torch.tensor([], dtype=self.dtype).element_size()
+        return torch.stack([self._view(lay.planes + q * lay.plane_stride * esz, self.n, self.dtype)
+                            for q in range(lay.nplanes)])
 
     def inv_sqrt_d(self):
         return self._view(self.layout().inv_sqrt_d, self.n, self.dtype)
