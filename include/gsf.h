@@ -310,6 +310,11 @@ gsf_status gsf_lobpcg_residual(const gsf_operator* op, int m, const void* X, con
  *   Synchronizes the stream. */
 gsf_status gsf_tune_apply(const gsf_operator* op, int m, const void* x, void* y, int reps,
                           int* best_rpt, float* times_us, void* stream);
+/* gsf_set_apply_rows: sets the BF apply's rows per thread (1, 2 or 4) for
+ *   block width m of this operator's class (precision, dimension, radius,
+ *   width, size class), as gsf_tune_apply would; process-wide.  GSF_EINVAL
+ *   for other values or a GF operator. */
+gsf_status gsf_set_apply_rows(const gsf_operator* op, int m, int rows_per_thread);
 
 /* ---- batching ----------------------------------------------------------------
  * Many independent items (each its own operator, signal and solver) filtered

@@ -825,4 +825,12 @@ gsf_status gsf_lobpcg_residual(const gsf_operator* h, int m, const void* X, cons
   return launch_residual(op.desc.prec, X, R, op.n, m, theta, s);
 }
 
+gsf_status gsf_set_apply_rows(const gsf_operator* h, int m, int rows_per_thread) {
+  if (h == nullptr || m < 1 || m > kMaxBlock || h->op.desc.kind != GSF_BF) return GSF_EINVAL;
+  if (rows_per_thread != 1 && rows_per_thread != 2 && rows_per_thread != 4) return GSF_EINVAL;
+  const int w = m >= 8 ? 8 : (m >= 4 ? 4 : m);
+  bf_set_rpt(h->op, w, rows_per_thread);
+  return GSF_OK;
+}
+
 }  // extern "C"

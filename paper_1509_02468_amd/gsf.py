@@ -98,6 +98,7 @@ def load_library(path: str = LIB_PATH):
         "gsf_rayleigh_ritz": ([i32, i32, vp, vp, dbl, dbl, vp, vp, vp, vp, vp, sz, vp], i32),
         "gsf_rr_workspace_bytes": ([], sz),
         "gsf_tune_apply": ([vp, i32, vp, vp, i32, P(ctypes.c_int), P(ctypes.c_float), vp], i32),
+        "gsf_set_apply_rows": ([vp, i32, i32], i32),
         "gsf_batch_workspace_bytes": ([P(BatchItem), i32, P(sz)], i32),
         "gsf_batch_create": ([P(BatchItem), i32, vp, sz, i32, P(vp)], i32),
         "gsf_batch_run": ([vp, vp], i32),
@@ -318,6 +319,10 @@ class Operator:
         _check(_lib.gsf_tune_apply(self.handle, m, _ptr(x), _ptr(y), reps, ctypes.byref(best), times,
                                    _stream(stream)), "tune_apply")
         return best.value, list(times)
+
+    def set_apply_rows(self, m, rows_per_thread):
+        """Pin the BF apply tile height for block width m (see gsf_set_apply_rows)."""
+        _check(_lib.gsf_set_apply_rows(self.handle, m, rows_per_thread), "set_apply_rows")
 
     def workspace(self, method, m=1):
         torch = _torch()

@@ -212,3 +212,39 @@ def test_generator_structure():
     c1, _ = scene_2d(64, 64, 0.05, 7)
     c2, _ = scene_2d(64, 64, 0.05, 7)
     assert np.array_equal(c1, c2)
+
+
+# ------------------------------------------------------------------ pointwise forms
+@pytest.mark.parametrize("shape", [(9, 11), (40,), (6, 5)])
+def test_pointwise_bf_lsym_matches_full_operator(shape):
+    """The point-by-point L_sym of eq. (2) equals the sparse-matrix oracle at
+    every point, borders and corners included."""
+    from oracle.pointwise import bf_lsym_at
+    from synth import piecewise_constant_1d
+    g = scene_2d(shape[0], shape[1], 0.05, 31)[1] if len(shape) == 2 else piecewise_constant_1d(shape[0], 0.1, 31)[1]
+    op = oracle.build_operator("bf", g, 2, 2.0, 0.15)
+    z = np.random.default_rng(32).standard_normal(op.n)
+    ref = op.apply_lsym(z)
+    got = bf_lsym_at(g, z, np.arange(op.n), 2, 2.0, 0.15)
+    np.testing.assert_allclose(got, ref, rtol=1e-12, atol=1e-13)
+
+
+@pytest.mark.parametrize("shape", [(9, 10), (30,)])
+def test_pointwise_gf_lsym_matches_full_operator(shape):
+    """The point-by-point L_sym of Algorithm 1 equals the oracle's operator."""
+    from oracle.pointwise import gf_lsym_at
+    from synth import piecewise_constant_1d
+    g = scene_2d(shape[0], shape[1], 0.05, 33)[1] if len(shape) == 2 else piecewise_constant_1d(shape[0], 0.1, 33)[1]
+    op = oracle.build_operator("gf", g, 2, eps=1e-2)
+    z = np.random.default_rng(34).standard_normal(op.n)
+    ref = op.apply_lsym(z)
+    got = gf_lsym_at(g, z, np.arange(op.n), 2, 1e-2)
+    np.testing.assert_allclose(got, ref, rtol=1e-11, atol=1e-12)
+
+
+def test_sample_points_cover_corners():
+    from oracle.pointwise import sample_points
+    pts = sample_points((50, 70), 40, 1)
+    for c in (0, 69, 49 * 70, 50 * 70 - 1):
+        assert c in pts
+    assert len(set(pts.tolist())) == len(pts) and pts.max() < 3500
