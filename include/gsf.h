@@ -68,8 +68,10 @@ typedef enum { GSF_METHOD_POWER = 0, GSF_METHOD_CG = 1, GSF_METHOD_LOBPCG = 2 } 
  *            W_ij = (1/|w|) sum_{k: i,j in w_k} (1/N_k)(1 + (g_i-mu_k)(g_j-mu_k)/(s_k^2+eps))
  *            (eq. (6) in the interior) has row sums d_i = N_i/|w|.
  *  ndim    1 (dims[0] = n) or 2 (dims[0] = rows H, dims[1] = columns W);
- *          a BF operator has fewer than 2^30 points, a GF operator fewer
- *          than 2^27.
+ *          a BF operator has fewer than 2^30 points and
+ *          (n + radius*(W+1)) * element size <= 2^32 bytes (2D; 1D:
+ *          (n + radius) * element size), so FP64 allows about 2^29 points;
+ *          a GF operator has fewer than 2^27 points.
  *  prec    element type of the guidance, of all vectors and of the stored
  *          operator.  Weights and window statistics are always computed in
  *          FP64 and rounded once to this type.

@@ -74,7 +74,11 @@ gsf_status validate_desc(const gsf_operator_desc* d) {
   if (d->ndim == 2 && (d->dims[0] > (int64_t)1 << 30 || d->dims[1] > (int64_t)1 << 30)) return GSF_EINVAL;
   if (n > ((int64_t)1 << 34)) return GSF_EINVAL;
   if (d->kind == GSF_BF) {
-    if (n >= ((int64_t)1 << 30)) return GSF_EINVAL;  // the BF apply indexes planes with 32 bits
+    // the BF apply addresses a padded plane with 32-bit byte offsets: the
+    // padded plane (ppad zeros, then n weights) must fit in 4 GiB
+    const int64_t ppad = d->ndim == 1 ? d->radius : (int64_t)d->radius * d->dims[1] + d->radius;
+    const int64_t elem = d->prec == GSF_F32 ? 4 : 8;
+    if (n >= ((int64_t)1 << 30) || (n + ppad) * elem > ((int64_t)1 << 32)) return GSF_EINVAL;
     if (!(d->sigma_d > 0.0) || std::isnan(d->sigma_d)) return GSF_EINVAL;
     if (!(d->sigma_r > 0.0) || std::isnan(d->sigma_r)) return GSF_EINVAL;
   } else {

@@ -68,6 +68,23 @@ def test_invalid_descriptors_rejected(lib, bad):
     assert lib.gsf_operator_workspace_bytes(ctypes.byref(_desc(**bad)), ctypes.byref(sz)) == 1
 
 
+def test_size_limits(lib):
+    """BF: fewer than 2^30 points and the padded plane addressable with 32-bit
+    byte offsets ((n + r (W + 1)) * element size <= 2^32); GF: fewer than 2^27."""
+    sz = ctypes.c_size_t()
+
+    def ok(**kw):
+        return lib.gsf_operator_workspace_bytes(ctypes.byref(_desc(**kw)), ctypes.byref(sz)) == 0
+    assert ok(dims=(1 << 14, (1 << 16) - 64), prec=0)         # 2^30 - 2^20 points, FP32
+    assert not ok(dims=(1 << 15, 1 << 15), prec=0)            # 2^30 points
+    assert ok(dims=(1 << 14, (1 << 15) - 64), prec=1)         # 2^29 - 2^20 points, FP64
+    assert not ok(dims=(1 << 14, (1 << 15) + 8), prec=1)      # above 2^29, FP64
+    assert not ok(ndim=1, dims=((1 << 29) + 1, 1), prec=1)
+    assert ok(ndim=1, dims=((1 << 29) - 8, 1), prec=1)
+    assert ok(kind=1, dims=(1 << 13, (1 << 14) - 1))
+    assert not ok(kind=1, dims=(1 << 13, 1 << 14))
+
+
 def test_build_rejects_small_workspace_and_nulls(lib):
     d = _desc()
     out = ctypes.c_void_p()
