@@ -156,7 +156,11 @@ struct MfmaAcc<double> {
 template <typename T, int NT>
 __global__ void __launch_bounds__(kThreads) gram_kernel(GramArgs g) {
   typedef typename MfmaAcc<T>::type acc_t;
-  constexpr int U = 8;  // point groups of 4 loaded ahead of their MFMAs
+  typedef const __attribute__((address_space(1))) T* gptr;
+  // groups of 4 points per stage (one MFMA k-step each); fewer for the wider
+  // tiles and FP64, whose stages hold more registers
+  constexpr int U = (NT == 1 && sizeof(T) == 4) ? 8 : 4;
+  constexpr int G = 4 * U;      // points per stage
   constexpr int ntb = NT == 1 ? 1 : 3, nta = NT == 1 ? 1 : 4;
   constexpr int nt = NT;
   __shared__ double wsum[4][4][64];  // one tile at a time: wave, register, lane
@@ -165,22 +169,26 @@ __global__ void __launch_bounds__(kThreads) gram_kernel(GramArgs g) {
   const int ns = g.ns, m = g.m;
   const int col = lane & 15, krow = lane >> 4;
 
-  // the S / AS column each lane feeds for tile row I (0 past the last column)
-  const T* sp[2] = {nullptr, nullptr};
-  const T* ap[2] = {nullptr, nullptr};
-  for (int I = 0; I < nt; ++I) {
+  // the S / AS column each lane feeds for tile row I; lanes past the last
+  // column read column 0 and feed zeros
+  gptr sp[2], ap[2];
+  bool live[2];
+#pragma unroll
+  for (int I = 0; I < 2; ++I) {
     const int c = 16 * I + col;
-    if (c < ns) {
-      const int b = c / m, j = c - (c / m) * m;
-      sp[I] = (const T*)g.S[b] + j;
-      ap[I] = (const T*)g.AS[b] + j;
-    }
+    live[I] = I < nt && c < ns;
+    const int cc = live[I] ? c : 0;
+    const int b = cc / m, j = cc - (cc / m) * m;
+    sp[I] = (gptr)g.S[b] + j;
+    ap[I] = (gptr)g.AS[b] + j;
   }
 
+  // FP32 partials move into FP64 every FL points (256); FP64 needs no flush
+  constexpr int FL = sizeof(T) == 4 ? 256 : 2 * G;
   const int64_t nw = (int64_t)gridDim.x * 4;
   const int64_t wid = (int64_t)blockIdx.x * 4 + wave;
   int64_t chunk = (g.n + nw - 1) / nw;
-  chunk = (chunk + 4 * U - 1) / (4 * U) * (4 * U);
+  chunk = (chunk + FL - 1) / FL * FL;
   const int64_t p_begin = wid * chunk;
   const int64_t p_end = (p_begin + chunk < g.n) ? p_begin + chunk : g.n;
 
@@ -199,55 +207,84 @@ __global__ void __launch_bounds__(kThreads) gram_kernel(GramArgs g) {
 #pragma unroll
   for (int t = 0; t < nta; ++t) acca[t] = acc_t{0, 0, 0, 0};
 
-  int steps = 0;
-  for (int64_t p0 = p_begin; p0 < p_end; p0 += 4 * U) {
-    T s0[U], s1[U], a0[U], a1[U];
+  // one stage: the U point groups starting at p0.  Every load is issued
+  // unconditionally (points past the end re-read p_begin); the 0/1 mask of a
+  // point (and of a column past ns) multiplies only the A operand of its
+  // MFMAs, when they run a stage later: A[i][k] = 0 removes point k from
+  // every product, and the tile entries of the dead B columns are never read.
+  // (Masking at load time lets the compiler sink the loads into branches or
+  // wait for them at once.)  A non-finite value at p_begin already makes the
+  // sums non-finite, so re-reading it changes nothing.
+  auto load = [&](int64_t p0, T (&s)[2][U], T (&a)[2][U], T (&mk)[2][U]) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int64_t p = p0 + 4 * u + krow;
       const bool ok = p < p_end;
-      s0[u] = (ok && sp[0]) ? sp[0][p * m] : T(0);
-      a0[u] = (ok && sp[0]) ? ap[0][p * m] : T(0);
-      s1[u] = (NT > 1 && ok && sp[1]) ? sp[1][p * m] : T(0);
-      a1[u] = (NT > 1 && ok && sp[1]) ? ap[1][p * m] : T(0);
+      const int64_t off = (ok ? p : p_begin) * m;
+#pragma unroll
+      for (int I = 0; I < nt; ++I) {
+        s[I][u] = sp[I][off];
+        a[I][u] = ap[I][off];
+        mk[I][u] = (ok && live[I]) ? T(1) : T(0);
+      }
     }
+  };
+  auto mfmas = [&](const T (&s)[2][U], const T (&a)[2][U], const T (&mk)[2][U]) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      accb[0] = MfmaAcc<T>::mfma(s0[u], s0[u], accb[0]);
-      acca[0] = MfmaAcc<T>::mfma(s0[u], a0[u], acca[0]);
+      const T s0m = s[0][u] * mk[0][u];
+      accb[0] = MfmaAcc<T>::mfma(s0m, s[0][u], accb[0]);
+      acca[0] = MfmaAcc<T>::mfma(s0m, a[0][u], acca[0]);
       if constexpr (NT > 1) {
-        accb[1] = MfmaAcc<T>::mfma(s0[u], s1[u], accb[1]);
-        accb[2] = MfmaAcc<T>::mfma(s1[u], s1[u], accb[2]);
-        acca[1] = MfmaAcc<T>::mfma(s0[u], a1[u], acca[1]);
-        acca[2] = MfmaAcc<T>::mfma(s1[u], a0[u], acca[2]);
-        acca[3] = MfmaAcc<T>::mfma(s1[u], a1[u], acca[3]);
+        const T s1m = s[1][u] * mk[1][u];
+        accb[1] = MfmaAcc<T>::mfma(s0m, s[1][u], accb[1]);
+        accb[2] = MfmaAcc<T>::mfma(s1m, s[1][u], accb[2]);
+        acca[1] = MfmaAcc<T>::mfma(s0m, a[1][u], acca[1]);
+        acca[2] = MfmaAcc<T>::mfma(s1m, a[0][u], acca[2]);
+        acca[3] = MfmaAcc<T>::mfma(s1m, a[1][u], acca[3]);
       }
     }
-    steps += U;
-    if (sizeof(T) == 4 && steps >= 64) {  // FP32: move each 256-point partial into FP64
-      steps = 0;
+  };
+  auto flush = [&]() {
 #pragma unroll
-      for (int t = 0; t < ntb; ++t) {
+    for (int t = 0; t < ntb; ++t) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) totb[t][v] += (double)accb[t][v];
-        accb[t] = acc_t{0, 0, 0, 0};
+      for (int v = 0; v < 4; ++v) totb[t][v] += (double)accb[t][v];
+      accb[t] = acc_t{0, 0, 0, 0};
+    }
+#pragma unroll
+    for (int t = 0; t < nta; ++t) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) tota[t][v] += (double)acca[t][v];
+      acca[t] = acc_t{0, 0, 0, 0};
+    }
+  };
+
+  // two register stages: the loads of the next stage are in flight while the
+  // MFMAs of the current one run
+  if (p_begin < p_end) {
+    T s0[2][U], a0[2][U], k0[2][U], s1[2][U], a1[2][U], k1[2][U];
+    load(p_begin, s0, a0, k0);
+    for (int64_t pf = p_begin; pf < p_end; pf += FL) {
+#pragma unroll
+      for (int q = 0; q < FL / (2 * G); ++q) {
+        const int64_t p0 = pf + (int64_t)q * 2 * G;
+        // the scheduling barriers keep each stage's loads ahead of the other
+        // stage's MFMAs (otherwise the mask products are hoisted next to the
+        // loads and wait for them)
+        load(p0 + G, s1, a1, k1);
+        __builtin_amdgcn_sched_barrier(0);
+        mfmas(s0, a0, k0);
+        __builtin_amdgcn_sched_barrier(0);
+        load(p0 + 2 * G, s0, a0, k0);
+        __builtin_amdgcn_sched_barrier(0);
+        mfmas(s1, a1, k1);
+        __builtin_amdgcn_sched_barrier(0);
       }
-#pragma unroll
-      for (int t = 0; t < nta; ++t) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) tota[t][v] += (double)acca[t][v];
-        acca[t] = acc_t{0, 0, 0, 0};
-      }
+      if (sizeof(T) == 4) flush();
     }
   }
-#pragma unroll
-  for (int t = 0; t < ntb; ++t)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) totb[t][v] += (double)accb[t][v];
-#pragma unroll
-  for (int t = 0; t < nta; ++t)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) tota[t][v] += (double)acca[t][v];
+  flush();
 
   // fixed-order sum over the 4 waves, one tile at a time.  Output layouts of
   // the two MFMA variants (entry e = i*16 + j of a tile):
@@ -280,8 +317,22 @@ __global__ void __launch_bounds__(kThreads) gram_kernel(GramArgs g) {
 }
 
 // ---------------------------------------------------------------------------
-// Rayleigh-Ritz on one workgroup (FP64)
+// Rayleigh-Ritz on one wave (FP64)
 // ---------------------------------------------------------------------------
+// The whole step runs on the first wave of the workgroup (the others only
+// help to load the Gram pair).  Lanes of one wave issue their LDS accesses in
+// program order and the LDS unit completes them in that order, so a store by
+// one lane is seen by a later load of another lane of the same wave: the
+// steps below need no workgroup barrier, only a compiler-level fence that
+// keeps LDS accesses in program order.
+__device__ __forceinline__ void wave_fence() { __asm__ volatile("" ::: "memory"); }
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
 // Reciprocal and reciprocal square root: the hardware approximations refined
 // by one Newton step (a few ulp), short dependency chains for the Jacobi
 // rotations.  The rotation stays orthogonal to rounding because c and s are
@@ -295,241 +346,269 @@ __device__ __forceinline__ double rsq_nr(double x) {
   const double e = fma(-x * r, r, 1.0);
   return fma(0.5 * r, e, r);
 }
+// Two Newton steps: full FP64 accuracy for the Cholesky pivots.
+__device__ __forceinline__ double rsq_nr2(double x) {
+  const double r = rsq_nr(x);
+  const double e = fma(-x * r, r, 1.0);
+  return fma(0.5 * r, e, r);
+}
 constexpr int KMAX = 24;
 constexpr int LD = KMAX + 1;
 
 struct RRShared {
-  double A[KMAX * LD];
+  double A[KMAX * LD];   // Gram pair as loaded (A = S^T A S, B = S^T S)
   double B[KMAX * LD];
-  double L[KMAX * LD];
-  double LK[KMAX * LD];  // compressed Cholesky factor of the kept columns
-  double M[KMAX * LD];
+  double SA[KMAX * LD];  // symmetrised and scaled to unit diag(B)
+  double SB[KMAX * LD];  // the same for B; work array of the Cholesky factorisation
+  double L[KMAX * LD];   // Cholesky factor (dropped columns zero)
+  double LK[KMAX * LD];  // compressed factor of the kept columns
+  double M[KMAX * LD];   // Jacobi matrix, two buffers
   double M2[KMAX * LD];
-  double V[KMAX * LD];
+  double V[KMAX * LD];   // accumulated rotations, two buffers
   double V2[KMAX * LD];
+  double Cs[KMAX * 8];   // output coefficients, staged
   double delta[KMAX];
-  double jself[KMAX + 1];
-  double joff[KMAX + 1];
-  double dnew[KMAX + 1];
-  int partner[KMAX + 1];
+  double rinv[KMAX];
+  double ev[KMAX];
   int good[KMAX];
   int kept[KMAX];
   int idx[KMAX];
   int order[KMAX];
-  double ev[KMAX];
-  double red[64];
-  double piv;
-  int keep;
-  int nk;
-  int stop;
 };
 
+// Players of pair `slot` in round `rnd` of the round-robin schedule over np
+// players (np even): player 0 stays, the others rotate.  p < q.
+__device__ __forceinline__ void rr_pair(int slot, int rnd, int np, int& p, int& q) {
+  const int n1 = np - 1;
+  int a = slot - 1 + rnd;
+  a = a >= n1 ? a - n1 : a;
+  int b = (np - 1 - slot) - 1 + rnd;
+  b = b >= n1 ? b - n1 : b;
+  const int pa = slot == 0 ? 0 : 1 + a, pb = 1 + b;
+  p = pa < pb ? pa : pb;
+  q = pa < pb ? pb : pa;
+}
+
+// The Jacobi rotation J = [[c, s], [-s, c]] (rows and columns p, q) that
+// annihilates m_pq of the symmetric 2 x 2 block [[m_pp, m_pq], [m_pq, m_qq]]:
+// with d = m_qq - m_pp, h = sqrt(d^2 + 4 m_pq^2) and u = d + sign(d) h (the
+// root t = 2 m_pq / u of t^2 + 2 theta t - 1 = 0 of smaller magnitude,
+// theta = d / (2 m_pq)), c = |u| / sqrt(2 h |u|) and s = sign(u) 2 m_pq /
+// sqrt(2 h |u|), which is c = (1 + t^2)^-1/2, s = t c with one reciprocal
+// square root for both (so c^2 + s^2 = 1 to rounding).  The rotated diagonal
+// is m_pp - t m_pq, m_qq + t m_pq, with t m_pq = sign(u) 4 h m_pq^2 / (2 h |u|).
+// The identity when `live` is false (m_pq = 0, or q is the dummy player);
+// no branches, so every lane runs the same instruction stream.
+struct JRot {
+  double c, s, dp, dq;
+};
+__device__ __forceinline__ JRot jacobi_rot(double mpp, double mqq, double mpq, bool live) {
+  live = live && mpq != 0.0;
+  const double apq = live ? mpq : 1.0;  // keeps the dead lanes finite
+  const double d = mqq - mpp;
+  const double y = fma(d, d, 4.0 * apq * apq);
+  const double h = y * rsq_nr(y);
+  const double au = fabs(d) + h;
+  const double r2 = rsq_nr(2.0 * h * au);
+  const double sg = d >= 0.0 ? 1.0 : -1.0;
+  const double s = sg * (2.0 * apq * r2);
+  const double tm = sg * (4.0 * h * apq * apq * (r2 * r2));
+  JRot r;
+  r.c = live ? au * r2 : 1.0;
+  r.s = live ? s : 0.0;
+  r.dp = live ? mpp - tm : mpp;
+  r.dq = live ? mqq + tm : mqq;
+  return r;
+}
+
 // Solves the Rayleigh-Ritz problem for GA, GB (ns x ns, already loaded into
-// sh.A and sh.B) and writes C (ns x m, row-major with leading dimension m),
-// theta and the kept flags.  All threads of the workgroup take part.
-__device__ __forceinline__ void rayleigh_ritz(RRShared& sh, int ns, int m, double drop_tol, double zero_tol, double* Cout,
-                              double* theta, int* kept_out, int* nkept_out) {
-  const int tid = threadIdx.x, nth = blockDim.x;
-  // symmetrise
-  for (int e = tid; e < ns * ns; e += nth) {
-    const int i = e / ns, j = e - (e / ns) * ns;
-    if (i < j) {
-      const double a = 0.5 * (sh.A[i * LD + j] + sh.A[j * LD + i]);
-      const double b = 0.5 * (sh.B[i * LD + j] + sh.B[j * LD + i]);
-      sh.M[i * LD + j] = a;
-      sh.M2[i * LD + j] = b;
-    }
+// sh.A and sh.B): C (ns x m, row-major with leading dimension m) and theta
+// (ascending) of the m smallest Ritz pairs, the kept flags and their count.
+// Called by the 64 lanes of one wave; KB >= ns is the padded size of the
+// triangular solves (the kept block is extended by an identity factor and
+// zero data there, which changes nothing and keeps the loops free of
+// conditionals).  Steps: symmetrise; scale to unit diag(GB) (columns with a
+// negligible diagonal are dropped); Cholesky GB = L L^T that drops columns
+// with a pivot below drop_tol; M = L^-1 GA L^-T on the kept columns; cyclic
+// Jacobi on M (parallel round-robin ordering, one 2 x 2 block of every
+// rotated pair of rows and columns per lane); C = L^-T Z.  Loads are issued
+// unconditionally (clamped indices) and only stores are masked, so a lane
+// never waits on a load inside a branch.
+template <int KB>
+__device__ void rayleigh_ritz_kb(RRShared& sh, int ns, int m, double drop_tol, double zero_tol, double* Cout,
+                                 double* theta, int* kept_out, int* nkept_out) {
+  const int lane = threadIdx.x & 63;
+  // unit-diagonal scaling: delta_j = diag(GB)_j^-1/2, 0 for a negligible column
+  const int lj = lane < ns ? lane : 0;
+  const double dl = sh.B[lj * LD + lj];
+  const double mx = wave_max(lane < ns && dl > 0.0 ? dl : 0.0);
+  const int gd = lane < ns && dl > zero_tol * zero_tol * mx;
+  if (lane < ns) {
+    sh.good[lane] = gd;
+    sh.delta[lane] = gd ? 1.0 / sqrt(dl) : 0.0;
   }
-  __syncthreads();
-  for (int e = tid; e < ns * ns; e += nth) {
-    const int i = e / ns, j = e - (e / ns) * ns;
-    if (i < j) {
-      sh.A[i * LD + j] = sh.A[j * LD + i] = sh.M[i * LD + j];
-      sh.B[i * LD + j] = sh.B[j * LD + i] = sh.M2[i * LD + j];
-    }
-  }
-  __syncthreads();
-  // zero columns and unit-diagonal scaling
-  if (tid == 0) {
-    double mx = 0.0;
-    for (int j = 0; j < ns; ++j) mx = sh.B[j * LD + j] > mx ? sh.B[j * LD + j] : mx;
-    for (int j = 0; j < ns; ++j) {
-      const double d = sh.B[j * LD + j];
-      const int gd = d > zero_tol * zero_tol * mx;
-      sh.good[j] = gd;
-      sh.delta[j] = gd ? 1.0 / sqrt(d) : 0.0;
-    }
-  }
-  __syncthreads();
-  for (int e = tid; e < ns * ns; e += nth) {
+  wave_fence();
+  for (int e = lane; e < ns * ns; e += 64) {
     const int i = e / ns, j = e - (e / ns) * ns;
     const double s = sh.delta[i] * sh.delta[j];
-    sh.A[i * LD + j] *= s;
-    sh.B[i * LD + j] *= s;
+    const double aij = sh.A[i * LD + j], aji = sh.A[j * LD + i];
+    const double bij = sh.B[i * LD + j], bji = sh.B[j * LD + i];
+    const double a = i == j ? aij : 0.5 * (aij + aji);
+    const double b = i == j ? bij : 0.5 * (bij + bji);
+    sh.SA[i * LD + j] = a * s;
+    sh.SB[i * LD + j] = b * s;
     sh.L[i * LD + j] = 0.0;
   }
-  __syncthreads();
-  // right-looking Cholesky of B with column dropping (lower triangle of B is the work array)
+  wave_fence();
+  // right-looking Cholesky of SB with column dropping: every lane computes the
+  // column entries it needs from SB itself (the same operations as the lane
+  // that stores them into L)
   for (int j = 0; j < ns; ++j) {
-    if (tid == 0) {
-      const double piv = sh.B[j * LD + j];
-      const int keep = sh.good[j] && (piv > drop_tol);
+    const double piv = sh.SB[j * LD + j];
+    const int keep = sh.good[j] && piv > drop_tol;
+    const double ip = rsq_nr2(keep ? piv : 1.0);  // 1 / L_jj
+    if (lane == 0) {
       sh.kept[j] = keep;
-      sh.keep = keep;
-      sh.piv = keep ? sqrt(piv) : 0.0;
-      if (keep) sh.L[j * LD + j] = sh.piv;
+      if (keep) sh.L[j * LD + j] = piv * ip;
     }
-    __syncthreads();
-    if (sh.keep) {
-      for (int i = j + 1 + tid; i < ns; i += nth) sh.L[i * LD + j] = sh.B[i * LD + j] / sh.piv;
-      __syncthreads();
-      const int rem = ns - j - 1;
-      for (int e = tid; e < rem * rem; e += nth) {
-        const int i = j + 1 + e / rem, l = j + 1 + (e - (e / rem) * rem);
-        if (l <= i) sh.B[i * LD + l] -= sh.L[i * LD + j] * sh.L[l * LD + j];
+    const int rem = ns - j - 1;
+    for (int e = lane; e < rem * rem; e += 64) {
+      const int i = j + 1 + e / rem, l = j + 1 + (e - (e / rem) * rem);
+      const double lij = sh.SB[i * LD + j] * ip;
+      const double llj = sh.SB[l * LD + j] * ip;
+      const double bil = sh.SB[i * LD + l];
+      if (keep && l <= i) {
+        sh.SB[i * LD + l] = bil - lij * llj;
+        if (l == j + 1) sh.L[i * LD + j] = lij;
       }
     }
-    __syncthreads();
+    wave_fence();
   }
-  if (tid == 0) {
-    int k = 0;
-    for (int j = 0; j < ns; ++j)
-      if (sh.kept[j]) sh.idx[k++] = j;
-    sh.nk = k;
+  const int kp = lane < ns ? sh.kept[lane] : 0;
+  const unsigned long long km = __ballot(kp);
+  const int K = __popcll(km);
+  if (kp) sh.idx[__popcll(km & ((1ull << lane) - 1ull))] = lane;
+  if (lane < ns) kept_out[lane] = kp;
+  if (lane == 0) *nkept_out = K;
+  wave_fence();
+  if (K < m) return;
+  // compressed factor LK and reduced A (in M2), padded to KB x KB with the
+  // identity and zeros; reciprocal pivots (1 on the padding)
+  for (int e = lane; e < KB * KB; e += 64) {
+    const int a = e / KB, b = e - (e / KB) * KB;
+    const int ia = sh.idx[a < K ? a : 0], ib = sh.idx[b < K ? b : 0];
+    const double lv = sh.L[ia * LD + ib], av = sh.SA[ia * LD + ib];
+    const bool in = a < K && b < K;
+    sh.LK[a * LD + b] = in ? (b <= a ? lv : 0.0) : (a == b ? 1.0 : 0.0);
+    sh.M2[a * LD + b] = in ? av : 0.0;
   }
-  __syncthreads();
-  const int K = sh.nk;
-  if (tid < ns) kept_out[tid] = sh.kept[tid];
-  if (tid == 0) *nkept_out = K;
-  if (K < m) {
-    __syncthreads();
-    return;
+  if (lane < KB) {
+    const int ia = sh.idx[lane < K ? lane : 0];
+    const double lv = sh.L[ia * LD + ia];
+    sh.rinv[lane] = lane < K ? 1.0 / lv : 1.0;
   }
-  // compressed factor LK (in L) and reduced A (in M2)
-  for (int e = tid; e < K * K; e += nth) {
+  wave_fence();
+  // T = LK^-1 A_K: lane c solves LK t = A_K[:, c] by forward substitution with
+  // its column in registers (LK read as LDS broadcasts), then writes row c of
+  // T^T.  A_K is symmetric, so M = T LK^-T = (LK^-1 T^T)^T.
+  {
+    const int c = lane < KB ? lane : 0;
+    double col[KB];
+#pragma unroll
+    for (int i = 0; i < KB; ++i) {
+      double v = sh.M2[i * LD + c];
+#pragma unroll
+      for (int t = 0; t < i; ++t) v -= sh.LK[i * LD + t] * col[t];
+      col[i] = v * sh.rinv[i];
+    }
+    if (lane < KB) {
+#pragma unroll
+      for (int i = 0; i < KB; ++i) sh.V[c * LD + i] = col[i];  // V = T^T
+    }
+  }
+  wave_fence();
+  {
+    const int c = lane < KB ? lane : 0;
+    double col[KB];
+#pragma unroll
+    for (int i = 0; i < KB; ++i) {
+      double v = sh.V[i * LD + c];
+#pragma unroll
+      for (int t = 0; t < i; ++t) v -= sh.LK[i * LD + t] * col[t];
+      col[i] = v * sh.rinv[i];
+    }
+    if (lane < KB) {
+#pragma unroll
+      for (int i = 0; i < KB; ++i) sh.M2[c * LD + i] = col[i];  // M2 = (LK^-1 T^T)^T = M
+    }
+  }
+  wave_fence();
+  for (int e = lane; e < K * K; e += 64) {
     const int a = e / K, b = e - (e / K) * K;
-    sh.LK[a * LD + b] = (b <= a) ? sh.L[sh.idx[a] * LD + sh.idx[b]] : 0.0;
-    sh.M2[a * LD + b] = sh.A[sh.idx[a] * LD + sh.idx[b]];
-  }
-  __syncthreads();
-  // T = LK^-1 A_K: thread c solves LK t = A_K[:, c] by forward substitution
-  // with its column in registers (LK read as LDS broadcasts), then writes row
-  // c of T^T.  A_K is symmetric, so M = T LK^-T = (LK^-1 T^T)^T.
-  if (tid < K) {
-    const int c = tid;
-    double col[KMAX];
-#pragma unroll
-    for (int i = 0; i < KMAX; ++i) {
-      if (i < K) {
-        double v = sh.M2[i * LD + c];
-#pragma unroll
-        for (int t = 0; t < KMAX; ++t)
-          if (t < i) v -= sh.LK[i * LD + t] * col[t];
-        col[i] = v / sh.LK[i * LD + i];
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < KMAX; ++i)
-      if (i < K) sh.V[c * LD + i] = col[i];  // V = T^T
-  }
-  __syncthreads();
-  if (tid < K) {
-    const int c = tid;
-    double col[KMAX];
-#pragma unroll
-    for (int i = 0; i < KMAX; ++i) {
-      if (i < K) {
-        double v = sh.V[i * LD + c];
-#pragma unroll
-        for (int t = 0; t < KMAX; ++t)
-          if (t < i) v -= sh.LK[i * LD + t] * col[t];
-        col[i] = v / sh.LK[i * LD + i];
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < KMAX; ++i)
-      if (i < K) sh.M2[c * LD + i] = col[i];  // M2 = (LK^-1 T^T)^T = M
-  }
-  __syncthreads();
-  for (int e = tid; e < K * K; e += nth) {
-    const int a = e / K, b = e - (e / K) * K;
-    sh.M[a * LD + b] = 0.5 * (sh.M2[a * LD + b] + sh.M2[b * LD + a]);
+    const double x = sh.M2[a * LD + b], y = sh.M2[b * LD + a];
+    sh.M[a * LD + b] = 0.5 * (x + y);
     sh.V[a * LD + b] = (a == b) ? 1.0 : 0.0;
   }
-  __syncthreads();
+  wave_fence();
 
-  // cyclic Jacobi with round-robin parallel ordering
+  // cyclic Jacobi: in each round the np/2 disjoint pairs of the round-robin
+  // schedule are rotated together, M <- J^T M J, V <- V J.  Lane b owns the
+  // 2 x 2 block (pair P = b / nh rows, pair Q = b % nh columns) and computes
+  // both rotations itself (bitwise the same on every lane that needs them).
   const int np = (K + 1) & ~1;  // players (a dummy when K is odd)
-  // this thread's matrix elements, fixed for the whole eigensolve
-  constexpr int EPT = (KMAX * KMAX + 63) / 64;  // enough for any launch of >= 64 threads
-  int ei[EPT], ej[EPT];
-#pragma unroll
-  for (int k = 0; k < EPT; ++k) {
-    const int e = tid + k * nth;
-    ei[k] = e < K * K ? e / K : -1;
-    ej[k] = e < K * K ? e - (e / K) * K : 0;
-  }
+  const int nh = np >> 1, nblk = nh * nh;
   double* Mc = sh.M;
   double* Mn = sh.M2;
   double* Vc = sh.V;
   double* Vn = sh.V2;
   for (int sweep = 0; sweep < 30; ++sweep) {
     for (int rnd = 0; rnd < np - 1; ++rnd) {
-      if (tid < np / 2) {
-        const int s0 = tid, s1 = np - 1 - tid;
-        const int pa = (s0 == 0) ? 0 : 1 + ((s0 - 1 + rnd) % (np - 1));
-        const int pb = 1 + ((s1 - 1 + rnd) % (np - 1));
-        const int p = pa < pb ? pa : pb, q = pa < pb ? pb : pa;
-        double c = 1.0, s = 0.0, t = 0.0, apq = 0.0;
-        if (q < K) {
-          apq = Mc[p * LD + q];
-          if (apq != 0.0) {
-            // t = tan of the rotation angle, the root of t^2 + 2 theta t - 1 = 0
-            // of smaller magnitude, theta = (a_qq - a_pp) / (2 a_pq)
-            const double d = Mc[q * LD + q] - Mc[p * LD + p];
-            const double y = fma(d, d, 4.0 * apq * apq);
-            const double h = y * rsq_nr(y);
-            t = 2.0 * apq * rcp_nr(d >= 0.0 ? d + h : d - h);
-            c = rsq_nr(fma(t, t, 1.0));
-            s = t * c;
+      for (int b0 = 0; b0 < nblk; b0 += 64) {
+        const int bl = b0 + lane;
+        const int b = bl < nblk ? bl : 0;
+        const int P = b / nh, Q = b - (b / nh) * nh;
+        int i0, i1, j0, j1;
+        rr_pair(P, rnd, np, i0, i1);
+        rr_pair(Q, rnd, np, j0, j1);
+        const bool ri = i1 < K, rj = j1 < K;  // the second player is not the dummy
+        const int i1c = ri ? i1 : i0, j1c = rj ? j1 : j0;
+        const double m00 = Mc[i0 * LD + j0], m01 = Mc[i0 * LD + j1c];
+        const double m10 = Mc[i1c * LD + j0], m11 = Mc[i1c * LD + j1c];
+        const double pp = Mc[i0 * LD + i0], qq = Mc[i1c * LD + i1c], pq = Mc[i0 * LD + i1c];
+        const double rr = Mc[j0 * LD + j0], ss = Mc[j1c * LD + j1c], rs = Mc[j0 * LD + j1c];
+        const double v00 = Vc[i0 * LD + j0], v01 = Vc[i0 * LD + j1c];
+        const double v10 = Vc[i1c * LD + j0], v11 = Vc[i1c * LD + j1c];
+        const JRot jp = jacobi_rot(pp, qq, pq, ri);
+        const JRot jq = jacobi_rot(rr, ss, rs, rj);
+        // X = J_P^T B, B' = X J_Q
+        const double x00 = jp.c * m00 - jp.s * m10, x01 = jp.c * m01 - jp.s * m11;
+        const double x10 = jp.s * m00 + jp.c * m10, x11 = jp.s * m01 + jp.c * m11;
+        double y00 = x00 * jq.c - x01 * jq.s, y01 = x00 * jq.s + x01 * jq.c;
+        double y10 = x10 * jq.c - x11 * jq.s, y11 = x10 * jq.s + x11 * jq.c;
+        if (P == Q) {  // the rotated pair itself: exact zero off the diagonal
+          y00 = jp.dp;
+          y11 = jp.dq;
+          y01 = 0.0;
+          y10 = 0.0;
+        }
+        if (bl < nblk) {
+          Mn[i0 * LD + j0] = y00;
+          Vn[i0 * LD + j0] = v00 * jq.c - v01 * jq.s;
+          if (rj) {
+            Mn[i0 * LD + j1] = y01;
+            Vn[i0 * LD + j1] = v00 * jq.s + v01 * jq.c;
+          }
+          if (ri) {
+            Mn[i1 * LD + j0] = y10;
+            Vn[i1 * LD + j0] = v10 * jq.c - v11 * jq.s;
+          }
+          if (ri && rj) {
+            Mn[i1 * LD + j1] = y11;
+            Vn[i1 * LD + j1] = v10 * jq.s + v11 * jq.c;
           }
         }
-        sh.partner[p] = q;
-        sh.partner[q] = p;
-        sh.jself[p] = c;
-        sh.jself[q] = c;
-        sh.joff[p] = -s;  // J[q][p]
-        sh.joff[q] = s;   // J[p][q]
-        // the rotated pair: a_pq becomes exactly 0, the diagonal moves by t a_pq
-        sh.dnew[p] = (q < K) ? Mc[p * LD + p] - t * apq : Mc[p * LD + p];
-        if (q < K) sh.dnew[q] = Mc[q * LD + q] + t * apq;
       }
-      __syncthreads();
-#pragma unroll
-      for (int k = 0; k < EPT; ++k) {
-        if (ei[k] < 0) continue;
-        const int i = ei[k], j = ej[k];
-        const int pi = sh.partner[i], pj = sh.partner[j];
-        const double ci = sh.jself[i], oi = sh.joff[i], cj = sh.jself[j], oj = sh.joff[j];
-        double v;
-        if (i == j) {
-          v = sh.dnew[i];
-        } else if (pi == j) {
-          v = 0.0;
-        } else {
-          v = ci * cj * Mc[i * LD + j];
-          if (pj < K) v += ci * oj * Mc[i * LD + pj];
-          if (pi < K) {
-            v += oi * cj * Mc[pi * LD + j];
-            if (pj < K) v += oi * oj * Mc[pi * LD + pj];
-          }
-        }
-        Mn[i * LD + j] = v;
-        double w = Vc[i * LD + j] * cj;
-        if (pj < K) w += Vc[i * LD + pj] * oj;
-        Vn[i * LD + j] = w;
-      }
-      __syncthreads();
+      wave_fence();
       double* t1 = Mc;
       Mc = Mn;
       Mn = t1;
@@ -537,69 +616,86 @@ __device__ __forceinline__ void rayleigh_ritz(RRShared& sh, int ns, int m, doubl
       Vc = Vn;
       Vn = t2;
     }
-    // convergence: off-diagonal mass relative to the whole
-    double acc[2] = {0.0, 0.0};
-    for (int e = tid; e < K * K; e += nth) {
+    // convergence: off-diagonal Frobenius mass below 1e-14 of the whole
+    // (relative); the butterfly sum leaves the same value on every lane
+    double off = 0.0, dia = 0.0;
+    for (int e = lane; e < K * K; e += 64) {
       const int i = e / K, j = e - (e / K) * K;
       const double v = Mc[i * LD + j] * Mc[i * LD + j];
-      if (i == j)
-        acc[1] += v;
-      else
-        acc[0] += v;
+      off += i == j ? 0.0 : v;
+      dia += i == j ? v : 0.0;
     }
-    block_sum<2>(acc, sh.red);
-    // off-diagonal Frobenius mass below 1e-14 of the whole (relative)
-    if (tid == 0) sh.stop = (acc[0] <= 1e-28 * (acc[0] + acc[1])) ? 1 : 0;
-    __syncthreads();
-    if (sh.stop) break;
+    off = wave_sum(off);
+    dia = wave_sum(dia);
+    if (off <= 1e-28 * (off + dia)) break;
   }
   // order eigenvalues ascending (ties by index)
-  if (tid < K) sh.ev[tid] = Mc[tid * LD + tid];
-  __syncthreads();
-  if (tid < K) {
-    int rank = 0;
-    const double e = sh.ev[tid];
-    for (int j = 0; j < K; ++j) rank += (sh.ev[j] < e || (sh.ev[j] == e && j < tid)) ? 1 : 0;
-    sh.order[rank] = tid;
+  {
+    const int li = lane < K ? lane : 0;
+    sh.ev[lane < KB ? lane : 0] = Mc[li * LD + li];  // lanes >= K store junk past K (never read)
   }
-  __syncthreads();
-  if (tid < m) theta[tid] = sh.ev[sh.order[tid]];
-  // C_K = LK^-T Z_m: thread t solves LK^T c = Z[:, order[t]] by back substitution
-  for (int e = tid; e < ns * m; e += nth) Cout[e] = 0.0;
-  __syncthreads();
-  if (tid < m) {
-    const int t = tid, col = sh.order[t];
-    double c[KMAX];
+  for (int e = lane; e < ns * m; e += 64) sh.Cs[e] = 0.0;
+  wave_fence();
+  {
+    const double e = sh.ev[lane < K ? lane : 0];
+    int rank = 0;
 #pragma unroll
-    for (int ii = KMAX - 1; ii >= 0; --ii) {
-      if (ii < K) {
-        double v = Vc[ii * LD + col];
+    for (int j = 0; j < KB; ++j) {
+      const double ej = sh.ev[j];
+      rank += (j < K && (ej < e || (ej == e && j < lane))) ? 1 : 0;
+    }
+    if (lane < K) sh.order[rank] = lane;
+  }
+  wave_fence();
+  // C_K = LK^-T Z_m: lane t solves LK^T c = Z[:, order[t]] by back substitution
+  {
+    const int t = lane < m ? lane : 0;
+    const int col = sh.order[t];
+    if (lane < m) theta[lane] = sh.ev[col];
+    double c[KB];
 #pragma unroll
-        for (int b = 0; b < KMAX; ++b)
-          if (b > ii && b < K) v -= sh.LK[b * LD + ii] * c[b];
-        c[ii] = v / sh.LK[ii * LD + ii];
-      }
+    for (int ii = KB - 1; ii >= 0; --ii) {
+      const double z = Vc[(ii < K ? ii : 0) * LD + col];
+      double v = ii < K ? z : 0.0;
+#pragma unroll
+      for (int b = ii + 1; b < KB; ++b) v -= sh.LK[b * LD + ii] * c[b];
+      c[ii] = v * sh.rinv[ii];
     }
     // sign: the largest-magnitude coefficient (first on ties) is positive, so
     // Ritz vectors (and residuals) have a fixed sign for a non-odd T
     double big = 0.0, sgn = 1.0;
 #pragma unroll
-    for (int a = 0; a < KMAX; ++a)
-      if (a < K) {
-        const double v = sh.delta[sh.idx[a]] * c[a];
-        if (fabs(v) > big) {
-          big = fabs(v);
-          sgn = v < 0.0 ? -1.0 : 1.0;
-        }
-      }
+    for (int a = 0; a < KB; ++a) {
+      const double v = sh.delta[sh.idx[a < K ? a : 0]] * c[a];
+      const bool more = a < K && fabs(v) > big;
+      big = more ? fabs(v) : big;
+      sgn = more ? (v < 0.0 ? -1.0 : 1.0) : sgn;
+    }
+    if (lane < m) {
 #pragma unroll
-    for (int a = 0; a < KMAX; ++a)
-      if (a < K) {
-        const int row = sh.idx[a];
-        Cout[row * m + t] = sgn * (sh.delta[row] * c[a]);
+      for (int a = 0; a < KB; ++a) {
+        const int row = sh.idx[a < K ? a : 0];
+        const double v = sgn * (sh.delta[row] * c[a]);
+        if (a < K) sh.Cs[row * m + t] = v;
       }
+    }
   }
-  __syncthreads();
+  wave_fence();
+  for (int e = lane; e < ns * m; e += 64) Cout[e] = sh.Cs[e];
+}
+
+__device__ void rayleigh_ritz(RRShared& sh, int ns, int m, double drop_tol, double zero_tol, double* Cout,
+                              double* theta, int* kept_out, int* nkept_out) {
+  if (ns <= 4)
+    rayleigh_ritz_kb<4>(sh, ns, m, drop_tol, zero_tol, Cout, theta, kept_out, nkept_out);
+  else if (ns <= 8)
+    rayleigh_ritz_kb<8>(sh, ns, m, drop_tol, zero_tol, Cout, theta, kept_out, nkept_out);
+  else if (ns <= 12)
+    rayleigh_ritz_kb<12>(sh, ns, m, drop_tol, zero_tol, Cout, theta, kept_out, nkept_out);
+  else if (ns <= 16)
+    rayleigh_ritz_kb<16>(sh, ns, m, drop_tol, zero_tol, Cout, theta, kept_out, nkept_out);
+  else
+    rayleigh_ritz_kb<KMAX>(sh, ns, m, drop_tol, zero_tol, Cout, theta, kept_out, nkept_out);
 }
 
 // First stage of the Gram reduction: workgroup (tile, chunk) sums the partials
@@ -623,10 +719,12 @@ __global__ void __launch_bounds__(kThreads) gram_reduce_kernel(GramArgs g) {
   g.level2[(size_t)chunk * st + e] = s;
 }
 
-// One workgroup: sums the chunks, assembles GA and GB (ns x ns) and runs the
-// Rayleigh-Ritz step.
+// One workgroup: sums the chunks and assembles GA and GB (ns x ns); its first
+// wave then runs the Rayleigh-Ritz step.
 __global__ void __launch_bounds__(kThreads) gram_rr_kernel(GramArgs g, RRArgs r) {
   __shared__ RRShared sh;
+  __shared__ int nkept;
+  __shared__ int keptf[KMAX];
   if (r.st != nullptr && !r.st->active) return;
   const int nt = (g.ns + 15) >> 4;
   const int ntb = n_tiles_b(nt), ntot = ntb + n_tiles_a(nt);
@@ -668,12 +766,10 @@ __global__ void __launch_bounds__(kThreads) gram_rr_kernel(GramArgs g, RRArgs r)
       r.gram_out[e] = sh.A[i * LD + j];
       r.gram_out[g.ns * g.ns + e] = sh.B[i * LD + j];
     }
-    __syncthreads();
   }
-  __shared__ int nkept;
-  __shared__ int keptf[KMAX];
+  if (threadIdx.x >= 64) return;
   rayleigh_ritz(sh, g.ns, g.m, r.drop_tol, r.zero_tol, r.C, r.theta, keptf, &nkept);
-  __syncthreads();
+  wave_fence();
   if (threadIdx.x == 0 && r.st != nullptr) {
     LobpcgState* st = r.st;
     st->nkept = nkept;
@@ -684,7 +780,7 @@ __global__ void __launch_bounds__(kThreads) gram_rr_kernel(GramArgs g, RRArgs r)
       st->active = 0;
       if (r.init) st->start_failed = 1;
     } else {
-      for (int j = 0; j < g.m; ++j) st->theta[j] = r.theta[j];
+      for (int j = 0; j < g.m; ++j) st->theta[j] = sh.ev[sh.order[j]];
     }
   }
   if (r.kept_out != nullptr && threadIdx.x < g.ns) r.kept_out[threadIdx.x] = keptf[threadIdx.x];
@@ -933,7 +1029,8 @@ gsf_status lob_launch_project(const LobArgs& a, void* B, int nb, hipStream_t s) 
   return hipGetLastError() == hipSuccess ? GSF_OK : GSF_EDEVICE;
 }
 
-// The Rayleigh-Ritz step runs on one workgroup of four waves.
+// The Gram pair is loaded by one workgroup of four waves; the Rayleigh-Ritz
+// step runs on its first wave.
 int rr_threads(int ns) { return kThreads; }
 
 int gram_tiles_total(int ns) {
@@ -961,18 +1058,20 @@ gsf_status lob_launch_gram(const GramArgs& g, const RRArgs& r, int prec, hipStre
 }
 
 // Rayleigh-Ritz alone on a Gram pair already in device memory (GA then GB,
-// ns x ns each, row-major) -- one workgroup.
+// ns x ns each, row-major) -- one workgroup, the step itself on its first wave.
 __global__ void __launch_bounds__(kThreads) rr_only_kernel(const double* __restrict__ G, int ns, int m, RRArgs r) {
   __shared__ RRShared sh;
+  __shared__ int nkept;
+  __shared__ int keptf[KMAX];
   for (int e = threadIdx.x; e < ns * ns; e += blockDim.x) {
     const int i = e / ns, j = e - (e / ns) * ns;
     sh.A[i * LD + j] = G[e];
     sh.B[i * LD + j] = G[ns * ns + e];
   }
   __syncthreads();
-  __shared__ int nkept;
-  __shared__ int keptf[KMAX];
+  if (threadIdx.x >= 64) return;
   rayleigh_ritz(sh, ns, m, r.drop_tol, r.zero_tol, r.C, r.theta, keptf, &nkept);
+  wave_fence();
   if (threadIdx.x < ns) r.kept_out[threadIdx.x] = keptf[threadIdx.x];
   if (threadIdx.x == 0) *r.nkept_out = nkept;
 }

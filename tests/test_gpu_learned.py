@@ -21,6 +21,7 @@ import pytest
 
 import oracle
 from oracle import convnet as cn
+from oracle.spectral import dense_normalized
 from synth import convnet_init, scene_2d
 
 pytestmark = pytest.mark.gpu
@@ -284,7 +285,7 @@ def test_lobpcg_random_network_matches_oracle(gsf):
     tol = 1e-9
     out, info = op.lobpcg_filter(gd, m, 3000, tol=tol, constraint=True, precond=T)
     ref = oracle.lobpcg_filter(oop, g.ravel(), m, 3000, tol=tol, constraint=True, precond=Tref)
-    lam = np.linalg.eigvalsh(oracle.spectral.dense_normalized(oop)[1])
+    lam = np.linalg.eigvalsh(dense_normalized(oop)[1])
     e = nrel(out.cpu().numpy(), ref[0])
     et = np.abs(np.array(list(info.theta)[:m]) - ref[1]).max()
     print(f"random net LOBPCG: one step y rel {e1:.2e}; converged in {info.iters} vs {ref[3].iters} steps: "

@@ -193,12 +193,19 @@ def test_block_gram_parity(gsf, prec, m, nb):
     assert rel(GA, Sf.T @ Af) <= tol
 
 
-@pytest.mark.parametrize("ns,m,drop", [(9, 3, False), (24, 8, False), (12, 4, True)])
+@pytest.mark.parametrize("ns,m,drop", [(1, 1, False), (2, 1, False), (9, 3, False), (16, 4, False),
+                                       (17, 5, False), (23, 8, False), (24, 8, False), (12, 4, True),
+                                       (24, 8, True)])
 def test_rayleigh_ritz_parity(gsf, ns, m, drop):
+    """The single-wave Rayleigh-Ritz step against the oracle's: even and odd
+    kept counts (a dummy player in the Jacobi schedule), up to 24 columns
+    (more 2 x 2 blocks than lanes), with nearly dependent columns dropped."""
     rng = np.random.default_rng(ns)
     S = rng.standard_normal((200, ns))
     if drop:
         S[:, 7] = 2.0 * S[:, 2] + 1e-9 * rng.standard_normal(200)
+        if ns > 20:
+            S[:, 19] = S[:, 3] - S[:, 11] + 1e-9 * rng.standard_normal(200)
     A0 = rng.standard_normal((200, 200))
     A = A0 @ A0.T / 200
     GA, GB = S.T @ A @ S, S.T @ S
