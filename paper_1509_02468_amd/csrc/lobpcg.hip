@@ -375,6 +375,8 @@ struct RRShared {
   int idx[KMAX];
   int order[KMAX];
 };
+// the Jacobi schedule table reuses A, B, SA and SB
+static_assert((KMAX - 1) * 3 * 64 * sizeof(uint32_t) <= 4 * sizeof(double) * KMAX * LD, "schedule table");
 
 // Players of pair `slot` in round `rnd` of the round-robin schedule over np
 // players (np even): player 0 stays, the others rotate.  p < q.
@@ -555,69 +557,75 @@ __device__ void rayleigh_ritz_kb(RRShared& sh, int ns, int m, double drop_tol, d
   // schedule are rotated together, M <- J^T M J, V <- V J.  Lane b owns the
   // 2 x 2 block (pair P = b / nh rows, pair Q = b % nh columns) and computes
   // both rotations itself (bitwise the same on every lane that needs them).
+  // The schedule is tabulated once per call (one word per round, block slot
+  // and lane, in the Gram and scaled arrays, which are dead by now), and the
+  // round loop alternates the two buffers explicitly so that every LDS
+  // address is a table offset plus a constant.
   const int np = (K + 1) & ~1;  // players (a dummy when K is odd)
-  const int nh = np >> 1, nblk = nh * nh;
-  double* Mc = sh.M;
-  double* Mn = sh.M2;
-  double* Vc = sh.V;
-  double* Vn = sh.V2;
-  for (int sweep = 0; sweep < 30; ++sweep) {
-    for (int rnd = 0; rnd < np - 1; ++rnd) {
-      for (int b0 = 0; b0 < nblk; b0 += 64) {
-        const int bl = b0 + lane;
-        const int b = bl < nblk ? bl : 0;
-        const int P = b / nh, Q = b - (b / nh) * nh;
-        int i0, i1, j0, j1;
-        rr_pair(P, rnd, np, i0, i1);
-        rr_pair(Q, rnd, np, j0, j1);
-        const bool ri = i1 < K, rj = j1 < K;  // the second player is not the dummy
-        const int i1c = ri ? i1 : i0, j1c = rj ? j1 : j0;
-        const double m00 = Mc[i0 * LD + j0], m01 = Mc[i0 * LD + j1c];
-        const double m10 = Mc[i1c * LD + j0], m11 = Mc[i1c * LD + j1c];
-        const double pp = Mc[i0 * LD + i0], qq = Mc[i1c * LD + i1c], pq = Mc[i0 * LD + i1c];
-        const double rr = Mc[j0 * LD + j0], ss = Mc[j1c * LD + j1c], rs = Mc[j0 * LD + j1c];
-        const double v00 = Vc[i0 * LD + j0], v01 = Vc[i0 * LD + j1c];
-        const double v10 = Vc[i1c * LD + j0], v11 = Vc[i1c * LD + j1c];
-        const JRot jp = jacobi_rot(pp, qq, pq, ri);
-        const JRot jq = jacobi_rot(rr, ss, rs, rj);
-        // X = J_P^T B, B' = X J_Q
-        const double x00 = jp.c * m00 - jp.s * m10, x01 = jp.c * m01 - jp.s * m11;
-        const double x10 = jp.s * m00 + jp.c * m10, x11 = jp.s * m01 + jp.c * m11;
-        double y00 = x00 * jq.c - x01 * jq.s, y01 = x00 * jq.s + x01 * jq.c;
-        double y10 = x10 * jq.c - x11 * jq.s, y11 = x10 * jq.s + x11 * jq.c;
-        if (P == Q) {  // the rotated pair itself: exact zero off the diagonal
-          y00 = jp.dp;
-          y11 = jp.dq;
-          y01 = 0.0;
-          y10 = 0.0;
+  const int nh = np >> 1, nblk = nh * nh, nr = np - 1;
+  const int nslot = (nblk + 63) >> 6;
+  uint32_t* tab = reinterpret_cast<uint32_t*>(sh.A);  // (KMAX-1) x 3 x 64 words fit in A, B, SA, SB
+  for (int r = 0; r < nr; ++r) {
+    for (int sl = 0; sl < nslot; ++sl) {
+      const int bl = sl * 64 + lane;
+      const int b = bl < nblk ? bl : 0;
+      const int P = b / nh, Q = b - (b / nh) * nh;
+      int i0, i1, j0, j1;
+      rr_pair(P, r, np, i0, i1);
+      rr_pair(Q, r, np, j0, j1);
+      const uint32_t ri = i1 < K, rj = j1 < K;  // the second player is not the dummy
+      const uint32_t i1c = ri ? i1 : i0, j1c = rj ? j1 : j0;
+      tab[(r * nslot + sl) * 64 + lane] = (uint32_t)i0 | (i1c << 5) | ((uint32_t)j0 << 10) | (j1c << 15) |
+                                          (ri << 20) | (rj << 21) | ((uint32_t)(bl < nblk) << 22) |
+                                          ((uint32_t)(P == Q) << 23);
+    }
+  }
+  wave_fence();
+  auto jround = [&](int rnd, const double* __restrict__ Mc, double* __restrict__ Mn, const double* __restrict__ Vc,
+                    double* __restrict__ Vn) {
+    for (int sl = 0; sl < nslot; ++sl) {
+      const uint32_t w = tab[(rnd * nslot + sl) * 64 + lane];
+      const int i0 = w & 31, i1 = (w >> 5) & 31, j0 = (w >> 10) & 31, j1 = (w >> 15) & 31;
+      const bool ri = (w >> 20) & 1, rj = (w >> 21) & 1, act = (w >> 22) & 1, dg = (w >> 23) & 1;
+      const int a0 = i0 * LD, a1 = i1 * LD, b0 = j0 * LD, b1 = j1 * LD;
+      const double m00 = Mc[a0 + j0], m01 = Mc[a0 + j1], m10 = Mc[a1 + j0], m11 = Mc[a1 + j1];
+      const double pp = Mc[a0 + i0], qq = Mc[a1 + i1], pq = Mc[a0 + i1];
+      const double rr = Mc[b0 + j0], ss = Mc[b1 + j1], rs = Mc[b0 + j1];
+      const double v00 = Vc[a0 + j0], v01 = Vc[a0 + j1], v10 = Vc[a1 + j0], v11 = Vc[a1 + j1];
+      const JRot jp = jacobi_rot(pp, qq, pq, ri);
+      const JRot jq = jacobi_rot(rr, ss, rs, rj);
+      // X = J_P^T B, B' = X J_Q
+      const double x00 = jp.c * m00 - jp.s * m10, x01 = jp.c * m01 - jp.s * m11;
+      const double x10 = jp.s * m00 + jp.c * m10, x11 = jp.s * m01 + jp.c * m11;
+      double y00 = x00 * jq.c - x01 * jq.s, y01 = x00 * jq.s + x01 * jq.c;
+      double y10 = x10 * jq.c - x11 * jq.s, y11 = x10 * jq.s + x11 * jq.c;
+      if (dg) {  // the rotated pair itself: exact zero off the diagonal
+        y00 = jp.dp;
+        y11 = jp.dq;
+        y01 = 0.0;
+        y10 = 0.0;
+      }
+      if (act) {
+        Mn[a0 + j0] = y00;
+        Vn[a0 + j0] = v00 * jq.c - v01 * jq.s;
+        if (rj) {
+          Mn[a0 + j1] = y01;
+          Vn[a0 + j1] = v00 * jq.s + v01 * jq.c;
         }
-        if (bl < nblk) {
-          Mn[i0 * LD + j0] = y00;
-          Vn[i0 * LD + j0] = v00 * jq.c - v01 * jq.s;
-          if (rj) {
-            Mn[i0 * LD + j1] = y01;
-            Vn[i0 * LD + j1] = v00 * jq.s + v01 * jq.c;
-          }
-          if (ri) {
-            Mn[i1 * LD + j0] = y10;
-            Vn[i1 * LD + j0] = v10 * jq.c - v11 * jq.s;
-          }
-          if (ri && rj) {
-            Mn[i1 * LD + j1] = y11;
-            Vn[i1 * LD + j1] = v10 * jq.s + v11 * jq.c;
-          }
+        if (ri) {
+          Mn[a1 + j0] = y10;
+          Vn[a1 + j0] = v10 * jq.c - v11 * jq.s;
+        }
+        if (ri && rj) {
+          Mn[a1 + j1] = y11;
+          Vn[a1 + j1] = v10 * jq.s + v11 * jq.c;
         }
       }
-      wave_fence();
-      double* t1 = Mc;
-      Mc = Mn;
-      Mn = t1;
-      double* t2 = Vc;
-      Vc = Vn;
-      Vn = t2;
     }
-    // convergence: off-diagonal Frobenius mass below 1e-14 of the whole
-    // (relative); the butterfly sum leaves the same value on every lane
+  };
+  // convergence: off-diagonal Frobenius mass below 1e-14 of the whole
+  // (relative); the butterfly sum leaves the same value on every lane
+  auto converged = [&](const double* Mc) {
     double off = 0.0, dia = 0.0;
     for (int e = lane; e < K * K; e += 64) {
       const int i = e / K, j = e - (e / K) * K;
@@ -627,8 +635,27 @@ __device__ void rayleigh_ritz_kb(RRShared& sh, int ns, int m, double drop_tol, d
     }
     off = wave_sum(off);
     dia = wave_sum(dia);
-    if (off <= 1e-28 * (off + dia)) break;
+    return off <= 1e-28 * (off + dia);
+  };
+  int rnd = 0, sweep = 0, cur = 0;  // cur = 1: the current matrix is in M2, V2
+  while (true) {
+    jround(rnd, sh.M, sh.M2, sh.V, sh.V2);
+    wave_fence();
+    cur = 1;
+    if (++rnd == nr) {
+      rnd = 0;
+      if (converged(sh.M2) || ++sweep == 30) break;
+    }
+    jround(rnd, sh.M2, sh.M, sh.V2, sh.V);
+    wave_fence();
+    cur = 0;
+    if (++rnd == nr) {
+      rnd = 0;
+      if (converged(sh.M) || ++sweep == 30) break;
+    }
   }
+  const double* Mc = cur ? sh.M2 : sh.M;
+  const double* Vc = cur ? sh.V2 : sh.V;
   // order eigenvalues ascending (ties by index)
   {
     const int li = lane < K ? lane : 0;
