@@ -304,7 +304,8 @@ gsf_status gsf_lobpcg_residual(const gsf_operator* op, int m, const void* X, con
 /* ---- tuning ---------------------------------------------------------------
  * gsf_tune_apply: times the BF apply (form L_sym, block width m in
  *   {1, 2, 3, 4, 8}) with 1, 2 and 4 grid rows per thread (tile heights 4, 8
- *   and 16 rows), `reps` launches each, on caller buffers x, y (n*m
+ *   and 16 rows; in 2D the two rows of a thread are computed together and
+ *   share every neighbour row), `reps` launches each, on caller buffers x, y (n*m
  *   elements); records the fastest choice for every later apply with the same
  *   precision, dimension, radius, width and size class (process-wide), and
  *   returns it in *best_rpt and the three timings (microseconds per launch)

@@ -20,6 +20,7 @@
 // HBM with coalesced row reads, and the mirrored reads hit rows that the L2 of
 // the XCD owning the band of tiles already holds.
 #pragma once
+#include <type_traits>
 #include "gsf_internal.h"
 
 namespace gsf {
@@ -41,7 +42,9 @@ struct ApplyArgs {
 
 // Rows of points per thread (RPT) is a template choice in {1, 2, 4}: more rows
 // amortise the LDS halo, fewer rows give more workgroups (and so more loads in
-// flight per CU).  The default below keeps the LDS tile under ~64 KB; the
+// flight per CU).  In 2D, RPT = 2 is the paired kernel (two rows computed
+// together, sharing each neighbour row); RPT = 1 and 4 take their rows one
+// after the other.  The default below keeps the LDS tile under ~64 KB; the
 // apply tuner may pick another one per (type, m, r).
 template <typename T, int M>
 struct Rows {
@@ -184,6 +187,175 @@ __global__ void __launch_bounds__(kThreads) bf_apply2d_kernel(ApplyArgs a) {
   }
 }
 
+// Two vertically adjacent points per thread: rows 2w and 2w+1 (w = wave) of
+// a 64 x 8 tile.  Every staged neighbour row is read from LDS once and used
+// by both points (2R+2 rows of 2R+1 neighbours per pair instead of two full
+// windows).  The rows are taken in phases in which every weight's plane and
+// position are fixed at compile time up to the row: mirrored rows above both
+// points, the row of point 0, the row of point 1, own rows below, and the
+// last row of point 1, so no weight load sits behind a branch.  A point's own
+// position (offset 0) gets a zero weight; the HBM traffic is that of one row
+// per thread on the same tile.
+template <typename T, int M, int R>
+__global__ void __launch_bounds__(kThreads) bf_apply2d_pair_kernel(ApplyArgs a) {
+  constexpr int TX = 64;
+  constexpr int TY = 8;
+  constexpr int LW = TX + 2 * R;
+  constexpr int LH = TY + 2 * R;
+  constexpr int NQ = 2 * R + 1;  // planes per plane row dy >= 1
+  __shared__ T us[LH * LW * M];
+  __shared__ double red[16];
+
+  const T* __restrict__ isqd = (const T*)a.isqd;
+  const T* __restrict__ x = (const T*)a.x;
+  T* __restrict__ y = (T*)a.y;
+  const int64_t W = a.cols, H = a.rows;
+
+  const int tile = xcd_tile(blockIdx.x, a.ntiles);
+  const int64_t ty0 = (int64_t)(tile / a.tiles_x) * TY;
+  const int64_t tx0 = (int64_t)(tile % a.tiles_x) * TX;
+  const bool zspace = (a.form != GSF_FORM_RW);
+
+  for (int e = threadIdx.x; e < LH * LW; e += kThreads) {
+    const int ly = e / LW, lx = e - (e / LW) * LW;
+    const int64_t gy = ty0 - R + ly, gx = tx0 - R + lx;
+    const bool in = gy >= 0 && gy < H && gx >= 0 && gx < W;
+    const int64_t p = gy * W + gx;
+    T s = T(1);
+    if (zspace && in) s = isqd[p];
+#pragma unroll
+    for (int c = 0; c < M; ++c) us[e * M + c] = in ? x[p * a.ldx + c] * s : T(0);
+  }
+  __syncthreads();
+
+  const int tx = threadIdx.x & 63, ly0 = 2 * (threadIdx.x >> 6);
+  const int64_t gx = tx0 + tx, gy0 = ty0 + ly0;
+  const bool valid0 = gy0 < H && gx < W, valid1 = gy0 + 1 < H && gx < W;
+  const int64_t p0 = valid0 ? gy0 * W + gx : 0;
+  const int64_t p1 = valid1 ? p0 + W : 0;
+  // byte offsets of the two points in a padded plane (32-bit, from uniform plane bases)
+  const uint32_t pv0 = ((uint32_t)p0 + (uint32_t)a.ppad) * (uint32_t)sizeof(T);
+  const uint32_t pv1 = ((uint32_t)p1 + (uint32_t)a.ppad) * (uint32_t)sizeof(T);
+  const uint32_t wb = (uint32_t)W * (uint32_t)sizeof(T);
+  const char* __restrict__ qb = (const char*)a.planes;
+  const ptrdiff_t qs = (ptrdiff_t)a.pstride * (ptrdiff_t)sizeof(T);
+  constexpr int TS = (int)sizeof(T);
+  const T* c0 = &us[((ly0 + R) * LW + tx + R) * M];
+  // Both points measure their neighbours against u0: acc0 = sum w0 (v - u0),
+  // acc1 = sum w1 (v - u0) and sw1 = sum w1, so that the Laplacian sums are
+  // -acc0 and (u1 - u0) sw1 - acc1.  One difference per neighbour and
+  // channel serves both points, and every term stays a difference of nearby
+  // values (no cancellation of whole values of u).  Skipped own positions
+  // carry a zero weight.
+  T u0[M], u1[M], acc0[M], acc1[M];
+  T sw1 = T(0);
+#pragma unroll
+  for (int c = 0; c < M; ++c) {
+    u0[c] = c0[c];
+    u1[c] = c0[LW * M + c];
+    acc0[c] = T(0);
+    acc1[c] = T(0);
+  }
+  // A row of the window: the weights of both points are loaded first (one
+  // uniform plane pointer per offset plus the lane's 32-bit byte offset),
+  // then the LDS neighbour row is consumed.  The empty asm makes the byte
+  // offsets opaque per row, so that the compiler keeps the plane pointers
+  // uniform instead of hoisting 64-bit per-lane sums of them.  F0/F1: which
+  // points take part; K0/K1: 0 own (plane q + dx, at o), 1 mirrored (q - dx,
+  // at o + dx), 2 the split row of the point itself (dx < 0 mirrored from
+  // plane -dx-1, dx > 0 own from plane dx-1, zero weight at dx = 0).
+  auto row = [&](const T* ur, const char* q0, const char* q1, uint32_t o0, uint32_t o1, auto F0, auto F1, auto K0,
+                 auto K1) {
+    __asm__ volatile("" : "+v"(o0), "+v"(o1));
+    T w0[NQ], w1[NQ];
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+      const int dx = i - R;
+      if constexpr (decltype(F0)::value) {
+        if constexpr (decltype(K0)::value == 0) w0[i] = *(const T*)(q0 + dx * qs + o0);
+        if constexpr (decltype(K0)::value == 1) w0[i] = *(const T*)(q0 - dx * qs + (o0 + (uint32_t)(dx * TS)));
+        if constexpr (decltype(K0)::value == 2) {
+          if (dx < 0) w0[i] = *(const T*)(qb + (-dx - 1) * qs + (o0 + (uint32_t)(dx * TS)));
+          if (dx > 0) w0[i] = *(const T*)(qb + (dx - 1) * qs + o0);
+          if (dx == 0) w0[i] = T(0);
+        }
+      }
+      if constexpr (decltype(F1)::value) {
+        if constexpr (decltype(K1)::value == 0) w1[i] = *(const T*)(q1 + dx * qs + o1);
+        if constexpr (decltype(K1)::value == 1) w1[i] = *(const T*)(q1 - dx * qs + (o1 + (uint32_t)(dx * TS)));
+        if constexpr (decltype(K1)::value == 2) {
+          if (dx < 0) w1[i] = *(const T*)(qb + (-dx - 1) * qs + (o1 + (uint32_t)(dx * TS)));
+          if (dx > 0) w1[i] = *(const T*)(qb + (dx - 1) * qs + o1);
+          if (dx == 0) w1[i] = T(0);
+        }
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+      const int dx = i - R;
+      if constexpr (decltype(F1)::value) sw1 += w1[i];
+#pragma unroll
+      for (int c = 0; c < M; ++c) {
+        const T dv = ur[dx * M + c] - u0[c];
+        if constexpr (decltype(F0)::value) acc0[c] = fma(w0[i], dv, acc0[c]);
+        if constexpr (decltype(F1)::value) acc1[c] = fma(w1[i], dv, acc1[c]);
+      }
+    }
+  };
+  using Y = std::true_type;
+  using N = std::false_type;
+  using OWN = std::integral_constant<int, 0>;
+  using MIR = std::integral_constant<int, 1>;
+  using SPL = std::integral_constant<int, 2>;
+  // plane q(0, dx) = dx - 1; q(dy, dx) = R + (dy - 1) (2R + 1) + dx + R for dy >= 1
+  auto qrow = [&](int dy) -> const char* { return qb + (ptrdiff_t)(R + (dy - 1) * NQ + R) * qs; };
+
+  // row -R: point 0 only, mirrored: plane q(R, -dx) at p0 - R W + dx
+  row(c0 - R * LW * M, qrow(R), qb, pv0 - (uint32_t)R * wb, 0u, Y{}, N{}, MIR{}, MIR{});
+  // rows -R+1 .. -1: both mirrored at p0 + a W + dx, planes q(-a, -dx), q(1 - a, -dx)
+#pragma unroll 1
+  for (int ar = R - 1; ar >= 1; --ar) {  // ar = -a
+    const uint32_t mrow = pv0 - (uint32_t)ar * wb;
+    row(c0 - ar * LW * M, qrow(ar), qrow(ar + 1), mrow, mrow, Y{}, Y{}, MIR{}, MIR{});
+  }
+  // row 0 (point 0's): point 0 split at p0; point 1 mirrored, plane q(1, -dx) at p0 + dx
+  row(c0, qb, qrow(1), pv0, pv0, Y{}, Y{}, SPL{}, MIR{});
+  // row 1 (point 1's): point 0 own q(1, dx) at p0; point 1 split at p1
+  row(c0 + LW * M, qrow(1), qb, pv0, pv1, Y{}, Y{}, OWN{}, SPL{});
+  // rows 2 .. R: both own, planes q(a, dx) at p0 and q(a - 1, dx) at p1
+#pragma unroll 1
+  for (int ar = 2; ar <= R; ++ar) row(c0 + ar * LW * M, qrow(ar), qrow(ar - 1), pv0, pv1, Y{}, Y{}, OWN{}, OWN{});
+  // row R + 1: point 1 only, own q(R, dx) at p1
+  row(c0 + (R + 1) * LW * M, qb, qrow(R), 0u, pv1, N{}, Y{}, OWN{}, OWN{});
+
+#pragma unroll
+  for (int c = 0; c < M; ++c) {
+    acc0[c] = -acc0[c];
+    acc1[c] = fma(u1[c] - u0[c], sw1, -acc1[c]);
+  }
+  double dotv = 0.0;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const bool valid = h == 0 ? valid0 : valid1;
+    const int64_t p = h == 0 ? p0 : p1;
+    if (valid) {
+      T xg[M], out[M];
+#pragma unroll
+      for (int c = 0; c < M; ++c) xg[c] = (a.form == GSF_FORM_LSYM) ? T(0) : x[p * a.ldx + c];
+      finish_point<T, M>(a.form, isqd[p], xg, h == 0 ? acc0 : acc1, out);
+#pragma unroll
+      for (int c = 0; c < M; ++c) y[p * a.ldy + c] = out[c];
+      if (M == 1 && a.dot != nullptr) dotv += (double)x[p * a.ldx] * (double)out[0];
+    }
+  }
+  if (a.dot != nullptr) {
+    double v[1] = {dotv};
+    block_sum<1>(v, red);
+    if (threadIdx.x == 0) a.dot[blockIdx.x] = v[0];
+  }
+}
+
 template <typename T, int M, int R, int RPT>
 __global__ void __launch_bounds__(kThreads) bf_apply1d_kernel(ApplyArgs a) {
   constexpr int TN = kThreads * RPT;
@@ -256,7 +428,14 @@ __global__ void __launch_bounds__(kThreads) bf_apply1d_kernel(ApplyArgs a) {
 
 template <typename T, int M, int R, int RPT>
 void launch_bf_tile(const ApplyArgs& a, int ndim, hipStream_t s, int* nblocks) {
-  if (ndim == 2) {
+  if (ndim == 2 && RPT == 2) {  // the 64 x 8 tile, two rows per thread computed together
+    ApplyArgs b = a;
+    b.tiles_x = (int)((a.cols + 63) / 64);
+    const int tiles_y = (int)((a.rows + 7) / 8);
+    b.ntiles = b.tiles_x * tiles_y;
+    *nblocks = b.ntiles;
+    bf_apply2d_pair_kernel<T, M, R><<<b.ntiles, kThreads, 0, s>>>(b);
+  } else if (ndim == 2) {
     constexpr int TY = 4 * RPT;
     ApplyArgs b = a;
     b.tiles_x = (int)((a.cols + 63) / 64);
