@@ -58,8 +58,10 @@ def _args():
 
 
 def kernels_only(a):
-    """Launch the dominant kernels alone (tuned tile choice), then a plain
-    device copy of 1 GiB whose counter readings calibrate the byte counters."""
+    """Launch the dominant kernels alone, every tile choice of the BF apply
+    (1, 2 and 4 rows per thread) for m = 1 and the block width, 10 launches
+    each, then a plain device copy of 1 GiB whose counter readings calibrate
+    the byte counters."""
     import torch
     import paper_1509_02468_amd as gsf
     from synth import WORKLOADS, make_signal
@@ -73,11 +75,13 @@ def kernels_only(a):
     x0 = torch.tensor(noisy.ravel(), dtype=dt, device="cuda")
     op = gsf.Operator(w["kind"], shape, x0, w["radius"], w["sigma_d"], w["sigma_r"], w["eps"], prec)
     for mm in sorted({1, m}):
-        op.tune_apply(mm, reps=5)
         xb = torch.randn((n, mm) if mm > 1 else (n,), dtype=dt, device="cuda")
         yb = torch.empty_like(xb)
-        for _ in range(10):
-            op.apply(xb, gsf.FORM_LSYM, out=yb)
+        for rows in ((1, 2, 4) if w["kind"] == "bf" else (0,)):
+            if rows:
+                op.set_apply_rows(mm, rows)
+            for _ in range(10):
+                op.apply(xb, gsf.FORM_LSYM, out=yb)
     src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
     dst = torch.empty_like(src)
     for _ in range(3):
@@ -391,16 +395,19 @@ def main():
     dom = m if rl[m][1] * (klob + 1) >= rl[1][1] * (kcg + 1) else 1
     algo, t_ms = rl[dom]
     achieved = algo / (t_ms * 1e-3) / 1e9
+    # HBM bytes per launch from the committed counter passes, for the tile the
+    # tuner chose (null when no entry covers that kernel)
     traffic = None
+    dom_rows = tuned[f"m{dom}"]["rows_per_thread"]
     if os.path.exists(TRAFFIC_FILE):
         try:
-            tr = json.load(open(TRAFFIC_FILE)).get(f"{a.workload}:m{dom}")
+            tr = json.load(open(TRAFFIC_FILE)).get(f"{a.workload}:m{dom}:rows{dom_rows}")
             traffic = tr.get("bytes_per_launch") if tr else None
         except Exception:
             traffic = None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": f"bf_apply2d m={dom}", "us_per_launch": round(t_ms * 1e3, 2),
+                "kernel": f"bf_apply2d m={dom} rows_per_thread={dom_rows}", "us_per_launch": round(t_ms * 1e3, 2),
                 "algorithmic_bytes_per_launch": algo,
                 "m1_us": round(rl[1][1] * 1e3, 2), f"m{m}_us": round(rl[m][1] * 1e3, 2)}
 
