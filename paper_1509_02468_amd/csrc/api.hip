@@ -583,6 +583,7 @@ gsf_status gsf_lobpcg_filter(const gsf_operator* h, const void* x0, void* x_out,
   rr.theta = w.theta;
   rr.st = w.st;
   rr.drop_tol = init.drop_tol;
+  rr.conv2 = op.desc.prec == GSF_F32 ? 1e-20 : 1e-28;
   rr.zero_tol = init.zero_tol;
 
   if (constraint) GSF_TRY(lob_launch_ynorm(a, nb, s));
@@ -597,6 +598,12 @@ gsf_status gsf_lobpcg_filter(const gsf_operator* h, const void* x0, void* x_out,
   GSF_TRY(lob_launch_gram(g, rr, op.desc.prec, s));
   rr.init = 0;
   GSF_TRY(lob_launch_mkernel(1, a, nb, m, 1, deg, s));  // X = X0 C, AX, W = R
+  // Without a preconditioner network or the constraint nothing between an
+  // update and the next Rayleigh-Ritz step reads the residual norms, so that
+  // step finalizes them (one launch less per iteration); the last update is
+  // finalized after the loop.
+  const bool fold = T == nullptr && !constraint;
+  bool pending = false;
   Poller poll(s, &w.st->active, info != nullptr && tol > 0.0);
   for (int k = 0; k < kmax; ++k) {
     if (!poll.keep_going(k)) break;
@@ -617,9 +624,14 @@ gsf_status gsf_lobpcg_filter(const gsf_operator* h, const void* x0, void* x_out,
     g.AS[0] = w.AX;
     g.AS[1] = w.AW;
     g.AS[2] = w.AP;
+    rr.fin_partials = pending ? w.vpart : nullptr;
+    rr.fin_nparts = nb;
+    rr.fin_stride = 2 * m;
     GSF_TRY(lob_launch_gram(g, rr, op.desc.prec, s));
-    GSF_TRY(lob_launch_mkernel(1, a, nb, ns, 0, deg, s));
+    GSF_TRY(lob_launch_mkernel(fold ? 4 : 1, a, nb, ns, 0, deg, s));
+    pending = fold;
   }
+  if (pending) GSF_TRY(lob_launch_mkernel(5, a, nb, m, 0, deg, s));
   GSF_TRY(lob_launch_mkernel(2, a, nb, m, 0, deg, s));  // X^T z0, Y^T z0
   GSF_TRY(lob_launch_mkernel(3, a, nb, m, 0, deg, s));  // x_out
   if (info == nullptr) return GSF_OK;

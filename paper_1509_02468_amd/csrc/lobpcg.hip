@@ -437,8 +437,8 @@ __device__ __forceinline__ JRot jacobi_rot(double mpp, double mqq, double mpq, b
 // unconditionally (clamped indices) and only stores are masked, so a lane
 // never waits on a load inside a branch.
 template <int KB>
-__device__ void rayleigh_ritz_kb(RRShared& sh, int ns, int m, double drop_tol, double zero_tol, double* Cout,
-                                 double* theta, int* kept_out, int* nkept_out) {
+__device__ void rayleigh_ritz_kb(RRShared& sh, int ns, int m, double drop_tol, double zero_tol, double conv2,
+                                 double* Cout, double* theta, int* kept_out, int* nkept_out) {
   const int lane = threadIdx.x & 63;
   // unit-diagonal scaling: delta_j = diag(GB)_j^-1/2, 0 for a negligible column
   const int lj = lane < ns ? lane : 0;
@@ -623,8 +623,11 @@ __device__ void rayleigh_ritz_kb(RRShared& sh, int ns, int m, double drop_tol, d
       }
     }
   };
-  // convergence: off-diagonal Frobenius mass below 1e-14 of the whole
-  // (relative); the butterfly sum leaves the same value on every lane
+  // convergence: off-diagonal Frobenius mass below sqrt(conv2) of the whole
+  // (relative: 1e-14 for FP64 data, 1e-10 for FP32 data, whose Gram entries
+  // carry ~1e-7 relative errors anyway); the butterfly sum leaves the same
+  // value on every lane
+  const double c2 = conv2 > 0.0 ? conv2 : 1e-28;
   auto converged = [&](const double* Mc) {
     double off = 0.0, dia = 0.0;
     for (int e = lane; e < K * K; e += 64) {
@@ -635,7 +638,7 @@ __device__ void rayleigh_ritz_kb(RRShared& sh, int ns, int m, double drop_tol, d
     }
     off = wave_sum(off);
     dia = wave_sum(dia);
-    return off <= 1e-28 * (off + dia);
+    return off <= c2 * (off + dia);
   };
   int rnd = 0, sweep = 0, cur = 0;  // cur = 1: the current matrix is in M2, V2
   while (true) {
@@ -684,8 +687,9 @@ __device__ void rayleigh_ritz_kb(RRShared& sh, int ns, int m, double drop_tol, d
     for (int ii = KB - 1; ii >= 0; --ii) {
       const double z = Vc[(ii < K ? ii : 0) * LD + col];
       double v = ii < K ? z : 0.0;
+      // oldest coefficients first: c[ii] then waits for c[ii + 1] through one FMA
 #pragma unroll
-      for (int b = ii + 1; b < KB; ++b) v -= sh.LK[b * LD + ii] * c[b];
+      for (int b = KB - 1; b > ii; --b) v -= sh.LK[b * LD + ii] * c[b];
       c[ii] = v * sh.rinv[ii];
     }
     // sign: the largest-magnitude coefficient (first on ties) is positive, so
@@ -711,18 +715,18 @@ __device__ void rayleigh_ritz_kb(RRShared& sh, int ns, int m, double drop_tol, d
   for (int e = lane; e < ns * m; e += 64) Cout[e] = sh.Cs[e];
 }
 
-__device__ void rayleigh_ritz(RRShared& sh, int ns, int m, double drop_tol, double zero_tol, double* Cout,
-                              double* theta, int* kept_out, int* nkept_out) {
+__device__ void rayleigh_ritz(RRShared& sh, int ns, int m, double drop_tol, double zero_tol, double conv2,
+                              double* Cout, double* theta, int* kept_out, int* nkept_out) {
   if (ns <= 4)
-    rayleigh_ritz_kb<4>(sh, ns, m, drop_tol, zero_tol, Cout, theta, kept_out, nkept_out);
+    rayleigh_ritz_kb<4>(sh, ns, m, drop_tol, zero_tol, conv2, Cout, theta, kept_out, nkept_out);
   else if (ns <= 8)
-    rayleigh_ritz_kb<8>(sh, ns, m, drop_tol, zero_tol, Cout, theta, kept_out, nkept_out);
+    rayleigh_ritz_kb<8>(sh, ns, m, drop_tol, zero_tol, conv2, Cout, theta, kept_out, nkept_out);
   else if (ns <= 12)
-    rayleigh_ritz_kb<12>(sh, ns, m, drop_tol, zero_tol, Cout, theta, kept_out, nkept_out);
+    rayleigh_ritz_kb<12>(sh, ns, m, drop_tol, zero_tol, conv2, Cout, theta, kept_out, nkept_out);
   else if (ns <= 16)
-    rayleigh_ritz_kb<16>(sh, ns, m, drop_tol, zero_tol, Cout, theta, kept_out, nkept_out);
+    rayleigh_ritz_kb<16>(sh, ns, m, drop_tol, zero_tol, conv2, Cout, theta, kept_out, nkept_out);
   else
-    rayleigh_ritz_kb<KMAX>(sh, ns, m, drop_tol, zero_tol, Cout, theta, kept_out, nkept_out);
+    rayleigh_ritz_kb<KMAX>(sh, ns, m, drop_tol, zero_tol, conv2, Cout, theta, kept_out, nkept_out);
 }
 
 // First stage of the Gram reduction: workgroup (tile, chunk) sums the partials
@@ -752,7 +756,37 @@ __global__ void __launch_bounds__(kThreads) gram_rr_kernel(GramArgs g, RRArgs r)
   __shared__ RRShared sh;
   __shared__ int nkept;
   __shared__ int keptf[KMAX];
+  __shared__ double fred[8 * 16];
+  __shared__ int live;
   if (r.st != nullptr && !r.st->active) return;
+  if (r.fin_partials != nullptr) {
+    // the previous update's residual norms, iteration count and convergence
+    // test (what lob_final_kernel does after an update without the
+    // constraint, in the same summation order)
+    double t[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) t[k] = 0.0;
+    for (int b = threadIdx.x; b < r.fin_nparts; b += blockDim.x) {
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        if (k < g.m) t[k] += r.fin_partials[(size_t)b * r.fin_stride + k];
+    }
+    block_sum<8>(t, fred);
+    if (threadIdx.x == 0) {
+      LobpcgState* st = r.st;
+      double mx = 0.0;
+      for (int j = 0; j < g.m; ++j) {
+        st->res[j] = sqrt(t[j]);
+        st->yx[j] = 0.0;
+        mx = st->res[j] > mx ? st->res[j] : mx;
+      }
+      st->iters += 1;
+      live = !(st->tol > 0.0 && mx <= st->tol);
+      if (!live) st->active = 0;
+    }
+    __syncthreads();
+    if (!live) return;
+  }
   const int nt = (g.ns + 15) >> 4;
   const int ntb = n_tiles_b(nt), ntot = ntb + n_tiles_a(nt);
   for (int e = threadIdx.x; e < ntot * 256; e += blockDim.x) {
@@ -795,7 +829,7 @@ __global__ void __launch_bounds__(kThreads) gram_rr_kernel(GramArgs g, RRArgs r)
     }
   }
   if (threadIdx.x >= 64) return;
-  rayleigh_ritz(sh, g.ns, g.m, r.drop_tol, r.zero_tol, r.C, r.theta, keptf, &nkept);
+  rayleigh_ritz(sh, g.ns, g.m, r.drop_tol, r.zero_tol, r.conv2, r.C, r.theta, keptf, &nkept);
   wave_fence();
   if (threadIdx.x == 0 && r.st != nullptr) {
     LobpcgState* st = r.st;
@@ -1006,6 +1040,17 @@ void launch_m_kernels(int which, const LobArgs& a, int nb, int ns, int first, St
         lob_update_kernel<T, M, 3><<<nb, kThreads, 0, s>>>(a, first);
       lob_final_kernel<2 * M><<<1, kThreads, 0, s>>>(a.vpart, nb, a.st, 2, M, first, a.constraint);
       break;
+    case 4:
+      if (ns == M)
+        lob_update_kernel<T, M, 1><<<nb, kThreads, 0, s>>>(a, first);
+      else if (ns == 2 * M)
+        lob_update_kernel<T, M, 2><<<nb, kThreads, 0, s>>>(a, first);
+      else
+        lob_update_kernel<T, M, 3><<<nb, kThreads, 0, s>>>(a, first);
+      break;
+    case 5:
+      lob_final_kernel<2 * M><<<1, kThreads, 0, s>>>(a.vpart, nb, a.st, 2, M, first, a.constraint);
+      break;
     case 2:
       lob_out_dots_kernel<T, M><<<nb, kThreads, 0, s>>>(a);
       lob_final_kernel<M + 1><<<1, kThreads, 0, s>>>(a.vpart, nb, a.st, 3, M, 0, a.constraint);
@@ -1097,7 +1142,7 @@ __global__ void __launch_bounds__(kThreads) rr_only_kernel(const double* __restr
   }
   __syncthreads();
   if (threadIdx.x >= 64) return;
-  rayleigh_ritz(sh, ns, m, r.drop_tol, r.zero_tol, r.C, r.theta, keptf, &nkept);
+  rayleigh_ritz(sh, ns, m, r.drop_tol, r.zero_tol, r.conv2, r.C, r.theta, keptf, &nkept);
   wave_fence();
   if (threadIdx.x < ns) r.kept_out[threadIdx.x] = keptf[threadIdx.x];
   if (threadIdx.x == 0) *r.nkept_out = nkept;

@@ -46,6 +46,12 @@ struct RRArgs {
   double* theta;
   LobpcgState* st;     // nullable
   double drop_tol, zero_tol;
+  double conv2;        // Jacobi stop: off-diagonal mass <= conv2 * total (0: 1e-28)
+  // nullable: per-workgroup partials of the previous update (stride values
+  // per workgroup, residual norms first) to finalize before the Rayleigh-Ritz
+  // step, in place of a separate finalize launch (no constraint)
+  const double* fin_partials;
+  int fin_nparts, fin_stride;
   double* gram_out;    // nullable: GA then GB (ns x ns)
   int* kept_out;       // nullable
   int* nkept_out;      // nullable
@@ -55,6 +61,8 @@ struct RRArgs {
 int gram_tiles_total(int ns);
 gsf_status lob_launch_ynorm(const LobArgs& a, int nb, hipStream_t s);
 // which: 0 start, 1 update (ns, first), 2 output dots, 3 output
+// which: 0 start block, 1 update + finalize, 2 output dots, 3 output,
+// 4 update without the finalize (see RRArgs::fin_partials), 5 the finalize alone
 gsf_status lob_launch_mkernel(int which, const LobArgs& a, int nb, int ns, int first, StartDegrees deg,
                               hipStream_t s);
 gsf_status lob_launch_project(const LobArgs& a, void* B, int nb, hipStream_t s);
