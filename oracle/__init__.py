@@ -16,6 +16,9 @@ Contents (each function cites the passage it follows):
   solvers    power iteration (Section 4), preconditioned CG for Lx = 0
              (Algorithm 2), block LOBPCG as a low-pass filter (Algorithm 3,
              Section 6).
+  reguided   the non-linear (re-guided) power and CG filters: the graph is
+             rebuilt from the current iterate every step (Sections 2-3,
+             the first way to iterate BF and GF; Algorithm 2's flexible beta).
   spectral   dense spectral factorization eq. (8) and GFT low-pass filters.
   quality    PSNR.
   convnet    FP64 reference of the learned convolutional preconditioner
@@ -30,6 +33,7 @@ from .solvers import (power_filter, cg_filter, cg_filter_normalized, modulated_s
                       rayleigh_ritz, lobpcg_filter, CgInfo, LobpcgInfo, precondition, lobpcg_residual,
                       shifted_cg, ShiftedCgInfo)
 from . import convnet
+from .reguided import power_filter_reguided, cg_filter_reguided
 from .quality import psnr
 
 __all__ = [
@@ -39,4 +43,5 @@ __all__ = [
     "power_filter", "cg_filter", "cg_filter_normalized", "modulated_start", "modulation_degrees", "rayleigh_ritz",
     "lobpcg_filter", "CgInfo", "LobpcgInfo", "psnr", "precondition", "lobpcg_residual", "shifted_cg",
     "ShiftedCgInfo", "convnet",
+    "power_filter_reguided", "cg_filter_reguided",
 ]
