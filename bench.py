@@ -47,6 +47,7 @@ def _args():
     ap.add_argument("--serial", action="store_true", help="run CG and LOBPCG one after the other")
     ap.add_argument("--no-batch", action="store_true", help="skip the uneven-batch measurement")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner measurement")
+    ap.add_argument("--no-reguided", action="store_true", help="skip the re-guided (non-linear) filter measurement")
     ap.add_argument("--learned-images", type=int, default=200, help="training images (10 pairs each)")
     ap.add_argument("--learned-eval", type=int, default=2048, help="side of the evaluation image")
     ap.add_argument("--precision-study", action="store_true",
@@ -235,6 +236,46 @@ def learned_bench(n_images=200, side=512, eval_side=2048, tol=1e-6, kmax=20000, 
             "time_ratio_learned_over_plain": round(res["learned"]["ms"] / max(res["plain"]["ms"], 1e-9), 3)}
 
 
+def reguided_bench(steps=20, reps=3):
+    """The re-guided (non-linear) filters on the metric's workload: every step
+    rebuilds the BF graph from the current iterate.  Reports ms per step of
+    CG and of the power filter, and of the operator build alone (the share of
+    a step that the rebuild takes)."""
+    import torch
+    import paper_1509_02468_amd as gsf
+    from synth import WORKLOADS, make_signal
+    w = WORKLOADS["image_1024_bf11"]
+    shape = w["shape"]
+    _, noisy = make_signal("image_1024_bf11")
+    x0 = torch.tensor(noisy.ravel().astype(np.float32), device="cuda")
+    par = dict(radius=w["radius"], sigma_d=w["sigma_d"], sigma_r=w["sigma_r"])
+    out = {"workload": "image_1024_bf11, graph rebuilt from the iterate every step", "steps": steps}
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return float(np.median(ts))
+
+    for name, method in (("cg", gsf.METHOD_CG), ("power", gsf.METHOD_POWER)):
+        ws = gsf.reguided_workspace("bf", shape, method, **par, prec=gsf.F32)
+        y = torch.empty_like(x0)
+        ms = timed(lambda: gsf.reguided_filter("bf", shape, x0, method, steps, **par, prec=gsf.F32, out=y, ws=ws,
+                                               info=False))
+        out[f"{name}_ms_per_step"] = round(ms / steps, 4)
+    op = gsf.Operator("bf", shape, x0, **par, prec=gsf.F32)
+    ms = timed(lambda: [gsf.Operator("bf", shape, x0, **par, prec=gsf.F32, ws=op.ws) for _ in range(steps)])
+    out["build_ms"] = round(ms / steps, 4)
+    return out
+
+
 def precision_study(oracle_side=384):
     """Per-result errors of the precision modes: FP32 data with MFMA Gram and
     FP64 Rayleigh-Ritz against the all-FP64 GPU run at 4096^2, and both
@@ -413,6 +454,7 @@ def main():
 
     batch = None if a.no_batch else batch_bench()
     learned_res = None if a.no_learned else learned_bench(a.learned_images, eval_side=a.learned_eval)
+    reguided_res = None if a.no_reguided else reguided_bench()
     cpu = None if a.no_cpu else cpu_baseline(w, noisy, a.cpu_seconds)
     out = {"metric": "Mpixel-iters/s of Laplacian apply", "value": round(value, 1), "unit": "Mpixel-iters/s",
            "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(ms, 3),
@@ -421,7 +463,8 @@ def main():
            "config": {"workload": a.workload, "shape": list(shape), "operator": f"{w['kind']} r={w['radius']}",
                       "cg_iters": kcg, "lobpcg_iters": klob, "lobpcg_m": m, "parallelism": "single-gpu",
                       "apply_tuning": tuned, "cg_lobpcg_streams": 2 if concurrent else 1},
-           "roofline": roofline, "cpu_baseline": cpu, "batch": batch, "learned": learned_res}
+           "roofline": roofline, "cpu_baseline": cpu, "batch": batch, "learned": learned_res,
+           "reguided": reguided_res}
     print(json.dumps(out), flush=True)
 
 

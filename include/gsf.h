@@ -56,7 +56,7 @@ typedef enum {
 
 typedef enum { GSF_BF = 0, GSF_GF = 1 } gsf_kind;
 typedef enum { GSF_F32 = 0, GSF_F64 = 1 } gsf_prec;
-typedef enum { GSF_FORM_N = 0, GSF_FORM_LSYM = 1, GSF_FORM_RW = 2 } gsf_form;
+typedef enum { GSF_FORM_N = 0, GSF_FORM_LSYM = 1, GSF_FORM_RW = 2, GSF_FORM_L = 3 } gsf_form;
 typedef enum { GSF_METHOD_POWER = 0, GSF_METHOD_CG = 1, GSF_METHOD_LOBPCG = 2 } gsf_method;
 
 /* Operator description.
@@ -74,7 +74,8 @@ typedef enum { GSF_METHOD_POWER = 0, GSF_METHOD_CG = 1, GSF_METHOD_LOBPCG = 2 } 
  *          a GF operator has fewer than 2^27 points.
  *  prec    element type of the guidance, of all vectors and of the stored
  *          operator.  Weights and window statistics are always computed in
- *          FP64 and rounded once to this type.
+ *          FP64 and rounded once to this type; BF degrees are the FP64 row
+ *          sums of the stored weights.
  *  radius  1..8.
  *  sigma_d, sigma_r > 0 (BF; +inf allowed, removing that factor).
  *  gf_eps  >= 0 (GF). */
@@ -163,10 +164,11 @@ gsf_status gsf_build_operator(const gsf_operator_desc* desc, const void* guidanc
 gsf_status gsf_operator_get_layout(const gsf_operator* op, gsf_operator_layout* out);
 void gsf_destroy_operator(gsf_operator* op);
 
-/* ---- apply (eqs. (1), (3); Section 4) -------------------------------------
- * y = F x for a block of m (1..8) vectors, F = N, L_sym or D^-1 W (`form`).
- * N and L_sym act on z-space vectors (z = D^1/2 x); RW acts on x directly.
- * x and y: n*m elements, point-major; y must not overlap x. */
+/* ---- apply (eqs. (1), (3), (4); Section 4) --------------------------------
+ * y = F x for a block of m (1..8) vectors, F = N, L_sym, D^-1 W or the
+ * Laplacian L = D - W (`form`).  N and L_sym act on z-space vectors
+ * (z = D^1/2 x); RW and L act on x directly.  x and y: n*m elements,
+ * point-major; y must not overlap x.  GSF_EINVAL for another form. */
 gsf_status gsf_apply(const gsf_operator* op, int form, int m, const void* x, void* y,
                      void* stream);
 
@@ -300,6 +302,31 @@ gsf_status gsf_shifted_cg(const gsf_operator* op, double alpha, const void* b, i
                           void* stream);
 gsf_status gsf_lobpcg_residual(const gsf_operator* op, int m, const void* X, const double* theta,
                                void* R, void* stream);
+
+/* ---- re-guided (non-linear) filters (Sections 2 and 3) ------------------------
+ * The first of the two ways the paper gives to iterate the BF and the GF: the
+ * previous result is the guidance of the next step, so the graph is rebuilt
+ * (weights of eq. (2), or the statistics of Algorithm 1) from the current
+ * iterate before every step.  `desc` gives the kind, shape, precision and
+ * parameters as for gsf_build_operator; the guidance of step 1 is x0.
+ *   GSF_METHOD_POWER: x <- D(x)^-1 W(x) x, kmax passes (eq. (3) per pass).
+ *   GSF_METHOD_CG: Algorithm 2 in x-space with L and D rebuilt from the
+ *     current iterate at the start of every step (the flexible beta of
+ *     gsf_cg_filter, which the end of Section 5 names as the form for matrices
+ *     that change): s = D_k^-1 r, q = L_k p, r updated as printed
+ *     (r <- r - alpha q), r_0 = -L(x0) x0.  Stops, statuses and tol as for
+ *     gsf_cg_filter, with the breakdown floor (tau)^2 x0^T D(x0) x0 and
+ *     ||r|| measured as sqrt(s^T r); info->res is that of the last step taken.
+ * x0, x_out: n elements (they may be the same buffer).  ws: device memory of
+ * gsf_reguided_workspace_bytes(desc, method) bytes, 256-byte aligned; it holds
+ * the rebuilt operator and the solver vectors.  Each step costs one operator
+ * build; with FP32 data the graph is built from the stored FP32 iterate.
+ * GSF_EINVAL for a bad descriptor, method, kmax < 0 or tol; GSF_ENOMEM for a
+ * short workspace.  info may be NULL (then no host sync). */
+gsf_status gsf_reguided_workspace_bytes(const gsf_operator_desc* desc, int method, size_t* bytes);
+gsf_status gsf_reguided_filter(const gsf_operator_desc* desc, int method, const void* x0, void* x_out,
+                               int kmax, double tol, void* ws, size_t ws_bytes, gsf_cg_info* info,
+                               void* stream);
 
 /* ---- tuning ---------------------------------------------------------------
  * gsf_tune_apply: times the BF apply (form L_sym, block width m in

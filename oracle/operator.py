@@ -19,7 +19,7 @@ import numpy as np
 from .graph import bf_weight_matrix, degrees
 from .guided import guided_filter, gf_degrees, gf_stats
 
-FORM_N, FORM_LSYM, FORM_RW = 0, 1, 2
+FORM_N, FORM_LSYM, FORM_RW, FORM_L = 0, 1, 2, 3
 
 
 @dataclass
@@ -73,7 +73,7 @@ class GraphOperator:
         return self._scale(np.asarray(x, dtype=np.float64), self.d) - self.apply_w(x)
 
     def apply(self, form: int, v):
-        return {FORM_N: self.apply_n, FORM_LSYM: self.apply_lsym, FORM_RW: self.apply_rw}[form](v)
+        return {FORM_N: self.apply_n, FORM_LSYM: self.apply_lsym, FORM_RW: self.apply_rw, FORM_L: self.apply_l}[form](v)
 
     # -- normalized planes (for parity with a stored-operator build) --------
     def gf_window_stats(self):

@@ -26,6 +26,12 @@ gsf_status launch_cg_pupdate(const Operator& op, const void* r, void* p, const C
 gsf_status launch_dot(const Operator& op, const void* a, const void* b, double* partials, int* nparts,
                       const CgState* st, hipStream_t s);
 gsf_status launch_cg_alpha(const double* partials, int nparts, CgState* st, hipStream_t s);
+gsf_status launch_rg_init(const Operator& op, const void* x, void* r, double* partials, CgState* st, hipStream_t s);
+gsf_status launch_rg_s_beta(const Operator& op, const void* r, const void* r_old, void* sv, double* partials,
+                            CgState* st, hipStream_t s);
+gsf_status launch_rg_alpha(const double* partials, int nparts, CgState* st, hipStream_t s);
+gsf_status launch_rg_update(const Operator& op, void* x, void* r, void* r_old, const void* p, const void* q,
+                            const CgState* st, hipStream_t s);
 gsf_status launch_cg_update(const Operator& op, void* z, void* r, const void* p, const void* q, double* partials,
                             CgState* st, hipStream_t s);
 
@@ -198,6 +204,44 @@ size_t carve_cg(const Operator& op, char* base, CgWs* w) {
   w->partials = (double*)c.take((size_t)nb * 2 * sizeof(double));
   w->st = (CgState*)c.take(sizeof(CgState));
   return c.off;
+}
+
+// Re-guided filters: the operator (rebuilt in place every step), then for CG
+// x-space r, r_old, s, p, q, partials and state; for the power filter one
+// spare iterate.
+struct RgWs {
+  Operator op;
+  void *r, *r_old, *s, *p, *q, *tmp;
+  double* partials;
+  CgState* st;
+};
+
+size_t carve_rg(const gsf_operator_desc* d, int method, char* base, RgWs* w) {
+  Carve c{base};
+  char* ob = (char*)c.take(align_up(layout_operator(d, nullptr, nullptr), kAlign));
+  layout_operator(d, &w->op, ob);
+  const size_t v = (size_t)w->op.n * w->op.elem;
+  if (method == GSF_METHOD_POWER) {
+    w->tmp = c.take(v);
+    return c.off;
+  }
+  w->r = c.take(v);
+  w->r_old = c.take(v);
+  w->s = c.take(v);
+  w->p = c.take(v);
+  w->q = c.take(v);
+  int nb = vec_blocks(w->op.n);
+  if (d->kind == GSF_BF) {
+    const int ab = bf_apply_blocks(w->op, 1);
+    nb = ab > nb ? ab : nb;
+  }
+  w->partials = (double*)c.take((size_t)nb * 2 * sizeof(double));
+  w->st = (CgState*)c.take(sizeof(CgState));
+  return c.off;
+}
+
+gsf_status build_any(const Operator& op, const void* guidance, hipStream_t s) {
+  return op.desc.kind == GSF_BF ? launch_bf_build(op, guidance, s) : launch_gf_build(op, guidance, s);
 }
 
 struct LobWs {
@@ -432,7 +476,7 @@ void gsf_destroy_operator(gsf_operator* h) { delete h; }
 
 gsf_status gsf_apply(const gsf_operator* h, int form, int m, const void* x, void* y, void* stream) {
   if (h == nullptr || x == nullptr || y == nullptr) return GSF_EINVAL;
-  if (form != GSF_FORM_N && form != GSF_FORM_LSYM && form != GSF_FORM_RW) return GSF_EINVAL;
+  if (form != GSF_FORM_N && form != GSF_FORM_LSYM && form != GSF_FORM_RW && form != GSF_FORM_L) return GSF_EINVAL;
   if (m < 1 || m > kMaxBlock) return GSF_EINVAL;
   const Operator& op = h->op;
   const size_t bytes = (size_t)op.n * m * op.elem;
@@ -652,6 +696,84 @@ gsf_status gsf_lobpcg_filter(const gsf_operator* h, const void* x0, void* x_out,
     info->res[j] = j < m ? host.res[j] : 0.0;
     info->theta[j] = j < m ? host.theta[j] : 0.0;
   }
+  return status;
+}
+
+// ---- re-guided (non-linear) filters -----------------------------------------
+gsf_status gsf_reguided_workspace_bytes(const gsf_operator_desc* desc, int method, size_t* bytes) {
+  if (bytes == nullptr || (method != GSF_METHOD_POWER && method != GSF_METHOD_CG)) return GSF_EINVAL;
+  GSF_TRY(validate_desc(desc));
+  RgWs w;
+  *bytes = carve_rg(desc, method, nullptr, &w);
+  return GSF_OK;
+}
+
+gsf_status gsf_reguided_filter(const gsf_operator_desc* desc, int method, const void* x0, void* x_out, int kmax,
+                               double tol, void* ws, size_t ws_bytes, gsf_cg_info* info, void* stream) {
+  if (x0 == nullptr || x_out == nullptr || kmax < 0 || !(tol >= 0.0) || !std::isfinite(tol)) return GSF_EINVAL;
+  if (method != GSF_METHOD_POWER && method != GSF_METHOD_CG) return GSF_EINVAL;
+  GSF_TRY(validate_desc(desc));
+  RgWs w;
+  if (ws == nullptr || ws_bytes < carve_rg(desc, method, nullptr, &w)) return GSF_ENOMEM;
+  carve_rg(desc, method, (char*)ws, &w);
+  const Operator& op = w.op;
+  hipStream_t s = (hipStream_t)stream;
+  const size_t v = (size_t)op.n * op.elem;
+  if (x_out != x0) GSF_TRY(hip_ok(hipMemcpyAsync(x_out, x0, v, hipMemcpyDeviceToDevice, s)));
+  if (method == GSF_METHOD_POWER) {
+    // x <- D(x)^-1 W(x) x, the graph built from the current iterate each pass
+    char* a = (char*)x_out;
+    char* b = (char*)w.tmp;
+    for (int k = 0; k < kmax; ++k) {
+      GSF_TRY(build_any(op, a, s));
+      GSF_TRY(apply_any(op, GSF_FORM_RW, 1, a, 1, b, 1, nullptr, nullptr, s));
+      char* t = a;
+      a = b;
+      b = t;
+    }
+    if (a != (char*)x_out) GSF_TRY(hip_ok(hipMemcpyAsync(x_out, a, v, hipMemcpyDeviceToDevice, s)));
+    if (info != nullptr) {
+      info->iters = kmax;
+      info->status = GSF_OK;
+      info->res0 = 0.0;
+      info->res = 0.0;
+    }
+    return GSF_OK;
+  }
+  // Algorithm 2 in x-space with L_k, D_k from the current iterate x (x_out)
+  CgState init{};
+  init.tol = tol;
+  init.tau = breakdown_tau(op.desc.prec);
+  GSF_TRY(launch_cg_state_init(w.st, init, s));
+  GSF_TRY(build_any(op, x_out, s));
+  GSF_TRY(apply_any(op, GSF_FORM_L, 1, x_out, 1, w.r, 1, nullptr, nullptr, s));
+  GSF_TRY(launch_rg_init(op, x_out, w.r, w.partials, w.st, s));
+  Poller poll(s, &w.st->active, info != nullptr && tol > 0.0);
+  for (int k = 1; k <= kmax; ++k) {
+    if (!poll.keep_going(k - 1)) break;
+    if (k > 1) GSF_TRY(build_any(op, x_out, s));
+    GSF_TRY(launch_rg_s_beta(op, w.r, w.r_old, w.s, w.partials, w.st, s));
+    GSF_TRY(launch_cg_pupdate(op, w.s, w.p, w.st, s));
+    int nparts = 0;
+    if (op.desc.kind == GSF_BF) {
+      GSF_TRY(apply_any(op, GSF_FORM_L, 1, w.p, 1, w.q, 1, w.partials, &nparts, s));
+    } else {
+      GSF_TRY(apply_any(op, GSF_FORM_L, 1, w.p, 1, w.q, 1, nullptr, nullptr, s));
+      GSF_TRY(launch_dot(op, w.p, w.q, w.partials, &nparts, w.st, s));
+    }
+    GSF_TRY(launch_rg_alpha(w.partials, nparts, w.st, s));
+    GSF_TRY(launch_rg_update(op, x_out, w.r, w.r_old, w.p, w.q, w.st, s));
+  }
+  if (info == nullptr) return GSF_OK;
+  CgState host{};
+  GSF_TRY(hip_ok(hipMemcpyAsync(&host, w.st, sizeof(host), hipMemcpyDeviceToHost, s)));
+  GSF_TRY(hip_ok(hipStreamSynchronize(s)));
+  gsf_status status = (gsf_status)host.status;
+  if (status == GSF_OK && tol > 0.0 && host.active && !(host.rho <= host.tol2)) status = GSF_ENOTCONV;
+  info->iters = host.iters;
+  info->status = status;
+  info->res0 = host.res0;
+  info->res = std::sqrt(host.rho > 0.0 ? host.rho : 0.0);
   return status;
 }
 

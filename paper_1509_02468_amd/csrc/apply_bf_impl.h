@@ -1,8 +1,9 @@
 // Normalized BF operator apply (kernel templates), Section 2 eqs. (1)-(4) and
 // the normalisation of Section 4, evaluated in Laplacian form:
-//   u = D^-1/2 z                      (z-space input; RW form: u = x)
+//   u = D^-1/2 z                      (z-space input; RW and L forms: u = x)
 //   (L u)_i = sum_j w_ij (u_i - u_j)  (eq. (4): L = D - W, self-loop cancels)
-//   L_sym z = D^-1/2 L u,   N z = z - L_sym z,   D^-1 W x = x - D^-1 L x (eq. (3))
+//   L_sym z = D^-1/2 L u,   N z = z - L_sym z,   D^-1 W x = x - D^-1 L x (eq. (3)),
+//   L x = L u
 // Summing weighted neighbour differences keeps L_sym z accurate when z is
 // smooth (forming z - N z would cancel all but a few digits of FP32).
 //
@@ -67,6 +68,9 @@ __device__ __forceinline__ void finish_point(int form, T is, const T* __restrict
   } else if (form == GSF_FORM_N) {
 #pragma unroll
     for (int c = 0; c < M; ++c) out[c] = xg[c] - is * acc[c];
+  } else if (form == GSF_FORM_L) {
+#pragma unroll
+    for (int c = 0; c < M; ++c) out[c] = acc[c];
   } else {  // RW: x - D^-1 L x
     const T id = is * is;
 #pragma unroll
@@ -100,7 +104,7 @@ __global__ void __launch_bounds__(kThreads) bf_apply2d_kernel(ApplyArgs a) {
   const int tile = xcd_tile(blockIdx.x, a.ntiles);
   const int64_t ty0 = (int64_t)(tile / a.tiles_x) * TY;
   const int64_t tx0 = (int64_t)(tile % a.tiles_x) * TX;
-  const bool zspace = (a.form != GSF_FORM_RW);
+  const bool zspace = (a.form == GSF_FORM_N || a.form == GSF_FORM_LSYM);
 
   // stage u = D^-1/2 z (or x) with halo
   for (int e = threadIdx.x; e < LH * LW; e += kThreads) {
@@ -173,7 +177,7 @@ __global__ void __launch_bounds__(kThreads) bf_apply2d_kernel(ApplyArgs a) {
     if (valid) {
       T xg[M], out[M];
 #pragma unroll
-      for (int c = 0; c < M; ++c) xg[c] = (a.form == GSF_FORM_LSYM) ? T(0) : x[p * a.ldx + c];
+      for (int c = 0; c < M; ++c) xg[c] = (a.form == GSF_FORM_LSYM || a.form == GSF_FORM_L) ? T(0) : x[p * a.ldx + c];
       finish_point<T, M>(a.form, isqd[p], xg, acc, out);
 #pragma unroll
       for (int c = 0; c < M; ++c) y[p * a.ldy + c] = out[c];
@@ -214,7 +218,7 @@ __global__ void __launch_bounds__(32 * TY) bf_apply2d_pair_kernel(ApplyArgs a) {
   const int tile = xcd_tile(blockIdx.x, a.ntiles);
   const int64_t ty0 = (int64_t)(tile / a.tiles_x) * TY;
   const int64_t tx0 = (int64_t)(tile % a.tiles_x) * TX;
-  const bool zspace = (a.form != GSF_FORM_RW);
+  const bool zspace = (a.form == GSF_FORM_N || a.form == GSF_FORM_LSYM);
 
   for (int e = threadIdx.x; e < LH * LW; e += NT) {
     const int ly = e / LW, lx = e - (e / LW) * LW;
@@ -353,7 +357,7 @@ __global__ void __launch_bounds__(32 * TY) bf_apply2d_pair_kernel(ApplyArgs a) {
     if (valid) {
       T xg[M], out[M];
 #pragma unroll
-      for (int c = 0; c < M; ++c) xg[c] = (a.form == GSF_FORM_LSYM) ? T(0) : x[p * a.ldx + c];
+      for (int c = 0; c < M; ++c) xg[c] = (a.form == GSF_FORM_LSYM || a.form == GSF_FORM_L) ? T(0) : x[p * a.ldx + c];
       finish_point<T, M>(a.form, isqd[p], xg, h == 0 ? acc0 : acc1, out);
 #pragma unroll
       for (int c = 0; c < M; ++c) y[p * a.ldy + c] = out[c];
@@ -380,7 +384,7 @@ __global__ void __launch_bounds__(kThreads) bf_apply1d_kernel(ApplyArgs a) {
   T* __restrict__ y = (T*)a.y;
   const int64_t n = a.n;
   const int64_t base = (int64_t)blockIdx.x * TN;
-  const bool zspace = (a.form != GSF_FORM_RW);
+  const bool zspace = (a.form == GSF_FORM_N || a.form == GSF_FORM_LSYM);
 
   for (int e = threadIdx.x; e < LN; e += kThreads) {
     const int64_t g = base - R + e;
@@ -423,7 +427,7 @@ __global__ void __launch_bounds__(kThreads) bf_apply1d_kernel(ApplyArgs a) {
     if (valid) {
       T xg[M], out[M];
 #pragma unroll
-      for (int c = 0; c < M; ++c) xg[c] = (a.form == GSF_FORM_LSYM) ? T(0) : x[p * a.ldx + c];
+      for (int c = 0; c < M; ++c) xg[c] = (a.form == GSF_FORM_LSYM || a.form == GSF_FORM_L) ? T(0) : x[p * a.ldx + c];
       finish_point<T, M>(a.form, isqd[p], xg, acc, out);
 #pragma unroll
       for (int c = 0; c < M; ++c) y[p * a.ldy + c] = out[c];

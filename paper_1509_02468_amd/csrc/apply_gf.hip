@@ -211,7 +211,8 @@ struct GfStage1 {
   }
 };
 
-// (a, b) -> y = D^1/2 GF(u) (N), x - D^1/2 GF(u) (L_sym) or GF(x) (RW)
+// (a, b) -> y = D^1/2 GF(u) (N), x - D^1/2 GF(u) (L_sym), GF(x) (RW) or
+// D (x - GF(x)) = L x (L, with d = N/|w|)
 template <typename T, int MM>
 struct GfStage2 {
   static constexpr int M = MM;
@@ -239,7 +240,7 @@ struct GfStage2 {
     T g, x;
   };
   __device__ __forceinline__ Epi pre(int i, int j) const {
-    return Epi{g[i], form == GSF_FORM_LSYM ? x[i * ldx + j] : T(0)};
+    return Epi{g[i], (form == GSF_FORM_LSYM || form == GSF_FORM_L) ? x[i * ldx + j] : T(0)};
   }
   __device__ __forceinline__ void store(int i, int j, double sa, double sb, double rc, double src,
                                         const Epi& e) const {
@@ -247,6 +248,8 @@ struct GfStage2 {
     double out;
     if (form == GSF_FORM_RW) {
       out = gfu * rc;
+    } else if (form == GSF_FORM_L) {
+      out = ((double)e.x - gfu * rc) * (sromega * sromega / rc);  // d (x - GF(x)), d = N/|w|
     } else {
       const double nx = gfu * (src * sromega);  // (g sum a + sum b) / sqrt(N_i |w|)
       out = form == GSF_FORM_LSYM ? (double)e.x - nx : nx;
@@ -316,7 +319,7 @@ template <typename T, int M>
 void gf_apply_group(const Operator& op, T* ab, int form, const T* x, int64_t ldx, T* y, int64_t ldy,
                     hipStream_t s) {
   const GfGeom geo = gf_geom(op);
-  if (form == GSF_FORM_RW) {
+  if (form == GSF_FORM_RW || form == GSF_FORM_L) {
     GfStage1<T, M, false> p1{x, (int)ldx, (const T*)op.g, nullptr, (const T*)op.mu, (const T*)op.inv, ab};
     gf_box_kernel<GfStage1<T, M, false>><<<gf_grid(op, geo), kGfLanes, 0, s>>>(p1, geo);
   } else {

@@ -1,7 +1,7 @@
 // Operator construction: BF weights and normalisation (Section 2, eq. (2),
-// eq. (4); Section 4 normalisation) and GF window statistics (Section 3,
-// Algorithm 1).  Everything is computed in FP64 and rounded once to the
-// storage type.
+// eq. (4); Section 4 normalisation).  Weights are computed in FP64 and rounded
+// once to the storage type; the degrees are FP64 row sums of the stored
+// weights (so D 1 = W 1 holds for the operator that is applied).
 #include <cmath>
 
 #include "gsf_internal.h"
@@ -24,48 +24,16 @@ __device__ __forceinline__ double bf_weight(double gi, double gj, int o2, const 
   return exp(-((double)o2 * p.cs + dg * dg * p.cr));
 }
 
-// K1: d_i = sum over the truncated window of w_ij (self-loop w_ii = 1 included).
+// K1: half-window planes of the symmetric weights w_{i,i+o} (0 off the grid),
+// each undirected edge evaluated once.  Plane order: 1D o = 1..r; 2D (0, 1..r)
+// then dy = 1..r with dx = -r..r.  Plane q's data starts at
+// planes + ppad + q * pstride; every element of the plane region that is not
+// a weight (the ppad zeros before each plane and the tail up to the next one)
+// is written as zero: thread i covers index i of every plane's stride window,
+// threads i < ppad also the region's tail.
 template <typename T>
-__global__ void __launch_bounds__(kThreads) bf_degree_kernel(const T* __restrict__ g, double* __restrict__ deg,
-                                                             BfParams p) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= p.n) return;
-  const int r = p.radius;
-  const double gi = (double)g[i];
-  double d = 0.0;
-  if (p.ndim == 1) {
-    for (int o = -r; o <= r; ++o) {
-      const int64_t j = i + o;
-      if (j < 0 || j >= p.n) continue;
-      d += bf_weight(gi, (double)g[j], o * o, p);
-    }
-  } else {
-    const int64_t y = i / p.cols, x = i - y * p.cols;
-    for (int dy = -r; dy <= r; ++dy) {
-      const int64_t yy = y + dy;
-      if (yy < 0 || yy >= p.rows) continue;
-      for (int dx = -r; dx <= r; ++dx) {
-        const int64_t xx = x + dx;
-        if (xx < 0 || xx >= p.cols) continue;
-        d += bf_weight(gi, (double)g[yy * p.cols + xx], dy * dy + dx * dx, p);
-      }
-    }
-  }
-  deg[i] = d;
-}
-
-// K2: half-window planes of the symmetric weights w_{i,i+o} (0 off the grid),
-// 1/sqrt(d_i) and sqrt(d_i).  Plane order: 1D o = 1..r; 2D (0, 1..r) then
-// dy = 1..r with dx = -r..r.
-// Plane q's data starts at planes + ppad + q * pstride; every element of the
-// plane region that is not a weight (the ppad zeros before each plane and the
-// tail up to the next one) is written as zero: thread i covers index i of
-// every plane's stride window, threads i < ppad also the region's tail.
-template <typename T>
-__global__ void __launch_bounds__(kThreads) bf_fold_kernel(const T* __restrict__ g, const double* __restrict__ deg,
-                                                           T* __restrict__ planes, T* __restrict__ diag,
-                                                           T* __restrict__ sqd, BfParams p, int64_t pstride,
-                                                           int64_t ppad, int nplanes) {
+__global__ void __launch_bounds__(kThreads) bf_fold_kernel(const T* __restrict__ g, T* __restrict__ planes,
+                                                           BfParams p, int64_t pstride, int64_t ppad, int nplanes) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= pstride) return;
   if (t < ppad)
@@ -79,9 +47,6 @@ __global__ void __launch_bounds__(kThreads) bf_fold_kernel(const T* __restrict__
   planes += ppad;
   const int r = p.radius;
   const double gi = (double)g[i];
-  const double di = deg[i];
-  diag[i] = (T)(1.0 / sqrt(di));
-  sqd[i] = (T)sqrt(di);
   int q = 0;
   if (p.ndim == 1) {
     for (int o = 1; o <= r; ++o, ++q) {
@@ -107,9 +72,45 @@ __global__ void __launch_bounds__(kThreads) bf_fold_kernel(const T* __restrict__
   }
 }
 
+// K2: d_i = 1 + sum_o w_{i,i+o} + sum_o w_{i-o,i} (the self-loop w_ii = 1 and
+// both halves of the window), read from the stored planes, so that d is
+// exactly the row sum of the stored weights; 1/sqrt(d_i) and sqrt(d_i).  The
+// mirrored reads use the zero pads and wrap-around zeros of the planes (as
+// the apply does), so every load is unconditional.  FP64 sums.
+template <typename T>
+__global__ void __launch_bounds__(kThreads) bf_degree_kernel(const T* __restrict__ planes, double* __restrict__ deg,
+                                                             T* __restrict__ diag, T* __restrict__ sqd, BfParams p,
+                                                             int64_t pstride, int64_t ppad, int nplanes) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= p.n) return;
+  const T* base = planes + ppad + i;
+  const int r = p.radius;
+  double d0 = 1.0, d1 = 0.0;
+  if (p.ndim == 1) {
+    for (int o = 1; o <= r; ++o) {
+      const T* pl = base + (int64_t)(o - 1) * pstride;
+      d0 += (double)pl[0];
+      d1 += (double)pl[-o];
+    }
+  } else {
+    const int64_t W = p.cols;
+#pragma unroll 4
+    for (int q = 0; q < nplanes; ++q) {
+      // plane q -> offset (dy, dx): q < r: (0, q + 1); else dy = 1 + (q - r) / (2r+1)
+      const int dy = q < r ? 0 : 1 + (q - r) / (2 * r + 1);
+      const int dx = q < r ? q + 1 : (q - r) - (dy - 1) * (2 * r + 1) - r;
+      const T* pl = base + (int64_t)q * pstride;
+      d0 += (double)pl[0];
+      d1 += (double)pl[-(dy * W + dx)];
+    }
+  }
+  const double d = d0 + d1;
+  deg[i] = d;
+  diag[i] = (T)(1.0 / sqrt(d));
+  sqd[i] = (T)sqrt(d);
+}
 
-// K3: mu_k = mean of g over the truncated window, inv_k = 1/(corr_g - mu^2 + eps)
-// (Algorithm 1, mean_g, corr_g, var_g), d_k = N_k/|w|, sqrt(d_k); copy of g.
+// 1 / (2 sigma^2), 0 for sigma = inf (the factor of eq. (2) is then 1)
 inline double inv_two_sigma2(double s) { return std::isinf(s) ? 0.0 : 1.0 / (2.0 * s * s); }
 
 }  // namespace
@@ -120,15 +121,15 @@ gsf_status launch_bf_build(const Operator& op, const void* guidance, hipStream_t
   const unsigned grid = (unsigned)((op.n + kThreads - 1) / kThreads);
   const unsigned fgrid = (unsigned)((op.pstride + kThreads - 1) / kThreads);
   if (op.desc.prec == GSF_F32) {
-    bf_degree_kernel<float><<<grid, kThreads, 0, s>>>((const float*)guidance, op.deg, p);
-    bf_fold_kernel<float><<<fgrid, kThreads, 0, s>>>((const float*)guidance, op.deg, (float*)op.planes,
-                                                     (float*)op.diag, (float*)op.sqd, p, op.pstride, op.ppad,
-                                                     op.nplanes);
+    bf_fold_kernel<float><<<fgrid, kThreads, 0, s>>>((const float*)guidance, (float*)op.planes, p, op.pstride,
+                                                     op.ppad, op.nplanes);
+    bf_degree_kernel<float><<<grid, kThreads, 0, s>>>((const float*)op.planes, op.deg, (float*)op.diag,
+                                                      (float*)op.sqd, p, op.pstride, op.ppad, op.nplanes);
   } else {
-    bf_degree_kernel<double><<<grid, kThreads, 0, s>>>((const double*)guidance, op.deg, p);
-    bf_fold_kernel<double><<<fgrid, kThreads, 0, s>>>((const double*)guidance, op.deg, (double*)op.planes,
-                                                      (double*)op.diag, (double*)op.sqd, p, op.pstride, op.ppad,
-                                                      op.nplanes);
+    bf_fold_kernel<double><<<fgrid, kThreads, 0, s>>>((const double*)guidance, (double*)op.planes, p, op.pstride,
+                                                      op.ppad, op.nplanes);
+    bf_degree_kernel<double><<<grid, kThreads, 0, s>>>((const double*)op.planes, op.deg, (double*)op.diag,
+                                                       (double*)op.sqd, p, op.pstride, op.ppad, op.nplanes);
   }
   return hipGetLastError() == hipSuccess ? GSF_OK : GSF_EDEVICE;
 }

@@ -1,5 +1,6 @@
-// Vector kernels of the power iteration and of CG (Algorithm 2 in z-space),
-// with deterministic FP64 reductions: each workgroup writes one partial per
+// Vector kernels of the power iteration and of CG (Algorithm 2 in z-space, and
+// in x-space for the re-guided filter, whose D changes every step), with
+// deterministic FP64 reductions: each workgroup writes one partial per
 // quantity, and a one-workgroup kernel that follows on the stream sums them in
 // workgroup order and updates the solver state.  (Handing the partials over
 // inside one launch would need an agent-scope release fence per workgroup,
@@ -164,6 +165,137 @@ __global__ void __launch_bounds__(kThreads) cg_beta_kernel(const double* __restr
   }
 }
 
+// ---- re-guided CG: Algorithm 2 in x-space, the graph rebuilt every step ----
+// r holds L x0 on entry: r <- -L x0 (r_0 of Algorithm 2 with b = 0); partial
+// x0^T D x0 for the breakdown floor.
+template <typename T>
+__global__ void __launch_bounds__(kThreads) rg_init_kernel(const T* __restrict__ x, T* __restrict__ r,
+                                                           const double* __restrict__ deg, int64_t n,
+                                                           double* __restrict__ partials) {
+  __shared__ double red[16];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  double v[1] = {0.0};
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    r[i] = -r[i];
+    const double xi = (double)x[i];
+    v[0] += xi * deg[i] * xi;
+  }
+  block_sum<1>(v, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = v[0];
+}
+
+// one workgroup: the breakdown floor (tau^2 x0^T D x0) and the state before step 1
+__global__ void __launch_bounds__(kThreads) rg_init_final_kernel(const double* __restrict__ partials, int nparts,
+                                                                 CgState* st) {
+  __shared__ double red[16];
+  double t[1];
+  reduce_partials<1>(partials, nparts, 1, t, red);
+  if (threadIdx.x == 0) {
+    st->floor = st->tau * st->tau * t[0];
+    st->rho = 0.0;
+    st->rho0 = 0.0;
+    st->res0 = 0.0;
+    st->tol2 = -1.0;
+    st->iters = 0;
+    st->k = 1;
+    st->beta = 0.0;
+    st->status = GSF_OK;
+    st->active = 1;
+  }
+}
+
+// s = D_k^-1 r with the degrees of the graph built for this step; partials of
+// s^T r and (from step 2 on) s^T r_old, both from the unrounded FP64 s
+template <typename T>
+__global__ void __launch_bounds__(kThreads) rg_s_kernel(const T* __restrict__ r, const T* __restrict__ r_old,
+                                                        const double* __restrict__ deg, T* __restrict__ s,
+                                                        int64_t n, double* __restrict__ partials,
+                                                        const CgState* st) {
+  __shared__ double red[32];
+  if (!st->active) return;
+  const bool later = st->k > 1;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  double v[2] = {0.0, 0.0};
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const double ri = (double)r[i];
+    const double si = ri / deg[i];
+    s[i] = (T)si;
+    v[0] += si * ri;
+    if (later) v[1] += si * (double)r_old[i];
+  }
+  block_sum<2>(v, red);
+  if (threadIdx.x == 0) {
+    partials[2 * blockIdx.x] = v[0];
+    partials[2 * blockIdx.x + 1] = v[1];
+  }
+}
+
+// one workgroup: rho = s^T r, the tests before step k, and the flexible
+// beta = (s^T r - s^T r_old) / (s_old^T r_old)
+__global__ void __launch_bounds__(kThreads) rg_beta_kernel(const double* __restrict__ partials, int nparts,
+                                                           CgState* st) {
+  __shared__ double red[32];
+  if (!st->active) return;
+  double t[2];
+  reduce_partials<2>(partials, nparts, 2, t, red);
+  if (threadIdx.x == 0) {
+    const double rho = t[0];
+    const int k = st->k;
+    if (k == 1) {
+      st->rho0 = rho;
+      st->res0 = sqrt(rho > 0.0 ? rho : 0.0);
+      st->tol2 = st->tol > 0.0 ? st->tol * st->tol * rho : -1.0;
+    }
+    if (!(__builtin_isfinite(rho) && rho > st->floor)) {
+      st->status = GSF_EBREAKDOWN;
+      st->active = 0;
+    } else if (st->tol2 > 0.0 && rho <= st->tol2) {
+      st->active = 0;
+    } else {
+      st->beta = k == 1 ? 0.0 : (rho - t[1]) / st->rho;
+    }
+    st->rho = rho;
+  }
+}
+
+// one workgroup: p^T q, alpha = rho / p^T q, breakdown test; the step is then
+// counted (the update that follows completes it)
+__global__ void __launch_bounds__(kThreads) rg_alpha_kernel(const double* __restrict__ partials, int nparts,
+                                                            CgState* st) {
+  __shared__ double red[16];
+  if (!st->active) return;
+  double t[1];
+  reduce_partials<1>(partials, nparts, 1, t, red);
+  if (threadIdx.x == 0) {
+    const double pq = t[0];
+    st->pq = pq;
+    if (!(__builtin_isfinite(pq) && pq > 0.0)) {
+      st->status = GSF_EBREAKDOWN;
+      st->active = 0;
+    } else {
+      st->alpha = st->rho / pq;
+      st->iters = st->k;
+      st->k = st->k + 1;
+    }
+  }
+}
+
+// x += alpha p; r_old = r; r -= alpha q
+template <typename T>
+__global__ void __launch_bounds__(kThreads) rg_update_kernel(T* __restrict__ x, T* __restrict__ r,
+                                                             T* __restrict__ r_old, const T* __restrict__ p,
+                                                             const T* __restrict__ q, int64_t n, const CgState* st) {
+  if (!st->active) return;
+  const T alpha = (T)st->alpha;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    x[i] += alpha * p[i];
+    const T ri = r[i];
+    r_old[i] = ri;
+    r[i] = ri - alpha * q[i];
+  }
+}
+
 }  // namespace
 
 int vec_blocks(int64_t n) {
@@ -229,6 +361,46 @@ gsf_status launch_cg_update(const Operator& op, void* z, void* r, const void* p,
     cg_update_kernel<double><<<nb, kThreads, 0, s>>>((double*)z, (double*)r, (const double*)p, (const double*)q,
                                                      op.n, partials, st);
   cg_beta_kernel<<<1, kThreads, 0, s>>>(partials, nb, st);
+  return hipGetLastError() == hipSuccess ? GSF_OK : GSF_EDEVICE;
+}
+
+gsf_status launch_rg_init(const Operator& op, const void* x, void* r, double* partials, CgState* st, hipStream_t s) {
+  const int nb = vec_blocks(op.n);
+  if (op.desc.prec == GSF_F32)
+    rg_init_kernel<float><<<nb, kThreads, 0, s>>>((const float*)x, (float*)r, op.deg, op.n, partials);
+  else
+    rg_init_kernel<double><<<nb, kThreads, 0, s>>>((const double*)x, (double*)r, op.deg, op.n, partials);
+  rg_init_final_kernel<<<1, kThreads, 0, s>>>(partials, nb, st);
+  return hipGetLastError() == hipSuccess ? GSF_OK : GSF_EDEVICE;
+}
+
+gsf_status launch_rg_s_beta(const Operator& op, const void* r, const void* r_old, void* sv, double* partials,
+                            CgState* st, hipStream_t s) {
+  const int nb = vec_blocks(op.n);
+  if (op.desc.prec == GSF_F32)
+    rg_s_kernel<float><<<nb, kThreads, 0, s>>>((const float*)r, (const float*)r_old, op.deg, (float*)sv, op.n,
+                                               partials, st);
+  else
+    rg_s_kernel<double><<<nb, kThreads, 0, s>>>((const double*)r, (const double*)r_old, op.deg, (double*)sv,
+                                                op.n, partials, st);
+  rg_beta_kernel<<<1, kThreads, 0, s>>>(partials, nb, st);
+  return hipGetLastError() == hipSuccess ? GSF_OK : GSF_EDEVICE;
+}
+
+gsf_status launch_rg_alpha(const double* partials, int nparts, CgState* st, hipStream_t s) {
+  rg_alpha_kernel<<<1, kThreads, 0, s>>>(partials, nparts, st);
+  return hipGetLastError() == hipSuccess ? GSF_OK : GSF_EDEVICE;
+}
+
+gsf_status launch_rg_update(const Operator& op, void* x, void* r, void* r_old, const void* p, const void* q,
+                            const CgState* st, hipStream_t s) {
+  const int nb = vec_blocks(op.n);
+  if (op.desc.prec == GSF_F32)
+    rg_update_kernel<float><<<nb, kThreads, 0, s>>>((float*)x, (float*)r, (float*)r_old, (const float*)p,
+                                                    (const float*)q, op.n, st);
+  else
+    rg_update_kernel<double><<<nb, kThreads, 0, s>>>((double*)x, (double*)r, (double*)r_old, (const double*)p,
+                                                     (const double*)q, op.n, st);
   return hipGetLastError() == hipSuccess ? GSF_OK : GSF_EDEVICE;
 }
 

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libgsf.so")
 OK, EINVAL, ENOMEM, EDEVICE, ENOTCONV, EBREAKDOWN = range(6)
 BF, GF = 0, 1
 F32, F64 = 0, 1
-FORM_N, FORM_LSYM, FORM_RW = 0, 1, 2
+FORM_N, FORM_LSYM, FORM_RW, FORM_L = 0, 1, 2, 3
 METHOD_POWER, METHOD_CG, METHOD_LOBPCG = 0, 1, 2
 STATUS_NAMES = {OK: "ok", EINVAL: "einval", ENOMEM: "enomem", EDEVICE: "edevice",
                 ENOTCONV: "notconv", EBREAKDOWN: "breakdown"}
@@ -92,6 +92,8 @@ def load_library(path: str = LIB_PATH):
         "gsf_solver_workspace_bytes": ([vp, i32, i32, P(sz)], i32),
         "gsf_power_filter": ([vp, vp, vp, i32, vp, sz, vp], i32),
         "gsf_cg_filter": ([vp, vp, vp, i32, dbl, vp, sz, P(CgInfo), vp], i32),
+        "gsf_reguided_workspace_bytes": ([P(OperatorDesc), i32, P(sz)], i32),
+        "gsf_reguided_filter": ([P(OperatorDesc), i32, vp, vp, i32, dbl, vp, sz, P(CgInfo), vp], i32),
         "gsf_lobpcg_filter": ([vp, vp, vp, i32, i32, dbl, i32, vp, vp, vp, sz, P(LobpcgInfo), vp], i32),
         "gsf_block_gram": ([i32, i64, i32, i32, P(vp), P(vp), vp, vp, vp, sz, vp], i32),
         "gsf_block_gram_workspace_bytes": ([i64, P(sz)], i32),
@@ -164,6 +166,34 @@ def make_desc(kind, shape, radius, sigma_d=0.0, sigma_r=0.0, eps=0.0, prec=F32):
     d.sigma_r = sigma_r
     d.gf_eps = eps
     return d
+
+
+def reguided_workspace(kind, shape, method, radius, sigma_d=0.0, sigma_r=0.0, eps=0.0, prec=F32):
+    """Device workspace (uint8 tensor) for reguided_filter with these parameters."""
+    torch = _torch()
+    lib = load_library()
+    d = make_desc(kind, tuple(int(v) for v in shape), radius, sigma_d, sigma_r, eps, prec)
+    nbytes = ctypes.c_size_t()
+    _check(lib.gsf_reguided_workspace_bytes(ctypes.byref(d), method, ctypes.byref(nbytes)), "reguided_workspace_bytes")
+    return torch.empty(max(int(nbytes.value), 1), dtype=torch.uint8, device="cuda")
+
+
+def reguided_filter(kind, shape, x0, method, kmax, radius, sigma_d=0.0, sigma_r=0.0, eps=0.0, prec=F32, tol=0.0,
+                    out=None, ws=None, info=True, stream=None):
+    """Re-guided (non-linear) power or CG filter (gsf_reguided_filter): the
+    graph is rebuilt from the current iterate before every step.  x0: device
+    tensor of n values of the precision's dtype.  Returns (x, CgInfo or None)."""
+    torch = _torch()
+    lib = load_library()
+    d = make_desc(kind, tuple(int(v) for v in shape), radius, sigma_d, sigma_r, eps, prec)
+    if ws is None:
+        ws = reguided_workspace(kind, shape, method, radius, sigma_d, sigma_r, eps, prec)
+    y = out if out is not None else torch.empty_like(x0)
+    inf = CgInfo()
+    st = lib.gsf_reguided_filter(ctypes.byref(d), method, _ptr(x0), _ptr(y), kmax, tol, _ptr(ws), ws.numel(),
+                                 ctypes.byref(inf) if info else None, _stream(stream))
+    _check(st, "reguided_filter")
+    return y, (inf if info else None)
 
 
 class Batch:

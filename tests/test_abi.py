@@ -85,6 +85,24 @@ def test_size_limits(lib):
     assert not ok(kind=1, dims=(1 << 13, 1 << 14))
 
 
+def test_reguided_argument_checks(lib):
+    """The re-guided filter validates before any device work."""
+    sz = ctypes.c_size_t()
+    d = _desc()
+    assert lib.gsf_reguided_workspace_bytes(ctypes.byref(d), 2, ctypes.byref(sz)) == 1   # LOBPCG: no
+    assert lib.gsf_reguided_workspace_bytes(ctypes.byref(d), 0, ctypes.byref(sz)) == 0
+    power = sz.value
+    assert lib.gsf_reguided_workspace_bytes(ctypes.byref(d), 1, ctypes.byref(sz)) == 0
+    assert sz.value > power >= (60 + 2) * 64 * 80 * 4
+    assert lib.gsf_reguided_workspace_bytes(ctypes.byref(_desc(radius=0)), 1, ctypes.byref(sz)) == 1
+    fake = ctypes.c_void_p(0x1000)
+    assert lib.gsf_reguided_filter(ctypes.byref(d), 1, None, fake, 5, 0.0, fake, 1 << 30, None, None) == 1
+    assert lib.gsf_reguided_filter(ctypes.byref(d), 1, fake, fake, -1, 0.0, fake, 1 << 30, None, None) == 1
+    assert lib.gsf_reguided_filter(ctypes.byref(d), 1, fake, fake, 5, -1.0, fake, 1 << 30, None, None) == 1
+    assert lib.gsf_reguided_filter(ctypes.byref(d), 3, fake, fake, 5, 0.0, fake, 1 << 30, None, None) == 1
+    assert lib.gsf_reguided_filter(ctypes.byref(d), 1, fake, fake, 5, 0.0, fake, 16, None, None) == 2
+
+
 def test_build_rejects_small_workspace_and_nulls(lib):
     d = _desc()
     out = ctypes.c_void_p()

@@ -75,7 +75,13 @@ def _build(gsf, case, prec):
 @pytest.mark.parametrize("case", BF_CASES)
 def test_bf_build_parity(gsf, case, prec):
     op, ref, _ = _build(gsf, case, prec)
-    np.testing.assert_allclose(op.degree().cpu().numpy(), ref.d, rtol=1e-13)
+    # degrees: FP64 row sums of the stored weights (the oracle's W rounded to
+    # the storage type; for FP64 data that is the oracle's d itself)
+    Wst = ref.W.tocsr().astype(np.float32).astype(np.float64) if prec == gsf.F32 else ref.W.tocsr()
+    d_ref = np.asarray(Wst.sum(axis=1)).ravel()
+    np.testing.assert_allclose(op.degree().cpu().numpy(), d_ref, rtol=1e-13)
+    if prec == gsf.F64:
+        np.testing.assert_allclose(d_ref, ref.d, rtol=1e-13)
     assert rel(op.sqrt_d().cpu().numpy(), ref.sqrt_d) <= TOL[prec]
     assert rel(op.inv_sqrt_d().cpu().numpy(), 1.0 / ref.sqrt_d) <= TOL[prec]
     # half-window planes against the oracle's W: w_{i,i+o}

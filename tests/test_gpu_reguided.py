@@ -1,0 +1,197 @@
+"""GPU parity of the re-guided (non-linear) filters and of the Laplacian apply
+form they use, through the C ABI, against the FP64 oracle.
+
+Tolerances (relative, 2-norm and max-norm): FP64 data 1e-12 (power, 6
+passes) and 1e-11 (CG, up to 60 steps); FP32 data, against the oracle fed the
+FP32-rounded iterate before each rebuild, 1e-5 (power) and 1e-4 (CG).  Every
+step rebuilds the graph from the iterate, so summation-order differences also
+pass through the weights of eq. (2), which move by ~|g_i - g_j| / sigma_r^2
+(about 10) times a change of the guidance; the bounds leave one to two orders
+of margin over the measured errors (FP64 <= 2e-14, FP32 <= 7e-7 at 12 steps)
+for that growth with the step count.  The L form of the apply: 1e-12 FP64,
+1e-5 FP32 (a single apply, as the other forms).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from synth import piecewise_constant_1d, scene_2d
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64).ravel()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    den2 = max(np.linalg.norm(b), 1e-300)
+    deni = max(np.abs(b).max(), 1e-300)
+    return max(np.linalg.norm(a - b) / den2, np.abs(a - b).max() / deni)
+
+
+def _signal(shape, seed):
+    if len(shape) == 1:
+        return piecewise_constant_1d(shape[0], 0.1, seed)[1]
+    return scene_2d(shape[0], shape[1], 0.05, seed)[1].ravel()
+
+
+# (kind, shape, seed, params): several tiles plus ragged tails
+CASES = [
+    ("bf", (3000,), 21, dict(radius=4, sigma_d=3.0, sigma_r=0.2)),
+    ("bf", (67, 130), 22, dict(radius=3, sigma_d=2.0, sigma_r=0.15)),
+    ("gf", (1500,), 23, dict(radius=4, eps=1e-2)),
+    ("gf", (70, 131), 24, dict(radius=3, eps=1e-2)),
+]
+
+
+def _dev(x, prec, gsf):
+    import torch
+    dt = torch.float32 if prec == gsf.F32 else torch.float64
+    return torch.tensor(np.ascontiguousarray(x), dtype=dt, device="cuda")
+
+
+def _oracle_kw(par):
+    return dict(radius=par["radius"], sigma_s=par.get("sigma_d", 0.0), sigma_r=par.get("sigma_r", 0.0),
+                eps=par.get("eps", 0.0))
+
+
+def _gpu_kw(par):
+    return dict(radius=par["radius"], sigma_d=par.get("sigma_d", 0.0), sigma_r=par.get("sigma_r", 0.0),
+                eps=par.get("eps", 0.0))
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("m", [1, 3])
+@pytest.mark.parametrize("kind,shape,seed,par", CASES)
+def test_apply_laplacian_form(gsf, kind, shape, seed, par, m, prec):
+    """y = L x = D x - W x (eq. (4)) on x-space vectors."""
+    g = _signal(shape, seed)
+    if prec == gsf.F32:
+        g = g.astype(np.float32).astype(np.float64)
+    op = gsf.Operator(kind, shape, _dev(g, prec, gsf), **_gpu_kw(par), prec=prec)
+    ref_op = oracle.build_operator(kind, g.reshape(shape), **{k: v for k, v in _oracle_kw(par).items()})
+    x = np.random.default_rng(seed).standard_normal((op.n, m))
+    if prec == gsf.F32:
+        x = x.astype(np.float32).astype(np.float64)
+    xd = _dev(x if m > 1 else x[:, 0], prec, gsf)
+    y = op.apply(xd, gsf.FORM_L).cpu().numpy().reshape(op.n, m)
+    ref = np.stack([ref_op.apply_l(x[:, j]) for j in range(m)], axis=1)
+    e = rel(y, ref)
+    print(f"L form {kind} {shape} m={m} prec={prec}: {e:.2e}")
+    assert e <= (1e-12 if prec == gsf.F64 else 1e-5)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("kind,shape,seed,par", CASES)
+def test_reguided_power_parity(gsf, kind, shape, seed, par, prec):
+    x0 = _signal(shape, seed)
+    if prec == gsf.F32:
+        x0 = x0.astype(np.float32).astype(np.float64)
+    k = 6
+    y, info = gsf.reguided_filter(kind, shape, _dev(x0, prec, gsf), gsf.METHOD_POWER, k, **_gpu_kw(par), prec=prec)
+    ref = oracle.power_filter_reguided(kind, x0, shape, k, **_oracle_kw(par),
+                                       data_prec="f32" if prec == gsf.F32 else "f64")
+    e = rel(y.cpu().numpy(), ref)
+    print(f"re-guided power {kind} {shape} prec={prec}: {e:.2e}")
+    assert info.iters == k and e <= (1e-12 if prec == gsf.F64 else 1e-5)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("kind,shape,seed,par", CASES)
+def test_reguided_cg_parity(gsf, kind, shape, seed, par, prec):
+    x0 = _signal(shape, seed)
+    if prec == gsf.F32:
+        x0 = x0.astype(np.float32).astype(np.float64)
+    k = 12
+    y, info = gsf.reguided_filter(kind, shape, _dev(x0, prec, gsf), gsf.METHOD_CG, k, **_gpu_kw(par), prec=prec)
+    ref, rinfo = oracle.cg_filter_reguided(kind, x0, shape, k, **_oracle_kw(par),
+                                           data_prec="f32" if prec == gsf.F32 else "f64")
+    e = rel(y.cpu().numpy(), ref)
+    print(f"re-guided CG {kind} {shape} prec={prec}: {e:.2e}, iters {info.iters} vs {rinfo.iters}, "
+          f"res {info.res:.3e} vs {rinfo.res:.3e}")
+    assert info.status == gsf.OK and rinfo.status == "ok"
+    assert info.iters == rinfo.iters == k
+    assert e <= (1e-11 if prec == gsf.F64 else 1e-4)
+    assert abs(info.res0 - rinfo.res0) <= (1e-12 if prec == gsf.F64 else 1e-5) * rinfo.res0
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_reguided_cg_tolerance_stop(gsf, prec):
+    """tol > 0: stops at the same step as the oracle, status OK."""
+    kind, shape, seed, par = CASES[1]
+    x0 = _signal(shape, seed)
+    if prec == gsf.F32:
+        x0 = x0.astype(np.float32).astype(np.float64)
+    y, info = gsf.reguided_filter(kind, shape, _dev(x0, prec, gsf), gsf.METHOD_CG, 500, **_gpu_kw(par), prec=prec,
+                                  tol=1e-3)
+    ref, rinfo = oracle.cg_filter_reguided(kind, x0, shape, 500, **_oracle_kw(par), tol=1e-3,
+                                           data_prec="f32" if prec == gsf.F32 else "f64")
+    print(f"re-guided CG to 1e-3 prec={prec}: {info.iters} vs {rinfo.iters} steps")
+    assert info.status == gsf.OK and rinfo.status == "ok"
+    assert abs(info.iters - rinfo.iters) <= (0 if prec == gsf.F64 else 2)
+    assert rel(y.cpu().numpy(), ref) <= (1e-11 if prec == gsf.F64 else 1e-4)
+
+
+@pytest.mark.parametrize("shape,seed", [((3000,), 25), ((67, 130), 26)])
+def test_reguided_bf_without_range_kernel_equals_linear_gpu(gsf, shape, seed):
+    """sigma_r = inf: the graph does not depend on the guidance, so the
+    re-guided filters equal the linear ones (x-space against z-space CG)."""
+    x0 = _signal(shape, seed)
+    par = dict(radius=3, sigma_d=2.0, sigma_r=float("inf"))
+    xd = _dev(x0, gsf.F64, gsf)
+    op = gsf.Operator("bf", shape, xd, **par, prec=gsf.F64)
+    lin = op.power_filter(xd, 5).cpu().numpy()
+    rg, _ = gsf.reguided_filter("bf", shape, xd, gsf.METHOD_POWER, 5, **par, prec=gsf.F64)
+    assert rel(rg.cpu().numpy(), lin) <= 1e-12
+    lin, li = op.cg_filter(xd, 10)
+    rg, ri = gsf.reguided_filter("bf", shape, xd, gsf.METHOD_CG, 10, **par, prec=gsf.F64)
+    e = rel(rg.cpu().numpy(), lin.cpu().numpy())
+    print(f"sigma_r = inf {shape}: re-guided CG vs linear CG {e:.2e}")
+    assert ri.iters == li.iters == 10 and e <= 1e-10
+
+
+@pytest.mark.parametrize("kind,shape,seed,par", CASES)
+def test_reguided_edge_cases(gsf, kind, shape, seed, par):
+    """kmax = 0 copies x0; a constant is a fixed point of the power filter and
+    stops CG at once (r0 = 0) with x unchanged; in-place (x_out = x0) works."""
+    import torch
+    x0 = _signal(shape, seed)
+    xd = _dev(x0, gsf.F64, gsf)
+    y, info = gsf.reguided_filter(kind, shape, xd, gsf.METHOD_CG, 0, **_gpu_kw(par), prec=gsf.F64)
+    assert torch.equal(y, xd) and info.iters == 0
+    c = _dev(np.full(x0.size, 0.37), gsf.F64, gsf)
+    y, _ = gsf.reguided_filter(kind, shape, c, gsf.METHOD_POWER, 3, **_gpu_kw(par), prec=gsf.F64)
+    assert rel(y.cpu().numpy(), np.full(x0.size, 0.37)) <= 1e-14
+    y, info = gsf.reguided_filter(kind, shape, c, gsf.METHOD_CG, 3, **_gpu_kw(par), prec=gsf.F64)
+    assert info.status == gsf.EBREAKDOWN and torch.equal(y, c)
+    ref = oracle.power_filter_reguided(kind, x0, shape, 2, **_oracle_kw(par))
+    xin = xd.clone()
+    gsf.reguided_filter(kind, shape, xin, gsf.METHOD_POWER, 2, **_gpu_kw(par), prec=gsf.F64, out=xin)
+    assert rel(xin.cpu().numpy(), ref) <= 1e-11
+
+
+def test_reguided_fullsize_properties(gsf):
+    """The 1024^2 BF 11x11 FP32 workload: step 1 of the re-guided CG equals one
+    step of the linear CG (the graph of x0); the GF re-guided filters keep
+    1^T D x (its degrees N_i/|w| do not depend on the guidance)."""
+    import torch
+    from synth import WORKLOADS, make_signal
+    w = WORKLOADS["image_1024_bf11"]
+    _, x = make_signal("image_1024_bf11")
+    xd = torch.tensor(x.astype(np.float32).ravel(), device="cuda")
+    par = dict(radius=w["radius"], sigma_d=w["sigma_d"], sigma_r=w["sigma_r"])
+    op = gsf.Operator("bf", w["shape"], xd, **par, prec=gsf.F32)
+    lin, _ = op.cg_filter(xd, 1)
+    rg, ri = gsf.reguided_filter("bf", w["shape"], xd, gsf.METHOD_CG, 1, **par, prec=gsf.F32)
+    e = rel(rg.cpu().numpy(), lin.cpu().numpy())
+    print(f"1024^2 re-guided CG step 1 vs linear: {e:.2e}")
+    assert ri.iters == 1 and e <= 1e-5
+    rg5, ri5 = gsf.reguided_filter("bf", w["shape"], xd, gsf.METHOD_CG, 5, **par, prec=gsf.F32)
+    assert ri5.iters == 5 and bool(torch.isfinite(rg5).all())
+    shape = w["shape"]
+    d = oracle.gf_degrees(shape, 4).ravel()
+    m0 = float(d @ x.astype(np.float32).astype(np.float64).ravel())
+    for method in (gsf.METHOD_POWER, gsf.METHOD_CG):
+        y, _ = gsf.reguided_filter("gf", shape, xd, method, 5, radius=4, eps=1e-2, prec=gsf.F32)
+        m1 = float(d @ y.double().cpu().numpy())
+        print(f"1024^2 GF re-guided method {method}: 1^T D x {m0:.6e} -> {m1:.6e}")
+        assert abs(m1 - m0) <= 1e-5 * abs(m0)
