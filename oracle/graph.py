@@ -3,7 +3,8 @@
 Readings (the paper leaves these open):
   * Window: a square (Chebyshev) window |o|_inf <= r around each pixel, so a
     K = (2r+1)^d point neighbourhood; the spatial term of eq. (2) uses the
-    Euclidean distance ||o||^2 in pixel units.
+    Euclidean distance ||o||^2 in pixel units.  The image experiment of
+    Section 7 uses the 5-point stencil instead: the cross of radius 1.
   * Self-loop: eq. (1) sums over all j including j = i, and eq. (3) must
     reproduce that average, so w_ii = exp(0) * exp(0) = 1 belongs to W and D.
   * Boundary: windows are truncated at the border (no padding), which keeps
@@ -19,20 +20,36 @@ import numpy as np
 import scipy.sparse as sp
 
 
-def window_offsets(ndim: int, radius: int):
-    """All offsets o of the square window |o|_inf <= radius, including o = 0."""
+def window_offsets(ndim: int, radius: int, stencil: str = "square"):
+    """All offsets o of the neighbourhood, including o = 0: the square window
+    |o|_inf <= radius, or the cross (the offsets along one axis, |o_k| <=
+    radius; radius 1 in 2D is the 5-point stencil of the image experiment of
+    Section 7).  In 1D both are the same interval."""
     rng = range(-radius, radius + 1)
-    return [np.array(o, dtype=np.int64) for o in itertools.product(rng, repeat=ndim)]
+    if stencil == "square" or ndim == 1:
+        return [np.array(o, dtype=np.int64) for o in itertools.product(rng, repeat=ndim)]
+    if stencil != "cross":
+        raise ValueError(stencil)
+    offs = [np.zeros(ndim, dtype=np.int64)]
+    for axis in range(ndim):
+        for k in rng:
+            if k != 0:
+                o = np.zeros(ndim, dtype=np.int64)
+                o[axis] = k
+                offs.append(o)
+    return offs
 
 
-def bf_weight_matrix(g: np.ndarray, radius: int, sigma_s: float, sigma_r: float) -> sp.csr_matrix:
+def bf_weight_matrix(g: np.ndarray, radius: int, sigma_s: float, sigma_r: float,
+                     stencil: str = "square") -> sp.csr_matrix:
     """Adjacency W of the BF graph, eq. (2):
 
         w_ij = exp(-||p_i - p_j||^2 / (2 sigma_s^2)) * exp(-|g_i - g_j|^2 / (2 sigma_r^2))
 
-    for every j in the (border-truncated) window of i, w_ii = 1 included.
-    Pixels are numbered row-major; p_i are integer grid coordinates.
-    sigma_s = inf or sigma_r = inf switch the corresponding factor to 1.
+    for every j in the (border-truncated) neighbourhood of i (`stencil`, see
+    `window_offsets`), w_ii = 1 included.  Pixels are numbered row-major; p_i
+    are integer grid coordinates.  sigma_s = inf or sigma_r = inf switch the
+    corresponding factor to 1.
     """
     g = np.asarray(g, dtype=np.float64)
     shape = g.shape
@@ -40,7 +57,7 @@ def bf_weight_matrix(g: np.ndarray, radius: int, sigma_s: float, sigma_r: float)
     gf = g.ravel()
     coords = np.indices(shape).reshape(len(shape), -1).T  # (n, ndim) grid positions p_i
     rows, cols, vals = [], [], []
-    for o in window_offsets(len(shape), radius):
+    for o in window_offsets(len(shape), radius, stencil):
         nb = coords + o
         inside = np.all((nb >= 0) & (nb < np.array(shape)), axis=1)
         i = np.flatnonzero(inside)

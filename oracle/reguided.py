@@ -35,25 +35,28 @@ def _round(x, data_prec: str):
     return x.astype(np.float32).astype(np.float64) if data_prec == "f32" else x
 
 
-def _build(kind, x, shape, radius, sigma_s, sigma_r, eps, data_prec):
-    return build_operator(kind, _round(x, data_prec).reshape(shape), radius, sigma_s, sigma_r, eps)
+def _build(kind, x, shape, radius, sigma_s, sigma_r, eps, data_prec, stencil, norm):
+    return build_operator(kind, _round(x, data_prec).reshape(shape), radius, sigma_s, sigma_r, eps, stencil, norm)
 
 
 def power_filter_reguided(kind: str, x0, shape, kmax: int, radius: int, sigma_s: float = 0.0,
-                          sigma_r: float = 0.0, eps: float = 0.0, data_prec: str = "f64"):
-    """kmax passes of x <- D(x)^-1 W(x) x (the non-linear iterated BF / GF)."""
+                          sigma_r: float = 0.0, eps: float = 0.0, data_prec: str = "f64",
+                          stencil: str = "square", norm: str = "d"):
+    """kmax passes of x <- D(x)^-1 W(x) x (the non-linear iterated BF / GF;
+    the RW form of the chosen normalization, see `build_operator`)."""
     x = np.asarray(x0, dtype=np.float64).ravel().copy()
     for _ in range(kmax):
-        op = _build(kind, x, shape, radius, sigma_s, sigma_r, eps, data_prec)
+        op = _build(kind, x, shape, radius, sigma_s, sigma_r, eps, data_prec, stencil, norm)
         x = op.apply_rw(x)
     return x
 
 
 def cg_filter_reguided(kind: str, x0, shape, kmax: int, radius: int, sigma_s: float = 0.0,
-                       sigma_r: float = 0.0, eps: float = 0.0, tol: float = 0.0, data_prec: str = "f64"):
+                       sigma_r: float = 0.0, eps: float = 0.0, tol: float = 0.0, data_prec: str = "f64",
+                       stencil: str = "square", norm: str = "d"):
     """Algorithm 2 with the graph rebuilt from the current iterate every step."""
     x = np.asarray(x0, dtype=np.float64).ravel().copy()
-    op = _build(kind, x, shape, radius, sigma_s, sigma_r, eps, data_prec)
+    op = _build(kind, x, shape, radius, sigma_s, sigma_r, eps, data_prec, stencil, norm)
     floor = (BREAKDOWN_TOL[data_prec] ** 2) * float(x @ (op.d * x))
     r = -op.apply_l(x)
     info = CgInfo()
@@ -61,7 +64,7 @@ def cg_filter_reguided(kind: str, x0, shape, kmax: int, radius: int, sigma_s: fl
     rho0 = None
     for k in range(1, kmax + 1):
         if k > 1:
-            op = _build(kind, x, shape, radius, sigma_s, sigma_r, eps, data_prec)
+            op = _build(kind, x, shape, radius, sigma_s, sigma_r, eps, data_prec, stencil, norm)
         s = r / op.d
         rho = float(s @ r)
         if k == 1:
