@@ -48,6 +48,8 @@ def _args():
     ap.add_argument("--no-batch", action="store_true", help="skip the uneven-batch measurement")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner measurement")
     ap.add_argument("--no-reguided", action="store_true", help="skip the re-guided (non-linear) filter measurement")
+    ap.add_argument("--no-image-experiment", action="store_true",
+                    help="skip the 5-point-lattice (diag L) image experiment (PSNR after 20 CG / LOBPCG steps)")
     ap.add_argument("--learned-images", type=int, default=200, help="training images (10 pairs each)")
     ap.add_argument("--learned-eval", type=int, default=2048, help="side of the evaluation image")
     ap.add_argument("--precision-study", action="store_true",
@@ -276,6 +278,69 @@ def reguided_bench(steps=20, reps=3):
     return out
 
 
+def image_experiment_bench(reps=3, apply_reps=200):
+    """The image experiment of Section 7 on its synthetic stand-in: 1024^2
+    scene with noise variance 0.01, BF weights on the 5-point lattice
+    (sigma_r = 0.1), (diag L) normalization, FP32.  Reports the PSNR of the
+    noisy image and of 20 steps of CG and of LOBPCG (m = 1) with and without
+    the constraint, the time of each run and of the build, and the 5-point
+    apply (m = 1, L_sym form) against the HBM roofline: its algorithmic bytes
+    per pixel are x, 1/sqrt(d), the two own weight planes and y (5 x 4 B; the
+    mirrored weights and the neighbours' x come from cache)."""
+    import torch
+    import paper_1509_02468_amd as gsf
+    from synth import WORKLOADS, make_signal
+    name = "image_1024_cross5"
+    w = WORKLOADS[name]
+    shape = w["shape"]
+    clean, noisy = make_signal(name)
+    x0 = torch.tensor(noisy.ravel().astype(np.float32), device="cuda")
+    par = dict(radius=w["radius"], sigma_d=w["sigma_d"], sigma_r=w["sigma_r"], stencil=w["stencil"], norm=w["norm"])
+
+    def psnr(y):
+        y = y.double().cpu().numpy() if hasattr(y, "cpu") else np.asarray(y, dtype=np.float64)
+        return round(float(10.0 * np.log10(1.0 / np.mean((y.ravel() - clean.ravel()) ** 2))), 3)
+
+    def timed(fn, n=reps):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(n):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return float(np.median(ts))
+
+    op = gsf.Operator("bf", shape, x0, **par, prec=gsf.F32)
+    out = {"workload": f"{name}: {shape[0]}x{shape[1]}, 5-point lattice, sigma_r={w['sigma_r']}, diag L "
+                       f"normalization, FP32", "psnr_noisy": psnr(noisy)}
+    out["build_ms"] = round(timed(lambda: gsf.Operator("bf", shape, x0, **par, prec=gsf.F32, ws=op.ws)), 4)
+    k = w["cg_iters"]
+    ws = op.workspace(gsf.METHOD_CG, 1)
+    y = torch.empty_like(x0)
+    out["cg_ms"] = round(timed(lambda: op.cg_filter(x0, k, out=y, ws=ws, info=False)), 4)
+    out["psnr_cg"] = psnr(y)
+    m, kl = w["lobpcg_m"], w["lobpcg_iters"]
+    wsl = op.workspace(gsf.METHOD_LOBPCG, m)
+    for c in (False, True):
+        tag = "lobpcg_constraint" if c else "lobpcg"
+        out[f"{tag}_ms"] = round(timed(lambda: op.lobpcg_filter(x0, m, kl, constraint=c, out=y, ws=wsl,
+                                                                info=False)), 4)
+        out[f"psnr_{tag}"] = psnr(y)
+    out["iters"] = {"cg": k, "lobpcg": kl, "lobpcg_m": m}
+    z = torch.empty_like(x0)
+    ms = timed(lambda: [op.apply(x0, gsf.FORM_LSYM, out=z) for _ in range(apply_reps)], 3) / apply_reps
+    algo = 5 * 4 * op.n
+    out["apply"] = {"kernel": "bf_cross2d m=1 radius=1", "us_per_launch": round(ms * 1e3, 2),
+                    "algorithmic_bytes_per_launch": algo,
+                    "achieved_gbs": round(algo / (ms * 1e-3) / 1e9, 1),
+                    "frac": round(algo / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    return out
+
+
 def precision_study(oracle_side=384):
     """Per-result errors of the precision modes: FP32 data with MFMA Gram and
     FP64 Rayleigh-Ritz against the all-FP64 GPU run at 4096^2, and both
@@ -455,6 +520,7 @@ def main():
     batch = None if a.no_batch else batch_bench()
     learned_res = None if a.no_learned else learned_bench(a.learned_images, eval_side=a.learned_eval)
     reguided_res = None if a.no_reguided else reguided_bench()
+    image_res = None if a.no_image_experiment else image_experiment_bench()
     cpu = None if a.no_cpu else cpu_baseline(w, noisy, a.cpu_seconds)
     out = {"metric": "Mpixel-iters/s of Laplacian apply", "value": round(value, 1), "unit": "Mpixel-iters/s",
            "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(ms, 3),
@@ -464,7 +530,7 @@ def main():
                       "cg_iters": kcg, "lobpcg_iters": klob, "lobpcg_m": m, "parallelism": "single-gpu",
                       "apply_tuning": tuned, "cg_lobpcg_streams": 2 if concurrent else 1},
            "roofline": roofline, "cpu_baseline": cpu, "batch": batch, "learned": learned_res,
-           "reguided": reguided_res}
+           "reguided": reguided_res, "image_experiment": image_res}
     print(json.dumps(out), flush=True)
 
 

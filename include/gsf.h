@@ -58,9 +58,12 @@ typedef enum { GSF_BF = 0, GSF_GF = 1 } gsf_kind;
 typedef enum { GSF_F32 = 0, GSF_F64 = 1 } gsf_prec;
 typedef enum { GSF_FORM_N = 0, GSF_FORM_LSYM = 1, GSF_FORM_RW = 2, GSF_FORM_L = 3 } gsf_form;
 typedef enum { GSF_METHOD_POWER = 0, GSF_METHOD_CG = 1, GSF_METHOD_LOBPCG = 2 } gsf_method;
+typedef enum { GSF_STENCIL_SQUARE = 0, GSF_STENCIL_CROSS = 1 } gsf_stencil;
+typedef enum { GSF_NORM_D = 0, GSF_NORM_DIAGL = 1 } gsf_norm;
 
 /* Operator description.
- *  kind    GSF_BF: weights of eq. (2) over the square window |o|_inf <= radius,
+ *  kind    GSF_BF: weights of eq. (2) over the neighbourhood chosen by
+ *            `stencil` (default: the square window |o|_inf <= radius),
  *            w_ij = exp(-||p_i - p_j||^2 / (2 sigma_d^2) - (g_i - g_j)^2 / (2 sigma_r^2)),
  *            self-loop w_ii = 1 included, windows truncated at the border.
  *          GSF_GF: Algorithm 1 with mean filters of width 2*radius+1 over
@@ -78,7 +81,24 @@ typedef enum { GSF_METHOD_POWER = 0, GSF_METHOD_CG = 1, GSF_METHOD_LOBPCG = 2 } 
  *          sums of the stored weights.
  *  radius  1..8.
  *  sigma_d, sigma_r > 0 (BF; +inf allowed, removing that factor).
- *  gf_eps  >= 0 (GF). */
+ *  gf_eps  >= 0 (GF).
+ *  stencil BF only (GF: must be GSF_STENCIL_SQUARE, else GSF_EINVAL).
+ *          GSF_STENCIL_SQUARE: the square window above.  GSF_STENCIL_CROSS:
+ *          the offsets along one axis, |o_k| <= radius (radius 1 in 2D is
+ *          the 5-point stencil of the image experiment of Section 7); in 1D
+ *          both are the same interval.
+ *  norm    BF only (GF: must be GSF_NORM_D, else GSF_EINVAL).
+ *          GSF_NORM_D: the normalizing diagonal is D (self-loop included),
+ *          so RW = D^-1 W is eq. (3) and D the preconditioner of Algorithm 2.
+ *          GSF_NORM_DIAGL: the normalizing diagonal is diag L (Section 4),
+ *          diag L_i = sum_{j != i} w_ij (the self-loop cancels in L = D - W),
+ *          summed in FP64 from the stored off-diagonal weights; it replaces
+ *          D in N, L_sym, RW = I - (diag L)^-1 L, the preconditioner and the
+ *          z-space map z = (diag L)^1/2 x.  A vertex whose stored
+ *          off-diagonal weights are all zero has a zero row and column in L;
+ *          its normalizing value is taken as 1 (the vertex is then a fixed
+ *          point of every filter).  The L form stays L = D - W.
+ *  A zero-initialised stencil / norm selects the defaults. */
 typedef struct {
   int32_t kind;
   int32_t ndim;
@@ -88,15 +108,18 @@ typedef struct {
   double sigma_d;
   double sigma_r;
   double gf_eps;
+  int32_t stencil;  /* gsf_stencil */
+  int32_t norm;     /* gsf_norm */
 } gsf_operator_desc;
 
 typedef struct gsf_operator gsf_operator;   /* opaque host handle */
 
 /* Device layout of a built operator, for inspection (all pointers point into
  * the caller's operator workspace; element type = prec).
- *  BF: `planes` holds nplanes = ((2r+1)^ndim - 1)/2 planes of n values; plane
- *      o (half-window offsets in the order: 1D o = 1..r; 2D (dy, dx) with
- *      dy = 0, dx = 1..r, then dy = 1..r, dx = -r..r) stores the weight
+ *  BF: `planes` holds nplanes = ((2r+1)^ndim - 1)/2 planes of n values
+ *      (2D cross stencil: 2r); plane o (half-window offsets in the order:
+ *      1D o = 1..r; 2D (dy, dx) with dy = 0, dx = 1..r, then dy = 1..r,
+ *      dx = -r..r; 2D cross (0, 1..r) then (1..r, 0)) stores the weight
  *      w_{i,i+o} of eq. (2) at index i (0 where i+o is outside the grid);
  *      each undirected edge is stored once.  Plane q starts at
  *      planes + q * plane_stride and is preceded by r*W + r (2D) or r (1D)
@@ -109,7 +132,8 @@ typedef struct gsf_operator gsf_operator;   /* opaque host handle */
  *      NULL (the workspace also holds 16 scratch planes of the apply, which
  *      is why two GF applies on one operator must not run concurrently).
  *  Both: `inv_sqrt_d` holds 1/sqrt(d_i), `sqrt_d` sqrt(d_i); `degree` holds
- *  d_i in FP64. */
+ *  d_i in FP64, where d is the normalizing diagonal (D, or diag L with the
+ *  isolated-vertex value 1 for GSF_NORM_DIAGL). */
 typedef struct {
   int32_t kind, ndim, prec, radius;
   int64_t n;

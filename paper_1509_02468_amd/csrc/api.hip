@@ -74,6 +74,9 @@ gsf_status validate_desc(const gsf_operator_desc* d) {
   if (d->ndim != 1 && d->ndim != 2) return GSF_EINVAL;
   if (d->prec != GSF_F32 && d->prec != GSF_F64) return GSF_EINVAL;
   if (d->radius < 1 || d->radius > kMaxRadius) return GSF_EINVAL;
+  if (d->stencil != GSF_STENCIL_SQUARE && d->stencil != GSF_STENCIL_CROSS) return GSF_EINVAL;
+  if (d->norm != GSF_NORM_D && d->norm != GSF_NORM_DIAGL) return GSF_EINVAL;
+  if (d->kind == GSF_GF && (d->stencil != GSF_STENCIL_SQUARE || d->norm != GSF_NORM_D)) return GSF_EINVAL;
   if (d->dims[0] < 1) return GSF_EINVAL;
   if (d->ndim == 2 && d->dims[1] < 1) return GSF_EINVAL;
   const int64_t n = d->ndim == 1 ? d->dims[0] : d->dims[0] * d->dims[1];
@@ -119,8 +122,7 @@ size_t layout_operator(const gsf_operator_desc* d, Operator* op, char* base) {
     op->elem = elem;
   }
   if (d->kind == GSF_BF) {
-    const int k = d->ndim == 1 ? 2 * d->radius + 1 : (2 * d->radius + 1) * (2 * d->radius + 1);
-    const int np = (k - 1) / 2;
+    const int np = bf_num_planes(*d);
     // every plane is preceded by ppad zeros, so that the apply's mirrored
     // reads w_{i-o,i} above the first row (or before the first sample) read
     // zeros instead of branching

@@ -14,9 +14,12 @@ void launch_bf_m(const bfk::ApplyArgs& a, int ndim, int r, int m, int rpt, hipSt
   }
 }
 
-// Tuned rows-per-thread choices, per (precision, ndim, radius, block width,
-// size class); 0 = not tuned (use the default).  Written by the apply tuner.
-int g_rpt[2][2][kMaxRadius + 1][kMaxBlock + 1][4];
+// Tuned rows-per-thread choices, per (precision, geometry, radius, block
+// width, size class); geometry 0 = 1D, 1 = 2D square window, 2 = 2D cross;
+// 0 = not tuned (use the default).  Written by the apply tuner.
+int g_rpt[2][3][kMaxRadius + 1][kMaxBlock + 1][4];
+
+int geometry(const Operator& op) { return op.desc.ndim == 1 ? 0 : (bf_cross2d(op.desc) ? 2 : 1); }
 
 int size_class(int64_t n) { return n < (1 << 16) ? 0 : (n < (1 << 20) ? 1 : (n < (1 << 23) ? 2 : 3)); }
 
@@ -25,12 +28,12 @@ int width_of(int left) { return left >= 8 ? 8 : (left >= 4 ? 4 : left); }
 }  // namespace
 
 int bf_rpt(const Operator& op, int w) {
-  const int t = g_rpt[op.desc.prec][op.desc.ndim - 1][op.desc.radius][w][size_class(op.n)];
+  const int t = g_rpt[op.desc.prec][geometry(op)][op.desc.radius][w][size_class(op.n)];
   return t > 0 ? t : bfk::default_rpt((int)op.elem, w);
 }
 
 void bf_set_rpt(const Operator& op, int w, int rpt) {
-  g_rpt[op.desc.prec][op.desc.ndim - 1][op.desc.radius][w][size_class(op.n)] = rpt;
+  g_rpt[op.desc.prec][geometry(op)][op.desc.radius][w][size_class(op.n)] = rpt;
 }
 
 gsf_status launch_bf_apply_rpt(const Operator& op, int form, int m, const void* x, int64_t ldx, void* y,
@@ -49,6 +52,7 @@ gsf_status launch_bf_apply_rpt(const Operator& op, int form, int m, const void* 
   a.rows = op.rows;
   a.cols = op.cols;
   a.form = form;
+  a.cross = bf_cross2d(op.desc) ? 1 : 0;
   a.dot = dot;
   // split m into supported block widths (8, 4, 3, 2, 1)
   int c0 = 0;

@@ -37,6 +37,7 @@ struct ApplyArgs {
   int64_t ldx, ldy;
   int64_t n, rows, cols;
   int form;
+  int cross;  // 2D cross stencil (planes (0, 1..R) then (1..R, 0))
   int tiles_x, ntiles;
   double* dot;  // nullable, per-workgroup partial sum x.y (m = 1)
 };
@@ -371,6 +372,100 @@ __global__ void __launch_bounds__(32 * TY) bf_apply2d_pair_kernel(ApplyArgs a) {
   }
 }
 
+// Cross stencil in 2D (the offsets along one axis, |o_k| <= R; R = 1 is the
+// 5-point stencil): planes 0..R-1 hold the offsets (0, dx), planes R..2R-1
+// the offsets (dy, 0).  Tiling and staging as in the square-window kernel;
+// each point reads 2R own and 2R mirrored weights.
+template <typename T, int M, int R, int RPT>
+__global__ void __launch_bounds__(kThreads) bf_cross2d_kernel(ApplyArgs a) {
+  constexpr int TX = 64;
+  constexpr int TY = 4 * RPT;
+  constexpr int LW = TX + 2 * R;
+  constexpr int LH = TY + 2 * R;
+  __shared__ T us[LH * LW * M];
+  __shared__ double red[16];
+
+  const T* __restrict__ planes = (const T*)a.planes;
+  const T* __restrict__ isqd = (const T*)a.isqd;
+  const T* __restrict__ x = (const T*)a.x;
+  T* __restrict__ y = (T*)a.y;
+  const int64_t W = a.cols, H = a.rows;
+
+  const int tile = xcd_tile(blockIdx.x, a.ntiles);
+  const int64_t ty0 = (int64_t)(tile / a.tiles_x) * TY;
+  const int64_t tx0 = (int64_t)(tile % a.tiles_x) * TX;
+  const bool zspace = (a.form == GSF_FORM_N || a.form == GSF_FORM_LSYM);
+
+  for (int e = threadIdx.x; e < LH * LW; e += kThreads) {
+    const int ly = e / LW, lx = e - (e / LW) * LW;
+    const int64_t gy = ty0 - R + ly, gx = tx0 - R + lx;
+    const bool in = gy >= 0 && gy < H && gx >= 0 && gx < W;
+    const int64_t p = gy * W + gx;
+    T s = T(1);
+    if (zspace && in) s = isqd[p];
+#pragma unroll
+    for (int c = 0; c < M; ++c) us[e * M + c] = in ? x[p * a.ldx + c] * s : T(0);
+  }
+  __syncthreads();
+
+  const int tx = threadIdx.x & 63, wy = threadIdx.x >> 6;
+  const int64_t gx = tx0 + tx;
+  const size_t qstep = (size_t)a.pstride * sizeof(T);
+  double dotv = 0.0;
+#pragma unroll 1
+  for (int rr = 0; rr < RPT; ++rr) {
+    const int ly = wy * RPT + rr;
+    const int64_t gy = ty0 + ly;
+    const bool valid = gy < H && gx < W;
+    const int64_t p = valid ? gy * W + gx : 0;
+    const T* uc = &us[((ly + R) * LW + tx + R) * M];
+    T ui[M], acc[M];
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+      ui[c] = uc[c];
+      acc[c] = T(0);
+    }
+    const uint32_t pv = ((uint32_t)p + (uint32_t)a.ppad) * (uint32_t)sizeof(T);
+    const uint32_t wb = (uint32_t)W * (uint32_t)sizeof(T);
+    const char* __restrict__ qh = (const char*)planes;                  // plane (0, 1)
+    const char* __restrict__ qv = (const char*)planes + (size_t)R * qstep;  // plane (1, 0)
+#pragma unroll
+    for (int k = 1; k <= R; ++k) {
+      const T wo = *(const T*)(qh + pv);
+      const T wm = *(const T*)(qh + (pv - (uint32_t)(k * (int)sizeof(T))));
+      const T vo = *(const T*)(qv + pv);
+      const T vm = *(const T*)(qv + (pv - (uint32_t)k * wb));
+      qh += qstep;
+      qv += qstep;
+      const T* ul = uc + k * M;
+      const T* ur = uc - k * M;
+      const T* ud = uc + k * LW * M;
+      const T* uu = uc - k * LW * M;
+#pragma unroll
+      for (int c = 0; c < M; ++c) {
+        acc[c] = fma(wo, ui[c] - ul[c], acc[c]);
+        acc[c] = fma(wm, ui[c] - ur[c], acc[c]);
+        acc[c] = fma(vo, ui[c] - ud[c], acc[c]);
+        acc[c] = fma(vm, ui[c] - uu[c], acc[c]);
+      }
+    }
+    if (valid) {
+      T xg[M], out[M];
+#pragma unroll
+      for (int c = 0; c < M; ++c) xg[c] = (a.form == GSF_FORM_LSYM || a.form == GSF_FORM_L) ? T(0) : x[p * a.ldx + c];
+      finish_point<T, M>(a.form, isqd[p], xg, acc, out);
+#pragma unroll
+      for (int c = 0; c < M; ++c) y[p * a.ldy + c] = out[c];
+      if (M == 1 && a.dot != nullptr) dotv += (double)x[p * a.ldx] * (double)out[0];
+    }
+  }
+  if (a.dot != nullptr) {
+    double v[1] = {dotv};
+    block_sum<1>(v, red);
+    if (threadIdx.x == 0) a.dot[blockIdx.x] = v[0];
+  }
+}
+
 template <typename T, int M, int R, int RPT>
 __global__ void __launch_bounds__(kThreads) bf_apply1d_kernel(ApplyArgs a) {
   constexpr int TN = kThreads * RPT;
@@ -443,7 +538,15 @@ __global__ void __launch_bounds__(kThreads) bf_apply1d_kernel(ApplyArgs a) {
 
 template <typename T, int M, int R, int RPT>
 void launch_bf_tile(const ApplyArgs& a, int ndim, hipStream_t s, int* nblocks) {
-  if (ndim == 2 && RPT == 2) {  // two rows per thread computed together
+  if (ndim == 2 && a.cross) {
+    constexpr int TY = 4 * RPT;
+    ApplyArgs b = a;
+    b.tiles_x = (int)((a.cols + 63) / 64);
+    const int tiles_y = (int)((a.rows + TY - 1) / TY);
+    b.ntiles = b.tiles_x * tiles_y;
+    *nblocks = b.ntiles;
+    bf_cross2d_kernel<T, M, R, RPT><<<b.ntiles, kThreads, 0, s>>>(b);
+  } else if (ndim == 2 && RPT == 2) {  // two rows per thread computed together
     constexpr int PTY = 8;
     ApplyArgs b = a;
     b.tiles_x = (int)((a.cols + 63) / 64);

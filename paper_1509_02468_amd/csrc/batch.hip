@@ -161,17 +161,18 @@ gsf_status gsf_batch_create(const gsf_batch_item* items, int count, void* ws, si
   }
   if (st == GSF_OK) st = hip_ok(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming));
 
-  // BF apply tile per class (precision, dimension, radius, width, size): built
+  // BF apply tile per class (precision, geometry, radius, width, size): built
   // operator of the first item of each class, its solver workspace as scratch.
   if (st == GSF_OK && autotune) {
-    std::map<std::tuple<int, int, int, int, int>, bool> done;
+    std::map<std::tuple<int, int, int, int, int, int>, bool> done;
     for (int i = 0; i < count && st == GSF_OK; ++i) {
       const gsf_batch_item& it = items[i];
       if (it.op.kind != GSF_BF || it.method == GSF_METHOD_POWER) continue;
       const int w = item_m(it) >= 8 ? 8 : (item_m(it) >= 4 ? 4 : item_m(it));
       const int64_t n = desc[i].n;
       const int sc = n < (1 << 16) ? 0 : (n < (1 << 20) ? 1 : (n < (1 << 23) ? 2 : 3));
-      auto key = std::make_tuple(it.op.prec, it.op.ndim, it.op.radius, w, sc);
+      const int cross = bf_cross2d(it.op) ? 1 : 0;
+      auto key = std::make_tuple(it.op.prec, it.op.ndim, cross, it.op.radius, w, sc);
       if (done.count(key)) continue;
       done[key] = true;
       gsf_operator* tmp = nullptr;

@@ -1,7 +1,10 @@
 // Operator construction: BF weights and normalisation (Section 2, eq. (2),
 // eq. (4); Section 4 normalisation).  Weights are computed in FP64 and rounded
 // once to the storage type; the degrees are FP64 row sums of the stored
-// weights (so D 1 = W 1 holds for the operator that is applied).
+// weights (so D 1 = W 1 holds for the operator that is applied).  The
+// (diag L) normalisation sums the off-diagonal weights only: the self-loop
+// cancels in L = D - W, and leaving it out of the sum (rather than taking
+// d_i - 1) keeps a small diag L_i exact to the sum's rounding.
 #include <cmath>
 
 #include "gsf_internal.h"
@@ -14,7 +17,26 @@ struct BfParams {
   int radius, ndim;
   double cs;  // 1 / (2 sigma_d^2), 0 for sigma_d = inf
   double cr;  // 1 / (2 sigma_r^2), 0 for sigma_r = inf
+  int cross;  // 2D cross stencil: offsets (0, 1..r) and (1..r, 0) only
+  int diagl;  // normalise by diag L instead of D
 };
+
+// 2D plane q -> half-window offset (dy, dx).  Square: q < r: (0, q + 1), else
+// dy = 1 + (q - r) / (2r+1), dx = -r..r.  Cross: q < r: (0, q + 1), else
+// (q - r + 1, 0).
+__device__ __forceinline__ void plane_offset(int q, const BfParams& p, int& dy, int& dx) {
+  const int r = p.radius;
+  if (q < r) {
+    dy = 0;
+    dx = q + 1;
+  } else if (p.cross) {
+    dy = q - r + 1;
+    dx = 0;
+  } else {
+    dy = 1 + (q - r) / (2 * r + 1);
+    dx = (q - r) - (dy - 1) * (2 * r + 1) - r;
+  }
+}
 
 // eq. (2) in one exponential: exp(-(|o|^2 cs + (g_i - g_j)^2 cr)).  The
 // argument is bitwise the same for (i, j) and (j, i), so W is exactly
@@ -57,17 +79,16 @@ __global__ void __launch_bounds__(kThreads) bf_fold_kernel(const T* __restrict__
     }
   } else {
     const int64_t y = i / p.cols, x = i - y * p.cols;
-    for (int dy = 0; dy <= r; ++dy) {
-      const int dx0 = (dy == 0) ? 1 : -r;
-      for (int dx = dx0; dx <= r; ++dx, ++q) {
-        const int64_t yy = y + dy, xx = x + dx;
-        double v = 0.0;
-        if (yy < p.rows && xx >= 0 && xx < p.cols) {
-          const int64_t j = yy * p.cols + xx;
-          v = bf_weight(gi, (double)g[j], dy * dy + dx * dx, p);
-        }
-        planes[(int64_t)q * pstride + i] = (T)v;
+    for (; q < nplanes; ++q) {
+      int dy, dx;
+      plane_offset(q, p, dy, dx);
+      const int64_t yy = y + dy, xx = x + dx;
+      double v = 0.0;
+      if (yy < p.rows && xx >= 0 && xx < p.cols) {
+        const int64_t j = yy * p.cols + xx;
+        v = bf_weight(gi, (double)g[j], dy * dy + dx * dx, p);
       }
+      planes[(int64_t)q * pstride + i] = (T)v;
     }
   }
 }
@@ -75,8 +96,11 @@ __global__ void __launch_bounds__(kThreads) bf_fold_kernel(const T* __restrict__
 // K2: d_i = 1 + sum_o w_{i,i+o} + sum_o w_{i-o,i} (the self-loop w_ii = 1 and
 // both halves of the window), read from the stored planes, so that d is
 // exactly the row sum of the stored weights; 1/sqrt(d_i) and sqrt(d_i).  The
-// mirrored reads use the zero pads and wrap-around zeros of the planes (as
-// the apply does), so every load is unconditional.  FP64 sums.
+// (diag L) normalisation leaves out the self-loop and takes 1 where the sum
+// is 0 (a vertex with no edge of nonzero weight: its row and column of L are
+// zero, so any positive scale leaves L_sym unchanged).  The mirrored reads
+// use the zero pads and wrap-around zeros of the planes (as the apply does),
+// so every load is unconditional.  FP64 sums.
 template <typename T>
 __global__ void __launch_bounds__(kThreads) bf_degree_kernel(const T* __restrict__ planes, double* __restrict__ deg,
                                                              T* __restrict__ diag, T* __restrict__ sqd, BfParams p,
@@ -85,7 +109,7 @@ __global__ void __launch_bounds__(kThreads) bf_degree_kernel(const T* __restrict
   if (i >= p.n) return;
   const T* base = planes + ppad + i;
   const int r = p.radius;
-  double d0 = 1.0, d1 = 0.0;
+  double d0 = p.diagl ? 0.0 : 1.0, d1 = 0.0;
   if (p.ndim == 1) {
     for (int o = 1; o <= r; ++o) {
       const T* pl = base + (int64_t)(o - 1) * pstride;
@@ -96,15 +120,15 @@ __global__ void __launch_bounds__(kThreads) bf_degree_kernel(const T* __restrict
     const int64_t W = p.cols;
 #pragma unroll 4
     for (int q = 0; q < nplanes; ++q) {
-      // plane q -> offset (dy, dx): q < r: (0, q + 1); else dy = 1 + (q - r) / (2r+1)
-      const int dy = q < r ? 0 : 1 + (q - r) / (2 * r + 1);
-      const int dx = q < r ? q + 1 : (q - r) - (dy - 1) * (2 * r + 1) - r;
+      int dy, dx;
+      plane_offset(q, p, dy, dx);
       const T* pl = base + (int64_t)q * pstride;
       d0 += (double)pl[0];
       d1 += (double)pl[-(dy * W + dx)];
     }
   }
-  const double d = d0 + d1;
+  double d = d0 + d1;
+  if (d == 0.0) d = 1.0;  // only reachable for diag L
   deg[i] = d;
   diag[i] = (T)(1.0 / sqrt(d));
   sqd[i] = (T)sqrt(d);
@@ -116,8 +140,15 @@ inline double inv_two_sigma2(double s) { return std::isinf(s) ? 0.0 : 1.0 / (2.0
 }  // namespace
 
 gsf_status launch_bf_build(const Operator& op, const void* guidance, hipStream_t s) {
-  BfParams p{op.n, op.rows, op.cols, op.desc.radius, op.desc.ndim, inv_two_sigma2(op.desc.sigma_d),
-             inv_two_sigma2(op.desc.sigma_r)};
+  BfParams p{op.n,
+             op.rows,
+             op.cols,
+             op.desc.radius,
+             op.desc.ndim,
+             inv_two_sigma2(op.desc.sigma_d),
+             inv_two_sigma2(op.desc.sigma_r),
+             bf_cross2d(op.desc) ? 1 : 0,
+             op.desc.norm == GSF_NORM_DIAGL ? 1 : 0};
   const unsigned grid = (unsigned)((op.n + kThreads - 1) / kThreads);
   const unsigned fgrid = (unsigned)((op.pstride + kThreads - 1) / kThreads);
   if (op.desc.prec == GSF_F32) {

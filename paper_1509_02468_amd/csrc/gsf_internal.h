@@ -36,6 +36,16 @@ struct Operator {
 
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+// BF: the 2D cross stencil (1D cross is the square window's interval).
+inline bool bf_cross2d(const gsf_operator_desc& d) { return d.ndim == 2 && d.stencil == GSF_STENCIL_CROSS; }
+
+// BF half-window planes: one per undirected offset pair {o, -o}, o != 0.
+inline int bf_num_planes(const gsf_operator_desc& d) {
+  if (d.ndim == 1) return d.radius;
+  if (d.stencil == GSF_STENCIL_CROSS) return 2 * d.radius;
+  return ((2 * d.radius + 1) * (2 * d.radius + 1) - 1) / 2;
+}
+
 // ---------------------------------------------------------------------------
 // device helpers
 // ---------------------------------------------------------------------------

@@ -22,6 +22,11 @@ BF, GF = 0, 1
 F32, F64 = 0, 1
 FORM_N, FORM_LSYM, FORM_RW, FORM_L = 0, 1, 2, 3
 METHOD_POWER, METHOD_CG, METHOD_LOBPCG = 0, 1, 2
+STENCIL_SQUARE, STENCIL_CROSS = 0, 1
+NORM_D, NORM_DIAGL = 0, 1
+_STENCILS = {"square": STENCIL_SQUARE, "cross": STENCIL_CROSS, STENCIL_SQUARE: STENCIL_SQUARE,
+             STENCIL_CROSS: STENCIL_CROSS}
+_NORMS = {"d": NORM_D, "diagl": NORM_DIAGL, NORM_D: NORM_D, NORM_DIAGL: NORM_DIAGL}
 STATUS_NAMES = {OK: "ok", EINVAL: "einval", ENOMEM: "enomem", EDEVICE: "edevice",
                 ENOTCONV: "notconv", EBREAKDOWN: "breakdown"}
 
@@ -29,7 +34,8 @@ STATUS_NAMES = {OK: "ok", EINVAL: "einval", ENOMEM: "enomem", EDEVICE: "edevice"
 class OperatorDesc(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("ndim", ctypes.c_int32), ("dims", ctypes.c_int64 * 2),
                 ("prec", ctypes.c_int32), ("radius", ctypes.c_int32), ("sigma_d", ctypes.c_double),
-                ("sigma_r", ctypes.c_double), ("gf_eps", ctypes.c_double)]
+                ("sigma_r", ctypes.c_double), ("gf_eps", ctypes.c_double), ("stencil", ctypes.c_int32),
+                ("norm", ctypes.c_int32)]
 
 
 class OperatorLayout(ctypes.Structure):
@@ -154,7 +160,9 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
-def make_desc(kind, shape, radius, sigma_d=0.0, sigma_r=0.0, eps=0.0, prec=F32):
+def make_desc(kind, shape, radius, sigma_d=0.0, sigma_r=0.0, eps=0.0, prec=F32, stencil="square", norm="d"):
+    """gsf_operator_desc; stencil "square" / "cross" and norm "d" / "diagl"
+    (or the GSF_STENCIL_* / GSF_NORM_* values)."""
     d = OperatorDesc()
     d.kind = BF if kind in ("bf", BF) else GF
     d.ndim = len(shape)
@@ -165,29 +173,32 @@ def make_desc(kind, shape, radius, sigma_d=0.0, sigma_r=0.0, eps=0.0, prec=F32):
     d.sigma_d = sigma_d
     d.sigma_r = sigma_r
     d.gf_eps = eps
+    d.stencil = _STENCILS[stencil]
+    d.norm = _NORMS[norm]
     return d
 
 
-def reguided_workspace(kind, shape, method, radius, sigma_d=0.0, sigma_r=0.0, eps=0.0, prec=F32):
+def reguided_workspace(kind, shape, method, radius, sigma_d=0.0, sigma_r=0.0, eps=0.0, prec=F32, stencil="square",
+                       norm="d"):
     """Device workspace (uint8 tensor) for reguided_filter with these parameters."""
     torch = _torch()
     lib = load_library()
-    d = make_desc(kind, tuple(int(v) for v in shape), radius, sigma_d, sigma_r, eps, prec)
+    d = make_desc(kind, tuple(int(v) for v in shape), radius, sigma_d, sigma_r, eps, prec, stencil, norm)
     nbytes = ctypes.c_size_t()
     _check(lib.gsf_reguided_workspace_bytes(ctypes.byref(d), method, ctypes.byref(nbytes)), "reguided_workspace_bytes")
     return torch.empty(max(int(nbytes.value), 1), dtype=torch.uint8, device="cuda")
 
 
 def reguided_filter(kind, shape, x0, method, kmax, radius, sigma_d=0.0, sigma_r=0.0, eps=0.0, prec=F32, tol=0.0,
-                    out=None, ws=None, info=True, stream=None):
+                    out=None, ws=None, info=True, stream=None, stencil="square", norm="d"):
     """Re-guided (non-linear) power or CG filter (gsf_reguided_filter): the
     graph is rebuilt from the current iterate before every step.  x0: device
     tensor of n values of the precision's dtype.  Returns (x, CgInfo or None)."""
     torch = _torch()
     lib = load_library()
-    d = make_desc(kind, tuple(int(v) for v in shape), radius, sigma_d, sigma_r, eps, prec)
+    d = make_desc(kind, tuple(int(v) for v in shape), radius, sigma_d, sigma_r, eps, prec, stencil, norm)
     if ws is None:
-        ws = reguided_workspace(kind, shape, method, radius, sigma_d, sigma_r, eps, prec)
+        ws = reguided_workspace(kind, shape, method, radius, sigma_d, sigma_r, eps, prec, stencil, norm)
     y = out if out is not None else torch.empty_like(x0)
     inf = CgInfo()
     st = lib.gsf_reguided_filter(ctypes.byref(d), method, _ptr(x0), _ptr(y), kmax, tol, _ptr(ws), ws.numel(),
@@ -213,7 +224,7 @@ class Batch:
             it.setdefault("out", torch.empty_like(it["x0"]))
             b = self.arr[k]
             b.op = make_desc(it["kind"], it["shape"], it["radius"], it.get("sigma_d", 0.0), it.get("sigma_r", 0.0),
-                             it.get("eps", 0.0), prec)
+                             it.get("eps", 0.0), prec, it.get("stencil", "square"), it.get("norm", "d"))
             b.guidance = it["guidance"].data_ptr()
             b.x0 = it["x0"].data_ptr()
             b.x_out = it["out"].data_ptr()
@@ -251,22 +262,13 @@ class Operator:
     Owns its device workspace (a torch uint8 tensor)."""
 
     def __init__(self, kind, shape, guidance, radius, sigma_d=0.0, sigma_r=0.0, eps=0.0, prec=F32,
-                 stream=None, ws=None):
+                 stream=None, ws=None, stencil="square", norm="d"):
         torch = _torch()
         lib = load_library()
         shape = tuple(int(s) for s in shape)
         self.shape, self.prec, self.kind, self.radius = shape, prec, kind, radius
         self.n = int(np.prod(shape))
-        d = OperatorDesc()
-        d.kind = BF if kind in ("bf", BF) else GF
-        d.ndim = len(shape)
-        d.dims[0] = shape[0]
-        d.dims[1] = shape[1] if len(shape) == 2 else 1
-        d.prec = prec
-        d.radius = radius
-        d.sigma_d = sigma_d
-        d.sigma_r = sigma_r
-        d.gf_eps = eps
+        d = make_desc(kind, shape, radius, sigma_d, sigma_r, eps, prec, stencil, norm)
         self.desc = d
         nbytes = ctypes.c_size_t()
         _check(lib.gsf_operator_workspace_bytes(ctypes.byref(d), ctypes.byref(nbytes)), "operator_workspace_bytes")

@@ -10,6 +10,12 @@ image_4096_bf7   2D 4096x4096, G2, sigma=0.08, seed 3; BF 7x7, sigma_d=2,
 image_4096_gf8   same image; GF radius 8, eps=1e-2; LOBPCG(m=8) 100.
 image_2048_bf11  2D 2048x2048 evaluation images (seeds 5900..5903); BF 11x11,
                  sigma_d=2, sigma_r=0.1; LOBPCG(m=4) with the constraint, tol 1e-6.
+image_1024_cross5  2D 1024x1024, G2, sigma=0.1 (noise variance 0.01, so a
+                 noisy PSNR of about 20 dB), seed 7; BF on the 5-point (cross,
+                 radius 1) lattice, sigma_r=0.1, sigma_d=1 (a common factor
+                 of every weight, which the (diag L) normalization removes),
+                 normalized by diag L, FP32; 20 steps of CG and of LOBPCG
+                 (m=1) with and without the constraint.
 """
 from __future__ import annotations
 
@@ -31,6 +37,9 @@ WORKLOADS = {
     "image_2048_bf11": dict(shape=(2048, 2048), sigma=0.05, seed=5900, kind="bf", radius=5,
                             sigma_d=2.0, sigma_r=0.1, eps=0.0, prec="f32",
                             lobpcg_m=4, tol=1e-6, max_iters=20000, constraint=True),
+    "image_1024_cross5": dict(shape=(1024, 1024), sigma=0.1, seed=7, kind="bf", radius=1,
+                              sigma_d=1.0, sigma_r=0.1, eps=0.0, prec="f32", stencil="cross", norm="diagl",
+                              cg_iters=20, lobpcg_iters=20, lobpcg_m=1),
 }
 
 
