@@ -50,6 +50,7 @@ def _args():
     ap.add_argument("--no-reguided", action="store_true", help="skip the re-guided (non-linear) filter measurement")
     ap.add_argument("--no-image-experiment", action="store_true",
                     help="skip the 5-point-lattice (diag L) image experiment (PSNR after 20 CG / LOBPCG steps)")
+    ap.add_argument("--no-study-1d", action="store_true", help="skip the 1D filter study (Section 6)")
     ap.add_argument("--learned-images", type=int, default=200, help="training images (10 pairs each)")
     ap.add_argument("--learned-eval", type=int, default=2048, help="side of the evaluation image")
     ap.add_argument("--precision-study", action="store_true",
@@ -341,6 +342,58 @@ def image_experiment_bench(reps=3, apply_reps=200):
     return out
 
 
+def study_1d_bench(reps=3):
+    """The 1D filter study of Section 6 on both signal lengths, FP64: RMS
+    error against the clean signal and run time of the self-guided BF (500
+    re-guided passes), the self-guided GF (20 passes), BF-CG with the
+    noiseless guidance (20 steps), and the GF-accelerated CG / LOBPCG and
+    BF-LOBPCG (20 steps, noiseless guidance)."""
+    import torch
+    import paper_1509_02468_amd as gsf
+    from synth import STUDY_1D, study_signal
+    bf, gf, k = STUDY_1D["bf"], STUDY_1D["gf"], STUDY_1D["krylov_steps"]
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            r = fn()
+            torch.cuda.synchronize()
+            ts.append((time.perf_counter() - t0) * 1e3)
+        return r, round(float(np.median(ts)), 3)
+
+    out = {"workload": "G3 piecewise-linear signals, sigma 0.1; BF radius 1 (sigma_d 1, sigma_r 0.1), "
+                       "GF radius 2 (eps 0.01); FP64", "passes": {"bf": bf["passes"], "gf": gf["passes"],
+                                                                 "krylov": k}}
+    for n in STUDY_1D["sizes"]:
+        clean, noisy = study_signal(n)
+        gd = torch.tensor(clean, device="cuda")
+        xd = torch.tensor(noisy, device="cuda")
+
+        def rms(y):
+            return round(float(np.sqrt(np.mean((y.cpu().numpy() - clean) ** 2))), 5)
+        res = {"noisy_rms": round(float(np.sqrt(np.mean((noisy - clean) ** 2))), 5)}
+        y, ms = timed(lambda: gsf.reguided_filter("bf", (n,), xd, gsf.METHOD_POWER, bf["passes"],
+                                                  radius=bf["radius"], sigma_d=bf["sigma_d"],
+                                                  sigma_r=bf["sigma_r"], prec=gsf.F64, info=False)[0])
+        res["bf_self_guided"] = {"rms": rms(y), "ms": ms}
+        y, ms = timed(lambda: gsf.reguided_filter("gf", (n,), xd, gsf.METHOD_POWER, gf["passes"],
+                                                  radius=gf["radius"], eps=gf["eps"], prec=gsf.F64, info=False)[0])
+        res["gf_self_guided"] = {"rms": rms(y), "ms": ms}
+        ops = {"bf": gsf.Operator("bf", (n,), gd, radius=bf["radius"], sigma_d=bf["sigma_d"],
+                                  sigma_r=bf["sigma_r"], prec=gsf.F64),
+               "gf": gsf.Operator("gf", (n,), gd, radius=gf["radius"], eps=gf["eps"], prec=gsf.F64)}
+        for name, op in ops.items():
+            y, ms = timed(lambda: op.cg_filter(xd, k, info=False)[0])
+            res[f"{name}_cg"] = {"rms": rms(y), "ms": ms}
+            y, ms = timed(lambda: op.lobpcg_filter(xd, 1, k, info=False)[0])
+            res[f"{name}_lobpcg"] = {"rms": rms(y), "ms": ms}
+        out[f"n{n}"] = res
+    return out
+
+
 def precision_study(oracle_side=384):
     """Per-result errors of the precision modes: FP32 data with MFMA Gram and
     FP64 Rayleigh-Ritz against the all-FP64 GPU run at 4096^2, and both
@@ -521,6 +574,7 @@ def main():
     learned_res = None if a.no_learned else learned_bench(a.learned_images, eval_side=a.learned_eval)
     reguided_res = None if a.no_reguided else reguided_bench()
     image_res = None if a.no_image_experiment else image_experiment_bench()
+    study_res = None if a.no_study_1d else study_1d_bench()
     cpu = None if a.no_cpu else cpu_baseline(w, noisy, a.cpu_seconds)
     out = {"metric": "Mpixel-iters/s of Laplacian apply", "value": round(value, 1), "unit": "Mpixel-iters/s",
            "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(ms, 3),
@@ -530,7 +584,8 @@ def main():
                       "cg_iters": kcg, "lobpcg_iters": klob, "lobpcg_m": m, "parallelism": "single-gpu",
                       "apply_tuning": tuned, "cg_lobpcg_streams": 2 if concurrent else 1},
            "roofline": roofline, "cpu_baseline": cpu, "batch": batch, "learned": learned_res,
-           "reguided": reguided_res, "image_experiment": image_res}
+           "reguided": reguided_res, "image_experiment": image_res,
+           "study_1d": study_res}
     print(json.dumps(out), flush=True)
 
 

@@ -9,6 +9,13 @@ paint shapes.  Both the CPU oracle and the GPU library consume their output.
 
 G1  1D: 8 distinct breakpoints drawn from {1, ..., n-1} without replacement,
     9 constant pieces with levels U[0,1], plus sigma * N(0,1) noise (no clip).
+G3  1D piecewise linear with steep ascents and descents: 6 edges at distinct
+    positions on a grid of spacing 2 max(width) + 2 (ends kept clear); each
+    edge is a linear ramp over U{2..6} samples that moves the level by
+    U[0.3, 0.7], up where the level is below 0.5 and down otherwise; between
+    edges the signal runs linearly with slope U[-0.5, 0.5] / n per sample from
+    the start level U[0,1]; linear interpolation between these knots; plus
+    sigma * N(0,1) noise (the paper's 0.1 * randn(N, 1) at sigma = 0.1).
 G2  2D: linear-gradient background g0 + (g1-g0) * t(p) along a random
     direction, then 40 random rectangles / disks (probability 1/2 each) in
     painter's order with intensities U[0,1], centres uniform over the image,
@@ -19,7 +26,7 @@ from __future__ import annotations
 
 import numpy as np
 
-__all__ = ["piecewise_constant_1d", "scene_2d", "batch_items", "lobpcg_gaussian_block", "convnet_init"]
+__all__ = ["piecewise_constant_1d", "piecewise_linear_1d", "scene_2d", "batch_items", "lobpcg_gaussian_block", "convnet_init"]
 
 
 def piecewise_constant_1d(n: int, sigma: float, seed, n_breaks: int = 8):
@@ -35,6 +42,33 @@ def piecewise_constant_1d(n: int, sigma: float, seed, n_breaks: int = 8):
     edges = np.concatenate(([0], cuts, [n]))
     for k in range(n_breaks + 1):
         clean[edges[k]:edges[k + 1]] = levels[k]
+    noisy = clean + sigma * rng.standard_normal(n)
+    return clean, noisy
+
+
+def piecewise_linear_1d(n: int, sigma: float, seed, n_edges: int = 6):
+    """Return (clean, noisy) float64 arrays of length n (G3)."""
+    rng = np.random.default_rng(seed)
+    widths = rng.integers(2, 7, size=n_edges)
+    gap = 2 * int(widths.max()) + 2
+    slots = np.arange(gap, n - gap, gap)
+    starts = np.sort(rng.choice(slots, size=min(n_edges, slots.size), replace=False))
+    level = rng.uniform(0.0, 1.0)
+    kx, ky = [0.0], [level]
+    prev = 0
+    for s0, w in zip(starts, widths[:starts.size]):
+        slope = rng.uniform(-0.5, 0.5) / n
+        kx.append(float(s0))
+        ky.append(level + slope * (s0 - prev))
+        step = rng.uniform(0.3, 0.7)
+        level = ky[-1] + (step if ky[-1] < 0.5 else -step)
+        prev = int(s0 + w)
+        kx.append(float(prev))
+        ky.append(level)
+    slope = rng.uniform(-0.5, 0.5) / n
+    kx.append(float(n - 1))
+    ky.append(level + slope * (n - 1 - prev))
+    clean = np.interp(np.arange(n, dtype=np.float64), kx, ky)
     noisy = clean + sigma * rng.standard_normal(n)
     return clean, noisy
 

@@ -16,10 +16,18 @@ image_1024_cross5  2D 1024x1024, G2, sigma=0.1 (noise variance 0.01, so a
                  of every weight, which the (diag L) normalization removes),
                  normalized by diag L, FP32; 20 steps of CG and of LOBPCG
                  (m=1) with and without the constraint.
+STUDY_1D         the 1D filter study of Section 6: G3 signals with N = 500
+                 and 1000 samples, sigma=0.1, seed 11; self-guided BF
+                 (re-guided, window width 3: radius 1, sigma_d=1,
+                 sigma_r=0.1) 500 passes; self-guided GF (re-guided, window
+                 width 5: radius 2, eps=0.01) 20 passes; BF-CG 20 steps with
+                 the noiseless signal as the guidance (same BF parameters,
+                 preconditioner D); the GF-accelerated filters (CG and LOBPCG
+                 m=1, 20 steps, noiseless guidance) and BF-LOBPCG 20; FP64.
 """
 from __future__ import annotations
 
-from .generators import piecewise_constant_1d, scene_2d
+from .generators import piecewise_constant_1d, piecewise_linear_1d, scene_2d
 
 WORKLOADS = {
     "signal_1d_4096": dict(shape=(4096,), sigma=0.1, seed=1, kind="bf", radius=5,
@@ -41,6 +49,17 @@ WORKLOADS = {
                               sigma_d=1.0, sigma_r=0.1, eps=0.0, prec="f32", stencil="cross", norm="diagl",
                               cg_iters=20, lobpcg_iters=20, lobpcg_m=1),
 }
+
+
+STUDY_1D = dict(sizes=(500, 1000), sigma=0.1, seed=11, prec="f64",
+                bf=dict(radius=1, sigma_d=1.0, sigma_r=0.1, passes=500),
+                gf=dict(radius=2, eps=0.01, passes=20),
+                krylov_steps=20)
+
+
+def study_signal(n: int):
+    """(clean, noisy) G3 signal of the 1D study with n samples."""
+    return piecewise_linear_1d(n, STUDY_1D["sigma"], STUDY_1D["seed"])
 
 
 def make_signal(name: str, shape=None, seed=None):
