@@ -21,6 +21,7 @@ Contents (each function cites the passage it follows):
              the first way to iterate BF and GF; Algorithm 2's flexible beta).
   spectral   dense spectral factorization eq. (8) and GFT low-pass filters.
   quality    PSNR.
+  colour     sRGB -> CIE-Lab (the colour guidance of Section 2).
   convnet    FP64 reference of the learned convolutional preconditioner
              (forward, backward, Adam) with BF16 rounding emulation.
 
@@ -29,19 +30,20 @@ Readings where the paper is silent or ambiguous are stated at each function.
 from .graph import window_offsets, bf_weight_matrix, degrees
 from .guided import box_sum, box_count, f_mean, guided_filter, gf_stats, gf_weight_matrix_dense, gf_degrees
 from .operator import GraphOperator, build_operator
-from .solvers import (power_filter, cg_filter, cg_filter_normalized, modulated_start, modulation_degrees,
+from .solvers import (power_filter, cg_filter, cg_filter_block, cg_filter_normalized, modulated_start, modulation_degrees,
                       rayleigh_ritz, lobpcg_filter, CgInfo, LobpcgInfo, precondition, lobpcg_residual,
                       shifted_cg, ShiftedCgInfo)
 from . import convnet
 from .reguided import power_filter_reguided, cg_filter_reguided
 from .quality import psnr
+from .colour import srgb_to_lab
 
 __all__ = [
     "window_offsets", "bf_weight_matrix", "degrees",
     "box_sum", "box_count", "f_mean", "guided_filter", "gf_stats", "gf_weight_matrix_dense", "gf_degrees",
     "GraphOperator", "build_operator",
-    "power_filter", "cg_filter", "cg_filter_normalized", "modulated_start", "modulation_degrees", "rayleigh_ritz",
+    "power_filter", "cg_filter", "cg_filter_block", "cg_filter_normalized", "modulated_start", "modulation_degrees", "rayleigh_ritz",
     "lobpcg_filter", "CgInfo", "LobpcgInfo", "psnr", "precondition", "lobpcg_residual", "shifted_cg",
     "ShiftedCgInfo", "convnet",
-    "power_filter_reguided", "cg_filter_reguided",
+    "power_filter_reguided", "cg_filter_reguided", "srgb_to_lab",
 ]

@@ -41,7 +41,7 @@ def window_offsets(ndim: int, radius: int, stencil: str = "square"):
 
 
 def bf_weight_matrix(g: np.ndarray, radius: int, sigma_s: float, sigma_r: float,
-                     stencil: str = "square") -> sp.csr_matrix:
+                     stencil: str = "square", channels: int = 1) -> sp.csr_matrix:
     """Adjacency W of the BF graph, eq. (2):
 
         w_ij = exp(-||p_i - p_j||^2 / (2 sigma_s^2)) * exp(-|g_i - g_j|^2 / (2 sigma_r^2))
@@ -49,12 +49,20 @@ def bf_weight_matrix(g: np.ndarray, radius: int, sigma_s: float, sigma_r: float,
     for every j in the (border-truncated) neighbourhood of i (`stencil`, see
     `window_offsets`), w_ii = 1 included.  Pixels are numbered row-major; p_i
     are integer grid coordinates.  sigma_s = inf or sigma_r = inf switch the
-    corresponding factor to 1.
+    corresponding factor to 1.  channels > 1: g has a trailing axis of that
+    length (a colour guidance, e.g. CIE-Lab as Section 2 suggests for colour
+    images) and |g_i - g_j| is the Euclidean distance of the channel vectors.
     """
     g = np.asarray(g, dtype=np.float64)
-    shape = g.shape
-    n = g.size
-    gf = g.ravel()
+    if channels > 1:
+        if g.shape[-1] != channels:
+            raise ValueError("guidance must end with an axis of `channels` values")
+        shape = g.shape[:-1]
+        gf = g.reshape(-1, channels)
+    else:
+        shape = g.shape
+        gf = g.reshape(-1, 1)
+    n = gf.shape[0]
     coords = np.indices(shape).reshape(len(shape), -1).T  # (n, ndim) grid positions p_i
     rows, cols, vals = [], [], []
     for o in window_offsets(len(shape), radius, stencil):
@@ -65,7 +73,7 @@ def bf_weight_matrix(g: np.ndarray, radius: int, sigma_s: float, sigma_r: float,
         dist2 = float(np.dot(o, o))
         spatial = np.exp(-dist2 / (2.0 * sigma_s ** 2)) if np.isfinite(sigma_s) else 1.0
         if np.isfinite(sigma_r):
-            photometric = np.exp(-((gf[i] - gf[j]) ** 2) / (2.0 * sigma_r ** 2))
+            photometric = np.exp(-np.sum((gf[i] - gf[j]) ** 2, axis=1) / (2.0 * sigma_r ** 2))
         else:
             photometric = np.ones(i.size)
         rows.append(i)

@@ -111,18 +111,19 @@ class GraphOperator:
 
 def build_operator(kind: str, guidance, radius: int, sigma_s: float = 0.0,
                    sigma_r: float = 0.0, eps: float = 0.0, stencil: str = "square",
-                   norm: str = "d") -> GraphOperator:
+                   norm: str = "d", channels: int = 1) -> GraphOperator:
     """Build the graph operator of the BF (eq. (2)) or the GF (eqs. (5)-(6))
     from a fixed guidance signal (the linear filters of Sections 2-3).
     stencil ("square", or "cross" for the 5-point-type lattice of Section 7)
     and norm ("d", or "diagl" for (diag L)^-1/2 L (diag L)^-1/2 of Section 4)
-    are BF options."""
+    are BF options, as is channels > 1 (a guidance with a trailing axis of
+    that many channels, e.g. CIE-Lab, see `bf_weight_matrix`)."""
     g = np.asarray(guidance, dtype=np.float64)
     if norm not in ("d", "diagl"):
         raise ValueError(norm)
     W_off = None
     if kind == "bf":
-        W = bf_weight_matrix(g, radius, sigma_s, sigma_r, stencil)
+        W = bf_weight_matrix(g, radius, sigma_s, sigma_r, stencil, channels)
         d = degrees(W)
         if norm == "diagl":
             W_off = (W - sp.diags(W.diagonal())).tocsr()  # exact: every w_ii is 1
@@ -132,12 +133,13 @@ def build_operator(kind: str, guidance, radius: int, sigma_s: float = 0.0,
         else:
             dl = d
     elif kind == "gf":
-        if stencil != "square" or norm != "d":
-            raise ValueError("stencil and norm options are BF-only")
+        if stencil != "square" or norm != "d" or channels != 1:
+            raise ValueError("stencil, norm and channel options are BF-only")
         W = None
         d = dl = gf_degrees(g.shape, radius).ravel()
     else:
         raise ValueError(kind)
-    return GraphOperator(kind=kind, shape=g.shape, guidance=g, radius=radius,
+    shape = g.shape[:-1] if channels > 1 else g.shape
+    return GraphOperator(kind=kind, shape=shape, guidance=g, radius=radius,
                          sigma_s=sigma_s, sigma_r=sigma_r, eps=eps, W=W, d=d,
                          sqrt_d=np.sqrt(d), stencil=stencil, norm=norm, dl=dl, W_off=W_off)

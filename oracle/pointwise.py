@@ -33,35 +33,42 @@ def _window(shape, p, radius):
     return pts, np.ravel_multi_index(tuple(pts.T), shape)
 
 
-def _bf_w(g, p, qs, sigma_s, sigma_r):
-    """eq. (2) between point p and the points qs (coords)."""
+def _bf_w(g, p, qs, sigma_s, sigma_r, channels=1):
+    """eq. (2) between point p and the points qs (coords); with channels > 1
+    g has a trailing channel axis and the photometric distance is the
+    Euclidean distance of the channel vectors."""
     o = qs - p[None, :]
     dist2 = np.sum(o * o, axis=1).astype(np.float64)
     gp = g[tuple(p)]
     gq = g[tuple(qs.T)]
+    d2 = np.sum((gq - gp[None, :]) ** 2, axis=1) if channels > 1 else (gp - gq) ** 2
     spatial = np.exp(-dist2 / (2.0 * sigma_s ** 2)) if np.isfinite(sigma_s) else 1.0
-    photometric = np.exp(-((gp - gq) ** 2) / (2.0 * sigma_r ** 2)) if np.isfinite(sigma_r) else 1.0
+    photometric = np.exp(-d2 / (2.0 * sigma_r ** 2)) if np.isfinite(sigma_r) else 1.0
     return spatial * photometric
 
 
-def bf_degree_at(g, p, radius, sigma_s, sigma_r):
-    qs, _ = _window(g.shape, p, radius)
-    return float(np.sum(_bf_w(g, p, qs, sigma_s, sigma_r)))
+def bf_degree_at(g, p, radius, sigma_s, sigma_r, channels=1):
+    grid = g.shape[:-1] if channels > 1 else g.shape
+    qs, _ = _window(grid, p, radius)
+    return float(np.sum(_bf_w(g, p, qs, sigma_s, sigma_r, channels)))
 
 
-def bf_lsym_at(g, z, points, radius: int, sigma_s: float, sigma_r: float):
-    """(L_sym z) at the given flat indices of the BF graph of guidance g;
-    z is (n,) or (n, m), the result (len(points),) or (len(points), m)."""
+def bf_lsym_at(g, z, points, radius: int, sigma_s: float, sigma_r: float, channels: int = 1):
+    """(L_sym z) at the given flat indices of the BF graph of guidance g
+    (channels > 1: g has a trailing channel axis); z is (n,) or (n, m), the
+    result (len(points),) or (len(points), m)."""
     g = np.asarray(g, dtype=np.float64)
+    grid = g.shape[:-1] if channels > 1 else g.shape
+    n = int(np.prod(grid))
     z = np.asarray(z, dtype=np.float64)
-    zf = z.reshape(g.size, -1)
+    zf = z.reshape(n, -1)
     out = np.empty((len(points), zf.shape[1]))
     for t, i in enumerate(points):
-        p = _coords(g.shape, i)
-        qs, qflat = _window(g.shape, p, radius)
-        w = _bf_w(g, p, qs, sigma_s, sigma_r)
+        p = _coords(grid, i)
+        qs, qflat = _window(grid, p, radius)
+        w = _bf_w(g, p, qs, sigma_s, sigma_r, channels)
         di = float(np.sum(w))
-        dq = np.array([bf_degree_at(g, q, radius, sigma_s, sigma_r) for q in qs])
+        dq = np.array([bf_degree_at(g, q, radius, sigma_s, sigma_r, channels) for q in qs])
         out[t] = zf[i] - (w / np.sqrt(dq)) @ zf[qflat] / np.sqrt(di)
     return out.reshape(len(points)) if z.ndim == 1 else out
 

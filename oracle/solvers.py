@@ -133,6 +133,19 @@ def cg_filter(op, x0, kmax: int, tol: float = 0.0, data_prec: str = "f64"):
     return x, info
 
 
+def cg_filter_block(op, X0, kmax: int, tol: float = 0.0, data_prec: str = "f64"):
+    """Algorithm 2 on each column of an n x m block (the channels of a colour
+    signal share one graph): the columns are independent CG runs, each with
+    its own stopping decisions.  Returns (Y, [CgInfo per column])."""
+    X0 = np.asarray(X0, dtype=np.float64)
+    out = np.empty_like(X0)
+    infos = []
+    for j in range(X0.shape[1]):
+        out[:, j], info = cg_filter(op, X0[:, j], kmax, tol, data_prec)
+        infos.append(info)
+    return out, infos
+
+
 def cg_filter_normalized(op, x0, kmax: int, tol: float = 0.0, data_prec: str = "f64", store=None):
     """The same iteration written for L_sym z = 0 in z = D^1/2 x with T = I
     (s = r); returns x = D^-1/2 z.
