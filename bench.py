@@ -51,6 +51,7 @@ def _args():
     ap.add_argument("--no-image-experiment", action="store_true",
                     help="skip the 5-point-lattice (diag L) image experiment (PSNR after 20 CG / LOBPCG steps)")
     ap.add_argument("--no-study-1d", action="store_true", help="skip the 1D filter study (Section 6)")
+    ap.add_argument("--no-colour", action="store_true", help="skip the colour (CIE-Lab guidance) measurement")
     ap.add_argument("--learned-images", type=int, default=200, help="training images (10 pairs each)")
     ap.add_argument("--learned-eval", type=int, default=2048, help="side of the evaluation image")
     ap.add_argument("--precision-study", action="store_true",
@@ -342,6 +343,65 @@ def image_experiment_bench(reps=3, apply_reps=200):
     return out
 
 
+def colour_bench(reps=3):
+    """Colour guidance (Section 2: the photometric distance in CIE-Lab) on the
+    1024^2 colour workload, FP32: the sRGB -> Lab conversion, the build from
+    the 3-channel Lab guidance, and the three RGB channels filtered as one
+    block (one 3-column apply per step) against three single-channel runs on
+    the same operator; PSNR of the outputs."""
+    import torch
+    import paper_1509_02468_amd as gsf
+    from synth import WORKLOADS, make_signal
+    name = "image_1024_rgb_bf11"
+    w = WORKLOADS[name]
+    shape = w["shape"]
+    clean, noisy = make_signal(name)
+    xd = torch.tensor(noisy.reshape(-1, 3).astype(np.float32), device="cuda")
+    cols = [xd[:, c].contiguous() for c in range(3)]
+    par = dict(radius=w["radius"], sigma_d=w["sigma_d"], sigma_r=w["sigma_r"], prec=gsf.F32, channels=3)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return round(float(np.median(ts)), 4)
+
+    def psnr(y):
+        y = y.double().cpu().numpy()
+        return round(float(10.0 * np.log10(1.0 / np.mean((y.ravel() - clean.ravel()) ** 2))), 3)
+
+    lab = torch.empty_like(xd)
+    out = {"workload": f"{name}: {shape[0]}x{shape[1]} RGB, CIE-Lab guidance, BF {2 * w['radius'] + 1}x"
+                       f"{2 * w['radius'] + 1}, sigma_r={w['sigma_r']} (Delta E), FP32",
+           "psnr_noisy": round(float(10.0 * np.log10(1.0 / np.mean((noisy - clean) ** 2))), 3)}
+    out["srgb_to_lab_ms"] = timed(lambda: gsf.srgb_to_lab(xd, out=lab))
+    op = gsf.Operator("bf", shape, lab, **par)
+    out["build_ms"] = timed(lambda: gsf.Operator("bf", shape, lab, **par, ws=op.ws))
+    k, kp = w["cg_iters"], w["power_iters"]
+    wsb = op.workspace(gsf.METHOD_CG, 3)
+    ws1 = op.workspace(gsf.METHOD_CG, 1)
+    y = torch.empty_like(xd)
+    ys = [torch.empty_like(c) for c in cols]
+    out["cg_block_ms"] = timed(lambda: op.cg_filter_block(xd, k, out=y, ws=wsb, info=False))
+    out["psnr_cg"] = psnr(y)
+    out["cg_3x_single_ms"] = timed(lambda: [op.cg_filter(cols[c], k, out=ys[c], ws=ws1, info=False)
+                                            for c in range(3)])
+    wpb = op.workspace(gsf.METHOD_POWER, 3)
+    wp1 = op.workspace(gsf.METHOD_POWER, 1)
+    out["power_block_ms"] = timed(lambda: op.power_filter_block(xd, kp, out=y, ws=wpb))
+    out["psnr_power"] = psnr(y)
+    out["power_3x_single_ms"] = timed(lambda: [op.power_filter(cols[c], kp, out=ys[c], ws=wp1) for c in range(3)])
+    out["iters"] = {"cg": k, "power": kp}
+    return out
+
+
 def study_1d_bench(reps=3):
     """The 1D filter study of Section 6 on both signal lengths, FP64: RMS
     error against the clean signal and run time of the self-guided BF (500
@@ -575,6 +635,7 @@ def main():
     reguided_res = None if a.no_reguided else reguided_bench()
     image_res = None if a.no_image_experiment else image_experiment_bench()
     study_res = None if a.no_study_1d else study_1d_bench()
+    colour_res = None if a.no_colour else colour_bench()
     cpu = None if a.no_cpu else cpu_baseline(w, noisy, a.cpu_seconds)
     out = {"metric": "Mpixel-iters/s of Laplacian apply", "value": round(value, 1), "unit": "Mpixel-iters/s",
            "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(ms, 3),
@@ -585,7 +646,7 @@ def main():
                       "apply_tuning": tuned, "cg_lobpcg_streams": 2 if concurrent else 1},
            "roofline": roofline, "cpu_baseline": cpu, "batch": batch, "learned": learned_res,
            "reguided": reguided_res, "image_experiment": image_res,
-           "study_1d": study_res}
+           "study_1d": study_res, "colour": colour_res}
     print(json.dumps(out), flush=True)
 
 

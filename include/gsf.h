@@ -98,7 +98,13 @@ typedef enum { GSF_NORM_D = 0, GSF_NORM_DIAGL = 1 } gsf_norm;
  *          off-diagonal weights are all zero has a zero row and column in L;
  *          its normalizing value is taken as 1 (the vertex is then a fixed
  *          point of every filter).  The L form stays L = D - W.
- *  A zero-initialised stencil / norm selects the defaults. */
+ *  channels BF only (GF: 0 or 1, else GSF_EINVAL): values per guidance point,
+ *          0..8 (0 means 1).  With C > 1 channels the guidance is point-major
+ *          (g[i*C + c]) and |g_i - g_j| in eq. (2) is the Euclidean distance
+ *          of the channel vectors: the colour guidance of Section 2, whose
+ *          photometric distance is measured in CIE-Lab (gsf_srgb_to_lab).
+ *          sigma_r is then in the guidance's units (CIE-Lab: Delta E).
+ *  A zero-initialised stencil / norm / channels selects the defaults. */
 typedef struct {
   int32_t kind;
   int32_t ndim;
@@ -108,8 +114,10 @@ typedef struct {
   double sigma_d;
   double sigma_r;
   double gf_eps;
-  int32_t stencil;  /* gsf_stencil */
-  int32_t norm;     /* gsf_norm */
+  int32_t stencil;   /* gsf_stencil */
+  int32_t norm;      /* gsf_norm */
+  int32_t channels;  /* guidance channels (BF), 0 or 1 = scalar */
+  int32_t reserved;  /* must be 0 */
 } gsf_operator_desc;
 
 typedef struct gsf_operator gsf_operator;   /* opaque host handle */
@@ -176,7 +184,8 @@ const char* gsf_status_string(int status);
  * gsf_operator_workspace_bytes: bytes of device workspace the operator needs.
  * gsf_build_operator: computes the weights (BF, eq. (2)) and degrees, or the
  *   guided-filter window statistics (Algorithm 1, the g-only lines), from the
- *   guidance `guidance` (n values of type prec) into `ws`, and returns a host
+ *   guidance `guidance` (n values of type prec; BF with C > 1 channels:
+ *   n*C values, point-major) into `ws`, and returns a host
  *   handle in *out.  The build is asynchronous: the guidance must stay valid
  *   until the stream has executed it (it is not read afterwards).
  *   GSF_EINVAL for bad shapes or parameters; a non-finite guidance value is
@@ -197,8 +206,9 @@ gsf_status gsf_apply(const gsf_operator* op, int form, int m, const void* x, voi
                      void* stream);
 
 /* ---- solvers ---------------------------------------------------------------
- * gsf_solver_workspace_bytes: workspace for `method` with block size m
- *   (m is ignored for power and CG). */
+ * gsf_solver_workspace_bytes: workspace for `method` with block size m: the
+ *   LOBPCG block, or the number of columns of the block power / CG filters
+ *   (m = 1 covers the single-vector power and CG filters). */
 gsf_status gsf_solver_workspace_bytes(const gsf_operator* op, int method, int m, size_t* bytes);
 
 /* Power iteration (Section 4): x_out = (D^-1 W)^kmax x0, kmax >= 0.
@@ -221,6 +231,35 @@ gsf_status gsf_power_filter(const gsf_operator* op, const void* x0, void* x_out,
  * the call: with info == NULL the call returns GSF_OK after enqueueing. */
 gsf_status gsf_cg_filter(const gsf_operator* op, const void* x0, void* x_out, int kmax,
                          double tol, void* ws, size_t ws_bytes, gsf_cg_info* info, void* stream);
+
+/* Multi-channel signals (the channels of a colour image filtered on one graph):
+ * x0 and x_out are n x m point-major blocks (m = 1..8; x0[i*m + c]), one
+ * m-column apply per step reads the operator once for all channels.
+ *  gsf_power_filter_block: every column as gsf_power_filter; x0 and x_out
+ *    may be the same buffer.
+ *  gsf_cg_filter_block: every column an independent run of gsf_cg_filter
+ *    (its own alpha, beta and stopping decisions; a stopped column keeps its
+ *    result while the others continue).  info: NULL or an array of m
+ *    summaries; the return value is the first non-OK column status, else
+ *    GSF_OK (known only after the stream has reached the end of the call, as
+ *    for gsf_cg_filter).
+ * Workspace: gsf_solver_workspace_bytes(op, method, m, ...).  GSF_EINVAL for
+ * m outside 1..8. */
+gsf_status gsf_power_filter_block(const gsf_operator* op, int m, const void* x0, void* x_out, int kmax,
+                                  void* ws, size_t ws_bytes, void* stream);
+gsf_status gsf_cg_filter_block(const gsf_operator* op, int m, const void* x0, void* x_out, int kmax,
+                               double tol, void* ws, size_t ws_bytes, gsf_cg_info* info, void* stream);
+
+/* Colour guidance (Section 2: the photometric distance in CIE-Lab).
+ * lab = CIE 1976 L*a*b* of sRGB values rgb (n points x 3 components,
+ * point-major, nominally in [0, 1]; no clipping): the IEC 61966-2-1 transfer
+ * curve, the linear RGB -> XYZ matrix of the sRGB primaries and the D65 white
+ * (chromaticities (0.64, 0.33), (0.30, 0.60), (0.15, 0.06), (0.3127, 0.3290)),
+ * and L* = 116 f(Y/Yn) - 16, a* = 500 (f(X/Xn) - f(Y/Yn)),
+ * b* = 200 (f(Y/Yn) - f(Z/Zn)) relative to that white; FP64 arithmetic,
+ * element type prec.  rgb and lab may be the same buffer.  GSF_EINVAL for
+ * n < 0, a bad prec or NULL pointers with n > 0. */
+gsf_status gsf_srgb_to_lab(int prec, int64_t n, const void* rgb, void* lab, void* stream);
 
 /* Block LOBPCG low-pass filter (Algorithm 3 generalised to m = 1..8 vectors):
  * operator L_sym, preconditioner T = I (T = D^-1 in x-space).  Start block
@@ -345,8 +384,9 @@ gsf_status gsf_lobpcg_residual(const gsf_operator* op, int m, const void* X, con
  * gsf_reguided_workspace_bytes(desc, method) bytes, 256-byte aligned; it holds
  * the rebuilt operator and the solver vectors.  Each step costs one operator
  * build; with FP32 data the graph is built from the stored FP32 iterate.
- * GSF_EINVAL for a bad descriptor, method, kmax < 0 or tol; GSF_ENOMEM for a
- * short workspace.  info may be NULL (then no host sync). */
+ * GSF_EINVAL for a bad descriptor, a descriptor with more than one guidance
+ * channel (the iterate is the guidance), method, kmax < 0 or tol; GSF_ENOMEM
+ * for a short workspace.  info may be NULL (then no host sync). */
 gsf_status gsf_reguided_workspace_bytes(const gsf_operator_desc* desc, int method, size_t* bytes);
 gsf_status gsf_reguided_filter(const gsf_operator_desc* desc, int method, const void* x0, void* x_out,
                                int kmax, double tol, void* ws, size_t ws_bytes, gsf_cg_info* info,

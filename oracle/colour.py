@@ -40,7 +40,8 @@ def srgb_matrix() -> np.ndarray:
 
 def srgb_to_linear(c):
     c = np.asarray(c, dtype=np.float64)
-    return np.where(c <= 0.04045, c / 12.92, ((c + 0.055) / 1.055) ** 2.4)
+    hi = np.maximum(c, 0.04045)  # the power branch only ever sees its own domain
+    return np.where(c <= 0.04045, c / 12.92, ((hi + 0.055) / 1.055) ** 2.4)
 
 
 def _f(t):

@@ -19,6 +19,11 @@ gsf_status launch_bf_apply_rpt(const Operator& op, int form, int m, const void* 
 gsf_status launch_gf_apply(const Operator& op, void* scratch, int form, int m, const void* x, int64_t ldx,
                            void* y, int64_t ldy, hipStream_t s);
 int vec_blocks(int64_t n);
+gsf_status launch_bscale(const Operator& op, int m, const void* in, void* out, int divide, hipStream_t s);
+gsf_status launch_bcg(int kind, const Operator& op, int m, void* z, void* r, void* p, void* q, double* partials,
+                      BlockCgState* st, hipStream_t s);
+gsf_status launch_bcg_state_init(BlockCgState* st, const BlockCgState& v, hipStream_t s);
+gsf_status launch_srgb_to_lab(int prec, int64_t n, const void* rgb, void* lab, hipStream_t s);
 gsf_status launch_scale(const Operator& op, const void* in, void* out, int divide, hipStream_t s);
 gsf_status launch_cg_init(const Operator& op, const void* z, void* r, double* partials, CgState* st,
                           hipStream_t s);
@@ -76,7 +81,9 @@ gsf_status validate_desc(const gsf_operator_desc* d) {
   if (d->radius < 1 || d->radius > kMaxRadius) return GSF_EINVAL;
   if (d->stencil != GSF_STENCIL_SQUARE && d->stencil != GSF_STENCIL_CROSS) return GSF_EINVAL;
   if (d->norm != GSF_NORM_D && d->norm != GSF_NORM_DIAGL) return GSF_EINVAL;
-  if (d->kind == GSF_GF && (d->stencil != GSF_STENCIL_SQUARE || d->norm != GSF_NORM_D)) return GSF_EINVAL;
+  if (d->channels < 0 || d->channels > kMaxBlock || d->reserved != 0) return GSF_EINVAL;
+  if (d->kind == GSF_GF && (d->stencil != GSF_STENCIL_SQUARE || d->norm != GSF_NORM_D || desc_channels(*d) != 1))
+    return GSF_EINVAL;
   if (d->dims[0] < 1) return GSF_EINVAL;
   if (d->ndim == 2 && d->dims[1] < 1) return GSF_EINVAL;
   const int64_t n = d->ndim == 1 ? d->dims[0] : d->dims[0] * d->dims[1];
@@ -205,6 +212,26 @@ size_t carve_cg(const Operator& op, char* base, CgWs* w) {
   }
   w->partials = (double*)c.take((size_t)nb * 2 * sizeof(double));
   w->st = (CgState*)c.take(sizeof(CgState));
+  return c.off;
+}
+
+// Block CG over m columns: z, r, p, q (n x m each), partials (2m per
+// workgroup) and the per-column state.
+struct BcgWs {
+  void *z, *r, *p, *q;
+  double* partials;
+  BlockCgState* st;
+};
+
+size_t carve_bcg(const Operator& op, int m, char* base, BcgWs* w) {
+  Carve c{base};
+  const size_t v = (size_t)op.n * m * op.elem;
+  w->z = c.take(v);
+  w->r = c.take(v);
+  w->p = c.take(v);
+  w->q = c.take(v);
+  w->partials = (double*)c.take((size_t)vec_blocks(op.n) * 2 * m * sizeof(double));
+  w->st = (BlockCgState*)c.take(sizeof(BlockCgState));
   return c.off;
 }
 
@@ -491,10 +518,14 @@ gsf_status gsf_solver_workspace_bytes(const gsf_operator* h, int method, int m, 
   if (h == nullptr || bytes == nullptr) return GSF_EINVAL;
   const Operator& op = h->op;
   if (method == GSF_METHOD_POWER) {
-    *bytes = 2 * align_up((size_t)op.n * op.elem, 256);
+    if (m < 1 || m > kMaxBlock) return GSF_EINVAL;
+    *bytes = 2 * align_up((size_t)op.n * m * op.elem, 256);
   } else if (method == GSF_METHOD_CG) {
+    if (m < 1 || m > kMaxBlock) return GSF_EINVAL;
     CgWs w;
-    *bytes = carve_cg(op, nullptr, &w);
+    BcgWs bw;
+    const size_t a = carve_cg(op, nullptr, &w), b = carve_bcg(op, m, nullptr, &bw);
+    *bytes = a > b ? a : b;
   } else if (method == GSF_METHOD_LOBPCG) {
     if (m < 1 || m > kMaxBlock) return GSF_EINVAL;
     LobWs w;
@@ -523,6 +554,82 @@ gsf_status gsf_power_filter(const gsf_operator* h, const void* x0, void* x_out, 
     b = t;
   }
   return launch_scale(op, a, x_out, 1, s);  // x = D^-1/2 z
+}
+
+gsf_status gsf_power_filter_block(const gsf_operator* h, int m, const void* x0, void* x_out, int kmax, void* ws,
+                                  size_t ws_bytes, void* stream) {
+  if (h == nullptr || x0 == nullptr || x_out == nullptr || kmax < 0 || m < 1 || m > kMaxBlock) return GSF_EINVAL;
+  const Operator& op = h->op;
+  const size_t v = align_up((size_t)op.n * m * op.elem, 256);
+  if (kmax > 0 && (ws == nullptr || ws_bytes < 2 * v)) return GSF_ENOMEM;
+  hipStream_t s = (hipStream_t)stream;
+  if (kmax == 0)
+    return hip_ok(hipMemcpyAsync(x_out, x0, (size_t)op.n * m * op.elem, hipMemcpyDeviceToDevice, s));
+  char* a = (char*)ws;
+  char* b = a + v;
+  GSF_TRY(launch_bscale(op, m, x0, a, 0, s));  // z = D^1/2 x, column by column
+  for (int k = 0; k < kmax; ++k) {
+    GSF_TRY(apply_any(op, GSF_FORM_N, m, a, m, b, m, nullptr, nullptr, s));
+    char* t = a;
+    a = b;
+    b = t;
+  }
+  return launch_bscale(op, m, a, x_out, 1, s);
+}
+
+gsf_status gsf_cg_filter_block(const gsf_operator* h, int m, const void* x0, void* x_out, int kmax, double tol,
+                               void* ws, size_t ws_bytes, gsf_cg_info* info, void* stream) {
+  if (h == nullptr || x0 == nullptr || x_out == nullptr || kmax < 0 || !(tol >= 0.0) || !std::isfinite(tol))
+    return GSF_EINVAL;
+  if (m < 1 || m > kMaxBlock) return GSF_EINVAL;
+  const Operator& op = h->op;
+  BcgWs w;
+  if (ws == nullptr || ws_bytes < carve_bcg(op, m, nullptr, &w)) return GSF_ENOMEM;
+  carve_bcg(op, m, (char*)ws, &w);
+  hipStream_t s = (hipStream_t)stream;
+  BlockCgState init{};
+  init.m = m;
+  init.active = 1;
+  for (int c = 0; c < m; ++c) {
+    init.col[c].tol = tol;
+    init.col[c].tau = breakdown_tau(op.desc.prec);
+  }
+  GSF_TRY(launch_bcg_state_init(w.st, init, s));
+  GSF_TRY(launch_bscale(op, m, x0, w.z, 0, s));
+  GSF_TRY(apply_any(op, GSF_FORM_LSYM, m, w.z, m, w.r, m, nullptr, nullptr, s));
+  GSF_TRY(launch_bcg(0, op, m, w.z, w.r, w.p, w.q, w.partials, w.st, s));
+  Poller poll(s, &w.st->active, info != nullptr && tol > 0.0);
+  for (int k = 1; k <= kmax; ++k) {
+    if (!poll.keep_going(k - 1)) break;
+    GSF_TRY(launch_bcg(1, op, m, w.z, w.r, w.p, w.q, w.partials, w.st, s));
+    GSF_TRY(apply_any(op, GSF_FORM_LSYM, m, w.p, m, w.q, m, nullptr, nullptr, s));
+    GSF_TRY(launch_bcg(2, op, m, w.z, w.r, w.p, w.q, w.partials, w.st, s));
+    GSF_TRY(launch_bcg(3, op, m, w.z, w.r, w.p, w.q, w.partials, w.st, s));
+  }
+  GSF_TRY(launch_bscale(op, m, w.z, x_out, 1, s));
+  if (info == nullptr) return GSF_OK;
+  BlockCgState host{};
+  GSF_TRY(hip_ok(hipMemcpyAsync(&host, w.st, sizeof(host), hipMemcpyDeviceToHost, s)));
+  GSF_TRY(hip_ok(hipStreamSynchronize(s)));
+  gsf_status first = GSF_OK;
+  for (int c = 0; c < m; ++c) {
+    const CgState& cs = host.col[c];
+    gsf_status status = (gsf_status)cs.status;
+    if (status == GSF_OK && tol > 0.0 && cs.active && !(cs.rho <= cs.tol2)) status = GSF_ENOTCONV;
+    info[c].iters = cs.iters;
+    info[c].status = status;
+    info[c].res0 = cs.res0;
+    info[c].res = std::sqrt(cs.rho > 0.0 ? cs.rho : 0.0);
+    if (first == GSF_OK) first = status;
+  }
+  return first;
+}
+
+gsf_status gsf_srgb_to_lab(int prec, int64_t n, const void* rgb, void* lab, void* stream) {
+  if (n < 0 || (prec != GSF_F32 && prec != GSF_F64)) return GSF_EINVAL;
+  if (n == 0) return GSF_OK;
+  if (rgb == nullptr || lab == nullptr) return GSF_EINVAL;
+  return launch_srgb_to_lab(prec, n, rgb, lab, (hipStream_t)stream);
 }
 
 gsf_status gsf_cg_filter(const gsf_operator* h, const void* x0, void* x_out, int kmax, double tol, void* ws,
@@ -705,6 +812,7 @@ gsf_status gsf_lobpcg_filter(const gsf_operator* h, const void* x0, void* x_out,
 gsf_status gsf_reguided_workspace_bytes(const gsf_operator_desc* desc, int method, size_t* bytes) {
   if (bytes == nullptr || (method != GSF_METHOD_POWER && method != GSF_METHOD_CG)) return GSF_EINVAL;
   GSF_TRY(validate_desc(desc));
+  if (desc_channels(*desc) != 1) return GSF_EINVAL;
   RgWs w;
   *bytes = carve_rg(desc, method, nullptr, &w);
   return GSF_OK;
@@ -715,6 +823,7 @@ gsf_status gsf_reguided_filter(const gsf_operator_desc* desc, int method, const 
   if (x0 == nullptr || x_out == nullptr || kmax < 0 || !(tol >= 0.0) || !std::isfinite(tol)) return GSF_EINVAL;
   if (method != GSF_METHOD_POWER && method != GSF_METHOD_CG) return GSF_EINVAL;
   GSF_TRY(validate_desc(desc));
+  if (desc_channels(*desc) != 1) return GSF_EINVAL;
   RgWs w;
   if (ws == nullptr || ws_bytes < carve_rg(desc, method, nullptr, &w)) return GSF_ENOMEM;
   carve_rg(desc, method, (char*)ws, &w);

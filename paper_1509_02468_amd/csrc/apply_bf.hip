@@ -29,7 +29,7 @@ int width_of(int left) { return left >= 8 ? 8 : (left >= 4 ? 4 : left); }
 
 int bf_rpt(const Operator& op, int w) {
   const int t = g_rpt[op.desc.prec][geometry(op)][op.desc.radius][w][size_class(op.n)];
-  return t > 0 ? t : bfk::default_rpt((int)op.elem, w);
+  return t > 0 ? t : bfk::default_rpt((int)op.elem, w, op.desc.radius);
 }
 
 void bf_set_rpt(const Operator& op, int w, int rpt) {

@@ -46,16 +46,15 @@ struct ApplyArgs {
 // amortise the LDS halo, fewer rows give more workgroups (and so more loads in
 // flight per CU).  In 2D, RPT = 2 is the paired kernel (two rows computed
 // together, sharing each neighbour row); RPT = 1 and 4 take their rows one
-// after the other.  The default below keeps the LDS tile under ~64 KB; the
-// apply tuner may pick another one per (type, m, r).
-template <typename T, int M>
-struct Rows {
-  static constexpr int MB = M * (int)sizeof(T);
-  static constexpr int RPT = MB <= 16 ? 4 : (MB <= 32 ? 2 : 1);
-};
-
-inline int default_rpt(int elem, int m) {
+// after the other.  The apply tuner may pick another one per (type, m, r).
+// Defaults: for wide windows (r >= 3) one row for a single FP32 column and
+// the paired kernel up to 32 bytes per point (measured at 1024^2, r = 5, FP32:
+// m = 1: 46 / 52 / 67 us for 1 / 2 / 4 rows; m = 3: 61 / 59 / 93; m = 4:
+// 73 / 66 / 77); for narrow windows four rows up to 16 bytes per point, where
+// the halo is a larger share of the tile.
+inline int default_rpt(int elem, int m, int radius) {
   const int mb = elem * m;
+  if (radius >= 3) return mb <= 4 ? 1 : (mb <= 32 ? 2 : 1);
   return mb <= 16 ? 4 : (mb <= 32 ? 2 : 1);
 }
 

@@ -17,8 +17,9 @@ struct BfParams {
   int radius, ndim;
   double cs;  // 1 / (2 sigma_d^2), 0 for sigma_d = inf
   double cr;  // 1 / (2 sigma_r^2), 0 for sigma_r = inf
-  int cross;  // 2D cross stencil: offsets (0, 1..r) and (1..r, 0) only
-  int diagl;  // normalise by diag L instead of D
+  int cross;     // 2D cross stencil: offsets (0, 1..r) and (1..r, 0) only
+  int diagl;     // normalise by diag L instead of D
+  int channels;  // guidance values per point (point-major)
 };
 
 // 2D plane q -> half-window offset (dy, dx).  Square: q < r: (0, q + 1), else
@@ -38,12 +39,26 @@ __device__ __forceinline__ void plane_offset(int q, const BfParams& p, int& dy, 
   }
 }
 
-// eq. (2) in one exponential: exp(-(|o|^2 cs + (g_i - g_j)^2 cr)).  The
-// argument is bitwise the same for (i, j) and (j, i), so W is exactly
-// symmetric wherever it is evaluated.
-__device__ __forceinline__ double bf_weight(double gi, double gj, int o2, const BfParams& p) {
-  const double dg = gi - gj;
-  return exp(-((double)o2 * p.cs + dg * dg * p.cr));
+// eq. (2) in one exponential: exp(-(|o|^2 cs + |g_i - g_j|^2 cr)), with
+// |g_i - g_j|^2 summed over the guidance channels in channel order (the
+// Euclidean distance of colour vectors, e.g. CIE-Lab).  The argument is
+// bitwise the same for (i, j) and (j, i), so W is exactly symmetric wherever
+// it is evaluated.
+template <typename T>
+__device__ __forceinline__ double bf_weight(const T* __restrict__ g, int64_t i, int64_t j, int o2,
+                                            const BfParams& p) {
+  double d2;
+  if (p.channels == 1) {
+    const double dg = (double)g[i] - (double)g[j];
+    d2 = dg * dg;
+  } else {
+    d2 = 0.0;
+    for (int c = 0; c < p.channels; ++c) {
+      const double dg = (double)g[i * p.channels + c] - (double)g[j * p.channels + c];
+      d2 += dg * dg;
+    }
+  }
+  return exp(-((double)o2 * p.cs + d2 * p.cr));
 }
 
 // K1: half-window planes of the symmetric weights w_{i,i+o} (0 off the grid),
@@ -68,13 +83,12 @@ __global__ void __launch_bounds__(kThreads) bf_fold_kernel(const T* __restrict__
   }
   planes += ppad;
   const int r = p.radius;
-  const double gi = (double)g[i];
   int q = 0;
   if (p.ndim == 1) {
     for (int o = 1; o <= r; ++o, ++q) {
       const int64_t j = i + o;
       double v = 0.0;
-      if (j < p.n) v = bf_weight(gi, (double)g[j], o * o, p);
+      if (j < p.n) v = bf_weight(g, i, j, o * o, p);
       planes[(int64_t)q * pstride + i] = (T)v;
     }
   } else {
@@ -86,7 +100,7 @@ __global__ void __launch_bounds__(kThreads) bf_fold_kernel(const T* __restrict__
       double v = 0.0;
       if (yy < p.rows && xx >= 0 && xx < p.cols) {
         const int64_t j = yy * p.cols + xx;
-        v = bf_weight(gi, (double)g[j], dy * dy + dx * dx, p);
+        v = bf_weight(g, i, j, dy * dy + dx * dx, p);
       }
       planes[(int64_t)q * pstride + i] = (T)v;
     }
@@ -148,7 +162,8 @@ gsf_status launch_bf_build(const Operator& op, const void* guidance, hipStream_t
              inv_two_sigma2(op.desc.sigma_d),
              inv_two_sigma2(op.desc.sigma_r),
              bf_cross2d(op.desc) ? 1 : 0,
-             op.desc.norm == GSF_NORM_DIAGL ? 1 : 0};
+             op.desc.norm == GSF_NORM_DIAGL ? 1 : 0,
+             desc_channels(op.desc)};
   const unsigned grid = (unsigned)((op.n + kThreads - 1) / kThreads);
   const unsigned fgrid = (unsigned)((op.pstride + kThreads - 1) / kThreads);
   if (op.desc.prec == GSF_F32) {

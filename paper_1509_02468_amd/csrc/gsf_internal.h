@@ -39,6 +39,9 @@ inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 // BF: the 2D cross stencil (1D cross is the square window's interval).
 inline bool bf_cross2d(const gsf_operator_desc& d) { return d.ndim == 2 && d.stencil == GSF_STENCIL_CROSS; }
 
+// Guidance channels (0 in a descriptor means 1).
+inline int desc_channels(const gsf_operator_desc& d) { return d.channels > 1 ? d.channels : 1; }
+
 // BF half-window planes: one per undirected offset pair {o, -o}, o != 0.
 inline int bf_num_planes(const gsf_operator_desc& d) {
   if (d.ndim == 1) return d.radius;

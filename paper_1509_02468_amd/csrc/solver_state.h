@@ -22,6 +22,15 @@ struct CgState {
   int32_t pad;
 };
 
+// Block CG: one state per column (the columns are independent CG runs that
+// share each apply) and whether any column is still running.
+struct BlockCgState {
+  CgState col[8];
+  int32_t m;
+  int32_t active;  // some column still active
+  int32_t pad[2];
+};
+
 struct LobpcgState {
   double theta[8];
   double res[8];       // residual norms of the current X

@@ -35,7 +35,7 @@ class OperatorDesc(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("ndim", ctypes.c_int32), ("dims", ctypes.c_int64 * 2),
                 ("prec", ctypes.c_int32), ("radius", ctypes.c_int32), ("sigma_d", ctypes.c_double),
                 ("sigma_r", ctypes.c_double), ("gf_eps", ctypes.c_double), ("stencil", ctypes.c_int32),
-                ("norm", ctypes.c_int32)]
+                ("norm", ctypes.c_int32), ("channels", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class OperatorLayout(ctypes.Structure):
@@ -98,6 +98,9 @@ def load_library(path: str = LIB_PATH):
         "gsf_solver_workspace_bytes": ([vp, i32, i32, P(sz)], i32),
         "gsf_power_filter": ([vp, vp, vp, i32, vp, sz, vp], i32),
         "gsf_cg_filter": ([vp, vp, vp, i32, dbl, vp, sz, P(CgInfo), vp], i32),
+        "gsf_power_filter_block": ([vp, i32, vp, vp, i32, vp, sz, vp], i32),
+        "gsf_cg_filter_block": ([vp, i32, vp, vp, i32, dbl, vp, sz, P(CgInfo), vp], i32),
+        "gsf_srgb_to_lab": ([i32, i64, vp, vp, vp], i32),
         "gsf_reguided_workspace_bytes": ([P(OperatorDesc), i32, P(sz)], i32),
         "gsf_reguided_filter": ([P(OperatorDesc), i32, vp, vp, i32, dbl, vp, sz, P(CgInfo), vp], i32),
         "gsf_lobpcg_filter": ([vp, vp, vp, i32, i32, dbl, i32, vp, vp, vp, sz, P(LobpcgInfo), vp], i32),
@@ -160,9 +163,10 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
-def make_desc(kind, shape, radius, sigma_d=0.0, sigma_r=0.0, eps=0.0, prec=F32, stencil="square", norm="d"):
+def make_desc(kind, shape, radius, sigma_d=0.0, sigma_r=0.0, eps=0.0, prec=F32, stencil="square", norm="d",
+              channels=1):
     """gsf_operator_desc; stencil "square" / "cross" and norm "d" / "diagl"
-    (or the GSF_STENCIL_* / GSF_NORM_* values)."""
+    (or the GSF_STENCIL_* / GSF_NORM_* values); channels of the guidance."""
     d = OperatorDesc()
     d.kind = BF if kind in ("bf", BF) else GF
     d.ndim = len(shape)
@@ -175,6 +179,7 @@ def make_desc(kind, shape, radius, sigma_d=0.0, sigma_r=0.0, eps=0.0, prec=F32, 
     d.gf_eps = eps
     d.stencil = _STENCILS[stencil]
     d.norm = _NORMS[norm]
+    d.channels = channels
     return d
 
 
@@ -205,6 +210,19 @@ def reguided_filter(kind, shape, x0, method, kmax, radius, sigma_d=0.0, sigma_r=
                                  ctypes.byref(inf) if info else None, _stream(stream))
     _check(st, "reguided_filter")
     return y, (inf if info else None)
+
+
+def srgb_to_lab(rgb, out=None, stream=None):
+    """CIE-Lab of an n x 3 sRGB device tensor (float32 or float64), by
+    gsf_srgb_to_lab."""
+    torch = _torch()
+    lib = load_library()
+    if rgb.dim() != 2 or rgb.shape[1] != 3 or not rgb.is_contiguous():
+        raise ValueError("rgb must be a contiguous n x 3 device tensor")
+    prec = F32 if rgb.dtype == torch.float32 else F64
+    y = out if out is not None else torch.empty_like(rgb)
+    _check(lib.gsf_srgb_to_lab(prec, rgb.shape[0], _ptr(rgb), _ptr(y), _stream(stream)), "srgb_to_lab")
+    return y
 
 
 class Batch:
@@ -262,13 +280,13 @@ class Operator:
     Owns its device workspace (a torch uint8 tensor)."""
 
     def __init__(self, kind, shape, guidance, radius, sigma_d=0.0, sigma_r=0.0, eps=0.0, prec=F32,
-                 stream=None, ws=None, stencil="square", norm="d"):
+                 stream=None, ws=None, stencil="square", norm="d", channels=1):
         torch = _torch()
         lib = load_library()
         shape = tuple(int(s) for s in shape)
         self.shape, self.prec, self.kind, self.radius = shape, prec, kind, radius
         self.n = int(np.prod(shape))
-        d = make_desc(kind, shape, radius, sigma_d, sigma_r, eps, prec, stencil, norm)
+        d = make_desc(kind, shape, radius, sigma_d, sigma_r, eps, prec, stencil, norm, channels)
         self.desc = d
         nbytes = ctypes.c_size_t()
         _check(lib.gsf_operator_workspace_bytes(ctypes.byref(d), ctypes.byref(nbytes)), "operator_workspace_bytes")
@@ -280,8 +298,8 @@ class Operator:
         if not isinstance(g, torch.Tensor):
             g = torch.as_tensor(np.ascontiguousarray(g))
         g = g.to(device="cuda", dtype=_dtype(prec)).contiguous().reshape(-1)
-        if g.numel() != self.n:
-            raise ValueError("guidance size does not match shape")
+        if g.numel() != self.n * max(int(channels), 1):
+            raise ValueError("guidance size does not match shape and channels")
         h = ctypes.c_void_p()
         _check(lib.gsf_build_operator(ctypes.byref(d), _ptr(g), _ptr(self.ws), nbytes.value, _stream(stream),
                                       ctypes.byref(h)), "build_operator")
@@ -369,6 +387,29 @@ class Operator:
         _check(_lib.gsf_power_filter(self.handle, _ptr(x0), _ptr(y), kmax, _ptr(ws), ws.numel(), _stream(stream)),
                "power_filter")
         return y
+
+    def power_filter_block(self, x0, kmax, out=None, ws=None, stream=None):
+        """Power filter of every column of an n x m block (gsf_power_filter_block)."""
+        torch = _torch()
+        m = x0.shape[1]
+        y = out if out is not None else torch.empty_like(x0)
+        ws = ws if ws is not None else self.workspace(METHOD_POWER, m)
+        _check(_lib.gsf_power_filter_block(self.handle, m, _ptr(x0), _ptr(y), kmax, _ptr(ws), ws.numel(),
+                                           _stream(stream)), "power_filter_block")
+        return y
+
+    def cg_filter_block(self, x0, kmax, tol=0.0, out=None, ws=None, info=True, stream=None):
+        """CG filter of every column of an n x m block (gsf_cg_filter_block);
+        returns (y, list of m CgInfo or None)."""
+        torch = _torch()
+        m = x0.shape[1]
+        y = out if out is not None else torch.empty_like(x0)
+        ws = ws if ws is not None else self.workspace(METHOD_CG, m)
+        infos = (CgInfo * m)()
+        st = _lib.gsf_cg_filter_block(self.handle, m, _ptr(x0), _ptr(y), kmax, tol, _ptr(ws), ws.numel(),
+                                      infos if info else None, _stream(stream))
+        _check(st, "cg_filter_block")
+        return y, (list(infos) if info else None)
 
     def cg_filter(self, x0, kmax, tol=0.0, out=None, ws=None, info=True, stream=None):
         torch = _torch()

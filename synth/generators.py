@@ -16,6 +16,9 @@ G3  1D piecewise linear with steep ascents and descents: 6 edges at distinct
     edges the signal runs linearly with slope U[-0.5, 0.5] / n per sample from
     the start level U[0,1]; linear interpolation between these knots; plus
     sigma * N(0,1) noise (the paper's 0.1 * randn(N, 1) at sigma = 0.1).
+G4  2D colour (sRGB in [0, 1]): G2's construction with RGB colours instead of
+    intensities (background gradient between two colours U[0,1]^3, shape
+    colours U[0,1]^3), plus sigma * N(0,1) noise on every channel.
 G2  2D: linear-gradient background g0 + (g1-g0) * t(p) along a random
     direction, then 40 random rectangles / disks (probability 1/2 each) in
     painter's order with intensities U[0,1], centres uniform over the image,
@@ -26,7 +29,7 @@ from __future__ import annotations
 
 import numpy as np
 
-__all__ = ["piecewise_constant_1d", "piecewise_linear_1d", "scene_2d", "batch_items", "lobpcg_gaussian_block", "convnet_init"]
+__all__ = ["piecewise_constant_1d", "piecewise_linear_1d", "scene_2d", "scene_2d_rgb", "batch_items", "lobpcg_gaussian_block", "convnet_init"]
 
 
 def piecewise_constant_1d(n: int, sigma: float, seed, n_breaks: int = 8):
@@ -104,6 +107,40 @@ def scene_2d(height: int, width: int, sigma: float, seed, n_shapes: int = 40):
             mask = (sub_y - cy) ** 2 + (sub_x - cx) ** 2 <= rad * rad
         img[y0:y1, x0:x1][mask] = level
     noisy = img + sigma * rng.standard_normal((height, width))
+    return img, noisy
+
+
+def scene_2d_rgb(height: int, width: int, sigma: float, seed, n_shapes: int = 40):
+    """Return (clean, noisy) float64 arrays of shape (height, width, 3) (G4)."""
+    rng = np.random.default_rng(seed)
+    side = float(max(height, width))
+    yy, xx = np.meshgrid(np.arange(height) + 0.5, np.arange(width) + 0.5, indexing="ij")
+    c0, c1 = rng.uniform(0.0, 1.0, size=(2, 3))
+    phi = rng.uniform(0.0, 2.0 * np.pi)
+    t = np.cos(phi) * xx + np.sin(phi) * yy
+    tmin, tmax = t.min(), t.max()
+    t = (t - tmin) / (tmax - tmin) if tmax > tmin else np.zeros_like(t)
+    img = c0[None, None, :] + (c1 - c0)[None, None, :] * t[..., None]
+    for _ in range(n_shapes):
+        is_rect = rng.uniform() < 0.5
+        cy = rng.uniform(0.0, height)
+        cx = rng.uniform(0.0, width)
+        colour = rng.uniform(0.0, 1.0, size=3)
+        if is_rect:
+            hy = rng.uniform(0.02, 0.15) * side
+            hx = rng.uniform(0.02, 0.15) * side
+            y0, y1 = int(max(0, np.floor(cy - hy))), int(min(height, np.ceil(cy + hy) + 1))
+            x0, x1 = int(max(0, np.floor(cx - hx))), int(min(width, np.ceil(cx + hx) + 1))
+            sub_y, sub_x = yy[y0:y1, x0:x1], xx[y0:y1, x0:x1]
+            mask = (np.abs(sub_y - cy) <= hy) & (np.abs(sub_x - cx) <= hx)
+        else:
+            rad = rng.uniform(0.02, 0.15) * side
+            y0, y1 = int(max(0, np.floor(cy - rad))), int(min(height, np.ceil(cy + rad) + 1))
+            x0, x1 = int(max(0, np.floor(cx - rad))), int(min(width, np.ceil(cx + rad) + 1))
+            sub_y, sub_x = yy[y0:y1, x0:x1], xx[y0:y1, x0:x1]
+            mask = (sub_y - cy) ** 2 + (sub_x - cx) ** 2 <= rad * rad
+        img[y0:y1, x0:x1][mask] = colour
+    noisy = img + sigma * rng.standard_normal((height, width, 3))
     return img, noisy
 
 

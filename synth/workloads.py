@@ -16,6 +16,10 @@ image_1024_cross5  2D 1024x1024, G2, sigma=0.1 (noise variance 0.01, so a
                  of every weight, which the (diag L) normalization removes),
                  normalized by diag L, FP32; 20 steps of CG and of LOBPCG
                  (m=1) with and without the constraint.
+image_1024_rgb_bf11  2D 1024x1024 colour (G4), sigma=0.05 per channel, seed
+                 12; guidance: the noisy image in CIE-Lab; BF 11x11, sigma_d=2,
+                 sigma_r=5 (Delta E units), FP32; the three RGB channels
+                 filtered as one block: 10 CG steps, 20 power passes.
 STUDY_1D         the 1D filter study of Section 6: G3 signals with N = 500
                  and 1000 samples, sigma=0.1, seed 11; self-guided BF
                  (re-guided, window width 3: radius 1, sigma_d=1,
@@ -27,7 +31,7 @@ STUDY_1D         the 1D filter study of Section 6: G3 signals with N = 500
 """
 from __future__ import annotations
 
-from .generators import piecewise_constant_1d, piecewise_linear_1d, scene_2d
+from .generators import piecewise_constant_1d, piecewise_linear_1d, scene_2d, scene_2d_rgb
 
 WORKLOADS = {
     "signal_1d_4096": dict(shape=(4096,), sigma=0.1, seed=1, kind="bf", radius=5,
@@ -48,6 +52,9 @@ WORKLOADS = {
     "image_1024_cross5": dict(shape=(1024, 1024), sigma=0.1, seed=7, kind="bf", radius=1,
                               sigma_d=1.0, sigma_r=0.1, eps=0.0, prec="f32", stencil="cross", norm="diagl",
                               cg_iters=20, lobpcg_iters=20, lobpcg_m=1),
+    "image_1024_rgb_bf11": dict(shape=(1024, 1024), sigma=0.05, seed=12, kind="bf", radius=5,
+                                sigma_d=2.0, sigma_r=5.0, eps=0.0, prec="f32", channels=3,
+                                cg_iters=10, power_iters=20),
 }
 
 
@@ -70,4 +77,6 @@ def make_signal(name: str, shape=None, seed=None):
     seed = w["seed"] if seed is None else seed
     if len(shape) == 1:
         return piecewise_constant_1d(shape[0], w["sigma"], seed)
+    if w.get("channels", 1) == 3:
+        return scene_2d_rgb(shape[0], shape[1], w["sigma"], seed)
     return scene_2d(shape[0], shape[1], w["sigma"], seed)

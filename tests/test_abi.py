@@ -45,6 +45,7 @@ def _desc(**kw):
     d.dims[0], d.dims[1] = kw.get("dims", (64, 80))
     d.sigma_d, d.sigma_r, d.gf_eps = kw.get("sigma_d", 2.0), kw.get("sigma_r", 0.1), kw.get("eps", 0.01)
     d.stencil, d.norm = kw.get("stencil", 0), kw.get("norm", 0)
+    d.channels, d.reserved = kw.get("channels", 0), kw.get("reserved", 0)
     return d
 
 
@@ -64,18 +65,21 @@ def test_operator_workspace_sizes(lib):
                                  dict(dims=(0, 5)), dict(sigma_r=0.0), dict(sigma_d=-1.0),
                                  dict(sigma_r=float("nan")), dict(kind=1, eps=-1.0),
                                  dict(kind=1, eps=float("inf")), dict(stencil=2), dict(stencil=-1),
-                                 dict(norm=2), dict(kind=1, stencil=1), dict(kind=1, norm=1)])
+                                 dict(norm=2), dict(kind=1, stencil=1), dict(kind=1, norm=1),
+                                 dict(channels=-1), dict(channels=9), dict(kind=1, channels=3),
+                                 dict(reserved=1)])
 def test_invalid_descriptors_rejected(lib, bad):
     sz = ctypes.c_size_t()
     assert lib.gsf_operator_workspace_bytes(ctypes.byref(_desc(**bad)), ctypes.byref(sz)) == 1
 
 
 def test_descriptor_layout_matches_header():
-    """The ctypes struct matches gsf_operator_desc: 64 bytes with the stencil
-    and norm fields last."""
+    """The ctypes struct matches gsf_operator_desc: 72 bytes with the stencil,
+    norm, channels and reserved fields last."""
     from paper_1509_02468_amd.gsf import OperatorDesc
-    assert ctypes.sizeof(OperatorDesc) == 64
+    assert ctypes.sizeof(OperatorDesc) == 72
     assert OperatorDesc.stencil.offset == 56 and OperatorDesc.norm.offset == 60
+    assert OperatorDesc.channels.offset == 64 and OperatorDesc.reserved.offset == 68
 
 
 def test_cross_stencil_workspace(lib):
@@ -177,3 +181,17 @@ def test_learned_preconditioner_argument_checks(lib):
     assert lib.gsf_lobpcg_residual(None, 4, v, v, v, None) == 1
     assert lib.gsf_net_make_pair(None, v, 1, v, 1, v, v, v, v, 1 << 30, None) == 1
     assert lib.gsf_net_pair_workspace_bytes(None, ctypes.byref(sz)) == 1
+
+
+def test_block_and_colour_argument_checks(lib):
+    """Host-side validation of the multi-channel entry points (no launch)."""
+    sz = ctypes.c_size_t()
+    assert lib.gsf_srgb_to_lab(0, -1, None, None, None) == 1
+    assert lib.gsf_srgb_to_lab(2, 10, None, None, None) == 1
+    assert lib.gsf_srgb_to_lab(0, 0, None, None, None) == 0
+    assert lib.gsf_srgb_to_lab(0, 10, None, None, None) == 1
+    assert lib.gsf_power_filter_block(None, 3, None, None, 5, None, 0, None) == 1
+    assert lib.gsf_cg_filter_block(None, 3, None, None, 5, 0.0, None, 0, None, None) == 1
+    d = _desc(channels=3)
+    assert lib.gsf_reguided_workspace_bytes(ctypes.byref(d), 0, ctypes.byref(sz)) == 1
+    assert lib.gsf_operator_workspace_bytes(ctypes.byref(d), ctypes.byref(sz)) == 0
