@@ -362,10 +362,10 @@ struct RRShared {
   double SB[KMAX * LD];  // the same for B; work array of the Cholesky factorisation
   double L[KMAX * LD];   // Cholesky factor (dropped columns zero)
   double LK[KMAX * LD];  // compressed factor of the kept columns
-  double M[KMAX * LD];   // reduced matrix L^-1 A L^-T, tridiagonalised in place
-  double M2[KMAX * LD];  // work; then the Householder vectors (row k: v_k)
-  double V[KMAX * LD];   // work; then the wanted eigenvectors (columns)
-  double V2[KMAX * LD];  // Givens rotations of the tridiagonal QR, transposed (row j: column j)
+  double M[KMAX * LD];   // Jacobi matrix, two buffers
+  double M2[KMAX * LD];
+  double V[KMAX * LD];   // accumulated rotations, two buffers
+  double V2[KMAX * LD];
   double Cs[KMAX * 8];   // output coefficients, staged
   double delta[KMAX];
   double rinv[KMAX];
@@ -375,12 +375,52 @@ struct RRShared {
   int idx[KMAX];
   int order[KMAX];
 };
-// Broadcast lane k's value of v to the whole wave (k uniform).
-__device__ __forceinline__ double bcast(double v, int k) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane((int)b, k);
-  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), k);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+// the Jacobi schedule table reuses A, B, SA and SB
+static_assert((KMAX - 1) * 3 * 64 * sizeof(uint32_t) <= 4 * sizeof(double) * KMAX * LD, "schedule table");
+
+// Players of pair `slot` in round `rnd` of the round-robin schedule over np
+// players (np even): player 0 stays, the others rotate.  p < q.
+__device__ __forceinline__ void rr_pair(int slot, int rnd, int np, int& p, int& q) {
+  const int n1 = np - 1;
+  int a = slot - 1 + rnd;
+  a = a >= n1 ? a - n1 : a;
+  int b = (np - 1 - slot) - 1 + rnd;
+  b = b >= n1 ? b - n1 : b;
+  const int pa = slot == 0 ? 0 : 1 + a, pb = 1 + b;
+  p = pa < pb ? pa : pb;
+  q = pa < pb ? pb : pa;
+}
+
+// The Jacobi rotation J = [[c, s], [-s, c]] (rows and columns p, q) that
+// annihilates m_pq of the symmetric 2 x 2 block [[m_pp, m_pq], [m_pq, m_qq]]:
+// with d = m_qq - m_pp, h = sqrt(d^2 + 4 m_pq^2) and u = d + sign(d) h (the
+// root t = 2 m_pq / u of t^2 + 2 theta t - 1 = 0 of smaller magnitude,
+// theta = d / (2 m_pq)), c = |u| / sqrt(2 h |u|) and s = sign(u) 2 m_pq /
+// sqrt(2 h |u|), which is c = (1 + t^2)^-1/2, s = t c with one reciprocal
+// square root for both (so c^2 + s^2 = 1 to rounding).  The rotated diagonal
+// is m_pp - t m_pq, m_qq + t m_pq, with t m_pq = sign(u) 4 h m_pq^2 / (2 h |u|).
+// The identity when `live` is false (m_pq = 0, or q is the dummy player);
+// no branches, so every lane runs the same instruction stream.
+struct JRot {
+  double c, s, dp, dq;
+};
+__device__ __forceinline__ JRot jacobi_rot(double mpp, double mqq, double mpq, bool live) {
+  live = live && mpq != 0.0;
+  const double apq = live ? mpq : 1.0;  // keeps the dead lanes finite
+  const double d = mqq - mpp;
+  const double y = fma(d, d, 4.0 * apq * apq);
+  const double h = y * rsq_nr(y);
+  const double au = fabs(d) + h;
+  const double r2 = rsq_nr(2.0 * h * au);
+  const double sg = d >= 0.0 ? 1.0 : -1.0;
+  const double s = sg * (2.0 * apq * r2);
+  const double tm = sg * (4.0 * h * apq * apq * (r2 * r2));
+  JRot r;
+  r.c = live ? au * r2 : 1.0;
+  r.s = live ? s : 0.0;
+  r.dp = live ? mpp - tm : mpp;
+  r.dq = live ? mqq + tm : mqq;
+  return r;
 }
 
 // Solves the Rayleigh-Ritz problem for GA, GB (ns x ns, already loaded into
@@ -391,12 +431,11 @@ __device__ __forceinline__ double bcast(double v, int k) {
 // zero data there, which changes nothing and keeps the loops free of
 // conditionals).  Steps: symmetrise; scale to unit diag(GB) (columns with a
 // negligible diagonal are dropped); Cholesky GB = L L^T that drops columns
-// with a pivot below drop_tol; M = L^-1 GA L^-T on the kept columns; the
-// eigenpairs of M by Householder tridiagonalisation and the implicit
-// symmetric tridiagonal QR iteration with the Wilkinson shift (Golub and Van
-// Loan, sections 8.3.1-8.3.3); C = L^-T Z for the m smallest.  Loads are
-// issued unconditionally (clamped indices) and only stores are masked, so a
-// lane never waits on a load inside a branch.
+// with a pivot below drop_tol; M = L^-1 GA L^-T on the kept columns; cyclic
+// Jacobi on M (parallel round-robin ordering, one 2 x 2 block of every
+// rotated pair of rows and columns per lane); C = L^-T Z.  Loads are issued
+// unconditionally (clamped indices) and only stores are masked, so a lane
+// never waits on a load inside a branch.
 template <int KB>
 __device__ void rayleigh_ritz_kb(RRShared& sh, int ns, int m, double drop_tol, double zero_tol, double conv2,
                                  double* Cout, double* theta, int* kept_out, int* nkept_out) {
@@ -514,158 +553,130 @@ __device__ void rayleigh_ritz_kb(RRShared& sh, int ns, int m, double drop_tol, d
   }
   wave_fence();
 
-  // Householder tridiagonalisation of M (K x K) in place: step k maps the
-  // column below the diagonal, x = M[k+1:, k], onto alpha e_1 with
-  // H = I - beta v v^T, v = x - alpha e_1, alpha = -sign(x_0) ||x||,
-  // beta = 1 / (||x||^2 - x_0 alpha), and updates the trailing block as
-  // M <- M - v w^T - w v^T with p = beta M v, w = p - (beta/2)(v^T p) v.
-  // Lane i holds entry i of x, v, p and w; row j of M is read at column i
-  // (contiguous across lanes; M stays symmetric to rounding).  The tridiagonal
-  // ends up distributed over the lanes: lane i holds d_i = T_ii and
-  // e_i = T_{i,i+1}; v_k is kept in row k of M2 and beta_k in lane k of hb.
-  double d = 0.0, e = 0.0, hb = 0.0;
-  const bool lk = lane < K;
-  for (int k = 0; k + 2 < K; ++k) {
-    const bool in = lane > k && lk;
-    const double xi = in ? sh.M[k * LD + (lane < K ? lane : 0)] : 0.0;
-    const double s2 = wave_sum(xi * xi);
-    const double x0 = bcast(xi, k + 1);
-    const double dk = sh.M[k * LD + k];
-    d = lane == k ? dk : d;
-    double vi = 0.0, beta = 0.0, alpha = x0;
-    if (s2 - x0 * x0 > 0.0) {  // uniform: something below the subdiagonal
-      const double sig = sqrt(s2);
-      alpha = x0 >= 0.0 ? -sig : sig;
-      beta = 1.0 / (s2 - x0 * alpha);
-      vi = lane == k + 1 ? x0 - alpha : xi;
-      double pi = 0.0;
-      for (int j = k + 1; j < K; ++j) pi = fma(sh.M[j * LD + (lane < K ? lane : 0)], bcast(vi, j), pi);
-      pi = in ? beta * pi : 0.0;
-      const double kc = 0.5 * beta * wave_sum(vi * pi);
-      const double wi = pi - kc * vi;
-      for (int j = k + 1; j < K; ++j) {
-        const double vj = bcast(vi, j), wj = bcast(wi, j);
-        const double mji = sh.M[j * LD + (lane < K ? lane : 0)];
-        if (in) sh.M[j * LD + lane] = mji - (vj * wi + wj * vi);
-      }
-      wave_fence();
+  // cyclic Jacobi: in each round the np/2 disjoint pairs of the round-robin
+  // schedule are rotated together, M <- J^T M J, V <- V J.  Lane b owns the
+  // 2 x 2 block (pair P = b / nh rows, pair Q = b % nh columns) and computes
+  // both rotations itself (bitwise the same on every lane that needs them).
+  // The schedule is tabulated once per call (one word per round, block slot
+  // and lane, in the Gram and scaled arrays, which are dead by now), and the
+  // round loop alternates the two buffers explicitly so that every LDS
+  // address is a table offset plus a constant.
+  const int np = (K + 1) & ~1;  // players (a dummy when K is odd)
+  const int nh = np >> 1, nblk = nh * nh, nr = np - 1;
+  const int nslot = (nblk + 63) >> 6;
+  uint32_t* tab = reinterpret_cast<uint32_t*>(sh.A);  // (KMAX-1) x 3 x 64 words fit in A, B, SA, SB
+  for (int r = 0; r < nr; ++r) {
+    for (int sl = 0; sl < nslot; ++sl) {
+      const int bl = sl * 64 + lane;
+      const int b = bl < nblk ? bl : 0;
+      const int P = b / nh, Q = b - (b / nh) * nh;
+      int i0, i1, j0, j1;
+      rr_pair(P, r, np, i0, i1);
+      rr_pair(Q, r, np, j0, j1);
+      const uint32_t ri = i1 < K, rj = j1 < K;  // the second player is not the dummy
+      const uint32_t i1c = ri ? i1 : i0, j1c = rj ? j1 : j0;
+      tab[(r * nslot + sl) * 64 + lane] = (uint32_t)i0 | (i1c << 5) | ((uint32_t)j0 << 10) | (j1c << 15) |
+                                          (ri << 20) | (rj << 21) | ((uint32_t)(bl < nblk) << 22) |
+                                          ((uint32_t)(P == Q) << 23);
     }
-    e = lane == k ? alpha : e;
-    hb = lane == k ? beta : hb;
-    if (lk) sh.M2[k * LD + lane] = vi;
-  }
-  // the trailing 1 x 1 or 2 x 2 block
-  if (K >= 2) {
-    const double a = sh.M[(K - 2) * LD + (K - 2)], b = sh.M[(K - 1) * LD + (K - 1)];
-    const double f = sh.M[(K - 1) * LD + (K - 2)];
-    d = lane == K - 2 ? a : (lane == K - 1 ? b : d);
-    e = lane == K - 2 ? f : e;
-  } else {
-    d = lane == 0 ? sh.M[0] : d;
-  }
-  e = lane < K - 1 ? e : 0.0;
-  // Z = I (stored transposed: row j of V2 is column j of Z)
-  for (int q = lane; q < K * K; q += 64) {
-    const int j = q / K, i = q - (q / K) * K;
-    sh.V2[j * LD + i] = i == j ? 1.0 : 0.0;
   }
   wave_fence();
-  // Implicit symmetric QR with the Wilkinson shift on the unreduced block
-  // [l, h] at the bottom of the undeflated part; an off-diagonal entry is set
-  // to zero once |e_i| <= tol (|d_i| + |d_{i+1}|).  Each step chases the
-  // bulge down with Givens rotations G = [[c, -s], [s, c]] on (k, k+1),
-  // T <- G^T T G, Z <- Z G.  All lanes compute the rotation chain (uniform
-  // values); lane i updates row i of Z.
-  const double tol = conv2 > 0.0 ? fmax(sqrt(conv2), 2.220446049250313e-16) : 2.220446049250313e-16;
-  for (int it = 0; it < 30 * KB; ++it) {
-    const double dn = __shfl_down(d, 1, 64);
-    if (lane < K - 1 && fabs(e) <= tol * (fabs(d) + fabs(dn))) e = 0.0;
-    const unsigned long long nz = __ballot(lane < K - 1 && e != 0.0);
-    if (nz == 0ull) break;
-    const int h = 64 - __clzll(nz);  // e_{h-1} != 0 and e_h, e_{h+1}, ... == 0
-    const unsigned long long zero_below = ~nz & ((1ull << (h - 1)) - 1ull);
-    const int l = zero_below ? 64 - __clzll(zero_below) : 0;
-    const double dh1 = bcast(d, h - 1), dh = bcast(d, h), eh1 = bcast(e, h - 1);
-    const double delta = 0.5 * (dh1 - dh);
-    const double den = delta + (delta >= 0.0 ? 1.0 : -1.0) * sqrt(fma(delta, delta, eh1 * eh1));
-    const double mu = dh - eh1 * (eh1 / den);
-    double x = bcast(d, l) - mu, z = bcast(e, l);
-    double a = bcast(d, l), f = bcast(e, l);
-    for (int k = l; k < h; ++k) {
-      const double q2 = fma(x, x, z * z);
-      const double ir = q2 > 0.0 ? rsq_nr2(q2) : 0.0;
-      const double c = q2 > 0.0 ? x * ir : 1.0, sn = q2 > 0.0 ? z * ir : 0.0;
-      if (k > l) e = lane == k - 1 ? q2 * ir : e;  // r = hypot(x, z)
-      const double b = bcast(d, k + 1);
-      const double cc = c * c, ss = sn * sn, cs = c * sn;
-      const double dk = fma(cc, a, fma(2.0 * cs, f, ss * b));
-      const double dk1 = fma(ss, a, fma(-2.0 * cs, f, cc * b));
-      const double ek = fma(cs, b - a, (cc - ss) * f);
-      d = lane == k ? dk : (lane == k + 1 ? dk1 : d);
-      e = lane == k ? ek : e;
-      if (k + 1 < h) {
-        const double en = bcast(e, k + 1);
-        const double ecn = c * en;
-        e = lane == k + 1 ? ecn : e;
-        x = ek;
-        z = sn * en;
-        a = dk1;
-        f = ecn;
+  auto jround = [&](int rnd, const double* __restrict__ Mc, double* __restrict__ Mn, const double* __restrict__ Vc,
+                    double* __restrict__ Vn) {
+    for (int sl = 0; sl < nslot; ++sl) {
+      const uint32_t w = tab[(rnd * nslot + sl) * 64 + lane];
+      const int i0 = w & 31, i1 = (w >> 5) & 31, j0 = (w >> 10) & 31, j1 = (w >> 15) & 31;
+      const bool ri = (w >> 20) & 1, rj = (w >> 21) & 1, act = (w >> 22) & 1, dg = (w >> 23) & 1;
+      const int a0 = i0 * LD, a1 = i1 * LD, b0 = j0 * LD, b1 = j1 * LD;
+      const double m00 = Mc[a0 + j0], m01 = Mc[a0 + j1], m10 = Mc[a1 + j0], m11 = Mc[a1 + j1];
+      const double pp = Mc[a0 + i0], qq = Mc[a1 + i1], pq = Mc[a0 + i1];
+      const double rr = Mc[b0 + j0], ss = Mc[b1 + j1], rs = Mc[b0 + j1];
+      const double v00 = Vc[a0 + j0], v01 = Vc[a0 + j1], v10 = Vc[a1 + j0], v11 = Vc[a1 + j1];
+      const JRot jp = jacobi_rot(pp, qq, pq, ri);
+      const JRot jq = jacobi_rot(rr, ss, rs, rj);
+      // X = J_P^T B, B' = X J_Q
+      const double x00 = jp.c * m00 - jp.s * m10, x01 = jp.c * m01 - jp.s * m11;
+      const double x10 = jp.s * m00 + jp.c * m10, x11 = jp.s * m01 + jp.c * m11;
+      double y00 = x00 * jq.c - x01 * jq.s, y01 = x00 * jq.s + x01 * jq.c;
+      double y10 = x10 * jq.c - x11 * jq.s, y11 = x10 * jq.s + x11 * jq.c;
+      if (dg) {  // the rotated pair itself: exact zero off the diagonal
+        y00 = jp.dp;
+        y11 = jp.dq;
+        y01 = 0.0;
+        y10 = 0.0;
       }
-      const double z0 = sh.V2[k * LD + (lane < K ? lane : 0)], z1 = sh.V2[(k + 1) * LD + (lane < K ? lane : 0)];
-      if (lk) {
-        sh.V2[k * LD + lane] = fma(c, z0, sn * z1);
-        sh.V2[(k + 1) * LD + lane] = fma(-sn, z0, c * z1);
+      if (act) {
+        Mn[a0 + j0] = y00;
+        Vn[a0 + j0] = v00 * jq.c - v01 * jq.s;
+        if (rj) {
+          Mn[a0 + j1] = y01;
+          Vn[a0 + j1] = v00 * jq.s + v01 * jq.c;
+        }
+        if (ri) {
+          Mn[a1 + j0] = y10;
+          Vn[a1 + j0] = v10 * jq.c - v11 * jq.s;
+        }
+        if (ri && rj) {
+          Mn[a1 + j1] = y11;
+          Vn[a1 + j1] = v10 * jq.s + v11 * jq.c;
+        }
       }
     }
+  };
+  // convergence: off-diagonal Frobenius mass below sqrt(conv2) of the whole
+  // (relative: 1e-14 for FP64 data, 1e-10 for FP32 data, whose Gram entries
+  // carry ~1e-7 relative errors anyway); the butterfly sum leaves the same
+  // value on every lane
+  const double c2 = conv2 > 0.0 ? conv2 : 1e-28;
+  auto converged = [&](const double* Mc) {
+    double off = 0.0, dia = 0.0;
+    for (int e = lane; e < K * K; e += 64) {
+      const int i = e / K, j = e - (e / K) * K;
+      const double v = Mc[i * LD + j] * Mc[i * LD + j];
+      off += i == j ? 0.0 : v;
+      dia += i == j ? v : 0.0;
+    }
+    off = wave_sum(off);
+    dia = wave_sum(dia);
+    return off <= c2 * (off + dia);
+  };
+  int rnd = 0, sweep = 0, cur = 0;  // cur = 1: the current matrix is in M2, V2
+  while (true) {
+    jround(rnd, sh.M, sh.M2, sh.V, sh.V2);
     wave_fence();
+    cur = 1;
+    if (++rnd == nr) {
+      rnd = 0;
+      if (converged(sh.M2) || ++sweep == 30) break;
+    }
+    jround(rnd, sh.M2, sh.M, sh.V2, sh.V);
+    wave_fence();
+    cur = 0;
+    if (++rnd == nr) {
+      rnd = 0;
+      if (converged(sh.M) || ++sweep == 30) break;
+    }
   }
-  // eigenvalues ascending (ties by index)
-  if (lk) sh.ev[lane] = d;
-  for (int q = lane; q < ns * m; q += 64) sh.Cs[q] = 0.0;
+  const double* Mc = cur ? sh.M2 : sh.M;
+  const double* Vc = cur ? sh.V2 : sh.V;
+  // order eigenvalues ascending (ties by index)
+  {
+    const int li = lane < K ? lane : 0;
+    sh.ev[lane < KB ? lane : 0] = Mc[li * LD + li];  // lanes >= K store junk past K (never read)
+  }
+  for (int e = lane; e < ns * m; e += 64) sh.Cs[e] = 0.0;
   wave_fence();
   {
-    const double ei = sh.ev[lane < K ? lane : 0];
+    const double e = sh.ev[lane < K ? lane : 0];
     int rank = 0;
 #pragma unroll
     for (int j = 0; j < KB; ++j) {
-      const double ej = sh.ev[j < K ? j : 0];
-      rank += (j < K && (ej < ei || (ej == ei && j < lane))) ? 1 : 0;
+      const double ej = sh.ev[j];
+      rank += (j < K && (ej < e || (ej == e && j < lane))) ? 1 : 0;
     }
-    if (lk) sh.order[rank] = lane;
+    if (lane < K) sh.order[rank] = lane;
   }
   wave_fence();
-  // eigenvectors of M for the m smallest: y = H_0 H_1 ... H_{K-3} z, lane i
-  // holding entry i of every wanted vector; stored as columns order[t] of V
-  {
-    double y[kMaxBlock];
-#pragma unroll
-    for (int t = 0; t < kMaxBlock; ++t) {
-      const int col = sh.order[t < m ? t : 0];
-      y[t] = (t < m && lk) ? sh.V2[col * LD + lane] : 0.0;
-    }
-    for (int k = K - 3; k >= 0; --k) {
-      const double vk = lk ? sh.M2[k * LD + lane] : 0.0;
-      const double bk = bcast(hb, k);
-      double dots[kMaxBlock];
-#pragma unroll
-      for (int t = 0; t < kMaxBlock; ++t) dots[t] = t < m ? vk * y[t] : 0.0;
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-#pragma unroll
-        for (int t = 0; t < kMaxBlock; ++t) dots[t] += __shfl_xor(dots[t], off, 64);
-      }
-#pragma unroll
-      for (int t = 0; t < kMaxBlock; ++t) y[t] = fma(-bk * dots[t], vk, y[t]);
-    }
-#pragma unroll
-    for (int t = 0; t < kMaxBlock; ++t) {
-      const int col = sh.order[t < m ? t : 0];
-      if (t < m && lk) sh.V[lane * LD + col] = y[t];
-    }
-  }
-  wave_fence();
-  const double* Vc = sh.V;
   // C_K = LK^-T Z_m: lane t solves LK^T c = Z[:, order[t]] by back substitution
   {
     const int t = lane < m ? lane : 0;
