@@ -45,6 +45,8 @@ def _args():
     ap.add_argument("--roofline-reps", type=int, default=50)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--serial", action="store_true", help="run CG and LOBPCG one after the other")
+    ap.add_argument("--separate", action="store_true",
+                    help="run CG and LOBPCG as two independent calls on two streams instead of the joint driver")
     ap.add_argument("--no-batch", action="store_true", help="skip the uneven-batch measurement")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner measurement")
     ap.add_argument("--no-reguided", action="store_true", help="skip the re-guided (non-linear) filter measurement")
@@ -64,9 +66,9 @@ def _args():
 
 def kernels_only(a):
     """Launch the dominant kernels alone, every tile choice of the BF apply
-    (1, 2 and 4 rows per thread) for m = 1 and the block width, 10 launches
-    each, then a plain device copy of 1 GiB whose counter readings calibrate
-    the byte counters."""
+    (1, 2 and 4 rows per thread) for m = 1, the block width and the joint
+    (m + 1)-column apply, 10 launches each, then a plain device copy of 1 GiB
+    whose counter readings calibrate the byte counters."""
     import torch
     import paper_1509_02468_amd as gsf
     from synth import WORKLOADS, make_signal
@@ -87,6 +89,14 @@ def kernels_only(a):
                 op.set_apply_rows(mm, rows)
             for _ in range(10):
                 op.apply(xb, gsf.FORM_LSYM, out=yb)
+    if w["kind"] == "bf":  # the joint (m + 1)-column apply of the joint CG + LOBPCG driver
+        xb = torch.randn((n, m), dtype=dt, device="cuda")
+        xc = torch.randn(n, dtype=dt, device="cuda")
+        yb, yc = torch.empty_like(xb), torch.empty_like(xc)
+        for rows in (1, 2, 4):
+            op.set_apply_rows(m, rows)
+            for _ in range(10):
+                op.apply_joint(xb, xc, gsf.FORM_LSYM, out=yb, out2=yc)
     src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
     dst = torch.empty_like(src)
     for _ in range(3):
@@ -547,20 +557,27 @@ def main():
         tuned[f"m{mm}"] = {"rows_per_thread": best, "us_by_rows_1_2_4": [round(t, 1) for t in times]}
     ws_cg = op.workspace(gsf.METHOD_CG)
     ws_lob = op.workspace(gsf.METHOD_LOBPCG, m)
+    ws_joint = op.joint_workspace(m)
     y_cg = torch.empty_like(x0)
     y_lob = torch.empty_like(x0)
 
-    # CG and LOBPCG are independent filters of the same operator: run them on
-    # two streams so CG's bandwidth-bound kernels fill the GPU while LOBPCG's
-    # one-workgroup Rayleigh-Ritz step runs.  LOBPCG, the longer chain, is
-    # enqueued first (measured: 12.7 ms per pair against 13.1 ms the other way
-    # round).  (A GF operator's apply uses the handle's scratch planes, so its
-    # filters stay on one stream.)
-    concurrent = (w["kind"] == "bf") and not a.serial
+    # CG and LOBPCG are independent filters of the same operator.  Default: the
+    # joint driver, whose step k of both filters shares one stencil pass (the
+    # CG vector as a fifth column of the LOBPCG block) and runs the CG scalars
+    # on a second stream while LOBPCG's one-workgroup Rayleigh-Ritz step runs.
+    # --separate: two independent calls on two streams (LOBPCG, the longer
+    # chain, enqueued first); --serial: one after the other.  (A GF operator's
+    # apply uses the handle's scratch planes, so its filters stay on one
+    # stream.)
+    mode = "serial" if (a.serial or w["kind"] != "bf") else ("separate" if a.separate else "joint")
+    concurrent = mode == "separate"
     s_cg, s_lob = torch.cuda.Stream(), torch.cuda.Stream()
 
     def step():
         op_s = gsf.Operator(w["kind"], shape, x0, w["radius"], w["sigma_d"], w["sigma_r"], w["eps"], prec)
+        if mode == "joint":
+            op_s.joint_filter(x0, kcg, x0, m, klob, out_cg=y_cg, out_lob=y_lob, ws=ws_joint, info=False)
+            return op_s
         if not concurrent:
             op_s.cg_filter(x0, kcg, out=y_cg, ws=ws_cg, info=False)
             op_s.lobpcg_filter(x0, m, klob, out=y_lob, ws=ws_lob, info=False)
@@ -589,46 +606,60 @@ def main():
     applies = n * ((kcg + 1) + m * (klob + 1))
     value = applies / (el / a.steps) / 1e6
 
-    # dominant kernel: stencil apply (m = 1 and m = block size), events on one stream
+    # dominant kernel: the stencil apply the step runs most (joint mode: the
+    # (m + 1)-column joint apply; else the m = 1 or the m-column apply), timed
+    # alone with events on its own stream
     K = (2 * w["radius"] + 1) ** len(shape)
     esz = 4 if prec == gsf.F32 else 8
     rl = {}
     s2 = torch.cuda.Stream()
-    for mm in (1, m):
-        xb = torch.randn((n, mm) if mm > 1 else (n,), dtype=dt, device="cuda")
-        yb = torch.empty_like(xb)
+
+    def time_launches(launch):
         with torch.cuda.stream(s2):
             for _ in range(5):
-                op.apply(xb, gsf.FORM_LSYM, out=yb, stream=s2)
+                launch()
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             e0.record(s2)
             for _ in range(a.roofline_reps):
-                op.apply(xb, gsf.FORM_LSYM, out=yb, stream=s2)
+                launch()
             e1.record(s2)
         e1.synchronize()
-        t_ms = e0.elapsed_time(e1) / a.roofline_reps
-        algo = esz * ((K + 1) // 2 + 2 * mm) * n
-        rl[mm] = (algo, t_ms)
-    # the block apply moves more bytes per launch and runs as often as the m = 1 apply
-    dom = m if rl[m][1] * (klob + 1) >= rl[1][1] * (kcg + 1) else 1
+        return e0.elapsed_time(e1) / a.roofline_reps
+
+    for mm in (1, m):
+        xb = torch.randn((n, mm) if mm > 1 else (n,), dtype=dt, device="cuda")
+        yb = torch.empty_like(xb)
+        t_ms = time_launches(lambda: op.apply(xb, gsf.FORM_LSYM, out=yb, stream=s2))
+        rl[f"m{mm}"] = (esz * ((K + 1) // 2 + 2 * mm) * n, t_ms)
+    if mode == "joint":
+        xb = torch.randn((n, m), dtype=dt, device="cuda")
+        xc = torch.randn(n, dtype=dt, device="cuda")
+        yb, yc = torch.empty_like(xb), torch.empty_like(xc)
+        t_ms = time_launches(lambda: op.apply_joint(xb, xc, gsf.FORM_LSYM, out=yb, out2=yc, stream=s2))
+        rl[f"m{m}+1"] = (esz * ((K + 1) // 2 + 2 * (m + 1)) * n, t_ms)
+        dom = f"m{m}+1"
+        dom_rows = tuned[f"m{m}"]["rows_per_thread"]
+    else:
+        # the block apply moves more bytes per launch and runs as often as the m = 1 apply
+        dom = f"m{m}" if rl[f"m{m}"][1] * (klob + 1) >= rl["m1"][1] * (kcg + 1) else "m1"
+        dom_rows = tuned[dom]["rows_per_thread"]
     algo, t_ms = rl[dom]
     achieved = algo / (t_ms * 1e-3) / 1e9
     # HBM bytes per launch from the committed counter passes, for the tile the
     # tuner chose (null when no entry covers that kernel)
     traffic = None
-    dom_rows = tuned[f"m{dom}"]["rows_per_thread"]
     if os.path.exists(TRAFFIC_FILE):
         try:
-            tr = json.load(open(TRAFFIC_FILE)).get(f"{a.workload}:m{dom}:rows{dom_rows}")
+            tr = json.load(open(TRAFFIC_FILE)).get(f"{a.workload}:{dom}:rows{dom_rows}")
             traffic = tr.get("bytes_per_launch") if tr else None
         except Exception:
             traffic = None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": f"bf_apply2d m={dom} rows_per_thread={dom_rows}", "us_per_launch": round(t_ms * 1e3, 2),
+                "kernel": f"bf_apply {dom} rows_per_thread={dom_rows}", "us_per_launch": round(t_ms * 1e3, 2),
                 "algorithmic_bytes_per_launch": algo,
-                "m1_us": round(rl[1][1] * 1e3, 2), f"m{m}_us": round(rl[m][1] * 1e3, 2)}
+                **{f"{k}_us": round(v[1] * 1e3, 2) for k, v in rl.items()}}
 
     batch = None if a.no_batch else batch_bench()
     learned_res = None if a.no_learned else learned_bench(a.learned_images, eval_side=a.learned_eval)
@@ -643,7 +674,7 @@ def main():
            "dtype": "f32" if prec == gsf.F32 else "f64", "data": "synthetic",
            "config": {"workload": a.workload, "shape": list(shape), "operator": f"{w['kind']} r={w['radius']}",
                       "cg_iters": kcg, "lobpcg_iters": klob, "lobpcg_m": m, "parallelism": "single-gpu",
-                      "apply_tuning": tuned, "cg_lobpcg_streams": 2 if concurrent else 1},
+                      "apply_tuning": tuned, "cg_lobpcg_mode": mode},
            "roofline": roofline, "cpu_baseline": cpu, "batch": batch, "learned": learned_res,
            "reguided": reguided_res, "image_experiment": image_res,
            "study_1d": study_res, "colour": colour_res}

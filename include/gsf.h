@@ -204,6 +204,12 @@ void gsf_destroy_operator(gsf_operator* op);
  * point-major; y must not overlap x.  GSF_EINVAL for another form. */
 gsf_status gsf_apply(const gsf_operator* op, int form, int m, const void* x, void* y,
                      void* stream);
+/* Joint apply: y = F x for an n x m block and y2 = F x2 for one more vector,
+ * in one pass over the operator where it offers that (BF on the square
+ * window or 1D, m = 1 or 4), else as two applies.  No output may overlap an
+ * input or the other output (GSF_EINVAL). */
+gsf_status gsf_apply_joint(const gsf_operator* op, int form, int m, const void* x, void* y, const void* x2,
+                           void* y2, void* stream);
 
 /* ---- solvers ---------------------------------------------------------------
  * gsf_solver_workspace_bytes: workspace for `method` with block size m: the
@@ -287,6 +293,26 @@ gsf_status gsf_lobpcg_filter(const gsf_operator* op, const void* x0, void* x_out
                              int kmax, double tol, int constraint, const gsf_precond* T,
                              void* ritz_vecs, void* ws, size_t ws_bytes, gsf_lobpcg_info* info,
                              void* stream);
+
+/* Joint CG + LOBPCG filters of one operator (Algorithms 2 and 3 side by side):
+ * the results are those of gsf_cg_filter(x0_cg, kmax_cg, tol 0) and
+ * gsf_lobpcg_filter(x0_lob, m, kmax_lob, tol 0, constraint, T = NULL) up to the
+ * summation order of the CG dot products.  While both run, step k of each
+ * shares one stencil pass: the CG vector is applied as one more column of the
+ * LOBPCG block (BF operators on the square window or 1D with m = 1 or 4; other
+ * operators apply the two blocks one after the other).  The CG scalars and
+ * updates run on a second stream of the device, which the library creates on
+ * first use and keeps until the process ends (default priority; forked from
+ * and joined back to `stream`, so the call is ordered on `stream` like the
+ * others); a handle must not run two joint calls at once.  x0_cg, x_cg: n elements; x0_lob, x_lob: n elements.
+ * Workspace: gsf_joint_workspace_bytes(op, m, ...).  cg_info, lob_info: NULL
+ * or summaries as for the single filters.  GSF_EINVAL for NULL pointers,
+ * kmax < 0 or m outside 1..8; GSF_ENOMEM for a short workspace; returns the
+ * LOBPCG status if not OK, else the CG status. */
+gsf_status gsf_joint_workspace_bytes(const gsf_operator* op, int m, size_t* bytes);
+gsf_status gsf_joint_filter(gsf_operator* op, const void* x0_cg, void* x_cg, int kmax_cg, const void* x0_lob,
+                            void* x_lob, int m, int kmax_lob, int constraint, void* ws, size_t ws_bytes,
+                            gsf_cg_info* cg_info, gsf_lobpcg_info* lob_info, void* stream);
 
 /* ---- learned preconditioner (the preconditioner T of Algorithm 3) ----------
  * Network: conv3x3 (2 -> 16 channels) + ReLU, conv3x3 (16 -> 16) + ReLU,

@@ -1,5 +1,6 @@
 // C ABI of libgsf: validation, workspace layout and the solver drivers.
 #include <cmath>
+#include <mutex>
 #include <cstring>
 #include <new>
 
@@ -24,6 +25,9 @@ gsf_status launch_bcg(int kind, const Operator& op, int m, void* z, void* r, voi
                       BlockCgState* st, hipStream_t s);
 gsf_status launch_bcg_state_init(BlockCgState* st, const BlockCgState& v, hipStream_t s);
 gsf_status launch_srgb_to_lab(int prec, int64_t n, const void* rgb, void* lab, hipStream_t s);
+bool launch_bf_apply_joint(const Operator& op, int form, int m, const void* x, int64_t ldx, void* y, int64_t ldy,
+                           const void* x2, int64_t ldx2, void* y2, int64_t ldy2, double* dot, int* nparts,
+                           hipStream_t s);
 gsf_status launch_scale(const Operator& op, const void* in, void* out, int divide, hipStream_t s);
 gsf_status launch_cg_init(const Operator& op, const void* z, void* r, double* partials, CgState* st,
                           hipStream_t s);
@@ -514,6 +518,27 @@ gsf_status gsf_apply(const gsf_operator* h, int form, int m, const void* x, void
   return apply_any(op, form, m, x, m, y, m, nullptr, nullptr, (hipStream_t)stream);
 }
 
+gsf_status gsf_apply_joint(const gsf_operator* h, int form, int m, const void* x, void* y, const void* x2, void* y2,
+                           void* stream) {
+  if (h == nullptr || x == nullptr || y == nullptr || x2 == nullptr || y2 == nullptr) return GSF_EINVAL;
+  if (form != GSF_FORM_N && form != GSF_FORM_LSYM && form != GSF_FORM_RW && form != GSF_FORM_L) return GSF_EINVAL;
+  if (m < 1 || m > kMaxBlock) return GSF_EINVAL;
+  const Operator& op = h->op;
+  const size_t bytes = (size_t)op.n * m * op.elem, b1 = (size_t)op.n * op.elem;
+  auto overlap = [](const void* a, size_t na, const void* b, size_t nb) {
+    const char *pa = (const char*)a, *pb = (const char*)b;
+    return pa < pb + nb && pb < pa + na;
+  };
+  if (overlap(x, bytes, y, bytes) || overlap(x, bytes, y2, b1) || overlap(x2, b1, y, bytes) ||
+      overlap(x2, b1, y2, b1) || overlap(y, bytes, y2, b1))
+    return GSF_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  if (launch_bf_apply_joint(op, form, m, x, m, y, m, x2, 1, y2, 1, nullptr, nullptr, s))
+    return hip_ok(hipGetLastError());
+  GSF_TRY(apply_any(op, form, m, x, m, y, m, nullptr, nullptr, s));
+  return apply_any(op, form, 1, x2, 1, y2, 1, nullptr, nullptr, s);
+}
+
 gsf_status gsf_solver_workspace_bytes(const gsf_operator* h, int method, int m, size_t* bytes) {
   if (h == nullptr || bytes == nullptr) return GSF_EINVAL;
   const Operator& op = h->op;
@@ -632,143 +657,144 @@ gsf_status gsf_srgb_to_lab(int prec, int64_t n, const void* rgb, void* lab, void
   return launch_srgb_to_lab(prec, n, rgb, lab, (hipStream_t)stream);
 }
 
-gsf_status gsf_cg_filter(const gsf_operator* h, const void* x0, void* x_out, int kmax, double tol, void* ws,
-                         size_t ws_bytes, gsf_cg_info* info, void* stream) {
-  if (h == nullptr || x0 == nullptr || x_out == nullptr || kmax < 0 || !(tol >= 0.0) || !std::isfinite(tol))
-    return GSF_EINVAL;
-  const Operator& op = h->op;
+namespace {
+
+// The CG filter (Algorithm 2 in z-space) as a sequence of enqueued phases, so
+// that the single filter and the joint CG + LOBPCG driver share them.
+struct CgRun {
+  const Operator& op;
   CgWs w;
-  if (ws == nullptr || ws_bytes < carve_cg(op, nullptr, &w)) return GSF_ENOMEM;
-  carve_cg(op, (char*)ws, &w);
-  hipStream_t s = (hipStream_t)stream;
-  CgState init{};
-  init.tol = tol;
-  init.tau = breakdown_tau(op.desc.prec);
-  GSF_TRY(launch_cg_state_init(w.st, init, s));
-  GSF_TRY(launch_scale(op, x0, w.z, 0, s));
-  GSF_TRY(apply_any(op, GSF_FORM_LSYM, 1, w.z, 1, w.r, 1, nullptr, nullptr, s));
-  GSF_TRY(launch_cg_init(op, w.z, w.r, w.partials, w.st, s));
-  Poller poll(s, &w.st->active, info != nullptr && tol > 0.0);
-  for (int k = 1; k <= kmax; ++k) {
-    if (!poll.keep_going(k - 1)) break;
-    GSF_TRY(launch_cg_pupdate(op, w.r, w.p, w.st, s));
-    int nparts = 0;
-    if (op.desc.kind == GSF_BF) {
-      GSF_TRY(apply_any(op, GSF_FORM_LSYM, 1, w.p, 1, w.q, 1, w.partials, &nparts, s));
-    } else {
-      GSF_TRY(apply_any(op, GSF_FORM_LSYM, 1, w.p, 1, w.q, 1, nullptr, nullptr, s));
-      GSF_TRY(launch_dot(op, w.p, w.q, w.partials, &nparts, w.st, s));
-    }
-    GSF_TRY(launch_cg_alpha(w.partials, nparts, w.st, s));
-    GSF_TRY(launch_cg_update(op, w.z, w.r, w.p, w.q, w.partials, w.st, s));
+  hipStream_t s;
+  int nparts = 0;
+  CgRun(const Operator& o, char* ws, hipStream_t st) : op(o), s(st) { carve_cg(op, ws, &w); }
+  gsf_status begin(const void* x0, double tol) {
+    CgState init{};
+    init.tol = tol;
+    init.tau = breakdown_tau(op.desc.prec);
+    GSF_TRY(launch_cg_state_init(w.st, init, s));
+    GSF_TRY(launch_scale(op, x0, w.z, 0, s));
+    GSF_TRY(apply_any(op, GSF_FORM_LSYM, 1, w.z, 1, w.r, 1, nullptr, nullptr, s));
+    return launch_cg_init(op, w.z, w.r, w.partials, w.st, s);
   }
-  GSF_TRY(launch_scale(op, w.z, x_out, 1, s));
-  if (info == nullptr) return GSF_OK;
-  CgState host{};
-  GSF_TRY(hip_ok(hipMemcpyAsync(&host, w.st, sizeof(host), hipMemcpyDeviceToHost, s)));
-  GSF_TRY(hip_ok(hipStreamSynchronize(s)));
-  gsf_status status = (gsf_status)host.status;
-  if (status == GSF_OK && tol > 0.0 && host.active && !(host.rho <= host.tol2)) status = GSF_ENOTCONV;
-  info->iters = host.iters;
-  info->status = status;
-  info->res0 = host.res0;
-  info->res = std::sqrt(host.rho > 0.0 ? host.rho : 0.0);
-  return status;
-}
+  gsf_status pre() { return launch_cg_pupdate(op, w.r, w.p, w.st, s); }
+  gsf_status apply() {  // q = L_sym p and the p^T q partials
+    if (op.desc.kind == GSF_BF) return apply_any(op, GSF_FORM_LSYM, 1, w.p, 1, w.q, 1, w.partials, &nparts, s);
+    GSF_TRY(apply_any(op, GSF_FORM_LSYM, 1, w.p, 1, w.q, 1, nullptr, nullptr, s));
+    return launch_dot(op, w.p, w.q, w.partials, &nparts, w.st, s);
+  }
+  gsf_status post() {
+    GSF_TRY(launch_cg_alpha(w.partials, nparts, w.st, s));
+    return launch_cg_update(op, w.z, w.r, w.p, w.q, w.partials, w.st, s);
+  }
+  gsf_status finish(void* x_out, double tol, gsf_cg_info* info) {
+    GSF_TRY(launch_scale(op, w.z, x_out, 1, s));
+    if (info == nullptr) return GSF_OK;
+    CgState host{};
+    GSF_TRY(hip_ok(hipMemcpyAsync(&host, w.st, sizeof(host), hipMemcpyDeviceToHost, s)));
+    GSF_TRY(hip_ok(hipStreamSynchronize(s)));
+    gsf_status status = (gsf_status)host.status;
+    if (status == GSF_OK && tol > 0.0 && host.active && !(host.rho <= host.tol2)) status = GSF_ENOTCONV;
+    info->iters = host.iters;
+    info->status = status;
+    info->res0 = host.res0;
+    info->res = std::sqrt(host.rho > 0.0 ? host.rho : 0.0);
+    return status;
+  }
+};
 
-gsf_status gsf_lobpcg_filter(const gsf_operator* h, const void* x0, void* x_out, int m, int kmax, double tol,
-                             int constraint, const gsf_precond* T, void* ritz_vecs, void* ws, size_t ws_bytes,
-                             gsf_lobpcg_info* info, void* stream) {
-  if (h == nullptr || x0 == nullptr || x_out == nullptr || kmax < 0 || !(tol >= 0.0) || !std::isfinite(tol))
-    return GSF_EINVAL;
-  if (m < 1 || m > kMaxBlock) return GSF_EINVAL;
-  const Operator& op = h->op;
-  if (T != nullptr && (T->n != op.n || T->rows != op.rows || T->cols != op.cols || T->prec != op.desc.prec))
-    return GSF_EINVAL;
+// The LOBPCG filter (Algorithm 3, block form) as enqueued phases.
+struct LobRun {
+  const Operator& op;
   LobWs w;
-  if (ws == nullptr || ws_bytes < carve_lob(op, m, nullptr, &w)) return GSF_ENOMEM;
-  carve_lob(op, m, (char*)ws, &w);
-  hipStream_t s = (hipStream_t)stream;
-
-  LobpcgState init{};
-  init.tol = tol;
-  init.drop_tol = drop_tol_of(op.desc.prec);
-  init.zero_tol = breakdown_tau(op.desc.prec);
-  init.m = m;
-  init.active = 1;
-  init.status = GSF_OK;
-  GSF_TRY(launch_lob_state_init(w.st, init, s));
-
+  hipStream_t s;
+  int m;
+  bool constraint;
+  const gsf_precond* T;
   LobArgs a{};
-  a.prec = op.desc.prec;
-  a.n = op.n;
-  a.rows = op.rows;
-  a.cols = op.cols;
-  a.ndim = op.desc.ndim;
-  a.m = m;
-  a.constraint = constraint ? 1 : 0;
-  a.x0 = x0;
-  a.sqd = op.sqd;
-  a.X = w.X;
-  a.W = w.W;
-  a.P = w.P;
-  a.AX = w.AX;
-  a.AW = w.AW;
-  a.AP = w.AP;
-  a.C = w.C;
-  a.vpart = w.vpart;
-  a.st = w.st;
-  a.xout = x_out;
-  a.ritz = ritz_vecs;
-  const int nb = vec_blocks(op.n);
-  const StartDegrees deg = start_degrees(op.desc.ndim, m);
-
   GramArgs g{};
-  g.m = m;
-  g.n = op.n;
-  g.nparts = gram_blocks(op.n);
-  g.partials = w.gram_partials;
-  g.level2 = w.gram_level2;
-  g.counter = w.gram_counter;
-  g.active = &w.st->active;
   RRArgs rr{};
-  rr.C = w.C;
-  rr.theta = w.theta;
-  rr.st = w.st;
-  rr.drop_tol = init.drop_tol;
-  rr.conv2 = op.desc.prec == GSF_F32 ? 1e-20 : 1e-28;
-  rr.zero_tol = init.zero_tol;
-
-  if (constraint) GSF_TRY(lob_launch_ynorm(a, nb, s));
-  GSF_TRY(lob_launch_mkernel(0, a, nb, m, 1, deg, s));  // X0
-  if (constraint) GSF_TRY(lob_launch_project(a, w.X, nb, s));
-  GSF_TRY(apply_any(op, GSF_FORM_LSYM, m, w.X, m, w.AX, m, nullptr, nullptr, s));
-  // start-block Rayleigh-Ritz
-  g.ns = m;
-  g.S[0] = w.X;
-  g.AS[0] = w.AX;
-  rr.init = 1;
-  GSF_TRY(lob_launch_gram(g, rr, op.desc.prec, s));
-  rr.init = 0;
-  GSF_TRY(lob_launch_mkernel(1, a, nb, m, 1, deg, s));  // X = X0 C, AX, W = R
-  // Without a preconditioner network or the constraint nothing between an
-  // update and the next Rayleigh-Ritz step reads the residual norms, so that
-  // step finalizes them (one launch less per iteration); the last update is
-  // finalized after the loop.
-  const bool fold = T == nullptr && !constraint;
-  bool pending = false;
-  Poller poll(s, &w.st->active, info != nullptr && tol > 0.0);
-  for (int k = 0; k < kmax; ++k) {
-    if (!poll.keep_going(k)) break;
+  int nb = 0;
+  StartDegrees deg{};
+  bool fold = false, pending = false;
+  LobRun(const Operator& o, int m_, bool con, const gsf_precond* T_, char* ws, hipStream_t st)
+      : op(o), s(st), m(m_), constraint(con), T(T_) {
+    carve_lob(op, m, ws, &w);
+  }
+  gsf_status begin(const void* x0, void* x_out, void* ritz_vecs, double tol) {
+    LobpcgState init{};
+    init.tol = tol;
+    init.drop_tol = drop_tol_of(op.desc.prec);
+    init.zero_tol = breakdown_tau(op.desc.prec);
+    init.m = m;
+    init.active = 1;
+    init.status = GSF_OK;
+    GSF_TRY(launch_lob_state_init(w.st, init, s));
+    a.prec = op.desc.prec;
+    a.n = op.n;
+    a.rows = op.rows;
+    a.cols = op.cols;
+    a.ndim = op.desc.ndim;
+    a.m = m;
+    a.constraint = constraint ? 1 : 0;
+    a.x0 = x0;
+    a.sqd = op.sqd;
+    a.X = w.X;
+    a.W = w.W;
+    a.P = w.P;
+    a.AX = w.AX;
+    a.AW = w.AW;
+    a.AP = w.AP;
+    a.C = w.C;
+    a.vpart = w.vpart;
+    a.st = w.st;
+    a.xout = x_out;
+    a.ritz = ritz_vecs;
+    nb = vec_blocks(op.n);
+    deg = start_degrees(op.desc.ndim, m);
+    g.m = m;
+    g.n = op.n;
+    g.nparts = gram_blocks(op.n);
+    g.partials = w.gram_partials;
+    g.level2 = w.gram_level2;
+    g.counter = w.gram_counter;
+    g.active = &w.st->active;
+    rr.C = w.C;
+    rr.theta = w.theta;
+    rr.st = w.st;
+    rr.drop_tol = init.drop_tol;
+    rr.conv2 = op.desc.prec == GSF_F32 ? 1e-20 : 1e-28;
+    rr.zero_tol = init.zero_tol;
+    if (constraint) GSF_TRY(lob_launch_ynorm(a, nb, s));
+    GSF_TRY(lob_launch_mkernel(0, a, nb, m, 1, deg, s));  // X0
+    if (constraint) GSF_TRY(lob_launch_project(a, w.X, nb, s));
+    GSF_TRY(apply_any(op, GSF_FORM_LSYM, m, w.X, m, w.AX, m, nullptr, nullptr, s));
+    // start-block Rayleigh-Ritz
+    g.ns = m;
+    g.S[0] = w.X;
+    g.AS[0] = w.AX;
+    rr.init = 1;
+    GSF_TRY(lob_launch_gram(g, rr, op.desc.prec, s));
+    rr.init = 0;
+    GSF_TRY(lob_launch_mkernel(1, a, nb, m, 1, deg, s));  // X = X0 C, AX, W = R
+    // Without a preconditioner network or the constraint nothing between an
+    // update and the next Rayleigh-Ritz step reads the residual norms, so that
+    // step finalizes them (one launch less per iteration); the last update is
+    // finalized at the end.
+    fold = T == nullptr && !constraint;
+    return GSF_OK;
+  }
+  gsf_status pre() {  // W = T(R), or the projected R
     if (T != nullptr) {
       GSF_TRY(net_infer(op.desc.prec, T->w, op.rows, op.cols, m, w.W, w.Z, T->g, constraint ? op.sqd : nullptr,
                         w.st->res, w.st, w.net_partials, s));
-      GSF_TRY(net_lob_select(op.desc.prec, op.rows, op.cols, m, constraint ? 1 : 0, w.W, w.Z, op.sqd,
-                             w.net_partials, w.st, s));
-    } else if (constraint) {
-      GSF_TRY(lob_launch_project(a, w.W, nb, s));
+      return net_lob_select(op.desc.prec, op.rows, op.cols, m, constraint ? 1 : 0, w.W, w.Z, op.sqd,
+                            w.net_partials, w.st, s);
     }
-    GSF_TRY(apply_any(op, GSF_FORM_LSYM, m, w.W, m, w.AW, m, nullptr, nullptr, s));
+    if (constraint) return lob_launch_project(a, w.W, nb, s);
+    return GSF_OK;
+  }
+  gsf_status apply() { return apply_any(op, GSF_FORM_LSYM, m, w.W, m, w.AW, m, nullptr, nullptr, s); }
+  gsf_status post(int k) {  // Rayleigh-Ritz on [X, W, P] and the update
     const int ns = (k == 0) ? 2 * m : 3 * m;
     g.ns = ns;
     g.S[0] = w.X;
@@ -783,29 +809,183 @@ gsf_status gsf_lobpcg_filter(const gsf_operator* h, const void* x0, void* x_out,
     GSF_TRY(lob_launch_gram(g, rr, op.desc.prec, s));
     GSF_TRY(lob_launch_mkernel(fold ? 4 : 1, a, nb, ns, 0, deg, s));
     pending = fold;
+    return GSF_OK;
   }
-  if (pending) GSF_TRY(lob_launch_mkernel(5, a, nb, m, 0, deg, s));
-  GSF_TRY(lob_launch_mkernel(2, a, nb, m, 0, deg, s));  // X^T z0, Y^T z0
-  GSF_TRY(lob_launch_mkernel(3, a, nb, m, 0, deg, s));  // x_out
-  if (info == nullptr) return GSF_OK;
-  LobpcgState host{};
-  GSF_TRY(hip_ok(hipMemcpyAsync(&host, w.st, sizeof(host), hipMemcpyDeviceToHost, s)));
-  GSF_TRY(hip_ok(hipStreamSynchronize(s)));
-  gsf_status status = (gsf_status)host.status;
-  double mx = 0.0;
-  for (int j = 0; j < m; ++j) mx = host.res[j] > mx ? host.res[j] : mx;
-  if (status == GSF_OK && tol > 0.0 && mx > tol) status = GSF_ENOTCONV;
-  info->iters = host.iters;
-  info->status = status;
-  info->dropped = host.dropped;
-  info->m = m;
-  info->fallbacks = host.fallbacks;
-  info->pad = 0;
-  for (int j = 0; j < 8; ++j) {
-    info->res[j] = j < m ? host.res[j] : 0.0;
-    info->theta[j] = j < m ? host.theta[j] : 0.0;
+  gsf_status finish(double tol, gsf_lobpcg_info* info) {
+    if (pending) GSF_TRY(lob_launch_mkernel(5, a, nb, m, 0, deg, s));
+    pending = false;
+    GSF_TRY(lob_launch_mkernel(2, a, nb, m, 0, deg, s));  // X^T z0, Y^T z0
+    GSF_TRY(lob_launch_mkernel(3, a, nb, m, 0, deg, s));  // x_out
+    if (info == nullptr) return GSF_OK;
+    LobpcgState host{};
+    GSF_TRY(hip_ok(hipMemcpyAsync(&host, w.st, sizeof(host), hipMemcpyDeviceToHost, s)));
+    GSF_TRY(hip_ok(hipStreamSynchronize(s)));
+    gsf_status status = (gsf_status)host.status;
+    double mx = 0.0;
+    for (int j = 0; j < m; ++j) mx = host.res[j] > mx ? host.res[j] : mx;
+    if (status == GSF_OK && tol > 0.0 && mx > tol) status = GSF_ENOTCONV;
+    info->iters = host.iters;
+    info->status = status;
+    info->dropped = host.dropped;
+    info->m = m;
+    info->fallbacks = host.fallbacks;
+    info->pad = 0;
+    for (int j = 0; j < 8; ++j) {
+      info->res[j] = j < m ? host.res[j] : 0.0;
+      info->theta[j] = j < m ? host.theta[j] : 0.0;
+    }
+    return status;
   }
-  return status;
+};
+
+}  // namespace
+
+gsf_status gsf_cg_filter(const gsf_operator* h, const void* x0, void* x_out, int kmax, double tol, void* ws,
+                         size_t ws_bytes, gsf_cg_info* info, void* stream) {
+  if (h == nullptr || x0 == nullptr || x_out == nullptr || kmax < 0 || !(tol >= 0.0) || !std::isfinite(tol))
+    return GSF_EINVAL;
+  const Operator& op = h->op;
+  CgWs w0;
+  if (ws == nullptr || ws_bytes < carve_cg(op, nullptr, &w0)) return GSF_ENOMEM;
+  CgRun cg(op, (char*)ws, (hipStream_t)stream);
+  GSF_TRY(cg.begin(x0, tol));
+  Poller poll(cg.s, &cg.w.st->active, info != nullptr && tol > 0.0);
+  for (int k = 1; k <= kmax; ++k) {
+    if (!poll.keep_going(k - 1)) break;
+    GSF_TRY(cg.pre());
+    GSF_TRY(cg.apply());
+    GSF_TRY(cg.post());
+  }
+  return cg.finish(x_out, tol, info);
+}
+
+gsf_status gsf_lobpcg_filter(const gsf_operator* h, const void* x0, void* x_out, int m, int kmax, double tol,
+                             int constraint, const gsf_precond* T, void* ritz_vecs, void* ws, size_t ws_bytes,
+                             gsf_lobpcg_info* info, void* stream) {
+  if (h == nullptr || x0 == nullptr || x_out == nullptr || kmax < 0 || !(tol >= 0.0) || !std::isfinite(tol))
+    return GSF_EINVAL;
+  if (m < 1 || m > kMaxBlock) return GSF_EINVAL;
+  const Operator& op = h->op;
+  if (T != nullptr && (T->n != op.n || T->rows != op.rows || T->cols != op.cols || T->prec != op.desc.prec))
+    return GSF_EINVAL;
+  LobWs w0;
+  if (ws == nullptr || ws_bytes < carve_lob(op, m, nullptr, &w0)) return GSF_ENOMEM;
+  LobRun lob(op, m, constraint != 0, T, (char*)ws, (hipStream_t)stream);
+  GSF_TRY(lob.begin(x0, x_out, ritz_vecs, tol));
+  Poller poll(lob.s, &lob.w.st->active, info != nullptr && tol > 0.0);
+  for (int k = 0; k < kmax; ++k) {
+    if (!poll.keep_going(k)) break;
+    GSF_TRY(lob.pre());
+    GSF_TRY(lob.apply());
+    GSF_TRY(lob.post(k));
+  }
+  return lob.finish(tol, info);
+}
+
+// The device's second stream (one per device, created on first use and kept
+// until the process ends) and the handle's fork / join events.
+static gsf_status ensure_aux(gsf_operator* h) {
+  if (h->ev_fork != nullptr) return GSF_OK;
+  static std::mutex mu;
+  static hipStream_t dev_aux[64] = {};
+  int dev = 0;
+  GSF_TRY(hip_ok(hipGetDevice(&dev)));
+  if (dev < 0 || dev >= 64) return GSF_EDEVICE;
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    if (dev_aux[dev] == nullptr) GSF_TRY(hip_ok(hipStreamCreateWithFlags(&dev_aux[dev], hipStreamNonBlocking)));
+  }
+  hipEvent_t e[3] = {nullptr, nullptr, nullptr};
+  for (int i = 0; i < 3; ++i) {
+    if (hipEventCreateWithFlags(&e[i], hipEventDisableTiming) != hipSuccess) {
+      for (int j = 0; j < i; ++j) hipEventDestroy(e[j]);
+      return GSF_EDEVICE;
+    }
+  }
+  h->aux = dev_aux[dev];
+  h->ev_fork = e[0];
+  h->ev_cg = e[1];
+  h->ev_apply = e[2];
+  return GSF_OK;
+}
+
+// Joint CG + LOBPCG filters of one operator: step k of both runs shares one
+// stencil pass, [A W | A p] from [W | p] (the CG vector as one more column of
+// the LOBPCG block), where the operator offers a joint apply; the CG scalars
+// and updates run on a second stream while the LOBPCG Rayleigh-Ritz step and
+// update run on the caller's.
+gsf_status gsf_joint_workspace_bytes(const gsf_operator* h, int m, size_t* bytes) {
+  if (h == nullptr || bytes == nullptr || m < 1 || m > kMaxBlock) return GSF_EINVAL;
+  CgWs cw;
+  LobWs lw;
+  *bytes = align_up(carve_cg(h->op, nullptr, &cw), kAlign) + carve_lob(h->op, m, nullptr, &lw);
+  return GSF_OK;
+}
+
+gsf_status gsf_joint_filter(gsf_operator* h, const void* x0_cg, void* x_cg, int kmax_cg, const void* x0_lob,
+                            void* x_lob, int m, int kmax_lob, int constraint, void* ws, size_t ws_bytes,
+                            gsf_cg_info* cg_info, gsf_lobpcg_info* lob_info, void* stream) {
+  if (h == nullptr || x0_cg == nullptr || x_cg == nullptr || x0_lob == nullptr || x_lob == nullptr)
+    return GSF_EINVAL;
+  if (kmax_cg < 0 || kmax_lob < 0 || m < 1 || m > kMaxBlock) return GSF_EINVAL;
+  size_t need = 0;
+  GSF_TRY(gsf_joint_workspace_bytes(h, m, &need));
+  if (ws == nullptr || ws_bytes < need) return GSF_ENOMEM;
+  const Operator& op = h->op;
+  hipStream_t s = (hipStream_t)stream;
+  // A GF apply uses the handle's scratch planes, so a GF operator keeps both
+  // chains on the caller's stream; BF applies share nothing but the operator.
+  const bool two = op.desc.kind == GSF_BF;
+  if (two) GSF_TRY(ensure_aux(h));
+  hipStream_t cs = two ? h->aux : s;
+  CgWs cw;
+  char* base = (char*)ws;
+  CgRun cg(op, base, cs);
+  LobRun lob(op, m, constraint != 0, nullptr, base + align_up(carve_cg(op, nullptr, &cw), kAlign), s);
+  if (two) {  // the CG chain forks from the caller's stream
+    GSF_TRY(hip_ok(hipEventRecord(h->ev_fork, s)));
+    GSF_TRY(hip_ok(hipStreamWaitEvent(cs, h->ev_fork, 0)));
+  }
+  GSF_TRY(cg.begin(x0_cg, 0.0));
+  GSF_TRY(lob.begin(x0_lob, x_lob, nullptr, 0.0));
+  const int kj = kmax_cg < kmax_lob ? kmax_cg : kmax_lob;
+  for (int k = 0; k < kmax_cg || k < kmax_lob; ++k) {
+    const bool both = k < kj;
+    if (k < kmax_cg) GSF_TRY(cg.pre());
+    if (k < kmax_lob) GSF_TRY(lob.pre());
+    bool joint = false;
+    if (both) {
+      // the joint apply on the caller's stream once p is ready
+      if (two) {
+        GSF_TRY(hip_ok(hipEventRecord(h->ev_cg, cs)));
+        GSF_TRY(hip_ok(hipStreamWaitEvent(s, h->ev_cg, 0)));
+      }
+      joint = launch_bf_apply_joint(op, GSF_FORM_LSYM, m, lob.w.W, m, lob.w.AW, m, cg.w.p, 1, cg.w.q, 1,
+                                    cg.w.partials, &cg.nparts, s);
+      if (joint) {
+        GSF_TRY(hip_ok(hipGetLastError()));
+        if (two) {
+          GSF_TRY(hip_ok(hipEventRecord(h->ev_apply, s)));
+          GSF_TRY(hip_ok(hipStreamWaitEvent(cs, h->ev_apply, 0)));
+        }
+      }
+    }
+    if (!joint) {
+      if (k < kmax_cg) GSF_TRY(cg.apply());
+      if (k < kmax_lob) GSF_TRY(lob.apply());
+    }
+    if (k < kmax_cg) GSF_TRY(cg.post());
+    if (k < kmax_lob) GSF_TRY(lob.post(k));
+  }
+  gsf_status st_cg = cg.finish(x_cg, 0.0, cg_info);
+  if (two) {  // join: the caller's stream waits for the CG chain
+    GSF_TRY(hip_ok(hipEventRecord(h->ev_cg, cs)));
+    GSF_TRY(hip_ok(hipStreamWaitEvent(s, h->ev_cg, 0)));
+  }
+  gsf_status st_lob = lob.finish(0.0, lob_info);
+  if (st_cg != GSF_OK && st_cg != GSF_EBREAKDOWN) return st_cg;
+  if (st_lob != GSF_OK) return st_lob;
+  return st_cg;
 }
 
 // ---- re-guided (non-linear) filters -----------------------------------------

@@ -77,6 +77,46 @@ gsf_status launch_bf_apply(const Operator& op, int form, int m, const void* x, i
   return launch_bf_apply_rpt(op, form, m, x, ldx, y, ldy, dot, nparts, 0, s);
 }
 
+// Joint apply: y = F x for m columns (x, y with leading dimensions ldx, ldy)
+// and y2 = F x2 for one more column (ldx2, ldy2) in one launch that reads the
+// operator once; the dot partials are those of x2 . y2.  Offered for BF
+// operators on the square window (or 1D) with m = 1 or 4; returns false
+// (nothing launched) otherwise.
+bool launch_bf_apply_joint(const Operator& op, int form, int m, const void* x, int64_t ldx, void* y, int64_t ldy,
+                           const void* x2, int64_t ldx2, void* y2, int64_t ldy2, double* dot, int* nparts,
+                           hipStream_t s) {
+  if (op.desc.kind != GSF_BF || bf_cross2d(op.desc) || (m != 1 && m != 4)) return false;
+  bfk::ApplyArgs a{};
+  a.planes = op.planes;
+  a.pstride = op.pstride;
+  a.ppad = op.ppad;
+  a.isqd = op.diag;
+  a.x = x;
+  a.y = y;
+  a.ldx = ldx;
+  a.ldy = ldy;
+  a.x2 = x2;
+  a.y2 = y2;
+  a.ldx2 = ldx2;
+  a.ldy2 = ldy2;
+  a.n = op.n;
+  a.rows = op.rows;
+  a.cols = op.cols;
+  a.form = form;
+  a.dot = dot;
+  const int rpt = bf_rpt(op, m);  // the tile tuned for the m-column block
+  int nb = 0;
+  if (op.desc.prec == GSF_F32) {
+    if (m == 1) bf_apply_joint_tm<float, 2>(a, op.desc.ndim, op.desc.radius, rpt, s, &nb);
+    else bf_apply_joint_tm<float, 5>(a, op.desc.ndim, op.desc.radius, rpt, s, &nb);
+  } else {
+    if (m == 1) bf_apply_joint_tm<double, 2>(a, op.desc.ndim, op.desc.radius, rpt, s, &nb);
+    else bf_apply_joint_tm<double, 5>(a, op.desc.ndim, op.desc.radius, rpt, s, &nb);
+  }
+  if (nparts) *nparts = nb;
+  return true;
+}
+
 // Upper bound of the workgroups (and so of the dot partials) of an apply.
 int bf_apply_blocks(const Operator& op, int m) {
   const int rpt = 1;  // fewest rows per thread = most workgroups

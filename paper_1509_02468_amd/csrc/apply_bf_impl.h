@@ -38,6 +38,12 @@ struct ApplyArgs {
   int64_t n, rows, cols;
   int form;
   int cross;  // 2D cross stencil (planes (0, 1..R) then (1..R, 0))
+  // joint apply (kernels with M2 = 1): the last column comes from x2 / goes
+  // to y2 (leading dimensions ldx2 / ldy2), the others from x / to y; the dot
+  // partials are then those of that column
+  const void* x2;
+  void* y2;
+  int64_t ldx2, ldy2;
   int tiles_x, ntiles;
   double* dot;  // nullable, per-workgroup partial sum x.y (m = 1)
 };
@@ -78,6 +84,27 @@ __device__ __forceinline__ void finish_point(int form, T is, const T* __restrict
   }
 }
 
+// Column c (a compile-time index after unrolling) of point p of the input and
+// output block: the first M - M2 columns in x / y, the last M2 in x2 / y2.
+template <typename T, int M, int M2>
+__device__ __forceinline__ T in_col(const ApplyArgs& a, int64_t p, int c) {
+  if (M2 > 0 && c >= M - M2) return ((const T*)a.x2)[p * a.ldx2 + (c - (M - M2))];
+  return ((const T*)a.x)[p * a.ldx + c];
+}
+template <typename T, int M, int M2>
+__device__ __forceinline__ void out_col(const ApplyArgs& a, int64_t p, int c, T v) {
+  if (M2 > 0 && c >= M - M2)
+    ((T*)a.y2)[p * a.ldy2 + (c - (M - M2))] = v;
+  else
+    ((T*)a.y)[p * a.ldy + c] = v;
+}
+// the column whose x . y partial the kernel reports (m = 1, or the joint column)
+template <int M, int M2>
+struct DotCol {
+  static constexpr bool on = M == 1 || M2 > 0;
+  static constexpr int c = M2 > 0 ? M - 1 : 0;
+};
+
 // How many offsets of one row of the window are scheduled together: all of
 // them for narrow blocks; for wide blocks fewer, so that the loaded weights
 // and neighbour values fit in registers at a useful occupancy.
@@ -86,7 +113,7 @@ struct DxUnroll {
   static constexpr int value = (M * (int)sizeof(T) >= 16) ? 4 : 17;
 };
 
-template <typename T, int M, int R, int RPT>
+template <typename T, int M, int R, int RPT, int M2 = 0>
 __global__ void __launch_bounds__(kThreads) bf_apply2d_kernel(ApplyArgs a) {
   constexpr int TX = 64;
   constexpr int TY = 4 * RPT;
@@ -115,7 +142,7 @@ __global__ void __launch_bounds__(kThreads) bf_apply2d_kernel(ApplyArgs a) {
     T s = T(1);
     if (zspace && in) s = isqd[p];
 #pragma unroll
-    for (int c = 0; c < M; ++c) us[e * M + c] = in ? x[p * a.ldx + c] * s : T(0);
+    for (int c = 0; c < M; ++c) us[e * M + c] = in ? in_col<T, M, M2>(a, p, c) * s : T(0);
   }
   __syncthreads();
 
@@ -177,11 +204,12 @@ __global__ void __launch_bounds__(kThreads) bf_apply2d_kernel(ApplyArgs a) {
     if (valid) {
       T xg[M], out[M];
 #pragma unroll
-      for (int c = 0; c < M; ++c) xg[c] = (a.form == GSF_FORM_LSYM || a.form == GSF_FORM_L) ? T(0) : x[p * a.ldx + c];
+      for (int c = 0; c < M; ++c) xg[c] = (a.form == GSF_FORM_LSYM || a.form == GSF_FORM_L) ? T(0) : in_col<T, M, M2>(a, p, c);
       finish_point<T, M>(a.form, isqd[p], xg, acc, out);
 #pragma unroll
-      for (int c = 0; c < M; ++c) y[p * a.ldy + c] = out[c];
-      if (M == 1 && a.dot != nullptr) dotv += (double)x[p * a.ldx] * (double)out[0];
+      for (int c = 0; c < M; ++c) out_col<T, M, M2>(a, p, c, out[c]);
+      if (DotCol<M, M2>::on && a.dot != nullptr)
+        dotv += (double)in_col<T, M, M2>(a, p, DotCol<M, M2>::c) * (double)out[DotCol<M, M2>::c];
     }
   }
   if (a.dot != nullptr) {
@@ -200,7 +228,7 @@ __global__ void __launch_bounds__(kThreads) bf_apply2d_kernel(ApplyArgs a) {
 // rows, so no weight load sits behind a branch.  A point's own position
 // (offset 0) gets a zero weight.  It pays where the one-row kernel is bound by
 // its arithmetic and LDS reads (wide blocks).
-template <typename T, int M, int R, int TY>
+template <typename T, int M, int R, int TY, int M2 = 0>
 __global__ void __launch_bounds__(32 * TY) bf_apply2d_pair_kernel(ApplyArgs a) {
   constexpr int TX = 64;
   constexpr int NT = 32 * TY;  // threads: 64 columns x TY/2 row pairs
@@ -228,7 +256,7 @@ __global__ void __launch_bounds__(32 * TY) bf_apply2d_pair_kernel(ApplyArgs a) {
     T s = T(1);
     if (zspace && in) s = isqd[p];
 #pragma unroll
-    for (int c = 0; c < M; ++c) us[e * M + c] = in ? x[p * a.ldx + c] * s : T(0);
+    for (int c = 0; c < M; ++c) us[e * M + c] = in ? in_col<T, M, M2>(a, p, c) * s : T(0);
   }
   __syncthreads();
 
@@ -357,11 +385,12 @@ __global__ void __launch_bounds__(32 * TY) bf_apply2d_pair_kernel(ApplyArgs a) {
     if (valid) {
       T xg[M], out[M];
 #pragma unroll
-      for (int c = 0; c < M; ++c) xg[c] = (a.form == GSF_FORM_LSYM || a.form == GSF_FORM_L) ? T(0) : x[p * a.ldx + c];
+      for (int c = 0; c < M; ++c) xg[c] = (a.form == GSF_FORM_LSYM || a.form == GSF_FORM_L) ? T(0) : in_col<T, M, M2>(a, p, c);
       finish_point<T, M>(a.form, isqd[p], xg, h == 0 ? acc0 : acc1, out);
 #pragma unroll
-      for (int c = 0; c < M; ++c) y[p * a.ldy + c] = out[c];
-      if (M == 1 && a.dot != nullptr) dotv += (double)x[p * a.ldx] * (double)out[0];
+      for (int c = 0; c < M; ++c) out_col<T, M, M2>(a, p, c, out[c]);
+      if (DotCol<M, M2>::on && a.dot != nullptr)
+        dotv += (double)in_col<T, M, M2>(a, p, DotCol<M, M2>::c) * (double)out[DotCol<M, M2>::c];
     }
   }
   if (a.dot != nullptr) {
@@ -465,7 +494,7 @@ __global__ void __launch_bounds__(kThreads) bf_cross2d_kernel(ApplyArgs a) {
   }
 }
 
-template <typename T, int M, int R, int RPT>
+template <typename T, int M, int R, int RPT, int M2 = 0>
 __global__ void __launch_bounds__(kThreads) bf_apply1d_kernel(ApplyArgs a) {
   constexpr int TN = kThreads * RPT;
   constexpr int LN = TN + 2 * R;
@@ -486,7 +515,7 @@ __global__ void __launch_bounds__(kThreads) bf_apply1d_kernel(ApplyArgs a) {
     T s = T(1);
     if (zspace && in) s = isqd[g];
 #pragma unroll
-    for (int c = 0; c < M; ++c) us[e * M + c] = in ? x[g * a.ldx + c] * s : T(0);
+    for (int c = 0; c < M; ++c) us[e * M + c] = in ? in_col<T, M, M2>(a, g, c) * s : T(0);
   }
   __syncthreads();
 
@@ -521,11 +550,12 @@ __global__ void __launch_bounds__(kThreads) bf_apply1d_kernel(ApplyArgs a) {
     if (valid) {
       T xg[M], out[M];
 #pragma unroll
-      for (int c = 0; c < M; ++c) xg[c] = (a.form == GSF_FORM_LSYM || a.form == GSF_FORM_L) ? T(0) : x[p * a.ldx + c];
+      for (int c = 0; c < M; ++c) xg[c] = (a.form == GSF_FORM_LSYM || a.form == GSF_FORM_L) ? T(0) : in_col<T, M, M2>(a, p, c);
       finish_point<T, M>(a.form, isqd[p], xg, acc, out);
 #pragma unroll
-      for (int c = 0; c < M; ++c) y[p * a.ldy + c] = out[c];
-      if (M == 1 && a.dot != nullptr) dotv += (double)x[p * a.ldx] * (double)out[0];
+      for (int c = 0; c < M; ++c) out_col<T, M, M2>(a, p, c, out[c]);
+      if (DotCol<M, M2>::on && a.dot != nullptr)
+        dotv += (double)in_col<T, M, M2>(a, p, DotCol<M, M2>::c) * (double)out[DotCol<M, M2>::c];
     }
   }
   if (a.dot != nullptr) {
@@ -535,24 +565,28 @@ __global__ void __launch_bounds__(kThreads) bf_apply1d_kernel(ApplyArgs a) {
   }
 }
 
-template <typename T, int M, int R, int RPT>
+template <typename T, int M, int R, int RPT, int M2 = 0>
 void launch_bf_tile(const ApplyArgs& a, int ndim, hipStream_t s, int* nblocks) {
-  if (ndim == 2 && a.cross) {
-    constexpr int TY = 4 * RPT;
-    ApplyArgs b = a;
-    b.tiles_x = (int)((a.cols + 63) / 64);
-    const int tiles_y = (int)((a.rows + TY - 1) / TY);
-    b.ntiles = b.tiles_x * tiles_y;
-    *nblocks = b.ntiles;
-    bf_cross2d_kernel<T, M, R, RPT><<<b.ntiles, kThreads, 0, s>>>(b);
-  } else if (ndim == 2 && RPT == 2) {  // two rows per thread computed together
+  if constexpr (M2 == 0) {  // joint applies are not offered for the cross stencil
+    if (ndim == 2 && a.cross) {
+      constexpr int TY = 4 * RPT;
+      ApplyArgs b = a;
+      b.tiles_x = (int)((a.cols + 63) / 64);
+      const int tiles_y = (int)((a.rows + TY - 1) / TY);
+      b.ntiles = b.tiles_x * tiles_y;
+      *nblocks = b.ntiles;
+      bf_cross2d_kernel<T, M, R, RPT><<<b.ntiles, kThreads, 0, s>>>(b);
+      return;
+    }
+  }
+  if (ndim == 2 && RPT == 2) {  // two rows per thread computed together
     constexpr int PTY = 8;
     ApplyArgs b = a;
     b.tiles_x = (int)((a.cols + 63) / 64);
     const int tiles_y = (int)((a.rows + PTY - 1) / PTY);
     b.ntiles = b.tiles_x * tiles_y;
     *nblocks = b.ntiles;
-    bf_apply2d_pair_kernel<T, M, R, PTY><<<b.ntiles, 32 * PTY, 0, s>>>(b);
+    bf_apply2d_pair_kernel<T, M, R, PTY, M2><<<b.ntiles, 32 * PTY, 0, s>>>(b);
   } else if (ndim == 2) {
     constexpr int TY = 4 * RPT;
     ApplyArgs b = a;
@@ -560,43 +594,43 @@ void launch_bf_tile(const ApplyArgs& a, int ndim, hipStream_t s, int* nblocks) {
     const int tiles_y = (int)((a.rows + TY - 1) / TY);
     b.ntiles = b.tiles_x * tiles_y;
     *nblocks = b.ntiles;
-    bf_apply2d_kernel<T, M, R, RPT><<<b.ntiles, kThreads, 0, s>>>(b);
+    bf_apply2d_kernel<T, M, R, RPT, M2><<<b.ntiles, kThreads, 0, s>>>(b);
   } else {
     constexpr int TN = kThreads * RPT;
     const int nb = (int)((a.n + TN - 1) / TN);
     *nblocks = nb;
-    bf_apply1d_kernel<T, M, R, RPT><<<nb, kThreads, 0, s>>>(a);
+    bf_apply1d_kernel<T, M, R, RPT, M2><<<nb, kThreads, 0, s>>>(a);
   }
 }
 
-template <typename T, int M, int R>
+template <typename T, int M, int R, int M2 = 0>
 void launch_bf_rpt(const ApplyArgs& a, int ndim, int rpt, hipStream_t s, int* nb) {
   constexpr int MB = M * (int)sizeof(T);
   // taller tiles do not fit in LDS for wide FP64 blocks
   if constexpr (MB <= 32) {
     if (rpt >= 4) {
-      launch_bf_tile<T, M, R, 4>(a, ndim, s, nb);
+      launch_bf_tile<T, M, R, 4, M2>(a, ndim, s, nb);
       return;
     }
     if (rpt >= 2) {
-      launch_bf_tile<T, M, R, 2>(a, ndim, s, nb);
+      launch_bf_tile<T, M, R, 2, M2>(a, ndim, s, nb);
       return;
     }
   }
-  launch_bf_tile<T, M, R, 1>(a, ndim, s, nb);
+  launch_bf_tile<T, M, R, 1, M2>(a, ndim, s, nb);
 }
 
-template <typename T, int M>
+template <typename T, int M, int M2 = 0>
 void launch_bf_r(const ApplyArgs& a, int ndim, int r, int rpt, hipStream_t s, int* nb) {
   switch (r) {
-    case 1: launch_bf_rpt<T, M, 1>(a, ndim, rpt, s, nb); break;
-    case 2: launch_bf_rpt<T, M, 2>(a, ndim, rpt, s, nb); break;
-    case 3: launch_bf_rpt<T, M, 3>(a, ndim, rpt, s, nb); break;
-    case 4: launch_bf_rpt<T, M, 4>(a, ndim, rpt, s, nb); break;
-    case 5: launch_bf_rpt<T, M, 5>(a, ndim, rpt, s, nb); break;
-    case 6: launch_bf_rpt<T, M, 6>(a, ndim, rpt, s, nb); break;
-    case 7: launch_bf_rpt<T, M, 7>(a, ndim, rpt, s, nb); break;
-    default: launch_bf_rpt<T, M, 8>(a, ndim, rpt, s, nb); break;
+    case 1: launch_bf_rpt<T, M, 1, M2>(a, ndim, rpt, s, nb); break;
+    case 2: launch_bf_rpt<T, M, 2, M2>(a, ndim, rpt, s, nb); break;
+    case 3: launch_bf_rpt<T, M, 3, M2>(a, ndim, rpt, s, nb); break;
+    case 4: launch_bf_rpt<T, M, 4, M2>(a, ndim, rpt, s, nb); break;
+    case 5: launch_bf_rpt<T, M, 5, M2>(a, ndim, rpt, s, nb); break;
+    case 6: launch_bf_rpt<T, M, 6, M2>(a, ndim, rpt, s, nb); break;
+    case 7: launch_bf_rpt<T, M, 7, M2>(a, ndim, rpt, s, nb); break;
+    default: launch_bf_rpt<T, M, 8, M2>(a, ndim, rpt, s, nb); break;
   }
 }
 
@@ -605,5 +639,8 @@ void launch_bf_r(const ApplyArgs& a, int ndim, int r, int rpt, hipStream_t s, in
 // one translation unit per (T, M) instantiates this
 template <typename T, int M>
 void bf_apply_tm(const bfk::ApplyArgs& a, int ndim, int r, int rpt, hipStream_t s, int* nb);
+// joint applies: M - 1 columns from x plus one from x2 (one translation unit per (T, M))
+template <typename T, int M>
+void bf_apply_joint_tm(const bfk::ApplyArgs& a, int ndim, int r, int rpt, hipStream_t s, int* nb);
 
 }  // namespace gsf

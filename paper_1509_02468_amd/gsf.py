@@ -101,6 +101,9 @@ def load_library(path: str = LIB_PATH):
         "gsf_power_filter_block": ([vp, i32, vp, vp, i32, vp, sz, vp], i32),
         "gsf_cg_filter_block": ([vp, i32, vp, vp, i32, dbl, vp, sz, P(CgInfo), vp], i32),
         "gsf_srgb_to_lab": ([i32, i64, vp, vp, vp], i32),
+        "gsf_joint_workspace_bytes": ([vp, i32, P(sz)], i32),
+        "gsf_apply_joint": ([vp, i32, i32, vp, vp, vp, vp, vp], i32),
+        "gsf_joint_filter": ([vp, vp, vp, i32, vp, vp, i32, i32, i32, vp, sz, P(CgInfo), P(LobpcgInfo), vp], i32),
         "gsf_reguided_workspace_bytes": ([P(OperatorDesc), i32, P(sz)], i32),
         "gsf_reguided_filter": ([P(OperatorDesc), i32, vp, vp, i32, dbl, vp, sz, P(CgInfo), vp], i32),
         "gsf_lobpcg_filter": ([vp, vp, vp, i32, i32, dbl, i32, vp, vp, vp, sz, P(LobpcgInfo), vp], i32),
@@ -358,6 +361,16 @@ class Operator:
         _check(_lib.gsf_apply(self.handle, form, m, _ptr(x), _ptr(y), _stream(stream)), "apply")
         return y
 
+    def apply_joint(self, x, x2, form=FORM_LSYM, out=None, out2=None, stream=None):
+        """(F x, F x2) for an n x m block x and a vector x2 in one pass (gsf_apply_joint)."""
+        torch = _torch()
+        m = 1 if x.dim() == 1 else x.shape[1]
+        y = out if out is not None else torch.empty_like(x)
+        y2 = out2 if out2 is not None else torch.empty_like(x2)
+        _check(_lib.gsf_apply_joint(self.handle, form, m, _ptr(x), _ptr(y), _ptr(x2), _ptr(y2), _stream(stream)),
+               "apply_joint")
+        return y, y2
+
     def tune_apply(self, m=1, reps=20, stream=None):
         """Pick the apply tile height for block width m (see gsf_tune_apply);
         returns (rows per thread, [us per launch for 1, 2, 4])."""
@@ -410,6 +423,28 @@ class Operator:
                                       infos if info else None, _stream(stream))
         _check(st, "cg_filter_block")
         return y, (list(infos) if info else None)
+
+    def joint_workspace(self, m):
+        torch = _torch()
+        nbytes = ctypes.c_size_t()
+        _check(_lib.gsf_joint_workspace_bytes(self.handle, m, ctypes.byref(nbytes)), "joint_workspace_bytes")
+        return torch.empty(max(int(nbytes.value), 1), dtype=torch.uint8, device="cuda")
+
+    def joint_filter(self, x0_cg, kmax_cg, x0_lob, m, kmax_lob, constraint=False, out_cg=None, out_lob=None,
+                     ws=None, info=True, stream=None):
+        """CG and LOBPCG filters side by side (gsf_joint_filter); returns
+        (x_cg, x_lob, CgInfo or None, LobpcgInfo or None)."""
+        torch = _torch()
+        ycg = out_cg if out_cg is not None else torch.empty_like(x0_cg)
+        ylob = out_lob if out_lob is not None else torch.empty_like(x0_lob)
+        ws = ws if ws is not None else self.joint_workspace(m)
+        ci, li = CgInfo(), LobpcgInfo()
+        st = _lib.gsf_joint_filter(self.handle, _ptr(x0_cg), _ptr(ycg), kmax_cg, _ptr(x0_lob), _ptr(ylob), m,
+                                   kmax_lob, int(bool(constraint)), _ptr(ws), ws.numel(),
+                                   ctypes.byref(ci) if info else None, ctypes.byref(li) if info else None,
+                                   _stream(stream))
+        _check(st, "joint_filter")
+        return ycg, ylob, (ci if info else None), (li if info else None)
 
     def cg_filter(self, x0, kmax, tol=0.0, out=None, ws=None, info=True, stream=None):
         torch = _torch()

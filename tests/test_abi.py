@@ -195,3 +195,9 @@ def test_block_and_colour_argument_checks(lib):
     d = _desc(channels=3)
     assert lib.gsf_reguided_workspace_bytes(ctypes.byref(d), 0, ctypes.byref(sz)) == 1
     assert lib.gsf_operator_workspace_bytes(ctypes.byref(d), ctypes.byref(sz)) == 0
+
+
+def test_joint_argument_checks(lib):
+    sz = ctypes.c_size_t()
+    assert lib.gsf_joint_workspace_bytes(None, 4, ctypes.byref(sz)) == 1
+    assert lib.gsf_joint_filter(None, None, None, 5, None, None, 4, 5, 0, None, 0, None, None, None) == 1
