@@ -128,7 +128,61 @@ def cpu_baseline(w, noisy, budget_s):
     return {"value": work / el / 1e6, "unit": "Mpixel-iters/s", "cores": 1, "kind": "oracle",
             "sample": f"{crop.shape[0]}x{crop.shape[1]} crop of the workload image, BF {2*w['radius']+1}x"
                       f"{2*w['radius']+1} operator (build {t_build:.1f} s excluded), repeated CG({k_cg}) + "
-                      f"LOBPCG(m={m}, {k_lob}) for {el:.1f} s, FP64, single thread"}
+                      f"LOBPCG(m={m}, {k_lob}) for {el:.1f} s, FP64, single thread",
+            "rows": rows_baseline()}
+
+
+def rows_baseline():
+    """The oracle timed on the workloads of the other measured rows (the
+    image experiment, the 1D study, colour, re-guided), single thread, FP64:
+    ms per run, on the whole workload or on the stated crop."""
+    import oracle
+    from synth import STUDY_1D, WORKLOADS, make_signal, study_signal
+    out = {}
+
+    def timed(fn):
+        t0 = time.perf_counter()
+        fn()
+        return round((time.perf_counter() - t0) * 1e3, 1)
+
+    w = WORKLOADS["image_1024_cross5"]
+    _, noisy = make_signal("image_1024_cross5")
+    x = noisy.astype(np.float32).astype(np.float64)
+    res = {"sample": "whole 1024x1024 image"}
+    box = {}
+    res["build_ms"] = timed(lambda: box.setdefault("op", oracle.build_operator(
+        "bf", x, w["radius"], w["sigma_d"], w["sigma_r"], stencil=w["stencil"], norm=w["norm"])))
+    op = box["op"]
+    res["cg_ms"] = timed(lambda: oracle.cg_filter(op, x.ravel(), w["cg_iters"], data_prec="f32"))
+    res["lobpcg_ms"] = timed(lambda: oracle.lobpcg_filter(op, x.ravel(), w["lobpcg_m"], w["lobpcg_iters"],
+                                                          data_prec="f32"))
+    out["image_experiment"] = res
+    bf, gf, k = STUDY_1D["bf"], STUDY_1D["gf"], STUDY_1D["krylov_steps"]
+    clean, noisy1 = study_signal(1000)
+    opc = oracle.build_operator("bf", clean, bf["radius"], bf["sigma_d"], bf["sigma_r"])
+    out["study_1d"] = {"sample": "N = 1000",
+                       "bf_self_guided_ms": timed(lambda: oracle.power_filter_reguided(
+                           "bf", noisy1, (1000,), bf["passes"], radius=bf["radius"], sigma_s=bf["sigma_d"],
+                           sigma_r=bf["sigma_r"])),
+                       "gf_self_guided_ms": timed(lambda: oracle.power_filter_reguided(
+                           "gf", noisy1, (1000,), gf["passes"], radius=gf["radius"], eps=gf["eps"])),
+                       "bf_cg_ms": timed(lambda: oracle.cg_filter(opc, noisy1, k))}
+    w = WORKLOADS["image_1024_rgb_bf11"]
+    _, rgb = make_signal("image_1024_rgb_bf11", shape=(128, 1024))
+    lab = oracle.srgb_to_lab(rgb)
+    box = {}
+    res = {"sample": "128x1024 crop"}
+    res["build_ms"] = timed(lambda: box.setdefault("op", oracle.build_operator(
+        "bf", lab, w["radius"], w["sigma_d"], w["sigma_r"], channels=3)))
+    res["cg_block_ms"] = timed(lambda: oracle.cg_filter_block(box["op"], rgb.reshape(-1, 3), w["cg_iters"]))
+    out["colour"] = res
+    w = WORKLOADS["image_1024_bf11"]
+    _, g = make_signal("image_1024_bf11", shape=(128, 1024))
+    out["reguided"] = {"sample": "128x1024 crop, 2 steps",
+                       "cg_ms_per_step": round(timed(lambda: oracle.cg_filter_reguided(
+                           "bf", g.ravel(), g.shape, 2, radius=w["radius"], sigma_s=w["sigma_d"],
+                           sigma_r=w["sigma_r"])) / 2, 1)}
+    return out
 
 
 def batch_bench(seed=4):
@@ -409,6 +463,16 @@ def colour_bench(reps=3):
     out["psnr_power"] = psnr(y)
     out["power_3x_single_ms"] = timed(lambda: [op.power_filter(cols[c], kp, out=ys[c], ws=wp1) for c in range(3)])
     out["iters"] = {"cg": k, "power": kp}
+    # the 3-column apply against the HBM roofline: 60 weight planes,
+    # 1/sqrt(d), 3 values in and 3 out per point
+    z = torch.empty_like(xd)
+    reps = 100
+    ms = timed(lambda: [op.apply(xd, gsf.FORM_LSYM, out=z) for _ in range(reps)]) / reps
+    K = (2 * w["radius"] + 1) ** 2
+    algo = 4 * ((K + 1) // 2 + 2 * 3) * xd.shape[0]
+    out["apply"] = {"kernel": "bf_apply m=3", "us_per_launch": round(ms * 1e3, 2),
+                    "algorithmic_bytes_per_launch": algo, "achieved_gbs": round(algo / (ms * 1e-3) / 1e9, 1),
+                    "frac": round(algo / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     return out
 
 
