@@ -466,8 +466,8 @@ def colour_bench(reps=3):
     # the 3-column apply against the HBM roofline: 60 weight planes,
     # 1/sqrt(d), 3 values in and 3 out per point
     z = torch.empty_like(xd)
-    reps = 100
-    ms = timed(lambda: [op.apply(xd, gsf.FORM_LSYM, out=z) for _ in range(reps)]) / reps
+    napp = 100
+    ms = timed(lambda: [op.apply(xd, gsf.FORM_LSYM, out=z) for _ in range(napp)]) / napp
     K = (2 * w["radius"] + 1) ** 2
     algo = 4 * ((K + 1) // 2 + 2 * 3) * xd.shape[0]
     out["apply"] = {"kernel": "bf_apply m=3", "us_per_launch": round(ms * 1e3, 2),
