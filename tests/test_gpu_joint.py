@@ -88,3 +88,26 @@ def test_joint_apply_rows_agree(gsf):
         ycg, ylob, _, _ = op.joint_filter(xd, 10, xd, 4, 10)
         assert rel(ycg.cpu().numpy(), rcg.cpu().numpy()) <= 1e-12
         assert rel(ylob.cpu().numpy(), rlob.cpu().numpy()) <= 1e-12
+
+
+def test_joint_fullsize_bench_configuration(gsf):
+    """The bench step's configuration (1024^2, BF 11x11, FP32, CG 50 and
+    LOBPCG m = 4 50 steps, the tile the tuner picks): the joint driver against
+    the two single filters, whose full-size parity with the oracle the
+    full-size tests establish."""
+    import torch
+    from synth import WORKLOADS, make_signal
+    w = WORKLOADS["image_1024_bf11"]
+    _, noisy = make_signal("image_1024_bf11")
+    x0 = torch.tensor(noisy.ravel().astype(np.float32), device="cuda")
+    op = gsf.Operator("bf", w["shape"], x0, w["radius"], w["sigma_d"], w["sigma_r"], 0.0, gsf.F32)
+    op.tune_apply(1, reps=5)
+    op.tune_apply(w["lobpcg_m"], reps=5)
+    ycg, ylob, ci, li = op.joint_filter(x0, w["cg_iters"], x0, w["lobpcg_m"], w["lobpcg_iters"])
+    rcg, rci = op.cg_filter(x0, w["cg_iters"])
+    rlob, rli = op.lobpcg_filter(x0, w["lobpcg_m"], w["lobpcg_iters"])
+    ecg, elob = rel(ycg.cpu().numpy(), rcg.cpu().numpy()), rel(ylob.cpu().numpy(), rlob.cpu().numpy())
+    print(f"joint 1024^2: cg {ecg:.2e}, lobpcg {elob:.2e}, theta {list(li.theta[:4])}")
+    assert ci.iters == rci.iters == w["cg_iters"] and li.iters == rli.iters == w["lobpcg_iters"]
+    assert ecg <= 1e-5 and elob <= 1e-5
+    np.testing.assert_allclose(np.array(li.theta[:4]), np.array(rli.theta[:4]), rtol=1e-6)
