@@ -75,8 +75,6 @@ constexpr size_t kAlign = 256;
 __global__ void lob_state_init_kernel(LobpcgState* dst, LobpcgState v) { *dst = v; }
 __global__ void cg_state_init_kernel(CgState* dst, CgState v) { *dst = v; }
 
-bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
-
 gsf_status validate_desc(const gsf_operator_desc* d) {
   if (d == nullptr) return GSF_EINVAL;
   if (d->kind != GSF_BF && d->kind != GSF_GF) return GSF_EINVAL;
@@ -366,9 +364,9 @@ class Poller {
     on_ = true;
   }
   ~Poller() {
-    if (pending_ >= 0) hipEventSynchronize(ev_[pending_]);
+    if (pending_ >= 0) (void)hipEventSynchronize(ev_[pending_]);
     for (int i = 0; i < 2; ++i)
-      if (ev_[i]) hipEventDestroy(ev_[i]);
+      if (ev_[i]) (void)hipEventDestroy(ev_[i]);
   }
   // false once the solver is known to have stopped (call before step k)
   bool keep_going(int k) {
@@ -898,7 +896,7 @@ static gsf_status ensure_aux(gsf_operator* h) {
   hipEvent_t e[3] = {nullptr, nullptr, nullptr};
   for (int i = 0; i < 3; ++i) {
     if (hipEventCreateWithFlags(&e[i], hipEventDisableTiming) != hipSuccess) {
-      for (int j = 0; j < i; ++j) hipEventDestroy(e[j]);
+      for (int j = 0; j < i; ++j) (void)hipEventDestroy(e[j]);
       return GSF_EDEVICE;
     }
   }
@@ -1177,7 +1175,7 @@ gsf_status gsf_tune_apply(const gsf_operator* h, int m, const void* x, void* y, 
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return GSF_EDEVICE;
   if (hipEventCreate(&e1) != hipSuccess) {
-    hipEventDestroy(e0);
+    (void)hipEventDestroy(e0);
     return GSF_EDEVICE;
   }
   const int cand[3] = {1, 2, 4};
@@ -1192,7 +1190,7 @@ gsf_status gsf_tune_apply(const gsf_operator* h, int m, const void* x, void* y, 
       st = launch_bf_apply_rpt(op, GSF_FORM_LSYM, m, x, m, y, m, nullptr, nullptr, cand[c], s);
     if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) { st = GSF_EDEVICE; break; }
     float ms = 0.f;
-    hipEventElapsedTime(&ms, e0, e1);
+    if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { st = GSF_EDEVICE; break; }
     const float us = ms * 1000.f / (float)reps;
     if (times_us) times_us[c] = us;
     if (us < best_t) {
@@ -1200,8 +1198,8 @@ gsf_status gsf_tune_apply(const gsf_operator* h, int m, const void* x, void* y, 
       best = cand[c];
     }
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   if (st != GSF_OK) return st;
   bf_set_rpt(op, w, best);
   if (best_rpt) *best_rpt = best;

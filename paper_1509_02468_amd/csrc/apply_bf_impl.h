@@ -124,9 +124,7 @@ __global__ void __launch_bounds__(kThreads) bf_apply2d_kernel(ApplyArgs a) {
 
   const T* __restrict__ planes = (const T*)a.planes;
   const T* __restrict__ isqd = (const T*)a.isqd;
-  const T* __restrict__ x = (const T*)a.x;
-  T* __restrict__ y = (T*)a.y;
-  const int64_t W = a.cols, H = a.rows, n = a.n;
+  const int64_t W = a.cols, H = a.rows;
 
   const int tile = xcd_tile(blockIdx.x, a.ntiles);
   const int64_t ty0 = (int64_t)(tile / a.tiles_x) * TY;
@@ -239,8 +237,6 @@ __global__ void __launch_bounds__(32 * TY) bf_apply2d_pair_kernel(ApplyArgs a) {
   __shared__ double red[16];
 
   const T* __restrict__ isqd = (const T*)a.isqd;
-  const T* __restrict__ x = (const T*)a.x;
-  T* __restrict__ y = (T*)a.y;
   const int64_t W = a.cols, H = a.rows;
 
   const int tile = xcd_tile(blockIdx.x, a.ntiles);
@@ -503,8 +499,6 @@ __global__ void __launch_bounds__(kThreads) bf_apply1d_kernel(ApplyArgs a) {
 
   const T* __restrict__ planes = (const T*)a.planes;
   const T* __restrict__ isqd = (const T*)a.isqd;
-  const T* __restrict__ x = (const T*)a.x;
-  T* __restrict__ y = (T*)a.y;
   const int64_t n = a.n;
   const int64_t base = (int64_t)blockIdx.x * TN;
   const bool zspace = (a.form == GSF_FORM_N || a.form == GSF_FORM_LSYM);

@@ -80,12 +80,12 @@ void free_batch(gsf_batch* b) {
   if (b == nullptr) return;
   for (gsf_operator* op : b->ops) gsf_destroy_operator(op);
   for (int k = 0; k < kBranches; ++k) {
-    if (b->exec[k]) hipGraphExecDestroy(b->exec[k]);
-    if (b->graph[k]) hipGraphDestroy(b->graph[k]);
-    if (b->join[k]) hipEventDestroy(b->join[k]);
-    if (b->stream[k]) hipStreamDestroy(b->stream[k]);
+    if (b->exec[k]) (void)hipGraphExecDestroy(b->exec[k]);
+    if (b->graph[k]) (void)hipGraphDestroy(b->graph[k]);
+    if (b->join[k]) (void)hipEventDestroy(b->join[k]);
+    if (b->stream[k]) (void)hipStreamDestroy(b->stream[k]);
   }
-  if (b->fork) hipEventDestroy(b->fork);
+  if (b->fork) (void)hipEventDestroy(b->fork);
   delete b;
 }
 
@@ -184,7 +184,7 @@ gsf_status gsf_batch_create(const gsf_batch_item* items, int count, void* ws, si
       gsf_destroy_operator(tmp);
     }
   }
-  if (s0) hipStreamDestroy(s0);
+  if (s0) (void)hipStreamDestroy(s0);
 
   // items over the branches, longest first onto the least loaded branch
   std::vector<int> order(count);

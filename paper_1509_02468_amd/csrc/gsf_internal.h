@@ -130,9 +130,9 @@ struct gsf_operator {
   hipStream_t aux = nullptr;
   hipEvent_t ev_fork = nullptr, ev_cg = nullptr, ev_apply = nullptr;
   ~gsf_operator() {
-    if (ev_fork) hipEventDestroy(ev_fork);
-    if (ev_cg) hipEventDestroy(ev_cg);
-    if (ev_apply) hipEventDestroy(ev_apply);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_cg) (void)hipEventDestroy(ev_cg);
+    if (ev_apply) (void)hipEventDestroy(ev_apply);
   }
 };
 

@@ -333,14 +333,10 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
-// Reciprocal and reciprocal square root: the hardware approximations refined
+// Reciprocal square root: the hardware approximation refined
 // by one Newton step (a few ulp), short dependency chains for the Jacobi
 // rotations.  The rotation stays orthogonal to rounding because c and s are
 // both derived from the same t: c = (1 + t^2)^-1/2, s = t c.
-__device__ __forceinline__ double rcp_nr(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  return fma(r, fma(-x, r, 1.0), r);
-}
 __device__ __forceinline__ double rsq_nr(double x) {
   double r = __builtin_amdgcn_rsq(x);
   const double e = fma(-x * r, r, 1.0);
@@ -844,7 +840,7 @@ __global__ void __launch_bounds__(kThreads) gram_rr_kernel(GramArgs g, RRArgs r)
       for (int j = 0; j < g.m; ++j) st->theta[j] = sh.ev[sh.order[j]];
     }
   }
-  if (r.kept_out != nullptr && threadIdx.x < g.ns) r.kept_out[threadIdx.x] = keptf[threadIdx.x];
+  if (r.kept_out != nullptr && (int)threadIdx.x < g.ns) r.kept_out[threadIdx.x] = keptf[threadIdx.x];
   if (r.nkept_out != nullptr && threadIdx.x == 0) *r.nkept_out = nkept;
 }
 
@@ -1144,7 +1140,7 @@ __global__ void __launch_bounds__(kThreads) rr_only_kernel(const double* __restr
   if (threadIdx.x >= 64) return;
   rayleigh_ritz(sh, ns, m, r.drop_tol, r.zero_tol, r.conv2, r.C, r.theta, keptf, &nkept);
   wave_fence();
-  if (threadIdx.x < ns) r.kept_out[threadIdx.x] = keptf[threadIdx.x];
+  if ((int)threadIdx.x < ns) r.kept_out[threadIdx.x] = keptf[threadIdx.x];
   if (threadIdx.x == 0) *r.nkept_out = nkept;
 }
 

@@ -21,7 +21,6 @@ namespace gsf {
 
 int vec_blocks(int64_t n);
 
-constexpr int kNetHidden = 16;
 constexpr int kOffW1 = 0, kOffW2 = 288, kOffW3 = 2592, kNetWeights = 2736;
 
 namespace {

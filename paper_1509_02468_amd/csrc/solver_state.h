@@ -34,7 +34,7 @@ struct BlockCgState {
 struct LobpcgState {
   double theta[8];
   double res[8];       // residual norms of the current X
-  double yx[8];        // Y^T W (constraint projection coefficients)
+  double yx[9];        // Y^T W (constraint projection coefficients); the output's X^T z0 and Y^T z0 (m + 1)
   double yz[8];        // Y^T T(R) (learned preconditioner)
   double ynorm_inv;    // 1 / ||sqrt(d)||
   double tol;

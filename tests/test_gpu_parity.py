@@ -233,6 +233,7 @@ def test_rayleigh_ritz_parity(gsf, ns, m, drop):
     (1, ("gf", (70, 131), 6), 4, 10, True),
     (0, ("bf", (67, 130), 3), 4, 20, True),
     (0, ("bf", (33, 200), 4), 8, 15, False),
+    (1, ("bf", (33, 200), 4), 8, 15, True),   # widest block with the constraint: m + 1 output coefficients
 ])
 def test_lobpcg_filter_parity(gsf, prec, case, m, k, constraint):
     import torch
