@@ -111,3 +111,26 @@ def test_joint_fullsize_bench_configuration(gsf):
     assert ci.iters == rci.iters == w["cg_iters"] and li.iters == rli.iters == w["lobpcg_iters"]
     assert ecg <= 1e-5 and elob <= 1e-5
     np.testing.assert_allclose(np.array(li.theta[:4]), np.array(rli.theta[:4]), rtol=1e-6)
+
+
+def test_joint_edge_cases(gsf):
+    """kmax = 0 on either side (the other filter runs alone; zero steps return
+    the input for CG and the start-block projection for LOBPCG, as the single
+    filters do); a constant CG input breaks down at once while LOBPCG runs on."""
+    import torch
+    shape = (40, 70)
+    x = scene_2d(*shape, 0.05, 12)[1]
+    xd = _dev(x.ravel(), gsf.F64, gsf)
+    op = gsf.Operator("bf", shape, xd, radius=2, sigma_d=2.0, sigma_r=0.1, prec=gsf.F64)
+    for kcg, klob in ((0, 8), (8, 0), (0, 0)):
+        ycg, ylob, ci, li = op.joint_filter(xd, kcg, xd, 4, klob)
+        rcg, _ = op.cg_filter(xd, kcg)
+        rlob, _ = op.lobpcg_filter(xd, 4, klob)
+        assert rel(ycg.cpu().numpy(), rcg.cpu().numpy()) <= 1e-13
+        assert rel(ylob.cpu().numpy(), rlob.cpu().numpy()) <= 1e-13
+        assert ci.iters == kcg and li.iters == klob
+    c = _dev(np.full(op.n, 0.3), gsf.F64, gsf)
+    ycg, ylob, ci, li = op.joint_filter(c, 10, xd, 4, 10)
+    assert ci.status == gsf.EBREAKDOWN and ci.iters == 0 and torch.equal(ycg, c)
+    rlob, _ = op.lobpcg_filter(xd, 4, 10)
+    assert li.iters == 10 and rel(ylob.cpu().numpy(), rlob.cpu().numpy()) <= 1e-13
