@@ -35,6 +35,11 @@ gsf_status launch_cg_pupdate(const Operator& op, const void* r, void* p, const C
 gsf_status launch_dot(const Operator& op, const void* a, const void* b, double* partials, int* nparts,
                       const CgState* st, hipStream_t s);
 gsf_status launch_cg_alpha(const double* partials, int nparts, CgState* st, hipStream_t s);
+gsf_status launch_cg_pbeta(const Operator& op, const void* r, void* p, const double* upd, CgState* st, int k,
+                           hipStream_t s);
+gsf_status launch_cg_aupdate(const Operator& op, void* z, void* r, const void* p, const void* q, const double* dots,
+                             int ndots, double* upd, CgState* st, int k, hipStream_t s);
+gsf_status launch_cg_close(const Operator& op, const double* upd, CgState* st, hipStream_t s);
 gsf_status launch_rg_init(const Operator& op, const void* x, void* r, double* partials, CgState* st, hipStream_t s);
 gsf_status launch_rg_s_beta(const Operator& op, const void* r, const void* r_old, void* sv, double* partials,
                             CgState* st, hipStream_t s);
@@ -196,7 +201,8 @@ double drop_tol_of(int prec) { return prec == GSF_F32 ? 1e-6 : 1e-10; }
 
 struct CgWs {
   void *z, *r, *p, *q;
-  double* partials;
+  double* partials;   // per-workgroup partials (the apply's p^T q, and the step kernels')
+  double* partials2;  // the fused update's r^T r partials
   CgState* st;
 };
 
@@ -213,6 +219,7 @@ size_t carve_cg(const Operator& op, char* base, CgWs* w) {
     nb = ab > nb ? ab : nb;
   }
   w->partials = (double*)c.take((size_t)nb * 2 * sizeof(double));
+  w->partials2 = (double*)c.take((size_t)vec_blocks(op.n) * 2 * sizeof(double));
   w->st = (CgState*)c.take(sizeof(CgState));
   return c.off;
 }
@@ -664,6 +671,7 @@ struct CgRun {
   CgWs w;
   hipStream_t s;
   int nparts = 0;
+  int steps = 0;  // steps issued
   CgRun(const Operator& o, char* ws, hipStream_t st) : op(o), s(st) { carve_cg(op, ws, &w); }
   gsf_status begin(const void* x0, double tol) {
     CgState init{};
@@ -674,17 +682,19 @@ struct CgRun {
     GSF_TRY(apply_any(op, GSF_FORM_LSYM, 1, w.z, 1, w.r, 1, nullptr, nullptr, s));
     return launch_cg_init(op, w.z, w.r, w.partials, w.st, s);
   }
-  gsf_status pre() { return launch_cg_pupdate(op, w.r, w.p, w.st, s); }
+  // step k (1-based): p from r (with beta from the last update's partials)
+  gsf_status pre(int k) { return launch_cg_pbeta(op, w.r, w.p, w.partials2, w.st, k, s); }
   gsf_status apply() {  // q = L_sym p and the p^T q partials
     if (op.desc.kind == GSF_BF) return apply_any(op, GSF_FORM_LSYM, 1, w.p, 1, w.q, 1, w.partials, &nparts, s);
     GSF_TRY(apply_any(op, GSF_FORM_LSYM, 1, w.p, 1, w.q, 1, nullptr, nullptr, s));
     return launch_dot(op, w.p, w.q, w.partials, &nparts, w.st, s);
   }
-  gsf_status post() {
-    GSF_TRY(launch_cg_alpha(w.partials, nparts, w.st, s));
-    return launch_cg_update(op, w.z, w.r, w.p, w.q, w.partials, w.st, s);
+  gsf_status post(int k) {  // alpha and the update of step k
+    steps = k;
+    return launch_cg_aupdate(op, w.z, w.r, w.p, w.q, w.partials, nparts, w.partials2, w.st, k, s);
   }
   gsf_status finish(void* x_out, double tol, gsf_cg_info* info) {
+    if (steps > 0) GSF_TRY(launch_cg_close(op, w.partials2, w.st, s));
     GSF_TRY(launch_scale(op, w.z, x_out, 1, s));
     if (info == nullptr) return GSF_OK;
     CgState host{};
@@ -850,9 +860,9 @@ gsf_status gsf_cg_filter(const gsf_operator* h, const void* x0, void* x_out, int
   Poller poll(cg.s, &cg.w.st->active, info != nullptr && tol > 0.0);
   for (int k = 1; k <= kmax; ++k) {
     if (!poll.keep_going(k - 1)) break;
-    GSF_TRY(cg.pre());
+    GSF_TRY(cg.pre(k));
     GSF_TRY(cg.apply());
-    GSF_TRY(cg.post());
+    GSF_TRY(cg.post(k));
   }
   return cg.finish(x_out, tol, info);
 }
@@ -949,7 +959,7 @@ gsf_status gsf_joint_filter(gsf_operator* h, const void* x0_cg, void* x_cg, int 
   const int kj = kmax_cg < kmax_lob ? kmax_cg : kmax_lob;
   for (int k = 0; k < kmax_cg || k < kmax_lob; ++k) {
     const bool both = k < kj;
-    if (k < kmax_cg) GSF_TRY(cg.pre());
+    if (k < kmax_cg) GSF_TRY(cg.pre(k + 1));
     if (k < kmax_lob) GSF_TRY(lob.pre());
     bool joint = false;
     if (both) {
@@ -972,7 +982,7 @@ gsf_status gsf_joint_filter(gsf_operator* h, const void* x0_cg, void* x_cg, int 
       if (k < kmax_cg) GSF_TRY(cg.apply());
       if (k < kmax_lob) GSF_TRY(lob.apply());
     }
-    if (k < kmax_cg) GSF_TRY(cg.post());
+    if (k < kmax_cg) GSF_TRY(cg.post(k + 1));
     if (k < kmax_lob) GSF_TRY(lob.post(k));
   }
   gsf_status st_cg = cg.finish(x_cg, 0.0, cg_info);

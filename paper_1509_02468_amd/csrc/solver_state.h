@@ -14,6 +14,7 @@ struct CgState {
   double tol2;   // tol^2 rho0, or -1
   double tau;    // breakdown tau of the data precision
   double alpha, beta, pq;
+  double rhob[2];  // r^T r by step parity (step k reads rhob[k & 1]; the fused CG kernels)
   int32_t active;
   int32_t status;
   int32_t iters;

@@ -117,7 +117,6 @@ def test_joint_edge_cases(gsf):
     """kmax = 0 on either side (the other filter runs alone; zero steps return
     the input for CG and the start-block projection for LOBPCG, as the single
     filters do); a constant CG input breaks down at once while LOBPCG runs on."""
-    import torch
     shape = (40, 70)
     x = scene_2d(*shape, 0.05, 12)[1]
     xd = _dev(x.ravel(), gsf.F64, gsf)
@@ -131,6 +130,7 @@ def test_joint_edge_cases(gsf):
         assert ci.iters == kcg and li.iters == klob
     c = _dev(np.full(op.n, 0.3), gsf.F64, gsf)
     ycg, ylob, ci, li = op.joint_filter(c, 10, xd, 4, 10)
-    assert ci.status == gsf.EBREAKDOWN and ci.iters == 0 and torch.equal(ycg, c)
+    assert ci.status == gsf.EBREAKDOWN and ci.iters == 0
+    np.testing.assert_allclose(ycg.cpu().numpy(), 0.3, rtol=1e-15)  # z = D^1/2 x and back
     rlob, _ = op.lobpcg_filter(xd, 4, 10)
     assert li.iters == 10 and rel(ylob.cpu().numpy(), rlob.cpu().numpy()) <= 1e-13
