@@ -29,7 +29,11 @@ int width_of(int left) { return left >= 8 ? 8 : (left >= 4 ? 4 : left); }
 
 int bf_rpt(const Operator& op, int w) {
   const int t = g_rpt[op.desc.prec][geometry(op)][op.desc.radius][w][size_class(op.n)];
-  return t > 0 ? t : bfk::default_rpt((int)op.elem, w, op.desc.radius);
+  if (t > 0) return t;
+  // cross stencil (measured at 1024^2, r = 1, FP32, us for 1 / 2 / 4 rows:
+  // m = 1 7.6 / 8.2 / 8.3, m = 4 10.0 / 8.7 / 10.0)
+  if (bf_cross2d(op.desc)) return (int)op.elem * w <= 4 ? 1 : 2;
+  return bfk::default_rpt((int)op.elem, w, op.desc.radius);
 }
 
 void bf_set_rpt(const Operator& op, int w, int rpt) {
