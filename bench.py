@@ -125,7 +125,15 @@ def cpu_baseline(w, noisy, budget_s):
         if time.perf_counter() - t0 > budget_s:
             break
     el = time.perf_counter() - t0
-    return {"value": work / el / 1e6, "unit": "Mpixel-iters/s", "cores": 1, "kind": "oracle",
+    cpu_model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu_model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"value": work / el / 1e6, "unit": "Mpixel-iters/s", "cores": 1, "kind": "oracle", "cpu_model": cpu_model,
             "sample": f"{crop.shape[0]}x{crop.shape[1]} crop of the workload image, BF {2*w['radius']+1}x"
                       f"{2*w['radius']+1} operator (build {t_build:.1f} s excluded), repeated CG({k_cg}) + "
                       f"LOBPCG(m={m}, {k_lob}) for {el:.1f} s, FP64, single thread",
@@ -710,6 +718,19 @@ def main():
         dom_rows = tuned[dom]["rows_per_thread"]
     algo, t_ms = rl[dom]
     achieved = algo / (t_ms * 1e-3) / 1e9
+    # what a plain device copy reaches (read + write of 1 GiB), the practical ceiling
+    src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record()
+    for _ in range(10):
+        dst.copy_(src)
+    c1.record()
+    c1.synchronize()
+    copy_gbs = 2 * src.numel() * 4 / (c0.elapsed_time(c1) / 10 * 1e-3) / 1e9
+    del src, dst
     # HBM bytes per launch from the committed counter passes, for the tile the
     # tuner chose (null when no entry covers that kernel)
     traffic = None
@@ -721,6 +742,7 @@ def main():
             traffic = None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "copy_gbs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4),
                 "kernel": f"bf_apply {dom} rows_per_thread={dom_rows}", "us_per_launch": round(t_ms * 1e3, 2),
                 "algorithmic_bytes_per_launch": algo,
                 **{f"{k}_us": round(v[1] * 1e3, 2) for k, v in rl.items()}}
