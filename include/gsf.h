@@ -410,6 +410,9 @@ gsf_status gsf_lobpcg_residual(const gsf_operator* op, int m, const void* X, con
  * gsf_reguided_workspace_bytes(desc, method) bytes, 256-byte aligned; it holds
  * the rebuilt operator and the solver vectors.  Each step costs one operator
  * build; with FP32 data the graph is built from the stored FP32 iterate.
+ * A 1D BF power filter whose signal fits in one workgroup's LDS (n <= 16384
+ * FP32, 8192 FP64) runs all passes in one launch, weights and sums in FP64,
+ * the iterate stored in the data type after every pass.
  * GSF_EINVAL for a bad descriptor, a descriptor with more than one guidance
  * channel (the iterate is the guidance), method, kmax < 0 or tol; GSF_ENOMEM
  * for a short workspace.  info may be NULL (then no host sync). */

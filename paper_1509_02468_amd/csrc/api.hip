@@ -28,6 +28,7 @@ gsf_status launch_srgb_to_lab(int prec, int64_t n, const void* rgb, void* lab, h
 bool launch_bf_apply_joint(const Operator& op, int form, int m, const void* x, int64_t ldx, void* y, int64_t ldy,
                            const void* x2, int64_t ldx2, void* y2, int64_t ldy2, double* dot, int* nparts,
                            hipStream_t s);
+bool launch_rg_power_small(const gsf_operator_desc& d, const void* x0, void* x_out, int kmax, hipStream_t s);
 gsf_status launch_scale(const Operator& op, const void* in, void* out, int divide, hipStream_t s);
 gsf_status launch_cg_init(const Operator& op, const void* z, void* r, double* partials, CgState* st,
                           hipStream_t s);
@@ -1018,6 +1019,17 @@ gsf_status gsf_reguided_filter(const gsf_operator_desc* desc, int method, const 
   const Operator& op = w.op;
   hipStream_t s = (hipStream_t)stream;
   const size_t v = (size_t)op.n * op.elem;
+  if (method == GSF_METHOD_POWER && launch_rg_power_small(*desc, x0, x_out, kmax, s)) {
+    // a 1D BF signal that fits in one workgroup's LDS: all passes in one launch
+    GSF_TRY(hip_ok(hipGetLastError()));
+    if (info != nullptr) {
+      info->iters = kmax;
+      info->status = GSF_OK;
+      info->res0 = 0.0;
+      info->res = 0.0;
+    }
+    return GSF_OK;
+  }
   if (x_out != x0) GSF_TRY(hip_ok(hipMemcpyAsync(x_out, x0, v, hipMemcpyDeviceToDevice, s)));
   if (method == GSF_METHOD_POWER) {
     // x <- D(x)^-1 W(x) x, the graph built from the current iterate each pass

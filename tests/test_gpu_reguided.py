@@ -195,3 +195,25 @@ def test_reguided_fullsize_properties(gsf):
         m1 = float(d @ y.double().cpu().numpy())
         print(f"1024^2 GF re-guided method {method}: 1^T D x {m0:.6e} -> {m1:.6e}")
         assert abs(m1 - m0) <= 1e-5 * abs(m0)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("n", [700, 20000])
+def test_reguided_power_1d_both_paths(gsf, n, prec):
+    """1D BF re-guided power filter: a signal that fits in one workgroup's LDS
+    runs in one launch (n = 700), a longer one on the multi-kernel path
+    (n = 20000 > 16384 FP32 / 8192 FP64 samples); both against the oracle,
+    with the (diag L) normalization too."""
+    x0 = piecewise_constant_1d(n, 0.1, 30 + n)[1]
+    if prec == gsf.F32:
+        x0 = x0.astype(np.float32).astype(np.float64)
+    dp = "f32" if prec == gsf.F32 else "f64"
+    for norm in ("d", "diagl"):
+        par = dict(radius=3, sigma_d=2.0, sigma_r=0.15)
+        y, info = gsf.reguided_filter("bf", (n,), _dev(x0, prec, gsf), gsf.METHOD_POWER, 25, **par, prec=prec,
+                                      norm=norm)
+        ref = oracle.power_filter_reguided("bf", x0, (n,), 25, radius=3, sigma_s=2.0, sigma_r=0.15, data_prec=dp,
+                                           norm=norm)
+        e = rel(y.cpu().numpy(), ref)
+        print(f"re-guided power 1D n={n} prec={prec} norm={norm}: {e:.2e}")
+        assert info.iters == 25 and e <= (1e-12 if prec == gsf.F64 else 1e-5)
