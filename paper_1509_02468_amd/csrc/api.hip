@@ -29,6 +29,7 @@ bool launch_bf_apply_joint(const Operator& op, int form, int m, const void* x, i
                            const void* x2, int64_t ldx2, void* y2, int64_t ldy2, double* dot, int* nparts,
                            hipStream_t s);
 bool launch_rg_power_small(const gsf_operator_desc& d, const void* x0, void* x_out, int kmax, hipStream_t s);
+bool launch_cg_small(const Operator& op, const void* x0, void* x_out, int kmax, CgState* st, hipStream_t s);
 gsf_status launch_scale(const Operator& op, const void* in, void* out, int divide, hipStream_t s);
 gsf_status launch_cg_init(const Operator& op, const void* z, void* r, double* partials, CgState* st,
                           hipStream_t s);
@@ -697,6 +698,9 @@ struct CgRun {
   gsf_status finish(void* x_out, double tol, gsf_cg_info* info) {
     if (steps > 0) GSF_TRY(launch_cg_close(op, w.partials2, w.st, s));
     GSF_TRY(launch_scale(op, w.z, x_out, 1, s));
+    return report(tol, info);
+  }
+  gsf_status report(double tol, gsf_cg_info* info) {  // info from the device state
     if (info == nullptr) return GSF_OK;
     CgState host{};
     GSF_TRY(hip_ok(hipMemcpyAsync(&host, w.st, sizeof(host), hipMemcpyDeviceToHost, s)));
@@ -857,6 +861,19 @@ gsf_status gsf_cg_filter(const gsf_operator* h, const void* x0, void* x_out, int
   CgWs w0;
   if (ws == nullptr || ws_bytes < carve_cg(op, nullptr, &w0)) return GSF_ENOMEM;
   CgRun cg(op, (char*)ws, (hipStream_t)stream);
+  {
+    // a 1D BF signal that fits in one workgroup: the whole filter in one launch
+    CgState init{};
+    init.tol = tol;
+    init.tau = breakdown_tau(op.desc.prec);
+    if (op.desc.kind == GSF_BF && op.desc.ndim == 1 && op.n <= 8192) {
+      GSF_TRY(launch_cg_state_init(cg.w.st, init, cg.s));
+      if (launch_cg_small(op, x0, x_out, kmax, cg.w.st, cg.s)) {
+        GSF_TRY(hip_ok(hipGetLastError()));
+        return cg.report(tol, info);
+      }
+    }
+  }
   GSF_TRY(cg.begin(x0, tol));
   Poller poll(cg.s, &cg.w.st->active, info != nullptr && tol > 0.0);
   for (int k = 1; k <= kmax; ++k) {

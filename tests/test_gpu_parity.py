@@ -302,3 +302,29 @@ def test_precision_study_lobpcg_m8_100_steps(gsf, kind, prec):
         assert ey <= 1e-8
     else:
         assert et <= 2e-5
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("n", [777, 8192, 8193, 12000])
+def test_cg_1d_small_and_large_paths(gsf, n, prec):
+    """1D BF CG: up to 8192 samples the filter runs in one workgroup, above on
+    the multi-kernel path; both against the oracle, with a tolerance stop at
+    the oracle's step and a breakdown for a constant input."""
+    x = piecewise_constant_1d(n, 0.1, 40 + n)[1]
+    xr = _round(x, prec, gsf)
+    op = gsf.Operator("bf", (n,), _torch(xr, prec, gsf), radius=4, sigma_d=3.0, sigma_r=0.2, prec=prec)
+    ref = oracle.build_operator("bf", xr, 4, 3.0, 0.2)
+    dp = "f32" if prec == 0 else "f64"
+    y, info = op.cg_filter(_torch(xr, prec, gsf), 25)
+    r, rinfo = oracle.cg_filter(ref, xr, 25, data_prec=dp)
+    e = rel(y.cpu().numpy(), r)
+    print(f"cg 1D n={n} prec={prec}: {e:.2e}")
+    assert info.iters == rinfo.iters == 25 and info.status == gsf.OK and e <= TOL[prec] * (100 if prec else 1)
+    assert abs(info.res0 - rinfo.res0) <= 1e-6 * rinfo.res0
+    y, info = op.cg_filter(_torch(xr, prec, gsf), 2000, tol=1e-4)
+    r, rinfo = oracle.cg_filter(ref, xr, 2000, tol=1e-4, data_prec=dp)
+    assert info.status == gsf.OK and abs(info.iters - rinfo.iters) <= (0 if prec else 2)
+    c = np.full(n, 0.4)
+    y, info = op.cg_filter(_torch(c, prec, gsf), 10)
+    assert info.status == gsf.EBREAKDOWN and info.iters == 0
+    np.testing.assert_allclose(y.cpu().numpy(), c, rtol=1e-6 if prec == 0 else 1e-15)
