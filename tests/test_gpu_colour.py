@@ -201,3 +201,27 @@ def test_colour_fullsize(gsf):
     P = op.power_filter_block(xd, w["power_iters"]).cpu().numpy()
     print(f"1024^2 colour: noisy {p0:.2f} dB, block CG {p1:.2f} dB, block power {psnr(P):.2f} dB")
     assert p1 >= p0 + 3.0 and psnr(P) >= p0 + 3.0
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_block_filters_on_gf_operator(gsf, prec):
+    """The block filters run on any operator: a GF operator (scalar guidance)
+    filtering a 3-channel block, against the oracle column by column."""
+    shape = (60, 90)
+    rgb = scene_2d_rgb(*shape, 0.05, 35)[1].reshape(-1, 3)
+    g = rgb.mean(axis=1)
+    rgb, g = _round(rgb, prec, gsf), _round(g, prec, gsf)
+    op = gsf.Operator("gf", shape, _dev(g, prec, gsf), radius=3, eps=1e-2, prec=prec)
+    ref = oracle.build_operator("gf", g.reshape(shape), 3, eps=1e-2)
+    xd = _dev(rgb, prec, gsf)
+    y = op.power_filter_block(xd, 6).cpu().numpy()
+    r = rgb.copy()
+    for _ in range(6):
+        r = ref.apply_rw(r)
+    assert rel(y, r) <= (1e-12 if prec == gsf.F64 else 1e-5)
+    y, infos = op.cg_filter_block(xd, 12)
+    r, rinfos = oracle.cg_filter_block(ref, rgb, 12, data_prec="f32" if prec == gsf.F32 else "f64")
+    e = rel(y.cpu().numpy(), r)
+    print(f"GF block CG prec={prec}: {e:.2e}")
+    assert e <= (1e-10 if prec == gsf.F64 else 1e-5)
+    assert all(i.iters == 12 for i in infos)
