@@ -314,9 +314,12 @@ def learned_bench(n_images=200, side=512, eval_side=2048, tol=1e-6, kmax=20000, 
 
 def reguided_bench(steps=20, reps=3):
     """The re-guided (non-linear) filters on the metric's workload: every step
-    rebuilds the BF graph from the current iterate.  Reports ms per step of
-    CG and of the power filter, and of the operator build alone (the share of
-    a step that the rebuild takes)."""
+    takes the BF graph of the current iterate.  The passes evaluate the
+    weights of eq. (2) where they use them (power: one pass per step; CG: a
+    degree pass and the L pass), so no planes are stored.  Reports ms per
+    step of CG and of the power filter, the weights evaluated per second by
+    the power pass (n (K - 1) per step), and, for comparison, the operator
+    build that stores the planes (what a rebuild per step would add)."""
     import torch
     import paper_1509_02468_amd as gsf
     from synth import WORKLOADS, make_signal
@@ -346,6 +349,9 @@ def reguided_bench(steps=20, reps=3):
         ms = timed(lambda: gsf.reguided_filter("bf", shape, x0, method, steps, **par, prec=gsf.F32, out=y, ws=ws,
                                                info=False))
         out[f"{name}_ms_per_step"] = round(ms / steps, 4)
+        if method == gsf.METHOD_POWER:
+            k = (2 * w["radius"] + 1) ** 2 - 1
+            out["power_weights_per_s"] = float(f"{x0.numel() * k / (ms / steps * 1e-3):.4g}")
     op = gsf.Operator("bf", shape, x0, **par, prec=gsf.F32)
     ms = timed(lambda: [gsf.Operator("bf", shape, x0, **par, prec=gsf.F32, ws=op.ws) for _ in range(steps)])
     out["build_ms"] = round(ms / steps, 4)

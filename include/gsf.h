@@ -179,6 +179,14 @@ typedef struct {
 /* ---- version / errors ------------------------------------------------- */
 int gsf_version(void);
 const char* gsf_status_string(int status);
+/* gsf_last_device_error: the HIP error code (hipError_t) behind the calling
+ * thread's latest GSF_EDEVICE, 0 if there was none since the last query;
+ * the query resets it.  A kernel launch is checked with hipGetLastError, so a
+ * failed HIP call that the caller made earlier in the thread and left
+ * unchecked is reported by the library's next launch check.
+ * gsf_device_error_string: HIP's text for such a code. */
+int gsf_last_device_error(void);
+const char* gsf_device_error_string(int code);
 
 /* ---- operator (Sections 2-3) ----------------------------------------------
  * gsf_operator_workspace_bytes: bytes of device workspace the operator needs.
@@ -408,8 +416,16 @@ gsf_status gsf_lobpcg_residual(const gsf_operator* op, int m, const void* X, con
  *     ||r|| measured as sqrt(s^T r); info->res is that of the last step taken.
  * x0, x_out: n elements (they may be the same buffer).  ws: device memory of
  * gsf_reguided_workspace_bytes(desc, method) bytes, 256-byte aligned; it holds
- * the rebuilt operator and the solver vectors.  Each step costs one operator
- * build; with FP32 data the graph is built from the stored FP32 iterate.
+ * the solver vectors and, for the GF, the rebuilt operator; for the BF only
+ * the degrees: no weight planes are stored.  BF: every pass evaluates the
+ * weights of eq. (2) from a tile of the iterate staged in LDS where it uses
+ * them (power: one pass per step, y_i = x_i - (1/d_i) sum_j w_ij (x_i - x_j);
+ * CG: a degree pass and the pass q = L p, q_i = sum_j w_ij (p_i - p_j)); with
+ * FP32 data a weight is 2^(-a log2 e) of its exponent a in FP32 (hardware
+ * exponential: relative error a few units of 2^-24 times 1 + |a|), row sums
+ * of the window in FP32 and their total in FP64; FP64 data: exp and all sums
+ * in FP64.  GF: each step costs one operator build.  With FP32 data the graph
+ * is built from the stored FP32 iterate.
  * A 1D BF power filter whose signal fits in one workgroup's LDS (n <= 16384
  * FP32, 8192 FP64) runs all passes in one launch, weights and sums in FP64,
  * the iterate stored in the data type after every pass.

@@ -10,6 +10,14 @@
 
 namespace gsf {
 
+thread_local int g_last_device_error = 0;
+
+gsf_status device_status(hipError_t e) {
+  if (e == hipSuccess) return GSF_OK;
+  g_last_device_error = (int)e;
+  return GSF_EDEVICE;
+}
+
 gsf_status launch_bf_apply(const Operator& op, int form, int m, const void* x, int64_t ldx, void* y,
                            int64_t ldy, double* dot, int* nparts, hipStream_t s);
 int bf_apply_blocks(const Operator& op, int m);
@@ -20,6 +28,9 @@ gsf_status launch_bf_apply_rpt(const Operator& op, int form, int m, const void* 
 gsf_status launch_gf_apply(const Operator& op, void* scratch, int form, int m, const void* x, int64_t ldx,
                            void* y, int64_t ldy, hipStream_t s);
 int vec_blocks(int64_t n);
+int rg_bf_blocks(const Operator& op);
+gsf_status launch_rg_bf(const Operator& op, int mode, const void* g, const void* v, void* y, double* dot,
+                        int* nparts, hipStream_t s);
 gsf_status launch_bscale(const Operator& op, int m, const void* in, void* out, int divide, hipStream_t s);
 gsf_status launch_bcg(int kind, const Operator& op, int m, void* z, void* r, void* p, void* q, double* partials,
                       BlockCgState* st, hipStream_t s);
@@ -258,8 +269,15 @@ struct RgWs {
 
 size_t carve_rg(const gsf_operator_desc* d, int method, char* base, RgWs* w) {
   Carve c{base};
-  char* ob = (char*)c.take(align_up(layout_operator(d, nullptr, nullptr), kAlign));
-  layout_operator(d, &w->op, ob);
+  if (d->kind == GSF_BF) {
+    // the fused passes evaluate the weights of eq. (2) where they are used:
+    // of the operator only the grid, the descriptor and the degrees
+    layout_operator(d, &w->op, nullptr);
+    w->op.deg = (double*)c.take((size_t)w->op.n * sizeof(double));
+  } else {
+    char* ob = (char*)c.take(align_up(layout_operator(d, nullptr, nullptr), kAlign));
+    layout_operator(d, &w->op, ob);
+  }
   const size_t v = (size_t)w->op.n * w->op.elem;
   if (method == GSF_METHOD_POWER) {
     w->tmp = c.take(v);
@@ -272,7 +290,7 @@ size_t carve_rg(const gsf_operator_desc* d, int method, char* base, RgWs* w) {
   w->q = c.take(v);
   int nb = vec_blocks(w->op.n);
   if (d->kind == GSF_BF) {
-    const int ab = bf_apply_blocks(w->op, 1);
+    const int ab = rg_bf_blocks(w->op);
     nb = ab > nb ? ab : nb;
   }
   w->partials = (double*)c.take((size_t)nb * 2 * sizeof(double));
@@ -343,7 +361,7 @@ StartDegrees start_degrees(int ndim, int m) {
   return d;
 }
 
-gsf_status hip_ok(hipError_t e) { return e == hipSuccess ? GSF_OK : GSF_EDEVICE; }
+gsf_status hip_ok(hipError_t e) { return device_status(e); }
 
 #define GSF_TRY(expr)                 \
   do {                                \
@@ -453,6 +471,14 @@ extern "C" {
 gsf_status gsf_block_gram_workspace_bytes(int64_t n, size_t* bytes);
 
 int gsf_version(void) { return 1; }
+
+int gsf_last_device_error(void) {
+  const int e = g_last_device_error;
+  g_last_device_error = 0;
+  return e;
+}
+
+const char* gsf_device_error_string(int code) { return hipGetErrorString((hipError_t)code); }
 
 const char* gsf_status_string(int status) {
   switch (status) {
@@ -1048,13 +1074,28 @@ gsf_status gsf_reguided_filter(const gsf_operator_desc* desc, int method, const 
     return GSF_OK;
   }
   if (x_out != x0) GSF_TRY(hip_ok(hipMemcpyAsync(x_out, x0, v, hipMemcpyDeviceToDevice, s)));
+  // BF: fused passes (mode 0 degrees, 1 D^-1 W g, 2 L v) that evaluate the
+  // weights of the current iterate's graph where they are used; GF: the
+  // operator build (window statistics) and its apply
+  const bool bf = op.desc.kind == GSF_BF;
+  auto rebuild = [&]() -> gsf_status {
+    return bf ? launch_rg_bf(op, 0, x_out, nullptr, nullptr, nullptr, nullptr, s) : build_any(op, x_out, s);
+  };
+  auto lap = [&](const void* v, void* y, double* dot, int* nparts) -> gsf_status {
+    if (bf) return launch_rg_bf(op, 2, x_out, v, y, dot, nparts, s);
+    return apply_any(op, GSF_FORM_L, 1, v, 1, y, 1, dot, nparts, s);
+  };
   if (method == GSF_METHOD_POWER) {
     // x <- D(x)^-1 W(x) x, the graph built from the current iterate each pass
     char* a = (char*)x_out;
     char* b = (char*)w.tmp;
     for (int k = 0; k < kmax; ++k) {
-      GSF_TRY(build_any(op, a, s));
-      GSF_TRY(apply_any(op, GSF_FORM_RW, 1, a, 1, b, 1, nullptr, nullptr, s));
+      if (bf) {
+        GSF_TRY(launch_rg_bf(op, 1, a, a, b, nullptr, nullptr, s));
+      } else {
+        GSF_TRY(build_any(op, a, s));
+        GSF_TRY(apply_any(op, GSF_FORM_RW, 1, a, 1, b, 1, nullptr, nullptr, s));
+      }
       char* t = a;
       a = b;
       b = t;
@@ -1073,20 +1114,20 @@ gsf_status gsf_reguided_filter(const gsf_operator_desc* desc, int method, const 
   init.tol = tol;
   init.tau = breakdown_tau(op.desc.prec);
   GSF_TRY(launch_cg_state_init(w.st, init, s));
-  GSF_TRY(build_any(op, x_out, s));
-  GSF_TRY(apply_any(op, GSF_FORM_L, 1, x_out, 1, w.r, 1, nullptr, nullptr, s));
+  GSF_TRY(rebuild());
+  GSF_TRY(lap(x_out, w.r, nullptr, nullptr));
   GSF_TRY(launch_rg_init(op, x_out, w.r, w.partials, w.st, s));
   Poller poll(s, &w.st->active, info != nullptr && tol > 0.0);
   for (int k = 1; k <= kmax; ++k) {
     if (!poll.keep_going(k - 1)) break;
-    if (k > 1) GSF_TRY(build_any(op, x_out, s));
+    if (k > 1) GSF_TRY(rebuild());
     GSF_TRY(launch_rg_s_beta(op, w.r, w.r_old, w.s, w.partials, w.st, s));
     GSF_TRY(launch_cg_pupdate(op, w.s, w.p, w.st, s));
     int nparts = 0;
-    if (op.desc.kind == GSF_BF) {
-      GSF_TRY(apply_any(op, GSF_FORM_L, 1, w.p, 1, w.q, 1, w.partials, &nparts, s));
+    if (bf) {
+      GSF_TRY(lap(w.p, w.q, w.partials, &nparts));
     } else {
-      GSF_TRY(apply_any(op, GSF_FORM_L, 1, w.p, 1, w.q, 1, nullptr, nullptr, s));
+      GSF_TRY(lap(w.p, w.q, nullptr, nullptr));
       GSF_TRY(launch_dot(op, w.p, w.q, w.partials, &nparts, w.st, s));
     }
     GSF_TRY(launch_rg_alpha(w.partials, nparts, w.st, s));

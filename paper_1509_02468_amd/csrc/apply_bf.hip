@@ -73,7 +73,7 @@ gsf_status launch_bf_apply_rpt(const Operator& op, int form, int m, const void* 
     c0 += w;
   }
   if (nparts) *nparts = nb;
-  return hipGetLastError() == hipSuccess ? GSF_OK : GSF_EDEVICE;
+  return launch_status();
 }
 
 gsf_status launch_bf_apply(const Operator& op, int form, int m, const void* x, int64_t ldx, void* y,

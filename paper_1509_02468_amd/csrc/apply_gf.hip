@@ -362,7 +362,7 @@ gsf_status launch_gf_apply(const Operator& op, void* scratch, int form, int m, c
     gf_apply_typed<float>(op, scratch, form, m, (const float*)x, ldx, (float*)y, ldy, s);
   else
     gf_apply_typed<double>(op, scratch, form, m, (const double*)x, ldx, (double*)y, ldy, s);
-  return hipGetLastError() == hipSuccess ? GSF_OK : GSF_EDEVICE;
+  return launch_status();
 }
 
 gsf_status launch_gf_build(const Operator& op, const void* guidance, hipStream_t s) {
@@ -376,7 +376,7 @@ gsf_status launch_gf_build(const Operator& op, const void* guidance, hipStream_t
                       (double*)op.sqd, (double*)op.diag, op.deg, op.desc.gf_eps, gf_omega(op)};
     gf_box_kernel<GfStats<double>><<<gf_grid(op, geo), kGfLanes, 0, s>>>(p, geo);
   }
-  return hipGetLastError() == hipSuccess ? GSF_OK : GSF_EDEVICE;
+  return launch_status();
 }
 
 }  // namespace gsf

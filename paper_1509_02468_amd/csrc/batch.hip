@@ -74,7 +74,7 @@ double item_work(const gsf_batch_item& it, const Operator& op) {
   return it.method == GSF_METHOD_LOBPCG ? n * k * (2.0 * it.m + 8.0) : n * k * 2.0;
 }
 
-gsf_status hip_ok(hipError_t e) { return e == hipSuccess ? GSF_OK : GSF_EDEVICE; }
+gsf_status hip_ok(hipError_t e) { return device_status(e); }
 
 void free_batch(gsf_batch* b) {
   if (b == nullptr) return;

@@ -366,7 +366,7 @@ gsf_status launch_bscale(const Operator& op, int m, const void* in, void* out, i
     launch_bscale_t<float>(op, m, in, out, divide, s);
   else
     launch_bscale_t<double>(op, m, in, out, divide, s);
-  return hipGetLastError() == hipSuccess ? GSF_OK : GSF_EDEVICE;
+  return launch_status();
 }
 
 // kind: 0 init (r <- -r, per-column rho0 and floor), 1 p update, 2 p^T q and
@@ -377,12 +377,12 @@ gsf_status launch_bcg(int kind, const Operator& op, int m, void* z, void* r, voi
     launch_bcg_t<float>(kind, op, m, z, r, p, q, partials, st, s);
   else
     launch_bcg_t<double>(kind, op, m, z, r, p, q, partials, st, s);
-  return hipGetLastError() == hipSuccess ? GSF_OK : GSF_EDEVICE;
+  return launch_status();
 }
 
 gsf_status launch_bcg_state_init(BlockCgState* st, const BlockCgState& v, hipStream_t s) {
   bcg_state_init_kernel<<<1, 1, 0, s>>>(st, v);
-  return hipGetLastError() == hipSuccess ? GSF_OK : GSF_EDEVICE;
+  return launch_status();
 }
 
 gsf_status launch_srgb_to_lab(int prec, int64_t n, const void* rgb, void* lab, hipStream_t s) {
@@ -392,7 +392,7 @@ gsf_status launch_srgb_to_lab(int prec, int64_t n, const void* rgb, void* lab, h
     srgb_to_lab_kernel<float><<<nb, kThreads, 0, s>>>((const float*)rgb, (float*)lab, n, p);
   else
     srgb_to_lab_kernel<double><<<nb, kThreads, 0, s>>>((const double*)rgb, (double*)lab, n, p);
-  return hipGetLastError() == hipSuccess ? GSF_OK : GSF_EDEVICE;
+  return launch_status();
 }
 
 }  // namespace gsf

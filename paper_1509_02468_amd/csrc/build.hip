@@ -177,7 +177,7 @@ gsf_status launch_bf_build(const Operator& op, const void* guidance, hipStream_t
     bf_degree_kernel<double><<<grid, kThreads, 0, s>>>((const double*)op.planes, op.deg, (double*)op.diag,
                                                        (double*)op.sqd, p, op.pstride, op.ppad, op.nplanes);
   }
-  return hipGetLastError() == hipSuccess ? GSF_OK : GSF_EDEVICE;
+  return launch_status();
 }
 
 }  // namespace gsf

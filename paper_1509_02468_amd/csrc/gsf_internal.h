@@ -105,6 +105,11 @@ __device__ __forceinline__ int xcd_tile(int b, int ntiles) {
   return k * q + (k < rem ? k : rem) + l;
 }
 
+// Status of a HIP call (GSF_EDEVICE on failure, the code kept for
+// gsf_last_device_error) and of the launches so far in this thread.
+gsf_status device_status(hipError_t e);
+inline gsf_status launch_status() { return device_status(hipGetLastError()); }
+
 // ---------------------------------------------------------------------------
 // launchers (implemented in the .hip files)
 // ---------------------------------------------------------------------------

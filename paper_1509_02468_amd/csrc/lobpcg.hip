@@ -1077,7 +1077,7 @@ gsf_status lob_launch_ynorm(const LobArgs& a, int nb, hipStream_t s) {
   else
     lob_ynorm_kernel<double><<<nb, kThreads, 0, s>>>((const double*)a.sqd, a.n, a.vpart, a.st);
   lob_final_kernel<1><<<1, kThreads, 0, s>>>(a.vpart, nb, a.st, 0, a.m, 0, 0);
-  return hipGetLastError() == hipSuccess ? GSF_OK : GSF_EDEVICE;
+  return launch_status();
 }
 
 gsf_status lob_launch_mkernel(int which, const LobArgs& a, int nb, int ns, int first, StartDegrees deg,
@@ -1086,7 +1086,7 @@ gsf_status lob_launch_mkernel(int which, const LobArgs& a, int nb, int ns, int f
     launch_m_dispatch<float>(which, a, nb, ns, first, deg, s);
   else
     launch_m_dispatch<double>(which, a, nb, ns, first, deg, s);
-  return hipGetLastError() == hipSuccess ? GSF_OK : GSF_EDEVICE;
+  return launch_status();
 }
 
 gsf_status lob_launch_project(const LobArgs& a, void* B, int nb, hipStream_t s) {
@@ -1094,7 +1094,7 @@ gsf_status lob_launch_project(const LobArgs& a, void* B, int nb, hipStream_t s) 
     lob_project_kernel<float><<<nb, kThreads, 0, s>>>((float*)B, (const float*)a.sqd, a.n, a.m, a.st);
   else
     lob_project_kernel<double><<<nb, kThreads, 0, s>>>((double*)B, (const double*)a.sqd, a.n, a.m, a.st);
-  return hipGetLastError() == hipSuccess ? GSF_OK : GSF_EDEVICE;
+  return launch_status();
 }
 
 // The Gram pair is loaded by one workgroup of four waves; the Rayleigh-Ritz
@@ -1122,7 +1122,7 @@ gsf_status lob_launch_gram(const GramArgs& g, const RRArgs& r, int prec, hipStre
   dim3 grid(gram_tiles_total(g.ns), kGramChunks);
   gram_reduce_kernel<<<grid, kThreads, 0, s>>>(g);
   gram_rr_kernel<<<1, rr_threads(g.ns), 0, s>>>(g, r);
-  return hipGetLastError() == hipSuccess ? GSF_OK : GSF_EDEVICE;
+  return launch_status();
 }
 
 // Rayleigh-Ritz alone on a Gram pair already in device memory (GA then GB,
@@ -1146,7 +1146,7 @@ __global__ void __launch_bounds__(kThreads) rr_only_kernel(const double* __restr
 
 gsf_status lob_launch_rr_only(const double* G, int ns, int m, const RRArgs& r, hipStream_t s) {
   rr_only_kernel<<<1, rr_threads(ns), 0, s>>>(G, ns, m, r);
-  return hipGetLastError() == hipSuccess ? GSF_OK : GSF_EDEVICE;
+  return launch_status();
 }
 
 }  // namespace gsf

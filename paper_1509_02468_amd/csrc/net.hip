@@ -811,7 +811,7 @@ gsf_status net_forward_train(const uint16_t* w, int batch, const int32_t* idx, i
   net_fwd1_kernel<<<nb, kThreads, 0, s>>>(a);
   net_fwd2_kernel<<<nb, kThreads, 0, s>>>(a);
   net_fwd3_kernel<<<targets != nullptr ? nbl : nb, kThreads, 0, s>>>(a);
-  if (targets == nullptr) return hipGetLastError() == hipSuccess ? GSF_OK : GSF_EDEVICE;
+  if (targets == nullptr) return launch_status();
   net_loss_final_kernel<<<1, kThreads, 0, s>>>(t.loss_part, nbl, 1.0 / ((double)batch * (double)hw), loss);
   net_bwd3_kernel<<<nb, kThreads, 0, s>>>(a);
   net_bwd2_kernel<<<nb, kThreads, 0, s>>>(a);
@@ -829,7 +829,7 @@ gsf_status net_forward_train(const uint16_t* w, int batch, const int32_t* idx, i
   net_wgrad_reduce_kernel<<<(kOffW3 - kOffW2 + kThreads - 1) / kThreads, kThreads, 0, s>>>(p2, gw, kOffW3 - kOffW2,
                                                                                         grad + kOffW2);
   net_wgrad_reduce_kernel<<<1, kThreads, 0, s>>>(p3, gw, kNetWeights - kOffW3, grad + kOffW3);
-  return hipGetLastError() == hipSuccess ? GSF_OK : GSF_EDEVICE;
+  return launch_status();
 }
 
 gsf_status net_adam(int64_t count, int t, double lr, double b1, double b2, double eps, float* w, float* mom,
@@ -837,12 +837,12 @@ gsf_status net_adam(int64_t count, int t, double lr, double b1, double b2, doubl
   const float bc1 = (float)(1.0 - std::pow(b1, t)), bc2 = (float)(1.0 - std::pow(b2, t));
   net_adam_kernel<<<px_blocks(count), kThreads, 0, s>>>(count, (float)b1, (float)b2, (float)eps, (float)lr, bc1, bc2,
                                                         w, mom, vel, grad, wb);
-  return hipGetLastError() == hipSuccess ? GSF_OK : GSF_EDEVICE;
+  return launch_status();
 }
 
 gsf_status net_to_bf16(int64_t count, const float* w, uint16_t* wb, hipStream_t s) {
   net_to_bf16_kernel<<<px_blocks(count), kThreads, 0, s>>>(count, w, wb);
-  return hipGetLastError() == hipSuccess ? GSF_OK : GSF_EDEVICE;
+  return launch_status();
 }
 
 int net_tiles(int64_t rows, int64_t cols) {
@@ -871,7 +871,7 @@ gsf_status net_infer(int prec, const uint16_t* w, int64_t rows, int64_t cols, in
     net_infer_kernel<float><<<a.ntiles, kNetThreads, 0, s>>>(a);
   else
     net_infer_kernel<double><<<a.ntiles, kNetThreads, 0, s>>>(a);
-  return hipGetLastError() == hipSuccess ? GSF_OK : GSF_EDEVICE;
+  return launch_status();
 }
 
 gsf_status net_lob_select(int prec, int64_t rows, int64_t cols, int m, int constraint, void* W, const void* Z,
@@ -885,7 +885,7 @@ gsf_status net_lob_select(int prec, int64_t rows, int64_t cols, int m, int const
   else
     net_select_kernel<double><<<nb, kThreads, 0, s>>>((double*)W, (const double*)Z, (const double*)sqd, n, m,
                                                       constraint, st);
-  return hipGetLastError() == hipSuccess ? GSF_OK : GSF_EDEVICE;
+  return launch_status();
 }
 
 gsf_status launch_colnorm(int prec, const void* R, int64_t n, int m, int64_t ld, double* partials, double* out,
@@ -896,7 +896,7 @@ gsf_status launch_colnorm(int prec, const void* R, int64_t n, int m, int64_t ld,
   else
     colnorm_kernel<double><<<nb, kThreads, 0, s>>>((const double*)R, n, m, ld, partials);
   colnorm_final_kernel<<<1, kThreads, 0, s>>>(partials, nb, out);
-  return hipGetLastError() == hipSuccess ? GSF_OK : GSF_EDEVICE;
+  return launch_status();
 }
 
 gsf_status launch_net_pair(int prec, const void* r, int64_t ldr, const void* y, int64_t ldy, const void* g,
@@ -908,7 +908,7 @@ gsf_status launch_net_pair(int prec, const void* r, int64_t ldr, const void* y, 
   else
     net_pair_kernel<double><<<nb, kThreads, 0, s>>>((const double*)r, ldr, (const double*)y, ldy, (const double*)g,
                                                     n, norm, in, tg);
-  return hipGetLastError() == hipSuccess ? GSF_OK : GSF_EDEVICE;
+  return launch_status();
 }
 
 gsf_status launch_residual(int prec, const void* X, void* R, int64_t n, int m, const double* theta, hipStream_t s) {
@@ -919,7 +919,7 @@ gsf_status launch_residual(int prec, const void* X, void* R, int64_t n, int m, c
     residual_kernel<float><<<nb, kThreads, 0, s>>>((const float*)X, (float*)R, n, m, th);
   else
     residual_kernel<double><<<nb, kThreads, 0, s>>>((const double*)X, (double*)R, n, m, th);
-  return hipGetLastError() == hipSuccess ? GSF_OK : GSF_EDEVICE;
+  return launch_status();
 }
 
 gsf_status launch_scg_init(int prec, const void* b, int64_t ldb, void* y, void* r, int64_t n, double* partials,
@@ -930,7 +930,7 @@ gsf_status launch_scg_init(int prec, const void* b, int64_t ldb, void* y, void* 
   else
     scg_init_kernel<double><<<nb, kThreads, 0, s>>>((const double*)b, ldb, (double*)y, (double*)r, n, partials);
   scg_init_final_kernel<<<1, kThreads, 0, s>>>(partials, nb, st);
-  return hipGetLastError() == hipSuccess ? GSF_OK : GSF_EDEVICE;
+  return launch_status();
 }
 
 gsf_status launch_scg_shift(int prec, const void* p, void* q, int64_t n, double shift, double* partials, int* nparts,
@@ -941,7 +941,7 @@ gsf_status launch_scg_shift(int prec, const void* p, void* q, int64_t n, double 
     scg_shift_kernel<float><<<nb, kThreads, 0, s>>>((const float*)p, (float*)q, n, shift, partials, st);
   else
     scg_shift_kernel<double><<<nb, kThreads, 0, s>>>((const double*)p, (double*)q, n, shift, partials, st);
-  return hipGetLastError() == hipSuccess ? GSF_OK : GSF_EDEVICE;
+  return launch_status();
 }
 
 }  // namespace gsf

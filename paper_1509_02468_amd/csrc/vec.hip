@@ -438,7 +438,7 @@ gsf_status launch_scale(const Operator& op, const void* in, void* out, int divid
   else
     scale_kernel<double><<<nb, kThreads, 0, s>>>((const double*)in, (const double*)op.sqd, (double*)out, op.n,
                                                  divide);
-  return hipGetLastError() == hipSuccess ? GSF_OK : GSF_EDEVICE;
+  return launch_status();
 }
 
 gsf_status launch_cg_init(const Operator& op, const void* z, void* r, double* partials, CgState* st,
@@ -449,7 +449,7 @@ gsf_status launch_cg_init(const Operator& op, const void* z, void* r, double* pa
   else
     cg_init_kernel<double><<<nb, kThreads, 0, s>>>((const double*)z, (double*)r, op.n, partials, st);
   cg_init_final_kernel<<<1, kThreads, 0, s>>>(partials, nb, st);
-  return hipGetLastError() == hipSuccess ? GSF_OK : GSF_EDEVICE;
+  return launch_status();
 }
 
 gsf_status launch_cg_pupdate(const Operator& op, const void* r, void* p, const CgState* st, hipStream_t s) {
@@ -458,7 +458,7 @@ gsf_status launch_cg_pupdate(const Operator& op, const void* r, void* p, const C
     cg_pupdate_kernel<float><<<nb, kThreads, 0, s>>>((const float*)r, (float*)p, op.n, st);
   else
     cg_pupdate_kernel<double><<<nb, kThreads, 0, s>>>((const double*)r, (double*)p, op.n, st);
-  return hipGetLastError() == hipSuccess ? GSF_OK : GSF_EDEVICE;
+  return launch_status();
 }
 
 gsf_status launch_dot(const Operator& op, const void* a, const void* b, double* partials, int* nparts,
@@ -469,12 +469,12 @@ gsf_status launch_dot(const Operator& op, const void* a, const void* b, double* 
     dot_kernel<float><<<nb, kThreads, 0, s>>>((const float*)a, (const float*)b, op.n, partials, st);
   else
     dot_kernel<double><<<nb, kThreads, 0, s>>>((const double*)a, (const double*)b, op.n, partials, st);
-  return hipGetLastError() == hipSuccess ? GSF_OK : GSF_EDEVICE;
+  return launch_status();
 }
 
 gsf_status launch_cg_alpha(const double* partials, int nparts, CgState* st, hipStream_t s) {
   cg_alpha_kernel<<<1, kThreads, 0, s>>>(partials, nparts, st);
-  return hipGetLastError() == hipSuccess ? GSF_OK : GSF_EDEVICE;
+  return launch_status();
 }
 
 gsf_status launch_cg_update(const Operator& op, void* z, void* r, const void* p, const void* q, double* partials,
@@ -487,7 +487,7 @@ gsf_status launch_cg_update(const Operator& op, void* z, void* r, const void* p,
     cg_update_kernel<double><<<nb, kThreads, 0, s>>>((double*)z, (double*)r, (const double*)p, (const double*)q,
                                                      op.n, partials, st);
   cg_beta_kernel<<<1, kThreads, 0, s>>>(partials, nb, st);
-  return hipGetLastError() == hipSuccess ? GSF_OK : GSF_EDEVICE;
+  return launch_status();
 }
 
 gsf_status launch_cg_pbeta(const Operator& op, const void* r, void* p, const double* upd, CgState* st, int k,
@@ -497,7 +497,7 @@ gsf_status launch_cg_pbeta(const Operator& op, const void* r, void* p, const dou
     cg_pbeta_kernel<float><<<nb, kThreads, 0, s>>>((const float*)r, (float*)p, op.n, upd, nb, st, k);
   else
     cg_pbeta_kernel<double><<<nb, kThreads, 0, s>>>((const double*)r, (double*)p, op.n, upd, nb, st, k);
-  return hipGetLastError() == hipSuccess ? GSF_OK : GSF_EDEVICE;
+  return launch_status();
 }
 
 gsf_status launch_cg_aupdate(const Operator& op, void* z, void* r, const void* p, const void* q, const double* dots,
@@ -509,12 +509,12 @@ gsf_status launch_cg_aupdate(const Operator& op, void* z, void* r, const void* p
   else
     cg_aupdate_kernel<double><<<nb, kThreads, 0, s>>>((double*)z, (double*)r, (const double*)p,
                                                       (const double*)q, op.n, dots, ndots, upd, st, k);
-  return hipGetLastError() == hipSuccess ? GSF_OK : GSF_EDEVICE;
+  return launch_status();
 }
 
 gsf_status launch_cg_close(const Operator& op, const double* upd, CgState* st, hipStream_t s) {
   cg_close_kernel<<<1, kThreads, 0, s>>>(upd, vec_blocks(op.n), st);
-  return hipGetLastError() == hipSuccess ? GSF_OK : GSF_EDEVICE;
+  return launch_status();
 }
 
 gsf_status launch_rg_init(const Operator& op, const void* x, void* r, double* partials, CgState* st, hipStream_t s) {
@@ -524,7 +524,7 @@ gsf_status launch_rg_init(const Operator& op, const void* x, void* r, double* pa
   else
     rg_init_kernel<double><<<nb, kThreads, 0, s>>>((const double*)x, (double*)r, op.deg, op.n, partials);
   rg_init_final_kernel<<<1, kThreads, 0, s>>>(partials, nb, st);
-  return hipGetLastError() == hipSuccess ? GSF_OK : GSF_EDEVICE;
+  return launch_status();
 }
 
 gsf_status launch_rg_s_beta(const Operator& op, const void* r, const void* r_old, void* sv, double* partials,
@@ -537,12 +537,12 @@ gsf_status launch_rg_s_beta(const Operator& op, const void* r, const void* r_old
     rg_s_kernel<double><<<nb, kThreads, 0, s>>>((const double*)r, (const double*)r_old, op.deg, (double*)sv,
                                                 op.n, partials, st);
   rg_beta_kernel<<<1, kThreads, 0, s>>>(partials, nb, st);
-  return hipGetLastError() == hipSuccess ? GSF_OK : GSF_EDEVICE;
+  return launch_status();
 }
 
 gsf_status launch_rg_alpha(const double* partials, int nparts, CgState* st, hipStream_t s) {
   rg_alpha_kernel<<<1, kThreads, 0, s>>>(partials, nparts, st);
-  return hipGetLastError() == hipSuccess ? GSF_OK : GSF_EDEVICE;
+  return launch_status();
 }
 
 gsf_status launch_rg_update(const Operator& op, void* x, void* r, void* r_old, const void* p, const void* q,
@@ -554,7 +554,7 @@ gsf_status launch_rg_update(const Operator& op, void* x, void* r, void* r_old, c
   else
     rg_update_kernel<double><<<nb, kThreads, 0, s>>>((double*)x, (double*)r, (double*)r_old, (const double*)p,
                                                      (const double*)q, op.n, st);
-  return hipGetLastError() == hipSuccess ? GSF_OK : GSF_EDEVICE;
+  return launch_status();
 }
 
 }  // namespace gsf

@@ -72,8 +72,8 @@ _lib = None
 
 
 class GsfError(RuntimeError):
-    def __init__(self, status, where):
-        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)}")
+    def __init__(self, status, where, detail=""):
+        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)}{detail}")
         self.status = status
 
 
@@ -90,6 +90,8 @@ def load_library(path: str = LIB_PATH):
     sig = {
         "gsf_version": ([], i32),
         "gsf_status_string": ([i32], ctypes.c_char_p),
+        "gsf_last_device_error": ([], i32),
+        "gsf_device_error_string": ([i32], ctypes.c_char_p),
         "gsf_operator_workspace_bytes": ([P(OperatorDesc), P(sz)], i32),
         "gsf_build_operator": ([P(OperatorDesc), vp, vp, sz, vp, P(vp)], i32),
         "gsf_operator_get_layout": ([vp, P(OperatorLayout)], i32),
@@ -142,7 +144,12 @@ def load_library(path: str = LIB_PATH):
 
 def _check(status, where):
     if status not in (OK, ENOTCONV, EBREAKDOWN):
-        raise GsfError(status, where)
+        detail = ""
+        if status == EDEVICE and _lib is not None:
+            code = _lib.gsf_last_device_error()
+            if code:
+                detail = f" (HIP error {code}: {_lib.gsf_device_error_string(code).decode()})"
+        raise GsfError(status, where, detail)
     return status
 
 

@@ -217,3 +217,54 @@ def test_reguided_power_1d_both_paths(gsf, n, prec):
         e = rel(y.cpu().numpy(), ref)
         print(f"re-guided power 1D n={n} prec={prec} norm={norm}: {e:.2e}")
         assert info.iters == 25 and e <= (1e-12 if prec == gsf.F64 else 1e-5)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("stencil,norm", [("square", "d"), ("square", "diagl"), ("cross", "d"), ("cross", "diagl")])
+def test_reguided_bf_interior_and_border_tiles(gsf, stencil, norm, prec):
+    """The BF passes evaluate the weights from a 64 x 16 tile of the iterate
+    and its halo in LDS, with a branch-free body for tiles whose halo lies on
+    the grid: 100 x 200 with radius 5 has such interior tiles as well as
+    border tiles on all four sides and ragged ones.  Power (4 passes) and CG
+    (6 steps) against the oracle; the FP32 weights use the hardware base-2
+    exponential (relative error a few units of 2^-24 times 1 + the exponent's
+    magnitude), well inside the bounds stated at the top."""
+    shape = (100, 200)
+    x0 = scene_2d(shape[0], shape[1], 0.05, 77)[1].ravel()
+    if prec == gsf.F32:
+        x0 = x0.astype(np.float32).astype(np.float64)
+    dp = "f32" if prec == gsf.F32 else "f64"
+    gp = dict(radius=5, sigma_d=3.0, sigma_r=0.15, stencil=stencil, norm=norm)
+    op_ = dict(radius=5, sigma_s=3.0, sigma_r=0.15, stencil=stencil, norm=norm, data_prec=dp)
+    y, info = gsf.reguided_filter("bf", shape, _dev(x0, prec, gsf), gsf.METHOD_POWER, 4, **gp, prec=prec)
+    ref = oracle.power_filter_reguided("bf", x0, shape, 4, **op_)
+    e = rel(y.cpu().numpy(), ref)
+    y, info = gsf.reguided_filter("bf", shape, _dev(x0, prec, gsf), gsf.METHOD_CG, 6, **gp, prec=prec)
+    ref, rinfo = oracle.cg_filter_reguided("bf", x0, shape, 6, **op_)
+    ec = rel(y.cpu().numpy(), ref)
+    print(f"re-guided BF 100x200 r=5 {stencil}/{norm} prec={prec}: power {e:.2e}, CG {ec:.2e}")
+    assert e <= (1e-12 if prec == gsf.F64 else 1e-5)
+    assert info.iters == rinfo.iters == 6 and ec <= (1e-11 if prec == gsf.F64 else 1e-4)
+    assert abs(info.res0 - rinfo.res0) <= (1e-12 if prec == gsf.F64 else 1e-5) * rinfo.res0
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("shape", [(40, 90), (5000,)])
+def test_reguided_bf_largest_radius(gsf, shape, prec):
+    """Radius 8 (the largest window): the LDS tile holds the largest halo
+    (80 x 32 points of the iterate and of the CG vector in 2D)."""
+    x0 = _signal(shape, 78)
+    if prec == gsf.F32:
+        x0 = x0.astype(np.float32).astype(np.float64)
+    dp = "f32" if prec == gsf.F32 else "f64"
+    y, _ = gsf.reguided_filter("bf", shape, _dev(x0, prec, gsf), gsf.METHOD_POWER, 3, radius=8, sigma_d=4.0,
+                               sigma_r=0.2, prec=prec)
+    ref = oracle.power_filter_reguided("bf", x0, shape, 3, radius=8, sigma_s=4.0, sigma_r=0.2, data_prec=dp)
+    e = rel(y.cpu().numpy(), ref)
+    y, info = gsf.reguided_filter("bf", shape, _dev(x0, prec, gsf), gsf.METHOD_CG, 4, radius=8, sigma_d=4.0,
+                                  sigma_r=0.2, prec=prec)
+    ref, rinfo = oracle.cg_filter_reguided("bf", x0, shape, 4, radius=8, sigma_s=4.0, sigma_r=0.2, data_prec=dp)
+    ec = rel(y.cpu().numpy(), ref)
+    print(f"re-guided BF radius 8 {shape} prec={prec}: power {e:.2e}, CG {ec:.2e}")
+    assert e <= (1e-12 if prec == gsf.F64 else 1e-5)
+    assert info.iters == rinfo.iters == 4 and ec <= (1e-11 if prec == gsf.F64 else 1e-4)
