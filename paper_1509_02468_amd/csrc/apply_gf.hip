@@ -109,64 +109,74 @@ __global__ void __launch_bounds__(kGfLanes) gf_box_kernel(P p, GfGeom g) {
   }
   // ring of the entering / leaving points of the next D output rows
   constexpr int D = M <= 2 ? 4 : (M == 4 ? 2 : 1);
+  // and of the epilogue's loads at the output points, the same D rows ahead
   Row fa[D], fd[D];
+  Epi ep[D][M];
+  auto out_col = [&](int t) { return t < nout ? c0 + cb + t : c0; };
 #pragma unroll
   for (int u = 0; u < D; ++u) {
     fa[u] = p.fetch(clamp_row(y0 + u + r) * g.cols + gcs);
     fd[u] = p.fetch(clamp_row(y0 + u - r) * g.cols + gcs);
+#pragma unroll
+    for (int t = 0; t < M; ++t) ep[u][t] = p.pre(clamp_row(y0 + u) * g.cols + out_col(t), j);
   }
+  // The body runs for every u, also past the workgroup's last row in the final
+  // group (only the stores are skipped there): a ring slot refilled on some
+  // paths only would need a register copy, and so a wait, every row.
   for (int yb = y0; yb < y1; yb += D) {
 #pragma unroll
     for (int u = 0; u < D; ++u) {
       const int yo = yb + u;
-      if (yo < y1) {
-        const int ya = yo + r, yd = yo - r;
-        Epi e[M];
+      const bool live = yo < y1;
+      const int ya = yo + r, yd = yo - r;
+      Epi e[M];
 #pragma unroll
-        for (int t = 0; t < M; ++t) e[t] = p.pre(yo * g.cols + (t < nout ? c0 + cb + t : c0), j);
-        const bool add = cok && ya < g.rows;
-#pragma unroll
-        for (int q = 0; q < M; ++q) {
-          const double2 v = p.value(fa[u], q);
-          s[2 * q] += add ? v.x : 0.0;
-          s[2 * q + 1] += add ? v.y : 0.0;
-        }
-        wave_lds_fence();
-#pragma unroll
-        for (int c = 0; c < 2 * M; ++c) vs[c][lane] = cok ? s[c] : 0.0;
-        wave_lds_fence();
-        const int vc = (ya < g.rows ? ya : g.rows - 1) - (yd < 0 ? 0 : yd) + 1;
-        const double rv = 1.0 / (double)vc, srv = sqrt(rv);
-        if (nout > 0) {
-          const double* v0 = &vs[2 * j][cb];
-          const double* v1 = &vs[2 * j + 1][cb];
-          double a0 = 0.0, a1 = 0.0;
-          for (int h = 0; h < 2 * r; ++h) {
-            a0 += v0[h];
-            a1 += v1[h];
-          }
-#pragma unroll
-          for (int t = 0; t < M; ++t) {
-            if (t < nout) {
-              a0 += v0[t + 2 * r];
-              a1 += v1[t + 2 * r];
-              p.store(yo * g.cols + c0 + cb + t, j, a0, a1, rv * rh[t], srv * srh[t], e[t]);
-              a0 -= v0[t];
-              a1 -= v1[t];
-            }
-          }
-        }
-        wave_lds_fence();
-        const bool sub = cok && yd >= 0;
-#pragma unroll
-        for (int q = 0; q < M; ++q) {
-          const double2 v = p.value(fd[u], q);
-          s[2 * q] -= sub ? v.x : 0.0;
-          s[2 * q + 1] -= sub ? v.y : 0.0;
-        }
-        fa[u] = p.fetch(clamp_row(ya + D) * g.cols + gcs);
-        fd[u] = p.fetch(clamp_row(yd + D) * g.cols + gcs);
+      for (int t = 0; t < M; ++t) {
+        e[t] = ep[u][t];
+        ep[u][t] = p.pre(clamp_row(yo + D) * g.cols + out_col(t), j);
       }
+      const bool add = cok && ya < g.rows;
+#pragma unroll
+      for (int q = 0; q < M; ++q) {
+        const double2 v = p.value(fa[u], q);
+        s[2 * q] += add ? v.x : 0.0;
+        s[2 * q + 1] += add ? v.y : 0.0;
+      }
+      wave_lds_fence();
+#pragma unroll
+      for (int c = 0; c < 2 * M; ++c) vs[c][lane] = cok ? s[c] : 0.0;
+      wave_lds_fence();
+      const int vc = (ya < g.rows ? ya : g.rows - 1) - (yd < 0 ? 0 : yd) + 1;
+      const double rv = 1.0 / (double)vc, srv = sqrt(rv);
+      if (nout > 0 && live) {
+        const double* v0 = &vs[2 * j][cb];
+        const double* v1 = &vs[2 * j + 1][cb];
+        double a0 = 0.0, a1 = 0.0;
+        for (int h = 0; h < 2 * r; ++h) {
+          a0 += v0[h];
+          a1 += v1[h];
+        }
+#pragma unroll
+        for (int t = 0; t < M; ++t) {
+          if (t < nout) {
+            a0 += v0[t + 2 * r];
+            a1 += v1[t + 2 * r];
+            p.store(yo * g.cols + c0 + cb + t, j, a0, a1, rv * rh[t], srv * srh[t], e[t]);
+            a0 -= v0[t];
+            a1 -= v1[t];
+          }
+        }
+      }
+      wave_lds_fence();
+      const bool sub = cok && yd >= 0;
+#pragma unroll
+      for (int q = 0; q < M; ++q) {
+        const double2 v = p.value(fd[u], q);
+        s[2 * q] -= sub ? v.x : 0.0;
+        s[2 * q + 1] -= sub ? v.y : 0.0;
+      }
+      fa[u] = p.fetch(clamp_row(ya + D) * g.cols + gcs);
+      fd[u] = p.fetch(clamp_row(yd + D) * g.cols + gcs);
     }
   }
 }
