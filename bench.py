@@ -54,6 +54,7 @@ def _args():
                     help="skip the 5-point-lattice (diag L) image experiment (PSNR after 20 CG / LOBPCG steps)")
     ap.add_argument("--no-study-1d", action="store_true", help="skip the 1D filter study (Section 6)")
     ap.add_argument("--no-colour", action="store_true", help="skip the colour (CIE-Lab guidance) measurement")
+    ap.add_argument("--no-gf", action="store_true", help="skip the GF apply measurement (4096^2, r = 8)")
     ap.add_argument("--learned-images", type=int, default=200, help="training images (10 pairs each)")
     ap.add_argument("--learned-eval", type=int, default=2048, help="side of the evaluation image")
     ap.add_argument("--precision-study", action="store_true",
@@ -421,6 +422,44 @@ def image_experiment_bench(reps=3, apply_reps=200):
     return out
 
 
+def gf_apply_bench(copy_gbs, reps=20):
+    """The GF apply (Algorithm 1 on the fixed guidance, normalized) on the
+    4096^2 GF workload (radius 8, FP32) for m = 1 and 8 columns, L_sym form,
+    timed with HIP events on the launch stream over `reps` launches, against
+    the HBM roofline.  Algorithmic bytes per point: x in and y out (4m each),
+    g, 1/sqrt(d), mu and 1/(var + eps) once (16), and the window
+    coefficients (a, b) written and read once (16m): 4(2m + 4) + 16m."""
+    import torch
+    import paper_1509_02468_amd as gsf
+    from synth import WORKLOADS, make_signal
+    w = WORKLOADS["image_4096_gf8"]
+    shape = w["shape"]
+    n = int(np.prod(shape))
+    _, noisy = make_signal("image_4096_gf8")
+    g = torch.tensor(noisy.ravel().astype(np.float32), device="cuda")
+    op = gsf.Operator("gf", shape, g, radius=w["radius"], eps=w["eps"], prec=gsf.F32)
+    out = {"workload": f"image_4096_gf8 ({shape[0]}x{shape[1]}, GF r={w['radius']}, FP32), L_sym form",
+           "copy_gbs": round(copy_gbs, 1)}
+    s = torch.cuda.current_stream()
+    for m in (1, 8):
+        x = torch.rand((n, m) if m > 1 else (n,), device="cuda", dtype=torch.float32)
+        y = torch.empty_like(x)
+        for _ in range(3):
+            op.apply(x, gsf.FORM_LSYM, out=y)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(reps):
+            op.apply(x, gsf.FORM_LSYM, out=y)
+        e1.record(s)
+        e1.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / reps
+        algo = n * (4 * (2 * m + 4) + 16 * m)
+        gbs = algo / (us * 1e-6) / 1e9
+        out[f"m{m}"] = {"us_per_apply": round(us, 1), "algorithmic_bytes": algo, "achieved_gbs": round(gbs, 1),
+                        "frac": round(gbs / HBM_PEAK_GBS, 4), "frac_of_copy": round(gbs / copy_gbs, 4)}
+    return out
+
+
 def colour_bench(reps=3):
     """Colour guidance (Section 2: the photometric distance in CIE-Lab) on the
     1024^2 colour workload, FP32: the sRGB -> Lab conversion, the build from
@@ -759,6 +798,7 @@ def main():
     image_res = None if a.no_image_experiment else image_experiment_bench()
     study_res = None if a.no_study_1d else study_1d_bench()
     colour_res = None if a.no_colour else colour_bench()
+    gf_res = None if a.no_gf else gf_apply_bench(copy_gbs)
     cpu = None if a.no_cpu else cpu_baseline(w, noisy, a.cpu_seconds)
     out = {"metric": "Mpixel-iters/s of Laplacian apply", "value": round(value, 1), "unit": "Mpixel-iters/s",
            "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(ms, 3),
@@ -769,7 +809,7 @@ def main():
                       "apply_tuning": tuned, "cg_lobpcg_mode": mode},
            "roofline": roofline, "cpu_baseline": cpu, "batch": batch, "learned": learned_res,
            "reguided": reguided_res, "image_experiment": image_res,
-           "study_1d": study_res, "colour": colour_res}
+           "study_1d": study_res, "colour": colour_res, "gf_apply": gf_res}
     print(json.dumps(out), flush=True)
 
 
