@@ -268,3 +268,23 @@ def test_reguided_bf_largest_radius(gsf, shape, prec):
     print(f"re-guided BF radius 8 {shape} prec={prec}: power {e:.2e}, CG {ec:.2e}")
     assert e <= (1e-12 if prec == gsf.F64 else 1e-5)
     assert info.iters == rinfo.iters == 4 and ec <= (1e-11 if prec == gsf.F64 else 1e-4)
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (1, 50), (50, 1), (2,), (3, 7)])
+def test_reguided_bf_tiny_grids(gsf, shape):
+    """Grids smaller than one tile and than the window, single rows and
+    columns: every tile is a border tile and most window points are off the
+    grid.  A single point has no edge (power leaves it unchanged, CG breaks
+    down at once: r_0 = 0); two points converge in one CG step and then break
+    down.  FP64 against the oracle, statuses and step counts included."""
+    x0 = np.random.default_rng(int(np.prod(shape))).random(int(np.prod(shape)))
+    par = dict(radius=2, sigma_d=1.5, sigma_r=0.2)
+    y, _ = gsf.reguided_filter("bf", shape, _dev(x0, gsf.F64, gsf), gsf.METHOD_POWER, 3, **par, prec=gsf.F64)
+    ref = oracle.power_filter_reguided("bf", x0, shape, 3, radius=2, sigma_s=1.5, sigma_r=0.2)
+    assert rel(y.cpu().numpy(), ref) <= 1e-12
+    y, info = gsf.reguided_filter("bf", shape, _dev(x0, gsf.F64, gsf), gsf.METHOD_CG, 4, **par, prec=gsf.F64)
+    ref, rinfo = oracle.cg_filter_reguided("bf", x0, shape, 4, radius=2, sigma_s=1.5, sigma_r=0.2)
+    st = {"ok": gsf.OK, "breakdown": gsf.EBREAKDOWN}[rinfo.status]
+    print(f"re-guided BF tiny {shape}: status {info.status} vs {rinfo.status}, iters {info.iters} vs {rinfo.iters}")
+    assert info.status == st and info.iters == rinfo.iters
+    assert rel(y.cpu().numpy(), ref) <= 1e-11
