@@ -1,7 +1,12 @@
 // Operator construction: BF weights and normalisation (Section 2, eq. (2),
-// eq. (4); Section 4 normalisation).  Weights are computed in FP64 and rounded
-// once to the storage type; the degrees are FP64 row sums of the stored
-// weights (so D 1 = W 1 holds for the operator that is applied).  The
+// eq. (4); Section 4 normalisation).  FP64 data and multi-channel guidance:
+// weights computed in FP64 and rounded once to the storage type, each
+// undirected edge once (fold), then the degrees as FP64 row sums of the
+// stored weights (so D 1 = W 1 holds for the operator that is applied).  FP32
+// data with one guidance channel takes the one-pass build of the window
+// kernels instead (FP32 exponentials, every weight of the window evaluated at
+// its point, the forward half stored; the degrees are again FP64 sums of the
+// stored values).  The
 // (diag L) normalisation sums the off-diagonal weights only: the self-loop
 // cancels in L = D - W, and leaving it out of the sum (rather than taking
 // d_i - 1) keeps a small diag L_i exact to the sum's rounding.
@@ -153,7 +158,11 @@ inline double inv_two_sigma2(double s) { return std::isinf(s) ? 0.0 : 1.0 / (2.0
 
 }  // namespace
 
+bool launch_bf_build_onepass(const Operator& op, const void* guidance, hipStream_t s);
+
 gsf_status launch_bf_build(const Operator& op, const void* guidance, hipStream_t s) {
+  // FP32 data with one guidance channel: one window pass (FP32 exponentials)
+  if (launch_bf_build_onepass(op, guidance, s)) return launch_status();
   BfParams p{op.n,
              op.rows,
              op.cols,

@@ -11,6 +11,11 @@
 //   LAP  y_i = sum_{j != i} w_ij (v_i - v_j) = (L v)_i (the self-loop cancels
 //        in L = D - W under both normalisations), and per workgroup the
 //        partial sum of v_i y_i
+//   BUILD the operator build of FP32 data in one pass: the weights of the
+//        forward half-window written into the planes (w_{i,i+o}, 0 off the
+//        grid), d_i as the FP64 sum of all the point's FP32 weights (the same
+//        values the planes hold, since w_ij and w_ji are bitwise equal), and
+//        1/sqrt(d_i), sqrt(d_i)
 // FP32 data: w = 2^(-(|o|^2 cs + (g_i - g_j)^2 cr) log2 e) with the hardware
 // base-2 exponential (the constants folded with log2 e; the relative error of
 // a weight is a few units of 2^-24 times (1 + its exponent's magnitude)); the
@@ -28,7 +33,7 @@ namespace {
 constexpr int kRgThreads = 256;
 constexpr int kRgPts = 4;  // outputs per thread
 
-enum { RG_DEG = 0, RG_RW = 1, RG_LAP = 2 };
+enum { RG_DEG = 0, RG_RW = 1, RG_LAP = 2, RG_BUILD = 3 };
 
 struct RgParams {
   int rows, cols;  // 1D: one row
@@ -38,7 +43,21 @@ struct RgParams {
   double cs, cr;   // 1 / (2 sigma^2), 0 for sigma = inf
   float ncs2, ncr2;  // -cs log2 e, -cr log2 e
   int tiles_x, ntiles;
+  // BUILD: the half-window planes (plane q's data at planes + ppad + q pstride)
+  // and the 1/sqrt(d), sqrt(d) outputs
+  void* planes;
+  int64_t pstride, ppad;
+  void* diag;
+  void* sqd;
 };
+
+// Plane of the forward offset (dy, dx) (dy > 0, or dy = 0 and dx > 0), in the
+// order of the operator build: (0, 1..r), then the rows dy = 1..r (all dx of
+// the square window, dx = 0 only on the cross lattice).
+__device__ __forceinline__ int rg_plane(int dy, int dx, int r, int cross) {
+  if (dy == 0) return dx - 1;
+  return cross ? r + dy - 1 : r + (dy - 1) * (2 * r + 1) + dx + r;
+}
 
 extern __shared__ double rg_smem[];
 
@@ -105,7 +124,15 @@ __device__ __forceinline__ void rg_tile(const T* __restrict__ gs, const T* __res
           const bool ok = (unsigned)(gyo[t] + dy) < (unsigned)p.rows && (unsigned)(gxo[t] + dx) < (unsigned)p.cols;
           w = ok ? w : T(0);
         }
-        rws[t] += w;
+        if (MODE == RG_BUILD) {
+          ws[t] += (double)w;
+          const bool fwd = dy > 0 || (dy == 0 && dx > 0);
+          if (fwd && (!BORDER || (gyo[t] < p.rows && gxo[t] < p.cols)))
+            ((T*)p.planes)[p.ppad + (int64_t)rg_plane(dy, dx, p.rx, p.cross) * p.pstride + gyo[t] * p.cols +
+                           gxo[t]] = w;
+        } else {
+          rws[t] += w;
+        }
         if (MODE == RG_RW) racc[t] = fma(w, d, racc[t]);
         if (MODE == RG_LAP) racc[t] = fma(w, vi[t] - vq[t * step], racc[t]);
       }
@@ -122,7 +149,11 @@ __device__ __forceinline__ void rg_tile(const T* __restrict__ gs, const T* __res
     const int i = gyo[t] * p.cols + gxo[t];
     double d = p.diagl ? ws[t] : 1.0 + ws[t];
     if (d == 0.0) d = 1.0;
-    if (MODE == RG_DEG) deg[i] = d;
+    if (MODE == RG_DEG || MODE == RG_BUILD) deg[i] = d;
+    if (MODE == RG_BUILD) {
+      ((T*)p.diag)[i] = (T)(1.0 / sqrt(d));
+      ((T*)p.sqd)[i] = (T)sqrt(d);
+    }
     if (MODE == RG_RW) y[i] = (T)((double)vi[t] - acc[t] / d);
     if (MODE == RG_LAP) {
       const T yt = (T)acc[t];
@@ -221,7 +252,39 @@ void rg_dispatch(const RgGeom& g, int mode, const void* gd, const void* v, void*
     rg_launch<T, RG_LAP>(g, gd, v, y, deg, dot, s);
 }
 
+// Zeros of the plane region that are not weights: the ppad entries before
+// each plane's data, the tail up to the next plane, and the ppad entries after
+// the last plane (the apply's mirrored reads land there instead of branching).
+template <typename T>
+__global__ void __launch_bounds__(kRgThreads) rg_plane_pads_kernel(T* __restrict__ planes, int64_t n,
+                                                                   int64_t pstride, int64_t ppad, int nplanes) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= pstride - n) return;
+  const int64_t idx = t < ppad ? t : t + n;  // skips the data [ppad, ppad + n)
+  for (int q = 0; q < nplanes; ++q) planes[(int64_t)q * pstride + idx] = T(0);
+  if (t < ppad) planes[(int64_t)nplanes * pstride + t] = T(0);
+}
+
 }  // namespace
+
+// Operator build of FP32 BF data with one guidance channel in one window
+// pass (the weights of eq. (2) in FP32, the degrees as FP64 sums of exactly
+// the stored values) plus the pad zeros; false (nothing launched) for other
+// descriptors, which take the two-kernel build with FP64 exponentials.
+bool launch_bf_build_onepass(const Operator& op, const void* guidance, hipStream_t s) {
+  if (op.desc.kind != GSF_BF || op.desc.prec != GSF_F32 || desc_channels(op.desc) != 1) return false;
+  RgGeom geo = rg_geom(op, RG_BUILD);
+  geo.p.planes = op.planes;
+  geo.p.pstride = op.pstride;
+  geo.p.ppad = op.ppad;
+  geo.p.diag = op.diag;
+  geo.p.sqd = op.sqd;
+  const int64_t npad = op.pstride - op.n;
+  rg_plane_pads_kernel<float><<<(unsigned)((npad + kRgThreads - 1) / kRgThreads), kRgThreads, 0, s>>>(
+      (float*)op.planes, op.n, op.pstride, op.ppad, op.nplanes);
+  rg_launch<float, RG_BUILD>(geo, guidance, nullptr, nullptr, op.deg, nullptr, s);
+  return true;
+}
 
 // Workgroups (and so partials) of one fused pass.
 int rg_bf_blocks(const Operator& op) { return rg_geom(op, RG_LAP).p.ntiles; }

@@ -74,17 +74,13 @@ def _build(gsf, case, prec):
 @pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("case", BF_CASES)
 def test_bf_build_parity(gsf, case, prec):
+    """Half-window planes against the oracle's W (w_{i,i+o}, 0 off the grid),
+    degrees as the FP64 row sums of exactly the stored weights (own planes
+    plus the mirrored entries w_{i-o,i}: D 1 = W 1 for the operator that is
+    applied) and against the oracle's d, sqrt(d) and 1/sqrt(d).  FP32 data:
+    the weights come from the FP32 exponential of the one-pass build, within
+    a few units of 2^-24 times 1 + the exponent's magnitude of the oracle's."""
     op, ref, _ = _build(gsf, case, prec)
-    # degrees: FP64 row sums of the stored weights (the oracle's W rounded to
-    # the storage type; for FP64 data that is the oracle's d itself)
-    Wst = ref.W.tocsr().astype(np.float32).astype(np.float64) if prec == gsf.F32 else ref.W.tocsr()
-    d_ref = np.asarray(Wst.sum(axis=1)).ravel()
-    np.testing.assert_allclose(op.degree().cpu().numpy(), d_ref, rtol=1e-13)
-    if prec == gsf.F64:
-        np.testing.assert_allclose(d_ref, ref.d, rtol=1e-13)
-    assert rel(op.sqrt_d().cpu().numpy(), ref.sqrt_d) <= TOL[prec]
-    assert rel(op.inv_sqrt_d().cpu().numpy(), 1.0 / ref.sqrt_d) <= TOL[prec]
-    # half-window planes against the oracle's W: w_{i,i+o}
     planes = op.planes().cpu().numpy().astype(np.float64)
     shape = ref.shape
     r = ref.radius
@@ -94,6 +90,7 @@ def test_bf_build_parity(gsf, case, prec):
         [(0, dx) for dx in range(1, r + 1)] + [(dy, dx) for dy in range(1, r + 1) for dx in range(-r, r + 1)]
     assert planes.shape[0] == len(offs)
     coords = np.indices(shape).reshape(len(shape), -1).T
+    d_st = np.ones(n)
     for q, o in enumerate(offs):
         nb = coords + np.array(o)
         inside = np.all((nb >= 0) & (nb < np.array(shape)), axis=1)
@@ -102,6 +99,14 @@ def test_bf_build_parity(gsf, case, prec):
         expect = np.zeros(n)
         expect[i] = np.asarray(W[i, j]).ravel()
         assert rel(planes[q], expect) <= TOL[prec], (q, o)
+        assert np.all(planes[q][~inside] == 0.0)
+        d_st[i] += planes[q][i]   # own half: w_{i,i+o}
+        d_st[j] += planes[q][i]   # mirrored half: w_{j-o,j} = w_{i,i+o} at j = i + o
+    deg = op.degree().cpu().numpy()
+    np.testing.assert_allclose(deg, d_st, rtol=1e-13)
+    assert rel(deg, ref.d) <= (1e-13 if prec == gsf.F64 else TOL[prec])
+    assert rel(op.sqrt_d().cpu().numpy(), ref.sqrt_d) <= TOL[prec]
+    assert rel(op.inv_sqrt_d().cpu().numpy(), 1.0 / ref.sqrt_d) <= TOL[prec]
 
 
 @pytest.mark.parametrize("prec", [0, 1])
