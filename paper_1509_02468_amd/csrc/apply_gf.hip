@@ -43,9 +43,10 @@ __device__ __forceinline__ int win_count(int v, int len, int r) {
 // own LDS operations complete in order, so no hardware barrier is needed.
 __device__ __forceinline__ void wave_lds_fence() { __asm__ volatile("" ::: "memory"); }
 
-// One wave owns a strip of 64 - 2r output columns (64 halo columns, one per
-// lane) and g.rb rows (8..64).  Lane l keeps the FP64 running vertical window sums
-// of column c0 - r + l for the 2M channels (P::M groups of two); per row it
+// One wave owns a strip of 64 CPL - 2r output columns (64 CPL halo columns,
+// CPL per lane: lane + 64 k) and g.rb rows (8..64).  Lane l keeps the FP64
+// running vertical window sums of its columns c0 - r + l + 64 k for the 2M
+// channels (P::M groups of two); per row it
 // adds the entering row, writes its sums to the wave's LDS row, and then
 // takes the horizontal window sums as lane (group, run of consecutive output
 // columns) with a sliding sum over that LDS row, before subtracting the
@@ -56,22 +57,29 @@ __device__ __forceinline__ void wave_lds_fence() { __asm__ volatile("" ::: "memo
 //   P::fetch(i)  -> Row;    P::value(row, j) -> double2 (group j)
 //   P::Epi / P::pre(k, j) / P::store(k, j, s0, s1, rc, src, e): epilogue at
 //   point k with rc = 1 / (points in the window), src = sqrt(rc).
-template <class P>
+template <class P, int CPL>
 __global__ void __launch_bounds__(kGfLanes) gf_box_kernel(P p, GfGeom g) {
   constexpr int M = P::M;
   constexpr int R = kGfLanes / M;  // runs per group
+  constexpr int W = kGfLanes * CPL;  // halo columns of the strip
+  constexpr int NO = M * CPL;        // most outputs of one lane's run
   typedef typename P::Row Row;
   typedef typename P::Epi Epi;
-  __shared__ double vs[2 * M][kGfLanes + 1];
-  const int r = g.r, ow = kGfLanes - 2 * r;
+  __shared__ double vs[2 * M][W + 1];
+  const int r = g.r, ow = W - 2 * r;
   const int lane = threadIdx.x;
   const int c0 = (int)blockIdx.x * ow;
   const int y0 = (int)blockIdx.y * g.rb;
   const int y1 = y0 + g.rb < g.rows ? y0 + g.rb : g.rows;
-  // column role
-  const int gc = c0 - r + lane;
-  const bool cok = gc >= 0 && gc < g.cols;
-  const int gcs = cok ? gc : 0;
+  // column role: halo columns lane + 64 k of the strip, k < CPL
+  bool cok[CPL];
+  int gcs[CPL];
+#pragma unroll
+  for (int k = 0; k < CPL; ++k) {
+    const int gc = c0 - r + lane + kGfLanes * k;
+    cok[k] = gc >= 0 && gc < g.cols;
+    gcs[k] = cok[k] ? gc : 0;
+  }
   // run role: group j, output columns [run * L, run * L + L) of the strip
   const int L = (ow + R - 1) / R;
   const int j = lane / R, run = lane - (lane / R) * R;
@@ -79,29 +87,32 @@ __global__ void __launch_bounds__(kGfLanes) gf_box_kernel(P p, GfGeom g) {
   int nout = ow - cb < L ? ow - cb : L;
   if (c0 + cb + nout > g.cols) nout = (int)(g.cols - c0 - cb);
   if (nout < 0) nout = 0;
-  double rh[M], srh[M];  // L <= ceil(62 M / 64) = M outputs per lane
+  double rh[NO], srh[NO];  // L <= ceil((64 CPL - 2) M / 64) <= M CPL outputs per lane
 #pragma unroll
-  for (int t = 0; t < M; ++t) {
+  for (int t = 0; t < NO; ++t) {
     rh[t] = 1.0 / (double)win_count(c0 + cb + t, g.cols, r);
     srh[t] = sqrt(rh[t]);
   }
 
-  double s[2 * M];
+  double s[CPL][2 * M];
 #pragma unroll
-  for (int c = 0; c < 2 * M; ++c) s[c] = 0.0;
+  for (int k = 0; k < CPL; ++k)
+#pragma unroll
+    for (int c = 0; c < 2 * M; ++c) s[k][c] = 0.0;
   auto clamp_row = [&](int y) { return y < 0 ? 0 : (y >= g.rows ? g.rows - 1 : y); };
   const int w0 = y0 - r < 0 ? 0 : y0 - r;
   const int w1 = y0 + r - 1 < g.rows - 1 ? y0 + r - 1 : g.rows - 1;
-  {
-    Row cur = p.fetch(clamp_row(w0) * g.cols + gcs);
+#pragma unroll
+  for (int k = 0; k < CPL; ++k) {
+    Row cur = p.fetch(clamp_row(w0) * g.cols + gcs[k]);
     for (int yy = w0; yy <= w1; ++yy) {
-      const Row nxt = p.fetch(clamp_row(yy + 1) * g.cols + gcs);
-      if (cok) {
+      const Row nxt = p.fetch(clamp_row(yy + 1) * g.cols + gcs[k]);
+      if (cok[k]) {
 #pragma unroll
         for (int q = 0; q < M; ++q) {
           const double2 v = p.value(cur, q);
-          s[2 * q] += v.x;
-          s[2 * q + 1] += v.y;
+          s[k][2 * q] += v.x;
+          s[k][2 * q + 1] += v.y;
         }
       }
       cur = nxt;
@@ -110,15 +121,18 @@ __global__ void __launch_bounds__(kGfLanes) gf_box_kernel(P p, GfGeom g) {
   // ring of the entering / leaving points of the next D output rows
   constexpr int D = M <= 2 ? 4 : (M == 4 ? 2 : 1);
   // and of the epilogue's loads at the output points, the same D rows ahead
-  Row fa[D], fd[D];
-  Epi ep[D][M];
+  Row fa[D][CPL], fd[D][CPL];
+  Epi ep[D][NO];
   auto out_col = [&](int t) { return t < nout ? c0 + cb + t : c0; };
 #pragma unroll
   for (int u = 0; u < D; ++u) {
-    fa[u] = p.fetch(clamp_row(y0 + u + r) * g.cols + gcs);
-    fd[u] = p.fetch(clamp_row(y0 + u - r) * g.cols + gcs);
 #pragma unroll
-    for (int t = 0; t < M; ++t) ep[u][t] = p.pre(clamp_row(y0 + u) * g.cols + out_col(t), j);
+    for (int k = 0; k < CPL; ++k) {
+      fa[u][k] = p.fetch(clamp_row(y0 + u + r) * g.cols + gcs[k]);
+      fd[u][k] = p.fetch(clamp_row(y0 + u - r) * g.cols + gcs[k]);
+    }
+#pragma unroll
+    for (int t = 0; t < NO; ++t) ep[u][t] = p.pre(clamp_row(y0 + u) * g.cols + out_col(t), j);
   }
   // The body runs for every u, also past the workgroup's last row in the final
   // group (only the stores are skipped there): a ring slot refilled on some
@@ -129,22 +143,27 @@ __global__ void __launch_bounds__(kGfLanes) gf_box_kernel(P p, GfGeom g) {
       const int yo = yb + u;
       const bool live = yo < y1;
       const int ya = yo + r, yd = yo - r;
-      Epi e[M];
+      Epi e[NO];
 #pragma unroll
-      for (int t = 0; t < M; ++t) {
+      for (int t = 0; t < NO; ++t) {
         e[t] = ep[u][t];
         ep[u][t] = p.pre(clamp_row(yo + D) * g.cols + out_col(t), j);
       }
-      const bool add = cok && ya < g.rows;
 #pragma unroll
-      for (int q = 0; q < M; ++q) {
-        const double2 v = p.value(fa[u], q);
-        s[2 * q] += add ? v.x : 0.0;
-        s[2 * q + 1] += add ? v.y : 0.0;
+      for (int k = 0; k < CPL; ++k) {
+        const bool add = cok[k] && ya < g.rows;
+#pragma unroll
+        for (int q = 0; q < M; ++q) {
+          const double2 v = p.value(fa[u][k], q);
+          s[k][2 * q] += add ? v.x : 0.0;
+          s[k][2 * q + 1] += add ? v.y : 0.0;
+        }
       }
       wave_lds_fence();
 #pragma unroll
-      for (int c = 0; c < 2 * M; ++c) vs[c][lane] = cok ? s[c] : 0.0;
+      for (int k = 0; k < CPL; ++k)
+#pragma unroll
+        for (int c = 0; c < 2 * M; ++c) vs[c][lane + kGfLanes * k] = cok[k] ? s[k][c] : 0.0;
       wave_lds_fence();
       const int vc = (ya < g.rows ? ya : g.rows - 1) - (yd < 0 ? 0 : yd) + 1;
       const double rv = 1.0 / (double)vc, srv = sqrt(rv);
@@ -157,7 +176,7 @@ __global__ void __launch_bounds__(kGfLanes) gf_box_kernel(P p, GfGeom g) {
           a1 += v1[h];
         }
 #pragma unroll
-        for (int t = 0; t < M; ++t) {
+        for (int t = 0; t < NO; ++t) {
           if (t < nout) {
             a0 += v0[t + 2 * r];
             a1 += v1[t + 2 * r];
@@ -168,15 +187,18 @@ __global__ void __launch_bounds__(kGfLanes) gf_box_kernel(P p, GfGeom g) {
         }
       }
       wave_lds_fence();
-      const bool sub = cok && yd >= 0;
 #pragma unroll
-      for (int q = 0; q < M; ++q) {
-        const double2 v = p.value(fd[u], q);
-        s[2 * q] -= sub ? v.x : 0.0;
-        s[2 * q + 1] -= sub ? v.y : 0.0;
+      for (int k = 0; k < CPL; ++k) {
+        const bool sub = cok[k] && yd >= 0;
+#pragma unroll
+        for (int q = 0; q < M; ++q) {
+          const double2 v = p.value(fd[u][k], q);
+          s[k][2 * q] -= sub ? v.x : 0.0;
+          s[k][2 * q + 1] -= sub ? v.y : 0.0;
+        }
+        fa[u][k] = p.fetch(clamp_row(ya + D) * g.cols + gcs[k]);
+        fd[u][k] = p.fetch(clamp_row(yd + D) * g.cols + gcs[k]);
       }
-      fa[u] = p.fetch(clamp_row(ya + D) * g.cols + gcs);
-      fd[u] = p.fetch(clamp_row(yd + D) * g.cols + gcs);
     }
   }
 }
@@ -307,18 +329,28 @@ struct GfStats {
 
 // Rows per workgroup: as many as possible (the 2r warm-up rows are amortised)
 // while the grid still has about 2048 waves to hide memory latency.
+template <int CPL>
 GfGeom gf_geom(const Operator& op) {
-  const int ow = kGfLanes - 2 * op.desc.radius;
+  const int ow = kGfLanes * CPL - 2 * op.desc.radius;
   const int64_t strips = (op.cols + ow - 1) / ow;
   int64_t rb = (op.rows * strips + 2047) / 2048;
   rb = rb < 8 ? 8 : (rb > kGfRowsMax ? kGfRowsMax : rb);
   return GfGeom{(int)op.rows, (int)op.cols, op.desc.radius, (int)rb};
 }
 
+template <int CPL>
 dim3 gf_grid(const Operator& op, const GfGeom& g) {
-  const int ow = kGfLanes - 2 * op.desc.radius;
+  const int ow = kGfLanes * CPL - 2 * op.desc.radius;
   return dim3((unsigned)((op.cols + ow - 1) / ow), (unsigned)((op.rows + g.rb - 1) / g.rb));
 }
+
+// Columns per lane: two for the one-column passes (half the LDS reads and
+// horizontal adds per output, and a 1/(64 - r) instead of 2r/(64 - 2r) halo
+// share), one for blocks, whose lanes already produce M outputs each.
+template <int M>
+struct GfCpl {
+  static constexpr int v = M == 1 ? 2 : 1;
+};
 
 double gf_omega(const Operator& op) {
   const double w = 2.0 * op.desc.radius + 1.0;
@@ -328,16 +360,18 @@ double gf_omega(const Operator& op) {
 template <typename T, int M>
 void gf_apply_group(const Operator& op, T* ab, int form, const T* x, int64_t ldx, T* y, int64_t ldy,
                     hipStream_t s) {
-  const GfGeom geo = gf_geom(op);
+  constexpr int C = GfCpl<M>::v;
+  const GfGeom geo = gf_geom<C>(op);
+  const dim3 grid = gf_grid<C>(op, geo);
   if (form == GSF_FORM_RW || form == GSF_FORM_L) {
     GfStage1<T, M, false> p1{x, (int)ldx, (const T*)op.g, nullptr, (const T*)op.mu, (const T*)op.inv, ab};
-    gf_box_kernel<GfStage1<T, M, false>><<<gf_grid(op, geo), kGfLanes, 0, s>>>(p1, geo);
+    gf_box_kernel<GfStage1<T, M, false>, C><<<grid, kGfLanes, 0, s>>>(p1, geo);
   } else {
     GfStage1<T, M, true> p1{x, (int)ldx, (const T*)op.g, (const T*)op.diag, (const T*)op.mu, (const T*)op.inv, ab};
-    gf_box_kernel<GfStage1<T, M, true>><<<gf_grid(op, geo), kGfLanes, 0, s>>>(p1, geo);
+    gf_box_kernel<GfStage1<T, M, true>, C><<<grid, kGfLanes, 0, s>>>(p1, geo);
   }
   GfStage2<T, M> p2{ab, (const T*)op.g, x, (int)ldx, y, (int)ldy, form, 1.0 / sqrt(gf_omega(op))};
-  gf_box_kernel<GfStage2<T, M>><<<gf_grid(op, geo), kGfLanes, 0, s>>>(p2, geo);
+  gf_box_kernel<GfStage2<T, M>, C><<<grid, kGfLanes, 0, s>>>(p2, geo);
 }
 
 template <typename T>
@@ -376,15 +410,16 @@ gsf_status launch_gf_apply(const Operator& op, void* scratch, int form, int m, c
 }
 
 gsf_status launch_gf_build(const Operator& op, const void* guidance, hipStream_t s) {
-  const GfGeom geo = gf_geom(op);
+  const GfGeom geo = gf_geom<2>(op);
+  const dim3 grid = gf_grid<2>(op, geo);
   if (op.desc.prec == GSF_F32) {
     GfStats<float> p{(const float*)guidance, (float*)op.g, (float*)op.mu, (float*)op.inv,
                      (float*)op.sqd, (float*)op.diag, op.deg, op.desc.gf_eps, gf_omega(op)};
-    gf_box_kernel<GfStats<float>><<<gf_grid(op, geo), kGfLanes, 0, s>>>(p, geo);
+    gf_box_kernel<GfStats<float>, 2><<<grid, kGfLanes, 0, s>>>(p, geo);
   } else {
     GfStats<double> p{(const double*)guidance, (double*)op.g, (double*)op.mu, (double*)op.inv,
                       (double*)op.sqd, (double*)op.diag, op.deg, op.desc.gf_eps, gf_omega(op)};
-    gf_box_kernel<GfStats<double>><<<gf_grid(op, geo), kGfLanes, 0, s>>>(p, geo);
+    gf_box_kernel<GfStats<double>, 2><<<grid, kGfLanes, 0, s>>>(p, geo);
   }
   return launch_status();
 }
