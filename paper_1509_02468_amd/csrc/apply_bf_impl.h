@@ -99,6 +99,16 @@ __device__ __forceinline__ void out_col(const ApplyArgs& a, int64_t p, int c, T 
     ((T*)a.y)[p * a.ldy + c] = v;
 }
 // the column whose x . y partial the kernel reports (m = 1, or the joint column)
+// FP32 windows wider than 11 x 11 (R >= 6, up to 289 terms per point): each
+// window row is summed in FP32 and the rows' sums in FP64, so that the sum's
+// rounding does not grow with the window (one sequential FP32 sum of 2K
+// sign-alternating terms reaches about 1e-5 of N x at R = 8); narrower windows
+// and FP64 data sum in the data type.
+template <typename T, int R>
+struct RowSums {
+  static constexpr bool on = R >= 6 && sizeof(T) == 4;
+};
+
 template <int M, int M2>
 struct DotCol {
   static constexpr bool on = M == 1 || M2 > 0;
@@ -155,11 +165,22 @@ __global__ void __launch_bounds__(kThreads) bf_apply2d_kernel(ApplyArgs a) {
     const int64_t p = valid ? gy * W + gx : 0;
     const T* uc = &us[((ly + R) * LW + tx + R) * M];
     T ui[M], acc[M];
+    double dacc[M];  // RowSums<T, R>: the FP64 total of the window rows' sums
 #pragma unroll
     for (int c = 0; c < M; ++c) {
       ui[c] = uc[c];
       acc[c] = T(0);
+      dacc[c] = 0.0;
     }
+    auto flush = [&]() {
+      if constexpr (RowSums<T, R>::on) {
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+          dacc[c] += (double)acc[c];
+          acc[c] = T(0);
+        }
+      }
+    };
     // byte offsets of this point in a padded plane (unsigned 32-bit, from a
     // uniform plane base)
     const uint32_t pv = ((uint32_t)p + (uint32_t)a.ppad) * (uint32_t)sizeof(T);
@@ -179,6 +200,7 @@ __global__ void __launch_bounds__(kThreads) bf_apply2d_kernel(ApplyArgs a) {
         acc[c] = fma(wm, ui[c] - um[c], acc[c]);
       }
     }
+    flush();
     // dy = 1..R, dx = -R..R: one row of 2R+1 planes per dy
 #pragma unroll 1
     for (int dy = 1; dy <= R; ++dy) {
@@ -198,6 +220,11 @@ __global__ void __launch_bounds__(kThreads) bf_apply2d_kernel(ApplyArgs a) {
           acc[c] = fma(wm, ui[c] - um[c], acc[c]);
         }
       }
+      flush();
+    }
+    if constexpr (RowSums<T, R>::on) {
+#pragma unroll
+      for (int c = 0; c < M; ++c) acc[c] = (T)dacc[c];
     }
     if (valid) {
       T xg[M], out[M];
@@ -279,13 +306,29 @@ __global__ void __launch_bounds__(32 * TY) bf_apply2d_pair_kernel(ApplyArgs a) {
   // carry a zero weight.
   T u0[M], u1[M], acc0[M], acc1[M];
   T sw1 = T(0);
+  double d0[M], d1[M], dsw1 = 0.0;  // RowSums<T, R>: FP64 totals of the rows' sums
 #pragma unroll
   for (int c = 0; c < M; ++c) {
     u0[c] = c0[c];
     u1[c] = c0[LW * M + c];
     acc0[c] = T(0);
     acc1[c] = T(0);
+    d0[c] = 0.0;
+    d1[c] = 0.0;
   }
+  auto flush = [&]() {
+    if constexpr (RowSums<T, R>::on) {
+#pragma unroll
+      for (int c = 0; c < M; ++c) {
+        d0[c] += (double)acc0[c];
+        d1[c] += (double)acc1[c];
+        acc0[c] = T(0);
+        acc1[c] = T(0);
+      }
+      dsw1 += (double)sw1;
+      sw1 = T(0);
+    }
+  };
   // A row of the window: the weights of both points are loaded first (one
   // uniform plane pointer per offset plus the lane's 32-bit byte offset),
   // then the LDS neighbour row is consumed.  The empty asm makes the byte
@@ -350,13 +393,17 @@ __global__ void __launch_bounds__(32 * TY) bf_apply2d_pair_kernel(ApplyArgs a) {
   // (71 VGPRs for 4 FP32 columns, radius 5).
   // row -R: point 0 only, mirrored: plane q(R, -dx) at p0 - R W + dx
   row(c0 - R * LW * M, qrow(R), qb, pv0 - (uint32_t)R * wb, 0u, Y{}, N{}, MIR{}, MIR{});
+  flush();
   // row R + 1: point 1 only, own q(R, dx) at p1
   row(c0 + (R + 1) * LW * M, qb, qrow(R), 0u, pv1, N{}, Y{}, OWN{}, OWN{});
+  flush();
 
   // row 0 (point 0's): point 0 split at p0; point 1 mirrored, plane q(1, -dx) at p0 + dx
   row(c0, qb, qrow(1), pv0, pv0, Y{}, Y{}, SPL{}, MIR{});
+  flush();
   // row 1 (point 1's): point 0 own q(1, dx) at p0; point 1 split at p1
   row(c0 + LW * M, qrow(1), qb, pv0, pv1, Y{}, Y{}, OWN{}, SPL{});
+  flush();
   // (one row per step of the loop, which keeps one row's weights live)
 #pragma unroll 1
   for (int j = 0; j < 2 * (R - 1); ++j) {
@@ -369,11 +416,20 @@ __global__ void __launch_bounds__(32 * TY) bf_apply2d_pair_kernel(ApplyArgs a) {
       // row k + 1: both own, planes q(k + 1, dx) at p0 and q(k, dx) at p1
       row(c0 + (k + 1) * LW * M, qrow(k + 1), qrow(k), pv0, pv1, Y{}, Y{}, OWN{}, OWN{});
     }
+    flush();
   }
+  if constexpr (RowSums<T, R>::on) {
 #pragma unroll
-  for (int c = 0; c < M; ++c) {
-    acc0[c] = -acc0[c];
-    acc1[c] = fma(u1[c] - u0[c], sw1, -acc1[c]);
+    for (int c = 0; c < M; ++c) {
+      acc0[c] = (T)(-d0[c]);
+      acc1[c] = (T)fma((double)(u1[c] - u0[c]), dsw1, -d1[c]);
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+      acc0[c] = -acc0[c];
+      acc1[c] = fma(u1[c] - u0[c], sw1, -acc1[c]);
+    }
   }
   double dotv = 0.0;
 #pragma unroll

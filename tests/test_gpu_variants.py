@@ -39,13 +39,15 @@ def _round(x, prec, gsf):
 
 
 # (shape, seed, radius, sigma_d, sigma_r, stencil, norm): several tiles and
-# ragged tails; radius 1 is the 5-point stencil
+# ragged tails; radius 1 is the 5-point stencil, radius 8 the largest window
 CASES = [
     ((67, 130), 41, 1, 1.0, 0.1, "cross", "diagl"),
     ((67, 130), 42, 1, 1.0, 0.1, "cross", "d"),
     ((33, 200), 43, 3, 2.0, 0.15, "cross", "diagl"),
     ((70, 131), 44, 2, 2.0, 0.1, "square", "diagl"),
     ((3000,), 45, 4, 3.0, 0.2, "cross", "diagl"),
+    ((40, 150), 46, 8, 4.0, 0.2, "square", "d"),      # the largest window: widest LDS halo
+    ((45, 100), 47, 8, 4.0, 0.2, "cross", "diagl"),
 ]
 
 
