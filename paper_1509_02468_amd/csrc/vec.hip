@@ -490,9 +490,18 @@ gsf_status launch_cg_update(const Operator& op, void* z, void* r, const void* p,
   return launch_status();
 }
 
+// Workgroups of the fused CG step kernels: each of them first reduces all of
+// the previous kernel's partials itself (the apply's, or the update's), so
+// their count multiplies those redundant reads; 512 workgroups still stream
+// the vectors at full bandwidth.
+int cg_step_blocks(int64_t n) {
+  const int nb = vec_blocks(n);
+  return nb < 512 ? nb : 512;
+}
+
 gsf_status launch_cg_pbeta(const Operator& op, const void* r, void* p, const double* upd, CgState* st, int k,
                            hipStream_t s) {
-  const int nb = vec_blocks(op.n);
+  const int nb = cg_step_blocks(op.n);
   if (op.desc.prec == GSF_F32)
     cg_pbeta_kernel<float><<<nb, kThreads, 0, s>>>((const float*)r, (float*)p, op.n, upd, nb, st, k);
   else
@@ -502,7 +511,7 @@ gsf_status launch_cg_pbeta(const Operator& op, const void* r, void* p, const dou
 
 gsf_status launch_cg_aupdate(const Operator& op, void* z, void* r, const void* p, const void* q, const double* dots,
                              int ndots, double* upd, CgState* st, int k, hipStream_t s) {
-  const int nb = vec_blocks(op.n);
+  const int nb = cg_step_blocks(op.n);
   if (op.desc.prec == GSF_F32)
     cg_aupdate_kernel<float><<<nb, kThreads, 0, s>>>((float*)z, (float*)r, (const float*)p, (const float*)q, op.n,
                                                      dots, ndots, upd, st, k);
@@ -513,7 +522,7 @@ gsf_status launch_cg_aupdate(const Operator& op, void* z, void* r, const void* p
 }
 
 gsf_status launch_cg_close(const Operator& op, const double* upd, CgState* st, hipStream_t s) {
-  cg_close_kernel<<<1, kThreads, 0, s>>>(upd, vec_blocks(op.n), st);
+  cg_close_kernel<<<1, kThreads, 0, s>>>(upd, cg_step_blocks(op.n), st);
   return launch_status();
 }
 
