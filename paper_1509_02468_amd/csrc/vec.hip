@@ -24,7 +24,7 @@ __global__ void __launch_bounds__(kThreads) scale_kernel(const T* __restrict__ i
 // r holds L_sym z on entry; r <- -L_sym z; state <- rho0, breakdown floor.
 template <typename T>
 __global__ void __launch_bounds__(kThreads) cg_init_kernel(const T* __restrict__ z, T* __restrict__ r, int64_t n,
-                                                           double* __restrict__ partials, CgState* st) {
+                                                           double* __restrict__ partials, CgState*) {
   __shared__ double red[32];
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   double v[2] = {0.0, 0.0};
