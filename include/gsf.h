@@ -184,9 +184,9 @@ int gsf_version(void);
 const char* gsf_status_string(int status);
 /* gsf_last_device_error: the HIP error code (hipError_t) behind the calling
  * thread's latest GSF_EDEVICE, 0 if there was none since the last query;
- * the query resets it.  A kernel launch is checked with hipGetLastError, so a
- * failed HIP call that the caller made earlier in the thread and left
- * unchecked is reported by the library's next launch check.
+ * the query resets it.  Kernel launches are checked with hipGetLastError;
+ * every call that takes a stream first drops an error that earlier HIP calls
+ * of other code left in the thread, so it reports only its own failures.
  * gsf_device_error_string: HIP's text for such a code. */
 int gsf_last_device_error(void);
 const char* gsf_device_error_string(int code);

@@ -501,6 +501,7 @@ gsf_status gsf_operator_workspace_bytes(const gsf_operator_desc* desc, size_t* b
 
 gsf_status gsf_build_operator(const gsf_operator_desc* desc, const void* guidance, void* ws, size_t ws_bytes,
                               void* stream, gsf_operator** out) {
+  clear_stale_errors();
   if (out == nullptr || guidance == nullptr || ws == nullptr) return GSF_EINVAL;
   GSF_TRY(validate_desc(desc));
   if (ws_bytes < layout_operator(desc, nullptr, nullptr)) return GSF_ENOMEM;
@@ -541,6 +542,7 @@ gsf_status gsf_operator_get_layout(const gsf_operator* h, gsf_operator_layout* o
 void gsf_destroy_operator(gsf_operator* h) { delete h; }
 
 gsf_status gsf_apply(const gsf_operator* h, int form, int m, const void* x, void* y, void* stream) {
+  clear_stale_errors();
   if (h == nullptr || x == nullptr || y == nullptr) return GSF_EINVAL;
   if (form != GSF_FORM_N && form != GSF_FORM_LSYM && form != GSF_FORM_RW && form != GSF_FORM_L) return GSF_EINVAL;
   if (m < 1 || m > kMaxBlock) return GSF_EINVAL;
@@ -553,6 +555,7 @@ gsf_status gsf_apply(const gsf_operator* h, int form, int m, const void* x, void
 
 gsf_status gsf_apply_joint(const gsf_operator* h, int form, int m, const void* x, void* y, const void* x2, void* y2,
                            void* stream) {
+  clear_stale_errors();
   if (h == nullptr || x == nullptr || y == nullptr || x2 == nullptr || y2 == nullptr) return GSF_EINVAL;
   if (form != GSF_FORM_N && form != GSF_FORM_LSYM && form != GSF_FORM_RW && form != GSF_FORM_L) return GSF_EINVAL;
   if (m < 1 || m > kMaxBlock) return GSF_EINVAL;
@@ -596,6 +599,7 @@ gsf_status gsf_solver_workspace_bytes(const gsf_operator* h, int method, int m, 
 
 gsf_status gsf_power_filter(const gsf_operator* h, const void* x0, void* x_out, int kmax, void* ws,
                             size_t ws_bytes, void* stream) {
+  clear_stale_errors();
   if (h == nullptr || x0 == nullptr || x_out == nullptr || kmax < 0) return GSF_EINVAL;
   const Operator& op = h->op;
   const size_t v = align_up((size_t)op.n * op.elem, 256);
@@ -616,6 +620,7 @@ gsf_status gsf_power_filter(const gsf_operator* h, const void* x0, void* x_out, 
 
 gsf_status gsf_power_filter_block(const gsf_operator* h, int m, const void* x0, void* x_out, int kmax, void* ws,
                                   size_t ws_bytes, void* stream) {
+  clear_stale_errors();
   if (h == nullptr || x0 == nullptr || x_out == nullptr || kmax < 0 || m < 1 || m > kMaxBlock) return GSF_EINVAL;
   const Operator& op = h->op;
   const size_t v = align_up((size_t)op.n * m * op.elem, 256);
@@ -637,6 +642,7 @@ gsf_status gsf_power_filter_block(const gsf_operator* h, int m, const void* x0, 
 
 gsf_status gsf_cg_filter_block(const gsf_operator* h, int m, const void* x0, void* x_out, int kmax, double tol,
                                void* ws, size_t ws_bytes, gsf_cg_info* info, void* stream) {
+  clear_stale_errors();
   if (h == nullptr || x0 == nullptr || x_out == nullptr || kmax < 0 || !(tol >= 0.0) || !std::isfinite(tol))
     return GSF_EINVAL;
   if (m < 1 || m > kMaxBlock) return GSF_EINVAL;
@@ -684,6 +690,7 @@ gsf_status gsf_cg_filter_block(const gsf_operator* h, int m, const void* x0, voi
 }
 
 gsf_status gsf_srgb_to_lab(int prec, int64_t n, const void* rgb, void* lab, void* stream) {
+  clear_stale_errors();
   if (n < 0 || (prec != GSF_F32 && prec != GSF_F64)) return GSF_EINVAL;
   if (n == 0) return GSF_OK;
   if (rgb == nullptr || lab == nullptr) return GSF_EINVAL;
@@ -881,6 +888,7 @@ struct LobRun {
 
 gsf_status gsf_cg_filter(const gsf_operator* h, const void* x0, void* x_out, int kmax, double tol, void* ws,
                          size_t ws_bytes, gsf_cg_info* info, void* stream) {
+  clear_stale_errors();
   if (h == nullptr || x0 == nullptr || x_out == nullptr || kmax < 0 || !(tol >= 0.0) || !std::isfinite(tol))
     return GSF_EINVAL;
   const Operator& op = h->op;
@@ -914,6 +922,7 @@ gsf_status gsf_cg_filter(const gsf_operator* h, const void* x0, void* x_out, int
 gsf_status gsf_lobpcg_filter(const gsf_operator* h, const void* x0, void* x_out, int m, int kmax, double tol,
                              int constraint, const gsf_precond* T, void* ritz_vecs, void* ws, size_t ws_bytes,
                              gsf_lobpcg_info* info, void* stream) {
+  clear_stale_errors();
   if (h == nullptr || x0 == nullptr || x_out == nullptr || kmax < 0 || !(tol >= 0.0) || !std::isfinite(tol))
     return GSF_EINVAL;
   if (m < 1 || m > kMaxBlock) return GSF_EINVAL;
@@ -977,6 +986,7 @@ gsf_status gsf_joint_workspace_bytes(const gsf_operator* h, int m, size_t* bytes
 gsf_status gsf_joint_filter(gsf_operator* h, const void* x0_cg, void* x_cg, int kmax_cg, const void* x0_lob,
                             void* x_lob, int m, int kmax_lob, int constraint, void* ws, size_t ws_bytes,
                             gsf_cg_info* cg_info, gsf_lobpcg_info* lob_info, void* stream) {
+  clear_stale_errors();
   if (h == nullptr || x0_cg == nullptr || x_cg == nullptr || x0_lob == nullptr || x_lob == nullptr)
     return GSF_EINVAL;
   if (kmax_cg < 0 || kmax_lob < 0 || m < 1 || m > kMaxBlock) return GSF_EINVAL;
@@ -1052,6 +1062,7 @@ gsf_status gsf_reguided_workspace_bytes(const gsf_operator_desc* desc, int metho
 
 gsf_status gsf_reguided_filter(const gsf_operator_desc* desc, int method, const void* x0, void* x_out, int kmax,
                                double tol, void* ws, size_t ws_bytes, gsf_cg_info* info, void* stream) {
+  clear_stale_errors();
   if (x0 == nullptr || x_out == nullptr || kmax < 0 || !(tol >= 0.0) || !std::isfinite(tol)) return GSF_EINVAL;
   if (method != GSF_METHOD_POWER && method != GSF_METHOD_CG) return GSF_EINVAL;
   GSF_TRY(validate_desc(desc));
@@ -1152,6 +1163,7 @@ gsf_status gsf_reguided_filter(const gsf_operator_desc* desc, int method, const 
 // host arrays GA, GB (ns x ns, ns = nb*m).  Synchronizes the stream.
 gsf_status gsf_block_gram(int prec, int64_t n, int m, int nb, const void* const* S, const void* const* AS,
                           double* GA, double* GB, void* ws, size_t ws_bytes, void* stream) {
+  clear_stale_errors();
   if (n < 1 || m < 1 || m > 8 || nb < 1 || nb > 3 || S == nullptr || AS == nullptr || GA == nullptr ||
       GB == nullptr)
     return GSF_EINVAL;
@@ -1214,6 +1226,7 @@ gsf_status gsf_block_gram_workspace_bytes(int64_t n, size_t* bytes) {
 gsf_status gsf_rayleigh_ritz(int ns, int m, const double* GA, const double* GB, double drop_tol, double zero_tol,
                              double* theta, double* C, int* kept, int* nkept, void* ws, size_t ws_bytes,
                              void* stream) {
+  clear_stale_errors();
   if (ns < 1 || ns > 24 || m < 1 || m > 8 || m > ns || !GA || !GB || !theta || !C || !kept || !nkept)
     return GSF_EINVAL;
   if (ws == nullptr || ws_bytes < 8192 + 4096) return GSF_ENOMEM;
@@ -1243,6 +1256,7 @@ size_t gsf_rr_workspace_bytes(void) { return 8192 + 4096; }
 
 gsf_status gsf_tune_apply(const gsf_operator* h, int m, const void* x, void* y, int reps, int* best_rpt,
                           float* times_us, void* stream) {
+  clear_stale_errors();
   if (h == nullptr || x == nullptr || y == nullptr || m < 1 || m > kMaxBlock || reps < 1) return GSF_EINVAL;
   const Operator& op = h->op;
   const int w = m >= 8 ? 8 : (m >= 4 ? 4 : m);
@@ -1288,6 +1302,7 @@ gsf_status gsf_tune_apply(const gsf_operator* h, int m, const void* x, void* y, 
 
 gsf_status gsf_shifted_cg(const gsf_operator* h, double alpha, const void* b, int64_t ldb, void* y, int kmax,
                           double tol, void* ws, size_t ws_bytes, gsf_cg_info* info, void* stream) {
+  clear_stale_errors();
   if (h == nullptr || b == nullptr || y == nullptr || ldb < 1 || kmax < 0 || !(alpha >= 0.0) ||
       !std::isfinite(alpha) || !(tol >= 0.0) || !std::isfinite(tol))
     return GSF_EINVAL;
@@ -1325,6 +1340,7 @@ gsf_status gsf_shifted_cg(const gsf_operator* h, double alpha, const void* b, in
 
 gsf_status gsf_lobpcg_residual(const gsf_operator* h, int m, const void* X, const double* theta, void* R,
                                void* stream) {
+  clear_stale_errors();
   if (h == nullptr || X == nullptr || theta == nullptr || R == nullptr || m < 1 || m > kMaxBlock) return GSF_EINVAL;
   const Operator& op = h->op;
   hipStream_t s = (hipStream_t)stream;

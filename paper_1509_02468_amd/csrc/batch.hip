@@ -233,6 +233,7 @@ gsf_status gsf_batch_create(const gsf_batch_item* items, int count, void* ws, si
 }
 
 gsf_status gsf_batch_run(gsf_batch* b, void* stream) {
+  clear_stale_errors();
   if (b == nullptr) return GSF_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   if (hipEventRecord(b->fork, s) != hipSuccess) return GSF_EDEVICE;
@@ -255,6 +256,7 @@ gsf_status gsf_batch_run(gsf_batch* b, void* stream) {
 }
 
 gsf_status gsf_batch_get_info(const gsf_batch* b, gsf_batch_info* info, void* stream) {
+  clear_stale_errors();
   if (b == nullptr || info == nullptr) return GSF_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   const int count = (int)b->items.size();

@@ -109,6 +109,10 @@ __device__ __forceinline__ int xcd_tile(int b, int ntiles) {
 // gsf_last_device_error) and of the launches so far in this thread.
 gsf_status device_status(hipError_t e);
 inline gsf_status launch_status() { return device_status(hipGetLastError()); }
+// Drops a HIP error that other code left in this thread (the runtime keeps
+// the last failed call's error until hipGetLastError reads it), so that the
+// launch checks of a call report only that call's own launches.
+inline void clear_stale_errors() { (void)hipGetLastError(); }
 
 // ---------------------------------------------------------------------------
 // launchers (implemented in the .hip files)

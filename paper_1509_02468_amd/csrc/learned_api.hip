@@ -47,6 +47,7 @@ gsf_status gsf_net_workspace_bytes(int batch, int64_t rows, int64_t cols, size_t
 
 gsf_status gsf_net_forward(const uint16_t* w, int batch, const int32_t* idx, int64_t rows, int64_t cols,
                            const float* inputs, float* y, void* ws, size_t ws_bytes, void* stream) {
+  clear_stale_errors();
   if (w == nullptr || idx == nullptr || inputs == nullptr || y == nullptr || batch < 1 || rows < 1 || cols < 1)
     return GSF_EINVAL;
   if (ws == nullptr || ws_bytes < net_train_bytes(batch, rows * cols)) return GSF_ENOMEM;
@@ -57,6 +58,7 @@ gsf_status gsf_net_forward(const uint16_t* w, int batch, const int32_t* idx, int
 gsf_status gsf_net_loss_grad(const uint16_t* w, int batch, const int32_t* idx, int64_t rows, int64_t cols,
                              const float* inputs, const float* targets, float* grad, double* loss, void* ws,
                              size_t ws_bytes, void* stream) {
+  clear_stale_errors();
   if (w == nullptr || idx == nullptr || inputs == nullptr || targets == nullptr || grad == nullptr ||
       loss == nullptr || batch < 1 || rows < 1 || cols < 1)
     return GSF_EINVAL;
@@ -67,6 +69,7 @@ gsf_status gsf_net_loss_grad(const uint16_t* w, int batch, const int32_t* idx, i
 
 gsf_status gsf_net_adam(int64_t count, int t, double lr, double beta1, double beta2, double eps, float* w, float* mom,
                         float* vel, const float* grad, uint16_t* w_bf16, void* stream) {
+  clear_stale_errors();
   if (count < 1 || t < 1 || w == nullptr || mom == nullptr || vel == nullptr || grad == nullptr ||
       w_bf16 == nullptr || !(lr > 0.0) || !(beta1 >= 0.0 && beta1 < 1.0) || !(beta2 >= 0.0 && beta2 < 1.0) ||
       !(eps > 0.0))
@@ -75,6 +78,7 @@ gsf_status gsf_net_adam(int64_t count, int t, double lr, double beta1, double be
 }
 
 gsf_status gsf_net_to_bf16(int64_t count, const float* w, uint16_t* w_bf16, void* stream) {
+  clear_stale_errors();
   if (count < 1 || w == nullptr || w_bf16 == nullptr) return GSF_EINVAL;
   return net_to_bf16(count, w, w_bf16, (hipStream_t)stream);
 }
@@ -87,6 +91,7 @@ gsf_status gsf_net_pair_workspace_bytes(const gsf_operator* op, size_t* bytes) {
 
 gsf_status gsf_net_make_pair(const gsf_operator* h, const void* r, int64_t ldr, const void* y, int64_t ldy,
                              const void* g, float* inputs, float* targets, void* ws, size_t ws_bytes, void* stream) {
+  clear_stale_errors();
   if (h == nullptr || r == nullptr || y == nullptr || g == nullptr || inputs == nullptr || targets == nullptr ||
       ldr < 1 || ldy < 1)
     return GSF_EINVAL;
@@ -126,6 +131,7 @@ gsf_status gsf_precond_workspace_bytes(const gsf_precond* T, int m, size_t* byte
 
 gsf_status gsf_precond_apply(const gsf_precond* T, int m, const void* R, void* W, void* ws, size_t ws_bytes,
                              void* stream) {
+  clear_stale_errors();
   if (T == nullptr || R == nullptr || W == nullptr || m < 1 || m > kMaxBlock) return GSF_EINVAL;
   size_t need = 0;
   gsf_precond_workspace_bytes(T, m, &need);

@@ -84,6 +84,10 @@ def load_library(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with `python -m paper_1509_02468_amd.build`")
+    # torch first: it brings its own HIP runtime, and libgsf must bind to that
+    # same runtime (loaded first, the library's link-time runtime is a second
+    # instance in the process, whose first launch then finds no device)
+    _torch()
     lib = ctypes.CDLL(path)
     vp, sz, i32, i64, dbl = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_int64, ctypes.c_double
     P = ctypes.POINTER
