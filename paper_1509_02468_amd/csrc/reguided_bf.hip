@@ -70,9 +70,12 @@ struct RgPitch {
   static constexpr int v = TW + 2 * kMaxRadius;
 };
 
-template <typename T, int MODE, int TW, int TH, bool BORDER>
+// C > 1 (BUILD only): the guidance has C channels, staged as C LDS planes
+// cplane values apart, and the photometric distance is the Euclidean one.
+template <typename T, int MODE, int TW, int TH, bool BORDER, int C>
 __device__ __forceinline__ void rg_tile(const T* __restrict__ gs, const T* __restrict__ vs, T* __restrict__ y,
-                                        double* __restrict__ deg, double& dotv, const RgParams& p, int x0, int y0) {
+                                        double* __restrict__ deg, double& dotv, const RgParams& p, int x0, int y0,
+                                        int cplane) {
   constexpr int pitch = RgPitch<TW>::v;
   // LDS distance between a thread's consecutive points: 256 / TW rows, or 256
   // columns of one row
@@ -82,6 +85,7 @@ __device__ __forceinline__ void rg_tile(const T* __restrict__ gs, const T* __res
   const int cc = (oy0 + p.ry) * pitch + ox0 + p.rx;  // centre of point 0
   int gyo[kRgPts], gxo[kRgPts];
   T gi[kRgPts], vi[kRgPts];
+  T gic[C][kRgPts];  // C > 1: the point's channels
   double acc[kRgPts], ws[kRgPts];
 #pragma unroll
   for (int t = 0; t < kRgPts; ++t) {
@@ -89,6 +93,8 @@ __device__ __forceinline__ void rg_tile(const T* __restrict__ gs, const T* __res
     gyo[t] = y0 + l / TW;
     gxo[t] = x0 + (l - (l / TW) * TW);
     gi[t] = gs[cc + t * step];
+#pragma unroll
+    for (int c = 0; c < C; ++c) gic[c][t] = gs[c * cplane + cc + t * step];
     vi[t] = MODE == RG_LAP ? vs[cc + t * step] : gi[t];
     acc[t] = 0.0;
     ws[t] = 0.0;
@@ -113,7 +119,16 @@ __device__ __forceinline__ void rg_tile(const T* __restrict__ gs, const T* __res
         const T gj = gq[t * step];
         const T d = gi[t] - gj;
         T w;
-        if constexpr (sizeof(T) == 4) {
+        if constexpr (C > 1) {
+          // sum of the channels' squared differences, kept finite for cr = 0
+          float d2 = 0.0f;
+#pragma unroll
+          for (int c = 0; c < C; ++c) {
+            const float dc = gic[c][t] - gq[c * cplane + t * step];
+            d2 = fmaf(dc, dc, d2);
+          }
+          w = __builtin_amdgcn_exp2f(fmaf(fminf(d2, 3.0e38f), p.ncr2, nsp));
+        } else if constexpr (sizeof(T) == 4) {
           // d (d cr') rather than d^2 cr': with cr = 0 (sigma_r = inf) the
           // term is 0 for any finite d, and a huge d gives 2^-inf = 0
           w = __builtin_amdgcn_exp2f(fmaf(d, d * p.ncr2, nsp));
@@ -163,7 +178,7 @@ __device__ __forceinline__ void rg_tile(const T* __restrict__ gs, const T* __res
   }
 }
 
-template <typename T, int MODE, int TW, int TH>
+template <typename T, int MODE, int TW, int TH, int C = 1>
 __global__ void __launch_bounds__(kRgThreads) rg_bf_kernel(const T* __restrict__ g, const T* __restrict__ v,
                                                            T* __restrict__ y, double* __restrict__ deg,
                                                            double* __restrict__ dot, RgParams p) {
@@ -181,16 +196,21 @@ __global__ void __launch_bounds__(kRgThreads) rg_bf_kernel(const T* __restrict__
     const int gy = y0 - p.ry + ly, gx = x0 - p.rx + lx;
     const bool in = (unsigned)gy < (unsigned)p.rows && (unsigned)gx < (unsigned)p.cols;
     const int i = in ? gy * p.cols + gx : 0;
-    gs[ly * pitch + lx] = in ? g[i] : T(0);
+    if constexpr (C == 1) {
+      gs[ly * pitch + lx] = in ? g[i] : T(0);
+    } else {
+#pragma unroll
+      for (int ch = 0; ch < C; ++ch) gs[ch * pitch * hrows + ly * pitch + lx] = in ? g[(int64_t)i * C + ch] : T(0);
+    }
     if (MODE == RG_LAP) vs[ly * pitch + lx] = in ? v[i] : T(0);
   }
   __syncthreads();
   const bool interior = x0 - p.rx >= 0 && x0 + TW + p.rx <= p.cols && y0 - p.ry >= 0 && y0 + TH + p.ry <= p.rows;
   double dotv = 0.0;
   if (interior)
-    rg_tile<T, MODE, TW, TH, false>(gs, vs, y, deg, dotv, p, x0, y0);
+    rg_tile<T, MODE, TW, TH, false, C>(gs, vs, y, deg, dotv, p, x0, y0, pitch * hrows);
   else
-    rg_tile<T, MODE, TW, TH, true>(gs, vs, y, deg, dotv, p, x0, y0);
+    rg_tile<T, MODE, TW, TH, true, C>(gs, vs, y, deg, dotv, p, x0, y0, pitch * hrows);
   if (MODE == RG_LAP && dot != nullptr) {
     double t[1] = {dotv};
     block_sum<1>(t, red);
@@ -231,14 +251,14 @@ RgGeom rg_geom(const Operator& op, int mode) {
   return g;
 }
 
-template <typename T, int MODE>
+template <typename T, int MODE, int C = 1>
 void rg_launch(const RgGeom& g, const void* gd, const void* v, void* y, double* deg, double* dot, hipStream_t s) {
   if (g.th == 16)
-    rg_bf_kernel<T, MODE, 64, 16><<<g.p.ntiles, kRgThreads, g.lds, s>>>((const T*)gd, (const T*)v, (T*)y, deg, dot,
-                                                                        g.p);
+    rg_bf_kernel<T, MODE, 64, 16, C><<<g.p.ntiles, kRgThreads, g.lds * C, s>>>((const T*)gd, (const T*)v, (T*)y,
+                                                                               deg, dot, g.p);
   else
-    rg_bf_kernel<T, MODE, 1024, 1><<<g.p.ntiles, kRgThreads, g.lds, s>>>((const T*)gd, (const T*)v, (T*)y, deg,
-                                                                         dot, g.p);
+    rg_bf_kernel<T, MODE, 1024, 1, C><<<g.p.ntiles, kRgThreads, g.lds * C, s>>>((const T*)gd, (const T*)v, (T*)y,
+                                                                                deg, dot, g.p);
 }
 
 template <typename T>
@@ -267,12 +287,13 @@ __global__ void __launch_bounds__(kRgThreads) rg_plane_pads_kernel(T* __restrict
 
 }  // namespace
 
-// Operator build of FP32 BF data with one guidance channel in one window
-// pass (the weights of eq. (2) in FP32, the degrees as FP64 sums of exactly
-// the stored values) plus the pad zeros; false (nothing launched) for other
-// descriptors, which take the two-kernel build with FP64 exponentials.
+// Operator build of FP32 BF data with one or three guidance channels in one
+// window pass (the weights of eq. (2) in FP32, the degrees as FP64 sums of
+// exactly the stored values) plus the pad zeros; false (nothing launched) for
+// other descriptors, which take the two-kernel build with FP64 exponentials.
 bool launch_bf_build_onepass(const Operator& op, const void* guidance, hipStream_t s) {
-  if (op.desc.kind != GSF_BF || op.desc.prec != GSF_F32 || desc_channels(op.desc) != 1) return false;
+  const int ch = desc_channels(op.desc);
+  if (op.desc.kind != GSF_BF || op.desc.prec != GSF_F32 || (ch != 1 && ch != 3)) return false;
   RgGeom geo = rg_geom(op, RG_BUILD);
   geo.p.planes = op.planes;
   geo.p.pstride = op.pstride;
@@ -282,7 +303,10 @@ bool launch_bf_build_onepass(const Operator& op, const void* guidance, hipStream
   const int64_t npad = op.pstride - op.n;
   rg_plane_pads_kernel<float><<<(unsigned)((npad + kRgThreads - 1) / kRgThreads), kRgThreads, 0, s>>>(
       (float*)op.planes, op.n, op.pstride, op.ppad, op.nplanes);
-  rg_launch<float, RG_BUILD>(geo, guidance, nullptr, nullptr, op.deg, nullptr, s);
+  if (ch == 3)
+    rg_launch<float, RG_BUILD, 3>(geo, guidance, nullptr, nullptr, op.deg, nullptr, s);  // e.g. CIE-Lab
+  else
+    rg_launch<float, RG_BUILD>(geo, guidance, nullptr, nullptr, op.deg, nullptr, s);
   return true;
 }
 

@@ -72,14 +72,18 @@ CASES = [((67, 130), 31), ((33, 200), 32)]
 @pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("shape,seed", CASES)
 def test_colour_build_parity(gsf, shape, seed, prec):
+    """Planes against the oracle's W of the Lab guidance; degrees as the FP64
+    row sums of exactly the stored weights (own planes and mirrored entries)
+    and against the oracle's d.  FP32 data: the one-pass build's FP32 squared
+    distance and exponential put a weight e^-a within about (4 + 3a) 2^-24 of
+    the oracle's, at most 1e-6 of the largest weight (bound 2e-6)."""
     op, ref, _ = _colour_case(gsf, shape, seed, prec)
     W = ref.W.tocsr()
-    Wst = W.astype(np.float32).astype(np.float64) if prec == gsf.F32 else W
-    np.testing.assert_allclose(op.degree().cpu().numpy(), np.asarray(Wst.sum(axis=1)).ravel(), rtol=1e-13)
     planes = op.planes().cpu().numpy().astype(np.float64)
     r = ref.radius
     offs = [(0, dx) for dx in range(1, r + 1)] + [(dy, dx) for dy in range(1, r + 1) for dx in range(-r, r + 1)]
     coords = np.indices(shape).reshape(2, -1).T
+    d_st = np.ones(ref.n)
     for q, o in enumerate(offs):
         nb = coords + np.array(o)
         inside = np.all((nb >= 0) & (nb < np.array(shape)), axis=1)
@@ -87,7 +91,12 @@ def test_colour_build_parity(gsf, shape, seed, prec):
         j = np.ravel_multi_index(tuple(nb[inside].T), shape)
         expect = np.zeros(ref.n)
         expect[i] = np.asarray(W[i, j]).ravel()
-        assert rel(planes[q], expect) <= (1e-15 if prec == gsf.F64 else 1e-7), (q, o)
+        assert rel(planes[q], expect) <= (1e-15 if prec == gsf.F64 else 2e-6), (q, o)
+        d_st[i] += planes[q][i]
+        d_st[j] += planes[q][i]
+    deg = op.degree().cpu().numpy()
+    np.testing.assert_allclose(deg, d_st, rtol=1e-13)
+    assert rel(deg, ref.d) <= (1e-13 if prec == gsf.F64 else 1e-5)
 
 
 @pytest.mark.parametrize("prec", [0, 1])
