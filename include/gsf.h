@@ -77,11 +77,12 @@ typedef enum { GSF_NORM_D = 0, GSF_NORM_DIAGL = 1 } gsf_norm;
  *          a GF operator has fewer than 2^27 points.
  *  prec    element type of the guidance, of all vectors and of the stored
  *          operator.  GF window statistics, and BF weights of FP64 data or of
- *          multi-channel guidance, are computed in FP64 and rounded once to
- *          this type; BF weights of FP32 data with one guidance channel are
- *          evaluated in FP32 (hardware base-2 exponential: relative error
- *          about (2 + 2a) 2^-24 for a weight e^-a).  BF degrees are always
- *          the FP64 row sums of exactly the stored weights.
+ *          guidance with other than 1 or 3 channels, are computed in FP64 and
+ *          rounded once to this type; BF weights of FP32 data with one or
+ *          three guidance channels are evaluated in FP32 (hardware base-2
+ *          exponential: relative error about (2 + 2a) 2^-24 for a weight e^-a
+ *          with one channel, (4 + 3a) 2^-24 with three).  BF degrees are
+ *          always the FP64 row sums of exactly the stored weights.
  *  radius  1..8.
  *  sigma_d, sigma_r > 0 (BF; +inf allowed, removing that factor).
  *  gf_eps  >= 0 (GF).
