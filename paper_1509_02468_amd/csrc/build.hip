@@ -1,10 +1,10 @@
 // Operator construction: BF weights and normalisation (Section 2, eq. (2),
-// eq. (4); Section 4 normalisation).  FP64 data and multi-channel guidance:
+// eq. (4); Section 4 normalisation).  FP64 data and other channel counts:
 // weights computed in FP64 and rounded once to the storage type, each
 // undirected edge once (fold), then the degrees as FP64 row sums of the
 // stored weights (so D 1 = W 1 holds for the operator that is applied).  FP32
-// data with one guidance channel takes the one-pass build of the window
-// kernels instead (FP32 exponentials, every weight of the window evaluated at
+// data with one or three guidance channels takes the one-pass build of the
+// window kernels instead (FP32 exponentials, every weight of the window evaluated at
 // its point, the forward half stored; the degrees are again FP64 sums of the
 // stored values).  The
 // (diag L) normalisation sums the off-diagonal weights only: the self-loop
@@ -161,7 +161,7 @@ inline double inv_two_sigma2(double s) { return std::isinf(s) ? 0.0 : 1.0 / (2.0
 bool launch_bf_build_onepass(const Operator& op, const void* guidance, hipStream_t s);
 
 gsf_status launch_bf_build(const Operator& op, const void* guidance, hipStream_t s) {
-  // FP32 data with one guidance channel: one window pass (FP32 exponentials)
+  // FP32 data with one or three guidance channels: one window pass (FP32 exponentials)
   if (launch_bf_build_onepass(op, guidance, s)) return launch_status();
   BfParams p{op.n,
              op.rows,
