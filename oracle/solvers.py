@@ -146,18 +146,12 @@ def cg_filter_block(op, X0, kmax: int, tol: float = 0.0, data_prec: str = "f64")
     return out, infos
 
 
-def cg_filter_normalized(op, x0, kmax: int, tol: float = 0.0, data_prec: str = "f64", store=None):
+def cg_filter_normalized(op, x0, kmax: int, tol: float = 0.0, data_prec: str = "f64"):
     """The same iteration written for L_sym z = 0 in z = D^1/2 x with T = I
-    (s = r); returns x = D^-1/2 z.
-
-    `store`, if given, is applied to every vector the iteration keeps (z, r,
-    p, q) right after it is formed; rounding to a storage format there
-    measures how much the filter amplifies that rounding (the sensitivity band
-    used to bound lower-precision runs)."""
-    keep = store if store is not None else (lambda v: v)
-    z = keep(op.sqrt_d * np.asarray(x0, dtype=np.float64).ravel())
+    (s = r); returns x = D^-1/2 z."""
+    z = op.sqrt_d * np.asarray(x0, dtype=np.float64).ravel()
     floor = (BREAKDOWN_TOL[data_prec] ** 2) * float(z @ z)
-    r = keep(-op.apply_lsym(z))
+    r = -op.apply_lsym(z)
     info = CgInfo()
     p = r_old = None
     rho0 = None
@@ -178,17 +172,17 @@ def cg_filter_normalized(op, x0, kmax: int, tol: float = 0.0, data_prec: str = "
             p = r
         else:
             beta = float(r @ (r - r_old)) / float(r_old @ r_old)
-            p = keep(r + beta * p)
-        q = keep(op.apply_lsym(p))
+            p = r + beta * p
+        q = op.apply_lsym(p)
         pq = float(p @ q)
         if not (np.isfinite(pq) and pq > 0.0):
             info.status = "breakdown"
             info.res = np.sqrt(rho)
             return z / op.sqrt_d, info
         alpha = rho / pq
-        z = keep(z + alpha * p)
+        z = z + alpha * p
         r_old = r
-        r = keep(r - alpha * q)
+        r = r - alpha * q
         info.iters = k
     info.res = float(np.sqrt(r @ r))
     if tol > 0.0 and info.res > tol * info.res0:

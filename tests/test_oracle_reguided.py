@@ -125,3 +125,76 @@ def test_reguidance_changes_the_filter(kind, sig, par):
     y, _ = oracle.cg_filter_reguided(kind, x, shape, 4, **par)
     yl, _ = oracle.cg_filter(op, x, 4)
     assert np.linalg.norm(y - yl) > 1e-6 * np.linalg.norm(yl)
+
+
+# ---------------------------------------------------------------------------
+# step 2 on a graph that changes, carried out by hand
+# ---------------------------------------------------------------------------
+def _bf_dense(g, shape, r, sd, sr):
+    """Eq. (2) written out point by point over the square window of radius
+    r (self-loop included, truncated at the border): an independent dense W."""
+    import itertools
+    import math
+    g = np.asarray(g, dtype=np.float64).ravel()
+    pts = list(itertools.product(*[range(s) for s in shape]))
+    n = len(pts)
+    W = np.zeros((n, n))
+    for i, pi in enumerate(pts):
+        for j, pj in enumerate(pts):
+            if max(abs(a - b) for a, b in zip(pi, pj)) <= r:
+                dist2 = sum((a - b) ** 2 for a, b in zip(pi, pj))
+                W[i, j] = math.exp(-dist2 / (2.0 * sd * sd) - (g[i] - g[j]) ** 2 / (2.0 * sr * sr))
+    return W
+
+
+def _two_steps_by_hand(x0, shape, r, sd, sr, mistake=None):
+    """Algorithm 2, steps 1 and 2, with L_k = D_k - W_k and D_k built from the
+    current iterate x_k before step k (the reading of the re-guided CG).
+    `mistake` plants a plausible misreading, for the checks that the pin
+    tells them apart:
+      "stale": step 2 keeps the graph of x_0 (the iterate before the last
+               update), i.e. the linear filter;
+      "recompute_r": step 2 takes r_1 = -L_1 x_1 instead of the updated r;
+      "new_d_old_s": the beta denominator uses s_old = D_1^-1 r_old."""
+    def graph(x):
+        W = _bf_dense(x, shape, r, sd, sr)
+        d = W.sum(axis=1)
+        return np.diag(d) - W, d
+
+    L0, d0 = graph(x0)
+    r0 = -L0 @ x0
+    s0 = r0 / d0
+    p0 = s0
+    q0 = L0 @ p0
+    a0 = (s0 @ r0) / (p0 @ q0)
+    x1 = x0 + a0 * p0
+    r1 = r0 - a0 * q0
+    L1, d1 = graph(x0 if mistake == "stale" else x1)
+    if mistake == "recompute_r":
+        r1 = -L1 @ x1
+    s1 = r1 / d1
+    s_old = r0 / d1 if mistake == "new_d_old_s" else s0
+    beta = (s1 @ (r1 - r0)) / (s_old @ r0)
+    p1 = s1 + beta * p0
+    q1 = L1 @ p1
+    a1 = (s1 @ r1) / (p1 @ q1)
+    return x1 + a1 * p1
+
+
+@pytest.mark.parametrize("x0,shape,r,sd,sr", [
+    (np.array([0.10, 0.18, 0.85, 0.80, 0.95, 0.22, 0.15]), (7,), 2, 1.5, 0.3),
+    (np.array([0.10, 0.20, 0.90, 0.15, 0.80, 0.85, 0.30, 0.25, 0.95]), (3, 3), 1, 1.0, 0.35),
+])
+def test_bf_cg_step_two_by_hand(x0, shape, r, sd, sr):
+    """Step 2 of the re-guided BF CG on a graph that changes (the weights of
+    eq. (2) written out densely from x_1, Algorithm 2's recursion carried out
+    by hand): the oracle agrees to rounding, and each planted misreading
+    (the graph of x_0 at step 2, r recomputed from L_1, the beta denominator
+    with D_1) lands far outside that."""
+    expect = _two_steps_by_hand(x0, shape, r, sd, sr)
+    y, info = oracle.cg_filter_reguided("bf", x0, shape, 2, radius=r, sigma_s=sd, sigma_r=sr)
+    assert info.iters == 2
+    np.testing.assert_allclose(y, expect, rtol=0, atol=1e-13)
+    for mistake in ("stale", "recompute_r", "new_d_old_s"):
+        wrong = _two_steps_by_hand(x0, shape, r, sd, sr, mistake)
+        assert np.abs(wrong - expect).max() > 1e-4, mistake
