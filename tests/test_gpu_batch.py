@@ -1,7 +1,8 @@
 """Batching (many uneven items, one graph launch): every item equals the same
 item filtered alone through the single-item calls (bitwise: the batch runs
 the same kernels), over repeated graph replays with eager work between them,
-and agrees with the FP64 oracle within the FP32 bounds."""
+and agrees with the FP64 oracle within the FP32 bound (1e-5 relative for
+every output; LOBPCG items also by their Ritz values and drop counts)."""
 import numpy as np
 import pytest
 
@@ -74,11 +75,12 @@ def test_batch_items_match_oracle(gsf):
         elif it["method"] == "cg":
             r, rinfo = oracle.cg_filter(ref, x.ravel(), it["kmax"], tol=it["tol"], data_prec="f32")
             assert info[k][0] == rinfo.iters
-            tol = 1e-4
+            tol = 1e-5
         else:
             r, th, _, rinfo = oracle.lobpcg_filter(ref, x.ravel(), it["m"], it["kmax"],
                                                    constraint=it.get("constraint", False), data_prec="f32")
-            tol = 1e-3
+            assert info[k][0] == rinfo.iters
+            tol = 1e-5
         got = it["out"].cpu().numpy().astype(np.float64)
         err = np.linalg.norm(got - r) / np.linalg.norm(r)
         print(f"batch item {k} {it['kind']} {it['method']} {it['shape']}: rel err {err:.2e}")

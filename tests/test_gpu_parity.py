@@ -2,19 +2,27 @@
 the FP64 CPU oracle on the same seeded inputs.
 
 Tolerances (relative, 2-norm and max-norm over the whole output):
-  FP64 path: 1e-12 for weights, apply and power iteration; CG and LOBPCG
-             outputs 1e-10 (30-50 steps amplify summation-order differences,
-             see the self-sensitivity test below).
-  FP32 path: 1e-5 for weights, apply, power iteration and CG; LOBPCG Ritz
-             values within 1e-5 * ||L_sym|| (||L_sym|| <= 2).
-For FP32 runs the oracle receives the FP32-rounded inputs, so the comparison
-measures the kernel's arithmetic, not the rounding of its inputs.
+  FP64 path: 1e-12 for weights, apply and power iteration; the CG and LOBPCG
+             outputs max(1e-12, 10 band), where the band is the oracle's own
+             self-sensitivity (the same filter on the grid in reverse point
+             order, which only reorders its sums; tests/sensitivity.py),
+             measured for each case as it runs.
+  FP32 path: 1e-5 for weights, apply, power iteration, CG and LOBPCG
+             outputs; LOBPCG Ritz values within 1e-5 * ||L_sym||
+             (||L_sym|| <= 2).
+LOBPCG runs compare their decisions first: the number of trial columns the
+Rayleigh-Ritz steps dropped must equal the oracle's wherever the oracle's
+reversed run takes the same decisions (a drop on the rounding threshold is
+not fixed by the method).  For FP32 runs the oracle receives the
+FP32-rounded inputs, so the comparison measures the kernel's arithmetic, not
+the rounding of its inputs.
 """
 import numpy as np
 import pytest
 
 import oracle
-from synth import piecewise_constant_1d, scene_2d
+from sensitivity import reference
+from synth import WORKLOADS, make_signal, piecewise_constant_1d, scene_2d
 
 pytestmark = pytest.mark.gpu
 
@@ -51,12 +59,26 @@ TOL = {0: 1e-5, 1: 1e-12}
 BF_CASES = [("bf", (4096,), 1), ("bf", (1000,), 2), ("bf", (67, 130), 3), ("bf", (33, 200), 4)]
 GF_CASES = [("gf", (1500,), 5), ("gf", (70, 131), 6)]
 
+# operator parameters per case: 1D the 4096-sample signal's BF (radius 5,
+# sigma_d 3, sigma_r 0.2); 67 x 130 the 1024^2 image's 11 x 11 window (radius
+# 5, sigma_d 2, sigma_r 0.1); 33 x 200 a 7 x 7 window; GF radius 4 (1D) or 3
+PARAMS = {
+    (4096,): dict(radius=5, sigma_d=3.0, sigma_r=0.2),
+    (1000,): dict(radius=5, sigma_d=3.0, sigma_r=0.2),
+    (67, 130): dict(radius=5, sigma_d=2.0, sigma_r=0.1),
+    (33, 200): dict(radius=3, sigma_d=2.0, sigma_r=0.1),
+}
+
 
 def _params(kind, shape):
     if kind == "bf":
-        r = 5 if len(shape) == 1 else (3 if shape[0] % 2 else 5)
-        return dict(radius=r, sigma_d=3.0 if len(shape) == 1 else 2.0, sigma_r=0.2 if len(shape) == 1 else 0.1)
+        return dict(PARAMS[tuple(shape)])
     return dict(radius=4 if len(shape) == 1 else 3, eps=1e-2)
+
+
+def _oracle_op(kind, grid, p):
+    return oracle.build_operator(kind, grid, p["radius"], p.get("sigma_d", 0.0), p.get("sigma_r", 0.0),
+                                 p.get("eps", 0.0))
 
 
 def _build(gsf, case, prec):
@@ -65,8 +87,7 @@ def _build(gsf, case, prec):
     p = _params(kind, shape)
     xr = _round(x, prec, gsf)
     op = gsf.Operator(kind, shape, _torch(x, prec, gsf), prec=prec, **p)
-    ref = oracle.build_operator(kind, xr.reshape(shape), p["radius"], p.get("sigma_d", 0.0), p.get("sigma_r", 0.0),
-                                p.get("eps", 0.0))
+    ref = _oracle_op(kind, xr.reshape(shape), p)
     return op, ref, xr.ravel()
 
 
@@ -156,17 +177,26 @@ def test_power_filter_parity(gsf, prec, case, k):
 
 
 # ------------------------------------------------------------------ CG
+def _grid(x, shape):
+    return np.asarray(x, dtype=np.float64).reshape(shape)
+
+
 @pytest.mark.parametrize("prec,case,k", [(1, ("bf", (4096,), 1), 30), (1, ("bf", (67, 130), 3), 30),
                                          (0, ("bf", (67, 130), 3), 30), (1, ("gf", (70, 131), 6), 20),
-                                         (0, ("bf", (33, 200), 4), 50)])
+                                         (0, ("bf", (33, 200), 4), 50), (1, ("bf", (33, 200), 4), 50)])
 def test_cg_filter_parity(gsf, prec, case, k):
-    op, ref, x = _build(gsf, case, prec)
+    op, _, x = _build(gsf, case, prec)
+    p = _params(case[0], op.shape)
+    dp = "f32" if prec == 0 else "f64"
     y, info = op.cg_filter(_torch(x, prec, gsf), k)
-    r, rinfo = oracle.cg_filter(ref, x, k, data_prec="f32" if prec == 0 else "f64")
+    ref = reference(lambda g: oracle.cg_filter(_oracle_op(case[0], g, p), g.ravel(), k, data_prec=dp),
+                    _grid(x, op.shape))
+    rinfo = ref.extra
     assert info.iters == rinfo.iters and info.status == 0
-    err = rel(y.cpu().numpy(), r)
-    print(f"cg {case} prec={prec} k={k}: rel err {err:.3e}")
-    assert err <= (1e-10 if prec == 1 else 1e-5), err
+    err = rel(y.cpu().numpy(), ref.y)
+    gate = ref.gate if prec == 1 else TOL[0]
+    print(f"cg {case} prec={prec} k={k}: rel err {err:.3e} (band {ref.band:.1e}, gate {gate:.1e})")
+    assert err <= gate, err
     assert abs(info.res0 - rinfo.res0) <= 1e-6 * rinfo.res0
 
 
@@ -181,11 +211,13 @@ def test_cg_constant_input_breakdown(gsf):
 
 
 def test_cg_tolerance_stop(gsf):
-    op, ref, x = _build(gsf, ("bf", (1000,), 2), 1)
+    op, _, x = _build(gsf, ("bf", (1000,), 2), 1)
+    p = _params("bf", op.shape)
     y, info = op.cg_filter(_torch(x, 1, gsf), 500, tol=1e-6)
-    r, rinfo = oracle.cg_filter_normalized(ref, x, 500, tol=1e-6)
-    assert info.status == 0 and info.iters == rinfo.iters
-    assert rel(y.cpu().numpy(), r) <= 1e-9
+    ref = reference(lambda g: oracle.cg_filter_normalized(_oracle_op("bf", g, p), g, 500, tol=1e-6), x)
+    assert ref.extra.iters == ref.extra_reversed.iters
+    assert info.status == 0 and info.iters == ref.extra.iters
+    assert rel(y.cpu().numpy(), ref.y) <= ref.gate
 
 
 # ------------------------------------------------------------------ Gram (MFMA) and Rayleigh-Ritz
@@ -231,6 +263,39 @@ def test_rayleigh_ritz_parity(gsf, ns, m, drop):
 
 
 # ------------------------------------------------------------------ LOBPCG
+def lobpcg_reference(kind, p, x, shape, m, k, prec, **kw):
+    """The oracle's LOBPCG output with its band (FP64 data) and decisions."""
+    dp = "f64" if prec == 1 else "f32"
+
+    def run(g):
+        y, th, X, info = oracle.lobpcg_filter(_oracle_op(kind, g, p), g.ravel(), m, k, data_prec=dp, **kw)
+        return y, (th, info)
+
+    return reference(run, _grid(x, shape))
+
+
+def check_lobpcg(info, y, ref, m, prec, label=""):
+    """Decisions first (steps; dropped columns where the oracle's reversed
+    run agrees with itself), then Ritz values and the output."""
+    th, rinfo = ref.extra
+    _, rinfo_rev = ref.extra_reversed
+    assert info.iters == rinfo.iters
+    if rinfo.dropped == rinfo_rev.dropped:
+        assert info.dropped == rinfo.dropped, (info.dropped, rinfo.dropped)
+    theta = np.array(info.theta[:m])
+    e = rel(y, ref.y)
+    print(f"lobpcg {label} prec={prec}: y rel {e:.2e} (band {ref.band:.1e}), theta abs "
+          f"{np.abs(theta - th).max():.2e}, dropped {info.dropped} vs {rinfo.dropped} "
+          f"(reversed oracle {rinfo_rev.dropped})")
+    if prec == 1:
+        np.testing.assert_allclose(theta, th, rtol=max(1e-9, ref.gate), atol=1e-12)
+        assert e <= ref.gate, e
+    else:
+        assert np.abs(theta - th).max() <= 2e-5
+        assert e <= TOL[0], e
+    return e
+
+
 @pytest.mark.parametrize("prec,case,m,k,constraint", [
     (1, ("bf", (4096,), 1), 3, 30, False),
     (1, ("bf", (4096,), 1), 3, 30, True),
@@ -242,20 +307,12 @@ def test_rayleigh_ritz_parity(gsf, ns, m, drop):
 ])
 def test_lobpcg_filter_parity(gsf, prec, case, m, k, constraint):
     import torch
-    op, ref, x = _build(gsf, case, prec)
+    op, _, x = _build(gsf, case, prec)
+    p = _params(case[0], op.shape)
     ritz = torch.empty((op.n, m), dtype=op.dtype, device="cuda")
     y, info = op.lobpcg_filter(_torch(x, prec, gsf), m, k, constraint=constraint, ritz=ritz)
-    r, th, X, rinfo = oracle.lobpcg_filter(ref, x, m, k, constraint=constraint,
-                                           data_prec="f64" if prec == 1 else "f32")
-    assert info.iters == rinfo.iters
-    theta = np.array(info.theta[:m])
-    if prec == 1:
-        assert info.dropped == rinfo.dropped
-        np.testing.assert_allclose(theta, th, rtol=1e-9, atol=1e-12)
-        assert rel(y.cpu().numpy(), r) <= 1e-9, rel(y.cpu().numpy(), r)
-    else:
-        assert np.abs(theta - th).max() <= 2e-5
-        assert rel(y.cpu().numpy(), r) <= 1e-3, rel(y.cpu().numpy(), r)
+    ref = lobpcg_reference(case[0], p, x, op.shape, m, k, prec, constraint=constraint)
+    check_lobpcg(info, y.cpu().numpy(), ref, m, prec, f"{case} m={m} k={k} c={constraint}")
 
 
 def test_lobpcg_identity_at_zero_steps(gsf):
@@ -279,34 +336,81 @@ def test_lobpcg_constant_input_breakdown(gsf):
 def test_precision_study_lobpcg_m8_100_steps(gsf, kind, prec):
     """The precision-study configuration (noise 0.08; BF 7x7 with sigma_d = 2,
     sigma_r = 0.15, or GF radius 8 with eps = 1e-2; LOBPCG m = 8, 100 steps)
-    at a size the oracle finishes in seconds.  FP64: Ritz values within 1e-9
-    relative, output within 1e-8 (100 steps of an m = 8 block amplify
-    summation-order differences more than the 30-step cases above).  FP32
-    (FP32 data and MFMA Gram, FP64 Rayleigh-Ritz): Ritz values within
-    1e-5 * ||L_sym|| (||L_sym|| <= 2); the output error is reported."""
-    import torch
+    at a size the oracle finishes in seconds.  FP64: Ritz values and output
+    within the band gate (100 steps of an m = 8 block amplify
+    summation-order differences: the BF band is ~5e-12).  FP32 (FP32 data and
+    MFMA Gram, FP64 Rayleigh-Ritz): Ritz values within 1e-5 * ||L_sym||
+    (||L_sym|| <= 2); the output error is reported, as the precision study
+    reports it: y projects z0 on all eight Ritz vectors, the upper ones far
+    from converged after 100 steps, and FP32 rounding moves their span and
+    the drop decisions (measured: BF 7x7 8.7e-4 with 90 drops against the
+    oracle's 106, Ritz values within 4.4e-9).  The GF run converges its first
+    column to the null vector within a few steps; its trial columns then sit
+    at the rounding level and are dropped on rounding decisions that the
+    oracle itself takes differently when its sums are reordered, so the drop
+    counts are compared only where the oracle agrees with itself."""
     H, W = 96, 112
     x = scene_2d(H, W, 0.08, 3)[1]
     xr = _round(x, prec, gsf)
-    if kind == "bf7":
-        op = gsf.Operator("bf", (H, W), _torch(xr, prec, gsf), 3, 2.0, 0.15, prec=prec)
-        ref = oracle.build_operator("bf", xr, 3, 2.0, 0.15)
-    else:
-        op = gsf.Operator("gf", (H, W), _torch(xr, prec, gsf), 8, eps=1e-2, prec=prec)
-        ref = oracle.build_operator("gf", xr, 8, eps=1e-2)
+    p = dict(radius=3, sigma_d=2.0, sigma_r=0.15) if kind == "bf7" else dict(radius=8, eps=1e-2)
+    okind = "bf" if kind == "bf7" else "gf"
+    op = gsf.Operator(okind, (H, W), _torch(xr, prec, gsf), prec=prec, **p)
     m, k = 8, 100
     y, info = op.lobpcg_filter(_torch(xr, prec, gsf), m, k)
-    r, th, X, rinfo = oracle.lobpcg_filter(ref, xr.ravel(), m, k, data_prec="f64" if prec == 1 else "f32")
+    ref = lobpcg_reference(okind, p, xr, (H, W), m, k, prec)
+    th, rinfo = ref.extra
     theta = np.array(info.theta[:m])
-    ey = rel(y.cpu().numpy(), r)
+    ey = rel(y.cpu().numpy(), ref.y)
     et = np.abs(theta - th).max()
     print(f"precision study {kind} prec {prec}: theta abs {et:.2e} (rel {np.abs(theta / th - 1).max():.2e}), "
-          f"y rel {ey:.2e}, dropped {info.dropped} vs {rinfo.dropped}")
+          f"y rel {ey:.2e} (band {ref.band:.1e}), dropped {info.dropped} vs {rinfo.dropped} "
+          f"(reversed oracle {ref.extra_reversed[1].dropped})")
+    assert info.iters == rinfo.iters == k
     if prec == 1:
-        np.testing.assert_allclose(theta, th, rtol=1e-9, atol=1e-12)
-        assert ey <= 1e-8
+        check_lobpcg(info, y.cpu().numpy(), ref, m, prec, f"precision study {kind}")
     else:
         assert et <= 2e-5
+
+
+# ------------------------------------------------------------------ the 1024^2 image's operator at 256^2
+@pytest.fixture(scope="module")
+def crop256():
+    """The top-left 256 x 256 crop of the 1024^2 workload image (noise 0.05,
+    seed 2) with its operator parameters (BF 11 x 11, sigma_d 2, sigma_r 0.1)."""
+    w = WORKLOADS["image_1024_bf11"]
+    x = make_signal("image_1024_bf11")[1][:256, :256].copy()
+    return x, dict(radius=w["radius"], sigma_d=w["sigma_d"], sigma_r=w["sigma_r"])
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_image_crop_cg50_lobpcg_m4_50_and_joint(gsf, crop256, prec):
+    """The bench step's filters on a 256^2 crop of its image, element by
+    element against the oracle: CG 50 steps, LOBPCG m = 4 50 steps (the 11 x 11
+    stored-plane apply, the MFMA Gram and the FP64 Rayleigh-Ritz step) and the
+    joint driver, whose shared stencil pass is the bench's timed kernel."""
+    x, p = crop256
+    xr = _round(x, prec, gsf)
+    shape = xr.shape
+    op = gsf.Operator("bf", shape, _torch(xr.ravel(), prec, gsf), prec=prec, **p)
+    xd = _torch(xr.ravel(), prec, gsf)
+    dp = "f32" if prec == 0 else "f64"
+    rcg = reference(lambda g: oracle.cg_filter(_oracle_op("bf", g, p), g.ravel(), 50, data_prec=dp), xr)
+    rlob = lobpcg_reference("bf", p, xr, shape, 4, 50, prec)
+    cg_gate = rcg.gate if prec == 1 else TOL[0]
+    y, info = op.cg_filter(xd, 50)
+    e = rel(y.cpu().numpy(), rcg.y)
+    print(f"crop CG 50 prec {prec}: {e:.2e} (band {rcg.band:.1e})")
+    assert info.iters == rcg.extra.iters == 50 and e <= cg_gate
+    y, info = op.lobpcg_filter(xd, 4, 50)
+    check_lobpcg(info, y.cpu().numpy(), rlob, 4, prec, "crop m=4 k=50")
+    for rows in (None, 1, 2, 4):
+        if rows is not None:
+            op.set_apply_rows(4, rows)
+        ycg, ylob, ci, li = op.joint_filter(xd, 50, xd, 4, 50)
+        e = rel(ycg.cpu().numpy(), rcg.y)
+        print(f"crop joint rows={rows} prec {prec}: cg {e:.2e}")
+        assert ci.iters == 50 and e <= cg_gate
+        check_lobpcg(li, ylob.cpu().numpy(), rlob, 4, prec, f"crop joint rows={rows}")
 
 
 @pytest.mark.parametrize("prec", [0, 1])
@@ -321,10 +425,11 @@ def test_cg_1d_small_and_large_paths(gsf, n, prec):
     ref = oracle.build_operator("bf", xr, 4, 3.0, 0.2)
     dp = "f32" if prec == 0 else "f64"
     y, info = op.cg_filter(_torch(xr, prec, gsf), 25)
-    r, rinfo = oracle.cg_filter(ref, xr, 25, data_prec=dp)
+    rr = reference(lambda g: oracle.cg_filter(oracle.build_operator("bf", g, 4, 3.0, 0.2), g, 25, data_prec=dp), xr)
+    r, rinfo = rr.y, rr.extra
     e = rel(y.cpu().numpy(), r)
-    print(f"cg 1D n={n} prec={prec}: {e:.2e}")
-    assert info.iters == rinfo.iters == 25 and info.status == gsf.OK and e <= TOL[prec] * (100 if prec else 1)
+    print(f"cg 1D n={n} prec={prec}: {e:.2e} (band {rr.band:.1e})")
+    assert info.iters == rinfo.iters == 25 and info.status == gsf.OK and e <= (rr.gate if prec else TOL[0])
     assert abs(info.res0 - rinfo.res0) <= 1e-6 * rinfo.res0
     y, info = op.cg_filter(_torch(xr, prec, gsf), 2000, tol=1e-4)
     r, rinfo = oracle.cg_filter(ref, xr, 2000, tol=1e-4, data_prec=dp)

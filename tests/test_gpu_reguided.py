@@ -1,20 +1,21 @@
 """GPU parity of the re-guided (non-linear) filters and of the Laplacian apply
 form they use, through the C ABI, against the FP64 oracle.
 
-Tolerances (relative, 2-norm and max-norm): FP64 data 1e-12 (power, 6
-passes) and 1e-11 (CG, up to 60 steps); FP32 data, against the oracle fed the
-FP32-rounded iterate before each rebuild, 1e-5 (power) and 1e-4 (CG).  Every
-step rebuilds the graph from the iterate, so summation-order differences also
-pass through the weights of eq. (2), which move by ~|g_i - g_j| / sigma_r^2
-(about 10) times a change of the guidance; the bounds leave one to two orders
-of margin over the measured errors (FP64 <= 2e-14, FP32 <= 7e-7 at 12 steps)
-for that growth with the step count.  The L form of the apply: 1e-12 FP64,
+Tolerances (relative, 2-norm and max-norm): FP64 data 1e-12 (power) and
+max(1e-12, 10 band) (CG), the band being the oracle's own self-sensitivity
+(the case on the grid in reverse point order, tests/sensitivity.py; every
+step rebuilds the graph from the iterate, so summation-order differences
+also pass through the weights of eq. (2), which move by ~|g_i - g_j| /
+sigma_r^2 times a change of the guidance, and the band measures that
+growth); FP32 data, against the oracle fed the FP32-rounded iterate before
+each rebuild, 1e-5 for power and CG.  The L form of the apply: 1e-12 FP64,
 1e-5 FP32 (a single apply, as the other forms).
 """
 import numpy as np
 import pytest
 
 import oracle
+from sensitivity import reference
 from synth import piecewise_constant_1d, scene_2d
 
 pytestmark = pytest.mark.gpu
@@ -41,6 +42,12 @@ CASES = [
     ("gf", (1500,), 23, dict(radius=4, eps=1e-2)),
     ("gf", (70, 131), 24, dict(radius=3, eps=1e-2)),
 ]
+
+
+def _rg_cg(kind, x0, shape, k, **okw):
+    """The oracle's re-guided CG with its self-sensitivity band."""
+    return reference(lambda g: oracle.cg_filter_reguided(kind, g.ravel(), shape, k, **okw),
+                     np.asarray(x0, dtype=np.float64).reshape(shape))
 
 
 def _dev(x, prec, gsf):
@@ -103,14 +110,14 @@ def test_reguided_cg_parity(gsf, kind, shape, seed, par, prec):
         x0 = x0.astype(np.float32).astype(np.float64)
     k = 12
     y, info = gsf.reguided_filter(kind, shape, _dev(x0, prec, gsf), gsf.METHOD_CG, k, **_gpu_kw(par), prec=prec)
-    ref, rinfo = oracle.cg_filter_reguided(kind, x0, shape, k, **_oracle_kw(par),
-                                           data_prec="f32" if prec == gsf.F32 else "f64")
+    rr = _rg_cg(kind, x0, shape, k, **_oracle_kw(par), data_prec="f32" if prec == gsf.F32 else "f64")
+    ref, rinfo = rr.y, rr.extra
     e = rel(y.cpu().numpy(), ref)
-    print(f"re-guided CG {kind} {shape} prec={prec}: {e:.2e}, iters {info.iters} vs {rinfo.iters}, "
-          f"res {info.res:.3e} vs {rinfo.res:.3e}")
+    print(f"re-guided CG {kind} {shape} prec={prec}: {e:.2e} (band {rr.band:.1e}), iters {info.iters} vs "
+          f"{rinfo.iters}, res {info.res:.3e} vs {rinfo.res:.3e}")
     assert info.status == gsf.OK and rinfo.status == "ok"
     assert info.iters == rinfo.iters == k
-    assert e <= (1e-11 if prec == gsf.F64 else 1e-4)
+    assert e <= (rr.gate if prec == gsf.F64 else 1e-5)
     assert abs(info.res0 - rinfo.res0) <= (1e-12 if prec == gsf.F64 else 1e-5) * rinfo.res0
 
 
@@ -123,12 +130,18 @@ def test_reguided_cg_tolerance_stop(gsf, prec):
         x0 = x0.astype(np.float32).astype(np.float64)
     y, info = gsf.reguided_filter(kind, shape, _dev(x0, prec, gsf), gsf.METHOD_CG, 500, **_gpu_kw(par), prec=prec,
                                   tol=1e-3)
-    ref, rinfo = oracle.cg_filter_reguided(kind, x0, shape, 500, **_oracle_kw(par), tol=1e-3,
-                                           data_prec="f32" if prec == gsf.F32 else "f64")
-    print(f"re-guided CG to 1e-3 prec={prec}: {info.iters} vs {rinfo.iters} steps")
+    rr = _rg_cg(kind, x0, shape, 500, **_oracle_kw(par), tol=1e-3, data_prec="f32" if prec == gsf.F32 else "f64")
+    ref, rinfo = rr.y, rr.extra
+    e = rel(y.cpu().numpy(), ref)
+    print(f"re-guided CG to 1e-3 prec={prec}: {info.iters} vs {rinfo.iters} steps, {e:.2e}")
     assert info.status == gsf.OK and rinfo.status == "ok"
-    assert abs(info.iters - rinfo.iters) <= (0 if prec == gsf.F64 else 2)
-    assert rel(y.cpu().numpy(), ref) <= (1e-11 if prec == gsf.F64 else 1e-4)
+    if prec == gsf.F64:
+        assert info.iters == rinfo.iters == rr.extra_reversed.iters and e <= rr.gate
+    else:
+        # the FP32 residual may cross the tolerance a step or two apart from
+        # the oracle's (a decision on rounding); the same step gives the bar
+        assert abs(info.iters - rinfo.iters) <= 2
+        assert e <= (1e-5 if info.iters == rinfo.iters else 1e-4)
 
 
 @pytest.mark.parametrize("shape,seed", [((3000,), 25), ((67, 130), 26)])
@@ -166,7 +179,7 @@ def test_reguided_edge_cases(gsf, kind, shape, seed, par):
     ref = oracle.power_filter_reguided(kind, x0, shape, 2, **_oracle_kw(par))
     xin = xd.clone()
     gsf.reguided_filter(kind, shape, xin, gsf.METHOD_POWER, 2, **_gpu_kw(par), prec=gsf.F64, out=xin)
-    assert rel(xin.cpu().numpy(), ref) <= 1e-11
+    assert rel(xin.cpu().numpy(), ref) <= 1e-12
 
 
 def test_reguided_fullsize_properties(gsf):
@@ -240,11 +253,12 @@ def test_reguided_bf_interior_and_border_tiles(gsf, stencil, norm, prec):
     ref = oracle.power_filter_reguided("bf", x0, shape, 4, **op_)
     e = rel(y.cpu().numpy(), ref)
     y, info = gsf.reguided_filter("bf", shape, _dev(x0, prec, gsf), gsf.METHOD_CG, 6, **gp, prec=prec)
-    ref, rinfo = oracle.cg_filter_reguided("bf", x0, shape, 6, **op_)
+    rr = _rg_cg("bf", x0, shape, 6, **op_)
+    ref, rinfo = rr.y, rr.extra
     ec = rel(y.cpu().numpy(), ref)
-    print(f"re-guided BF 100x200 r=5 {stencil}/{norm} prec={prec}: power {e:.2e}, CG {ec:.2e}")
+    print(f"re-guided BF 100x200 r=5 {stencil}/{norm} prec={prec}: power {e:.2e}, CG {ec:.2e} (band {rr.band:.1e})")
     assert e <= (1e-12 if prec == gsf.F64 else 1e-5)
-    assert info.iters == rinfo.iters == 6 and ec <= (1e-11 if prec == gsf.F64 else 1e-4)
+    assert info.iters == rinfo.iters == 6 and ec <= (rr.gate if prec == gsf.F64 else 1e-5)
     assert abs(info.res0 - rinfo.res0) <= (1e-12 if prec == gsf.F64 else 1e-5) * rinfo.res0
 
 
@@ -263,11 +277,12 @@ def test_reguided_bf_largest_radius(gsf, shape, prec):
     e = rel(y.cpu().numpy(), ref)
     y, info = gsf.reguided_filter("bf", shape, _dev(x0, prec, gsf), gsf.METHOD_CG, 4, radius=8, sigma_d=4.0,
                                   sigma_r=0.2, prec=prec)
-    ref, rinfo = oracle.cg_filter_reguided("bf", x0, shape, 4, radius=8, sigma_s=4.0, sigma_r=0.2, data_prec=dp)
+    rr = _rg_cg("bf", x0, shape, 4, radius=8, sigma_s=4.0, sigma_r=0.2, data_prec=dp)
+    ref, rinfo = rr.y, rr.extra
     ec = rel(y.cpu().numpy(), ref)
-    print(f"re-guided BF radius 8 {shape} prec={prec}: power {e:.2e}, CG {ec:.2e}")
+    print(f"re-guided BF radius 8 {shape} prec={prec}: power {e:.2e}, CG {ec:.2e} (band {rr.band:.1e})")
     assert e <= (1e-12 if prec == gsf.F64 else 1e-5)
-    assert info.iters == rinfo.iters == 4 and ec <= (1e-11 if prec == gsf.F64 else 1e-4)
+    assert info.iters == rinfo.iters == 4 and ec <= (rr.gate if prec == gsf.F64 else 1e-5)
 
 
 @pytest.mark.parametrize("shape", [(1, 1), (1, 50), (50, 1), (2,), (3, 7)])
@@ -283,8 +298,9 @@ def test_reguided_bf_tiny_grids(gsf, shape):
     ref = oracle.power_filter_reguided("bf", x0, shape, 3, radius=2, sigma_s=1.5, sigma_r=0.2)
     assert rel(y.cpu().numpy(), ref) <= 1e-12
     y, info = gsf.reguided_filter("bf", shape, _dev(x0, gsf.F64, gsf), gsf.METHOD_CG, 4, **par, prec=gsf.F64)
-    ref, rinfo = oracle.cg_filter_reguided("bf", x0, shape, 4, radius=2, sigma_s=1.5, sigma_r=0.2)
+    rr = _rg_cg("bf", x0, shape, 4, radius=2, sigma_s=1.5, sigma_r=0.2)
+    ref, rinfo = rr.y, rr.extra
     st = {"ok": gsf.OK, "breakdown": gsf.EBREAKDOWN}[rinfo.status]
     print(f"re-guided BF tiny {shape}: status {info.status} vs {rinfo.status}, iters {info.iters} vs {rinfo.iters}")
     assert info.status == st and info.iters == rinfo.iters
-    assert rel(y.cpu().numpy(), ref) <= 1e-11
+    assert rel(y.cpu().numpy(), ref) <= rr.gate
