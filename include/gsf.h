@@ -51,7 +51,8 @@ typedef enum {
   GSF_ENOMEM = 2,      /* workspace smaller than the size query returned */
   GSF_EDEVICE = 3,     /* a HIP runtime call failed */
   GSF_ENOTCONV = 4,    /* tol > 0 was not reached within kmax steps; the result is still valid */
-  GSF_EBREAKDOWN = 5   /* the iteration stopped early (see each solver); the result is still valid */
+  GSF_EBREAKDOWN = 5,  /* the iteration stopped early (see each solver); the result is still valid */
+  GSF_ESCRATCH = 6     /* gsf_cg_filter_noalloc: the problem needs more than its static scratch */
 } gsf_status;
 
 typedef enum { GSF_BF = 0, GSF_GF = 1 } gsf_kind;
@@ -249,6 +250,30 @@ gsf_status gsf_power_filter(const gsf_operator* op, const void* x0, void* x_out,
  * the call: with info == NULL the call returns GSF_OK after enqueueing. */
 gsf_status gsf_cg_filter(const gsf_operator* op, const void* x0, void* x_out, int kmax,
                          double tol, void* ws, size_t ws_bytes, gsf_cg_info* info, void* stream);
+
+/* gsf_cg_filter without a workspace argument, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation.  It computes what gsf_cg_filter computes
+ * (same kernels in the same order; bitwise the same result and info) in a
+ * workspace of the library's own: one static device array of
+ * GSF_NOALLOC_SCRATCH_BYTES (64 MiB) per device, part of the library's code
+ * object, which each device holds from the first call until the process ends.
+ * The call allocates nothing (no hipMalloc / hipFree, no pinned host
+ * staging): the host does not poll for an early stop, so with tol > 0 all
+ * kmax steps are enqueued and those after the stop do no work on the device;
+ * a non-NULL info synchronizes the stream and reads the device state into it.
+ * Every call on one device uses the same array and overwrites what the
+ * previous call left there (the solver state is re-initialised by each call):
+ * calls that overlap on one device (other streams, other threads) race, and
+ * so does a graph replay that overlaps another call.
+ * GSF_ESCRATCH, with nothing enqueued and x_out untouched, when the CG
+ * workspace of the operator (gsf_solver_workspace_bytes(op, GSF_METHOD_CG, 1))
+ * exceeds GSF_NOALLOC_SCRATCH_BYTES: four vectors of n elements plus
+ * reduction partials, so up to about 4.1 M FP32 or 2 M FP64 points.  Other
+ * arguments and errors as gsf_cg_filter. */
+#define GSF_NOALLOC_SCRATCH_BYTES (64u << 20)
+gsf_status gsf_cg_filter_noalloc(const gsf_operator* op, const void* x0, void* x_out, int kmax,
+                                 double tol, gsf_cg_info* info, void* stream);
 
 /* Multi-channel signals (the channels of a colour image filtered on one graph):
  * x0 and x_out are n x m point-major blocks (m = 1..8; x0[i*m + c]), one

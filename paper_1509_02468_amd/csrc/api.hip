@@ -488,6 +488,7 @@ const char* gsf_status_string(int status) {
     case GSF_EDEVICE: return "HIP runtime error";
     case GSF_ENOTCONV: return "tolerance not reached";
     case GSF_EBREAKDOWN: return "iteration broke down";
+    case GSF_ESCRATCH: return "problem larger than the static scratch";
     default: return "unknown status";
   }
 }
@@ -886,15 +887,15 @@ struct LobRun {
 
 }  // namespace
 
-gsf_status gsf_cg_filter(const gsf_operator* h, const void* x0, void* x_out, int kmax, double tol, void* ws,
-                         size_t ws_bytes, gsf_cg_info* info, void* stream) {
-  clear_stale_errors();
-  if (h == nullptr || x0 == nullptr || x_out == nullptr || kmax < 0 || !(tol >= 0.0) || !std::isfinite(tol))
-    return GSF_EINVAL;
-  const Operator& op = h->op;
-  CgWs w0;
-  if (ws == nullptr || ws_bytes < carve_cg(op, nullptr, &w0)) return GSF_ENOMEM;
-  CgRun cg(op, (char*)ws, (hipStream_t)stream);
+namespace {
+
+// The CG filter on a carved workspace `ws` (arguments already validated).
+// poll: the host may stop issuing steps once the device state reports the
+// stop (pinned host memory, allocated once per thread); without it every
+// step is issued and the steps after a stop are no-ops on the device.
+gsf_status cg_filter_run(const Operator& op, const void* x0, void* x_out, int kmax, double tol, char* ws,
+                         gsf_cg_info* info, hipStream_t stream, bool poll_host) {
+  CgRun cg(op, ws, stream);
   {
     // a 1D BF signal that fits in one workgroup: the whole filter in one launch
     CgState init{};
@@ -909,7 +910,7 @@ gsf_status gsf_cg_filter(const gsf_operator* h, const void* x0, void* x_out, int
     }
   }
   GSF_TRY(cg.begin(x0, tol));
-  Poller poll(cg.s, &cg.w.st->active, info != nullptr && tol > 0.0);
+  Poller poll(cg.s, &cg.w.st->active, poll_host && info != nullptr && tol > 0.0);
   for (int k = 1; k <= kmax; ++k) {
     if (!poll.keep_going(k - 1)) break;
     GSF_TRY(cg.pre(k));
@@ -917,6 +918,58 @@ gsf_status gsf_cg_filter(const gsf_operator* h, const void* x0, void* x_out, int
     GSF_TRY(cg.post(k));
   }
   return cg.finish(x_out, tol, info);
+}
+
+// Workspace of gsf_cg_filter_noalloc: one array per device, in the code
+// object's device memory, kept until the process ends.  Host code must not
+// pass `scratch` itself to a kernel (on the host the name is a stand-in, not
+// a device address): the address comes from hipGetSymbolAddress, taken once
+// per device with that device current.
+constexpr size_t kNoAllocScratchBytes = (size_t)GSF_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_address[kMaxDevices] = {};
+
+gsf_status scratch_address(void** out) {
+  int dev = -1;
+  GSF_TRY(hip_ok(hipGetDevice(&dev)));
+  if (dev < 0 || dev >= kMaxDevices) return GSF_EINVAL;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (g_scratch_address[dev] == nullptr) {
+    void* p = nullptr;
+    GSF_TRY(hip_ok(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch))));
+    if (p == nullptr) return GSF_EDEVICE;
+    g_scratch_address[dev] = p;
+  }
+  *out = g_scratch_address[dev];
+  return GSF_OK;
+}
+
+}  // namespace
+
+gsf_status gsf_cg_filter(const gsf_operator* h, const void* x0, void* x_out, int kmax, double tol, void* ws,
+                         size_t ws_bytes, gsf_cg_info* info, void* stream) {
+  clear_stale_errors();
+  if (h == nullptr || x0 == nullptr || x_out == nullptr || kmax < 0 || !(tol >= 0.0) || !std::isfinite(tol))
+    return GSF_EINVAL;
+  const Operator& op = h->op;
+  CgWs w0;
+  if (ws == nullptr || ws_bytes < carve_cg(op, nullptr, &w0)) return GSF_ENOMEM;
+  return cg_filter_run(op, x0, x_out, kmax, tol, (char*)ws, info, (hipStream_t)stream, true);
+}
+
+gsf_status gsf_cg_filter_noalloc(const gsf_operator* h, const void* x0, void* x_out, int kmax, double tol,
+                                 gsf_cg_info* info, void* stream) {
+  clear_stale_errors();
+  if (h == nullptr || x0 == nullptr || x_out == nullptr || kmax < 0 || !(tol >= 0.0) || !std::isfinite(tol))
+    return GSF_EINVAL;
+  const Operator& op = h->op;
+  CgWs w0;
+  if (carve_cg(op, nullptr, &w0) > kNoAllocScratchBytes) return GSF_ESCRATCH;
+  void* ws = nullptr;
+  GSF_TRY(scratch_address(&ws));
+  return cg_filter_run(op, x0, x_out, kmax, tol, (char*)ws, info, (hipStream_t)stream, false);
 }
 
 gsf_status gsf_lobpcg_filter(const gsf_operator* h, const void* x0, void* x_out, int m, int kmax, double tol,

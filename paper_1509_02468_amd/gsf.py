@@ -17,7 +17,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgsf.so")
 
-OK, EINVAL, ENOMEM, EDEVICE, ENOTCONV, EBREAKDOWN = range(6)
+OK, EINVAL, ENOMEM, EDEVICE, ENOTCONV, EBREAKDOWN, ESCRATCH = range(7)
 BF, GF = 0, 1
 F32, F64 = 0, 1
 FORM_N, FORM_LSYM, FORM_RW, FORM_L = 0, 1, 2, 3
@@ -28,7 +28,7 @@ _STENCILS = {"square": STENCIL_SQUARE, "cross": STENCIL_CROSS, STENCIL_SQUARE: S
              STENCIL_CROSS: STENCIL_CROSS}
 _NORMS = {"d": NORM_D, "diagl": NORM_DIAGL, NORM_D: NORM_D, NORM_DIAGL: NORM_DIAGL}
 STATUS_NAMES = {OK: "ok", EINVAL: "einval", ENOMEM: "enomem", EDEVICE: "edevice",
-                ENOTCONV: "notconv", EBREAKDOWN: "breakdown"}
+                ENOTCONV: "notconv", EBREAKDOWN: "breakdown", ESCRATCH: "escratch"}
 
 
 class OperatorDesc(ctypes.Structure):
@@ -104,6 +104,7 @@ def load_library(path: str = LIB_PATH):
         "gsf_solver_workspace_bytes": ([vp, i32, i32, P(sz)], i32),
         "gsf_power_filter": ([vp, vp, vp, i32, vp, sz, vp], i32),
         "gsf_cg_filter": ([vp, vp, vp, i32, dbl, vp, sz, P(CgInfo), vp], i32),
+        "gsf_cg_filter_noalloc": ([vp, vp, vp, i32, dbl, P(CgInfo), vp], i32),
         "gsf_power_filter_block": ([vp, i32, vp, vp, i32, vp, sz, vp], i32),
         "gsf_cg_filter_block": ([vp, i32, vp, vp, i32, dbl, vp, sz, P(CgInfo), vp], i32),
         "gsf_srgb_to_lab": ([i32, i64, vp, vp, vp], i32),
@@ -465,6 +466,16 @@ class Operator:
         st = _lib.gsf_cg_filter(self.handle, _ptr(x0), _ptr(y), kmax, tol, _ptr(ws), ws.numel(),
                                 ctypes.byref(inf) if info else None, _stream(stream))
         _check(st, "cg_filter")
+        return y, (inf if info else None)
+
+    def cg_filter_noalloc(self, x0, kmax, tol=0.0, out=None, info=True, stream=None):
+        """gsf_cg_filter_noalloc: the CG filter in the library's static scratch."""
+        torch = _torch()
+        y = out if out is not None else torch.empty_like(x0)
+        inf = CgInfo()
+        st = _lib.gsf_cg_filter_noalloc(self.handle, _ptr(x0), _ptr(y), kmax, tol,
+                                        ctypes.byref(inf) if info else None, _stream(stream))
+        _check(st, "cg_filter_noalloc")
         return y, (inf if info else None)
 
     def lobpcg_filter(self, x0, m, kmax, tol=0.0, constraint=False, out=None, ritz=None, ws=None, info=True,
