@@ -55,6 +55,11 @@ def _args():
     ap.add_argument("--no-study-1d", action="store_true", help="skip the 1D filter study (Section 6)")
     ap.add_argument("--no-colour", action="store_true", help="skip the colour (CIE-Lab guidance) measurement")
     ap.add_argument("--no-gf", action="store_true", help="skip the GF apply measurement (4096^2, r = 8)")
+    ap.add_argument("--no-1d", action="store_true", help="skip the 4096-sample 1D latency measurement")
+    ap.add_argument("--no-4096", action="store_true",
+                    help="skip the 4096^2 legs (BF 7x7 apply, precision study)")
+    ap.add_argument("--oracle-side", type=int, default=160,
+                    help="side of the image on which the precision study also runs the FP64 oracle")
     ap.add_argument("--learned-images", type=int, default=200, help="training images (10 pairs each)")
     ap.add_argument("--learned-eval", type=int, default=2048, help="side of the evaluation image")
     ap.add_argument("--precision-study", action="store_true",
@@ -426,9 +431,11 @@ def gf_apply_bench(copy_gbs, reps=20):
     """The GF apply (Algorithm 1 on the fixed guidance, normalized) on the
     4096^2 GF workload (radius 8, FP32) for m = 1 and 8 columns, L_sym form,
     timed with HIP events on the launch stream over `reps` launches, against
-    the HBM roofline.  Algorithmic bytes per point: x in and y out (4m each),
-    g, 1/sqrt(d), mu and 1/(var + eps) once (16), and the window
-    coefficients (a, b) written and read once (16m): 4(2m + 4) + 16m."""
+    the HBM roofline.  Algorithmic bytes per point are what Algorithm 1 must
+    move: x in and y out (4m each) and the guidance data g, mu_k and
+    1/(sigma_k^2 + eps) once (12): 4(3 + 2m).  Anything else the kernels move
+    (1/sqrt(d), intermediate window coefficients) is implementation traffic,
+    measured by the counters (profiles/)."""
     import torch
     import paper_1509_02468_amd as gsf
     from synth import WORKLOADS, make_signal
@@ -453,10 +460,96 @@ def gf_apply_bench(copy_gbs, reps=20):
         e1.record(s)
         e1.synchronize()
         us = e0.elapsed_time(e1) * 1e3 / reps
-        algo = n * (4 * (2 * m + 4) + 16 * m)
+        algo = n * 4 * (3 + 2 * m)
         gbs = algo / (us * 1e-6) / 1e9
         out[f"m{m}"] = {"us_per_apply": round(us, 1), "algorithmic_bytes": algo, "achieved_gbs": round(gbs, 1),
                         "frac": round(gbs / HBM_PEAK_GBS, 4), "frac_of_copy": round(gbs / copy_gbs, 4)}
+    return out
+
+
+def signal_1d_bench(reps=10):
+    """The 4096-sample 1D workload (BF radius 5, sigma_d 3, sigma_r 0.2,
+    FP64): microseconds per iteration of 30 power passes, 30 CG steps and 30
+    LOBPCG (m = 3) steps, each run timed whole with HIP events (median of
+    `reps`).  At 262 KB per apply this workload is bound by launch and
+    reduction latency, not by bandwidth."""
+    import torch
+    import paper_1509_02468_amd as gsf
+    from synth import WORKLOADS, make_signal
+    w = WORKLOADS["signal_1d_4096"]
+    _, noisy = make_signal("signal_1d_4096")
+    x0 = torch.tensor(noisy, dtype=torch.float64, device="cuda")
+    op = gsf.Operator("bf", w["shape"], x0, w["radius"], w["sigma_d"], w["sigma_r"], 0.0, gsf.F64)
+    y = torch.empty_like(x0)
+    wsp, wsc = op.workspace(gsf.METHOD_POWER), op.workspace(gsf.METHOD_CG)
+    m = w["lobpcg_m"]
+    wsl = op.workspace(gsf.METHOD_LOBPCG, m)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return float(np.median(ts))
+
+    out = {"workload": "signal_1d_4096 (n = 4096, BF r = 5, FP64)"}
+    for name, k, fn in (("power", w["power_iters"], lambda: op.power_filter(x0, w["power_iters"], out=y, ws=wsp)),
+                        ("cg", w["cg_iters"], lambda: op.cg_filter(x0, w["cg_iters"], out=y, ws=wsc, info=False)),
+                        ("lobpcg_m3", w["lobpcg_iters"],
+                         lambda: op.lobpcg_filter(x0, m, w["lobpcg_iters"], out=y, ws=wsl, info=False)),
+                        ("lobpcg_m3_constraint", w["lobpcg_iters"],
+                         lambda: op.lobpcg_filter(x0, m, w["lobpcg_iters"], constraint=True, out=y, ws=wsl,
+                                                  info=False))):
+        ms = timed(fn)
+        out[name] = {"iters": k, "ms": round(ms, 4), "us_per_iter": round(ms * 1e3 / k, 2)}
+    return out
+
+
+def image_4096_bf7_bench(copy_gbs, reps=20):
+    """The 4096^2 BF 7x7 apply (sigma_d 2, sigma_r 0.15, FP32), where the
+    working set (1.6 GB of weight planes) is far above the 256 MB
+    Infinity Cache: m = 1 and m = 8 columns, L_sym form, tile tuned, timed
+    with HIP events on the launch stream over `reps` launches.  Algorithmic
+    bytes per point 4 ((K + 1)/2 + 2m) with K = 49."""
+    import torch
+    import paper_1509_02468_amd as gsf
+    from synth import WORKLOADS, make_signal
+    w = WORKLOADS["image_4096_bf7"]
+    shape = w["shape"]
+    n = int(np.prod(shape))
+    _, noisy = make_signal("image_4096_bf7")
+    g = torch.tensor(noisy.ravel().astype(np.float32), device="cuda")
+    op = gsf.Operator("bf", shape, g, w["radius"], w["sigma_d"], w["sigma_r"], 0.0, gsf.F32)
+    K = (2 * w["radius"] + 1) ** 2
+    out = {"workload": f"image_4096_bf7 ({shape[0]}x{shape[1]}, BF {2 * w['radius'] + 1}x{2 * w['radius'] + 1}, "
+                       f"FP32), L_sym form", "copy_gbs": round(copy_gbs, 1)}
+    s = torch.cuda.current_stream()
+    for m in (1, 8):
+        x = torch.rand((n, m) if m > 1 else (n,), device="cuda", dtype=torch.float32)
+        y = torch.empty_like(x)
+        best, times = op.tune_apply(m, reps=10)
+        for _ in range(3):
+            op.apply(x, gsf.FORM_LSYM, out=y)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(reps):
+            op.apply(x, gsf.FORM_LSYM, out=y)
+        e1.record(s)
+        e1.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / reps
+        algo = n * 4 * ((K + 1) // 2 + 2 * m)
+        gbs = algo / (us * 1e-6) / 1e9
+        out[f"m{m}"] = {"us_per_apply": round(us, 1), "rows_per_thread": best,
+                        "us_by_rows_1_2_4": [round(t, 1) for t in times], "algorithmic_bytes": algo,
+                        "achieved_gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+                        "frac_of_copy": round(gbs / copy_gbs, 4)}
+        del x, y
     return out
 
 
@@ -582,10 +675,12 @@ def study_1d_bench(reps=3):
 
 
 def precision_study(oracle_side=384):
-    """Per-result errors of the precision modes: FP32 data with MFMA Gram and
-    FP64 Rayleigh-Ritz against the all-FP64 GPU run at 4096^2, and both
-    against the FP64 oracle at oracle_side^2 (same generator class and
-    operators; the oracle cannot run at 4096^2 in bounded time)."""
+    """Per-result errors of the precision modes (the 4096^2 workloads, BF 7x7
+    and GF radius 8, LOBPCG m = 8, 100 steps): FP32 data with MFMA Gram and
+    FP64 Rayleigh-Ritz against the all-FP64 GPU run at 4096^2 (Ritz values,
+    output, residuals, time per step), and both against the FP64 oracle at
+    oracle_side^2 (same generator class and operators; the oracle cannot run
+    at 4096^2 in bounded time)."""
     import torch
     import paper_1509_02468_amd as gsf
     import oracle
@@ -620,7 +715,8 @@ def precision_study(oracle_side=384):
                         "fp32_vs_fp64_theta_rel": float(np.abs(t32 / t64 - 1).max()),
                         "fp32_vs_fp64_y_rel": rel(y32, y64),
                         "fp32_res_max": float(r32.max()), "fp64_res_max": float(r64.max()),
-                        "fp32_s": round(s32, 3), "fp64_s": round(s64, 3)}}
+                        "fp32_s": round(s32, 3), "fp64_s": round(s64, 3),
+                        "fp32_ms_per_step": round(s32 * 1e3 / k, 3), "fp64_ms_per_step": round(s64 * 1e3 / k, 3)}}
         xs = scene_2d(oracle_side, oracle_side, w["sigma"], w["seed"])[1].astype(np.float32).astype(np.float64)
         shp = (oracle_side, oracle_side)
         ys32, ts32, _, _ = run(w["kind"], shp, xs, gsf.F32, w, m, k)
@@ -644,7 +740,7 @@ def main():
         import torch
         import paper_1509_02468_amd as gsf
         gsf.load_library()
-        print(json.dumps({"precision_study": precision_study()}))
+        print(json.dumps({"precision_study": precision_study(a.oracle_side)}))
         return
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is described in DESIGN.md"}))
@@ -799,6 +895,9 @@ def main():
     study_res = None if a.no_study_1d else study_1d_bench()
     colour_res = None if a.no_colour else colour_bench()
     gf_res = None if a.no_gf else gf_apply_bench(copy_gbs)
+    sig_res = None if a.no_1d else signal_1d_bench()
+    bf7_res = None if a.no_4096 else image_4096_bf7_bench(copy_gbs)
+    prec_res = None if a.no_4096 else precision_study(a.oracle_side)
     cpu = None if a.no_cpu else cpu_baseline(w, noisy, a.cpu_seconds)
     out = {"metric": "Mpixel-iters/s of Laplacian apply", "value": round(value, 1), "unit": "Mpixel-iters/s",
            "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(ms, 3),
@@ -809,7 +908,8 @@ def main():
                       "apply_tuning": tuned, "cg_lobpcg_mode": mode},
            "roofline": roofline, "cpu_baseline": cpu, "batch": batch, "learned": learned_res,
            "reguided": reguided_res, "image_experiment": image_res,
-           "study_1d": study_res, "colour": colour_res, "gf_apply": gf_res}
+           "study_1d": study_res, "colour": colour_res, "gf_apply": gf_res, "signal_1d_4096": sig_res,
+           "image_4096_bf7": bf7_res, "precision_study": prec_res}
     print(json.dumps(out), flush=True)
 
 
