@@ -809,7 +809,6 @@ struct LobRun {
     rr.theta = w.theta;
     rr.st = w.st;
     rr.drop_tol = init.drop_tol;
-    rr.conv2 = op.desc.prec == GSF_F32 ? 1e-20 : 1e-28;
     rr.zero_tol = init.zero_tol;
     if (constraint) GSF_TRY(lob_launch_ynorm(a, nb, s));
     GSF_TRY(lob_launch_mkernel(0, a, nb, m, 1, deg, s));  // X0

@@ -10,8 +10,9 @@
 //                  256 points then in FP64; FP64: v_mfma_f64_16x16x4f64)
 //   gram_reduce /  fixed-order two-level reduction of the tiles, then the
 //   gram_rr        Rayleigh-Ritz step on one workgroup in FP64: unit-diagonal scaling,
-//                  column-dropping Cholesky, reduction to L^-1 A L^-T, cyclic
-//                  parallel Jacobi eigensolver, m smallest Ritz pairs
+//                  column-dropping Cholesky, reduction to L^-1 A L^-T, the m
+//                  smallest eigenpairs (Householder tridiagonalisation,
+//                  bisection, inverse iteration), m smallest Ritz pairs
 //   lob_update     X = S C, AX = (AS) C, P = [W,P] C, AP likewise, the next
 //                  residual W = AX - X Theta and its norms (and Y^T W)
 //   lob_out_dots / lob_output: y = X X^T z0 (+ Y Y^T z0), x_out = y / sqrt(d)
@@ -333,10 +334,8 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
-// Reciprocal square root: the hardware approximation refined
-// by one Newton step (a few ulp), short dependency chains for the Jacobi
-// rotations.  The rotation stays orthogonal to rounding because c and s are
-// both derived from the same t: c = (1 + t^2)^-1/2, s = t c.
+// Reciprocal square root: the hardware approximation refined by one Newton
+// step (a few ulp).
 __device__ __forceinline__ double rsq_nr(double x) {
   double r = __builtin_amdgcn_rsq(x);
   const double e = fma(-x * r, r, 1.0);
@@ -358,11 +357,15 @@ struct RRShared {
   double SB[KMAX * LD];  // the same for B; work array of the Cholesky factorisation
   double L[KMAX * LD];   // Cholesky factor (dropped columns zero)
   double LK[KMAX * LD];  // compressed factor of the kept columns
-  double M[KMAX * LD];   // Jacobi matrix, two buffers
-  double M2[KMAX * LD];
-  double V[KMAX * LD];   // accumulated rotations, two buffers
-  double V2[KMAX * LD];
+  double M[KMAX * LD];   // the reduced matrix L^-1 A L^-T, then the tridiagonal rows
+  double M2[KMAX * LD];  // work array of the triangular solves
+  double V[KMAX * LD];   // eigenvectors (columns 0..m-1)
   double Cs[KMAX * 8];   // output coefficients, staged
+  double bc[2][KMAX];    // broadcast rows of the tridiagonalisation (v, w)
+  double H[KMAX][KMAX];  // reflector vectors v_j (row j) of the tridiagonalisation
+  double hb[KMAX];       // their factors beta_j
+  double lu[8][5][KMAX]; // inverse iteration: per eigenvector LU of T - lambda I (u0, u1, u2, f, swap)
+  double Y[8][KMAX];     // eigenvectors of T (rows of the lane-parallel phases)
   double delta[KMAX];
   double rinv[KMAX];
   double ev[KMAX];
@@ -370,72 +373,305 @@ struct RRShared {
   int kept[KMAX];
   int idx[KMAX];
   int order[KMAX];
+  int nk;                // kept columns (shared with the other waves)
 };
-// the Jacobi schedule table reuses A, B, SA and SB
-static_assert((KMAX - 1) * 3 * 64 * sizeof(uint32_t) <= 4 * sizeof(double) * KMAX * LD, "schedule table");
 
-// Players of pair `slot` in round `rnd` of the round-robin schedule over np
-// players (np even): player 0 stays, the others rotate.  p < q.
-__device__ __forceinline__ void rr_pair(int slot, int rnd, int np, int& p, int& q) {
-  const int n1 = np - 1;
-  int a = slot - 1 + rnd;
-  a = a >= n1 ? a - n1 : a;
-  int b = (np - 1 - slot) - 1 + rnd;
-  b = b >= n1 ? b - n1 : b;
-  const int pa = slot == 0 ? 0 : 1 + a, pb = 1 + b;
-  p = pa < pb ? pa : pb;
-  q = pa < pb ? pb : pa;
+// ---------------------------------------------------------------------------
+// Small symmetric eigenproblem: the m smallest eigenpairs of the K x K matrix
+// in sh.M (K <= KB <= 24), on the four waves of the workgroup:
+//  1. Householder tridiagonalisation T = Q^T M Q on wave 0 (lane i owns row i
+//     in registers; v and w of each reflector are broadcast through LDS;
+//     column sums by DPP within rows of 16 lanes);
+//  2. per eigenvalue, multisection bisection of the Sturm count: one wave per
+//     eigenvalue (two for m > 4), its 64 (32) lanes evaluate the count at
+//     evenly spaced shifts of the bracket, which shrinks by 65 (33) per round
+//     down to about 2^-60 of the Gershgorin interval; rows past K are padded
+//     with a diagonal far above the spectrum, so every loop has the fixed
+//     length KB and no branch;
+//  3. inverse iteration for its eigenvector in the first lane of the same
+//     wave: Gaussian elimination with partial pivoting of T - lambda I in
+//     registers, two solves from a fixed start vector;
+//  4. classical Gram-Schmidt, twice, over the m vectors on wave 0, which keeps
+//     the vectors of a cluster of eigenvalues orthonormal;
+//  5. back-transform z = Q y by the reflectors, one wave per vector.
+// Single-wave code is bound by the latency of its dependency chains; these
+// chains are short, branch-free and spread over four SIMDs.  The cyclic Jacobi
+// method this replaces ran 5-6 sweeps of K - 1 rounds, each an LDS round trip
+// and two chained rotations (38-45 us per call at K = 12).
+// ---------------------------------------------------------------------------
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+// Sum over the first KB lanes of the wave (lanes past the rows must hold 0),
+// returned to every lane; every lane must be active.
+template <int KB>
+__device__ __forceinline__ double sum_rows(double v) {
+  v += dpp_d<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+  v += dpp_d<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+  v += dpp_d<0x141>(v);  // row_half_mirror: the other quad of the half row
+  v += dpp_d<0x140>(v);  // row_mirror: the other half of the row
+  if constexpr (KB <= 16) return readlane_d(v, 0);
+  return readlane_d(v, 0) + readlane_d(v, 16);
 }
 
-// The Jacobi rotation J = [[c, s], [-s, c]] (rows and columns p, q) that
-// annihilates m_pq of the symmetric 2 x 2 block [[m_pp, m_pq], [m_pq, m_qq]]:
-// with d = m_qq - m_pp, h = sqrt(d^2 + 4 m_pq^2) and u = d + sign(d) h (the
-// root t = 2 m_pq / u of t^2 + 2 theta t - 1 = 0 of smaller magnitude,
-// theta = d / (2 m_pq)), c = |u| / sqrt(2 h |u|) and s = sign(u) 2 m_pq /
-// sqrt(2 h |u|), which is c = (1 + t^2)^-1/2, s = t c with one reciprocal
-// square root for both (so c^2 + s^2 = 1 to rounding).  The rotated diagonal
-// is m_pp - t m_pq, m_qq + t m_pq, with t m_pq = sign(u) 4 h m_pq^2 / (2 h |u|).
-// The identity when `live` is false (m_pq = 0, or q is the dummy player);
-// no branches, so every lane runs the same instruction stream.
-struct JRot {
-  double c, s, dp, dq;
-};
-__device__ __forceinline__ JRot jacobi_rot(double mpp, double mqq, double mpq, bool live) {
-  live = live && mpq != 0.0;
-  const double apq = live ? mpq : 1.0;  // keeps the dead lanes finite
-  const double d = mqq - mpp;
-  const double y = fma(d, d, 4.0 * apq * apq);
-  const double h = y * rsq_nr(y);
-  const double au = fabs(d) + h;
-  const double r2 = rsq_nr(2.0 * h * au);
-  const double sg = d >= 0.0 ? 1.0 : -1.0;
-  const double s = sg * (2.0 * apq * r2);
-  const double tm = sg * (4.0 * h * apq * apq * (r2 * r2));
-  JRot r;
-  r.c = live ? au * r2 : 1.0;
-  r.s = live ? s : 0.0;
-  r.dp = live ? mpp - tm : mpp;
-  r.dq = live ? mqq + tm : mqq;
-  return r;
+constexpr double kPadDiag = 1e4;  // diagonal of the padding rows: far above any Ritz value of L_sym (<= 2)
+
+// Number of eigenvalues of T below sigma: sign changes of the leading
+// principal minors p_i of T - sigma I (Sturm), by the three-term recurrence
+// p_i = (d_i - sigma) p_(i-1) - e_(i-1)^2 p_(i-2), no divisions; a zero minor
+// takes the sign opposite to its predecessor.  With Ritz values in [0, 2] and
+// at most 24 rows the minors stay within about 1e+-100 (the padding rows
+// multiply by ~1e4 each), so no rescaling is needed.
+template <int KB>
+__device__ __forceinline__ int sturm_count(const double (&d)[KB], const double (&e2)[KB], double sigma) {
+  double pm2 = 1.0, pm1 = d[0] - sigma;
+  pm1 = pm1 == 0.0 ? -1e-300 : pm1;
+  int c = pm1 < 0.0 ? 1 : 0;
+#pragma unroll
+  for (int i = 1; i < KB; ++i) {
+    double p = fma(d[i] - sigma, pm1, -e2[i - 1] * pm2);
+    p = p == 0.0 ? (pm1 < 0.0 ? 1e-300 : -1e-300) : p;
+    c += ((p < 0.0) != (pm1 < 0.0)) ? 1 : 0;
+    pm2 = pm1;
+    pm1 = p;
+  }
+  return c;
+}
+
+// Step 1 (wave 0): T = Q^T M Q; the rows of T back into sh.M, the reflector
+// vectors v_j into sh.H[j] and their factors into sh.hb.
+template <int KB>
+__device__ void tridiagonalize(RRShared& sh, int K) {
+  const int lane = threadIdx.x & 63;
+  const bool row = lane < KB;
+  const int li = lane < K ? lane : 0;
+  double a[KB];
+#pragma unroll
+  for (int k = 0; k < KB; ++k) a[k] = (lane < K && k < K) ? sh.M[li * LD + k] : 0.0;
+#pragma unroll
+  for (int j = 0; j + 2 < KB; ++j) {
+    const double xj = (lane > j && row) ? a[j] : 0.0;
+    const double s2 = sum_rows<KB>(xj * xj);
+    const double x0 = readlane_d(a[j], j + 1);
+    const double nrm = sqrt(s2);
+    const double alpha = x0 >= 0.0 ? -nrm : nrm;
+    const double v = lane == j + 1 ? x0 - alpha : xj;
+    const double vtv = 2.0 * (s2 - alpha * x0);
+    const double beta = vtv > 0.0 ? 2.0 / vtv : 0.0;
+    if (row) {
+      sh.bc[0][lane] = v;
+      sh.H[j][lane] = v;
+    }
+    if (lane == 0) sh.hb[j] = beta;
+    wave_fence();
+    double p0 = 0.0, p1 = 0.0;  // two chains: half the dependent FMAs
+#pragma unroll
+    for (int k = j + 1; k < KB; ++k) {
+      if ((k & 1) == 0) p0 = fma(a[k], sh.bc[0][k], p0);
+      else p1 = fma(a[k], sh.bc[0][k], p1);
+    }
+    const double p = (p0 + p1) * beta;
+    const double kc = 0.5 * beta * sum_rows<KB>(row ? v * p : 0.0);
+    const double w = p - kc * v;
+    if (row) sh.bc[1][lane] = w;
+    wave_fence();
+    // A -= v w^T + w v^T: columns left of j are untouched (their rows are
+    // already reduced, so w is zero there); column j takes w_j = p_j
+#pragma unroll
+    for (int k = j; k < KB; ++k) {
+      const double vk = k > j ? sh.bc[0][k] : 0.0;
+      a[k] -= v * sh.bc[1][k] + w * vk;
+    }
+    wave_fence();
+  }
+  if (row) {
+#pragma unroll
+    for (int k = 0; k < KB; ++k) sh.M[lane * LD + k] = a[k];
+  }
+}
+
+// Steps 2-3 (every wave): eigenvalues t = wave (and wave + 4 for m > 4) into
+// sh.ev[t], their eigenvectors of T into sh.Y[t].
+template <int KB>
+__device__ void eig_pairs(RRShared& sh, int K, int m) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // T with the padding rows: d = kPadDiag, e = 0 past row K - 1
+  double d[KB], e2[KB], eo[KB];
+  double glo = 0.0, ghi = 0.0, tnorm = 0.0;
+#pragma unroll
+  for (int i = 0; i < KB; ++i) {
+    d[i] = i < K ? sh.M[i * LD + i] : kPadDiag;
+    eo[i] = i + 1 < K ? sh.M[(i + 1) * LD + i] : 0.0;  // T[i+1][i] = T[i][i+1]
+    e2[i] = eo[i] * eo[i];
+    const double r = fabs(eo[i]) + (i > 0 ? fabs(eo[i - 1]) : 0.0);
+    if (i < K) {
+      glo = (i == 0 || d[i] - r < glo) ? d[i] - r : glo;
+      ghi = (i == 0 || d[i] + r > ghi) ? d[i] + r : ghi;
+      tnorm = fmax(tnorm, fabs(d[i]) + r);
+    }
+  }
+  const int half = m > 4 ? 1 : 0;            // two eigenvalues per wave
+  const int G = half ? 32 : 64;              // lanes per eigenvalue
+  const int rounds = half ? 12 : 10;         // 33^12, 65^10 > 2^60
+  const int sub = half ? (lane >> 5) : 0;
+  const int t = wave + 4 * sub;              // this lane's eigenvalue (t >= m: idle copy)
+  const int tc = t < m ? t : m - 1;
+  const int s = lane & (G - 1);
+  const double pad = 1e-14 * fmax(fabs(glo), fabs(ghi)) + 1e-300;
+  double lo = glo - pad, hi = ghi + pad;
+  for (int rnd = 0; rnd < rounds; ++rnd) {
+    const double step = (hi - lo) * (1.0 / (double)(G + 1));
+    const double sig = fma((double)(s + 1), step, lo);
+    const int c = sturm_count<KB>(d, e2, sig);
+    const unsigned long long bal = __ballot(c <= tc);
+    const unsigned long long grp = half ? ((bal >> (32 * sub)) & 0xFFFFFFFFull) : bal;
+    const int top = grp ? 63 - __clzll(grp) : -1;  // highest shift whose count is <= t
+    const double nlo = top >= 0 ? fma((double)(top + 1), step, lo) : lo;
+    const double nhi = top + 1 < G ? fma((double)(top + 2), step, lo) : hi;
+    lo = nlo;
+    hi = nhi;
+  }
+  const double lam = 0.5 * (lo + hi);
+  // inverse iteration in the first lane of each group
+  const double ptiny = 1e-16 * (tnorm > 0.0 ? tnorm : 1.0);
+  double u0[KB], u1[KB], u2[KB], f[KB], y[KB];
+  unsigned int sw = 0;
+  {
+    double c0 = d[0] - lam, c1 = eo[0], c2 = 0.0;
+#pragma unroll
+    for (int i = 0; i + 1 < KB; ++i) {
+      const double sb = eo[i], dn = d[i + 1] - lam, sp = eo[i + 1 < KB ? i + 1 : 0] * (i + 1 < KB - 1 ? 1.0 : 0.0);
+      const bool swp = fabs(sb) > fabs(c0);
+      const double piv = fabs(c0) > ptiny ? c0 : (c0 < 0.0 ? -ptiny : ptiny);
+      const double fi = swp ? c0 / sb : sb / piv;
+      u0[i] = swp ? sb : piv;
+      u1[i] = swp ? dn : c1;
+      u2[i] = swp ? sp : c2;
+      f[i] = fi;
+      sw |= swp ? (1u << i) : 0u;
+      const double n0 = swp ? c1 - fi * dn : dn - fi * c1;
+      const double n1 = swp ? c2 - fi * sp : sp - fi * c2;
+      c0 = n0;
+      c1 = n1;
+      c2 = 0.0;
+    }
+    u0[KB - 1] = fabs(c0) > ptiny ? c0 : (c0 < 0.0 ? -ptiny : ptiny);
+    u1[KB - 1] = 0.0;
+    u2[KB - 1] = 0.0;
+    f[KB - 1] = 0.0;
+#pragma unroll
+    for (int i = 0; i < KB; ++i) u0[i] = 1.0 / u0[i];  // the back substitution multiplies
+  }
+#pragma unroll
+  for (int i = 0; i < KB; ++i) y[i] = 1.0 + 0.05 * (double)(((i * 7 + tc * 13 + 3) % 11) - 5);
+  for (int it = 0; it < 2; ++it) {
+#pragma unroll
+    for (int i = 0; i + 1 < KB; ++i) {
+      const bool swp = (sw >> i) & 1u;
+      const double ri = y[i], rn = y[i + 1];
+      y[i] = swp ? rn : ri;
+      y[i + 1] = swp ? ri - f[i] * rn : rn - f[i] * ri;
+    }
+#pragma unroll
+    for (int i = KB - 1; i >= 0; --i) {
+      double v = y[i];
+      if (i + 1 < KB) v -= u1[i] * y[i + 1];
+      if (i + 2 < KB) v -= u2[i] * y[i + 2];
+      y[i] = v * u0[i];
+    }
+    double nn = 0.0;
+#pragma unroll
+    for (int i = 0; i < KB; ++i) nn = fma(y[i], y[i], nn);
+    const double sc = 1.0 / sqrt(nn);
+#pragma unroll
+    for (int i = 0; i < KB; ++i) y[i] *= sc;
+  }
+  if (s == 0 && t < m) {
+    sh.ev[t] = lam;
+#pragma unroll
+    for (int i = 0; i < KB; ++i) sh.Y[t][i] = i < K ? y[i] : 0.0;
+  }
+}
+
+// Step 4 (wave 0): classical Gram-Schmidt twice over sh.Y[0..m), lane = row.
+template <int KB>
+__device__ void orthonormalize(RRShared& sh, int m) {
+  const int lane = threadIdx.x & 63;
+  const bool row = lane < KB;
+  double z[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) z[q] = (q < m && row) ? sh.Y[q][row ? lane : 0] : 0.0;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    if (q < m) {
+#pragma unroll
+      for (int pass = 0; pass < 2; ++pass) {
+        double dq[8];
+#pragma unroll
+        for (int s = 0; s < q; ++s) dq[s] = sum_rows<KB>(z[s] * z[q]);
+#pragma unroll
+        for (int s = 0; s < q; ++s) z[q] -= dq[s] * z[s];
+      }
+      const double nq = sum_rows<KB>(z[q] * z[q]);
+      z[q] *= 1.0 / sqrt(nq);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 8; ++q)
+    if (q < m && row) sh.Y[q][lane] = z[q];
+}
+
+// Step 5 (every wave): z_t = Q y_t for t = wave (and wave + 4) into column t of sh.V.
+template <int KB>
+__device__ void back_transform(RRShared& sh, int K, int m) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const bool row = lane < KB;
+  const int t0 = wave, t1 = wave + 4;
+  double z0 = (t0 < m && row) ? sh.Y[t0][row ? lane : 0] : 0.0;
+  double z1 = (t1 < m && row) ? sh.Y[t1 < 8 ? t1 : 0][row ? lane : 0] : 0.0;
+#pragma unroll
+  for (int j = KB - 3; j >= 0; --j) {
+    const double vj = row ? sh.H[j][lane] : 0.0;
+    const double bj = sh.hb[j];
+    const double d0 = sum_rows<KB>(vj * z0);
+    const double d1 = sum_rows<KB>(vj * z1);
+    z0 -= (bj * d0) * vj;
+    z1 -= (bj * d1) * vj;
+  }
+  if (lane < K) {
+    if (t0 < m) sh.V[lane * LD + t0] = z0;
+    if (t1 < m) sh.V[lane * LD + t1] = z1;
+  }
 }
 
 // Solves the Rayleigh-Ritz problem for GA, GB (ns x ns, already loaded into
 // sh.A and sh.B): C (ns x m, row-major with leading dimension m) and theta
 // (ascending) of the m smallest Ritz pairs, the kept flags and their count.
-// Called by the 64 lanes of one wave; KB >= ns is the padded size of the
+// Called by all four waves of the workgroup (every thread must call it): the
+// sequential steps run on wave 0, the eigenpairs on all four, with workgroup
+// barriers between the phases.  KB >= ns is the padded size of the
 // triangular solves (the kept block is extended by an identity factor and
 // zero data there, which changes nothing and keeps the loops free of
 // conditionals).  Steps: symmetrise; scale to unit diag(GB) (columns with a
 // negligible diagonal are dropped); Cholesky GB = L L^T that drops columns
-// with a pivot below drop_tol; M = L^-1 GA L^-T on the kept columns; cyclic
-// Jacobi on M (parallel round-robin ordering, one 2 x 2 block of every
-// rotated pair of rows and columns per lane); C = L^-T Z.  Loads are issued
+// with a pivot below drop_tol; M = L^-1 GA L^-T on the kept columns; the m
+// smallest eigenpairs Z of M (tridiagonalisation, bisection, inverse
+// iteration on all four waves); C = L^-T Z.  Loads are issued
 // unconditionally (clamped indices) and only stores are masked, so a lane
 // never waits on a load inside a branch.
 template <int KB>
-__device__ void rayleigh_ritz_kb(RRShared& sh, int ns, int m, double drop_tol, double zero_tol, double conv2,
+__device__ void rayleigh_ritz_kb(RRShared& sh, int ns, int m, double drop_tol, double zero_tol,
                                  double* Cout, double* theta, int* kept_out, int* nkept_out) {
   const int lane = threadIdx.x & 63;
+  if (threadIdx.x < 64) {
   // unit-diagonal scaling: delta_j = diag(GB)_j^-1/2, 0 for a negligible column
   const int lj = lane < ns ? lane : 0;
   const double dl = sh.B[lj * LD + lj];
@@ -458,38 +694,49 @@ __device__ void rayleigh_ritz_kb(RRShared& sh, int ns, int m, double drop_tol, d
     sh.L[i * LD + j] = 0.0;
   }
   wave_fence();
-  // right-looking Cholesky of SB with column dropping: every lane computes the
-  // column entries it needs from SB itself (the same operations as the lane
-  // that stores them into L)
-  for (int j = 0; j < ns; ++j) {
-    const double piv = sh.SB[j * LD + j];
-    const int keep = sh.good[j] && piv > drop_tol;
-    const double ip = rsq_nr2(keep ? piv : 1.0);  // 1 / L_jj
-    if (lane == 0) {
-      sh.kept[j] = keep;
-      if (keep) sh.L[j * LD + j] = piv * ip;
-    }
-    const int rem = ns - j - 1;
-    for (int e = lane; e < rem * rem; e += 64) {
-      const int i = j + 1 + e / rem, l = j + 1 + (e - (e / rem) * rem);
-      const double lij = sh.SB[i * LD + j] * ip;
-      const double llj = sh.SB[l * LD + j] * ip;
-      const double bil = sh.SB[i * LD + l];
-      if (keep && l <= i) {
-        sh.SB[i * LD + l] = bil - lij * llj;
-        if (l == j + 1) sh.L[i * LD + j] = lij;
+  // right-looking Cholesky of SB with column dropping, lane i owning row i
+  // (lower triangle) in registers: column j's pivot comes from lane j, the
+  // column itself is broadcast through LDS for the rank-1 update of the rows
+  // below; a dropped column leaves L and the trailing rows unchanged
+  {
+    double sb[KB];
+#pragma unroll
+    for (int k = 0; k < KB; ++k) sb[k] = (lane < ns && k < ns) ? sh.SB[lj * LD + k] : 0.0;
+#pragma unroll
+    for (int j = 0; j < KB; ++j) {
+      if (j < ns) {
+        const double piv = readlane_d(sb[j], j);
+        const int keep = sh.good[j] && piv > drop_tol;
+        const double ip = rsq_nr2(keep ? piv : 1.0);  // 1 / L_jj
+        const double lij = sb[j] * ip;
+        if (lane == 0) sh.kept[j] = keep;
+        if (keep) {
+          if (lane > j && lane < ns) sh.L[lane * LD + j] = lij;
+          if (lane == j) sh.L[j * LD + j] = piv * ip;
+          if (lane < KB) sh.bc[0][lane] = lij;
+          wave_fence();
+#pragma unroll
+          for (int l = j + 1; l < KB; ++l) {
+            const double llj = sh.bc[0][l];
+            sb[l] = (lane > j && l <= lane) ? fma(-lij, llj, sb[l]) : sb[l];
+          }
+          wave_fence();
+        }
       }
     }
-    wave_fence();
   }
+  wave_fence();
   const int kp = lane < ns ? sh.kept[lane] : 0;
   const unsigned long long km = __ballot(kp);
   const int K = __popcll(km);
   if (kp) sh.idx[__popcll(km & ((1ull << lane) - 1ull))] = lane;
   if (lane < ns) kept_out[lane] = kp;
-  if (lane == 0) *nkept_out = K;
+  if (lane == 0) {
+    *nkept_out = K;
+    sh.nk = K;
+  }
   wave_fence();
-  if (K < m) return;
+  if (K >= m) {
   // compressed factor LK and reduced A (in M2), padded to KB x KB with the
   // identity and zeros; reciprocal pivots (1 on the padding)
   for (int e = lane; e < KB * KB; e += 64) {
@@ -545,133 +792,26 @@ __device__ void rayleigh_ritz_kb(RRShared& sh, int ns, int m, double drop_tol, d
     const int a = e / K, b = e - (e / K) * K;
     const double x = sh.M2[a * LD + b], y = sh.M2[b * LD + a];
     sh.M[a * LD + b] = 0.5 * (x + y);
-    sh.V[a * LD + b] = (a == b) ? 1.0 : 0.0;
   }
   wave_fence();
-
-  // cyclic Jacobi: in each round the np/2 disjoint pairs of the round-robin
-  // schedule are rotated together, M <- J^T M J, V <- V J.  Lane b owns the
-  // 2 x 2 block (pair P = b / nh rows, pair Q = b % nh columns) and computes
-  // both rotations itself (bitwise the same on every lane that needs them).
-  // The schedule is tabulated once per call (one word per round, block slot
-  // and lane, in the Gram and scaled arrays, which are dead by now), and the
-  // round loop alternates the two buffers explicitly so that every LDS
-  // address is a table offset plus a constant.
-  const int np = (K + 1) & ~1;  // players (a dummy when K is odd)
-  const int nh = np >> 1, nblk = nh * nh, nr = np - 1;
-  const int nslot = (nblk + 63) >> 6;
-  uint32_t* tab = reinterpret_cast<uint32_t*>(sh.A);  // (KMAX-1) x 3 x 64 words fit in A, B, SA, SB
-  for (int r = 0; r < nr; ++r) {
-    for (int sl = 0; sl < nslot; ++sl) {
-      const int bl = sl * 64 + lane;
-      const int b = bl < nblk ? bl : 0;
-      const int P = b / nh, Q = b - (b / nh) * nh;
-      int i0, i1, j0, j1;
-      rr_pair(P, r, np, i0, i1);
-      rr_pair(Q, r, np, j0, j1);
-      const uint32_t ri = i1 < K, rj = j1 < K;  // the second player is not the dummy
-      const uint32_t i1c = ri ? i1 : i0, j1c = rj ? j1 : j0;
-      tab[(r * nslot + sl) * 64 + lane] = (uint32_t)i0 | (i1c << 5) | ((uint32_t)j0 << 10) | (j1c << 15) |
-                                          (ri << 20) | (rj << 21) | ((uint32_t)(bl < nblk) << 22) |
-                                          ((uint32_t)(P == Q) << 23);
-    }
-  }
-  wave_fence();
-  auto jround = [&](int rnd, const double* __restrict__ Mc, double* __restrict__ Mn, const double* __restrict__ Vc,
-                    double* __restrict__ Vn) {
-    for (int sl = 0; sl < nslot; ++sl) {
-      const uint32_t w = tab[(rnd * nslot + sl) * 64 + lane];
-      const int i0 = w & 31, i1 = (w >> 5) & 31, j0 = (w >> 10) & 31, j1 = (w >> 15) & 31;
-      const bool ri = (w >> 20) & 1, rj = (w >> 21) & 1, act = (w >> 22) & 1, dg = (w >> 23) & 1;
-      const int a0 = i0 * LD, a1 = i1 * LD, b0 = j0 * LD, b1 = j1 * LD;
-      const double m00 = Mc[a0 + j0], m01 = Mc[a0 + j1], m10 = Mc[a1 + j0], m11 = Mc[a1 + j1];
-      const double pp = Mc[a0 + i0], qq = Mc[a1 + i1], pq = Mc[a0 + i1];
-      const double rr = Mc[b0 + j0], ss = Mc[b1 + j1], rs = Mc[b0 + j1];
-      const double v00 = Vc[a0 + j0], v01 = Vc[a0 + j1], v10 = Vc[a1 + j0], v11 = Vc[a1 + j1];
-      const JRot jp = jacobi_rot(pp, qq, pq, ri);
-      const JRot jq = jacobi_rot(rr, ss, rs, rj);
-      // X = J_P^T B, B' = X J_Q
-      const double x00 = jp.c * m00 - jp.s * m10, x01 = jp.c * m01 - jp.s * m11;
-      const double x10 = jp.s * m00 + jp.c * m10, x11 = jp.s * m01 + jp.c * m11;
-      double y00 = x00 * jq.c - x01 * jq.s, y01 = x00 * jq.s + x01 * jq.c;
-      double y10 = x10 * jq.c - x11 * jq.s, y11 = x10 * jq.s + x11 * jq.c;
-      if (dg) {  // the rotated pair itself: exact zero off the diagonal
-        y00 = jp.dp;
-        y11 = jp.dq;
-        y01 = 0.0;
-        y10 = 0.0;
-      }
-      if (act) {
-        Mn[a0 + j0] = y00;
-        Vn[a0 + j0] = v00 * jq.c - v01 * jq.s;
-        if (rj) {
-          Mn[a0 + j1] = y01;
-          Vn[a0 + j1] = v00 * jq.s + v01 * jq.c;
-        }
-        if (ri) {
-          Mn[a1 + j0] = y10;
-          Vn[a1 + j0] = v10 * jq.c - v11 * jq.s;
-        }
-        if (ri && rj) {
-          Mn[a1 + j1] = y11;
-          Vn[a1 + j1] = v10 * jq.s + v11 * jq.c;
-        }
-      }
-    }
-  };
-  // convergence: off-diagonal Frobenius mass below sqrt(conv2) of the whole
-  // (relative: 1e-14 for FP64 data, 1e-10 for FP32 data, whose Gram entries
-  // carry ~1e-7 relative errors anyway); the butterfly sum leaves the same
-  // value on every lane
-  const double c2 = conv2 > 0.0 ? conv2 : 1e-28;
-  auto converged = [&](const double* Mc) {
-    double off = 0.0, dia = 0.0;
-    for (int e = lane; e < K * K; e += 64) {
-      const int i = e / K, j = e - (e / K) * K;
-      const double v = Mc[i * LD + j] * Mc[i * LD + j];
-      off += i == j ? 0.0 : v;
-      dia += i == j ? v : 0.0;
-    }
-    off = wave_sum(off);
-    dia = wave_sum(dia);
-    return off <= c2 * (off + dia);
-  };
-  int rnd = 0, sweep = 0, cur = 0;  // cur = 1: the current matrix is in M2, V2
-  while (true) {
-    jround(rnd, sh.M, sh.M2, sh.V, sh.V2);
-    wave_fence();
-    cur = 1;
-    if (++rnd == nr) {
-      rnd = 0;
-      if (converged(sh.M2) || ++sweep == 30) break;
-    }
-    jround(rnd, sh.M2, sh.M, sh.V2, sh.V);
-    wave_fence();
-    cur = 0;
-    if (++rnd == nr) {
-      rnd = 0;
-      if (converged(sh.M) || ++sweep == 30) break;
-    }
-  }
-  const double* Mc = cur ? sh.M2 : sh.M;
-  const double* Vc = cur ? sh.V2 : sh.V;
-  // order eigenvalues ascending (ties by index)
-  {
-    const int li = lane < K ? lane : 0;
-    sh.ev[lane < KB ? lane : 0] = Mc[li * LD + li];  // lanes >= K store junk past K (never read)
-  }
+  tridiagonalize<KB>(sh, K);
+  }  // K >= m
+  }  // wave 0
+  __syncthreads();
+  const int K = sh.nk;
+  if (K < m) return;
+  // the m smallest eigenpairs of M: eigenvalues ascending in ev[0..m),
+  // eigenvectors in the columns 0..m-1 of V
+  eig_pairs<KB>(sh, K, m);
+  __syncthreads();
+  if (threadIdx.x < 64) orthonormalize<KB>(sh, m);
+  __syncthreads();
+  back_transform<KB>(sh, K, m);
+  __syncthreads();
+  if (threadIdx.x >= 64) return;
+  const double* Vc = sh.V;
+  if (lane < m) sh.order[lane] = lane;
   for (int e = lane; e < ns * m; e += 64) sh.Cs[e] = 0.0;
-  wave_fence();
-  {
-    const double e = sh.ev[lane < K ? lane : 0];
-    int rank = 0;
-#pragma unroll
-    for (int j = 0; j < KB; ++j) {
-      const double ej = sh.ev[j];
-      rank += (j < K && (ej < e || (ej == e && j < lane))) ? 1 : 0;
-    }
-    if (lane < K) sh.order[rank] = lane;
-  }
   wave_fence();
   // C_K = LK^-T Z_m: lane t solves LK^T c = Z[:, order[t]] by back substitution
   {
@@ -711,18 +851,18 @@ __device__ void rayleigh_ritz_kb(RRShared& sh, int ns, int m, double drop_tol, d
   for (int e = lane; e < ns * m; e += 64) Cout[e] = sh.Cs[e];
 }
 
-__device__ void rayleigh_ritz(RRShared& sh, int ns, int m, double drop_tol, double zero_tol, double conv2,
+__device__ void rayleigh_ritz(RRShared& sh, int ns, int m, double drop_tol, double zero_tol,
                               double* Cout, double* theta, int* kept_out, int* nkept_out) {
   if (ns <= 4)
-    rayleigh_ritz_kb<4>(sh, ns, m, drop_tol, zero_tol, conv2, Cout, theta, kept_out, nkept_out);
+    rayleigh_ritz_kb<4>(sh, ns, m, drop_tol, zero_tol, Cout, theta, kept_out, nkept_out);
   else if (ns <= 8)
-    rayleigh_ritz_kb<8>(sh, ns, m, drop_tol, zero_tol, conv2, Cout, theta, kept_out, nkept_out);
+    rayleigh_ritz_kb<8>(sh, ns, m, drop_tol, zero_tol, Cout, theta, kept_out, nkept_out);
   else if (ns <= 12)
-    rayleigh_ritz_kb<12>(sh, ns, m, drop_tol, zero_tol, conv2, Cout, theta, kept_out, nkept_out);
+    rayleigh_ritz_kb<12>(sh, ns, m, drop_tol, zero_tol, Cout, theta, kept_out, nkept_out);
   else if (ns <= 16)
-    rayleigh_ritz_kb<16>(sh, ns, m, drop_tol, zero_tol, conv2, Cout, theta, kept_out, nkept_out);
+    rayleigh_ritz_kb<16>(sh, ns, m, drop_tol, zero_tol, Cout, theta, kept_out, nkept_out);
   else
-    rayleigh_ritz_kb<KMAX>(sh, ns, m, drop_tol, zero_tol, conv2, Cout, theta, kept_out, nkept_out);
+    rayleigh_ritz_kb<KMAX>(sh, ns, m, drop_tol, zero_tol, Cout, theta, kept_out, nkept_out);
 }
 
 // First stage of the Gram reduction: workgroup (tile, chunk) sums the partials
@@ -755,17 +895,37 @@ __global__ void __launch_bounds__(kThreads) gram_rr_kernel(GramArgs g, RRArgs r)
   __shared__ double fred[8 * 16];
   __shared__ int live;
   if (r.st != nullptr && !r.st->active) return;
+  const int nt = (g.ns + 15) >> 4;
+  const int ntb = n_tiles_b(nt), ntot = ntb + n_tiles_a(nt);
+  // Everything this kernel reads from global memory was written by other
+  // workgroups of earlier kernels (other XCDs), so each load is a long trip:
+  // the first batch of Gram chunk values and the residual partials are all
+  // issued before any of them is used.
+  double v0[kGramChunks];
+#pragma unroll
+  for (int c = 0; c < kGramChunks; ++c) v0[c] = g.level2[(size_t)c * (ntot * 256) + threadIdx.x];
   if (r.fin_partials != nullptr) {
     // the previous update's residual norms, iteration count and convergence
     // test (what lob_final_kernel does after an update without the
-    // constraint, in the same summation order)
+    // constraint, in the same summation order); at most 1024 partial rows
     double t[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) t[k] = 0.0;
-    for (int b = threadIdx.x; b < r.fin_nparts; b += blockDim.x) {
+    for (int b0 = 0; b0 < r.fin_nparts; b0 += 4 * (int)blockDim.x) {
+      double fv[4][8];
 #pragma unroll
-      for (int k = 0; k < 8; ++k)
-        if (k < g.m) t[k] += r.fin_partials[(size_t)b * r.fin_stride + k];
+      for (int it = 0; it < 4; ++it) {
+        const int b = b0 + it * (int)blockDim.x + (int)threadIdx.x;
+        const int bb = b < r.fin_nparts ? b : 0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) fv[it][k] = r.fin_partials[(size_t)bb * r.fin_stride + (k < g.m ? k : 0)];
+      }
+#pragma unroll
+      for (int it = 0; it < 4; ++it) {
+        const bool ok = b0 + it * (int)blockDim.x + (int)threadIdx.x < r.fin_nparts;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) t[k] += (ok && k < g.m) ? fv[it][k] : 0.0;
+      }
     }
     block_sum<8>(t, fred);
     if (threadIdx.x == 0) {
@@ -783,12 +943,8 @@ __global__ void __launch_bounds__(kThreads) gram_rr_kernel(GramArgs g, RRArgs r)
     __syncthreads();
     if (!live) return;
   }
-  const int nt = (g.ns + 15) >> 4;
-  const int ntb = n_tiles_b(nt), ntot = ntb + n_tiles_a(nt);
-  for (int e = threadIdx.x; e < ntot * 256; e += blockDim.x) {
-    double v[kGramChunks];
-#pragma unroll
-    for (int c = 0; c < kGramChunks; ++c) v[c] = g.level2[(size_t)c * (ntot * 256) + e];
+  // entry e of the Gram tiles (chunk sums in v) into sh.A / sh.B
+  auto place = [&](int e, const double (&v)[kGramChunks]) {
     double s = 0.0;
 #pragma unroll
     for (int c = 0; c < kGramChunks; ++c) s += v[c];
@@ -815,6 +971,13 @@ __global__ void __launch_bounds__(kThreads) gram_rr_kernel(GramArgs g, RRArgs r)
         sh.A[row * LD + colj] = s;
       }
     }
+  };
+  place(threadIdx.x, v0);  // ntot >= 2: every thread has a first entry
+  for (int e = threadIdx.x + blockDim.x; e < ntot * 256; e += blockDim.x) {
+    double v[kGramChunks];
+#pragma unroll
+    for (int c = 0; c < kGramChunks; ++c) v[c] = g.level2[(size_t)c * (ntot * 256) + e];
+    place(e, v);
   }
   __syncthreads();
   if (r.gram_out != nullptr) {
@@ -824,8 +987,8 @@ __global__ void __launch_bounds__(kThreads) gram_rr_kernel(GramArgs g, RRArgs r)
       r.gram_out[g.ns * g.ns + e] = sh.B[i * LD + j];
     }
   }
+  rayleigh_ritz(sh, g.ns, g.m, r.drop_tol, r.zero_tol, r.C, r.theta, keptf, &nkept);
   if (threadIdx.x >= 64) return;
-  rayleigh_ritz(sh, g.ns, g.m, r.drop_tol, r.zero_tol, r.conv2, r.C, r.theta, keptf, &nkept);
   wave_fence();
   if (threadIdx.x == 0 && r.st != nullptr) {
     LobpcgState* st = r.st;
@@ -1137,8 +1300,8 @@ __global__ void __launch_bounds__(kThreads) rr_only_kernel(const double* __restr
     sh.B[i * LD + j] = G[ns * ns + e];
   }
   __syncthreads();
+  rayleigh_ritz(sh, ns, m, r.drop_tol, r.zero_tol, r.C, r.theta, keptf, &nkept);
   if (threadIdx.x >= 64) return;
-  rayleigh_ritz(sh, ns, m, r.drop_tol, r.zero_tol, r.conv2, r.C, r.theta, keptf, &nkept);
   wave_fence();
   if ((int)threadIdx.x < ns) r.kept_out[threadIdx.x] = keptf[threadIdx.x];
   if (threadIdx.x == 0) *r.nkept_out = nkept;

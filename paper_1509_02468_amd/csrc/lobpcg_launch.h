@@ -46,7 +46,6 @@ struct RRArgs {
   double* theta;
   LobpcgState* st;     // nullable
   double drop_tol, zero_tol;
-  double conv2;        // Jacobi stop: off-diagonal mass <= conv2 * total (0: 1e-28)
   // nullable: per-workgroup partials of the previous update (stride values
   // per workgroup, residual norms first) to finalize before the Rayleigh-Ritz
   // step, in place of a separate finalize launch (no constraint)
