@@ -213,10 +213,15 @@ void gsf_destroy_operator(gsf_operator* op);
 /* ---- apply (eqs. (1), (3), (4); Section 4) --------------------------------
  * y = F x for a block of m (1..8) vectors, F = N, L_sym, D^-1 W or the
  * Laplacian L = D - W (`form`).  N and L_sym act on z-space vectors
- * (z = D^1/2 x); RW and L act on x directly.  x and y: n*m elements,
- * point-major; y must not overlap x.  GSF_EINVAL for another form. */
-gsf_status gsf_apply(const gsf_operator* op, int form, int m, const void* x, void* y,
-                     void* stream);
+ * (z = D^1/2 x); RW and L act on x directly.  Column j of grid point i is
+ * x[i*ldx + j] and y[i*ldy + j]: ldx, ldy >= m are the elements between
+ * consecutive points (0 means m, the dense point-major block), so that m
+ * columns of a wider point-major array can be applied in place; x must hold
+ * (n-1)*ldx + m elements, y (n-1)*ldy + m.  The extents of x and y must not
+ * overlap.  GSF_EINVAL for another form, m outside 1..8, ldx or ldy below m
+ * (other than 0), or overlapping extents. */
+gsf_status gsf_apply(const gsf_operator* op, int form, int m, const void* x, int64_t ldx, void* y,
+                     int64_t ldy, void* stream);
 /* Joint apply: y = F x for an n x m block and y2 = F x2 for one more vector,
  * in one pass over the operator where it offers that (BF on the square
  * window or 1D, m = 1 or 4), else as two applies.  No output may overlap an
@@ -316,6 +321,8 @@ gsf_status gsf_srgb_to_lab(int prec, int64_t n, const void* rgb, void* lab, void
  * <= tau^2 max norm^2), keep the m smallest Ritz pairs, P = [W, P] C.
  * Output x_out = D^-1/2 (X X^T z0 (+ Y Y^T z0)), n elements.
  * ritz_vecs (NULL or n*m, z-space, column signs with x_j^T z0 >= 0).
+ * ritz_vals_host (NULL or m host doubles): the Ritz values theta_j ascending;
+ * non-NULL synchronizes the stream, as a non-NULL info does.
  * tol > 0 stops when every column residual <= tol (GSF_ENOTCONV if not met);
  * with info != NULL the host then also stops issuing steps (it reads the
  * device convergence flag every 16 steps, 16 steps behind the queue).
@@ -328,8 +335,8 @@ gsf_status gsf_srgb_to_lab(int prec, int64_t n, const void* rgb, void* lab, void
 typedef struct gsf_precond gsf_precond;
 gsf_status gsf_lobpcg_filter(const gsf_operator* op, const void* x0, void* x_out, int m,
                              int kmax, double tol, int constraint, const gsf_precond* T,
-                             void* ritz_vecs, void* ws, size_t ws_bytes, gsf_lobpcg_info* info,
-                             void* stream);
+                             void* ritz_vecs, double* ritz_vals_host, void* ws, size_t ws_bytes,
+                             gsf_lobpcg_info* info, void* stream);
 
 /* Joint CG + LOBPCG filters of one operator (Algorithms 2 and 3 side by side):
  * the results are those of gsf_cg_filter(x0_cg, kmax_cg, tol 0) and
@@ -539,6 +546,13 @@ gsf_status gsf_batch_create(const gsf_batch_item* items, int count, void* ws, si
 gsf_status gsf_batch_run(gsf_batch* batch, void* stream);
 gsf_status gsf_batch_get_info(const gsf_batch* batch, gsf_batch_info* info, void* stream);
 void gsf_batch_destroy(gsf_batch* batch);
+/* gsf_batch_filter: the whole batch in one call (create without autotuning
+ *   or graphs, run, read the info, destroy): ws as for gsf_batch_create, info
+ *   NULL or a host array of count summaries.  The plan's branch streams are
+ *   destroyed before returning, so the call synchronizes `stream`.  Returns
+ *   the first item status other than OK, ENOTCONV or EBREAKDOWN, else OK. */
+gsf_status gsf_batch_filter(const gsf_batch_item* items, int count, void* ws, size_t ws_bytes,
+                            gsf_batch_info* info, void* stream);
 
 /* ---- diagnostic entry points (the solver's inner kernels on caller data) ----
  * gsf_block_gram: the Gram pair of the LOBPCG Rayleigh-Ritz step (Algorithm 3,

@@ -542,16 +542,22 @@ gsf_status gsf_operator_get_layout(const gsf_operator* h, gsf_operator_layout* o
 
 void gsf_destroy_operator(gsf_operator* h) { delete h; }
 
-gsf_status gsf_apply(const gsf_operator* h, int form, int m, const void* x, void* y, void* stream) {
+gsf_status gsf_apply(const gsf_operator* h, int form, int m, const void* x, int64_t ldx, void* y, int64_t ldy,
+                     void* stream) {
   clear_stale_errors();
   if (h == nullptr || x == nullptr || y == nullptr) return GSF_EINVAL;
   if (form != GSF_FORM_N && form != GSF_FORM_LSYM && form != GSF_FORM_RW && form != GSF_FORM_L) return GSF_EINVAL;
   if (m < 1 || m > kMaxBlock) return GSF_EINVAL;
+  if (ldx == 0) ldx = m;
+  if (ldy == 0) ldy = m;
+  if (ldx < m || ldy < m) return GSF_EINVAL;
   const Operator& op = h->op;
-  const size_t bytes = (size_t)op.n * m * op.elem;
+  // extents: (n - 1) ld + m elements
+  const size_t xb = ((size_t)(op.n - 1) * (size_t)ldx + (size_t)m) * op.elem;
+  const size_t yb = ((size_t)(op.n - 1) * (size_t)ldy + (size_t)m) * op.elem;
   const char *xa = (const char*)x, *ya = (const char*)y;
-  if (xa < ya + bytes && ya < xa + bytes) return GSF_EINVAL;  // overlap
-  return apply_any(op, form, m, x, m, y, m, nullptr, nullptr, (hipStream_t)stream);
+  if (xa < ya + yb && ya < xa + xb) return GSF_EINVAL;  // overlap
+  return apply_any(op, form, m, x, ldx, y, ldy, nullptr, nullptr, (hipStream_t)stream);
 }
 
 gsf_status gsf_apply_joint(const gsf_operator* h, int form, int m, const void* x, void* y, const void* x2, void* y2,
@@ -972,8 +978,8 @@ gsf_status gsf_cg_filter_noalloc(const gsf_operator* h, const void* x0, void* x_
 }
 
 gsf_status gsf_lobpcg_filter(const gsf_operator* h, const void* x0, void* x_out, int m, int kmax, double tol,
-                             int constraint, const gsf_precond* T, void* ritz_vecs, void* ws, size_t ws_bytes,
-                             gsf_lobpcg_info* info, void* stream) {
+                             int constraint, const gsf_precond* T, void* ritz_vecs, double* ritz_vals_host, void* ws,
+                             size_t ws_bytes, gsf_lobpcg_info* info, void* stream) {
   clear_stale_errors();
   if (h == nullptr || x0 == nullptr || x_out == nullptr || kmax < 0 || !(tol >= 0.0) || !std::isfinite(tol))
     return GSF_EINVAL;
@@ -992,7 +998,12 @@ gsf_status gsf_lobpcg_filter(const gsf_operator* h, const void* x0, void* x_out,
     GSF_TRY(lob.apply());
     GSF_TRY(lob.post(k));
   }
-  return lob.finish(tol, info);
+  if (ritz_vals_host == nullptr) return lob.finish(tol, info);
+  gsf_lobpcg_info local{};
+  gsf_lobpcg_info* out = info != nullptr ? info : &local;
+  const gsf_status st = lob.finish(tol, out);
+  for (int j = 0; j < m; ++j) ritz_vals_host[j] = out->theta[j];
+  return st;
 }
 
 // The device's second stream (one per device, created on first use and kept

@@ -103,7 +103,8 @@ gsf_status issue_item(gsf_batch* b, int i, hipStream_t s) {
   if (it.method == GSF_METHOD_POWER) return gsf_power_filter(b->ops[i], it.x0, it.x_out, it.kmax, sw, sb, s);
   if (it.method == GSF_METHOD_CG)
     return gsf_cg_filter(b->ops[i], it.x0, it.x_out, it.kmax, it.tol, sw, sb, nullptr, s);
-  return gsf_lobpcg_filter(b->ops[i], it.x0, it.x_out, it.m, it.kmax, it.tol, it.constraint, nullptr, nullptr, sw, sb,
+  return gsf_lobpcg_filter(b->ops[i], it.x0, it.x_out, it.m, it.kmax, it.tol, it.constraint, nullptr, nullptr, nullptr,
+                           sw, sb,
                            nullptr, s);
 }
 
@@ -307,5 +308,26 @@ gsf_status gsf_batch_get_info(const gsf_batch* b, gsf_batch_info* info, void* st
 }
 
 void gsf_batch_destroy(gsf_batch* b) { free_batch(b); }
+
+gsf_status gsf_batch_filter(const gsf_batch_item* items, int count, void* ws, size_t ws_bytes, gsf_batch_info* info,
+                            void* stream) {
+  gsf_batch* b = nullptr;
+  gsf_status st = gsf_batch_create(items, count, ws, ws_bytes, 0, &b);
+  if (st != GSF_OK) return st;
+  st = gsf_batch_run(b, stream);
+  if (st == GSF_OK) {
+    std::vector<gsf_batch_info> local;
+    if (info == nullptr) local.resize(count);
+    gsf_batch_info* out = info != nullptr ? info : local.data();
+    st = gsf_batch_get_info(b, out, stream);  // synchronizes the stream
+    for (int i = 0; st == GSF_OK && i < count; ++i)
+      if (out[i].status != GSF_OK && out[i].status != GSF_ENOTCONV && out[i].status != GSF_EBREAKDOWN)
+        st = (gsf_status)out[i].status;
+  } else {
+    (void)hipStreamSynchronize((hipStream_t)stream);
+  }
+  gsf_batch_destroy(b);
+  return st;
+}
 
 }  // extern "C"

@@ -100,7 +100,7 @@ def load_library(path: str = LIB_PATH):
         "gsf_build_operator": ([P(OperatorDesc), vp, vp, sz, vp, P(vp)], i32),
         "gsf_operator_get_layout": ([vp, P(OperatorLayout)], i32),
         "gsf_destroy_operator": ([vp], None),
-        "gsf_apply": ([vp, i32, i32, vp, vp, vp], i32),
+        "gsf_apply": ([vp, i32, i32, vp, i64, vp, i64, vp], i32),
         "gsf_solver_workspace_bytes": ([vp, i32, i32, P(sz)], i32),
         "gsf_power_filter": ([vp, vp, vp, i32, vp, sz, vp], i32),
         "gsf_cg_filter": ([vp, vp, vp, i32, dbl, vp, sz, P(CgInfo), vp], i32),
@@ -113,7 +113,7 @@ def load_library(path: str = LIB_PATH):
         "gsf_joint_filter": ([vp, vp, vp, i32, vp, vp, i32, i32, i32, vp, sz, P(CgInfo), P(LobpcgInfo), vp], i32),
         "gsf_reguided_workspace_bytes": ([P(OperatorDesc), i32, P(sz)], i32),
         "gsf_reguided_filter": ([P(OperatorDesc), i32, vp, vp, i32, dbl, vp, sz, P(CgInfo), vp], i32),
-        "gsf_lobpcg_filter": ([vp, vp, vp, i32, i32, dbl, i32, vp, vp, vp, sz, P(LobpcgInfo), vp], i32),
+        "gsf_lobpcg_filter": ([vp, vp, vp, i32, i32, dbl, i32, vp, vp, P(dbl), vp, sz, P(LobpcgInfo), vp], i32),
         "gsf_block_gram": ([i32, i64, i32, i32, P(vp), P(vp), vp, vp, vp, sz, vp], i32),
         "gsf_block_gram_workspace_bytes": ([i64, P(sz)], i32),
         "gsf_rayleigh_ritz": ([i32, i32, vp, vp, dbl, dbl, vp, vp, vp, vp, vp, sz, vp], i32),
@@ -125,6 +125,7 @@ def load_library(path: str = LIB_PATH):
         "gsf_batch_run": ([vp, vp], i32),
         "gsf_batch_get_info": ([vp, P(BatchInfo), vp], i32),
         "gsf_batch_destroy": ([vp], None),
+        "gsf_batch_filter": ([P(BatchItem), i32, vp, sz, P(BatchInfo), vp], i32),
         "gsf_net_workspace_bytes": ([i32, i64, i64, P(sz)], i32),
         "gsf_net_forward": ([vp, i32, vp, i64, i64, vp, vp, vp, sz, vp], i32),
         "gsf_net_loss_grad": ([vp, i32, vp, i64, i64, vp, vp, vp, vp, vp, sz, vp], i32),
@@ -248,27 +249,40 @@ class Batch:
 
     METHODS = {"power": METHOD_POWER, "cg": METHOD_CG, "lobpcg": METHOD_LOBPCG}
 
-    def __init__(self, items, prec=F32, autotune=True, graphs=False):
+    @classmethod
+    def describe(cls, items, prec):
+        """The gsf_batch_item array of `items` (outputs allocated into item["out"])."""
         torch = _torch()
-        lib = load_library()
-        self.items = items
-        self.arr = (BatchItem * len(items))()
+        arr = (BatchItem * len(items))()
         for k, it in enumerate(items):
             it.setdefault("out", torch.empty_like(it["x0"]))
-            b = self.arr[k]
+            b = arr[k]
             b.op = make_desc(it["kind"], it["shape"], it["radius"], it.get("sigma_d", 0.0), it.get("sigma_r", 0.0),
                              it.get("eps", 0.0), prec, it.get("stencil", "square"), it.get("norm", "d"))
             b.guidance = it["guidance"].data_ptr()
             b.x0 = it["x0"].data_ptr()
             b.x_out = it["out"].data_ptr()
-            b.method = self.METHODS[it["method"]]
+            b.method = cls.METHODS[it["method"]]
             b.m = it.get("m", 1)
             b.kmax = it["kmax"]
             b.constraint = int(bool(it.get("constraint", False)))
             b.tol = it.get("tol", 0.0)
+        return arr
+
+    @staticmethod
+    def workspace(arr, count):
+        torch = _torch()
         nbytes = ctypes.c_size_t()
-        _check(lib.gsf_batch_workspace_bytes(self.arr, len(items), ctypes.byref(nbytes)), "batch_workspace_bytes")
-        self.ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device="cuda")
+        _check(load_library().gsf_batch_workspace_bytes(arr, count, ctypes.byref(nbytes)), "batch_workspace_bytes")
+        return torch.empty(int(nbytes.value), dtype=torch.uint8, device="cuda"), nbytes.value
+
+    def __init__(self, items, prec=F32, autotune=True, graphs=False):
+        torch = _torch()
+        lib = load_library()
+        self.items = items
+        self.arr = self.describe(items, prec)
+        self.ws, nb = self.workspace(self.arr, len(items))
+        nbytes = ctypes.c_size_t(nb)
         torch.cuda.synchronize()
         h = ctypes.c_void_p()
         flags = (1 if autotune else 0) | (2 if graphs else 0)
@@ -288,6 +302,16 @@ class Batch:
         if getattr(self, "handle", None) and _lib is not None:
             _lib.gsf_batch_destroy(self.handle)
             self.handle = None
+
+
+def batch_filter(items, prec=F32, stream=None):
+    """gsf_batch_filter: the whole batch in one call (synchronizes the stream);
+    returns [(iters, status, res0, res)] per item, outputs in item["out"]."""
+    arr = Batch.describe(items, prec)
+    ws, nb = Batch.workspace(arr, len(items))
+    out = (BatchInfo * len(items))()
+    _check(load_library().gsf_batch_filter(arr, len(items), _ptr(ws), nb, out, _stream(stream)), "batch_filter")
+    return [(o.iters, o.status, o.res0, o.res) for o in out]
 
 
 class Operator:
@@ -364,13 +388,27 @@ class Operator:
         return self._view(lay.mu, self.n, self.dtype), self._view(lay.inv, self.n, self.dtype)
 
     # -- entry points --------------------------------------------------------
+    @staticmethod
+    def _ld(t, m):
+        """Elements between consecutive points of a vector (m = 1) or of an
+        n x m block whose rows are contiguous (a column slice of a wider
+        point-major array is allowed)."""
+        if t.dim() == 1:
+            if not t.is_contiguous():
+                raise ValueError("a vector must be contiguous")
+            return 1
+        if t.stride(1) != 1 or t.stride(0) < m:
+            raise ValueError("a block needs contiguous rows (stride 1 within a point)")
+        return t.stride(0)
+
     def apply(self, x, form=FORM_N, out=None, stream=None):
         torch = _torch()
         m = 1 if x.dim() == 1 else x.shape[1]
-        if x.dtype != self.dtype or not x.is_cuda or not x.is_contiguous():
-            raise ValueError("x must be a contiguous device tensor of the operator dtype")
-        y = out if out is not None else torch.empty_like(x)
-        _check(_lib.gsf_apply(self.handle, form, m, _ptr(x), _ptr(y), _stream(stream)), "apply")
+        if x.dtype != self.dtype or not x.is_cuda:
+            raise ValueError("x must be a device tensor of the operator dtype")
+        y = out if out is not None else torch.empty(x.shape, dtype=x.dtype, device=x.device)
+        _check(_lib.gsf_apply(self.handle, form, m, _ptr(x), self._ld(x, m), _ptr(y), self._ld(y, m),
+                              _stream(stream)), "apply")
         return y
 
     def apply_joint(self, x, x2, form=FORM_LSYM, out=None, out2=None, stream=None):
@@ -479,14 +517,17 @@ class Operator:
         return y, (inf if info else None)
 
     def lobpcg_filter(self, x0, m, kmax, tol=0.0, constraint=False, out=None, ritz=None, ws=None, info=True,
-                      stream=None, precond=None):
+                      stream=None, precond=None, ritz_vals=None):
+        """ritz_vals: None or a ctypes array of m doubles that receives the
+        Ritz values (gsf_lobpcg_filter's ritz_vals_host)."""
         torch = _torch()
         y = out if out is not None else torch.empty_like(x0)
         ws = ws if ws is not None else self.workspace(METHOD_LOBPCG, m)
         inf = LobpcgInfo()
         st = _lib.gsf_lobpcg_filter(self.handle, _ptr(x0), _ptr(y), m, kmax, tol, int(bool(constraint)),
                                     precond.handle if precond is not None else None,
-                                    _ptr(ritz) if ritz is not None else None, _ptr(ws), ws.numel(),
+                                    _ptr(ritz) if ritz is not None else None,
+                                    ritz_vals if ritz_vals is not None else None, _ptr(ws), ws.numel(),
                                     ctypes.byref(inf) if info else None, _stream(stream))
         _check(st, "lobpcg_filter")
         return y, (inf if info else None)

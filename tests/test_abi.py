@@ -150,7 +150,7 @@ def test_build_rejects_small_workspace_and_nulls(lib):
 def test_solver_calls_reject_null_operator(lib):
     sz = ctypes.c_size_t()
     assert lib.gsf_solver_workspace_bytes(None, 1, 1, ctypes.byref(sz)) == 1
-    assert lib.gsf_apply(None, 0, 1, None, None, None) == 1
+    assert lib.gsf_apply(None, 0, 1, None, 0, None, 0, None) == 1
     assert lib.gsf_rr_workspace_bytes() > 0
 
 
