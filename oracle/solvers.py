@@ -51,6 +51,10 @@ block of m vectors (our reading; the paper gives the single-vector method):
   returned in x-space as D^-1/2 y.  It is the identity at k = 0 and tends to
   the GFT low-pass U_m U_m^T z0 (Section 4) as the Ritz block converges.
   tol > 0 stops once every column's residual ||A x_j - theta_j x_j|| <= tol.
+  AX is carried by the update's linear combinations and recomputed as A X
+  after every `refresh`-th step (20; 0 never), so that the rounding the
+  recurrence accumulates does not set a floor under the residual (C-10, C-16:
+  in exact arithmetic both give the same AX).
 """
 from __future__ import annotations
 
@@ -59,6 +63,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 DROP_TOL = {"f64": 1e-10, "f32": 1e-6}
+AX_REFRESH = 20
 BREAKDOWN_TOL = {"f64": 1e-13, "f32": 1e-6}
 
 
@@ -310,7 +315,7 @@ def precondition(T, R):
 
 
 def lobpcg_filter(op, x0, m: int, kmax: int, tol: float = 0.0, constraint: bool = False,
-                  data_prec: str = "f64", X0=None, precond=None):
+                  data_prec: str = "f64", X0=None, precond=None, refresh: int = AX_REFRESH):
     """Block LOBPCG low-pass filter (see module docstring).
     precond: None (T = I) or a callable R (n, m) -> T(R) used with the
     fallback rule of `precondition` (flexible LOBPCG: T may change or be
@@ -359,6 +364,8 @@ def lobpcg_filter(op, x0, m: int, kmax: int, tol: float = 0.0, constraint: bool 
         Cp = C.copy()
         Cp[:m, :] = 0.0
         X, AX, P, AP = S @ C, AS @ C, S @ Cp, AS @ Cp
+        if refresh > 0 and (k + 1) % refresh == 0:
+            AX = A(X)
         info.iters = k + 1
         info.theta_history.append(theta.copy())
         res = np.linalg.norm(AX - X * theta[None, :], axis=0)

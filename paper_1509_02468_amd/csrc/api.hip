@@ -1,5 +1,6 @@
 // C ABI of libgsf: validation, workspace layout and the solver drivers.
 #include <cmath>
+#include <cstddef>
 #include <mutex>
 #include <cstring>
 #include <new>
@@ -210,6 +211,8 @@ struct Carve {
 };
 
 double breakdown_tau(int prec) { return prec == GSF_F32 ? 1e-6 : 1e-13; }
+// LOBPCG recomputes AX = A X after every kAxRefresh-th step
+constexpr int kAxRefresh = 20;
 double drop_tol_of(int prec) { return prec == GSF_F32 ? 1e-6 : 1e-10; }
 
 struct CgWs {
@@ -781,6 +784,7 @@ struct LobRun {
     init.m = m;
     init.active = 1;
     init.status = GSF_OK;
+    for (int j = 0; j < m; ++j) init.cid[j * m + j] = 1.0;
     GSF_TRY(launch_lob_state_init(w.st, init, s));
     a.prec = op.desc.prec;
     a.n = op.n;
@@ -859,7 +863,19 @@ struct LobRun {
     rr.fin_nparts = nb;
     rr.fin_stride = 2 * m;
     GSF_TRY(lob_launch_gram(g, rr, op.desc.prec, s));
-    GSF_TRY(lob_launch_mkernel(fold ? 4 : 1, a, nb, ns, 0, deg, s));
+    if ((k + 1) % kAxRefresh != 0) {
+      GSF_TRY(lob_launch_mkernel(fold ? 4 : 1, a, nb, ns, 0, deg, s));
+    } else {
+      // every kAxRefresh steps AX = A X explicitly (the update's linear
+      // combinations accumulate rounding that would floor the residual), then
+      // the residual of that AX: it, not the carried one, makes this step's
+      // convergence decision
+      GSF_TRY(lob_launch_mkernel(4, a, nb, ns, 0, deg, s));
+      GSF_TRY(apply_any(op, GSF_FORM_LSYM, m, w.X, m, w.AX, m, nullptr, nullptr, s));
+      LobArgs ai = a;
+      ai.C = reinterpret_cast<const double*>(reinterpret_cast<const char*>(w.st) + offsetof(LobpcgState, cid));
+      GSF_TRY(lob_launch_mkernel(fold ? 7 : 6, ai, nb, m, 1, deg, s));
+    }
     pending = fold;
     return GSF_OK;
   }

@@ -1210,6 +1210,13 @@ void launch_m_kernels(int which, const LobArgs& a, int nb, int ns, int first, St
     case 5:
       lob_final_kernel<2 * M><<<1, kThreads, 0, s>>>(a.vpart, nb, a.st, 2, M, first, a.constraint);
       break;
+    case 6:  // W = AX - X Theta of a recomputed AX (a.C = I: X, AX copied, P, AP kept), finalized as an update
+      lob_update_kernel<T, M, 1><<<nb, kThreads, 0, s>>>(a, 1);
+      lob_final_kernel<2 * M><<<1, kThreads, 0, s>>>(a.vpart, nb, a.st, 2, M, 0, a.constraint);
+      break;
+    case 7:  // the same, its finalize folded into the next Rayleigh-Ritz step
+      lob_update_kernel<T, M, 1><<<nb, kThreads, 0, s>>>(a, 1);
+      break;
     case 2:
       lob_out_dots_kernel<T, M><<<nb, kThreads, 0, s>>>(a);
       lob_final_kernel<M + 1><<<1, kThreads, 0, s>>>(a.vpart, nb, a.st, 3, M, 0, a.constraint);

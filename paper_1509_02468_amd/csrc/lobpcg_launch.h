@@ -61,7 +61,8 @@ int gram_tiles_total(int ns);
 gsf_status lob_launch_ynorm(const LobArgs& a, int nb, hipStream_t s);
 // which: 0 start, 1 update (ns, first), 2 output dots, 3 output
 // which: 0 start block, 1 update + finalize, 2 output dots, 3 output,
-// 4 update without the finalize (see RRArgs::fin_partials), 5 the finalize alone
+// 4 update without the finalize (see RRArgs::fin_partials), 5 the finalize alone,
+// 6 / 7 the residual of a recomputed AX with / without the finalize (a.C = I)
 gsf_status lob_launch_mkernel(int which, const LobArgs& a, int nb, int ns, int first, StartDegrees deg,
                               hipStream_t s);
 gsf_status lob_launch_project(const LobArgs& a, void* B, int nb, hipStream_t s);

@@ -56,6 +56,7 @@ struct LobpcgState {
   int32_t pad2;
   unsigned int counter;
   unsigned int counter2;
+  double cid[64];      // m x m identity coefficients: the residual of a refreshed AX
 };
 
 }  // namespace gsf

@@ -305,3 +305,21 @@ def test_rayleigh_ritz_sign_convention():
     w, V = sla.eigh(GA, GB)
     np.testing.assert_allclose(theta, w[:3], rtol=1e-10)
     np.testing.assert_allclose(np.abs(C), np.abs(V[:, :3]), rtol=1e-8, atol=1e-10)
+
+
+def test_lobpcg_ax_refresh_changes_only_rounding():
+    """The explicit AX refresh (every 20 steps by default) is an identity in
+    exact arithmetic: runs refreshing every step, every 20 steps and never
+    agree to rounding after 60 steps, and the refreshed run's reported
+    residuals are those of the explicit L_sym X."""
+    import oracle
+    from synth import scene_2d
+    g = scene_2d(30, 36, 0.05, 17)[1]
+    op = oracle.build_operator("bf", g, 2, 2.0, 0.1)
+    outs = [oracle.lobpcg_filter(op, g.ravel(), 3, 60, refresh=r) for r in (0, 1, 20)]
+    for y, th, X, info in outs[1:]:
+        assert np.linalg.norm(y - outs[0][0]) <= 1e-10 * np.linalg.norm(outs[0][0])
+        np.testing.assert_allclose(th, outs[0][1], rtol=1e-10, atol=1e-14)
+    y, th, X, info = outs[2]
+    R = op.apply_lsym(X) - X * th[None, :]
+    np.testing.assert_allclose(np.linalg.norm(R, axis=0), info.res, rtol=1e-6, atol=1e-14)
