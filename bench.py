@@ -269,53 +269,85 @@ def batch_bench(seed=4):
             "items_converged": int(sum(1 for i in info if i[1] == 0)), "outputs_equal_sequential": bool(same)}
 
 
-def learned_bench(n_images=200, side=512, eval_side=2048, tol=1e-6, kmax=20000, m=4):
+def learned_bench(n_images=200, side=512, eval_side=2048, tol=1e-6, kmax=20000, m=4, alpha=1e-2, inner=30,
+                  snapshots=None):
     """Learned preconditioner: training pairs from the method itself on
     n_images noisy scenes of side^2 (BF 11x11, sigma_d = 2, sigma_r = 0.1,
     noise 0.05), 20 Adam epochs (batch 16, lr 1e-3), then block LOBPCG
     (m = 4, constraint, FP32 data, FP64 Rayleigh-Ritz) to a residual of tol on
-    an unseen eval_side^2 scene, plain T = I against the learned T."""
+    an unseen eval_side^2 scene: plain T = I, the learned T, and the T it is
+    trained to imitate (`inner` CG steps on (L_sym + alpha I) y = r, the
+    reference bound).  The learned run stops at three times the plain step
+    count (beyond that it has lost).  Losses of the zero and the identity
+    networks on the training pairs stand beside the trained one."""
     import torch
     import paper_1509_02468_amd as gsf
     from paper_1509_02468_amd import learned
     from synth import scene_2d, convnet_init
 
+    snapshots = learned.SNAPSHOTS if snapshots is None else snapshots
     imgs = [scene_2d(side, side, 0.05, 5000 + i)[1] for i in range(n_images)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    inputs, targets, cgi = learned.generate_pairs(imgs, 5, 2.0, 0.1, m=m)
+    inputs, targets, cgi = learned.generate_pairs(imgs, 5, 2.0, 0.1, m=m, snapshots=snapshots, alpha=alpha)
     torch.cuda.synchronize()
     t_pairs = time.perf_counter() - t0
     t0 = time.perf_counter()
     trainer, losses = learned.train(inputs, targets, side, side, convnet_init(5), epochs=20, batch=16, lr=1e-3)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
+    pair_loss = {"trained": learned.dataset_loss(trainer.w.cpu().numpy(), inputs, targets, side, side),
+                 "zero_net": learned.dataset_loss(np.zeros(gsf.NET_WEIGHTS, dtype=np.float32), inputs, targets,
+                                                  side, side),
+                 "identity_net": learned.dataset_loss(learned.identity_weights(), inputs, targets, side, side)}
     del inputs, targets
     g = scene_2d(eval_side, eval_side, 0.05, 5900)[1]
     gd = torch.tensor(g.ravel(), dtype=torch.float32, device="cuda")
     op = gsf.Operator("bf", (eval_side, eval_side), gd, 5, 2.0, 0.1, prec=gsf.F32)
     op.tune_apply(m)
+    op.tune_apply(1)
     T = gsf.Precond(op, gd, trainer.wb)
+    S = gsf.Precond.shifted(op, alpha, inner)
     ws = op.workspace(gsf.METHOD_LOBPCG, m)
+    # one preconditioner application on an m-column block, device time
+    R = torch.randn((op.n, m), dtype=torch.float32, device="cuda")
+    Wout = torch.empty_like(R)
+    T.apply(R, out=Wout)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for _ in range(10):
+        T.apply(R, out=Wout)
+    ev[1].record()
+    torch.cuda.synchronize()
+    net_ms = ev[0].elapsed_time(ev[1]) / 10
     res = {}
-    for name, P in (("plain", None), ("learned", T)):
+    for name, P in (("plain", None), ("learned", T), ("shifted_solve", S)):
+        cap = kmax if name != "learned" else max(3 * res["plain"]["iters"], 100)
         op.lobpcg_filter(gd, m, 3, constraint=True, ws=ws, precond=P)  # warm-up
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        _, info = op.lobpcg_filter(gd, m, kmax, tol=tol, constraint=True, ws=ws, precond=P)
+        _, info = op.lobpcg_filter(gd, m, cap, tol=tol, constraint=True, ws=ws, precond=P)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         res[name] = {"iters": info.iters, "ms": round(dt * 1e3, 1), "ms_per_iter": round(dt * 1e3 / max(info.iters, 1), 3),
-                     "status": gsf.gsf.STATUS_NAMES.get(info.status, info.status),
+                     "status": gsf.gsf.STATUS_NAMES.get(info.status, info.status), "kmax": cap,
                      "max_res": float(max(list(info.res)[:m])), "theta": [float(t) for t in list(info.theta)[:m]],
                      "fallbacks": info.fallbacks}
+    net_flop = 2.0 * (16 * 2 * 9 + 16 * 16 * 9 + 16 * 9) * op.n * m
     return {"workload": f"learned_bf11_train{n_images}x{side}_eval{eval_side}",
-            "train": {"pairs": n_images * 10, "pair_gen_s": round(t_pairs, 1), "train_s": round(t_train, 1),
+            "train": {"pairs": n_images * len(snapshots), "snapshots": list(snapshots), "alpha": alpha,
+                      "pair_gen_s": round(t_pairs, 1), "train_s": round(t_train, 1),
                       "cg_iters_mean": round(float(np.mean(cgi)), 1), "loss_first_epoch": round(float(losses[0]), 3),
-                      "loss_last_epoch": round(float(losses[-1]), 3)},
+                      "loss_last_epoch": round(float(losses[-1]), 3),
+                      "loss_on_pairs": {k: round(v, 3) for k, v in pair_loss.items()}},
+            "inference": {"ms_per_block": round(net_ms, 3), "m": m,
+                          "tflops": round(net_flop / (net_ms * 1e-3) / 1e12, 1)},
             "tol": tol, "plain": res["plain"], "learned": res["learned"],
+            "shifted_solve": dict(res["shifted_solve"], alpha=alpha, inner_cg_steps=inner),
             "iters_ratio_learned_over_plain": round(res["learned"]["iters"] / max(res["plain"]["iters"], 1), 3),
-            "time_ratio_learned_over_plain": round(res["learned"]["ms"] / max(res["plain"]["ms"], 1e-9), 3)}
+            "time_ratio_learned_over_plain": round(res["learned"]["ms"] / max(res["plain"]["ms"], 1e-9), 3),
+            "iters_ratio_shifted_solve_over_plain": round(res["shifted_solve"]["iters"] / max(res["plain"]["iters"], 1),
+                                                          3)}
 
 
 def reguided_bench(steps=20, reps=3):

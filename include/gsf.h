@@ -327,11 +327,12 @@ gsf_status gsf_srgb_to_lab(int prec, int64_t n, const void* rgb, void* lab, void
  * with info != NULL the host then also stops issuing steps (it reads the
  * device convergence flag every 16 steps, 16 steps behind the queue).
  * A start block of rank < m returns x0 with GSF_EBREAKDOWN.
- * T: NULL (plain method) or a learned preconditioner (gsf_precond_create)
- *   built for this operator's grid and precision; then W = T(R) column by
- *   column (flexible LOBPCG: the Rayleigh-Ritz step on [X, W, P] is
- *   unchanged), with T = I for a column whose T(r) has a non-finite entry or
- *   r^T T(r) <= 0 (counted in info->fallbacks). */
+ * T: NULL (plain method), a learned preconditioner (gsf_precond_create) or
+ *   a shifted solve (gsf_precond_create_shifted) built for this operator's
+ *   grid and precision; then W = T(R) column by column (flexible LOBPCG: the
+ *   Rayleigh-Ritz step on [X, W, P] is unchanged), with T = I for a column
+ *   whose T(r) has a non-finite entry or r^T T(r) <= 0 (counted in
+ *   info->fallbacks). */
 typedef struct gsf_precond gsf_precond;
 gsf_status gsf_lobpcg_filter(const gsf_operator* op, const void* x0, void* x_out, int m,
                              int kmax, double tol, int constraint, const gsf_precond* T,
@@ -415,6 +416,17 @@ gsf_status gsf_net_make_pair(const gsf_operator* op, const void* r, int64_t ldr,
  * Errors: GSF_EINVAL for null pointers or m outside 1..8. */
 gsf_status gsf_precond_create(const gsf_operator* op, const void* g, const uint16_t* w_bf16,
                               gsf_precond** out);
+/* The preconditioner the network is trained to imitate, as a reference:
+ * T(r) = the iterate after inner_steps CG steps on (L_sym + alpha I) y = r
+ * from y = 0 (gsf_shifted_cg's recurrences, no tolerance; a zero column gives
+ * y = 0, which the fallback rule then replaces by r).  Its cost is
+ * inner_steps single-column applies per column and LOBPCG step.  The
+ * operator is borrowed; the handle owns the CG scratch (about 4n elements,
+ * allocated here and freed by gsf_precond_destroy), so one handle serves one
+ * call at a time.  gsf_precond_apply runs the solve without the fallback.
+ * GSF_EINVAL for a null op / out, alpha <= 0 or non-finite, inner_steps < 1;
+ * GSF_ENOMEM if the scratch cannot be allocated. */
+gsf_status gsf_precond_create_shifted(const gsf_operator* op, double alpha, int inner_steps, gsf_precond** out);
 void gsf_precond_destroy(gsf_precond* T);
 gsf_status gsf_precond_workspace_bytes(const gsf_precond* T, int m, size_t* bytes);
 gsf_status gsf_precond_apply(const gsf_precond* T, int m, const void* R, void* W, void* ws,

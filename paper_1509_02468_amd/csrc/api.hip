@@ -76,7 +76,12 @@ gsf_status net_infer(int prec, const uint16_t* w, int64_t rows, int64_t cols, in
                      const void* g, const void* sqd, const double* colnorm, const LobpcgState* st, double* partials,
                      hipStream_t s);
 gsf_status net_lob_select(int prec, int64_t rows, int64_t cols, int m, int constraint, void* W, const void* Z,
-                          const void* sqd, const double* partials, LobpcgState* st, hipStream_t s);
+                          const void* sqd, const double* partials, int nparts, LobpcgState* st, hipStream_t s);
+int tz_blocks(int64_t rows, int64_t cols);
+gsf_status shifted_precond_apply(const gsf_precond* T, int m, const void* R, void* Z, hipStream_t s);
+gsf_status launch_tz_partials(int prec, const void* R, const void* Z, const void* sqd, int64_t rows, int64_t cols,
+                              int m, const LobpcgState* st, double* partials, hipStream_t s);
+gsf_status launch_col_copy(int prec, const void* src, int64_t lds, void* dst, int64_t ldd, int64_t n, hipStream_t s);
 gsf_status launch_colnorm(int prec, const void* R, int64_t n, int m, int64_t ld, double* partials, double* out,
                           hipStream_t s);
 gsf_status launch_net_pair(int prec, const void* r, int64_t ldr, const void* y, int64_t ldy, const void* g,
@@ -758,6 +763,42 @@ struct CgRun {
   }
 };
 
+// Shifted-solve preconditioner: for every column j of the n x m block R,
+// Z[:, j] = y after T->inner CG steps on (L_sym + alpha I) y = R[:, j] from
+// y = 0 (the recurrences of gsf_shifted_cg with tol 0: every step runs unless
+// the column is zero or p^T q <= 0 stops it early).
+}  // namespace
+}  // extern "C"
+
+namespace gsf {
+gsf_status shifted_precond_apply(const gsf_precond* T, int m, const void* R, void* Z, hipStream_t s) {
+  const Operator& op = T->op->op;
+  CgWs cw;
+  carve_cg(op, (char*)T->mem, &cw);
+  void* y = cw.z;
+  for (int j = 0; j < m; ++j) {
+    CgState init{};
+    init.tol = 0.0;
+    GSF_TRY(launch_cg_state_init(cw.st, init, s));
+    GSF_TRY(launch_scg_init(op.desc.prec, (const char*)R + (size_t)j * op.elem, m, y, cw.r, op.n, cw.partials,
+                            cw.st, s));
+    for (int k = 1; k <= T->inner; ++k) {
+      GSF_TRY(launch_cg_pupdate(op, cw.r, cw.p, cw.st, s));
+      GSF_TRY(apply_any(op, GSF_FORM_LSYM, 1, cw.p, 1, cw.q, 1, nullptr, nullptr, s));
+      int nparts = 0;
+      GSF_TRY(launch_scg_shift(op.desc.prec, cw.p, cw.q, op.n, T->alpha, cw.partials, &nparts, cw.st, s));
+      GSF_TRY(launch_cg_alpha(cw.partials, nparts, cw.st, s));
+      GSF_TRY(launch_cg_update(op, y, cw.r, cw.p, cw.q, cw.partials, cw.st, s));
+    }
+    GSF_TRY(launch_col_copy(op.desc.prec, y, 1, (char*)Z + (size_t)j * op.elem, m, op.n, s));
+  }
+  return GSF_OK;
+}
+}  // namespace gsf
+
+extern "C" {
+namespace {
+
 // The LOBPCG filter (Algorithm 3, block form) as enqueued phases.
 struct LobRun {
   const Operator& op;
@@ -840,11 +881,18 @@ struct LobRun {
     return GSF_OK;
   }
   gsf_status pre() {  // W = T(R), or the projected R
+    if (T != nullptr && T->kind == kPrecondShifted) {
+      GSF_TRY(shifted_precond_apply(T, m, w.W, w.Z, s));
+      GSF_TRY(launch_tz_partials(op.desc.prec, w.W, w.Z, constraint ? op.sqd : nullptr, op.rows, op.cols, m, w.st,
+                                 w.net_partials, s));
+      return net_lob_select(op.desc.prec, op.rows, op.cols, m, constraint ? 1 : 0, w.W, w.Z, op.sqd,
+                            w.net_partials, tz_blocks(op.rows, op.cols), w.st, s);
+    }
     if (T != nullptr) {
       GSF_TRY(net_infer(op.desc.prec, T->w, op.rows, op.cols, m, w.W, w.Z, T->g, constraint ? op.sqd : nullptr,
                         w.st->res, w.st, w.net_partials, s));
       return net_lob_select(op.desc.prec, op.rows, op.cols, m, constraint ? 1 : 0, w.W, w.Z, op.sqd,
-                            w.net_partials, w.st, s);
+                            w.net_partials, net_tiles(op.rows, op.cols), w.st, s);
     }
     if (constraint) return lob_launch_project(a, w.W, nb, s);
     return GSF_OK;
@@ -1415,6 +1463,30 @@ gsf_status gsf_shifted_cg(const gsf_operator* h, double alpha, const void* b, in
   info->res0 = host.res0;
   info->res = std::sqrt(host.rho > 0.0 ? host.rho : 0.0);
   return status;
+}
+
+gsf_status gsf_precond_create_shifted(const gsf_operator* h, double alpha, int inner_steps, gsf_precond** out) {
+  clear_stale_errors();
+  if (h == nullptr || out == nullptr || !(alpha > 0.0) || !std::isfinite(alpha) || inner_steps < 1) return GSF_EINVAL;
+  CgWs cw;
+  const size_t bytes = carve_cg(h->op, nullptr, &cw);
+  gsf_precond* T = new (std::nothrow) gsf_precond;
+  if (T == nullptr) return GSF_EDEVICE;
+  if (hipMalloc(&T->mem, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    delete T;
+    return GSF_ENOMEM;
+  }
+  T->n = h->op.n;
+  T->rows = h->op.rows;
+  T->cols = h->op.cols;
+  T->prec = h->op.desc.prec;
+  T->kind = kPrecondShifted;
+  T->op = h;
+  T->alpha = alpha;
+  T->inner = inner_steps;
+  *out = T;
+  return GSF_OK;
 }
 
 gsf_status gsf_lobpcg_residual(const gsf_operator* h, int m, const void* X, const double* theta, void* R,

@@ -145,10 +145,19 @@ struct gsf_operator {
   }
 };
 
-// Learned preconditioner: grid, precision and borrowed device pointers.
+// Preconditioner handle: the learned network (grid, precision and borrowed
+// device pointers) or the shifted solve T(r) = `inner` CG steps on
+// (L_sym + alpha I) y = r from y = 0 (the operator borrowed, the CG scratch
+// owned by the handle).
+constexpr int kPrecondNet = 0, kPrecondShifted = 1;
 struct gsf_precond {
   int64_t n, rows, cols;
   int prec;
-  const void* g;       // guidance, n elements of the operator's type
-  const uint16_t* w;   // BF16 weights
+  int kind = kPrecondNet;
+  const void* g = nullptr;       // guidance, n elements of the operator's type
+  const uint16_t* w = nullptr;   // BF16 weights
+  const gsf_operator* op = nullptr;
+  double alpha = 0.0;
+  int inner = 0;
+  void* mem = nullptr;           // device scratch of the shifted solve
 };

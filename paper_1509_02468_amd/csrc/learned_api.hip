@@ -23,6 +23,7 @@ gsf_status launch_colnorm(int prec, const void* R, int64_t n, int m, int64_t ld,
 gsf_status launch_net_pair(int prec, const void* r, int64_t ldr, const void* y, int64_t ldy, const void* g,
                            int64_t n, const double* norm, float* in, float* tg, hipStream_t s);
 int vec_blocks(int64_t n);
+gsf_status shifted_precond_apply(const gsf_precond* T, int m, const void* R, void* Z, hipStream_t s);
 }  // namespace gsf
 
 using namespace gsf;
@@ -120,7 +121,11 @@ gsf_status gsf_precond_create(const gsf_operator* h, const void* g, const uint16
   return GSF_OK;
 }
 
-void gsf_precond_destroy(gsf_precond* T) { delete T; }
+void gsf_precond_destroy(gsf_precond* T) {
+  if (T == nullptr) return;
+  if (T->mem != nullptr) (void)hipFree(T->mem);
+  delete T;
+}
 
 gsf_status gsf_precond_workspace_bytes(const gsf_precond* T, int m, size_t* bytes) {
   if (T == nullptr || bytes == nullptr || m < 1 || m > kMaxBlock) return GSF_EINVAL;
@@ -141,6 +146,7 @@ gsf_status gsf_precond_apply(const gsf_precond* T, int m, const void* R, void* W
   double* norms = (double*)((char*)ws + pb);
   double* npart = (double*)((char*)ws + pb + 256);
   hipStream_t s = (hipStream_t)stream;
+  if (T->kind == kPrecondShifted) return shifted_precond_apply(T, m, R, W, s);
   GSF_TRY(launch_colnorm(T->prec, R, T->n, m, m, cpart, norms, s));
   return net_infer(T->prec, T->w, T->rows, T->cols, m, R, W, T->g, nullptr, norms, nullptr, npart, s);
 }

@@ -614,6 +614,44 @@ __global__ void __launch_bounds__(kThreads) net_select_kernel(T* __restrict__ W,
   }
 }
 
+// Partials of the fallback test for a preconditioner output Z computed
+// outside the network kernel: per column r^T z, (Y^T z with Y = sqrt(d) /
+// ||sqrt(d)||, when sqd != nullptr) and the count of non-finite entries, in
+// the layout net_final_kernel reads (3 values per column, 3m per workgroup).
+template <typename T>
+__global__ void __launch_bounds__(kThreads) tz_partials_kernel(const T* __restrict__ R, const T* __restrict__ Z,
+                                                               const T* __restrict__ sqd, int64_t n, int m,
+                                                               const LobpcgState* st, double* __restrict__ partials) {
+  __shared__ double red[16 * 3 * kMaxBlock];
+  double v[3 * kMaxBlock];
+#pragma unroll
+  for (int k = 0; k < 3 * kMaxBlock; ++k) v[k] = 0.0;
+  const double yinv = sqd != nullptr ? st->ynorm_inv : 0.0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const double yi = sqd != nullptr ? (double)sqd[i] * yinv : 0.0;
+#pragma unroll
+    for (int j = 0; j < kMaxBlock; ++j)
+      if (j < m) {
+        const double z = (double)Z[i * m + j];
+        v[3 * j] += (double)R[i * m + j] * z;
+        v[3 * j + 1] += yi * z;
+        if (!__builtin_isfinite(z)) v[3 * j + 2] += 1.0;
+      }
+  }
+  block_sum<3 * kMaxBlock>(v, red);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 3 * m; ++k) partials[(size_t)blockIdx.x * 3 * m + k] = v[k];
+}
+
+// dst[i * ldd] = src[i * lds]
+template <typename T>
+__global__ void __launch_bounds__(kThreads) col_copy_kernel(const T* __restrict__ src, int64_t lds, T* __restrict__ dst,
+                                                            int64_t ldd, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i * ldd] = src[i * lds];
+}
+
 // ||R_j||^2 partials of an n x m block
 template <typename T>
 __global__ void __launch_bounds__(kThreads) colnorm_kernel(const T* __restrict__ R, int64_t n, int m,
@@ -875,9 +913,9 @@ gsf_status net_infer(int prec, const uint16_t* w, int64_t rows, int64_t cols, in
 }
 
 gsf_status net_lob_select(int prec, int64_t rows, int64_t cols, int m, int constraint, void* W, const void* Z,
-                          const void* sqd, const double* partials, LobpcgState* st, hipStream_t s) {
+                          const void* sqd, const double* partials, int nparts, LobpcgState* st, hipStream_t s) {
   const int64_t n = rows * cols;
-  net_final_kernel<<<1, kThreads, 0, s>>>(partials, net_tiles(rows, cols), m, st);
+  net_final_kernel<<<1, kThreads, 0, s>>>(partials, nparts, m, st);
   const int nb = vec_blocks(n);
   if (prec == GSF_F32)
     net_select_kernel<float><<<nb, kThreads, 0, s>>>((float*)W, (const float*)Z, (const float*)sqd, n, m, constraint,
@@ -885,6 +923,33 @@ gsf_status net_lob_select(int prec, int64_t rows, int64_t cols, int m, int const
   else
     net_select_kernel<double><<<nb, kThreads, 0, s>>>((double*)W, (const double*)Z, (const double*)sqd, n, m,
                                                       constraint, st);
+  return launch_status();
+}
+
+int tz_blocks(int64_t rows, int64_t cols) {
+  const int a = vec_blocks(rows * cols), b = net_tiles(rows, cols);
+  return a < b ? a : b;
+}
+
+gsf_status launch_tz_partials(int prec, const void* R, const void* Z, const void* sqd, int64_t rows, int64_t cols,
+                              int m, const LobpcgState* st, double* partials, hipStream_t s) {
+  const int nb = tz_blocks(rows, cols);
+  const int64_t n = rows * cols;
+  if (prec == GSF_F32)
+    tz_partials_kernel<float><<<nb, kThreads, 0, s>>>((const float*)R, (const float*)Z, (const float*)sqd, n, m, st,
+                                                      partials);
+  else
+    tz_partials_kernel<double><<<nb, kThreads, 0, s>>>((const double*)R, (const double*)Z, (const double*)sqd, n, m,
+                                                       st, partials);
+  return launch_status();
+}
+
+gsf_status launch_col_copy(int prec, const void* src, int64_t lds, void* dst, int64_t ldd, int64_t n, hipStream_t s) {
+  const int nb = vec_blocks(n);
+  if (prec == GSF_F32)
+    col_copy_kernel<float><<<nb, kThreads, 0, s>>>((const float*)src, lds, (float*)dst, ldd, n);
+  else
+    col_copy_kernel<double><<<nb, kThreads, 0, s>>>((const double*)src, lds, (double*)dst, ldd, n);
   return launch_status();
 }
 

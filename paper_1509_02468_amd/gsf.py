@@ -134,6 +134,7 @@ def load_library(path: str = LIB_PATH):
         "gsf_net_pair_workspace_bytes": ([vp, P(sz)], i32),
         "gsf_net_make_pair": ([vp, vp, i64, vp, i64, vp, vp, vp, vp, sz, vp], i32),
         "gsf_precond_create": ([vp, vp, vp, P(vp)], i32),
+        "gsf_precond_create_shifted": ([vp, dbl, i32, P(vp)], i32),
         "gsf_precond_destroy": ([vp], None),
         "gsf_precond_workspace_bytes": ([vp, i32, P(sz)], i32),
         "gsf_precond_apply": ([vp, i32, vp, vp, vp, sz, vp], i32),
@@ -570,7 +571,19 @@ NET_WEIGHTS = 2736
 class Precond:
     """Learned preconditioner handle (gsf_precond_create): borrows the
     operator grid, the guidance tensor and the BF16 weight tensor (uint16 or
-    bfloat16 storage), which must stay alive."""
+    bfloat16 storage), which must stay alive.  Precond.shifted(op, alpha,
+    inner) is the shifted-solve reference T (gsf_precond_create_shifted)."""
+
+    @classmethod
+    def shifted(cls, op, alpha, inner):
+        lib = load_library()
+        self = cls.__new__(cls)
+        self.op, self.g, self.w = op, None, None
+        h = ctypes.c_void_p()
+        _check(lib.gsf_precond_create_shifted(op.handle, float(alpha), int(inner), ctypes.byref(h)),
+               "precond_create_shifted")
+        self.handle = h
+        return self
 
     def __init__(self, op, guidance, w_bf16):
         lib = load_library()

@@ -2,8 +2,10 @@
 Algorithm 3): training pairs from the method itself, Adam on the GPU.
 
 Pairs: for each training image, block LOBPCG (m columns, with the constraint)
-is run for k = 0, 5, ..., 45 steps; the residual block R = L_sym X - X Theta
-of the returned Ritz pairs gives one column r (column k/5 mod m), and its
+is run for k steps for each k of a snapshot list (SNAPSHOTS: 0, 5, ..., 45;
+TRAJECTORY: 0, 5, 10, 20, ..., 1280, residuals from the whole run to a
+tolerance); the residual block R = L_sym X - X Theta of the returned Ritz
+pairs gives one column r (column s mod m for the s-th snapshot), and its
 target t = (L_sym + alpha I)^-1 r comes from CG to a relative residual of
 cg_tol.  Both are scaled by s = RMS(r) (the network sees r / s and learns
 t / s).  All arithmetic runs in libgsf (this module only sequences the
@@ -16,6 +18,39 @@ import numpy as np
 from . import gsf
 
 SNAPSHOTS = tuple(range(0, 50, 5))
+# residuals from the whole run to the tolerance, not only its first steps
+TRAJECTORY = (0, 5, 10, 20, 40, 80, 160, 320, 640, 1280)
+
+
+def identity_weights():
+    """Weights of the network with net(r, g) = r exactly (u = relu(u) -
+    relu(-u) through the two hidden layers): the T = I baseline."""
+    w = np.zeros(gsf.NET_WEIGHTS, dtype=np.float32)
+    w1, w2, w3 = 0, 16 * 2 * 9, 16 * 2 * 9 + 16 * 16 * 9
+    centre = 4  # (ky, kx) = (1, 1)
+    w[w1 + (0 * 2 + 0) * 9 + centre] = 1.0    # channel 0 <- +r
+    w[w1 + (1 * 2 + 0) * 9 + centre] = -1.0   # channel 1 <- -r
+    w[w2 + (0 * 16 + 0) * 9 + centre] = 1.0
+    w[w2 + (1 * 16 + 1) * 9 + centre] = 1.0
+    w[w3 + 0 * 9 + centre] = 1.0
+    w[w3 + 1 * 9 + centre] = -1.0
+    return w
+
+
+def dataset_loss(w, inputs, targets, rows, cols, batch=16):
+    """Mean loss of the weights w (FP32, rounded to BF16 as in training)
+    over the whole training set, in batches of `batch` samples: the zero
+    network gives mean(t^2), the identity network mean((r - t)^2)."""
+    import torch
+    P = inputs.shape[0]
+    trainer = gsf.NetTrainer(w, batch, rows, cols)
+    total, count = 0.0, 0
+    for b0 in range(0, P - batch + 1, batch):
+        idx = torch.arange(b0, b0 + batch, dtype=torch.int32, device="cuda")
+        loss, _ = trainer.loss_grad(idx, inputs, targets)
+        total += float(loss[0]) * batch
+        count += batch
+    return total / max(count, 1)
 
 
 def generate_pairs(images, radius, sigma_d, sigma_r, m=4, snapshots=SNAPSHOTS, alpha=1e-2, cg_tol=1e-10,

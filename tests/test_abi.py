@@ -5,6 +5,8 @@ import ctypes
 import os
 import re
 
+import numpy as np
+
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -180,6 +182,12 @@ def test_learned_preconditioner_argument_checks(lib):
     assert lib.gsf_net_to_bf16(0, v, v, None) == 1
     h = ctypes.c_void_p()
     assert lib.gsf_precond_create(None, v, v, ctypes.byref(h)) == 1
+    d = ctypes.c_double
+    assert lib.gsf_precond_create_shifted(None, d(1e-2), 10, ctypes.byref(h)) == 1
+    assert lib.gsf_precond_create_shifted(v, d(0.0), 10, ctypes.byref(h)) == 1
+    assert lib.gsf_precond_create_shifted(v, d(float("nan")), 10, ctypes.byref(h)) == 1
+    assert lib.gsf_precond_create_shifted(v, d(1e-2), 0, ctypes.byref(h)) == 1
+    assert lib.gsf_precond_create_shifted(v, d(1e-2), 10, None) == 1
     assert lib.gsf_precond_workspace_bytes(None, 4, ctypes.byref(sz)) == 1
     assert lib.gsf_precond_apply(None, 4, v, v, v, 1 << 30, None) == 1
     assert lib.gsf_shifted_cg(None, 1e-2, v, 1, v, 10, 1e-10, v, 1 << 30, None, None) == 1
@@ -206,3 +214,11 @@ def test_joint_argument_checks(lib):
     sz = ctypes.c_size_t()
     assert lib.gsf_joint_workspace_bytes(None, 4, ctypes.byref(sz)) == 1
     assert lib.gsf_joint_filter(None, None, None, 5, None, None, 4, 5, 0, None, 0, None, None, None) == 1
+
+
+def test_identity_weights_layout():
+    """The package's identity network is the oracle's (same weight layout:
+    W1 [16][2][3][3], W2 [16][16][3][3], W3 [16][3][3])."""
+    from oracle import convnet as cn
+    from paper_1509_02468_amd import learned
+    assert np.array_equal(learned.identity_weights().astype(np.float64), cn.identity_weights())

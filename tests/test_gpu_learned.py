@@ -296,6 +296,86 @@ def test_lobpcg_random_network_matches_oracle(gsf):
     assert e <= max(1e-6, 100 * tol / gap)
 
 
+def _shifted_T(oop, alpha, inner):
+    """The oracle's shifted-solve T: `inner` plain CG steps on
+    (L_sym + alpha I) y = r from y = 0, column by column."""
+    def T(R):
+        return np.column_stack([oracle.shifted_cg(oop, alpha, R[:, j], inner, 0.0)[0] for j in range(R.shape[1])])
+    return T
+
+
+@pytest.mark.parametrize("prec_name", ["f32", "f64"])
+def test_shifted_precond_apply_matches_oracle(gsf, prec_name):
+    """The shifted-solve reference T on a block with uneven column scales and
+    one zero column (whose solve stops at once: y = 0).  FP64 to 1e-11
+    relative; FP32 to 1e-5 (twelve CG steps on a system with condition
+    number <= (2 + alpha) / alpha, data rounded to FP32)."""
+    import torch
+    prec = gsf.F32 if prec_name == "f32" else gsf.F64
+    dt = torch.float32 if prec == gsf.F32 else torch.float64
+    H, W, m, alpha, inner = 37, 45, 4, 1e-2, 12
+    g = scene_2d(H, W, 0.05, 31)[1]
+    R = np.random.default_rng(32).standard_normal((H * W, m)) * np.array([1.0, 1e-3, 40.0, 0.0])
+    if prec == gsf.F32:
+        R = R.astype(np.float32).astype(np.float64)
+        g = g.astype(np.float32).astype(np.float64)
+    op = gsf.Operator("bf", (H, W), _dev(g.ravel(), dt), 3, 2.0, 0.1, prec=prec)
+    oop = oracle.build_operator("bf", g, 3, 2.0, 0.1)
+    T = gsf.Precond.shifted(op, alpha, inner)
+    out = T.apply(_dev(R, dt)).cpu().numpy()
+    ref = _shifted_T(oop, alpha, inner)(R)
+    assert np.all(out[:, 3] == 0.0)
+    for j in range(3):
+        e = nrel(out[:, j], ref[:, j])
+        print(f"shifted T {prec_name} col {j}: rel {e:.2e}")
+        assert e <= (1e-11 if prec == gsf.F64 else 1e-5)
+
+
+@pytest.mark.parametrize("constraint", [False, True])
+def test_lobpcg_shifted_precond_matches_oracle(gsf, constraint):
+    """Flexible LOBPCG with the shifted-solve T, FP64 against the oracle
+    with the same T (gate max(1e-12, 10 band), the band of the oracle run on
+    the reversed grid), Ritz values and the per-column fallback count."""
+    from sensitivity import reference
+    op, oop, g, gd = _lob_case(gsf, gsf.F64)
+    alpha, inner, m, k = 1e-2, 10, 3, 8
+    T = gsf.Precond.shifted(op, alpha, inner)
+    out, info = op.lobpcg_filter(gd, m, k, constraint=constraint, precond=T)
+
+    def run(gg):
+        o = oracle.build_operator("bf", gg, 2, 2.0, 0.1)
+        y, th, _, rinfo = oracle.lobpcg_filter(o, gg.ravel(), m, k, constraint=constraint,
+                                               precond=_shifted_T(o, alpha, inner))
+        return y, (th, rinfo)
+    ref = reference(run, g)
+    th, rinfo = ref.extra
+    e = nrel(out.cpu().numpy(), ref.y)
+    print(f"shifted-T LOBPCG (constraint={constraint}): y rel {e:.2e} (gate {ref.gate:.1e}), "
+          f"fallbacks {info.fallbacks}, dropped {info.dropped}/{rinfo.dropped}")
+    assert info.fallbacks == 0 and info.iters == k
+    assert e <= ref.gate
+    np.testing.assert_allclose(np.array(list(info.theta)[:m]), th, rtol=max(1e-10, ref.gate), atol=1e-13)
+
+
+def test_shifted_precond_bound_cuts_lobpcg_steps(gsf):
+    """What the learned T is trained to imitate pays: with the shifted solve
+    (alpha = 1e-2, 30 inner CG steps) LOBPCG reaches tol 1e-6 in at most a
+    third of the plain method's steps on a 96 x 96 scene (BF 11 x 11, m = 4,
+    the constraint).  The oracle's exact-solve study of the same setting
+    (tests/test_oracle_solvers.py) gives the unrounded bound."""
+    import torch
+    side = 96
+    g = scene_2d(side, side, 0.05, 5900)[1]
+    gd = torch.tensor(g.ravel(), dtype=torch.float64, device="cuda")
+    op = gsf.Operator("bf", (side, side), gd, 5, 2.0, 0.1, prec=gsf.F64)
+    T = gsf.Precond.shifted(op, 1e-2, 30)
+    ip = op.lobpcg_filter(gd, 4, 5000, tol=1e-6, constraint=True)[1]
+    it = op.lobpcg_filter(gd, 4, 5000, tol=1e-6, constraint=True, precond=T)[1]
+    print(f"96^2 LOBPCG steps to 1e-6: plain {ip.iters}, shifted-solve T {it.iters} (fallbacks {it.fallbacks})")
+    assert ip.status == gsf.OK and it.status == gsf.OK
+    assert 3 * it.iters <= ip.iters
+
+
 def test_training_reduces_loss(gsf):
     """A few Adam steps on pairs generated by the method itself (residuals of
     LOBPCG, targets from the shifted CG) lower the loss."""
@@ -308,26 +388,40 @@ def test_training_reduces_loss(gsf):
     assert losses[-1] < 0.7 * losses[0]
 
 
-def test_trained_network_gain_over_identity(gsf):
-    """What the trained network gains over T = I: on residuals of an unseen
-    scene, T(r) is closer to the training target (L_sym + alpha I)^-1 r than
-    r itself (cosine of the angle, averaged over the residual columns of
-    several LOBPCG steps).  The LOBPCG step counts with and without T are
-    printed; at this window size the network does not shorten the runs (see
-    the design notes), which the benchmark reports at full size."""
-    import torch
+@pytest.fixture(scope="module")
+def trained(gsf):
+    """A network trained on 12 scenes of 96 x 96 (residuals of LOBPCG steps
+    0, 10, 20, 40, 80 and 160, targets (L_sym + 1e-2 I)^-1 r), with the
+    losses of the zero and the identity networks on the same pairs."""
     from paper_1509_02468_amd import learned
     side = 96
     imgs = [scene_2d(side, side, 0.05, 600 + i)[1] for i in range(12)]
-    inputs, targets, _ = learned.generate_pairs(imgs, 5, 2.0, 0.1, m=4, snapshots=(0, 5, 10, 20))
+    inputs, targets, _ = learned.generate_pairs(imgs, 5, 2.0, 0.1, m=4, snapshots=(0, 10, 20, 40, 80, 160))
     trainer, losses = learned.train(inputs, targets, side, side, convnet_init(21), epochs=30, batch=8, lr=3e-3)
+    zero = learned.dataset_loss(np.zeros(gsf.NET_WEIGHTS, dtype=np.float32), inputs, targets, side, side, batch=8)
+    ident = learned.dataset_loss(learned.identity_weights(), inputs, targets, side, side, batch=8)
+    final = learned.dataset_loss(trainer.w.cpu().numpy(), inputs, targets, side, side, batch=8)
+    print(f"training loss {losses[0]:.2f} -> {losses[-1]:.2f}; on all pairs: trained {final:.2f}, "
+          f"zero net {zero:.2f}, identity net {ident:.2f}")
+    return dict(side=side, trainer=trainer, losses=losses, zero=zero, ident=ident, final=final)
+
+
+def test_trained_network_gain_over_identity(gsf, trained):
+    """What the trained network gains over T = I: on the training pairs its
+    loss is below those of the zero and the identity networks, and on
+    residuals of an unseen scene T(r) is closer in angle to the target
+    (L_sym + alpha I)^-1 r than r itself (cosine averaged over the residual
+    columns of several LOBPCG steps)."""
+    import torch
+    side, trainer = trained["side"], trained["trainer"]
+    assert trained["final"] < min(trained["zero"], trained["ident"])
     g = scene_2d(side, side, 0.05, 699)[1]
     gd = torch.tensor(g.ravel(), dtype=torch.float64, device="cuda")
     op = gsf.Operator("bf", (side, side), gd, 5, 2.0, 0.1, prec=gsf.F64)
     T = gsf.Precond(op, gd, trainer.wb)
     X = torch.empty((side * side, 4), dtype=torch.float64, device="cuda")
     c_id, c_net = [], []
-    for k in (0, 10, 30):
+    for k in (0, 10, 30, 100):
         _, info = op.lobpcg_filter(gd, 4, k, constraint=True, ritz=X)
         R = op.lobpcg_residual(X, list(info.theta)[:4])
         TR = T.apply(R)
@@ -336,10 +430,32 @@ def test_trained_network_gain_over_identity(gsf):
             r, w = R[:, j].contiguous(), TR[:, j].contiguous()
             c_id.append(float(r @ t / (r.norm() * t.norm())))
             c_net.append(float(w @ t / (w.norm() * t.norm())))
-    ip = op.lobpcg_filter(gd, 4, 5000, tol=1e-6, constraint=True)[1]
-    il = op.lobpcg_filter(gd, 4, 5000, tol=1e-6, constraint=True, precond=T)[1]
-    print(f"loss {losses[0]:.1f} -> {losses[-1]:.1f}; cos to target: identity {np.mean(c_id):.3f}, "
-          f"network {np.mean(c_net):.3f}; LOBPCG steps to 1e-6: plain {ip.iters}, learned {il.iters} "
-          f"(fallbacks {il.fallbacks})")
-    assert losses[-1] < losses[0]
+    print(f"cos to target: identity {np.mean(c_id):.3f}, network {np.mean(c_net):.3f}")
     assert np.mean(c_net) > np.mean(c_id) + 0.1
+
+
+@pytest.mark.xfail(strict=True, reason="the network's 7 x 7 receptive field is smaller than one application "
+                   "of the 11 x 11 operator, so it cannot imitate the non-local (L_sym + alpha I)^-1 whose "
+                   "exact form does cut the steps (test_shifted_precond_bound_cuts_lobpcg_steps)")
+def test_learned_precond_cuts_lobpcg_steps(gsf, trained):
+    """The learned T against the plain method on an unseen 96 x 96 scene
+    (tol 1e-6, m = 4, the constraint): it would pay if it cut the steps by
+    more than 1.5 (its cost is about half a LOBPCG step) and the wall time
+    with it."""
+    import time
+    import torch
+    side, trainer = trained["side"], trained["trainer"]
+    g = scene_2d(side, side, 0.05, 699)[1]
+    gd = torch.tensor(g.ravel(), dtype=torch.float64, device="cuda")
+    op = gsf.Operator("bf", (side, side), gd, 5, 2.0, 0.1, prec=gsf.F64)
+    T = gsf.Precond(op, gd, trainer.wb)
+    res = {}
+    for name, P in (("plain", None), ("learned", T)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = op.lobpcg_filter(gd, 4, 5000, tol=1e-6, constraint=True, precond=P)[1]
+        res[name] = (info.iters, time.perf_counter() - t0, info.fallbacks, info.status)
+    print(f"LOBPCG to 1e-6 (steps, s, fallbacks, status): {res}")
+    assert res["learned"][3] == gsf.OK
+    assert 1.5 * res["learned"][0] <= res["plain"][0]
+    assert res["learned"][1] < res["plain"][1]
