@@ -399,9 +399,16 @@ void gf_apply_typed(const Operator& op, void* scratch, int form, int m, const T*
 
 }  // namespace
 
-// Scratch: 2 * kMaxBlock planes of n elements (a, b of up to 8 columns).
+gsf_status launch_gf_apply_fused(const Operator& op, int form, const float* x, int64_t ldx, float* y, int64_t ldy,
+                                 hipStream_t s);
+
+// One FP32 column: the one-pass kernel (apply_gf_fused.hip).  Blocks and FP64
+// data: the two passes above; scratch: 2 * kMaxBlock planes of n elements
+// (a, b of up to 8 columns).
 gsf_status launch_gf_apply(const Operator& op, void* scratch, int form, int m, const void* x, int64_t ldx,
                            void* y, int64_t ldy, hipStream_t s) {
+  if (op.desc.prec == GSF_F32 && m == 1)
+    return launch_gf_apply_fused(op, form, (const float*)x, ldx, (float*)y, ldy, s);
   if (op.desc.prec == GSF_F32)
     gf_apply_typed<float>(op, scratch, form, m, (const float*)x, ldx, (float*)y, ldy, s);
   else
