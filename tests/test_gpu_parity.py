@@ -438,3 +438,34 @@ def test_cg_1d_small_and_large_paths(gsf, n, prec):
     y, info = op.cg_filter(_torch(c, prec, gsf), 10)
     assert info.status == gsf.EBREAKDOWN and info.iters == 0
     np.testing.assert_allclose(y.cpu().numpy(), c, rtol=1e-6 if prec == 0 else 1e-15)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("shape,radius", [((5, 9), 3), ((9, 5), 3), ((1, 700), 2), ((300, 1), 4), ((37, 500), 8),
+                                          ((70, 131), 1), ((600,), 8), ((3,), 8), ((1,), 2)])
+def test_gf_one_column_all_forms_edges(gsf, shape, radius, prec):
+    """The GF apply of one column (FP32: the one-pass kernel; FP64: the two
+    passes) on grids smaller than the window, single rows and columns, several
+    256-column strips, tiny 1D signals, every radius class; all four forms,
+    a strided x / y (every third point of a wider array) against the oracle."""
+    import torch
+    rng = np.random.default_rng(7 + radius)
+    g = rng.uniform(0.0, 1.0, shape)
+    g = _round(g, prec, gsf)
+    op = gsf.Operator("gf", shape, _torch(g.ravel(), prec, gsf), radius=radius, eps=1e-2, prec=prec)
+    ref = oracle.build_operator("gf", g, radius, eps=1e-2)
+    x = _round(rng.standard_normal(op.n), prec, gsf)
+    wide = np.zeros((op.n, 3))
+    wide[:, 1] = x
+    xd = _torch(wide, prec, gsf)
+    for form in (gsf.FORM_N, gsf.FORM_LSYM, gsf.FORM_RW, gsf.FORM_L):
+        y = op.apply(xd[:, 1:2], form).cpu().numpy().ravel()
+        yw = torch.zeros_like(xd)
+        op.apply(xd[:, 1:2], form, out=yw[:, 2:3])
+        r = ref.apply(form, x)
+        # relative to the input's scale: a Laplacian form can vanish (one point)
+        scale = max(np.linalg.norm(r), np.linalg.norm(x))
+        e = max(np.linalg.norm(y - r) / scale, np.abs(y - r).max() / max(np.abs(r).max(), np.abs(x).max()))
+        assert e <= TOL[prec], (form, e)
+        assert np.array_equal(yw[:, 2].cpu().numpy(), y)
+        assert not yw[:, 0].any() and not yw[:, 1].any()
