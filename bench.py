@@ -63,8 +63,9 @@ def _args():
     ap.add_argument("--learned-images", type=int, default=200, help="training images (10 pairs each)")
     ap.add_argument("--learned-eval", type=int, default=2048, help="side of the evaluation image")
     ap.add_argument("--precision-study", action="store_true",
-                    help="FP32 against all-FP64 LOBPCG (m = 8, 100 steps) on the 4096^2 BF 7x7 and GF r = 8 "
-                         "workloads, and both against the FP64 oracle on a 384^2 image of the same class")
+                    help="only the precision study (the default run includes it): FP32 against all-FP64 LOBPCG "
+                         "(m = 8, 100 steps) on the 4096^2 BF 7x7 and GF r = 8 workloads, and both against the "
+                         "FP64 oracle on an --oracle-side image of the same class")
     ap.add_argument("--kernels-only", action="store_true",
                     help="only the stencil applies (m = 1 and m) and a 1 GiB copy, for hardware counters")
     return ap.parse_args()
@@ -706,7 +707,7 @@ def study_1d_bench(reps=3):
     return out
 
 
-def precision_study(oracle_side=384):
+def precision_study(oracle_side=160):
     """Per-result errors of the precision modes (the 4096^2 workloads, BF 7x7
     and GF radius 8, LOBPCG m = 8, 100 steps): FP32 data with MFMA Gram and
     FP64 Rayleigh-Ritz against the all-FP64 GPU run at 4096^2 (Ritz values,
