@@ -504,8 +504,9 @@ def signal_1d_bench(reps=10):
     """The 4096-sample 1D workload (BF radius 5, sigma_d 3, sigma_r 0.2,
     FP64): microseconds per iteration of 30 power passes, 30 CG steps and 30
     LOBPCG (m = 3) steps, each run timed whole with HIP events (median of
-    `reps`).  At 262 KB per apply this workload is bound by launch and
-    reduction latency, not by bandwidth."""
+    `reps`), issued eagerly and replayed from a HIP graph of the whole call.
+    At 262 KB per apply this workload is bound by launch and reduction
+    latency, not by bandwidth."""
     import torch
     import paper_1509_02468_amd as gsf
     from synth import WORKLOADS, make_signal
@@ -541,6 +542,14 @@ def signal_1d_bench(reps=10):
                                                   info=False))):
         ms = timed(fn)
         out[name] = {"iters": k, "ms": round(ms, 4), "us_per_iter": round(ms * 1e3 / k, 2)}
+        # the same call recorded once into a HIP graph and replayed (no host
+        # launches inside the timed region)
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            fn()
+        ms_g = timed(graph.replay)
+        out[name]["graph_us_per_iter"] = round(ms_g * 1e3 / k, 2)
+        del graph
     return out
 
 

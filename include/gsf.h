@@ -502,6 +502,24 @@ gsf_status gsf_tune_apply(const gsf_operator* op, int m, const void* x, void* y,
  *   width, size class), as gsf_tune_apply would; process-wide.  GSF_EINVAL
  *   for other values or a GF operator. */
 gsf_status gsf_set_apply_rows(const gsf_operator* op, int m, int rows_per_thread);
+/* gsf_get_apply_rows: the rows per thread the BF apply of block width m uses
+ *   for this operator (the tuned or set value of its class, else the
+ *   default); 0 for a GF operator.  GSF_EINVAL for NULL or m outside 1..8. */
+gsf_status gsf_get_apply_rows(const gsf_operator* op, int m, int* rows_per_thread);
+/* The process-wide table of tuned tile heights as a JSON file, so that a
+ * tuning run can be reused by later processes:
+ *   {"gsf_apply_tiles": [{"prec": 0|1, "geometry": 0 (1D) | 1 (2D square) |
+ *    2 (2D cross), "radius": 1..8, "width": 1|2|3|4|8, "size_class": 0..3
+ *    (n < 2^16, 2^20, 2^23, larger), "rows_per_thread": 1|2|4}, ...]}
+ *  gsf_tune_table_save: writes the tuned entries (count in *entries, NULL
+ *    allowed).  gsf_tune_table_load: reads a file of that form and sets its
+ *    entries (others unchanged); nothing is set if any entry is malformed or
+ *    out of range.  GSF_EINVAL for a NULL path, a file that cannot be opened,
+ *    written or parsed.  gsf_tune_table_clear: back to the defaults.
+ *  Not synchronised with concurrent tuning in other threads. */
+gsf_status gsf_tune_table_save(const char* path, int* entries);
+gsf_status gsf_tune_table_load(const char* path, int* entries);
+void gsf_tune_table_clear(void);
 
 /* ---- batching ----------------------------------------------------------------
  * Many independent items (each its own operator, signal and solver) filtered

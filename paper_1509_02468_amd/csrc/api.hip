@@ -4,6 +4,8 @@
 #include <mutex>
 #include <cstring>
 #include <new>
+#include <string>
+#include <cstdio>
 
 #include "gsf_internal.h"
 #include "lobpcg_launch.h"
@@ -78,6 +80,9 @@ gsf_status net_infer(int prec, const uint16_t* w, int64_t rows, int64_t cols, in
 gsf_status net_lob_select(int prec, int64_t rows, int64_t cols, int m, int constraint, void* W, const void* Z,
                           const void* sqd, const double* partials, int nparts, LobpcgState* st, hipStream_t s);
 int tz_blocks(int64_t rows, int64_t cols);
+int tune_table_write(FILE* f);
+int tune_table_read(const std::string& text);
+void tune_table_clear();
 gsf_status shifted_precond_apply(const gsf_precond* T, int m, const void* R, void* Z, hipStream_t s);
 gsf_status launch_tz_partials(int prec, const void* R, const void* Z, const void* sqd, int64_t rows, int64_t cols,
                               int m, const LobpcgState* st, double* partials, hipStream_t s);
@@ -1498,6 +1503,45 @@ gsf_status gsf_lobpcg_residual(const gsf_operator* h, int m, const void* X, cons
   GSF_TRY(apply_any(op, GSF_FORM_LSYM, m, X, m, R, m, nullptr, nullptr, s));
   return launch_residual(op.desc.prec, X, R, op.n, m, theta, s);
 }
+
+gsf_status gsf_get_apply_rows(const gsf_operator* h, int m, int* rows_per_thread) {
+  if (h == nullptr || rows_per_thread == nullptr || m < 1 || m > kMaxBlock) return GSF_EINVAL;
+  if (h->op.desc.kind != GSF_BF) {
+    *rows_per_thread = 0;
+    return GSF_OK;
+  }
+  const int w = m >= 8 ? 8 : (m >= 4 ? 4 : m);
+  *rows_per_thread = bf_rpt(h->op, w);
+  return GSF_OK;
+}
+
+gsf_status gsf_tune_table_save(const char* path, int* entries) {
+  if (path == nullptr) return GSF_EINVAL;
+  FILE* f = std::fopen(path, "w");
+  if (f == nullptr) return GSF_EINVAL;
+  const int count = tune_table_write(f);
+  const bool bad = std::ferror(f) != 0;
+  if (std::fclose(f) != 0 || bad) return GSF_EINVAL;
+  if (entries) *entries = count;
+  return GSF_OK;
+}
+
+gsf_status gsf_tune_table_load(const char* path, int* entries) {
+  if (path == nullptr) return GSF_EINVAL;
+  FILE* f = std::fopen(path, "r");
+  if (f == nullptr) return GSF_EINVAL;
+  std::string text;
+  char buf[4096];
+  size_t got;
+  while ((got = std::fread(buf, 1, sizeof(buf), f)) > 0) text.append(buf, got);
+  std::fclose(f);
+  const int count = tune_table_read(text);
+  if (count < 0) return GSF_EINVAL;
+  if (entries) *entries = count;
+  return GSF_OK;
+}
+
+void gsf_tune_table_clear(void) { tune_table_clear(); }
 
 gsf_status gsf_set_apply_rows(const gsf_operator* h, int m, int rows_per_thread) {
   if (h == nullptr || m < 1 || m > kMaxBlock || h->op.desc.kind != GSF_BF) return GSF_EINVAL;

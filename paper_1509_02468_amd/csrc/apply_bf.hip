@@ -1,4 +1,11 @@
-// BF apply: host dispatch over element type and block width.
+// BF apply: host dispatch over element type and block width, and the table
+// of tuned tile heights (with its JSON file form).
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
 #include "apply_bf_impl.h"
 
 namespace gsf {
@@ -39,6 +46,73 @@ int bf_rpt(const Operator& op, int w) {
 void bf_set_rpt(const Operator& op, int w, int rpt) {
   g_rpt[op.desc.prec][geometry(op)][op.desc.radius][w][size_class(op.n)] = rpt;
 }
+
+// Tuned-tile table as JSON: {"gsf_apply_tiles": [{"prec": p, "geometry": g,
+// "radius": r, "width": w, "size_class": c, "rows_per_thread": t}, ...]}
+// (only the tuned entries; geometry 0 = 1D, 1 = 2D square window, 2 = 2D
+// cross; size class 0..3 = n below 2^16, 2^20, 2^23, above).
+static const char* kTileKeys[6] = {"prec", "geometry", "radius", "width", "size_class", "rows_per_thread"};
+
+int tune_table_write(FILE* f) {
+  int count = 0;
+  std::fputs("{\"gsf_apply_tiles\": [", f);
+  for (int p = 0; p < 2; ++p)
+    for (int g = 0; g < 3; ++g)
+      for (int r = 0; r <= kMaxRadius; ++r)
+        for (int w = 0; w <= kMaxBlock; ++w)
+          for (int c = 0; c < 4; ++c) {
+            const int t = g_rpt[p][g][r][w][c];
+            if (t <= 0) continue;
+            std::fprintf(f, "%s\n  {\"prec\": %d, \"geometry\": %d, \"radius\": %d, \"width\": %d, "
+                            "\"size_class\": %d, \"rows_per_thread\": %d}",
+                         count ? "," : "", p, g, r, w, c, t);
+            ++count;
+          }
+  std::fputs("\n]}\n", f);
+  return count;
+}
+
+// Parses the table; entries replace the current values of their keys only if
+// the whole text is valid.  Returns the entry count, or -1 if malformed.
+int tune_table_read(const std::string& text) {
+  struct E { int v[6]; };
+  std::vector<E> es;
+  const size_t lst = text.find("\"gsf_apply_tiles\"");
+  if (lst == std::string::npos) return -1;
+  size_t pos = text.find('[', lst);
+  if (pos == std::string::npos) return -1;
+  const size_t end = text.find(']', pos);
+  if (end == std::string::npos) return -1;
+  while (true) {
+    const size_t o = text.find('{', pos);
+    if (o == std::string::npos || o > end) break;
+    const size_t cl = text.find('}', o);
+    if (cl == std::string::npos || cl > end) return -1;
+    const std::string obj = text.substr(o, cl - o + 1);
+    E e;
+    for (int k = 0; k < 6; ++k) {
+      const std::string key = std::string("\"") + kTileKeys[k] + "\"";
+      const size_t kp = obj.find(key);
+      if (kp == std::string::npos) return -1;
+      const size_t colon = obj.find(':', kp + key.size());
+      if (colon == std::string::npos) return -1;
+      char* stop = nullptr;
+      const long v = std::strtol(obj.c_str() + colon + 1, &stop, 10);
+      if (stop == obj.c_str() + colon + 1) return -1;
+      e.v[k] = (int)v;
+    }
+    const bool ok = e.v[0] >= 0 && e.v[0] < 2 && e.v[1] >= 0 && e.v[1] < 3 && e.v[2] >= 1 && e.v[2] <= kMaxRadius &&
+                    (e.v[3] == 1 || e.v[3] == 2 || e.v[3] == 3 || e.v[3] == 4 || e.v[3] == 8) && e.v[4] >= 0 &&
+                    e.v[4] < 4 && (e.v[5] == 1 || e.v[5] == 2 || e.v[5] == 4);
+    if (!ok) return -1;
+    es.push_back(e);
+    pos = cl + 1;
+  }
+  for (const E& e : es) g_rpt[e.v[0]][e.v[1]][e.v[2]][e.v[3]][e.v[4]] = e.v[5];
+  return (int)es.size();
+}
+
+void tune_table_clear() { std::memset(g_rpt, 0, sizeof(g_rpt)); }
 
 gsf_status launch_bf_apply_rpt(const Operator& op, int form, int m, const void* x, int64_t ldx, void* y,
                                int64_t ldy, double* dot, int* nparts, int rpt_override, hipStream_t s);

@@ -134,6 +134,10 @@ def load_library(path: str = LIB_PATH):
         "gsf_net_pair_workspace_bytes": ([vp, P(sz)], i32),
         "gsf_net_make_pair": ([vp, vp, i64, vp, i64, vp, vp, vp, vp, sz, vp], i32),
         "gsf_precond_create": ([vp, vp, vp, P(vp)], i32),
+        "gsf_get_apply_rows": ([vp, i32, P(i32)], i32),
+        "gsf_tune_table_save": ([ctypes.c_char_p, P(i32)], i32),
+        "gsf_tune_table_load": ([ctypes.c_char_p, P(i32)], i32),
+        "gsf_tune_table_clear": ([], None),
         "gsf_precond_create_shifted": ([vp, dbl, i32, P(vp)], i32),
         "gsf_precond_destroy": ([vp], None),
         "gsf_precond_workspace_bytes": ([vp, i32, P(sz)], i32),
@@ -434,6 +438,12 @@ class Operator:
                                    _stream(stream)), "tune_apply")
         return best.value, list(times)
 
+    def apply_rows(self, m):
+        """Rows per thread the BF apply of block width m uses (gsf_get_apply_rows)."""
+        v = ctypes.c_int()
+        _check(_lib.gsf_get_apply_rows(self.handle, m, ctypes.byref(v)), "get_apply_rows")
+        return v.value
+
     def set_apply_rows(self, m, rows_per_thread):
         """Pin the BF apply tile height for block width m (see gsf_set_apply_rows)."""
         _check(_lib.gsf_set_apply_rows(self.handle, m, rows_per_thread), "set_apply_rows")
@@ -660,6 +670,26 @@ class NetTrainer:
         _check(_lib.gsf_net_forward(_ptr(self.wb), idx.numel(), _ptr(idx), self.rows, self.cols, _ptr(inputs),
                                     _ptr(y), _ptr(ws), ws.numel(), _stream(stream)), "net_forward")
         return y
+
+
+def tune_table_save(path):
+    """Write the tuned apply tiles to a JSON file (gsf_tune_table_save); returns the entry count."""
+    lib = load_library()
+    n = ctypes.c_int()
+    _check(lib.gsf_tune_table_save(os.fsencode(path), ctypes.byref(n)), "tune_table_save")
+    return n.value
+
+
+def tune_table_load(path):
+    """Read tuned apply tiles from a JSON file (gsf_tune_table_load); returns the entry count."""
+    lib = load_library()
+    n = ctypes.c_int()
+    _check(lib.gsf_tune_table_load(os.fsencode(path), ctypes.byref(n)), "tune_table_load")
+    return n.value
+
+
+def tune_table_clear():
+    load_library().gsf_tune_table_clear()
 
 
 def build_operator(kind, shape, guidance, radius, sigma_d=0.0, sigma_r=0.0, eps=0.0, prec=F32, stream=None):

@@ -222,3 +222,35 @@ def test_identity_weights_layout():
     from oracle import convnet as cn
     from paper_1509_02468_amd import learned
     assert np.array_equal(learned.identity_weights().astype(np.float64), cn.identity_weights())
+
+
+def test_tune_table_json_round_trip(lib, tmp_path):
+    """The tuned-tile table survives a save / clear / load cycle through its
+    JSON file; malformed or out-of-range files are rejected and leave the
+    table unchanged (host only: no operator, no device)."""
+    import json
+    import paper_1509_02468_amd as pkg
+    pkg.tune_table_clear()
+    src = tmp_path / "tiles.json"
+    entries = [dict(prec=0, geometry=1, radius=5, width=4, size_class=1, rows_per_thread=2),
+               dict(prec=1, geometry=0, radius=3, width=1, size_class=3, rows_per_thread=4)]
+    src.write_text(json.dumps({"gsf_apply_tiles": entries}))
+    assert pkg.tune_table_load(str(src)) == 2
+    out = tmp_path / "saved.json"
+    assert pkg.tune_table_save(str(out)) == 2
+    key = lambda e: tuple(e[k] for k in ("prec", "geometry", "radius", "width", "size_class"))
+    assert sorted(json.loads(out.read_text())["gsf_apply_tiles"], key=key) == sorted(entries, key=key)
+    for bad in ({"gsf_apply_tiles": [dict(entries[0], rows_per_thread=3)]},
+                {"gsf_apply_tiles": [dict(entries[0], width=5)]},
+                {"gsf_apply_tiles": [{"prec": 0, "geometry": 1}]},
+                {"tiles": entries}):
+        src.write_text(json.dumps(bad))
+        with pytest.raises(pkg.GsfError):
+            pkg.tune_table_load(str(src))
+    assert pkg.tune_table_save(str(out)) == 2
+    with pytest.raises(pkg.GsfError):
+        pkg.tune_table_load(str(tmp_path / "missing.json"))
+    assert lib.gsf_tune_table_save(None, None) == 1
+    pkg.tune_table_clear()
+    assert pkg.tune_table_save(str(out)) == 0
+    assert json.loads(out.read_text()) == {"gsf_apply_tiles": []}
