@@ -50,7 +50,10 @@ block of m vectors (our reading; the paper gives the single-vector method):
   output: the projection y = X X^T z0 (+ Y Y^T z0 with the constraint),
   returned in x-space as D^-1/2 y.  It is the identity at k = 0 and tends to
   the GFT low-pass U_m U_m^T z0 (Section 4) as the Ritz block converges.
-  tol > 0 stops once every column's residual ||A x_j - theta_j x_j|| <= tol.
+  tol > 0 stops once every column's residual ||A x_j - theta_j x_j|| <= tol;
+  until then a column whose residual is already <= tol is soft-locked: its
+  x_j stays in the Rayleigh-Ritz basis but its W column is zero (so the
+  Rayleigh-Ritz step drops it and counts the drop).
   AX is carried by the update's linear combinations and recomputed as A X
   after every `refresh`-th step (20; 0 never), so that the rounding the
   recurrence accumulates does not set a floor under the residual (C-10, C-16:
@@ -205,6 +208,8 @@ class LobpcgInfo:
     dropped: int = 0          # columns removed by the Rayleigh-Ritz Cholesky
     res: np.ndarray = None    # final per-column residual norms
     theta_history: list = field(default_factory=list)
+    res_history: list = field(default_factory=list)    # residual norms each step starts from
+    drop_history: list = field(default_factory=list)   # columns dropped by each step
 
 
 def modulation_degrees(ndim: int, m: int):
@@ -350,6 +355,10 @@ def lobpcg_filter(op, x0, m: int, kmax: int, tol: float = 0.0, constraint: bool 
         if tol > 0.0 and np.max(res) <= tol:
             break
         W = R if precond is None else precondition(precond, R)
+        if tol > 0.0:
+            # soft locking: a column already at the tolerance adds no search
+            # direction (its zero column is then dropped by rayleigh_ritz)
+            W = np.where((res <= tol)[None, :], 0.0, W)
         if constraint:
             W = W - np.outer(Y, Y @ W)
         AW = A(W)
@@ -361,6 +370,8 @@ def lobpcg_filter(op, x0, m: int, kmax: int, tol: float = 0.0, constraint: bool 
             AS = np.column_stack([AX, AW, AP])
         theta, C, kept = rayleigh_ritz(S.T @ AS, S.T @ S, m, drop_tol, zero_tol)
         info.dropped += int(np.count_nonzero(~kept))
+        info.res_history.append(res.copy())
+        info.drop_history.append(int(np.count_nonzero(~kept)))
         Cp = C.copy()
         Cp[:m, :] = 0.0
         X, AX, P, AP = S @ C, AS @ C, S @ Cp, AS @ Cp

@@ -894,6 +894,7 @@ __global__ void __launch_bounds__(kThreads) gram_rr_kernel(GramArgs g, RRArgs r)
   __shared__ int keptf[KMAX];
   __shared__ double fred[8 * 16];
   __shared__ int live;
+  __shared__ int lockm;
   if (r.st != nullptr && !r.st->active) return;
   const int nt = (g.ns + 15) >> 4;
   const int ntb = n_tiles_b(nt), ntot = ntb + n_tiles_a(nt);
@@ -978,6 +979,30 @@ __global__ void __launch_bounds__(kThreads) gram_rr_kernel(GramArgs g, RRArgs r)
 #pragma unroll
     for (int c = 0; c < kGramChunks; ++c) v[c] = g.level2[(size_t)c * (ntot * 256) + e];
     place(e, v);
+  }
+  // soft locking (tol > 0): a column whose residual is already at the
+  // tolerance adds no search direction, i.e. its W column counts as zero:
+  // the W rows and columns of both Gram matrices are cleared, and the
+  // Rayleigh-Ritz step drops the column
+  if (threadIdx.x == 0) {
+    int mask = 0;
+    if (!r.init && r.st != nullptr && r.st->tol > 0.0 && g.ns > g.m)
+      for (int j = 0; j < g.m; ++j)
+        if (r.st->res[j] <= r.st->tol) mask |= 1 << j;
+    lockm = mask;
+  }
+  __syncthreads();
+  if (lockm != 0) {
+    const int lk = lockm;
+    for (int e = threadIdx.x; e < g.ns * g.ns; e += blockDim.x) {
+      const int i = e / g.ns, j = e - (e / g.ns) * g.ns;
+      const bool li = i >= g.m && i < 2 * g.m && ((lk >> (i - g.m)) & 1);
+      const bool lj = j >= g.m && j < 2 * g.m && ((lk >> (j - g.m)) & 1);
+      if (li || lj) {
+        sh.A[i * LD + j] = 0.0;
+        sh.B[i * LD + j] = 0.0;
+      }
+    }
   }
   __syncthreads();
   if (r.gram_out != nullptr) {

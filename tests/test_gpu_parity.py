@@ -469,3 +469,41 @@ def test_gf_one_column_all_forms_edges(gsf, shape, radius, prec):
         assert e <= TOL[prec], (form, e)
         assert np.array_equal(yw[:, 2].cpu().numpy(), y)
         assert not yw[:, 0].any() and not yw[:, 1].any()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_lobpcg_soft_locking_parity(gsf, prec):
+    """LOBPCG to a tolerance, where columns reach it at different steps and
+    are soft-locked (their W columns count as zero): the GPU stops at the
+    oracle's step with the same drop count (where the oracle's reversed run
+    agrees) and the same Ritz values, and its output meets the FP64 band gate
+    or the FP32 bar."""
+    shape, seed = (20, 20), 3
+    g = scene_2d(*shape, 0.05, seed)[1]
+    par = dict(radius=2, sigma_d=2.0, sigma_r=0.3)
+    gr = _round(g, prec, gsf)
+    tol = 1e-9 if prec == 1 else 1e-5
+    op = gsf.Operator("bf", shape, _torch(gr.ravel(), prec, gsf), **par, prec=prec)
+    y, info = op.lobpcg_filter(_torch(gr.ravel(), prec, gsf), 3, 500, tol=tol)
+
+    def run(gg):
+        o = oracle.build_operator("bf", gg, 2, 2.0, 0.3)
+        yy, th, _, rinfo = oracle.lobpcg_filter(o, gg.ravel(), 3, 500, tol=tol,
+                                                data_prec="f64" if prec == 1 else "f32")
+        return yy, (th, rinfo)
+    ref = reference(run, gr)
+    th, rinfo = ref.extra
+    e = rel(y.cpu().numpy(), ref.y)
+    print(f"soft locking prec={prec}: iters {info.iters}/{rinfo.iters}, dropped {info.dropped}/{rinfo.dropped} "
+          f"(reversed {ref.extra_reversed[1].dropped}), y rel {e:.2e}")
+    assert info.status == gsf.OK and rinfo.status == "ok"
+    assert sum(rinfo.drop_history) > 0
+    if prec == 1:
+        assert info.iters == rinfo.iters
+        if rinfo.dropped == ref.extra_reversed[1].dropped:
+            assert info.dropped == rinfo.dropped
+        assert e <= ref.gate
+        np.testing.assert_allclose(np.array(list(info.theta)[:3]), th, rtol=1e-9, atol=1e-13)
+    else:
+        assert abs(info.iters - rinfo.iters) <= 3
+        assert e <= 1e-5

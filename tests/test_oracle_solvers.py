@@ -351,3 +351,30 @@ def test_exact_shifted_solve_preconditioner_bound():
     assert plain.status == "ok"
     assert 3 * steps[0] <= plain.iters
     assert steps[0] <= steps[1] <= steps[2] <= plain.iters
+
+
+def test_lobpcg_soft_locking():
+    """tol > 0: a column whose residual is already at the tolerance has a
+    zero W column, so every step that starts from such a residual drops at
+    least that many columns; the locked run still converges to the lowest
+    eigenpairs of the dense operator, and with tol = 0 nothing is locked."""
+    g = scene_2d(20, 20, 0.05, 3)[1]
+    op = oracle.build_operator("bf", g, 2, 2.0, 0.3)
+    tol = 1e-9
+    y, th, X, info = oracle.lobpcg_filter(op, g.ravel(), 3, 500, tol=tol)
+    assert info.status == "ok"
+    locked_steps = 0
+    for res, drops in zip(info.res_history, info.drop_history):
+        nl = int(np.count_nonzero(res <= tol))
+        assert drops >= nl
+        locked_steps += nl > 0
+    assert locked_steps >= 3
+    lam = eig_lsym(op)[0]
+    np.testing.assert_allclose(th, lam[:3], atol=1e-12)
+    assert np.max(info.res) <= tol
+    # the same iteration without a tolerance: nothing is locked, so its first
+    # steps (before any column reaches 1e-9) drop nothing more than the locked run
+    _, _, _, free = oracle.lobpcg_filter(op, g.ravel(), 3, info.iters)
+    first = next(k for k, r in enumerate(info.res_history) if np.any(r <= tol))
+    assert free.drop_history[:first] == info.drop_history[:first]
+    assert sum(free.drop_history) < info.dropped
