@@ -324,6 +324,8 @@ gsf_status gsf_srgb_to_lab(int prec, int64_t n, const void* rgb, void* lab, void
  * ritz_vals_host (NULL or m host doubles): the Ritz values theta_j ascending;
  * non-NULL synchronizes the stream, as a non-NULL info does.
  * tol > 0 stops when every column residual <= tol (GSF_ENOTCONV if not met);
+ * until then a column already at tol is soft-locked: its W column counts as
+ * zero (dropped by the Rayleigh-Ritz step, counted in info->dropped);
  * with info != NULL the host then also stops issuing steps (it reads the
  * device convergence flag every 16 steps, 16 steps behind the queue).
  * A start block of rank < m returns x0 with GSF_EBREAKDOWN.
