@@ -345,7 +345,7 @@ size_t carve_lob(const Operator& op, int m, char* base, LobWs* w) {
   w->AW = c.take(blk);
   w->AP = c.take(blk);
   w->gram_partials = (double*)c.take((size_t)gram_blocks(op.n) * 7 * 256 * sizeof(double));
-  w->gram_level2 = (double*)c.take((size_t)kGramChunks * 7 * 256 * sizeof(double));
+  w->gram_level2 = (double*)c.take((size_t)kGramLevel2Doubles * sizeof(double));
   w->C = (double*)c.take(24 * 8 * sizeof(double));
   w->theta = (double*)c.take(8 * sizeof(double));
   w->vpart = (double*)c.take((size_t)vec_blocks(op.n) * 17 * sizeof(double));
@@ -1311,7 +1311,7 @@ gsf_status gsf_block_gram(int prec, int64_t n, int m, int nb, const void* const*
   g.n = n;
   g.nparts = gb;
   g.partials = (double*)w.take((size_t)gb * 7 * 256 * 8);
-  g.level2 = (double*)w.take((size_t)kGramChunks * 7 * 256 * 8);
+  g.level2 = (double*)w.take((size_t)kGramLevel2Doubles * 8);
   double* gout = (double*)w.take(2 * 24 * 24 * 8);
   double* C = (double*)w.take(24 * 8 * 8);
   double* th = (double*)w.take(64);
@@ -1342,7 +1342,7 @@ gsf_status gsf_block_gram_workspace_bytes(int64_t n, size_t* bytes) {
   Carve c{nullptr};
   const int gb = gram_blocks(n);
   c.take((size_t)gb * 7 * 256 * 8);
-  c.take((size_t)kGramChunks * 7 * 256 * 8);
+  c.take((size_t)kGramLevel2Doubles * 8);
   c.take(2 * 24 * 24 * 8);
   c.take(24 * 8 * 8);
   c.take(64);

@@ -865,10 +865,45 @@ __device__ void rayleigh_ritz(RRShared& sh, int ns, int m, double drop_tol, doub
     rayleigh_ritz_kb<KMAX>(sh, ns, m, drop_tol, zero_tol, Cout, theta, kept_out, nkept_out);
 }
 
+// The previous update's residual sums (|R_j|^2 for j < m, summed over its
+// workgroup partials in workgroup order) into fin[0..7], for the
+// Rayleigh-Ritz step that finalizes them; one workgroup.
+__device__ void fin_reduce(const RRArgs& r, int m, double* fin) {
+  __shared__ double fred[8 * 16];
+  double t[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) t[k] = 0.0;
+  for (int b0 = 0; b0 < r.fin_nparts; b0 += 4 * (int)blockDim.x) {
+    double fv[4][8];
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+      const int b = b0 + it * (int)blockDim.x + (int)threadIdx.x;
+      const int bb = b < r.fin_nparts ? b : 0;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) fv[it][k] = r.fin_partials[(size_t)bb * r.fin_stride + (k < m ? k : 0)];
+    }
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+      const bool ok = b0 + it * (int)blockDim.x + (int)threadIdx.x < r.fin_nparts;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) t[k] += (ok && k < m) ? fv[it][k] : 0.0;
+    }
+  }
+  block_sum<8>(t, fred);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 8; ++k) fin[k] = t[k];
+}
+
 // First stage of the Gram reduction: workgroup (tile, chunk) sums the partials
-// of its chunk of Gram workgroups for the 256 entries of one tile.
-__global__ void __launch_bounds__(kThreads) gram_reduce_kernel(GramArgs g) {
+// of its chunk of Gram workgroups for the 256 entries of one tile; the extra
+// workgroup column (blockIdx.x = tiles) reduces the previous update's residual
+// partials for the Rayleigh-Ritz step, off its critical path.
+__global__ void __launch_bounds__(kThreads) gram_reduce_kernel(GramArgs g, RRArgs r) {
   if (g.active != nullptr && *g.active == 0) return;
+  if ((int)blockIdx.x == (int)gridDim.x - 1) {
+    if (blockIdx.y == 0 && r.fin_partials != nullptr) fin_reduce(r, g.m, g.level2 + kGramFinSlot);
+    return;
+  }
   const int nt = (g.ns + 15) >> 4;
   const int ntot = n_tiles_b(nt) + n_tiles_a(nt);
   const int tile = blockIdx.x, chunk = blockIdx.y, nchunks = gridDim.y;
@@ -892,7 +927,6 @@ __global__ void __launch_bounds__(kThreads) gram_rr_kernel(GramArgs g, RRArgs r)
   __shared__ RRShared sh;
   __shared__ int nkept;
   __shared__ int keptf[KMAX];
-  __shared__ double fred[8 * 16];
   __shared__ int live;
   __shared__ int lockm;
   if (r.st != nullptr && !r.st->active) return;
@@ -908,27 +942,12 @@ __global__ void __launch_bounds__(kThreads) gram_rr_kernel(GramArgs g, RRArgs r)
   if (r.fin_partials != nullptr) {
     // the previous update's residual norms, iteration count and convergence
     // test (what lob_final_kernel does after an update without the
-    // constraint, in the same summation order); at most 1024 partial rows
+    // constraint, in the same summation order); the sums come reduced from
+    // gram_reduce_kernel's extra workgroup
     double t[8];
+    if (threadIdx.x == 0)
 #pragma unroll
-    for (int k = 0; k < 8; ++k) t[k] = 0.0;
-    for (int b0 = 0; b0 < r.fin_nparts; b0 += 4 * (int)blockDim.x) {
-      double fv[4][8];
-#pragma unroll
-      for (int it = 0; it < 4; ++it) {
-        const int b = b0 + it * (int)blockDim.x + (int)threadIdx.x;
-        const int bb = b < r.fin_nparts ? b : 0;
-#pragma unroll
-        for (int k = 0; k < 8; ++k) fv[it][k] = r.fin_partials[(size_t)bb * r.fin_stride + (k < g.m ? k : 0)];
-      }
-#pragma unroll
-      for (int it = 0; it < 4; ++it) {
-        const bool ok = b0 + it * (int)blockDim.x + (int)threadIdx.x < r.fin_nparts;
-#pragma unroll
-        for (int k = 0; k < 8; ++k) t[k] += (ok && k < g.m) ? fv[it][k] : 0.0;
-      }
-    }
-    block_sum<8>(t, fred);
+      for (int k = 0; k < 8; ++k) t[k] = g.level2[kGramFinSlot + k];
     if (threadIdx.x == 0) {
       LobpcgState* st = r.st;
       double mx = 0.0;
@@ -1314,8 +1333,8 @@ gsf_status lob_launch_gram(const GramArgs& g, const RRArgs& r, int prec, hipStre
     else
       gram_kernel<double, 1><<<g.nparts, kThreads, 0, s>>>(g);
   }
-  dim3 grid(gram_tiles_total(g.ns), kGramChunks);
-  gram_reduce_kernel<<<grid, kThreads, 0, s>>>(g);
+  dim3 grid(gram_tiles_total(g.ns) + 1, kGramChunks);
+  gram_reduce_kernel<<<grid, kThreads, 0, s>>>(g, r);
   gram_rr_kernel<<<1, rr_threads(g.ns), 0, s>>>(g, r);
   return launch_status();
 }

@@ -7,6 +7,10 @@
 namespace gsf {
 
 constexpr int kGramChunks = 16;     // first-stage split of the Gram partial reduction
+// level-2 buffer: kGramChunks x (up to 7 tiles) x 256 chunk sums, then the
+// previous update's reduced residual sums (8 values, at kGramFinSlot)
+constexpr int kGramFinSlot = kGramChunks * 7 * 256;
+constexpr int kGramLevel2Doubles = kGramFinSlot + 32;
 constexpr int kGramPerChunk = 64;   // partials per chunk (kGramBlocks / kGramChunks)
 constexpr int kGramBlocks = 1024; // workgroups of the Gram kernel (at most)
 
