@@ -6,8 +6,9 @@
 //   lob_start      X0[:, j] = z0 * phi_j (Legendre modulations), Y^T X0
 //   lob_project    B -= Y c (constraint projection of a block)
 //   gram           partial Gram tiles S^T S, S^T (A S) of S = [X, W, P] with
-//                  MFMA (FP32: v_mfma_f32_16x16x4f32 accumulated in FP32 over
-//                  256 points then in FP64; FP64: v_mfma_f64_16x16x4f64)
+//                  MFMA, v_mfma_f64_16x16x4f64 for both data types (an FP32
+//                  value widened to FP64 loses nothing and the product of two
+//                  is exact in FP64, so FP32 data get FP64 sums too)
 //   gram_reduce /  fixed-order two-level reduction of the tiles, then the
 //   gram_rr        Rayleigh-Ritz step on one workgroup in FP64: unit-diagonal scaling,
 //                  column-dropping Cholesky, reduction to L^-1 A L^-T, the m
@@ -137,29 +138,19 @@ __global__ void __launch_bounds__(kThreads) lob_project_kernel(T* __restrict__ B
 __device__ __forceinline__ int n_tiles_b(int nt) { return nt == 1 ? 1 : 3; }
 __device__ __forceinline__ int n_tiles_a(int nt) { return nt == 1 ? 1 : 4; }
 
-template <typename T>
-struct MfmaAcc;
-template <>
-struct MfmaAcc<float> {
-  typedef floatx4 type;
-  static __device__ __forceinline__ floatx4 mfma(float a, float b, floatx4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-  }
-};
-template <>
-struct MfmaAcc<double> {
-  typedef doublex4 type;
-  static __device__ __forceinline__ doublex4 mfma(double a, double b, doublex4 c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-  }
-};
+__device__ __forceinline__ doublex4 mfma64(double a, double b, doublex4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
 
 template <typename T, int NT>
 __global__ void __launch_bounds__(kThreads) gram_kernel(GramArgs g) {
-  typedef typename MfmaAcc<T>::type acc_t;
+  // every product and sum in FP64: the Gram entries that steer a nearly
+  // converged column (X^T A W ~ ||r||) are far below the size of their
+  // terms, and FP32 sums of FP32 products lose them
+  typedef doublex4 acc_t;
   typedef const __attribute__((address_space(1))) T* gptr;
   // groups of 4 points per stage (one MFMA k-step each); fewer for the wider
-  // tiles and FP64, whose stages hold more registers
+  // tiles and FP64 data, whose stages hold more registers
   constexpr int U = (NT == 1 && sizeof(T) == 4) ? 8 : 4;
   constexpr int G = 4 * U;      // points per stage
   constexpr int ntb = NT == 1 ? 1 : 3, nta = NT == 1 ? 1 : 4;
@@ -184,8 +175,8 @@ __global__ void __launch_bounds__(kThreads) gram_kernel(GramArgs g) {
     ap[I] = (gptr)g.AS[b] + j;
   }
 
-  // FP32 partials move into FP64 every FL points (256); FP64 needs no flush
-  constexpr int FL = sizeof(T) == 4 ? 256 : 2 * G;
+  // the loop body covers two stages
+  constexpr int FL = 2 * G;
   const int64_t nw = (int64_t)gridDim.x * 4;
   const int64_t wid = (int64_t)blockIdx.x * 4 + wave;
   int64_t chunk = (g.n + nw - 1) / nw;
@@ -233,32 +224,28 @@ __global__ void __launch_bounds__(kThreads) gram_kernel(GramArgs g) {
   auto mfmas = [&](const T (&s)[2][U], const T (&a)[2][U], const T (&mk)[2][U]) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const T s0m = s[0][u] * mk[0][u];
-      accb[0] = MfmaAcc<T>::mfma(s0m, s[0][u], accb[0]);
-      acca[0] = MfmaAcc<T>::mfma(s0m, a[0][u], acca[0]);
+      const double s0 = (double)s[0][u], s0m = (double)(s[0][u] * mk[0][u]);
+      accb[0] = mfma64(s0m, s0, accb[0]);
+      acca[0] = mfma64(s0m, (double)a[0][u], acca[0]);
       if constexpr (NT > 1) {
-        const T s1m = s[1][u] * mk[1][u];
-        accb[1] = MfmaAcc<T>::mfma(s0m, s[1][u], accb[1]);
-        accb[2] = MfmaAcc<T>::mfma(s1m, s[1][u], accb[2]);
-        acca[1] = MfmaAcc<T>::mfma(s0m, a[1][u], acca[1]);
-        acca[2] = MfmaAcc<T>::mfma(s1m, a[0][u], acca[2]);
-        acca[3] = MfmaAcc<T>::mfma(s1m, a[1][u], acca[3]);
+        const double s1 = (double)s[1][u], s1m = (double)(s[1][u] * mk[1][u]);
+        accb[1] = mfma64(s0m, s1, accb[1]);
+        accb[2] = mfma64(s1m, s1, accb[2]);
+        acca[1] = mfma64(s0m, (double)a[1][u], acca[1]);
+        acca[2] = mfma64(s1m, (double)a[0][u], acca[2]);
+        acca[3] = mfma64(s1m, (double)a[1][u], acca[3]);
       }
     }
   };
   auto flush = [&]() {
 #pragma unroll
-    for (int t = 0; t < ntb; ++t) {
+    for (int t = 0; t < ntb; ++t)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) totb[t][v] += (double)accb[t][v];
-      accb[t] = acc_t{0, 0, 0, 0};
-    }
+      for (int v = 0; v < 4; ++v) totb[t][v] = accb[t][v];
 #pragma unroll
-    for (int t = 0; t < nta; ++t) {
+    for (int t = 0; t < nta; ++t)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) tota[t][v] += (double)acca[t][v];
-      acca[t] = acc_t{0, 0, 0, 0};
-    }
+      for (int v = 0; v < 4; ++v) tota[t][v] = acca[t][v];
   };
 
   // two register stages: the loads of the next stage are in flight while the
@@ -282,15 +269,13 @@ __global__ void __launch_bounds__(kThreads) gram_kernel(GramArgs g) {
         mfmas(s1, a1, k1);
         __builtin_amdgcn_sched_barrier(0);
       }
-      if (sizeof(T) == 4) flush();
     }
   }
   flush();
 
-  // fixed-order sum over the 4 waves, one tile at a time.  Output layouts of
-  // the two MFMA variants (entry e = i*16 + j of a tile):
-  //   16x16x4 f32: D[i][j] in lane j + 16*(i/4), register i%4
-  //   16x16x4 f64: D[i][j] in lane j + 16*(i%4), register i/4
+  // fixed-order sum over the 4 waves, one tile at a time.  Output layout of
+  // 16x16x4 f64 (entry e = i*16 + j of a tile): D[i][j] in lane
+  // j + 16*(i%4), register i/4
   const int ntot = ntb + nta;
   for (int t = 0; t < ntot; ++t) {
 #pragma unroll
@@ -308,8 +293,8 @@ __global__ void __launch_bounds__(kThreads) gram_kernel(GramArgs g) {
     {
       const int ij = threadIdx.x;  // 256 threads = 256 entries
       const int i = ij >> 4, j = ij & 15;
-      const int ln = sizeof(T) == 4 ? j + 16 * (i >> 2) : j + 16 * (i & 3);
-      const int v = sizeof(T) == 4 ? (i & 3) : (i >> 2);
+      const int ln = j + 16 * (i & 3);
+      const int v = i >> 2;
       const double sm = wsum[0][v][ln] + wsum[1][v][ln] + wsum[2][v][ln] + wsum[3][v][ln];
       g.partials[((size_t)blockIdx.x * ntot + t) * 256 + ij] = sm;
     }

@@ -89,3 +89,4 @@ def reference(run, *grids) -> Reference:
     yr, extra_r = run(*[flip_grid(g) for g in grids])
     b = rel(np.asarray(y, dtype=np.float64), flip_points(np.asarray(yr, dtype=np.float64)))
     return Reference(y=y, extra=extra, extra_reversed=extra_r, band=b, gate=max(FLOOR, FACTOR * b))
+

@@ -231,9 +231,14 @@ def test_block_gram_parity(gsf, prec, m, nb):
     A = [_round(rng.standard_normal((n, m)), prec, gsf) for _ in range(nb)]
     GA, GB = gsf.block_gram([_torch(s, prec, gsf) for s in S], [_torch(a, prec, gsf) for a in A], prec=prec)
     Sf, Af = np.column_stack(S), np.column_stack(A)
-    tol = 1e-13 if prec == 1 else 2e-6
-    assert rel(GB, Sf.T @ Sf) <= tol
-    assert rel(GA, Sf.T @ Af) <= tol
+    assert rel(GB, Sf.T @ Sf) <= 1e-13
+    assert rel(GA, Sf.T @ Af) <= 1e-13
+    # entry by entry: products of FP32 or FP64 data summed in FP64 stay within
+    # the textbook bound n 2^-53 |S|^T |A| of the exact sum (FP32 sums would
+    # not, on entries much smaller than their terms)
+    bound = n * 2.0 ** -53
+    assert np.all(np.abs(GB - Sf.T @ Sf) <= bound * (np.abs(Sf).T @ np.abs(Sf)))
+    assert np.all(np.abs(GA - Sf.T @ Af) <= bound * (np.abs(Sf).T @ np.abs(Af)))
 
 
 @pytest.mark.parametrize("ns,m,drop", [(1, 1, False), (2, 1, False), (9, 3, False), (16, 4, False),
