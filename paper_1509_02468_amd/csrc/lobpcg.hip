@@ -6,9 +6,10 @@
 //   lob_start      X0[:, j] = z0 * phi_j (Legendre modulations), Y^T X0
 //   lob_project    B -= Y c (constraint projection of a block)
 //   gram           partial Gram tiles S^T S, S^T (A S) of S = [X, W, P] with
-//                  MFMA, v_mfma_f64_16x16x4f64 for both data types (an FP32
-//                  value widened to FP64 loses nothing and the product of two
-//                  is exact in FP64, so FP32 data get FP64 sums too)
+//                  MFMA, 4x4 tiles of v_mfma_f64_4x4x4f64 for both data types
+//                  (an FP32 value widened to FP64 loses nothing and the
+//                  product of two is exact in FP64, so FP32 data get FP64 sums
+//                  too)
 //   gram_reduce /  fixed-order two-level reduction of the tiles, then the
 //   gram_rr        Rayleigh-Ritz step on one workgroup in FP64: unit-diagonal scaling,
 //                  column-dropping Cholesky, reduction to L^-1 A L^-T, the m
@@ -26,8 +27,6 @@
 namespace gsf {
 namespace {
 
-typedef float floatx4 __attribute__((ext_vector_type(4)));
-typedef double doublex4 __attribute__((ext_vector_type(4)));
 
 // ---------------------------------------------------------------------------
 // small helpers
@@ -133,50 +132,68 @@ __global__ void __launch_bounds__(kThreads) lob_project_kernel(T* __restrict__ B
 // ---------------------------------------------------------------------------
 // Gram tiles with MFMA
 // ---------------------------------------------------------------------------
-// Tiles of 16x16: nt = ceil(ns/16) tile rows.  S^T S: upper tiles (I <= J)
-// in the order (0,0), (0,1), (1,1); S^T AS: all tiles (0,0), (0,1), (1,0), (1,1).
+// Output format (read by the reductions and the Rayleigh-Ritz step): tiles of
+// 16x16 entries, nt = ceil(ns/16) tile rows.  S^T S: upper tiles (I <= J) in
+// the order (0,0), (0,1), (1,1); S^T AS: all tiles (0,0), (0,1), (1,0), (1,1).
 __device__ __forceinline__ int n_tiles_b(int nt) { return nt == 1 ? 1 : 3; }
 __device__ __forceinline__ int n_tiles_a(int nt) { return nt == 1 ? 1 : 4; }
 
-__device__ __forceinline__ doublex4 mfma64(double a, double b, doublex4 c) {
-  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+// v_mfma_f64_4x4x4f64 runs four independent 4x4x4 products (blocks q = 0..3).
+// Lane l holds A[i = l%4][k = l/16] and B[k = l/16][j = l%4] of block
+// q = (l/4)%4, and receives D[i = l/16][j = l%4] of that block (found with a
+// probe of the instruction on the GPU).
+__device__ __forceinline__ double mfma4(double a, double b, double c) {
+  return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
 }
 
-template <typename T, int NT>
+// index of the S^T S tile (I, J), I <= J, of TG column groups (row-major upper)
+template <int TG>
+__device__ __forceinline__ constexpr int tile_b(int I, int J) {
+  return I * TG - (I * (I - 1)) / 2 + (J - I);
+}
+
+// S^T S and S^T AS over the points of each workgroup, in FP64 for both data
+// types: an FP32 value widened to FP64 loses nothing and the product of two is
+// exact in FP64, so FP32 data get exact products and FP64 sums.  (The entries
+// that steer a nearly converged column, X^T A W ~ ||r||, are far below the
+// size of their terms; FP32 sums lose them.)
+//
+// The ns columns form TG groups of 4.  Every lane takes one point and one
+// column of a group: lane l reads point p0 + l/4, column 4G + l%4, which
+// makes each group's loads one contiguous run per instruction for m = 4 and
+// 8.  With that mapping block q of the MFMA sums the points p0 + 4k + q, and
+// one instruction adds 16 points to the 4x4 tile of groups (I, J):
+// A = the S values of group I, B = the AS (or S) values of group J.  A stage
+// of 16 points is TG loads of S and TG of AS per lane, TG^2 + TG(TG+1)/2
+// MFMAs.  The four blocks are summed across lanes at the end, then the four
+// waves, in fixed order.
+template <typename T, int TG>
 __global__ void __launch_bounds__(kThreads) gram_kernel(GramArgs g) {
-  // every product and sum in FP64: the Gram entries that steer a nearly
-  // converged column (X^T A W ~ ||r||) are far below the size of their
-  // terms, and FP32 sums of FP32 products lose them
-  typedef doublex4 acc_t;
   typedef const __attribute__((address_space(1))) T* gptr;
-  // groups of 4 points per stage (one MFMA k-step each); fewer for the wider
-  // tiles and FP64 data, whose stages hold more registers
-  constexpr int U = (NT == 1 && sizeof(T) == 4) ? 8 : 4;
-  constexpr int G = 4 * U;      // points per stage
-  constexpr int ntb = NT == 1 ? 1 : 3, nta = NT == 1 ? 1 : 4;
-  constexpr int nt = NT;
-  __shared__ double wsum[4][4][64];  // one tile at a time: wave, register, lane
+  constexpr int NA = TG * TG, NB = TG * (TG + 1) / 2;
+  constexpr int NS = 3;        // register stages (loads of the next two in flight)
+  constexpr int FL = NS * 16;  // points of one loop trip
+  __shared__ double red[4][NA + NB][16];
   if (g.active != nullptr && *g.active == 0) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int ns = g.ns, m = g.m;
-  const int col = lane & 15, krow = lane >> 4;
+  const int pl = lane >> 2, cl = lane & 3;
 
-  // the S / AS column each lane feeds for tile row I; lanes past the last
-  // column read column 0 and feed zeros
-  gptr sp[2], ap[2];
-  bool live[2];
+  // the S / AS column this lane feeds for group G; lanes past the last
+  // column read column 0 and feed zeros as A operands
+  gptr sp[TG], ap[TG];
+  float lv[TG];
 #pragma unroll
-  for (int I = 0; I < 2; ++I) {
-    const int c = 16 * I + col;
-    live[I] = I < nt && c < ns;
-    const int cc = live[I] ? c : 0;
+  for (int G = 0; G < TG; ++G) {
+    const int c = 4 * G + cl;
+    const bool live = c < ns;
+    const int cc = live ? c : 0;
     const int b = cc / m, j = cc - (cc / m) * m;
-    sp[I] = (gptr)g.S[b] + j;
-    ap[I] = (gptr)g.AS[b] + j;
+    sp[G] = (gptr)g.S[b] + j;
+    ap[G] = (gptr)g.AS[b] + j;
+    lv[G] = live ? 1.0f : 0.0f;
   }
 
-  // the loop body covers two stages
-  constexpr int FL = 2 * G;
   const int64_t nw = (int64_t)gridDim.x * 4;
   const int64_t wid = (int64_t)blockIdx.x * 4 + wave;
   int64_t chunk = (g.n + nw - 1) / nw;
@@ -184,121 +201,108 @@ __global__ void __launch_bounds__(kThreads) gram_kernel(GramArgs g) {
   const int64_t p_begin = wid * chunk;
   const int64_t p_end = (p_begin + chunk < g.n) ? p_begin + chunk : g.n;
 
-  double totb[ntb][4], tota[nta][4];
+  double acca[NA], accb[NB];
 #pragma unroll
-  for (int t = 0; t < ntb; ++t)
+  for (int t = 0; t < NA; ++t) acca[t] = 0.0;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) totb[t][v] = 0.0;
-#pragma unroll
-  for (int t = 0; t < nta; ++t)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) tota[t][v] = 0.0;
-  acc_t accb[ntb], acca[nta];
-#pragma unroll
-  for (int t = 0; t < ntb; ++t) accb[t] = acc_t{0, 0, 0, 0};
-#pragma unroll
-  for (int t = 0; t < nta; ++t) acca[t] = acc_t{0, 0, 0, 0};
+  for (int t = 0; t < NB; ++t) accb[t] = 0.0;
 
-  // one stage: the U point groups starting at p0.  Every load is issued
-  // unconditionally (points past the end re-read p_begin); the 0/1 mask of a
-  // point (and of a column past ns) multiplies only the A operand of its
-  // MFMAs, when they run a stage later: A[i][k] = 0 removes point k from
-  // every product, and the tile entries of the dead B columns are never read.
-  // (Masking at load time lets the compiler sink the loads into branches or
-  // wait for them at once.)  A non-finite value at p_begin already makes the
-  // sums non-finite, so re-reading it changes nothing.
-  auto load = [&](int64_t p0, T (&s)[2][U], T (&a)[2][U], T (&mk)[2][U]) {
+  // loads are unconditional (a point past the end re-reads p_begin); its
+  // 0/1 mask multiplies only the A operands, when the stage's MFMAs run
+  auto load = [&](int64_t p0, T (&sv)[TG], T (&av)[TG], T& mk) {
+    const int64_t p = p0 + pl;
+    const bool ok = p < p_end;
+    const int64_t off = (ok ? p : p_begin) * m;
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int64_t p = p0 + 4 * u + krow;
-      const bool ok = p < p_end;
-      const int64_t off = (ok ? p : p_begin) * m;
-#pragma unroll
-      for (int I = 0; I < nt; ++I) {
-        s[I][u] = sp[I][off];
-        a[I][u] = ap[I][off];
-        mk[I][u] = (ok && live[I]) ? T(1) : T(0);
-      }
+    for (int G = 0; G < TG; ++G) {
+      sv[G] = sp[G][off];
+      av[G] = ap[G][off];
     }
+    mk = ok ? T(1) : T(0);
   };
-  auto mfmas = [&](const T (&s)[2][U], const T (&a)[2][U], const T (&mk)[2][U]) {
+  auto mfmas = [&](const T (&sv)[TG], const T (&av)[TG], T mk) {
+    double sa[TG], sb[TG], ab[TG];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const double s0 = (double)s[0][u], s0m = (double)(s[0][u] * mk[0][u]);
-      accb[0] = mfma64(s0m, s0, accb[0]);
-      acca[0] = mfma64(s0m, (double)a[0][u], acca[0]);
-      if constexpr (NT > 1) {
-        const double s1 = (double)s[1][u], s1m = (double)(s[1][u] * mk[1][u]);
-        accb[1] = mfma64(s0m, s1, accb[1]);
-        accb[2] = mfma64(s1m, s1, accb[2]);
-        acca[1] = mfma64(s0m, (double)a[1][u], acca[1]);
-        acca[2] = mfma64(s1m, (double)a[0][u], acca[2]);
-        acca[3] = mfma64(s1m, (double)a[1][u], acca[3]);
-      }
+    for (int G = 0; G < TG; ++G) {
+      sa[G] = (double)(sv[G] * (mk * (T)lv[G]));
+      sb[G] = (double)sv[G];
+      ab[G] = (double)av[G];
     }
-  };
-  auto flush = [&]() {
 #pragma unroll
-    for (int t = 0; t < ntb; ++t)
+    for (int I = 0; I < TG; ++I)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) totb[t][v] = accb[t][v];
+      for (int J = 0; J < TG; ++J) acca[I * TG + J] = mfma4(sa[I], ab[J], acca[I * TG + J]);
 #pragma unroll
-    for (int t = 0; t < nta; ++t)
+    for (int I = 0; I < TG; ++I)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) tota[t][v] = acca[t][v];
+      for (int J = I; J < TG; ++J) accb[tile_b<TG>(I, J)] = mfma4(sa[I], sb[J], accb[tile_b<TG>(I, J)]);
   };
 
-  // two register stages: the loads of the next stage are in flight while the
-  // MFMAs of the current one run
   if (p_begin < p_end) {
-    T s0[2][U], a0[2][U], k0[2][U], s1[2][U], a1[2][U], k1[2][U];
-    load(p_begin, s0, a0, k0);
+    T sv[NS][TG], av[NS][TG], mk[NS];
+#pragma unroll
+    for (int q = 0; q < NS - 1; ++q) load(p_begin + (int64_t)q * 16, sv[q], av[q], mk[q]);
     for (int64_t pf = p_begin; pf < p_end; pf += FL) {
 #pragma unroll
-      for (int q = 0; q < FL / (2 * G); ++q) {
-        const int64_t p0 = pf + (int64_t)q * 2 * G;
-        // the scheduling barriers keep each stage's loads ahead of the other
-        // stage's MFMAs (otherwise the mask products are hoisted next to the
-        // loads and wait for them)
-        load(p0 + G, s1, a1, k1);
+      for (int q = 0; q < NS; ++q) {
+        // refill the slot the previous stage's MFMAs consumed; the scheduling
+        // barriers keep each stage's loads ahead of the other stages' MFMAs
+        const int lq = (q + NS - 1) % NS;
+        load(pf + (int64_t)(q + NS - 1) * 16, sv[lq], av[lq], mk[lq]);
         __builtin_amdgcn_sched_barrier(0);
-        mfmas(s0, a0, k0);
-        __builtin_amdgcn_sched_barrier(0);
-        load(p0 + 2 * G, s0, a0, k0);
-        __builtin_amdgcn_sched_barrier(0);
-        mfmas(s1, a1, k1);
+        mfmas(sv[q], av[q], mk[q]);
         __builtin_amdgcn_sched_barrier(0);
       }
     }
   }
-  flush();
 
-  // fixed-order sum over the 4 waves, one tile at a time.  Output layout of
-  // 16x16x4 f64 (entry e = i*16 + j of a tile): D[i][j] in lane
-  // j + 16*(i%4), register i/4
-  const int ntot = ntb + nta;
-  for (int t = 0; t < ntot; ++t) {
+  // blocks q = 0..3 (lanes 4q apart within each row of 16) summed as
+  // (q0 + q1) + (q2 + q3); lane 16i + j then holds D[i][j]
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      double val = 0.0;
-#pragma unroll
-      for (int tt = 0; tt < ntb; ++tt)
-        if (t == tt) val = totb[tt][v];
-#pragma unroll
-      for (int tt = 0; tt < nta; ++tt)
-        if (t == ntb + tt) val = tota[tt][v];
-      wsum[wave][v][lane] = val;
+  for (int t = 0; t < NA + NB; ++t) {
+    double v = t < NA ? acca[t] : accb[t - NA];
+    v += __shfl_xor(v, 4, 64);
+    v += __shfl_xor(v, 8, 64);
+    if ((lane & 12) == 0) red[wave][t][4 * (lane >> 4) + cl] = v;
+  }
+  __syncthreads();
+
+  // the 16x16 output tiles: entry (row, col) of GB or GA from its 4x4 tile,
+  // the lower S^T S tiles as mirrors of the upper ones (the same products in
+  // the same order), zero past the last group; the four waves in order
+  const int nt = (ns + 15) >> 4;
+  const int ntb = n_tiles_b(nt), ntot = ntb + n_tiles_a(nt);
+  for (int e = threadIdx.x; e < ntot * 256; e += kThreads) {
+    const int t16 = e >> 8, i16 = (e & 255) >> 4, j16 = e & 15;
+    bool isb;
+    int I16, J16;
+    if (t16 < ntb) {
+      isb = true;
+      I16 = (t16 == 2) ? 1 : 0;
+      J16 = (t16 == 0) ? 0 : 1;
+    } else {
+      isb = false;
+      I16 = (nt == 1) ? 0 : (t16 - ntb) >> 1;
+      J16 = (nt == 1) ? 0 : (t16 - ntb) & 1;
     }
-    __syncthreads();
-    {
-      const int ij = threadIdx.x;  // 256 threads = 256 entries
-      const int i = ij >> 4, j = ij & 15;
-      const int ln = j + 16 * (i & 3);
-      const int v = i >> 2;
-      const double sm = wsum[0][v][ln] + wsum[1][v][ln] + wsum[2][v][ln] + wsum[3][v][ln];
-      g.partials[((size_t)blockIdx.x * ntot + t) * 256 + ij] = sm;
+    const int row = 16 * I16 + i16, col = 16 * J16 + j16;
+    const int GI = row >> 2, GJ = col >> 2;
+    double sm = 0.0;
+    if (GI < TG && GJ < TG) {
+      int t, sub;
+      if (!isb) {
+        t = GI * TG + GJ;
+        sub = 4 * (row & 3) + (col & 3);
+      } else if (GI <= GJ) {
+        t = NA + tile_b<TG>(GI, GJ);
+        sub = 4 * (row & 3) + (col & 3);
+      } else {
+        t = NA + tile_b<TG>(GJ, GI);
+        sub = 4 * (col & 3) + (row & 3);
+      }
+      sm = red[0][t][sub] + red[1][t][sub] + red[2][t][sub] + red[3][t][sub];
     }
-    __syncthreads();
+    g.partials[((size_t)blockIdx.x * ntot + t16) * 256 + (e & 255)] = sm;
   }
 }
 
@@ -1305,19 +1309,24 @@ int gram_tiles_total(int ns) {
   return nt == 1 ? 2 : 7;
 }
 
-gsf_status lob_launch_gram(const GramArgs& g, const RRArgs& r, int prec, hipStream_t s) {
-  const bool two = g.ns > 16;
-  if (prec == GSF_F32) {
-    if (two)
-      gram_kernel<float, 2><<<g.nparts, kThreads, 0, s>>>(g);
-    else
-      gram_kernel<float, 1><<<g.nparts, kThreads, 0, s>>>(g);
-  } else {
-    if (two)
-      gram_kernel<double, 2><<<g.nparts, kThreads, 0, s>>>(g);
-    else
-      gram_kernel<double, 1><<<g.nparts, kThreads, 0, s>>>(g);
+template <typename T>
+void launch_gram_kernel(const GramArgs& g, hipStream_t s) {
+  switch ((g.ns + 3) >> 2) {
+    case 1: gram_kernel<T, 1><<<g.nparts, kThreads, 0, s>>>(g); break;
+    case 2: gram_kernel<T, 2><<<g.nparts, kThreads, 0, s>>>(g); break;
+    case 3: gram_kernel<T, 3><<<g.nparts, kThreads, 0, s>>>(g); break;
+    case 4: gram_kernel<T, 4><<<g.nparts, kThreads, 0, s>>>(g); break;
+    case 5: gram_kernel<T, 5><<<g.nparts, kThreads, 0, s>>>(g); break;
+    default: gram_kernel<T, 6><<<g.nparts, kThreads, 0, s>>>(g); break;
   }
+}
+
+gsf_status lob_launch_gram(const GramArgs& g, const RRArgs& r, int prec, hipStream_t s) {
+  if (g.ns < 1 || g.ns > KMAX) return GSF_EINVAL;
+  if (prec == GSF_F32)
+    launch_gram_kernel<float>(g, s);
+  else
+    launch_gram_kernel<double>(g, s);
   dim3 grid(gram_tiles_total(g.ns) + 1, kGramChunks);
   gram_reduce_kernel<<<grid, kThreads, 0, s>>>(g, r);
   gram_rr_kernel<<<1, rr_threads(g.ns), 0, s>>>(g, r);
