@@ -850,7 +850,8 @@ def main():
     # CG and LOBPCG are independent filters of the same operator.  Default: the
     # joint driver, whose step k of both filters shares one stencil pass (the
     # CG vector as a fifth column of the LOBPCG block) and runs the CG scalars
-    # on a second stream while LOBPCG's one-workgroup Rayleigh-Ritz step runs.
+    # and vector updates as extra workgroups of LOBPCG's Gram-reduction and
+    # one-workgroup Rayleigh-Ritz launches.
     # --separate: two independent calls on two streams (LOBPCG, the longer
     # chain, enqueued first); --serial: one after the other.  (A GF operator's
     # apply uses the handle's scratch planes, so its filters stay on one

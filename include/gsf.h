@@ -347,11 +347,10 @@ gsf_status gsf_lobpcg_filter(const gsf_operator* op, const void* x0, void* x_out
  * summation order of the CG dot products.  While both run, step k of each
  * shares one stencil pass: the CG vector is applied as one more column of the
  * LOBPCG block (BF operators on the square window or 1D with m = 1 or 4; other
- * operators apply the two blocks one after the other).  The CG scalars and
- * updates run on a second stream of the device, which the library creates on
- * first use and keeps until the process ends (default priority; forked from
- * and joined back to `stream`, so the call is ordered on `stream` like the
- * others); a handle must not run two joint calls at once.  x0_cg, x_cg: n elements; x0_lob, x_lob: n elements.
+ * operators apply the two blocks one after the other).  Everything runs on
+ * `stream`: the CG scalars and vector updates run as extra workgroups of the
+ * LOBPCG Gram-reduction and Rayleigh-Ritz launches.  x0_cg, x_cg: n elements;
+ * x0_lob, x_lob: n elements.
  * Workspace: gsf_joint_workspace_bytes(op, m, ...).  cg_info, lob_info: NULL
  * or summaries as for the single filters.  GSF_EINVAL for NULL pointers,
  * kmax < 0 or m outside 1..8; GSF_ENOMEM for a short workspace; returns the

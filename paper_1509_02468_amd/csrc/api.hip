@@ -7,6 +7,7 @@
 #include <string>
 #include <cstdio>
 
+#include "cg_step.h"
 #include "gsf_internal.h"
 #include "lobpcg_launch.h"
 #include "solver_state.h"
@@ -748,6 +749,24 @@ struct CgRun {
     steps = k;
     return launch_cg_aupdate(op, w.z, w.r, w.p, w.q, w.partials, nparts, w.partials2, w.st, k, s);
   }
+  // step k's update (or direction) phase, to run as extra workgroups of
+  // another launch on s (the update reads the p^T q partials of the last apply)
+  CgStepArgs phase(int k) const {
+    CgStepArgs a{};
+    a.prec = op.desc.prec;
+    a.nblk = cg_step_blocks(op.n);
+    a.k = k;
+    a.ndots = nparts;
+    a.z = w.z;
+    a.r = w.r;
+    a.p = w.p;
+    a.q = w.q;
+    a.n = op.n;
+    a.dots = w.partials;
+    a.upd = w.partials2;
+    a.st = w.st;
+    return a;
+  }
   gsf_status finish(void* x_out, double tol, gsf_cg_info* info) {
     if (steps > 0) GSF_TRY(launch_cg_close(op, w.partials2, w.st, s));
     GSF_TRY(launch_scale(op, w.z, x_out, 1, s));
@@ -818,6 +837,9 @@ struct LobRun {
   int nb = 0;
   StartDegrees deg{};
   bool fold = false, pending = false;
+  // the joint driver's CG phases carried by the next post() (nullable)
+  const CgStepArgs* cg_update = nullptr;
+  const CgStepArgs* cg_direction = nullptr;
   LobRun(const Operator& o, int m_, bool con, const gsf_precond* T_, char* ws, hipStream_t st)
       : op(o), s(st), m(m_), constraint(con), T(T_) {
     carve_lob(op, m, ws, &w);
@@ -915,7 +937,7 @@ struct LobRun {
     rr.fin_partials = pending ? w.vpart : nullptr;
     rr.fin_nparts = nb;
     rr.fin_stride = 2 * m;
-    GSF_TRY(lob_launch_gram(g, rr, op.desc.prec, s));
+    GSF_TRY(lob_launch_gram(g, rr, op.desc.prec, s, cg_update, cg_direction));
     if ((k + 1) % kAxRefresh != 0) {
       GSF_TRY(lob_launch_mkernel(fold ? 4 : 1, a, nb, ns, 0, deg, s));
     } else {
@@ -1075,38 +1097,14 @@ gsf_status gsf_lobpcg_filter(const gsf_operator* h, const void* x0, void* x_out,
   return st;
 }
 
-// The device's second stream (one per device, created on first use and kept
-// until the process ends) and the handle's fork / join events.
-static gsf_status ensure_aux(gsf_operator* h) {
-  if (h->ev_fork != nullptr) return GSF_OK;
-  static std::mutex mu;
-  static hipStream_t dev_aux[64] = {};
-  int dev = 0;
-  GSF_TRY(hip_ok(hipGetDevice(&dev)));
-  if (dev < 0 || dev >= 64) return GSF_EDEVICE;
-  {
-    std::lock_guard<std::mutex> lock(mu);
-    if (dev_aux[dev] == nullptr) GSF_TRY(hip_ok(hipStreamCreateWithFlags(&dev_aux[dev], hipStreamNonBlocking)));
-  }
-  hipEvent_t e[3] = {nullptr, nullptr, nullptr};
-  for (int i = 0; i < 3; ++i) {
-    if (hipEventCreateWithFlags(&e[i], hipEventDisableTiming) != hipSuccess) {
-      for (int j = 0; j < i; ++j) (void)hipEventDestroy(e[j]);
-      return GSF_EDEVICE;
-    }
-  }
-  h->aux = dev_aux[dev];
-  h->ev_fork = e[0];
-  h->ev_cg = e[1];
-  h->ev_apply = e[2];
-  return GSF_OK;
-}
-
 // Joint CG + LOBPCG filters of one operator: step k of both runs shares one
 // stencil pass, [A W | A p] from [W | p] (the CG vector as one more column of
-// the LOBPCG block), where the operator offers a joint apply; the CG scalars
-// and updates run on a second stream while the LOBPCG Rayleigh-Ritz step and
-// update run on the caller's.
+// the LOBPCG block), where the operator offers a joint apply.  Everything runs
+// on the caller's stream: the CG update of step k and the direction of step
+// k + 1 run as extra workgroups of the LOBPCG Gram-reduction and
+// Rayleigh-Ritz launches, which use a handful of workgroups themselves.
+// (A second stream for the CG phases cost two event waits per step, each
+// delaying the next launch by about 6 us.)
 gsf_status gsf_joint_workspace_bytes(const gsf_operator* h, int m, size_t* bytes) {
   if (h == nullptr || bytes == nullptr || m < 1 || m > kMaxBlock) return GSF_EINVAL;
   CgWs cw;
@@ -1127,55 +1125,46 @@ gsf_status gsf_joint_filter(gsf_operator* h, const void* x0_cg, void* x_cg, int 
   if (ws == nullptr || ws_bytes < need) return GSF_ENOMEM;
   const Operator& op = h->op;
   hipStream_t s = (hipStream_t)stream;
-  // A GF apply uses the handle's scratch planes, so a GF operator keeps both
-  // chains on the caller's stream; BF applies share nothing but the operator.
-  const bool two = op.desc.kind == GSF_BF;
-  if (two) GSF_TRY(ensure_aux(h));
-  hipStream_t cs = two ? h->aux : s;
   CgWs cw;
   char* base = (char*)ws;
-  CgRun cg(op, base, cs);
+  CgRun cg(op, base, s);
   LobRun lob(op, m, constraint != 0, nullptr, base + align_up(carve_cg(op, nullptr, &cw), kAlign), s);
-  if (two) {  // the CG chain forks from the caller's stream
-    GSF_TRY(hip_ok(hipEventRecord(h->ev_fork, s)));
-    GSF_TRY(hip_ok(hipStreamWaitEvent(cs, h->ev_fork, 0)));
-  }
   GSF_TRY(cg.begin(x0_cg, 0.0));
   GSF_TRY(lob.begin(x0_lob, x_lob, nullptr, 0.0));
   const int kj = kmax_cg < kmax_lob ? kmax_cg : kmax_lob;
+  bool p_ready = false;  // the next CG direction was formed in the last Rayleigh-Ritz launch
   for (int k = 0; k < kmax_cg || k < kmax_lob; ++k) {
     const bool both = k < kj;
-    if (k < kmax_cg) GSF_TRY(cg.pre(k + 1));
+    if (k < kmax_cg && !p_ready) GSF_TRY(cg.pre(k + 1));
+    p_ready = false;
     if (k < kmax_lob) GSF_TRY(lob.pre());
     bool joint = false;
     if (both) {
-      // the joint apply on the caller's stream once p is ready
-      if (two) {
-        GSF_TRY(hip_ok(hipEventRecord(h->ev_cg, cs)));
-        GSF_TRY(hip_ok(hipStreamWaitEvent(s, h->ev_cg, 0)));
-      }
       joint = launch_bf_apply_joint(op, GSF_FORM_LSYM, m, lob.w.W, m, lob.w.AW, m, cg.w.p, 1, cg.w.q, 1,
                                     cg.w.partials, &cg.nparts, s);
-      if (joint) {
-        GSF_TRY(hip_ok(hipGetLastError()));
-        if (two) {
-          GSF_TRY(hip_ok(hipEventRecord(h->ev_apply, s)));
-          GSF_TRY(hip_ok(hipStreamWaitEvent(cs, h->ev_apply, 0)));
-        }
-      }
+      if (joint) GSF_TRY(hip_ok(hipGetLastError()));
     }
     if (!joint) {
       if (k < kmax_cg) GSF_TRY(cg.apply());
       if (k < kmax_lob) GSF_TRY(lob.apply());
     }
-    if (k < kmax_cg) GSF_TRY(cg.post(k + 1));
-    if (k < kmax_lob) GSF_TRY(lob.post(k));
+    if (both) {
+      // CG's update of step k + 1 in the Gram-reduction launch, the direction
+      // of step k + 2 (when there is one) in the Rayleigh-Ritz launch
+      const CgStepArgs upd = cg.phase(k + 1), dir = cg.phase(k + 2);
+      cg.steps = k + 1;
+      lob.cg_update = &upd;
+      lob.cg_direction = k + 1 < kmax_cg ? &dir : nullptr;
+      const gsf_status st = lob.post(k);
+      lob.cg_update = lob.cg_direction = nullptr;
+      GSF_TRY(st);
+      p_ready = k + 1 < kmax_cg;
+    } else {
+      if (k < kmax_cg) GSF_TRY(cg.post(k + 1));
+      if (k < kmax_lob) GSF_TRY(lob.post(k));
+    }
   }
   gsf_status st_cg = cg.finish(x_cg, 0.0, cg_info);
-  if (two) {  // join: the caller's stream waits for the CG chain
-    GSF_TRY(hip_ok(hipEventRecord(h->ev_cg, cs)));
-    GSF_TRY(hip_ok(hipStreamWaitEvent(s, h->ev_cg, 0)));
-  }
   gsf_status st_lob = lob.finish(0.0, lob_info);
   if (st_cg != GSF_OK && st_cg != GSF_EBREAKDOWN) return st_cg;
   if (st_lob != GSF_OK) return st_lob;

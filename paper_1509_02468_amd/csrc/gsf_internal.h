@@ -133,16 +133,6 @@ int apply_num_blocks(const Operator& op, int m);
 
 struct gsf_operator {
   gsf::Operator op;
-  // joint CG + LOBPCG driver: the device's second stream (shared by all
-  // handles, kept until the process ends) and this handle's events that fork
-  // and join it, created on first use
-  hipStream_t aux = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_cg = nullptr, ev_apply = nullptr;
-  ~gsf_operator() {
-    if (ev_fork) (void)hipEventDestroy(ev_fork);
-    if (ev_cg) (void)hipEventDestroy(ev_cg);
-    if (ev_apply) (void)hipEventDestroy(ev_apply);
-  }
 };
 
 // Preconditioner handle: the learned network (grid, precision and borrowed

@@ -20,6 +20,7 @@
 //   lob_out_dots / lob_output: y = X X^T z0 (+ Y Y^T z0), x_out = y / sqrt(d)
 #include <cmath>
 
+#include "cg_step.h"
 #include "gsf_internal.h"
 #include "solver_state.h"
 #include "lobpcg_launch.h"
@@ -137,6 +138,25 @@ __global__ void __launch_bounds__(kThreads) lob_project_kernel(T* __restrict__ B
 // the order (0,0), (0,1), (1,1); S^T AS: all tiles (0,0), (0,1), (1,0), (1,1).
 __device__ __forceinline__ int n_tiles_b(int nt) { return nt == 1 ? 1 : 3; }
 __device__ __forceinline__ int n_tiles_a(int nt) { return nt == 1 ? 1 : 4; }
+
+// Gram matrix (GB = S^T S or GA = S^T AS), row and column of entry e of the
+// tile sequence above (tile e >> 8, entry (e & 255) = 16 i + j)
+__device__ __forceinline__ void tile_entry(int e, int nt, bool& isb, int& row, int& col) {
+  const int t = e >> 8, i = (e & 255) >> 4, j = e & 15;
+  const int ntb = n_tiles_b(nt);
+  int I, J;
+  if (t < ntb) {
+    isb = true;
+    I = (t == 2) ? 1 : 0;
+    J = (t == 0) ? 0 : 1;
+  } else {
+    isb = false;
+    I = (nt == 1) ? 0 : (t - ntb) >> 1;
+    J = (nt == 1) ? 0 : (t - ntb) & 1;
+  }
+  row = 16 * I + i;
+  col = 16 * J + j;
+}
 
 // v_mfma_f64_4x4x4f64 runs four independent 4x4x4 products (blocks q = 0..3).
 // Lane l holds A[i = l%4][k = l/16] and B[k = l/16][j = l%4] of block
@@ -269,40 +289,29 @@ __global__ void __launch_bounds__(kThreads) gram_kernel(GramArgs g) {
 
   // the 16x16 output tiles: entry (row, col) of GB or GA from its 4x4 tile,
   // the lower S^T S tiles as mirrors of the upper ones (the same products in
-  // the same order), zero past the last group; the four waves in order
+  // the same order); the four waves in order.  Entries past ns are neither
+  // written nor read by the reductions.
   const int nt = (ns + 15) >> 4;
-  const int ntb = n_tiles_b(nt), ntot = ntb + n_tiles_a(nt);
+  const int ntot = n_tiles_b(nt) + n_tiles_a(nt);
   for (int e = threadIdx.x; e < ntot * 256; e += kThreads) {
-    const int t16 = e >> 8, i16 = (e & 255) >> 4, j16 = e & 15;
     bool isb;
-    int I16, J16;
-    if (t16 < ntb) {
-      isb = true;
-      I16 = (t16 == 2) ? 1 : 0;
-      J16 = (t16 == 0) ? 0 : 1;
-    } else {
-      isb = false;
-      I16 = (nt == 1) ? 0 : (t16 - ntb) >> 1;
-      J16 = (nt == 1) ? 0 : (t16 - ntb) & 1;
-    }
-    const int row = 16 * I16 + i16, col = 16 * J16 + j16;
+    int row, col;
+    tile_entry(e, nt, isb, row, col);
+    if (row >= ns || col >= ns) continue;
     const int GI = row >> 2, GJ = col >> 2;
-    double sm = 0.0;
-    if (GI < TG && GJ < TG) {
-      int t, sub;
-      if (!isb) {
-        t = GI * TG + GJ;
-        sub = 4 * (row & 3) + (col & 3);
-      } else if (GI <= GJ) {
-        t = NA + tile_b<TG>(GI, GJ);
-        sub = 4 * (row & 3) + (col & 3);
-      } else {
-        t = NA + tile_b<TG>(GJ, GI);
-        sub = 4 * (col & 3) + (row & 3);
-      }
-      sm = red[0][t][sub] + red[1][t][sub] + red[2][t][sub] + red[3][t][sub];
+    int t, sub;
+    if (!isb) {
+      t = GI * TG + GJ;
+      sub = 4 * (row & 3) + (col & 3);
+    } else if (GI <= GJ) {
+      t = NA + tile_b<TG>(GI, GJ);
+      sub = 4 * (row & 3) + (col & 3);
+    } else {
+      t = NA + tile_b<TG>(GJ, GI);
+      sub = 4 * (col & 3) + (row & 3);
     }
-    g.partials[((size_t)blockIdx.x * ntot + t16) * 256 + (e & 255)] = sm;
+    const double sm = red[0][t][sub] + red[1][t][sub] + red[2][t][sub] + red[3][t][sub];
+    g.partials[(size_t)blockIdx.x * ntot * 256 + e] = sm;
   }
 }
 
@@ -884,12 +893,20 @@ __device__ void fin_reduce(const RRArgs& r, int m, double* fin) {
 }
 
 // First stage of the Gram reduction: workgroup (tile, chunk) sums the partials
-// of its chunk of Gram workgroups for the 256 entries of one tile; the extra
-// workgroup column (blockIdx.x = tiles) reduces the previous update's residual
-// partials for the Rayleigh-Ritz step, off its critical path.
-__global__ void __launch_bounds__(kThreads) gram_reduce_kernel(GramArgs g, RRArgs r) {
+// of its chunk of Gram workgroups for the 256 entries of one tile; the
+// workgroup column after the tiles reduces the previous update's residual
+// partials for the Rayleigh-Ritz step, off its critical path; further columns
+// (cg.nblk > 0) run a CG update phase of the joint driver (the launch's own
+// work is latency-bound and leaves the GPU almost idle).
+__global__ void __launch_bounds__(kThreads) gram_reduce_kernel(GramArgs g, RRArgs r, CgStepArgs cg) {
+  const int ntiles = n_tiles_b((g.ns + 15) >> 4) + n_tiles_a((g.ns + 15) >> 4);
+  if ((int)blockIdx.x > ntiles) {
+    const int bid = ((int)blockIdx.x - ntiles - 1) * (int)gridDim.y + (int)blockIdx.y;
+    if (bid < cg.nblk) cg_aupdate_step(cg, bid);
+    return;
+  }
   if (g.active != nullptr && *g.active == 0) return;
-  if ((int)blockIdx.x == (int)gridDim.x - 1) {
+  if ((int)blockIdx.x == ntiles) {
     if (blockIdx.y == 0 && r.fin_partials != nullptr) fin_reduce(r, g.m, g.level2 + kGramFinSlot);
     return;
   }
@@ -900,6 +917,12 @@ __global__ void __launch_bounds__(kThreads) gram_reduce_kernel(GramArgs g, RRArg
   const int b0 = chunk * per, b1 = (b0 + per < g.nparts) ? b0 + per : g.nparts;
   const int e = tile * 256 + threadIdx.x;
   const size_t st = (size_t)ntot * 256;
+  {
+    bool isb;
+    int row, col;
+    tile_entry(e, nt, isb, row, col);
+    if (row >= g.ns || col >= g.ns) return;  // not written by the Gram kernel, not read
+  }
   // up to kGramPerChunk partials, loaded together, summed in order
   double v[kGramPerChunk];
 #pragma unroll
@@ -910,9 +933,14 @@ __global__ void __launch_bounds__(kThreads) gram_reduce_kernel(GramArgs g, RRArg
   g.level2[(size_t)chunk * st + e] = s;
 }
 
-// One workgroup: sums the chunks and assembles GA and GB (ns x ns); its first
-// wave then runs the Rayleigh-Ritz step.
-__global__ void __launch_bounds__(kThreads) gram_rr_kernel(GramArgs g, RRArgs r) {
+// Workgroup 0: sums the chunks and assembles GA and GB (ns x ns); its first
+// wave then runs the Rayleigh-Ritz step.  Workgroups 1.. (cg.nblk of them)
+// run a CG direction phase of the joint driver.
+__global__ void __launch_bounds__(kThreads) gram_rr_kernel(GramArgs g, RRArgs r, CgStepArgs cg) {
+  if (blockIdx.x > 0) {
+    cg_pbeta_step(cg, (int)blockIdx.x - 1);
+    return;
+  }
   __shared__ RRShared sh;
   __shared__ int nkept;
   __shared__ int keptf[KMAX];
@@ -920,7 +948,7 @@ __global__ void __launch_bounds__(kThreads) gram_rr_kernel(GramArgs g, RRArgs r)
   __shared__ int lockm;
   if (r.st != nullptr && !r.st->active) return;
   const int nt = (g.ns + 15) >> 4;
-  const int ntb = n_tiles_b(nt), ntot = ntb + n_tiles_a(nt);
+  const int ntot = n_tiles_b(nt) + n_tiles_a(nt);
   // Everything this kernel reads from global memory was written by other
   // workgroups of earlier kernels (other XCDs), so each load is a long trip:
   // the first batch of Gram chunk values and the residual partials are all
@@ -957,25 +985,13 @@ __global__ void __launch_bounds__(kThreads) gram_rr_kernel(GramArgs g, RRArgs r)
     double s = 0.0;
 #pragma unroll
     for (int c = 0; c < kGramChunks; ++c) s += v[c];
-    const int t = e >> 8, i = (e & 255) >> 4, j = e & 15;
-    int I, J;
     bool isb;
-    if (t < ntb) {
-      isb = true;
-      I = (t == 2) ? 1 : 0;
-      J = (t == 0) ? 0 : 1;
-    } else {
-      isb = false;
-      const int ta = t - ntb;
-      I = ta >> 1;
-      J = ta & 1;
-      if (nt == 1) I = J = 0;
-    }
-    const int row = 16 * I + i, colj = 16 * J + j;
+    int row, colj;
+    tile_entry(e, nt, isb, row, colj);
     if (row < g.ns && colj < g.ns) {
       if (isb) {
         sh.B[row * LD + colj] = s;
-        if (I != J) sh.B[colj * LD + row] = s;  // the lower off-diagonal tile is the mirror
+        if ((row >> 4) != (colj >> 4)) sh.B[colj * LD + row] = s;  // the lower off-diagonal tile is the mirror
       } else {
         sh.A[row * LD + colj] = s;
       }
@@ -1321,15 +1337,19 @@ void launch_gram_kernel(const GramArgs& g, hipStream_t s) {
   }
 }
 
-gsf_status lob_launch_gram(const GramArgs& g, const RRArgs& r, int prec, hipStream_t s) {
+gsf_status lob_launch_gram(const GramArgs& g, const RRArgs& r, int prec, hipStream_t s,
+                           const CgStepArgs* cg_update, const CgStepArgs* cg_direction) {
   if (g.ns < 1 || g.ns > KMAX) return GSF_EINVAL;
   if (prec == GSF_F32)
     launch_gram_kernel<float>(g, s);
   else
     launch_gram_kernel<double>(g, s);
-  dim3 grid(gram_tiles_total(g.ns) + 1, kGramChunks);
-  gram_reduce_kernel<<<grid, kThreads, 0, s>>>(g, r);
-  gram_rr_kernel<<<1, rr_threads(g.ns), 0, s>>>(g, r);
+  const CgStepArgs none{};
+  const CgStepArgs& ca = cg_update != nullptr ? *cg_update : none;
+  const CgStepArgs& cp = cg_direction != nullptr ? *cg_direction : none;
+  dim3 grid(gram_tiles_total(g.ns) + 1 + (ca.nblk + kGramChunks - 1) / kGramChunks, kGramChunks);
+  gram_reduce_kernel<<<grid, kThreads, 0, s>>>(g, r, ca);
+  gram_rr_kernel<<<1 + cp.nblk, rr_threads(g.ns), 0, s>>>(g, r, cp);
   return launch_status();
 }
 

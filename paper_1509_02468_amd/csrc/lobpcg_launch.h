@@ -70,7 +70,13 @@ gsf_status lob_launch_ynorm(const LobArgs& a, int nb, hipStream_t s);
 gsf_status lob_launch_mkernel(int which, const LobArgs& a, int nb, int ns, int first, StartDegrees deg,
                               hipStream_t s);
 gsf_status lob_launch_project(const LobArgs& a, void* B, int nb, hipStream_t s);
-gsf_status lob_launch_gram(const GramArgs& g, const RRArgs& r, int prec, hipStream_t s);
+// Gram partials, their reduction and the Rayleigh-Ritz step.  cg_update /
+// cg_direction (nullable): a CG update phase run as extra workgroups of the
+// reduction launch, and a CG direction phase run as extra workgroups of the
+// Rayleigh-Ritz launch (the joint CG + LOBPCG driver).
+struct CgStepArgs;
+gsf_status lob_launch_gram(const GramArgs& g, const RRArgs& r, int prec, hipStream_t s,
+                           const CgStepArgs* cg_update = nullptr, const CgStepArgs* cg_direction = nullptr);
 gsf_status lob_launch_rr_only(const double* G, int ns, int m, const RRArgs& r, hipStream_t s);
 gsf_status launch_lob_state_init(LobpcgState* dst, const LobpcgState& v, hipStream_t s);
 gsf_status launch_cg_state_init(CgState* dst, const CgState& v, hipStream_t s);

@@ -7,6 +7,7 @@
 // which writes back the whole L2 of its XCD.)
 #include <cmath>
 
+#include "cg_step.h"
 #include "gsf_internal.h"
 #include "solver_state.h"
 
@@ -167,109 +168,21 @@ __global__ void __launch_bounds__(kThreads) cg_beta_kernel(const double* __restr
 }
 
 // ---- fused CG step: three launches per step instead of five ----------------
-// Every workgroup sums the previous kernel's partials itself, in the same
-// fixed order as the one-workgroup kernels, so all take bitwise the same
-// scalars; workgroup 0 records them.  Scalars that other workgroups read in
-// the same launch are never overwritten in it: r^T r is kept by step parity
-// (step k's value in rhob[k & 1]) and the step index comes from the host.
-
-// all threads get the fixed-order sum of NV partials per workgroup
-template <int NV>
-__device__ __forceinline__ void reduce_all(const double* partials, int nparts, double (&t)[NV], double* red,
-                                           double* bc) {
-  reduce_partials<NV>(partials, nparts, NV, t, red);
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int k = 0; k < NV; ++k) bc[k] = t[k];
-  }
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < NV; ++k) t[k] = bc[k];
-}
-
-// step k >= 1: k = 1: p = r.  k > 1: rho_k and r_k^T r_{k-1} from the last
-// update's partials, the tests before step k, beta = (rho_k - r_k^T r_{k-1}) /
-// rho_{k-1}, p = r + beta p.
+// (the bodies are in cg_step.h, shared with the joint driver's launches)
 template <typename T>
 __global__ void __launch_bounds__(kThreads) cg_pbeta_kernel(const T* __restrict__ r, T* __restrict__ p, int64_t n,
                                                             const double* __restrict__ partials, int nparts,
                                                             CgState* st, int k) {
-  __shared__ double red[32];
-  __shared__ double bc[2];
-  if (!st->active) return;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  if (k == 1) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = r[i];
-    return;
-  }
-  double t[2];
-  reduce_all<2>(partials, nparts, t, red, bc);
-  const double rho = t[0];
-  const bool stop_bd = !(__builtin_isfinite(rho) && rho > st->floor);
-  const bool stop_tol = !stop_bd && st->tol2 > 0.0 && rho <= st->tol2;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    st->rho = rho;
-    st->rhob[k & 1] = rho;
-    if (stop_bd) {
-      st->status = GSF_EBREAKDOWN;
-      st->active = 0;
-    } else if (stop_tol) {
-      st->active = 0;
-    }
-  }
-  if (stop_bd || stop_tol) return;
-  const double beta = (rho - t[1]) / st->rhob[(k - 1) & 1];
-  if (blockIdx.x == 0 && threadIdx.x == 0) st->beta = beta;
-  const T b = (T)beta;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = r[i] + b * p[i];
+  cg_pbeta_body<T>(r, p, n, partials, nparts, st, k, blockIdx.x, gridDim.x);
 }
 
-// step k: p^T q from the apply's partials, the breakdown test, alpha =
-// rho_k / p^T q; z += alpha p, r -= alpha q; partials of r_new^T r_new and
-// r_new^T r_old into upd (not the buffer the dot partials are read from).
 template <typename T>
 __global__ void __launch_bounds__(kThreads) cg_aupdate_kernel(T* __restrict__ z, T* __restrict__ r,
                                                               const T* __restrict__ p, const T* __restrict__ q,
                                                               int64_t n, const double* __restrict__ dots,
                                                               int ndots, double* __restrict__ upd, CgState* st,
                                                               int k) {
-  __shared__ double red[32];
-  __shared__ double bc[2];
-  if (!st->active) return;
-  double t[1];
-  reduce_all<1>(dots, ndots, t, red, bc);
-  const double pq = t[0];
-  if (!(__builtin_isfinite(pq) && pq > 0.0)) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      st->pq = pq;
-      st->status = GSF_EBREAKDOWN;
-      st->active = 0;
-    }
-    return;
-  }
-  const double alpha_d = st->rhob[k & 1] / pq;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    st->pq = pq;
-    st->alpha = alpha_d;
-    st->iters = k;
-    st->k = k + 1;
-  }
-  const T alpha = (T)alpha_d;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  double v[2] = {0.0, 0.0};
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-    z[i] += alpha * p[i];
-    const T ro = r[i];
-    const T rn = ro - alpha * q[i];
-    r[i] = rn;
-    v[0] += (double)rn * (double)rn;
-    v[1] += (double)rn * (double)ro;
-  }
-  block_sum<2>(v, red);
-  if (threadIdx.x == 0) {
-    upd[2 * blockIdx.x] = v[0];
-    upd[2 * blockIdx.x + 1] = v[1];
-  }
+  cg_aupdate_body<T>(z, r, p, q, n, dots, ndots, upd, st, k, blockIdx.x, gridDim.x);
 }
 
 // one workgroup after the last step: the final residual and its tests
