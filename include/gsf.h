@@ -490,10 +490,13 @@ gsf_status gsf_reguided_filter(const gsf_operator_desc* desc, int method, const 
  * gsf_tune_apply: times the BF apply (form L_sym, block width m in
  *   {1, 2, 3, 4, 8}) with 1, 2 and 4 grid rows per thread (tile heights 4, 8
  *   and 16 rows; in 2D the two rows of a thread are computed together and
- *   share every neighbour row), `reps` launches each, on caller buffers x, y (n*m
- *   elements); records the fastest choice for every later apply with the same
- *   precision, dimension, radius, width and size class (process-wide), and
- *   returns it in *best_rpt and the three timings (microseconds per launch)
+ *   share every neighbour row), in three interleaved rounds of `reps`
+ *   launches per candidate, on caller buffers x, y (n*m elements); each
+ *   candidate's time is its best round.  The current choice of the class
+ *   (tuned earlier, else the default) is kept unless another candidate is
+ *   faster by more than 3%; the result holds for every later apply with the
+ *   same precision, dimension, radius, width and size class (process-wide)
+ *   and is returned in *best_rpt, the three timings (microseconds per launch)
  *   in times_us (NULL allowed).  GF operators: no-op, *best_rpt = 0.
  *   Synchronizes the stream. */
 gsf_status gsf_tune_apply(const gsf_operator* op, int m, const void* x, void* y, int reps,
@@ -542,8 +545,13 @@ void gsf_tune_table_clear(void);
  *    pointers are then baked in: buffers must stay at the same addresses
  *    while the batch exists; their contents may change between runs).
  *    Without GSF_BATCH_GRAPHS each run issues the items' kernels from the
- *    library onto the branch streams (measured faster on ROCm 7.2, whose
- *    graph launch costs more host time per kernel node than a launch).
+ *    library onto the branch streams (on the 320-item batch: 352 ms replayed,
+ *    359 ms issued, the issue rate of the host thread varying by machine).
+ *    The first plan created on a device also creates three helper streams of
+ *    the library (default priority, kept until the process ends), which run
+ *    one empty kernel each before any branch stream runs (the branch streams
+ *    then share the device's hardware queues evenly; measured 352-356 ms
+ *    against 455-474 ms without); the first carries the tile tuning.
  *  gsf_batch_run: runs the batch ordered after prior work on `stream`;
  *    later work on `stream` waits for every branch (asynchronous).
  *  gsf_batch_get_info: per item (host array of count), after synchronizing
