@@ -936,7 +936,12 @@ __global__ void __launch_bounds__(kThreads) gram_reduce_kernel(GramArgs g, RRArg
 // Workgroup 0: sums the chunks and assembles GA and GB (ns x ns); its first
 // wave then runs the Rayleigh-Ritz step.  Workgroups 1.. (cg.nblk of them)
 // run a CG direction phase of the joint driver.
-__global__ void __launch_bounds__(kThreads) gram_rr_kernel(GramArgs g, RRArgs r, CgStepArgs cg) {
+//
+// direct != 0 (at most kGramChunks Gram workgroups and no CG phase): no
+// reduction launch ran; the partials take the place of the chunk sums (the
+// reduction would have copied them one to one, so the sums are bitwise the
+// same) and this workgroup sums the previous update's residual partials.
+__global__ void __launch_bounds__(kThreads) gram_rr_kernel(GramArgs g, RRArgs r, CgStepArgs cg, int direct) {
   if (blockIdx.x > 0) {
     cg_pbeta_step(cg, (int)blockIdx.x - 1);
     return;
@@ -953,18 +958,23 @@ __global__ void __launch_bounds__(kThreads) gram_rr_kernel(GramArgs g, RRArgs r,
   // workgroups of earlier kernels (other XCDs), so each load is a long trip:
   // the first batch of Gram chunk values and the residual partials are all
   // issued before any of them is used.
+  const double* chunks = direct ? g.partials : g.level2;
+  const int nchunks = direct ? g.nparts : kGramChunks;
   double v0[kGramChunks];
 #pragma unroll
-  for (int c = 0; c < kGramChunks; ++c) v0[c] = g.level2[(size_t)c * (ntot * 256) + threadIdx.x];
+  for (int c = 0; c < kGramChunks; ++c) v0[c] = c < nchunks ? chunks[(size_t)c * (ntot * 256) + threadIdx.x] : 0.0;
   if (r.fin_partials != nullptr) {
     // the previous update's residual norms, iteration count and convergence
     // test (what lob_final_kernel does after an update without the
     // constraint, in the same summation order); the sums come reduced from
-    // gram_reduce_kernel's extra workgroup
+    // gram_reduce_kernel's extra workgroup, or from this workgroup (direct)
+    __shared__ double fin_here[8];
+    if (direct) fin_reduce(r, g.m, fin_here);
+    const double* fin = direct ? fin_here : g.level2 + kGramFinSlot;
     double t[8];
     if (threadIdx.x == 0)
 #pragma unroll
-      for (int k = 0; k < 8; ++k) t[k] = g.level2[kGramFinSlot + k];
+      for (int k = 0; k < 8; ++k) t[k] = fin[k];
     if (threadIdx.x == 0) {
       LobpcgState* st = r.st;
       double mx = 0.0;
@@ -1001,7 +1011,7 @@ __global__ void __launch_bounds__(kThreads) gram_rr_kernel(GramArgs g, RRArgs r,
   for (int e = threadIdx.x + blockDim.x; e < ntot * 256; e += blockDim.x) {
     double v[kGramChunks];
 #pragma unroll
-    for (int c = 0; c < kGramChunks; ++c) v[c] = g.level2[(size_t)c * (ntot * 256) + e];
+    for (int c = 0; c < kGramChunks; ++c) v[c] = c < nchunks ? chunks[(size_t)c * (ntot * 256) + e] : 0.0;
     place(e, v);
   }
   // soft locking (tol > 0): a column whose residual is already at the
@@ -1347,9 +1357,14 @@ gsf_status lob_launch_gram(const GramArgs& g, const RRArgs& r, int prec, hipStre
   const CgStepArgs none{};
   const CgStepArgs& ca = cg_update != nullptr ? *cg_update : none;
   const CgStepArgs& cp = cg_direction != nullptr ? *cg_direction : none;
-  dim3 grid(gram_tiles_total(g.ns) + 1 + (ca.nblk + kGramChunks - 1) / kGramChunks, kGramChunks);
-  gram_reduce_kernel<<<grid, kThreads, 0, s>>>(g, r, ca);
-  gram_rr_kernel<<<1 + cp.nblk, rr_threads(g.ns), 0, s>>>(g, r, cp);
+  // with at most kGramChunks Gram workgroups the reduction launch would only
+  // copy the partials: the Rayleigh-Ritz workgroup reads them itself
+  const int direct = (g.nparts <= kGramChunks && ca.nblk == 0) ? 1 : 0;
+  if (!direct) {
+    dim3 grid(gram_tiles_total(g.ns) + 1 + (ca.nblk + kGramChunks - 1) / kGramChunks, kGramChunks);
+    gram_reduce_kernel<<<grid, kThreads, 0, s>>>(g, r, ca);
+  }
+  gram_rr_kernel<<<1 + cp.nblk, rr_threads(g.ns), 0, s>>>(g, r, cp, direct);
   return launch_status();
 }
 
