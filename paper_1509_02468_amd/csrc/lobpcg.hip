@@ -10,11 +10,14 @@
 //                  (an FP32 value widened to FP64 loses nothing and the
 //                  product of two is exact in FP64, so FP32 data get FP64 sums
 //                  too)
-//   gram_reduce /  fixed-order two-level reduction of the tiles, then the
-//   gram_rr        Rayleigh-Ritz step on one workgroup in FP64: unit-diagonal scaling,
-//                  column-dropping Cholesky, reduction to L^-1 A L^-T, the m
-//                  smallest eigenpairs (Householder tridiagonalisation,
-//                  bisection, inverse iteration), m smallest Ritz pairs
+//   gram_reduce /  fixed-order two-level reduction of the tiles (one level,
+//   gram_rr        inside gram_rr, with at most 16 Gram workgroups), then the
+//                  Rayleigh-Ritz step on one workgroup in FP64: unit-diagonal
+//                  scaling, column-dropping Cholesky, reduction to
+//                  L^-1 A L^-T, the m smallest eigenpairs (Householder
+//                  tridiagonalisation, bisection, inverse iteration), m
+//                  smallest Ritz pairs; extra workgroups of both launches run
+//                  the joint driver's CG phases (cg_step.h)
 //   lob_update     X = S C, AX = (AS) C, P = [W,P] C, AP likewise, the next
 //                  residual W = AX - X Theta and its norms (and Y^T W)
 //   lob_out_dots / lob_output: y = X X^T z0 (+ Y Y^T z0), x_out = y / sqrt(d)
