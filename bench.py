@@ -137,9 +137,9 @@ def _oracle_loop(args):
 
 
 def cpu_baseline_all_cores(w, crop, budget_s):
-    """The same loop in one process per available host core (at most 16, the
-    GPU machine's share), started together; the aggregate rate is the sum of the
-    per-process rates."""
+    """The same loop in one process per available host core (at most 16),
+    started together; the aggregate rate is the sum of the per-process
+    rates."""
     import multiprocessing as mp
     try:
         cores = len(os.sched_getaffinity(0))
@@ -820,7 +820,7 @@ def main():
         print(json.dumps({"precision_study": precision_study(a.oracle_side)}))
         return
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is described in DESIGN.md"}))
+        print(json.dumps({"error": f"--gpus {a.gpus}: the filters run on one GPU; there is no multi-GPU path (use --gpus 1)"}))
         sys.exit(2)
     import torch
     import paper_1509_02468_amd as gsf
