@@ -337,8 +337,12 @@ __global__ void __launch_bounds__(kThreads) rg_update_kernel(T* __restrict__ x, 
 
 }  // namespace
 
+// Workgroups of the point-wise vector kernels: one point per thread up to
+// 1024 workgroups (grid-stride beyond).  Small problems get many short
+// workgroups rather than a few long ones: at n = 4096 the LOBPCG update took
+// 10.9 us on 4 workgroups of 4 points per thread.
 int vec_blocks(int64_t n) {
-  int64_t b = (n + kThreads * 4 - 1) / (kThreads * 4);
+  int64_t b = (n + kThreads - 1) / kThreads;
   if (b < 1) b = 1;
   if (b > 1024) b = 1024;
   return (int)b;
