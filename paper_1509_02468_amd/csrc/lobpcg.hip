@@ -858,6 +858,8 @@ __device__ void rayleigh_ritz(RRShared& sh, int ns, int m, double drop_tol, doub
     rayleigh_ritz_kb<4>(sh, ns, m, drop_tol, zero_tol, Cout, theta, kept_out, nkept_out);
   else if (ns <= 8)
     rayleigh_ritz_kb<8>(sh, ns, m, drop_tol, zero_tol, Cout, theta, kept_out, nkept_out);
+  else if (ns <= 10)
+    rayleigh_ritz_kb<10>(sh, ns, m, drop_tol, zero_tol, Cout, theta, kept_out, nkept_out);
   else if (ns <= 12)
     rayleigh_ritz_kb<12>(sh, ns, m, drop_tol, zero_tol, Cout, theta, kept_out, nkept_out);
   else if (ns <= 16)
