@@ -381,7 +381,7 @@ struct RRShared {
 // Small symmetric eigenproblem: the m smallest eigenpairs of the K x K matrix
 // in sh.M (K <= KB <= 24), on the four waves of the workgroup:
 //  1. Householder tridiagonalisation T = Q^T M Q on wave 0 (lane i owns row i
-//     in registers; v and w of each reflector are broadcast through LDS;
+//     in registers; v and w of each reflector are read from their lanes;
 //     column sums by DPP within rows of 16 lanes);
 //  2. per eigenvalue, multisection bisection of the Sturm count: one wave per
 //     eigenvalue (two for m > 4), its 64 (32) lanes evaluate the count at
@@ -467,32 +467,28 @@ __device__ void tridiagonalize(RRShared& sh, int K) {
     const double v = lane == j + 1 ? x0 - alpha : xj;
     const double vtv = 2.0 * (s2 - alpha * x0);
     const double beta = vtv > 0.0 ? 2.0 / vtv : 0.0;
-    if (row) {
-      sh.bc[0][lane] = v;
-      sh.H[j][lane] = v;
-    }
+    if (row) sh.H[j][lane] = v;
     if (lane == 0) sh.hb[j] = beta;
-    wave_fence();
+    // v_k and w_k come from lane k by lane reads (an LDS broadcast with its
+    // waits cost about 1 us per call)
     double p0 = 0.0, p1 = 0.0;  // two chains: half the dependent FMAs
 #pragma unroll
     for (int k = j + 1; k < KB; ++k) {
-      if ((k & 1) == 0) p0 = fma(a[k], sh.bc[0][k], p0);
-      else p1 = fma(a[k], sh.bc[0][k], p1);
+      if ((k & 1) == 0) p0 = fma(a[k], readlane_d(v, k), p0);
+      else p1 = fma(a[k], readlane_d(v, k), p1);
     }
     const double p = (p0 + p1) * beta;
     const double kc = 0.5 * beta * sum_rows<KB>(row ? v * p : 0.0);
     const double w = p - kc * v;
-    if (row) sh.bc[1][lane] = w;
-    wave_fence();
     // A -= v w^T + w v^T: columns left of j are untouched (their rows are
     // already reduced, so w is zero there); column j takes w_j = p_j
 #pragma unroll
     for (int k = j; k < KB; ++k) {
-      const double vk = k > j ? sh.bc[0][k] : 0.0;
-      a[k] -= v * sh.bc[1][k] + w * vk;
+      const double vk = k > j ? readlane_d(v, k) : 0.0;
+      a[k] -= v * readlane_d(w, k) + w * vk;
     }
-    wave_fence();
   }
+  wave_fence();
   if (row) {
 #pragma unroll
     for (int k = 0; k < KB; ++k) sh.M[lane * LD + k] = a[k];
@@ -696,9 +692,10 @@ __device__ void rayleigh_ritz_kb(RRShared& sh, int ns, int m, double drop_tol, d
   }
   wave_fence();
   // right-looking Cholesky of SB with column dropping, lane i owning row i
-  // (lower triangle) in registers: column j's pivot comes from lane j, the
-  // column itself is broadcast through LDS for the rank-1 update of the rows
-  // below; a dropped column leaves L and the trailing rows unchanged
+  // (lower triangle) in registers: column j's pivot and its entries come
+  // from their lanes by lane reads for the rank-1 update of the rows below
+  // (an LDS broadcast instead cost 1 us per LOBPCG step at 9 columns); a
+  // dropped column leaves L and the trailing rows unchanged
   {
     double sb[KB];
 #pragma unroll
@@ -714,14 +711,11 @@ __device__ void rayleigh_ritz_kb(RRShared& sh, int ns, int m, double drop_tol, d
         if (keep) {
           if (lane > j && lane < ns) sh.L[lane * LD + j] = lij;
           if (lane == j) sh.L[j * LD + j] = piv * ip;
-          if (lane < KB) sh.bc[0][lane] = lij;
-          wave_fence();
 #pragma unroll
           for (int l = j + 1; l < KB; ++l) {
-            const double llj = sh.bc[0][l];
+            const double llj = readlane_d(lij, l);  // L[l][j], from lane l
             sb[l] = (lane > j && l <= lane) ? fma(-lij, llj, sb[l]) : sb[l];
           }
-          wave_fence();
         }
       }
     }
