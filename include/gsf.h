@@ -316,7 +316,8 @@ gsf_status gsf_srgb_to_lab(int prec, int64_t n, const void* rgb, void* lab, void
  * total degree, then row degree).  With constraint != 0 every block is kept
  * orthogonal to Y = D^1/2 e / ||D^1/2 e|| (x orthogonal to e in the D inner
  * product).  Each step: R = AX - X Theta, W = R (projected), Rayleigh-Ritz on
- * [X, W, P] in FP64 with a column-dropping Cholesky (drop when the pivot of the
+ * [X, W, P] in FP64 (the Gram pair summed in FP64 from exact products for
+ * either element type) with a column-dropping Cholesky (drop when the pivot of the
  * unit-diagonal Gram is <= 1e-10 (FP64) / 1e-6 (FP32), or the column norm^2 is
  * <= tau^2 max norm^2), keep the m smallest Ritz pairs, P = [W, P] C.
  * Output x_out = D^-1/2 (X X^T z0 (+ Y Y^T z0)), n elements.
@@ -597,9 +598,11 @@ gsf_status gsf_batch_filter(const gsf_batch_item* items, int count, void* ws, si
  * gsf_block_gram: the Gram pair of the LOBPCG Rayleigh-Ritz step (Algorithm 3,
  *   the Rayleigh-Ritz line): GA = S^T (A S), GB = S^T S for S = [S0 .. S_{nb-1}]
  *   (nb = 1..3 point-major blocks of n x m, m = 1..8, element type prec) and
- *   AS = [A0 ..]; S and AS are arrays of nb device pointers.  Results are
- *   written to host arrays GA, GB (ns x ns, ns = nb*m, row-major).  The
- *   device workspace size comes from gsf_block_gram_workspace_bytes(n).
+ *   AS = [A0 ..]; S and AS are arrays of nb device pointers.  Every product
+ *   and sum is FP64 for both element types (the product of two FP32 values
+ *   is exact in FP64), in a fixed order.  Results are written to host arrays
+ *   GA, GB (ns x ns, ns = nb*m, row-major).  The device workspace size comes
+ *   from gsf_block_gram_workspace_bytes(n).
  *   Synchronizes the stream.
  * gsf_rayleigh_ritz: the FP64 Rayleigh-Ritz step on a host Gram pair
  *   (ns = 1..24, m <= min(8, ns)): the m smallest Ritz values theta (host, m)
