@@ -939,15 +939,15 @@ struct LobRun {
     rr.fin_partials = pending ? w.vpart : nullptr;
     rr.fin_nparts = nb;
     rr.fin_stride = 2 * m;
-    GSF_TRY(lob_launch_gram(g, rr, op.desc.prec, s, cg_update, cg_direction));
+    GSF_TRY(lob_launch_gram(g, rr, op.desc.prec, s, cg_update));
     if ((k + 1) % kAxRefresh != 0) {
-      GSF_TRY(lob_launch_mkernel(fold ? 4 : 1, a, nb, ns, 0, deg, s));
+      GSF_TRY(lob_launch_mkernel(fold ? 4 : 1, a, nb, ns, 0, deg, s, cg_direction));
     } else {
       // every kAxRefresh steps AX = A X explicitly (the update's linear
       // combinations accumulate rounding that would floor the residual), then
       // the residual of that AX: it, not the carried one, makes this step's
       // convergence decision
-      GSF_TRY(lob_launch_mkernel(4, a, nb, ns, 0, deg, s));
+      GSF_TRY(lob_launch_mkernel(4, a, nb, ns, 0, deg, s, cg_direction));
       GSF_TRY(apply_any(op, GSF_FORM_LSYM, m, w.X, m, w.AX, m, nullptr, nullptr, s));
       LobArgs ai = a;
       ai.C = reinterpret_cast<const double*>(reinterpret_cast<const char*>(w.st) + offsetof(LobpcgState, cid));
@@ -1102,9 +1102,9 @@ gsf_status gsf_lobpcg_filter(const gsf_operator* h, const void* x0, void* x_out,
 // Joint CG + LOBPCG filters of one operator: step k of both runs shares one
 // stencil pass, [A W | A p] from [W | p] (the CG vector as one more column of
 // the LOBPCG block), where the operator offers a joint apply.  Everything runs
-// on the caller's stream: the CG update of step k and the direction of step
-// k + 1 run as extra workgroups of the LOBPCG Gram-reduction and
-// Rayleigh-Ritz launches, which use a handful of workgroups themselves.
+// on the caller's stream: the CG update of step k runs as extra workgroups of
+// the LOBPCG Rayleigh-Ritz launch (one workgroup of its own), and the
+// direction of step k + 1 as extra workgroups of the LOBPCG update launch.
 // (A second stream for the CG phases cost two event waits per step, each
 // delaying the next launch by about 6 us.)
 gsf_status gsf_joint_workspace_bytes(const gsf_operator* h, int m, size_t* bytes) {
@@ -1151,8 +1151,8 @@ gsf_status gsf_joint_filter(gsf_operator* h, const void* x0_cg, void* x_cg, int 
       if (k < kmax_lob) GSF_TRY(lob.apply());
     }
     if (both) {
-      // CG's update of step k + 1 in the Gram-reduction launch, the direction
-      // of step k + 2 (when there is one) in the Rayleigh-Ritz launch
+      // CG's update of step k + 1 in the Rayleigh-Ritz launch, the direction
+      // of step k + 2 (when there is one) in the LOBPCG update launch
       const CgStepArgs upd = cg.phase(k + 1), dir = cg.phase(k + 2);
       cg.steps = k + 1;
       lob.cg_update = &upd;

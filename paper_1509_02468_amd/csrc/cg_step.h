@@ -1,9 +1,9 @@
 // The two vector phases of a CG step (Algorithm 2 in z-space) as device
 // functions that take their workgroup index and the workgroup count, so that
 // they run either as launches of their own or as extra workgroups of another
-// launch on the same stream (the joint CG + LOBPCG driver places them in the
-// LOBPCG Gram-reduction and Rayleigh-Ritz launches, whose own work leaves the
-// GPU almost idle).
+// launch on the same stream (the joint CG + LOBPCG driver places the update in
+// the LOBPCG Rayleigh-Ritz launch, whose one workgroup leaves the GPU almost
+// idle, and the direction in the LOBPCG update launch).
 //
 // Every workgroup sums the previous phase's partials itself, in the same
 // fixed order as a one-workgroup kernel, so all take bitwise the same
@@ -131,13 +131,6 @@ __device__ __forceinline__ void cg_aupdate_body(T* __restrict__ z, T* __restrict
     upd[2 * bid] = v[0];
     upd[2 * bid + 1] = v[1];
   }
-}
-
-__device__ __forceinline__ void cg_pbeta_step(const CgStepArgs& a, int bid) {
-  if (a.prec == GSF_F32)
-    cg_pbeta_body<float>((const float*)a.r, (float*)a.p, a.n, a.upd, a.nblk, a.st, a.k, bid, a.nblk);
-  else
-    cg_pbeta_body<double>((const double*)a.r, (double*)a.p, a.n, a.upd, a.nblk, a.st, a.k, bid, a.nblk);
 }
 
 __device__ __forceinline__ void cg_aupdate_step(const CgStepArgs& a, int bid) {

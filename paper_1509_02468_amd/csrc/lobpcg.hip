@@ -894,16 +894,9 @@ __device__ void fin_reduce(const RRArgs& r, int m, double* fin) {
 // First stage of the Gram reduction: workgroup (tile, chunk) sums the partials
 // of its chunk of Gram workgroups for the 256 entries of one tile; the
 // workgroup column after the tiles reduces the previous update's residual
-// partials for the Rayleigh-Ritz step, off its critical path; further columns
-// (cg.nblk > 0) run a CG update phase of the joint driver (the launch's own
-// work is latency-bound and leaves the GPU almost idle).
-__global__ void __launch_bounds__(kThreads) gram_reduce_kernel(GramArgs g, RRArgs r, CgStepArgs cg) {
+// partials for the Rayleigh-Ritz step, off its critical path.
+__global__ void __launch_bounds__(kThreads) gram_reduce_kernel(GramArgs g, RRArgs r) {
   const int ntiles = n_tiles_b((g.ns + 15) >> 4) + n_tiles_a((g.ns + 15) >> 4);
-  if ((int)blockIdx.x > ntiles) {
-    const int bid = ((int)blockIdx.x - ntiles - 1) * (int)gridDim.y + (int)blockIdx.y;
-    if (bid < cg.nblk) cg_aupdate_step(cg, bid);
-    return;
-  }
   if (g.active != nullptr && *g.active == 0) return;
   if ((int)blockIdx.x == ntiles) {
     if (blockIdx.y == 0 && r.fin_partials != nullptr) fin_reduce(r, g.m, g.level2 + kGramFinSlot);
@@ -934,15 +927,15 @@ __global__ void __launch_bounds__(kThreads) gram_reduce_kernel(GramArgs g, RRArg
 
 // Workgroup 0: sums the chunks and assembles GA and GB (ns x ns); its first
 // wave then runs the Rayleigh-Ritz step.  Workgroups 1.. (cg.nblk of them)
-// run a CG direction phase of the joint driver.
+// run a CG update phase of the joint driver on the CUs the step leaves idle.
 //
-// direct != 0 (at most kGramChunks Gram workgroups and no CG phase): no
+// direct != 0 (at most kGramChunks Gram workgroups): no
 // reduction launch ran; the partials take the place of the chunk sums (the
 // reduction would have copied them one to one, so the sums are bitwise the
 // same) and this workgroup sums the previous update's residual partials.
 __global__ void __launch_bounds__(kThreads) gram_rr_kernel(GramArgs g, RRArgs r, CgStepArgs cg, int direct) {
   if (blockIdx.x > 0) {
-    cg_pbeta_step(cg, (int)blockIdx.x - 1);
+    cg_aupdate_step(cg, (int)blockIdx.x - 1);
     return;
   }
   __shared__ RRShared sh;
@@ -1098,12 +1091,20 @@ __device__ __forceinline__ void store_row(T* __restrict__ dst, const T (&v)[M]) 
 
 // NB = number of blocks in the trial basis: 1 (start block), 2 ([X, W]),
 // 3 ([X, W, P]).  Coefficients C (NB*M x M, FP64) are read from LDS; every
-// output column is accumulated in FP64 and rounded once.
+// output column is accumulated in FP64 and rounded once.  The last cg.nblk
+// workgroups run a CG direction phase of the joint driver (same element
+// type): the update streams the LOBPCG block, and the direction's three
+// vector passes share the launch instead of adding one to the step.
 template <typename T, int M, int NB>
-__global__ void __launch_bounds__(kThreads) lob_update_kernel(LobArgs a, int first) {
+__global__ void __launch_bounds__(kThreads) lob_update_kernel(LobArgs a, int first, CgStepArgs cg) {
   __shared__ double Cs[3 * M * M];
   __shared__ double th[M];
   __shared__ double red[16 * 2 * M];
+  const int nupd = (int)gridDim.x - cg.nblk;
+  if ((int)blockIdx.x >= nupd) {
+    cg_pbeta_body<T>((const T*)cg.r, (T*)cg.p, cg.n, cg.upd, cg.nblk, cg.st, cg.k, (int)blockIdx.x - nupd, cg.nblk);
+    return;
+  }
   LobpcgState* st = a.st;
   if (!st->active) return;
   for (int e = threadIdx.x; e < NB * M * M; e += blockDim.x) Cs[e] = a.C[e];
@@ -1117,7 +1118,7 @@ __global__ void __launch_bounds__(kThreads) lob_update_kernel(LobArgs a, int fir
   T* __restrict__ AP = (T*)a.AP;
   const T* __restrict__ sqd = (const T*)a.sqd;
   const double yinv = st->ynorm_inv;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t stride = (int64_t)nupd * blockDim.x;
   double v[2 * M];
 #pragma unroll
   for (int j = 0; j < 2 * M; ++j) v[j] = 0.0;
@@ -1242,7 +1243,10 @@ __global__ void __launch_bounds__(kThreads) lob_output_kernel(LobArgs a) {
 }
 
 template <typename T, int M>
-void launch_m_kernels(int which, const LobArgs& a, int nb, int ns, int first, StartDegrees deg, hipStream_t s) {
+void launch_m_kernels(int which, const LobArgs& a, int nb, int ns, int first, StartDegrees deg,
+                      const CgStepArgs& cg, hipStream_t s) {
+  const CgStepArgs none{};
+  const int nbc = nb + cg.nblk;  // the update launches, with the CG phase's workgroups
   switch (which) {
     case 0:
       lob_start_kernel<T, M><<<nb, kThreads, 0, s>>>(a, deg);
@@ -1250,30 +1254,30 @@ void launch_m_kernels(int which, const LobArgs& a, int nb, int ns, int first, St
       break;
     case 1:
       if (ns == M)
-        lob_update_kernel<T, M, 1><<<nb, kThreads, 0, s>>>(a, first);
+        lob_update_kernel<T, M, 1><<<nbc, kThreads, 0, s>>>(a, first, cg);
       else if (ns == 2 * M)
-        lob_update_kernel<T, M, 2><<<nb, kThreads, 0, s>>>(a, first);
+        lob_update_kernel<T, M, 2><<<nbc, kThreads, 0, s>>>(a, first, cg);
       else
-        lob_update_kernel<T, M, 3><<<nb, kThreads, 0, s>>>(a, first);
+        lob_update_kernel<T, M, 3><<<nbc, kThreads, 0, s>>>(a, first, cg);
       lob_final_kernel<2 * M><<<1, kThreads, 0, s>>>(a.vpart, nb, a.st, 2, M, first, a.constraint);
       break;
     case 4:
       if (ns == M)
-        lob_update_kernel<T, M, 1><<<nb, kThreads, 0, s>>>(a, first);
+        lob_update_kernel<T, M, 1><<<nbc, kThreads, 0, s>>>(a, first, cg);
       else if (ns == 2 * M)
-        lob_update_kernel<T, M, 2><<<nb, kThreads, 0, s>>>(a, first);
+        lob_update_kernel<T, M, 2><<<nbc, kThreads, 0, s>>>(a, first, cg);
       else
-        lob_update_kernel<T, M, 3><<<nb, kThreads, 0, s>>>(a, first);
+        lob_update_kernel<T, M, 3><<<nbc, kThreads, 0, s>>>(a, first, cg);
       break;
     case 5:
       lob_final_kernel<2 * M><<<1, kThreads, 0, s>>>(a.vpart, nb, a.st, 2, M, first, a.constraint);
       break;
     case 6:  // W = AX - X Theta of a recomputed AX (a.C = I: X, AX copied, P, AP kept), finalized as an update
-      lob_update_kernel<T, M, 1><<<nb, kThreads, 0, s>>>(a, 1);
+      lob_update_kernel<T, M, 1><<<nb, kThreads, 0, s>>>(a, 1, none);
       lob_final_kernel<2 * M><<<1, kThreads, 0, s>>>(a.vpart, nb, a.st, 2, M, 0, a.constraint);
       break;
     case 7:  // the same, its finalize folded into the next Rayleigh-Ritz step
-      lob_update_kernel<T, M, 1><<<nb, kThreads, 0, s>>>(a, 1);
+      lob_update_kernel<T, M, 1><<<nb, kThreads, 0, s>>>(a, 1, none);
       break;
     case 2:
       lob_out_dots_kernel<T, M><<<nb, kThreads, 0, s>>>(a);
@@ -1284,16 +1288,17 @@ void launch_m_kernels(int which, const LobArgs& a, int nb, int ns, int first, St
 }
 
 template <typename T>
-void launch_m_dispatch(int which, const LobArgs& a, int nb, int ns, int first, StartDegrees deg, hipStream_t s) {
+void launch_m_dispatch(int which, const LobArgs& a, int nb, int ns, int first, StartDegrees deg, const CgStepArgs& cg,
+                       hipStream_t s) {
   switch (a.m) {
-    case 1: launch_m_kernels<T, 1>(which, a, nb, ns, first, deg, s); break;
-    case 2: launch_m_kernels<T, 2>(which, a, nb, ns, first, deg, s); break;
-    case 3: launch_m_kernels<T, 3>(which, a, nb, ns, first, deg, s); break;
-    case 4: launch_m_kernels<T, 4>(which, a, nb, ns, first, deg, s); break;
-    case 5: launch_m_kernels<T, 5>(which, a, nb, ns, first, deg, s); break;
-    case 6: launch_m_kernels<T, 6>(which, a, nb, ns, first, deg, s); break;
-    case 7: launch_m_kernels<T, 7>(which, a, nb, ns, first, deg, s); break;
-    default: launch_m_kernels<T, 8>(which, a, nb, ns, first, deg, s); break;
+    case 1: launch_m_kernels<T, 1>(which, a, nb, ns, first, deg, cg, s); break;
+    case 2: launch_m_kernels<T, 2>(which, a, nb, ns, first, deg, cg, s); break;
+    case 3: launch_m_kernels<T, 3>(which, a, nb, ns, first, deg, cg, s); break;
+    case 4: launch_m_kernels<T, 4>(which, a, nb, ns, first, deg, cg, s); break;
+    case 5: launch_m_kernels<T, 5>(which, a, nb, ns, first, deg, cg, s); break;
+    case 6: launch_m_kernels<T, 6>(which, a, nb, ns, first, deg, cg, s); break;
+    case 7: launch_m_kernels<T, 7>(which, a, nb, ns, first, deg, cg, s); break;
+    default: launch_m_kernels<T, 8>(which, a, nb, ns, first, deg, cg, s); break;
   }
 }
 
@@ -1309,11 +1314,14 @@ gsf_status lob_launch_ynorm(const LobArgs& a, int nb, hipStream_t s) {
 }
 
 gsf_status lob_launch_mkernel(int which, const LobArgs& a, int nb, int ns, int first, StartDegrees deg,
-                              hipStream_t s) {
+                              hipStream_t s, const CgStepArgs* cg_direction) {
+  const CgStepArgs none{};
+  const CgStepArgs& cp = (cg_direction != nullptr && (which == 1 || which == 4)) ? *cg_direction : none;
+  if (cp.nblk > 0 && cp.prec != a.prec) return GSF_EINVAL;
   if (a.prec == GSF_F32)
-    launch_m_dispatch<float>(which, a, nb, ns, first, deg, s);
+    launch_m_dispatch<float>(which, a, nb, ns, first, deg, cp, s);
   else
-    launch_m_dispatch<double>(which, a, nb, ns, first, deg, s);
+    launch_m_dispatch<double>(which, a, nb, ns, first, deg, cp, s);
   return launch_status();
 }
 
@@ -1347,7 +1355,7 @@ void launch_gram_kernel(const GramArgs& g, hipStream_t s) {
 }
 
 gsf_status lob_launch_gram(const GramArgs& g, const RRArgs& r, int prec, hipStream_t s,
-                           const CgStepArgs* cg_update, const CgStepArgs* cg_direction) {
+                           const CgStepArgs* cg_update) {
   if (g.ns < 1 || g.ns > KMAX) return GSF_EINVAL;
   if (prec == GSF_F32)
     launch_gram_kernel<float>(g, s);
@@ -1355,15 +1363,14 @@ gsf_status lob_launch_gram(const GramArgs& g, const RRArgs& r, int prec, hipStre
     launch_gram_kernel<double>(g, s);
   const CgStepArgs none{};
   const CgStepArgs& ca = cg_update != nullptr ? *cg_update : none;
-  const CgStepArgs& cp = cg_direction != nullptr ? *cg_direction : none;
   // with at most kGramChunks Gram workgroups the reduction launch would only
   // copy the partials: the Rayleigh-Ritz workgroup reads them itself
-  const int direct = (g.nparts <= kGramChunks && ca.nblk == 0) ? 1 : 0;
+  const int direct = g.nparts <= kGramChunks ? 1 : 0;
   if (!direct) {
-    dim3 grid(gram_tiles_total(g.ns) + 1 + (ca.nblk + kGramChunks - 1) / kGramChunks, kGramChunks);
-    gram_reduce_kernel<<<grid, kThreads, 0, s>>>(g, r, ca);
+    dim3 grid(gram_tiles_total(g.ns) + 1, kGramChunks);
+    gram_reduce_kernel<<<grid, kThreads, 0, s>>>(g, r);
   }
-  gram_rr_kernel<<<1 + cp.nblk, rr_threads(g.ns), 0, s>>>(g, r, cp, direct);
+  gram_rr_kernel<<<1 + ca.nblk, rr_threads(g.ns), 0, s>>>(g, r, ca, direct);
   return launch_status();
 }
 

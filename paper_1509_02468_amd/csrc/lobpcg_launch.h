@@ -63,20 +63,21 @@ struct RRArgs {
 
 int gram_tiles_total(int ns);
 gsf_status lob_launch_ynorm(const LobArgs& a, int nb, hipStream_t s);
-// which: 0 start, 1 update (ns, first), 2 output dots, 3 output
+struct CgStepArgs;
 // which: 0 start block, 1 update + finalize, 2 output dots, 3 output,
 // 4 update without the finalize (see RRArgs::fin_partials), 5 the finalize alone,
-// 6 / 7 the residual of a recomputed AX with / without the finalize (a.C = I)
+// 6 / 7 the residual of a recomputed AX with / without the finalize (a.C = I).
+// cg_direction (nullable, same precision; which = 1 or 4 only): a CG
+// direction phase run as extra workgroups of the update launch (the joint
+// CG + LOBPCG driver).
 gsf_status lob_launch_mkernel(int which, const LobArgs& a, int nb, int ns, int first, StartDegrees deg,
-                              hipStream_t s);
+                              hipStream_t s, const CgStepArgs* cg_direction = nullptr);
 gsf_status lob_launch_project(const LobArgs& a, void* B, int nb, hipStream_t s);
-// Gram partials, their reduction and the Rayleigh-Ritz step.  cg_update /
-// cg_direction (nullable): a CG update phase run as extra workgroups of the
-// reduction launch, and a CG direction phase run as extra workgroups of the
-// Rayleigh-Ritz launch (the joint CG + LOBPCG driver).
-struct CgStepArgs;
+// Gram partials, their reduction and the Rayleigh-Ritz step.  cg_update
+// (nullable): a CG update phase run as extra workgroups of the Rayleigh-Ritz
+// launch (the joint CG + LOBPCG driver).
 gsf_status lob_launch_gram(const GramArgs& g, const RRArgs& r, int prec, hipStream_t s,
-                           const CgStepArgs* cg_update = nullptr, const CgStepArgs* cg_direction = nullptr);
+                           const CgStepArgs* cg_update = nullptr);
 gsf_status lob_launch_rr_only(const double* G, int ns, int m, const RRArgs& r, hipStream_t s);
 gsf_status launch_lob_state_init(LobpcgState* dst, const LobpcgState& v, hipStream_t s);
 gsf_status launch_cg_state_init(CgState* dst, const CgState& v, hipStream_t s);
