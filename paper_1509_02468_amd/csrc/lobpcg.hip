@@ -943,18 +943,28 @@ __global__ void __launch_bounds__(kThreads) gram_rr_kernel(GramArgs g, RRArgs r,
   __shared__ int keptf[KMAX];
   __shared__ int live;
   __shared__ int lockm;
-  if (r.st != nullptr && !r.st->active) return;
   const int nt = (g.ns + 15) >> 4;
   const int ntot = n_tiles_b(nt) + n_tiles_a(nt);
-  // Everything this kernel reads from global memory was written by other
-  // workgroups of earlier kernels (other XCDs), so each load is a long trip:
-  // the first batch of Gram chunk values and the residual partials are all
-  // issued before any of them is used.
+  // Everything this kernel reads from global memory was written by earlier
+  // kernels (other XCDs), so each load is a long trip: the chunk values of
+  // every thread's first two entries (all entries for ns <= 16), the solver
+  // state and the residual sums are all issued before any of them is used
+  // (also before the state says whether the step runs at all).
   const double* chunks = direct ? g.partials : g.level2;
   const int nchunks = direct ? g.nparts : kGramChunks;
-  double v0[kGramChunks];
+  const int e1 = (int)threadIdx.x + (int)blockDim.x;  // ntot >= 2: every thread has two entries
+  double v0[kGramChunks], v1[kGramChunks];
 #pragma unroll
-  for (int c = 0; c < kGramChunks; ++c) v0[c] = c < nchunks ? chunks[(size_t)c * (ntot * 256) + threadIdx.x] : 0.0;
+  for (int c = 0; c < kGramChunks; ++c) {
+    v0[c] = c < nchunks ? chunks[(size_t)c * (ntot * 256) + threadIdx.x] : 0.0;
+    v1[c] = c < nchunks ? chunks[(size_t)c * (ntot * 256) + e1] : 0.0;
+  }
+  LobpcgState* st = r.st;
+  const int active = st != nullptr ? st->active : 1;
+  const double tol = st != nullptr ? st->tol : 0.0;
+  const int iters0 = st != nullptr ? st->iters : 0;
+  const int dropped0 = st != nullptr ? st->dropped : 0;
+  if (!active) return;
   if (r.fin_partials != nullptr) {
     // the previous update's residual norms, iteration count and convergence
     // test (what lob_final_kernel does after an update without the
@@ -968,15 +978,15 @@ __global__ void __launch_bounds__(kThreads) gram_rr_kernel(GramArgs g, RRArgs r,
 #pragma unroll
       for (int k = 0; k < 8; ++k) t[k] = fin[k];
     if (threadIdx.x == 0) {
-      LobpcgState* st = r.st;
       double mx = 0.0;
       for (int j = 0; j < g.m; ++j) {
-        st->res[j] = sqrt(t[j]);
+        const double rj = sqrt(t[j]);
+        st->res[j] = rj;
         st->yx[j] = 0.0;
-        mx = st->res[j] > mx ? st->res[j] : mx;
+        mx = rj > mx ? rj : mx;
       }
-      st->iters += 1;
-      live = !(st->tol > 0.0 && mx <= st->tol);
+      st->iters = iters0 + 1;
+      live = !(tol > 0.0 && mx <= tol);
       if (!live) st->active = 0;
     }
     __syncthreads();
@@ -999,8 +1009,9 @@ __global__ void __launch_bounds__(kThreads) gram_rr_kernel(GramArgs g, RRArgs r,
       }
     }
   };
-  place(threadIdx.x, v0);  // ntot >= 2: every thread has a first entry
-  for (int e = threadIdx.x + blockDim.x; e < ntot * 256; e += blockDim.x) {
+  place(threadIdx.x, v0);
+  place(e1, v1);
+  for (int e = e1 + blockDim.x; e < ntot * 256; e += blockDim.x) {
     double v[kGramChunks];
 #pragma unroll
     for (int c = 0; c < kGramChunks; ++c) v[c] = c < nchunks ? chunks[(size_t)c * (ntot * 256) + e] : 0.0;
@@ -1012,9 +1023,9 @@ __global__ void __launch_bounds__(kThreads) gram_rr_kernel(GramArgs g, RRArgs r,
   // Rayleigh-Ritz step drops the column
   if (threadIdx.x == 0) {
     int mask = 0;
-    if (!r.init && r.st != nullptr && r.st->tol > 0.0 && g.ns > g.m)
+    if (!r.init && st != nullptr && tol > 0.0 && g.ns > g.m)
       for (int j = 0; j < g.m; ++j)
-        if (r.st->res[j] <= r.st->tol) mask |= 1 << j;
+        if (st->res[j] <= tol) mask |= 1 << j;
     lockm = mask;
   }
   __syncthreads();
@@ -1041,11 +1052,10 @@ __global__ void __launch_bounds__(kThreads) gram_rr_kernel(GramArgs g, RRArgs r,
   rayleigh_ritz(sh, g.ns, g.m, r.drop_tol, r.zero_tol, r.C, r.theta, keptf, &nkept);
   if (threadIdx.x >= 64) return;
   wave_fence();
-  if (threadIdx.x == 0 && r.st != nullptr) {
-    LobpcgState* st = r.st;
+  if (threadIdx.x == 0 && st != nullptr) {
     st->nkept = nkept;
     for (int j = 0; j < g.ns; ++j) st->kept[j] = keptf[j];
-    st->dropped += g.ns - nkept;
+    st->dropped = dropped0 + g.ns - nkept;
     if (nkept < g.m) {
       st->status = GSF_EBREAKDOWN;
       st->active = 0;
@@ -1370,7 +1380,11 @@ gsf_status lob_launch_gram(const GramArgs& g, const RRArgs& r, int prec, hipStre
     dim3 grid(gram_tiles_total(g.ns) + 1, kGramChunks);
     gram_reduce_kernel<<<grid, kThreads, 0, s>>>(g, r);
   }
-  gram_rr_kernel<<<1 + ca.nblk, rr_threads(g.ns), 0, s>>>(g, r, ca, direct);
+  // with a CG phase, 24 KB of unused LDS per workgroup (about 83 KB with the
+  // step's own) keep a second workgroup off the Rayleigh-Ritz workgroup's CU:
+  // 41.5 us per call at 1024^2, m = 4 against 42.3 us when a CG workgroup
+  // shares it (the CG phase itself ends long before the step)
+  gram_rr_kernel<<<1 + ca.nblk, rr_threads(g.ns), ca.nblk > 0 ? 24 * 1024 : 0, s>>>(g, r, ca, direct);
   return launch_status();
 }
 
