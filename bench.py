@@ -853,9 +853,9 @@ def main():
 
     # CG and LOBPCG are independent filters of the same operator.  Default: the
     # joint driver, whose step k of both filters shares one stencil pass (the
-    # CG vector as a fifth column of the LOBPCG block) and runs the CG scalars
-    # and vector updates as extra workgroups of LOBPCG's Gram-reduction and
-    # one-workgroup Rayleigh-Ritz launches.
+    # CG vector as a fifth column of the LOBPCG block) and runs the CG update
+    # and direction as extra workgroups of LOBPCG's one-workgroup
+    # Rayleigh-Ritz launch and of its update launch.
     # --separate: two independent calls on two streams (LOBPCG, the longer
     # chain, enqueued first); --serial: one after the other.  (A GF operator's
     # apply uses the handle's scratch planes, so its filters stay on one

@@ -349,8 +349,9 @@ gsf_status gsf_lobpcg_filter(const gsf_operator* op, const void* x0, void* x_out
  * shares one stencil pass: the CG vector is applied as one more column of the
  * LOBPCG block (BF operators on the square window or 1D with m = 1 or 4; other
  * operators apply the two blocks one after the other).  Everything runs on
- * `stream`: the CG scalars and vector updates run as extra workgroups of the
- * LOBPCG Gram-reduction and Rayleigh-Ritz launches.  x0_cg, x_cg: n elements;
+ * `stream`: the CG update (alpha, x, r) runs as extra workgroups of the LOBPCG
+ * Rayleigh-Ritz launch and the CG direction (beta, p) as extra workgroups of
+ * the LOBPCG update launch.  x0_cg, x_cg: n elements;
  * x0_lob, x_lob: n elements.
  * Workspace: gsf_joint_workspace_bytes(op, m, ...).  cg_info, lob_info: NULL
  * or summaries as for the single filters.  GSF_EINVAL for NULL pointers,

@@ -325,7 +325,6 @@ struct LobWs {
   double* C;
   double* theta;
   double* vpart;
-  unsigned int* gram_counter;
   LobpcgState* st;
 };
 
@@ -352,7 +351,6 @@ size_t carve_lob(const Operator& op, int m, char* base, LobWs* w) {
   w->C = (double*)c.take(24 * 8 * sizeof(double));
   w->theta = (double*)c.take(8 * sizeof(double));
   w->vpart = (double*)c.take((size_t)vec_blocks(op.n) * 17 * sizeof(double));
-  w->gram_counter = (unsigned int*)c.take(64);
   w->st = (LobpcgState*)c.take(sizeof(LobpcgState));
   w->Z = c.take(blk);
   w->net_partials = (double*)c.take((size_t)net_tiles(op.rows, op.cols) * 3 * m * sizeof(double));
@@ -883,7 +881,6 @@ struct LobRun {
     g.nparts = gram_blocks(op.n);
     g.partials = w.gram_partials;
     g.level2 = w.gram_level2;
-    g.counter = w.gram_counter;
     g.active = &w.st->active;
     rr.C = w.C;
     rr.theta = w.theta;
@@ -1307,7 +1304,6 @@ gsf_status gsf_block_gram(int prec, int64_t n, int m, int nb, const void* const*
   double* C = (double*)w.take(24 * 8 * 8);
   double* th = (double*)w.take(64);
   int* kept = (int*)w.take(256);
-  g.counter = (unsigned int*)w.take(64);
   for (int b = 0; b < nb; ++b) {
     g.S[b] = S[b];
     g.AS[b] = AS[b];
@@ -1338,7 +1334,6 @@ gsf_status gsf_block_gram_workspace_bytes(int64_t n, size_t* bytes) {
   c.take(24 * 8 * 8);
   c.take(64);
   c.take(256);
-  c.take(64);
   *bytes = c.off;
   return GSF_OK;
 }

@@ -41,7 +41,6 @@ struct GramArgs {
   int nparts;          // workgroups of the Gram kernel
   double* partials;    // nparts x tiles x 256
   double* level2;      // kGramChunks x tiles x 256
-  unsigned int* counter;
   const int* active;   // nullable
 };
 

@@ -19,7 +19,6 @@ struct CgState {
   int32_t status;
   int32_t iters;
   int32_t k;     // 1-based index of the next step
-  unsigned int counter;
   int32_t pad;
 };
 
@@ -54,8 +53,6 @@ struct LobpcgState {
   int32_t tuse[8];     // column j uses T(r_j) this step (else T = I)
   int32_t fallbacks;   // column-steps that fell back to T = I
   int32_t pad2;
-  unsigned int counter;
-  unsigned int counter2;
   double cid[64];      // m x m identity coefficients: the residual of a refreshed AX
 };
 
