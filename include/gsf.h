@@ -346,8 +346,8 @@ gsf_status gsf_lobpcg_filter(const gsf_operator* op, const void* x0, void* x_out
  * the results are those of gsf_cg_filter(x0_cg, kmax_cg, tol 0) and
  * gsf_lobpcg_filter(x0_lob, m, kmax_lob, tol 0, constraint, T = NULL) up to the
  * summation order of the CG dot products.  While both run, step k of each
- * shares one stencil pass: the CG vector is applied as one more column of the
- * LOBPCG block (BF operators on the square window or 1D with m = 1 or 4; other
+ * shares one stencil pass, and so do their starts (r0 = -L_sym z0 with
+ * A X0): the CG vector is applied as one more column of the LOBPCG block (BF operators on the square window or 1D with m = 1 or 4; other
  * operators apply the two blocks one after the other).  Everything runs on
  * `stream`: the CG update (alpha, x, r) runs as extra workgroups of the LOBPCG
  * Rayleigh-Ritz launch and the CG direction (beta, p) as extra workgroups of

@@ -729,15 +729,21 @@ struct CgRun {
   int nparts = 0;
   int steps = 0;  // steps issued
   CgRun(const Operator& o, char* ws, hipStream_t st) : op(o), s(st) { carve_cg(op, ws, &w); }
+  // the start: z0, r0 = -L_sym z0 and the initial scalars (begin_pre, the
+  // apply z -> r, begin_post; the joint driver applies z with the LOBPCG block)
   gsf_status begin(const void* x0, double tol) {
+    GSF_TRY(begin_pre(x0, tol));
+    GSF_TRY(apply_any(op, GSF_FORM_LSYM, 1, w.z, 1, w.r, 1, nullptr, nullptr, s));
+    return begin_post();
+  }
+  gsf_status begin_pre(const void* x0, double tol) {
     CgState init{};
     init.tol = tol;
     init.tau = breakdown_tau(op.desc.prec);
     GSF_TRY(launch_cg_state_init(w.st, init, s));
-    GSF_TRY(launch_scale(op, x0, w.z, 0, s));
-    GSF_TRY(apply_any(op, GSF_FORM_LSYM, 1, w.z, 1, w.r, 1, nullptr, nullptr, s));
-    return launch_cg_init(op, w.z, w.r, w.partials, w.st, s);
+    return launch_scale(op, x0, w.z, 0, s);
   }
+  gsf_status begin_post() { return launch_cg_init(op, w.z, w.r, w.partials, w.st, s); }
   // step k (1-based): p from r (with beta from the last update's partials)
   gsf_status pre(int k) { return launch_cg_pbeta(op, w.r, w.p, w.partials2, w.st, k, s); }
   gsf_status apply() {  // q = L_sym p and the p^T q partials
@@ -844,7 +850,15 @@ struct LobRun {
       : op(o), s(st), m(m_), constraint(con), T(T_) {
     carve_lob(op, m, ws, &w);
   }
+  // the start (begin_pre: state, X0; the apply X0 -> AX; begin_post: the
+  // start-block Rayleigh-Ritz step and update; the joint driver applies X0
+  // together with the CG start vector)
   gsf_status begin(const void* x0, void* x_out, void* ritz_vecs, double tol) {
+    GSF_TRY(begin_pre(x0, x_out, ritz_vecs, tol));
+    GSF_TRY(apply_any(op, GSF_FORM_LSYM, m, w.X, m, w.AX, m, nullptr, nullptr, s));
+    return begin_post();
+  }
+  gsf_status begin_pre(const void* x0, void* x_out, void* ritz_vecs, double tol) {
     LobpcgState init{};
     init.tol = tol;
     init.drop_tol = drop_tol_of(op.desc.prec);
@@ -890,7 +904,9 @@ struct LobRun {
     if (constraint) GSF_TRY(lob_launch_ynorm(a, nb, s));
     GSF_TRY(lob_launch_mkernel(0, a, nb, m, 1, deg, s));  // X0
     if (constraint) GSF_TRY(lob_launch_project(a, w.X, nb, s));
-    GSF_TRY(apply_any(op, GSF_FORM_LSYM, m, w.X, m, w.AX, m, nullptr, nullptr, s));
+    return GSF_OK;
+  }
+  gsf_status begin_post() {
     // start-block Rayleigh-Ritz
     g.ns = m;
     g.S[0] = w.X;
@@ -1098,7 +1114,8 @@ gsf_status gsf_lobpcg_filter(const gsf_operator* h, const void* x0, void* x_out,
 
 // Joint CG + LOBPCG filters of one operator: step k of both runs shares one
 // stencil pass, [A W | A p] from [W | p] (the CG vector as one more column of
-// the LOBPCG block), where the operator offers a joint apply.  Everything runs
+// the LOBPCG block), where the operator offers a joint apply; so do the
+// starts, [A X0 | L_sym z0].  Everything runs
 // on the caller's stream: the CG update of step k runs as extra workgroups of
 // the LOBPCG Rayleigh-Ritz launch (one workgroup of its own), and the
 // direction of step k + 1 as extra workgroups of the LOBPCG update launch.
@@ -1128,8 +1145,19 @@ gsf_status gsf_joint_filter(gsf_operator* h, const void* x0_cg, void* x_cg, int 
   char* base = (char*)ws;
   CgRun cg(op, base, s);
   LobRun lob(op, m, constraint != 0, nullptr, base + align_up(carve_cg(op, nullptr, &cw), kAlign), s);
-  GSF_TRY(cg.begin(x0_cg, 0.0));
-  GSF_TRY(lob.begin(x0_lob, x_lob, nullptr, 0.0));
+  // the two starts share one stencil pass too: [X0 | z0] -> [A X0 | L_sym z0]
+  GSF_TRY(cg.begin_pre(x0_cg, 0.0));
+  GSF_TRY(lob.begin_pre(x0_lob, x_lob, nullptr, 0.0));
+  const bool joint0 = launch_bf_apply_joint(op, GSF_FORM_LSYM, m, lob.w.X, m, lob.w.AX, m, cg.w.z, 1, cg.w.r, 1,
+                                            cg.w.partials, &cg.nparts, s);
+  if (joint0) {
+    GSF_TRY(hip_ok(hipGetLastError()));
+  } else {
+    GSF_TRY(apply_any(op, GSF_FORM_LSYM, 1, cg.w.z, 1, cg.w.r, 1, nullptr, nullptr, s));
+    GSF_TRY(apply_any(op, GSF_FORM_LSYM, m, lob.w.X, m, lob.w.AX, m, nullptr, nullptr, s));
+  }
+  GSF_TRY(cg.begin_post());
+  GSF_TRY(lob.begin_post());
   const int kj = kmax_cg < kmax_lob ? kmax_cg : kmax_lob;
   bool p_ready = false;  // the next CG direction was formed in the last Rayleigh-Ritz launch
   for (int k = 0; k < kmax_cg || k < kmax_lob; ++k) {
