@@ -354,8 +354,6 @@ constexpr int LD = KMAX + 1;
 struct RRShared {
   double A[KMAX * LD];   // Gram pair as loaded (A = S^T A S, B = S^T S)
   double B[KMAX * LD];
-  double SA[KMAX * LD];  // symmetrised and scaled to unit diag(B)
-  double SB[KMAX * LD];  // the same for B; work array of the Cholesky factorisation
   double L[KMAX * LD];   // Cholesky factor (dropped columns zero)
   double LK[KMAX * LD];  // compressed factor of the kept columns
   double M[KMAX * LD];   // the reduced matrix L^-1 A L^-T, then the tridiagonal rows
@@ -679,27 +677,23 @@ __device__ void rayleigh_ritz_kb(RRShared& sh, int ns, int m, double drop_tol, d
     sh.delta[lane] = gd ? 1.0 / sqrt(dl) : 0.0;
   }
   wave_fence();
-  for (int e = lane; e < ns * ns; e += 64) {
-    const int i = e / ns, j = e - (e / ns) * ns;
-    const double s = sh.delta[i] * sh.delta[j];
-    const double aij = sh.A[i * LD + j], aji = sh.A[j * LD + i];
-    const double bij = sh.B[i * LD + j], bji = sh.B[j * LD + i];
-    const double a = i == j ? aij : 0.5 * (aij + aji);
-    const double b = i == j ? bij : 0.5 * (bij + bji);
-    sh.SA[i * LD + j] = a * s;
-    sh.SB[i * LD + j] = b * s;
-    sh.L[i * LD + j] = 0.0;
-  }
-  wave_fence();
-  // right-looking Cholesky of SB with column dropping, lane i owning row i
-  // (lower triangle) in registers: column j's pivot and its entries come
-  // from their lanes by lane reads for the rank-1 update of the rows below
-  // (an LDS broadcast instead cost 1 us per LOBPCG step at 9 columns); a
-  // dropped column leaves L and the trailing rows unchanged
+  // right-looking Cholesky of the symmetrised, scaled B with column dropping,
+  // lane i owning row i (lower triangle) in registers: column j's pivot and
+  // its entries come from their lanes by lane reads for the rank-1 update of
+  // the rows below (an LDS broadcast instead cost 1 us per LOBPCG step at 9
+  // columns); a dropped column leaves L and the trailing rows unchanged.  The
+  // scaled entries (b_ij + b_ji) / 2 delta_i delta_j are formed as the rows
+  // are loaded (and those of A where the compression reads them); only the
+  // lower triangle of the kept columns of L is ever read.
   {
     double sb[KB];
 #pragma unroll
-    for (int k = 0; k < KB; ++k) sb[k] = (lane < ns && k < ns) ? sh.SB[lj * LD + k] : 0.0;
+    for (int k = 0; k < KB; ++k) {
+      const int kc = k < ns ? k : 0;
+      const double bij = sh.B[lj * LD + kc], bji = sh.B[kc * LD + lj];
+      const double b = lj == kc ? bij : 0.5 * (bij + bji);
+      sb[k] = (lane < ns && k < ns) ? b * (sh.delta[lj] * sh.delta[kc]) : 0.0;
+    }
 #pragma unroll
     for (int j = 0; j < KB; ++j) {
       if (j < ns) {
@@ -737,7 +731,9 @@ __device__ void rayleigh_ritz_kb(RRShared& sh, int ns, int m, double drop_tol, d
   for (int e = lane; e < KB * KB; e += 64) {
     const int a = e / KB, b = e - (e / KB) * KB;
     const int ia = sh.idx[a < K ? a : 0], ib = sh.idx[b < K ? b : 0];
-    const double lv = sh.L[ia * LD + ib], av = sh.SA[ia * LD + ib];
+    const double aij = sh.A[ia * LD + ib], aji = sh.A[ib * LD + ia];
+    const double lv = sh.L[ia * LD + ib];
+    const double av = (ia == ib ? aij : 0.5 * (aij + aji)) * (sh.delta[ia] * sh.delta[ib]);
     const bool in = a < K && b < K;
     sh.LK[a * LD + b] = in ? (b <= a ? lv : 0.0) : (a == b ? 1.0 : 0.0);
     sh.M2[a * LD + b] = in ? av : 0.0;
@@ -1021,23 +1017,26 @@ __global__ void __launch_bounds__(kThreads) gram_rr_kernel(GramArgs g, RRArgs r,
   // tolerance adds no search direction, i.e. its W column counts as zero:
   // the W rows and columns of both Gram matrices are cleared, and the
   // Rayleigh-Ritz step drops the column
-  if (threadIdx.x == 0) {
-    int mask = 0;
-    if (!r.init && st != nullptr && tol > 0.0 && g.ns > g.m)
+  // (tol, like the rest of the condition, is the same for every thread, so
+  // a run without a tolerance skips the mask and its barrier)
+  if (!r.init && st != nullptr && tol > 0.0 && g.ns > g.m) {
+    if (threadIdx.x == 0) {
+      int mask = 0;
       for (int j = 0; j < g.m; ++j)
         if (st->res[j] <= tol) mask |= 1 << j;
-    lockm = mask;
-  }
-  __syncthreads();
-  if (lockm != 0) {
-    const int lk = lockm;
-    for (int e = threadIdx.x; e < g.ns * g.ns; e += blockDim.x) {
-      const int i = e / g.ns, j = e - (e / g.ns) * g.ns;
-      const bool li = i >= g.m && i < 2 * g.m && ((lk >> (i - g.m)) & 1);
-      const bool lj = j >= g.m && j < 2 * g.m && ((lk >> (j - g.m)) & 1);
-      if (li || lj) {
-        sh.A[i * LD + j] = 0.0;
-        sh.B[i * LD + j] = 0.0;
+      lockm = mask;
+    }
+    __syncthreads();
+    if (lockm != 0) {
+      const int lk = lockm;
+      for (int e = threadIdx.x; e < g.ns * g.ns; e += blockDim.x) {
+        const int i = e / g.ns, j = e - (e / g.ns) * g.ns;
+        const bool li = i >= g.m && i < 2 * g.m && ((lk >> (i - g.m)) & 1);
+        const bool lj = j >= g.m && j < 2 * g.m && ((lk >> (j - g.m)) & 1);
+        if (li || lj) {
+          sh.A[i * LD + j] = 0.0;
+          sh.B[i * LD + j] = 0.0;
+        }
       }
     }
   }
@@ -1401,11 +1400,13 @@ gsf_status lob_launch_gram(const GramArgs& g, const RRArgs& r, int prec, hipStre
     dim3 grid(gram_tiles_total(g.ns) + 1, kGramChunks);
     gram_reduce_kernel<<<grid, kThreads, 0, s>>>(g, r);
   }
-  // with a CG phase, 24 KB of unused LDS per workgroup (about 83 KB with the
-  // step's own) keep a second workgroup off the Rayleigh-Ritz workgroup's CU:
-  // 41.5 us per call at 1024^2, m = 4 against 42.3 us when a CG workgroup
+  // with a CG phase, unused LDS brings each workgroup above half of a CU's
+  // 160 KB, which keeps a second workgroup off the Rayleigh-Ritz workgroup's
+  // CU: 41.5 us per call at 1024^2, m = 4 against 42.3 us when a CG workgroup
   // shares it (the CG phase itself ends long before the step)
-  gram_rr_kernel<<<1 + ca.nblk, rr_threads(g.ns), ca.nblk > 0 ? 24 * 1024 : 0, s>>>(g, r, ca, direct);
+  constexpr size_t kHalfCu = 80 * 1024 + 1024;
+  constexpr size_t kReserve = sizeof(RRShared) < kHalfCu ? kHalfCu - sizeof(RRShared) : 0;
+  gram_rr_kernel<<<1 + ca.nblk, rr_threads(g.ns), ca.nblk > 0 ? kReserve : 0, s>>>(g, r, ca, direct);
   return launch_status();
 }
 
