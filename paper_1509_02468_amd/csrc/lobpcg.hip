@@ -368,8 +368,6 @@ struct RRShared {
   double delta[KMAX];
   double rinv[KMAX];
   double ev[KMAX];
-  int good[KMAX];
-  int kept[KMAX];
   int idx[KMAX];
   int order[KMAX];
   int nk;                // kept columns (shared with the other waves)
@@ -672,10 +670,8 @@ __device__ void rayleigh_ritz_kb(RRShared& sh, int ns, int m, double drop_tol, d
   const double dl = sh.B[lj * LD + lj];
   const double mx = wave_max(lane < ns && dl > 0.0 ? dl : 0.0);
   const int gd = lane < ns && dl > zero_tol * zero_tol * mx;
-  if (lane < ns) {
-    sh.good[lane] = gd;
-    sh.delta[lane] = gd ? 1.0 / sqrt(dl) : 0.0;
-  }
+  const unsigned long long goodm = __ballot(gd);  // the flags as a wave-uniform mask
+  if (lane < ns) sh.delta[lane] = gd ? 1.0 / sqrt(dl) : 0.0;
   wave_fence();
   // right-looking Cholesky of the symmetrised, scaled B with column dropping,
   // lane i owning row i (lower triangle) in registers: column j's pivot and
@@ -685,6 +681,7 @@ __device__ void rayleigh_ritz_kb(RRShared& sh, int ns, int m, double drop_tol, d
   // scaled entries (b_ij + b_ji) / 2 delta_i delta_j are formed as the rows
   // are loaded (and those of A where the compression reads them); only the
   // lower triangle of the kept columns of L is ever read.
+  unsigned long long keptm = 0;  // kept columns, wave-uniform
   {
     double sb[KB];
 #pragma unroll
@@ -698,10 +695,10 @@ __device__ void rayleigh_ritz_kb(RRShared& sh, int ns, int m, double drop_tol, d
     for (int j = 0; j < KB; ++j) {
       if (j < ns) {
         const double piv = readlane_d(sb[j], j);
-        const int keep = sh.good[j] && piv > drop_tol;
+        const int keep = ((goodm >> j) & 1ull) && piv > drop_tol;
         const double ip = rsq_nr2(keep ? piv : 1.0);  // 1 / L_jj
         const double lij = sb[j] * ip;
-        if (lane == 0) sh.kept[j] = keep;
+        keptm |= (unsigned long long)keep << j;
         if (keep) {
           if (lane > j && lane < ns) sh.L[lane * LD + j] = lij;
           if (lane == j) sh.L[j * LD + j] = piv * ip;
@@ -715,8 +712,8 @@ __device__ void rayleigh_ritz_kb(RRShared& sh, int ns, int m, double drop_tol, d
     }
   }
   wave_fence();
-  const int kp = lane < ns ? sh.kept[lane] : 0;
-  const unsigned long long km = __ballot(kp);
+  const int kp = lane < ns ? (int)((keptm >> lane) & 1ull) : 0;
+  const unsigned long long km = keptm;
   const int K = __popcll(km);
   if (kp) sh.idx[__popcll(km & ((1ull << lane) - 1ull))] = lane;
   if (lane < ns) kept_out[lane] = kp;
