@@ -338,13 +338,18 @@ __global__ void __launch_bounds__(kThreads) rg_update_kernel(T* __restrict__ x, 
 }  // namespace
 
 // Workgroups of the point-wise vector kernels: one point per thread up to
-// 1024 workgroups (grid-stride beyond).  Small problems get many short
+// 512 workgroups (grid-stride beyond).  Small problems get many short
 // workgroups rather than a few long ones: at n = 4096 the LOBPCG update took
-// 10.9 us on 4 workgroups of 4 points per thread.
+// 10.9 us on 4 workgroups of 4 points per thread.  The cap, compared in
+// alternating runs on one GPU: 512 workgroups against 256 / 768 / 1024 / 2048
+// took 9.49-9.51 against 9.62 / 9.51 / 9.54-9.58 / 9.73 ms per joint CG50 +
+// LOBPCG50 call at 1024^2, and 2.83-2.84 against 2.84-2.85 / 2.87-2.89 /
+// 2.87-2.88 ms per LOBPCG step at 4096^2, m = 8 (fewer, longer workgroups
+// leave room for the CG phase that shares the update launch).
 int vec_blocks(int64_t n) {
   int64_t b = (n + kThreads - 1) / kThreads;
   if (b < 1) b = 1;
-  if (b > 1024) b = 1024;
+  if (b > 512) b = 512;
   return (int)b;
 }
 
