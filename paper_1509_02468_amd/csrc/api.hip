@@ -329,7 +329,7 @@ struct LobWs {
 };
 
 // Workgroups of the Gram kernel: 256 points each (64 per wave) up to
-// kGramBlocks; at n = 4096 the Gram took 9.5 us on 4 workgroups of 1024.
+// kGramBlocks (512); at n = 4096 the Gram took 9.5 us on 4 workgroups of 1024.
 int gram_blocks(int64_t n) {
   int64_t b = (n + 255) / 256;
   if (b < 1) b = 1;

@@ -11,8 +11,12 @@ constexpr int kGramChunks = 16;     // first-stage split of the Gram partial red
 // previous update's reduced residual sums (8 values, at kGramFinSlot)
 constexpr int kGramFinSlot = kGramChunks * 7 * 256;
 constexpr int kGramLevel2Doubles = kGramFinSlot + 32;
-constexpr int kGramPerChunk = 64;   // partials per chunk (kGramBlocks / kGramChunks)
-constexpr int kGramBlocks = 1024; // workgroups of the Gram kernel (at most)
+// workgroups of the Gram kernel (at most), compared in alternating runs on one
+// GPU: 256 / 384 / 512 / 768 / 1024 took 9.63 / 9.55 / 9.41-9.43 / 9.45 /
+// 9.46-9.47 ms per joint CG50 + LOBPCG50 call at 1024^2 and 2.76 / 2.87 /
+// 2.73-2.76 / 2.73-2.75 / 2.84-2.85 ms per LOBPCG step at 4096^2, m = 8
+constexpr int kGramBlocks = 512;
+constexpr int kGramPerChunk = kGramBlocks / kGramChunks;  // partials per chunk
 
 struct LobArgs {
   int prec;
