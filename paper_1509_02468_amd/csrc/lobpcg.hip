@@ -922,7 +922,7 @@ __global__ void __launch_bounds__(kThreads) gram_reduce_kernel(GramArgs g, RRArg
 // wave then runs the Rayleigh-Ritz step.  Workgroups 1.. (cg.nblk of them)
 // run a CG update phase of the joint driver on the CUs the step leaves idle.
 //
-// direct != 0 (at most kGramChunks Gram workgroups): no
+// direct != 0 (at most kGramDirect Gram workgroups): no
 // reduction launch ran; the partials take the place of the chunk sums (the
 // reduction would have copied them one to one, so the sums are bitwise the
 // same) and this workgroup sums the previous update's residual partials.
@@ -946,9 +946,9 @@ __global__ void __launch_bounds__(kThreads) gram_rr_kernel(GramArgs g, RRArgs r,
   const double* chunks = direct ? g.partials : g.level2;
   const int nchunks = direct ? g.nparts : kGramChunks;
   const int e1 = (int)threadIdx.x + (int)blockDim.x;  // ntot >= 2: every thread has two entries
-  double v0[kGramChunks], v1[kGramChunks];
+  double v0[kGramDirect], v1[kGramDirect];
 #pragma unroll
-  for (int c = 0; c < kGramChunks; ++c) {
+  for (int c = 0; c < kGramDirect; ++c) {
     v0[c] = c < nchunks ? chunks[(size_t)c * (ntot * 256) + threadIdx.x] : 0.0;
     v1[c] = c < nchunks ? chunks[(size_t)c * (ntot * 256) + e1] : 0.0;
   }
@@ -986,10 +986,10 @@ __global__ void __launch_bounds__(kThreads) gram_rr_kernel(GramArgs g, RRArgs r,
     if (!live) return;
   }
   // entry e of the Gram tiles (chunk sums in v) into sh.A / sh.B
-  auto place = [&](int e, const double (&v)[kGramChunks]) {
+  auto place = [&](int e, const double (&v)[kGramDirect]) {
     double s = 0.0;
 #pragma unroll
-    for (int c = 0; c < kGramChunks; ++c) s += v[c];
+    for (int c = 0; c < kGramDirect; ++c) s += v[c];
     bool isb;
     int row, colj;
     tile_entry(e, nt, isb, row, colj);
@@ -1005,9 +1005,9 @@ __global__ void __launch_bounds__(kThreads) gram_rr_kernel(GramArgs g, RRArgs r,
   place(threadIdx.x, v0);
   place(e1, v1);
   for (int e = e1 + blockDim.x; e < ntot * 256; e += blockDim.x) {
-    double v[kGramChunks];
+    double v[kGramDirect];
 #pragma unroll
-    for (int c = 0; c < kGramChunks; ++c) v[c] = c < nchunks ? chunks[(size_t)c * (ntot * 256) + e] : 0.0;
+    for (int c = 0; c < kGramDirect; ++c) v[c] = c < nchunks ? chunks[(size_t)c * (ntot * 256) + e] : 0.0;
     place(e, v);
   }
   // soft locking (tol > 0): a column whose residual is already at the
@@ -1390,9 +1390,9 @@ gsf_status lob_launch_gram(const GramArgs& g, const RRArgs& r, int prec, hipStre
     launch_gram_kernel<double>(g, s);
   const CgStepArgs none{};
   const CgStepArgs& ca = cg_update != nullptr ? *cg_update : none;
-  // with at most kGramChunks Gram workgroups the reduction launch would only
+  // with at most kGramDirect Gram workgroups the reduction launch would only
   // copy the partials: the Rayleigh-Ritz workgroup reads them itself
-  const int direct = g.nparts <= kGramChunks ? 1 : 0;
+  const int direct = g.nparts <= kGramDirect ? 1 : 0;
   if (!direct) {
     dim3 grid(gram_tiles_total(g.ns) + 1, kGramChunks);
     gram_reduce_kernel<<<grid, kThreads, 0, s>>>(g, r);

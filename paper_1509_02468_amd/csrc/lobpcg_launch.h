@@ -6,7 +6,13 @@
 
 namespace gsf {
 
-constexpr int kGramChunks = 16;     // first-stage split of the Gram partial reduction
+// first-stage split of the Gram partial reduction: the reduction launch sums
+// kGramPerChunk partials per chunk, the Rayleigh-Ritz workgroup the chunks
+// (4 / 8 / 16 chunks: 9.48-9.50 / 9.38-9.45 / 9.44-9.47 ms per joint CG50 +
+// LOBPCG50 call at 1024^2 in alternating runs on one GPU; equal at 4096^2)
+constexpr int kGramChunks = 8;
+constexpr int kGramDirect = 16;     // at most this many Gram workgroups: no reduction launch
+static_assert(kGramChunks <= kGramDirect, "the Rayleigh-Ritz workgroup sums at most kGramDirect values per entry");
 // level-2 buffer: kGramChunks x (up to 7 tiles) x 256 chunk sums, then the
 // previous update's reduced residual sums (8 values, at kGramFinSlot)
 constexpr int kGramFinSlot = kGramChunks * 7 * 256;
