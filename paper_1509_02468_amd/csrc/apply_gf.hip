@@ -23,7 +23,12 @@ namespace gsf {
 namespace {
 
 constexpr int kGfLanes = 64;   // one wave per workgroup; lane = halo column
-constexpr int kGfRowsMax = 64;  // output rows per workgroup (fewer on small grids)
+// output rows per workgroup (fewer on small grids); 16 / 24 / 32 / 64 / 128
+// compared in alternating runs on one GPU at 4096^2, r = 8, FP32: m = 8 apply
+// 1485 / 1462 / 1438-1447 / 1474 / (step +1%) us, m = 4 820 / 798 / 787-791 /
+// 807-810 us: more, shorter workgroups hide the row loads better than the
+// fewer warm-up rows of long ones save
+constexpr int kGfRowsMax = 32;
 
 // 32-bit indices: the operator build rejects GF grids of 2^27 points or more,
 // so point * 16 fits.
@@ -327,8 +332,9 @@ struct GfStats {
   }
 };
 
-// Rows per workgroup: as many as possible (the 2r warm-up rows are amortised)
-// while the grid still has about 2048 waves to hide memory latency.
+// Rows per workgroup: as many as possible up to kGfRowsMax (the 2r warm-up
+// rows are amortised) while the grid still has about 2048 waves to hide
+// memory latency.
 template <int CPL>
 GfGeom gf_geom(const Operator& op) {
   const int ow = kGfLanes * CPL - 2 * op.desc.radius;
